@@ -1,0 +1,182 @@
+/*
+ * yastn.h -- C ABI of the MI355X block-sparse tensordot library.
+ *
+ * The library contracts two abelian-symmetric (Z_m, U(1) and their direct
+ * products) block-sparse tensors, the operation described in Sec. II.B
+ * ("Fusion and contractions") of Rams, Wojtowicz, Sinha, Hasik, "YASTN: Yet
+ * another symmetric tensor networks" (arXiv:2405.12196):
+ *
+ *     C_{{i}{j}} = sum_{{x}} A_{{i} u {x}} B_{{j} u {x}}
+ *
+ * computed as: match A's and B's blocks on the charges of the contracted legs,
+ * group the matches by the fused contracted charge X (one dense sector GEMM
+ * C_IJ = sum_X A_IX B_XJ per X), and write the result straight into C's
+ * blocks.  Tensors follow Sec. II.A: a leg is V(s, t, D) (signature s = +-1,
+ * charge sectors t, sector dims D); a block is named by a tuple of charges,
+ * one per leg, and a stored block obeys the block form of charge conservation
+ * sum_i s_i rho_i = n; all blocks of a tensor live in ONE 1D buffer (lazy
+ * storage), each block dense in C (row-major) order.
+ *
+ * Conventions
+ *   - Every call returns yastn_status; nothing throws across the ABI.  On an
+ *     error, yastn_last_error() returns a thread-local message.
+ *   - Host pointers are marked [host], device pointers [device].  Every
+ *     descriptor array is read during the call and copied; the caller keeps
+ *     ownership of everything it passes in.
+ *   - Device buffers (tensor data, workspace) are owned by the caller.
+ *   - hip_stream is a hipStream_t (NULL = the legacy default stream).
+ */
+#ifndef YASTN_H
+#define YASTN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define YASTN_ABI_VERSION 1
+#define YASTN_MAX_RANK 8   /* legs per tensor                                  */
+#define YASTN_MAX_NSYM 4   /* charge components (e.g. U(1)xU(1) has nsym = 2)  */
+
+typedef enum {
+  YASTN_OK = 0,
+  YASTN_ERR_ARG = 1,        /* null pointer, rank/nsym out of range, axes out of range or repeated,
+                               axes of unequal length, signature not +-1, negative or overlapping
+                               block offsets, unsupported option                                */
+  YASTN_ERR_SYM = 2,        /* sym_mod differs between A and B, or an entry is 1 or negative    */
+  YASTN_ERR_CHARGE = 3,     /* a block violates sum_i s_i rho_i = n (Sec. II.A)                  */
+  YASTN_ERR_SIGNATURE = 4,  /* a contracted leg pair has equal signatures (a leg contracts only
+                               with its dual, Sec. II.A footnote on conjugation)                 */
+  YASTN_ERR_SHAPE = 5,      /* a dim < 1, one charge with two dims on a leg, or a contracted
+                               charge with different dims in A and B                             */
+  YASTN_ERR_DUPLICATE = 6,  /* a charge tuple occurs twice in one tensor                         */
+  YASTN_ERR_NOMEM = 7,      /* host or device allocation failed                                  */
+  YASTN_ERR_HIP = 8,        /* a HIP runtime call failed (no device, launch failure, ...)        */
+  YASTN_ERR_STATE = 9       /* call not valid for this plan (e.g. buffer too small, job mix)     */
+} yastn_status;
+
+/* Arithmetic of the sector GEMMs.  F64: FP64 MFMA.  F32: FP32 MFMA.  BF16X3 /
+ * BF16X6: each FP32 operand split into bf16 terms hi + mid (+ lo), products
+ * hi*hi + hi*mid + mid*hi (X3; + mid*mid + hi*lo + lo*hi for X6) on bf16 MFMA;
+ * all reduced precisions accumulate in FP32. */
+typedef enum { YASTN_F64 = 0, YASTN_F32 = 1, YASTN_BF16X3 = 2, YASTN_BF16X6 = 3 } yastn_precision;
+
+/* Element type of a stored tensor buffer. */
+typedef enum { YASTN_DTYPE_F64 = 0, YASTN_DTYPE_F32 = 1 } yastn_dtype;
+
+/* One block-sparse tensor (Sec. II.A).  All arrays [host]. */
+typedef struct {
+  int32_t rank;              /* number of legs, 0..YASTN_MAX_RANK                               */
+  int32_t nsym;              /* charge components, 1..YASTN_MAX_NSYM                            */
+  const int32_t *sym_mod;    /* [nsym] 0 = U(1) (charges in Z); m >= 2 = Z_m (reduced mod m)    */
+  const int8_t *sig;         /* [rank] leg signatures, +1 or -1                                 */
+  const int32_t *n;          /* [nsym] total charge n                                           */
+  int64_t nblocks;           /* stored blocks (may be 0)                                        */
+  const int32_t *charges;    /* [nblocks][rank][nsym] charge of each block on each leg          */
+  const int64_t *shapes;     /* [nblocks][rank] block dims, each >= 1                           */
+  const int64_t *offsets;    /* [nblocks] first element of each block in the 1D buffer; blocks
+                                must not overlap; any order                                     */
+} yastn_tensor_desc;
+
+/* One tensordot: C = tensordot(A, B, axes=(axes_a, axes_b)) (the paper's
+ * tensordot listing).  C's legs are A's uncontracted legs in order, then B's. */
+typedef struct {
+  yastn_tensor_desc a, b;
+  int32_t ncontract;         /* number of contracted leg pairs                                  */
+  const int32_t *axes_a;     /* [ncontract] [host] legs of A                                    */
+  const int32_t *axes_b;     /* [ncontract] [host] matching legs of B                           */
+} yastn_problem;
+
+typedef struct {
+  yastn_precision precision; /* arithmetic of the sector GEMMs                                  */
+  yastn_dtype in_dtype;      /* element type of A and B buffers                                 */
+  yastn_dtype out_dtype;     /* element type of C buffers                                       */
+  int32_t tile_rows;         /* rows per wave tile: 16, 32 or 64; 0 = chosen by the autotuner   */
+  int32_t flags;             /* reserved, must be 0                                             */
+} yastn_options;
+
+typedef struct {
+  int64_t blocks_a, blocks_b;  /* stored blocks of A and B                                      */
+  int64_t pairs;               /* matched (A block, B block) pairs                              */
+  int64_t sectors;             /* distinct fused contracted charges X with >= 1 pair            */
+  int64_t c_blocks;            /* blocks of C                                                   */
+  int64_t c_numel;             /* elements of C (contiguous, rule: ascending charge order)      */
+  int64_t numel_a, numel_b;    /* stored elements of A and B                                    */
+  int64_t max_m, max_k, max_n; /* largest fused sector matrix dims                              */
+  int64_t tiles;               /* wave tiles of the grouped GEMM for this problem               */
+  double useful_flops;         /* sum over matched pairs of 2*m*k*n                             */
+  double mfma_flops;           /* flops the MFMA tiles execute (padding included)               */
+  double alg_bytes;            /* (numel_a + numel_b) * in bytes + c_numel * out bytes          */
+} yastn_stats;
+
+typedef struct yastn_plan_s *yastn_plan_t;
+
+/* Build a plan for nprob independent problems that will run in one grouped
+ * launch.  Validates every descriptor on the host (all error classes above),
+ * then matches blocks with the charge-hash join kernel on the device (the
+ * plan's device tables are allocated here), reads the matches back, and
+ * derives C's structure: blocks (a_free, b_free) reached by at least one
+ * matched pair, in ascending lexicographic order of the (normalised) charge
+ * tuple, stored contiguously; n_C = n_A + n_B.  A contracted charge present
+ * in only one operand contributes nothing (Sec. II.B footnote).
+ * Synchronises hip_stream once.  opts may be NULL (F64, F64 in/out, auto). */
+yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_options *opts,
+                        void *hip_stream, yastn_plan_t *out);
+
+/* Structure of problem prob's output.  The returned arrays are owned by the
+ * plan and live until yastn_free.  c->charges / shapes / offsets are [host]. */
+yastn_status yastn_plan_output(yastn_plan_t plan, int32_t prob, yastn_tensor_desc *c,
+                               int64_t *c_numel);
+
+/* Device workspace yastn_contract needs, in bytes (may be 0). */
+yastn_status yastn_plan_workspace(yastn_plan_t plan, size_t *bytes);
+
+yastn_status yastn_plan_stats(yastn_plan_t plan, int32_t prob, yastn_stats *st);
+
+/* Run every problem of the plan in one grouped launch, asynchronously on
+ * hip_stream.  a[p], b[p] [device] are the input buffers of problem p (any
+ * values with the planned structure; in_dtype elements), c[p] [device] its
+ * output buffer of c_numel elements (out_dtype), fully overwritten: C need
+ * not be zeroed.  The host arrays a, b, c are read during the call.
+ * workspace [device] must hold yastn_plan_workspace bytes (256-byte aligned)
+ * and must not be shared by calls that may overlap.  Results are
+ * deterministic: no atomics, fixed summation order per output element. */
+yastn_status yastn_contract(yastn_plan_t plan, const void *const *a, const void *const *b,
+                            void *const *c, void *workspace, void *hip_stream);
+
+/* One entry of a multi-plan launch (continuous batching across requests). */
+typedef struct {
+  yastn_plan_t plan;
+  const void *const *a;      /* [host array of nprob device pointers]                           */
+  const void *const *b;
+  void *const *c;
+  void *workspace;           /* [device] this job's workspace                                   */
+} yastn_job;
+
+/* Run the problems of several plans in one grouped launch on hip_stream.
+ * All plans must share precision and dtypes (else YASTN_ERR_STATE).  Each
+ * job's results are bitwise equal to running it alone with yastn_contract. */
+yastn_status yastn_contract_jobs(const yastn_job *jobs, int32_t njobs, void *hip_stream);
+
+/* FP64 Frobenius norm and max |x| of a [device] buffer of n elements
+ * (dtype), written as out[0] = ||x||_F, out[1] = max|x| ([device], FP64).
+ * Deterministic two-pass reduction; workspace [device] must hold
+ * yastn_norm_workspace() bytes. */
+size_t yastn_norm_workspace(void);
+yastn_status yastn_norm(const void *x, int64_t n, yastn_dtype dtype, double *out, void *workspace,
+                        void *hip_stream);
+
+/* Release a plan (host and device tables).  NULL is ignored.  The caller must
+ * make sure no launch that uses the plan is still running. */
+void yastn_free(yastn_plan_t plan);
+
+const char *yastn_last_error(void);
+const char *yastn_status_string(yastn_status s);
+int32_t yastn_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* YASTN_H */

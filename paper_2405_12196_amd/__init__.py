@@ -1,0 +1,298 @@
+"""Python binding of the MI355X block-sparse tensordot library (libyastn.so).
+
+Argument marshalling only: every step of the contraction (matching, fusing,
+sector GEMMs, output scatter, norms) runs in the library's HIP kernels.
+PyTorch supplies device memory and streams.  If the compiled library is
+missing this package raises on first use; there is no fallback path.
+
+Names follow the C ABI in include/yastn.h:
+    plan(problems, ...)        -> Plan            (yastn_plan)
+    Plan.output(p)             -> structure of C  (yastn_plan_output)
+    Plan.contract(a, b, c, ws) -> None, async     (yastn_contract)
+    contract_jobs(jobs)        -> None, async     (yastn_contract_jobs)
+    norm(x, out, ws)           -> None, async     (yastn_norm)
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libyastn.so")
+
+F64, F32, BF16X3, BF16X6 = 0, 1, 2, 3
+DTYPE_F64, DTYPE_F32 = 0, 1
+PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3, "bf16x6": BF16X6}
+STATUS = ["OK", "ERR_ARG", "ERR_SYM", "ERR_CHARGE", "ERR_SIGNATURE", "ERR_SHAPE",
+          "ERR_DUPLICATE", "ERR_NOMEM", "ERR_HIP", "ERR_STATE"]
+
+EXPORTS = ["yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats",
+           "yastn_contract", "yastn_contract_jobs", "yastn_norm_workspace", "yastn_norm",
+           "yastn_free", "yastn_last_error", "yastn_status_string", "yastn_abi_version"]
+
+
+class YastnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        name = STATUS[status] if 0 <= status < len(STATUS) else str(status)
+        super().__init__(f"{name}: {msg}")
+        self.status = name
+
+
+class TensorDesc(C.Structure):
+    _fields_ = [("rank", C.c_int32), ("nsym", C.c_int32), ("sym_mod", C.POINTER(C.c_int32)),
+                ("sig", C.POINTER(C.c_int8)), ("n", C.POINTER(C.c_int32)), ("nblocks", C.c_int64),
+                ("charges", C.POINTER(C.c_int32)), ("shapes", C.POINTER(C.c_int64)),
+                ("offsets", C.POINTER(C.c_int64))]
+
+
+class Problem(C.Structure):
+    _fields_ = [("a", TensorDesc), ("b", TensorDesc), ("ncontract", C.c_int32),
+                ("axes_a", C.POINTER(C.c_int32)), ("axes_b", C.POINTER(C.c_int32))]
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("in_dtype", C.c_int32), ("out_dtype", C.c_int32),
+                ("tile_rows", C.c_int32), ("flags", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("blocks_a", "blocks_b", "pairs", "sectors", "c_blocks",
+                                         "c_numel", "numel_a", "numel_b", "max_m", "max_k", "max_n",
+                                         "tiles")] + \
+               [("useful_flops", C.c_double), ("mfma_flops", C.c_double), ("alg_bytes", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Job(C.Structure):
+    _fields_ = [("plan", C.c_void_p), ("a", C.POINTER(C.c_void_p)), ("b", C.POINTER(C.c_void_p)),
+                ("c", C.POINTER(C.c_void_p)), ("workspace", C.c_void_p)]
+
+
+_LIB = None
+
+
+def lib():
+    """Load libyastn.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not found: build it with paper_2405_12196_amd/build.py "
+                              "(no fallback path exists)")
+        L = C.CDLL(LIB_PATH)
+        L.yastn_plan.argtypes = [C.POINTER(Problem), C.c_int32, C.POINTER(Options), C.c_void_p,
+                                 C.POINTER(C.c_void_p)]
+        L.yastn_plan_output.argtypes = [C.c_void_p, C.c_int32, C.POINTER(TensorDesc), C.POINTER(C.c_int64)]
+        L.yastn_plan_workspace.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
+        L.yastn_plan_stats.argtypes = [C.c_void_p, C.c_int32, C.POINTER(Stats)]
+        L.yastn_contract.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                     C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]
+        L.yastn_contract_jobs.argtypes = [C.POINTER(Job), C.c_int32, C.c_void_p]
+        L.yastn_norm_workspace.restype = C.c_size_t
+        L.yastn_norm.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.yastn_free.argtypes = [C.c_void_p]
+        L.yastn_free.restype = None
+        L.yastn_last_error.restype = C.c_char_p
+        L.yastn_status_string.restype = C.c_char_p
+        L.yastn_status_string.argtypes = [C.c_int32]
+        for f in ("yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats",
+                  "yastn_contract", "yastn_contract_jobs", "yastn_norm"):
+            getattr(L, f).restype = C.c_int32
+        _LIB = L
+    return _LIB
+
+
+def _check(status: int):
+    if status != 0:
+        raise YastnError(status, lib().yastn_last_error().decode())
+
+
+# ---------------------------------------------------------------------------
+# descriptors
+# ---------------------------------------------------------------------------
+def _arr(x, dtype):
+    return np.ascontiguousarray(np.asarray(x), dtype=dtype)
+
+
+class _Keep:
+    """Holds numpy arrays alive while a descriptor points at them."""
+
+    def __init__(self):
+        self.items = []
+
+    def ptr(self, arr, ctype):
+        self.items.append(arr)
+        return arr.ctypes.data_as(C.POINTER(ctype))
+
+
+def _desc(t, keep: _Keep) -> TensorDesc:
+    """Descriptor of anything with sym_mod, sig, n, charges, shapes, offsets."""
+    charges = _arr(t.charges, np.int32)
+    shapes = _arr(t.shapes, np.int64)
+    offsets = _arr(t.offsets, np.int64)
+    sig = _arr(t.sig, np.int8)
+    sym = _arr(t.sym_mod, np.int32)
+    n = _arr(t.n, np.int32)
+    d = TensorDesc()
+    d.rank = int(sig.shape[0])
+    d.nsym = int(sym.shape[0])
+    d.sym_mod = keep.ptr(sym, C.c_int32)
+    d.sig = keep.ptr(sig, C.c_int8)
+    d.n = keep.ptr(n, C.c_int32)
+    d.nblocks = int(offsets.shape[0])
+    d.charges = keep.ptr(charges, C.c_int32)
+    d.shapes = keep.ptr(shapes, C.c_int64)
+    d.offsets = keep.ptr(offsets, C.c_int64)
+    return d
+
+
+@dataclass
+class Structure:
+    """Block structure of a tensor (no data): what yastn_plan_output returns."""
+
+    sym_mod: tuple
+    sig: np.ndarray
+    n: np.ndarray
+    charges: np.ndarray
+    shapes: np.ndarray
+    offsets: np.ndarray
+    numel: int
+
+    @property
+    def nblocks(self):
+        return int(self.offsets.shape[0])
+
+
+def _ptr(x) -> int:
+    """Device address of a torch tensor or an int."""
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        if not torch.cuda.is_available():
+            return 0
+        return int(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+class Plan:
+    """A validated, matched and tiled set of tensordot problems (yastn_plan)."""
+
+    def __init__(self, problems, precision="f64", in_dtype=None, out_dtype=None, tile_rows=0, stream=None):
+        L = lib()
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        if in_dtype is None:
+            in_dtype = DTYPE_F64 if prec == F64 else DTYPE_F32
+        if out_dtype is None:
+            out_dtype = DTYPE_F64 if prec == F64 else DTYPE_F32
+        self.precision, self.in_dtype, self.out_dtype = prec, in_dtype, out_dtype
+        keep = _Keep()
+        arr = (Problem * max(1, len(problems)))()
+        for i, (a, b, axes_a, axes_b) in enumerate(problems):
+            arr[i].a = _desc(a, keep)
+            arr[i].b = _desc(b, keep)
+            xa, xb = _arr(list(axes_a), np.int32), _arr(list(axes_b), np.int32)
+            arr[i].ncontract = int(len(axes_a)) if len(axes_a) == len(axes_b) else -1
+            arr[i].axes_a = keep.ptr(xa, C.c_int32)
+            arr[i].axes_b = keep.ptr(xb, C.c_int32)
+        opts = Options(prec, in_dtype, out_dtype, tile_rows, 0)
+        h = C.c_void_p()
+        _check(L.yastn_plan(arr, len(problems), C.byref(opts), C.c_void_p(_stream(stream)),
+                            C.byref(h)))
+        self._h = h
+        self.nprob = len(problems)
+        ws = C.c_size_t()
+        _check(L.yastn_plan_workspace(h, C.byref(ws)))
+        self.workspace_bytes = int(ws.value)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def output(self, p: int = 0) -> Structure:
+        d = TensorDesc()
+        n = C.c_int64()
+        _check(lib().yastn_plan_output(self._h, p, C.byref(d), C.byref(n)))
+        nb, r, s = d.nblocks, d.rank, d.nsym
+
+        def cp(ptr, count, dtype):
+            if count == 0:
+                return np.zeros(0, dtype=dtype)
+            return np.ctypeslib.as_array(ptr, shape=(count,)).astype(dtype, copy=True)
+        return Structure(tuple(int(v) for v in cp(d.sym_mod, s, np.int32)),
+                         cp(d.sig, r, np.int8) if r else np.zeros(0, np.int8),
+                         cp(d.n, s, np.int32),
+                         cp(d.charges, nb * r * s, np.int32).reshape(nb, r, s),
+                         cp(d.shapes, nb * r, np.int64).reshape(nb, r),
+                         cp(d.offsets, nb, np.int64), int(n.value))
+
+    def stats(self, p: int = 0) -> dict:
+        st = Stats()
+        _check(lib().yastn_plan_stats(self._h, p, C.byref(st)))
+        return st.as_dict()
+
+    def contract(self, a, b, c, workspace=None, stream=None):
+        """a, b, c: sequences (one per problem) of device buffers (torch tensors
+        or addresses).  Asynchronous on ``stream`` (torch's current by default)."""
+        n = self.nprob
+        pa = (C.c_void_p * max(1, n))(*[_ptr(x) for x in a])
+        pb = (C.c_void_p * max(1, n))(*[_ptr(x) for x in b])
+        pc = (C.c_void_p * max(1, n))(*[_ptr(x) for x in c])
+        _check(lib().yastn_contract(self._h, pa, pb, pc, C.c_void_p(_ptr(workspace)),
+                                    C.c_void_p(_stream(stream))))
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().yastn_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def plan(problems, **kw) -> Plan:
+    return Plan(problems, **kw)
+
+
+def contract_jobs(jobs, stream=None):
+    """jobs: list of (Plan, a_list, b_list, c_list, workspace): one grouped launch."""
+    keep = []
+    arr = (Job * max(1, len(jobs)))()
+    for i, (pl, a, b, c, ws) in enumerate(jobs):
+        n = pl.nprob
+        pa = (C.c_void_p * max(1, n))(*[_ptr(x) for x in a])
+        pb = (C.c_void_p * max(1, n))(*[_ptr(x) for x in b])
+        pc = (C.c_void_p * max(1, n))(*[_ptr(x) for x in c])
+        keep += [pa, pb, pc]
+        arr[i].plan = pl.handle
+        arr[i].a = C.cast(pa, C.POINTER(C.c_void_p))
+        arr[i].b = C.cast(pb, C.POINTER(C.c_void_p))
+        arr[i].c = C.cast(pc, C.POINTER(C.c_void_p))
+        arr[i].workspace = _ptr(ws)
+    _check(lib().yastn_contract_jobs(arr, len(jobs), C.c_void_p(_stream(stream))))
+
+
+def norm_workspace_bytes() -> int:
+    return int(lib().yastn_norm_workspace())
+
+
+def norm(x, n: int, out, workspace, dtype=DTYPE_F64, stream=None):
+    """out[0] = ||x[:n]||_F, out[1] = max |x[:n]| (FP64, on the device)."""
+    _check(lib().yastn_norm(C.c_void_p(_ptr(x)), int(n), int(dtype), C.c_void_p(_ptr(out)),
+                            C.c_void_p(_ptr(workspace)), C.c_void_p(_stream(stream))))

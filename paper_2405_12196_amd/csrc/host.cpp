@@ -1,0 +1,515 @@
+// Host side of the plan: descriptor validation, output structure and tiling.
+//
+// Validation follows the paper's definitions (Sec. II.A): a stored block obeys
+// sum_i s_i rho_i = n; a leg carries one dim per charge; blocks are named by
+// their charge tuple, so a tuple occurs once.  Contracted legs pair a leg with
+// its dual (opposite signature) and must agree on the dim of every charge
+// both carry; a charge present on one side only contributes nothing (Sec.
+// II.B footnote on contraction partners).
+//
+// The matching itself (which A block meets which B block) comes from the
+// charge-hash join kernel; this file only groups its matches into sectors
+// (fused contracted charge X), row/contracted/column tuples, output blocks
+// and wave tiles.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <numeric>
+
+#include "planner.hpp"
+
+namespace yastn {
+
+namespace {
+thread_local std::string g_err;
+
+int64_t norm_charge(int64_t v, int32_t m) {
+  if (m == 0) return v;
+  int64_t r = v % m;
+  return r < 0 ? r + m : r;
+}
+
+yastn_status copy_tensor(const yastn_tensor_desc &d, HostTensor &t, const char *name) {
+  std::string nm(name);
+  if (d.rank < 0 || d.rank > YASTN_MAX_RANK) return set_error(YASTN_ERR_ARG, nm + ": rank out of range");
+  if (d.nsym < 1 || d.nsym > YASTN_MAX_NSYM) return set_error(YASTN_ERR_ARG, nm + ": nsym out of range");
+  if (!d.sym_mod || !d.n || (d.rank > 0 && !d.sig)) return set_error(YASTN_ERR_ARG, nm + ": null pointer");
+  if (d.nblocks < 0) return set_error(YASTN_ERR_ARG, nm + ": negative nblocks");
+  if (d.nblocks > 0 && ((d.rank > 0 && (!d.charges || !d.shapes)) || !d.offsets))
+    return set_error(YASTN_ERR_ARG, nm + ": null block arrays");
+  if (d.nblocks > (int64_t(1) << 30)) return set_error(YASTN_ERR_ARG, nm + ": too many blocks");
+  t.rank = d.rank;
+  t.nsym = d.nsym;
+  for (int c = 0; c < d.nsym; ++c) t.sym_mod[c] = d.sym_mod[c];
+  for (int i = 0; i < d.rank; ++i) t.sig[i] = d.sig[i];
+  t.nblocks = d.nblocks;
+  t.charges.assign(size_t(d.nblocks) * d.rank * d.nsym, 0);
+  t.shapes.assign(size_t(d.nblocks) * d.rank, 0);
+  t.offsets.assign(size_t(d.nblocks), 0);
+  if (d.nblocks) {
+    if (d.rank) {
+      std::memcpy(t.shapes.data(), d.shapes, t.shapes.size() * sizeof(int64_t));
+      for (size_t e = 0; e < t.charges.size(); ++e)
+        t.charges[e] = (int32_t)norm_charge(d.charges[e], d.sym_mod[e % d.nsym]);
+    }
+    std::memcpy(t.offsets.data(), d.offsets, t.offsets.size() * sizeof(int64_t));
+  }
+  for (int c = 0; c < d.nsym; ++c) t.n[c] = (int32_t)norm_charge(d.n[c], d.sym_mod[c]);
+  return YASTN_OK;
+}
+
+struct TupleLess {
+  const HostTensor *t;
+  bool operator()(int64_t x, int64_t y) const {
+    const int32_t *a = t->q(x, 0), *b = t->q(y, 0);
+    return std::lexicographical_compare(a, a + t->rank * t->nsym, b, b + t->rank * t->nsym);
+  }
+};
+
+yastn_status check_tensor(const HostTensor &t, const char *name,
+                          std::vector<std::map<std::vector<int32_t>, int64_t>> &legdims) {
+  std::string nm(name);
+  for (int i = 0; i < t.rank; ++i)
+    if (t.sig[i] != 1 && t.sig[i] != -1) return set_error(YASTN_ERR_ARG, nm + ": signature must be +1 or -1");
+  for (int64_t b = 0; b < t.nblocks; ++b)
+    for (int i = 0; i < t.rank; ++i) {
+      if (t.dim(b, i) < 1) return set_error(YASTN_ERR_SHAPE, nm + ": block dims must be >= 1");
+      if (t.dim(b, i) > (int64_t(1) << 30)) return set_error(YASTN_ERR_ARG, nm + ": block dim too large");
+    }
+  for (int64_t b = 0; b < t.nblocks; ++b) {
+    int64_t sz = 1;
+    for (int i = 0; i < t.rank; ++i) {
+      sz *= t.dim(b, i);
+      if (sz > (int64_t(1) << 31) - 1) return set_error(YASTN_ERR_ARG, nm + ": block larger than 2^31 elements");
+    }
+  }
+  // duplicates (a charge tuple names one block)
+  std::vector<int64_t> idx(t.nblocks);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::sort(idx.begin(), idx.end(), TupleLess{&t});
+  for (int64_t k = 1; k < t.nblocks; ++k)
+    if (!TupleLess{&t}(idx[k - 1], idx[k]) && !TupleLess{&t}(idx[k], idx[k - 1]))
+      return set_error(YASTN_ERR_DUPLICATE, nm + ": a charge tuple occurs twice");
+  // block form of charge conservation
+  for (int64_t b = 0; b < t.nblocks; ++b)
+    for (int c = 0; c < t.nsym; ++c) {
+      int64_t s = 0;
+      for (int i = 0; i < t.rank; ++i) s += int64_t(t.sig[i]) * t.q(b, i)[c];
+      if (norm_charge(s, t.sym_mod[c]) != t.n[c])
+        return set_error(YASTN_ERR_CHARGE, nm + ": a block violates sum_i s_i rho_i = n");
+    }
+  // one dim per charge and leg
+  legdims.assign(t.rank, {});
+  for (int64_t b = 0; b < t.nblocks; ++b)
+    for (int i = 0; i < t.rank; ++i) {
+      std::vector<int32_t> key(t.q(b, i), t.q(b, i) + t.nsym);
+      auto it = legdims[i].emplace(key, t.dim(b, i)).first;
+      if (it->second != t.dim(b, i)) return set_error(YASTN_ERR_SHAPE, nm + ": one charge has two dims on a leg");
+    }
+  // offsets: non-negative, blocks disjoint
+  std::vector<std::pair<int64_t, int64_t>> spans(t.nblocks);
+  for (int64_t b = 0; b < t.nblocks; ++b) {
+    if (t.offsets[b] < 0) return set_error(YASTN_ERR_ARG, nm + ": negative block offset");
+    spans[b] = {t.offsets[b], t.size(b)};
+  }
+  std::sort(spans.begin(), spans.end());
+  for (int64_t k = 1; k < t.nblocks; ++k)
+    if (spans[k - 1].first + spans[k - 1].second > spans[k].first)
+      return set_error(YASTN_ERR_ARG, nm + ": blocks overlap in the 1D buffer");
+  return YASTN_OK;
+}
+
+}  // namespace
+
+int64_t HostTensor::size(int64_t b) const {
+  int64_t s = 1;
+  for (int i = 0; i < rank; ++i) s *= dim(b, i);
+  return s;
+}
+
+yastn_status set_error(yastn_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+const char *last_error_cstr() { return g_err.c_str(); }
+
+yastn_status check_options(const yastn_options *o, yastn_options *out) {
+  yastn_options d{};
+  d.precision = YASTN_F64;
+  d.in_dtype = YASTN_DTYPE_F64;
+  d.out_dtype = YASTN_DTYPE_F64;
+  d.tile_rows = 0;
+  d.flags = 0;
+  if (o) d = *o;
+  if (d.precision < YASTN_F64 || d.precision > YASTN_BF16X6) return set_error(YASTN_ERR_ARG, "unknown precision");
+  if (d.in_dtype != YASTN_DTYPE_F64 && d.in_dtype != YASTN_DTYPE_F32) return set_error(YASTN_ERR_ARG, "unknown in_dtype");
+  if (d.out_dtype != YASTN_DTYPE_F64 && d.out_dtype != YASTN_DTYPE_F32) return set_error(YASTN_ERR_ARG, "unknown out_dtype");
+  if (d.precision == YASTN_F64 && (d.in_dtype != YASTN_DTYPE_F64 || d.out_dtype != YASTN_DTYPE_F64))
+    return set_error(YASTN_ERR_ARG, "F64 arithmetic needs F64 input and output buffers");
+  if (d.tile_rows != 0 && d.tile_rows != 16 && d.tile_rows != 32 && d.tile_rows != 64)
+    return set_error(YASTN_ERR_ARG, "tile_rows must be 0, 16, 32 or 64");
+  if (d.flags != 0) return set_error(YASTN_ERR_ARG, "flags must be 0");
+  *out = d;
+  return YASTN_OK;
+}
+
+yastn_status validate_problem(const yastn_problem &p, HostProblem &hp) {
+  const yastn_tensor_desc &A = p.a, &B = p.b;
+  if (p.ncontract < 0 || p.ncontract > YASTN_MAX_RANK) return set_error(YASTN_ERR_ARG, "ncontract out of range");
+  if (p.ncontract > 0 && (!p.axes_a || !p.axes_b)) return set_error(YASTN_ERR_ARG, "null axes");
+  if (A.rank < 0 || A.rank > YASTN_MAX_RANK || B.rank < 0 || B.rank > YASTN_MAX_RANK)
+    return set_error(YASTN_ERR_ARG, "rank out of range");
+  if (p.ncontract > A.rank || p.ncontract > B.rank) return set_error(YASTN_ERR_ARG, "more contracted legs than legs");
+  bool used_a[YASTN_MAX_RANK] = {false}, used_b[YASTN_MAX_RANK] = {false};
+  for (int c = 0; c < p.ncontract; ++c) {
+    int x = p.axes_a[c], y = p.axes_b[c];
+    if (x < 0 || x >= A.rank || y < 0 || y >= B.rank || used_a[x] || used_b[y])
+      return set_error(YASTN_ERR_ARG, "axes out of range or repeated");
+    used_a[x] = used_b[y] = true;
+  }
+  if (A.nsym != B.nsym) return set_error(YASTN_ERR_SYM, "A and B have different nsym");
+  if (A.nsym < 1 || A.nsym > YASTN_MAX_NSYM) return set_error(YASTN_ERR_ARG, "nsym out of range");
+  if (!A.sym_mod || !B.sym_mod) return set_error(YASTN_ERR_ARG, "null sym_mod");
+  for (int c = 0; c < A.nsym; ++c) {
+    if (A.sym_mod[c] != B.sym_mod[c]) return set_error(YASTN_ERR_SYM, "A and B have different symmetry");
+    if (A.sym_mod[c] < 0 || A.sym_mod[c] == 1) return set_error(YASTN_ERR_SYM, "sym_mod must be 0 (U(1)) or >= 2 (Z_m)");
+  }
+  yastn_status st;
+  if ((st = copy_tensor(A, hp.a, "A")) != YASTN_OK) return st;
+  if ((st = copy_tensor(B, hp.b, "B")) != YASTN_OK) return st;
+  std::vector<std::map<std::vector<int32_t>, int64_t>> da, db;
+  if ((st = check_tensor(hp.a, "A", da)) != YASTN_OK) return st;
+  if ((st = check_tensor(hp.b, "B", db)) != YASTN_OK) return st;
+  for (int c = 0; c < p.ncontract; ++c)
+    if (hp.a.sig[p.axes_a[c]] == hp.b.sig[p.axes_b[c]])
+      return set_error(YASTN_ERR_SIGNATURE, "a contracted leg pair has equal signatures");
+  for (int c = 0; c < p.ncontract; ++c)
+    for (auto &kv : da[p.axes_a[c]]) {
+      auto it = db[p.axes_b[c]].find(kv.first);
+      if (it != db[p.axes_b[c]].end() && it->second != kv.second)
+        return set_error(YASTN_ERR_SHAPE, "a contracted charge has different dims in A and B");
+    }
+  hp.nc = p.ncontract;
+  for (int c = 0; c < p.ncontract; ++c) {
+    hp.axes_a[c] = p.axes_a[c];
+    hp.axes_b[c] = p.axes_b[c];
+  }
+  hp.nfa = hp.nfb = 0;
+  for (int i = 0; i < A.rank; ++i)
+    if (!used_a[i]) hp.fa[hp.nfa++] = i;
+  for (int i = 0; i < B.rank; ++i)
+    if (!used_b[i]) hp.fb[hp.nfb++] = i;
+  for (int64_t b = 0; b < hp.a.nblocks; ++b) hp.a.numel += hp.a.size(b);
+  for (int64_t b = 0; b < hp.b.nblocks; ++b) hp.b.numel += hp.b.size(b);
+  return YASTN_OK;
+}
+
+void contracted_keys(const HostTensor &t, const int *axes, int nc, std::vector<int32_t> &keys) {
+  keys.assign(size_t(t.nblocks) * nc * t.nsym, 0);
+  for (int64_t b = 0; b < t.nblocks; ++b)
+    for (int c = 0; c < nc; ++c)
+      for (int s = 0; s < t.nsym; ++s) keys[(b * nc + c) * t.nsym + s] = t.q(b, axes[c])[s];
+}
+
+namespace {
+using Key = std::vector<int32_t>;
+
+Key legs_key(const HostTensor &t, int64_t b, const int *legs, int nl) {
+  Key k;
+  k.reserve(size_t(nl) * t.nsym);
+  for (int i = 0; i < nl; ++i) k.insert(k.end(), t.q(b, legs[i]), t.q(b, legs[i]) + t.nsym);
+  return k;
+}
+
+struct SectorBuild {
+  std::map<Key, int> rows, ctrs, cols;             // tuple -> local id (assigned after collection)
+  std::vector<std::pair<int64_t, int64_t>> pairs;  // (A block, B block)
+};
+}  // namespace
+
+yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::pair<int32_t, int32_t>> &pairs,
+                             int64_t a_base, int64_t b_base, PlanTables &t, int cb) {
+  const HostTensor &A = hp.a, &B = hp.b;
+  const int nsym = A.nsym, nc = hp.nc;
+  // ---- group matches by sector X = sum over A's contracted legs of s_i rho_i
+  std::map<Key, SectorBuild> sect;
+  for (auto &pr : pairs) {
+    int64_t ia = pr.first, jb = pr.second;
+    Key X(nsym, 0);
+    for (int s = 0; s < nsym; ++s) {
+      int64_t v = 0;
+      for (int c = 0; c < nc; ++c) v += int64_t(A.sig[hp.axes_a[c]]) * A.q(ia, hp.axes_a[c])[s];
+      X[s] = (int32_t)norm_charge(v, A.sym_mod[s]);
+    }
+    SectorBuild &sb = sect[X];
+    sb.rows.emplace(legs_key(A, ia, hp.fa, hp.nfa), 0);
+    sb.ctrs.emplace(legs_key(A, ia, hp.axes_a, nc), 0);
+    sb.cols.emplace(legs_key(B, jb, hp.fb, hp.nfb), 0);
+    sb.pairs.emplace_back(ia, jb);
+  }
+  // ---- A storage structure: classes of free legs, contracted positions
+  bool isctr[YASTN_MAX_RANK] = {false};
+  int cpos[YASTN_MAX_RANK];  // storage leg -> index in axes order
+  for (int c = 0; c < nc; ++c) {
+    isctr[hp.axes_a[c]] = true;
+    cpos[hp.axes_a[c]] = c;
+  }
+  int act_g[kMaxAct + 1], nact = 0, fcls[YASTN_MAX_RANK];
+  for (int q = 0; q < hp.nfa; ++q) {
+    int f = hp.fa[q], g = 0;
+    for (int l = f + 1; l < A.rank; ++l) g += isctr[l];
+    if (nact == 0 || act_g[nact - 1] != g) {
+      if (nact == kMaxAct) return set_error(YASTN_ERR_ARG, "leg interleaving of A too deep (more than 4 free-leg groups)");
+      act_g[nact++] = g;
+    }
+    fcls[q] = nact - 1;
+  }
+  // contracted legs in storage order (for P_a: dims of the last g contracted legs)
+  int ctr_storage[YASTN_MAX_RANK], nct = 0;
+  for (int l = 0; l < A.rank; ++l)
+    if (isctr[l]) ctr_storage[nct++] = cpos[l];
+  DevProb dp{};
+  dp.nact = nact;
+  dp.nc = nc;
+  dp.nfb = hp.nfb;
+  t.probs.push_back(dp);
+  // ---- output blocks: (A free tuple, B free tuple) reached by >= 1 pair, ascending order
+  std::map<Key, std::vector<int64_t>> cblocks;  // key -> shape
+  for (auto &kv : sect)
+    for (auto &pr : kv.second.pairs) {
+      Key k = legs_key(A, pr.first, hp.fa, hp.nfa);
+      Key kb = legs_key(B, pr.second, hp.fb, hp.nfb);
+      k.insert(k.end(), kb.begin(), kb.end());
+      auto it = cblocks.find(k);
+      if (it == cblocks.end()) {
+        std::vector<int64_t> shp;
+        for (int q = 0; q < hp.nfa; ++q) shp.push_back(A.dim(pr.first, hp.fa[q]));
+        for (int q = 0; q < hp.nfb; ++q) shp.push_back(B.dim(pr.second, hp.fb[q]));
+        cblocks.emplace(std::move(k), std::move(shp));
+      }
+    }
+  hp.c_rank = hp.nfa + hp.nfb;
+  for (int q = 0; q < hp.nfa; ++q) hp.c_sig[q] = A.sig[hp.fa[q]];
+  for (int q = 0; q < hp.nfb; ++q) hp.c_sig[hp.nfa + q] = B.sig[hp.fb[q]];
+  for (int s = 0; s < nsym; ++s) hp.c_n[s] = (int32_t)norm_charge(int64_t(A.n[s]) + B.n[s], A.sym_mod[s]);
+  hp.c_charges.clear();
+  hp.c_shapes.clear();
+  hp.c_offsets.clear();
+  std::map<Key, int64_t> coff;
+  int64_t pos = 0;
+  for (auto &kv : cblocks) {
+    hp.c_charges.insert(hp.c_charges.end(), kv.first.begin(), kv.first.end());
+    hp.c_shapes.insert(hp.c_shapes.end(), kv.second.begin(), kv.second.end());
+    hp.c_offsets.push_back(pos);
+    coff.emplace(kv.first, pos);
+    int64_t sz = 1;
+    for (int64_t d : kv.second) sz *= d;
+    pos += sz;
+  }
+  hp.c_numel = pos;
+  // ---- A block offsets and B block strides (plan-global indices)
+  for (int64_t b = 0; b < A.nblocks; ++b) t.aoff.push_back(A.offsets[b]);
+  for (int64_t b = 0; b < B.nblocks; ++b) {
+    DevBBlock bb{};
+    bb.off = B.offsets[b];
+    int64_t stride[YASTN_MAX_RANK];
+    int64_t st = 1;
+    for (int l = B.rank - 1; l >= 0; --l) {
+      stride[l] = st;
+      st *= B.dim(b, l);
+    }
+    for (int c = 0; c < nc; ++c) bb.sc[c] = (int32_t)stride[hp.axes_b[c]];
+    for (int q = 0; q < hp.nfb; ++q) bb.sf[q] = (int32_t)stride[hp.fb[q]];
+    t.bblocks.push_back(bb);
+  }
+  // ---- sectors, tuples, grids, pack items, tiles
+  yastn_stats &S = hp.stats;
+  S = yastn_stats{};
+  S.blocks_a = A.nblocks;
+  S.blocks_b = B.nblocks;
+  S.pairs = (int64_t)pairs.size();
+  S.sectors = (int64_t)sect.size();
+  S.c_blocks = (int64_t)cblocks.size();
+  S.c_numel = hp.c_numel;
+  S.numel_a = A.numel;
+  S.numel_b = B.numel;
+  const int TN = 16 * cb;
+  for (auto &kv : sect) {
+    SectorBuild &sb = kv.second;
+    int id = 0;
+    for (auto &r : sb.rows) r.second = id++;
+    id = 0;
+    for (auto &r : sb.ctrs) r.second = id++;
+    id = 0;
+    for (auto &r : sb.cols) r.second = id++;
+    const int R = (int)sb.rows.size(), Sn = (int)sb.ctrs.size(), Q = (int)sb.cols.size();
+    DevSector ds{};
+    ds.prob = prob;
+    ds.S = Sn;
+    ds.Q = Q;
+    ds.ctr0 = (int32_t)t.ctrs.size();
+    ds.col0 = (int32_t)t.cols.size();
+    // representative blocks for the dims of each tuple
+    std::vector<int64_t> row_rep(R, -1), ctr_rep(Sn, -1), col_rep(Q, -1);
+    std::vector<int32_t> agrid(size_t(R) * Sn, -1), bgrid(size_t(Sn) * Q, -1);
+    for (auto &pr : sb.pairs) {
+      int i = sb.rows.at(legs_key(A, pr.first, hp.fa, hp.nfa));
+      int s = sb.ctrs.at(legs_key(A, pr.first, hp.axes_a, nc));
+      int j = sb.cols.at(legs_key(B, pr.second, hp.fb, hp.nfb));
+      row_rep[i] = pr.first;
+      ctr_rep[s] = pr.first;
+      col_rep[j] = pr.second;
+      agrid[size_t(i) * Sn + s] = (int32_t)(a_base + pr.first);
+      bgrid[size_t(s) * Q + j] = (int32_t)(b_base + pr.second);
+    }
+    // contracted tuples (K space, ascending charge order)
+    int32_t K = 0;
+    for (int s = 0; s < Sn; ++s) {
+      DevCtrTuple ct{};
+      int64_t ia = ctr_rep[s];
+      int64_t k = 1;
+      for (int c = 0; c < nc; ++c) {
+        ct.dims[c] = (int32_t)A.dim(ia, hp.axes_a[c]);
+        k *= ct.dims[c];
+      }
+      ct.k = (int32_t)k;
+      ct.ko = K;
+      for (int c = 0; c < nc; ++c) {
+        int64_t p = 1;
+        for (int l = hp.axes_a[c] + 1; l < A.rank; ++l)
+          if (isctr[l]) p *= A.dim(ia, l);
+        ct.cac[c] = (int32_t)p;
+      }
+      for (int a = 0; a < nact; ++a) {
+        int64_t p = 1;
+        for (int g = 0; g < act_g[a]; ++g) p *= ct.dims[ctr_storage[nct - 1 - g]];
+        ct.p[a] = (int32_t)p;
+      }
+      K += ct.k;
+      t.ctrs.push_back(ct);
+    }
+    ds.K = K;
+    int32_t N = 0;
+    for (int j = 0; j < Q; ++j) {
+      DevColTuple ctp{};
+      int64_t n = 1;
+      for (int q = 0; q < hp.nfb; ++q) {
+        ctp.dims[q] = (int32_t)B.dim(col_rep[j], hp.fb[q]);
+        n *= ctp.dims[q];
+      }
+      ctp.n = (int32_t)n;
+      ctp.no = N;
+      N += ctp.n;
+      t.cols.push_back(ctp);
+    }
+    ds.N = N;
+    ds.bpack = t.bpack_elems;
+    t.bpack_elems += int64_t(K) * N;
+    const int32_t sec_id = (int32_t)t.sectors.size();
+    t.sectors.push_back(ds);
+    for (int s = 0; s < Sn; ++s)
+      for (int j = 0; j < Q; ++j) t.items.push_back(DevPackItem{sec_id, s, j, bgrid[size_t(s) * Q + j]});
+    std::vector<Key> rowkeys(R), colkeys(Q);
+    for (auto &r : sb.rows) rowkeys[r.second] = r.first;
+    for (auto &c : sb.cols) colkeys[c.second] = c.first;
+    int64_t M = 0;
+    for (int i = 0; i < R; ++i) {
+      DevRowTuple rt{};
+      rt.sector = sec_id;
+      int64_t ia = row_rep[i];
+      int64_t m = 1;
+      for (int q = 0; q < hp.nfa; ++q) m *= A.dim(ia, hp.fa[q]);
+      rt.m = (int32_t)m;
+      M += m;
+      for (int a = 0; a <= nact; ++a) {
+        int64_t p = 1;
+        for (int q = 0; q < hp.nfa; ++q)
+          if (fcls[q] >= a) p *= A.dim(ia, hp.fa[q]);
+        rt.lsuf[a] = (int32_t)p;
+      }
+      for (int c = 0; c < nc; ++c) {
+        int64_t p = 1;
+        for (int q = 0; q < hp.nfa; ++q)
+          if (hp.fa[q] > hp.axes_a[c]) p *= A.dim(ia, hp.fa[q]);
+        rt.fac[c] = (int32_t)p;
+      }
+      rt.agrid = (int64_t)t.agrid.size();
+      t.agrid.insert(t.agrid.end(), agrid.begin() + size_t(i) * Sn, agrid.begin() + size_t(i + 1) * Sn);
+      rt.cgrid = (int64_t)t.cgrid.size();
+      for (int j = 0; j < Q; ++j) {
+        Key k = rowkeys[i];
+        k.insert(k.end(), colkeys[j].begin(), colkeys[j].end());
+        auto it = coff.find(k);
+        t.cgrid.push_back(it == coff.end() ? -1 : it->second);
+      }
+      const int32_t row_id = (int32_t)t.rows.size();
+      t.rows.push_back(rt);
+      for (int32_t m0 = 0; m0 < rt.m; m0 += kWaveRows)
+        for (int32_t n0 = 0; n0 < N; n0 += TN) {
+          DevTile tl{};
+          tl.rowtuple = row_id;
+          tl.m0 = m0;
+          tl.n0 = n0;
+          tl.nrows = (int16_t)std::min<int32_t>(kWaveRows, rt.m - m0);
+          tl.ncols = (int16_t)std::min<int32_t>(TN, N - n0);
+          t.tiles.push_back(tl);
+          S.tiles += 1;
+          S.mfma_flops += 2.0 * (16.0 * ((tl.nrows + 15) / 16)) * (4.0 * ((K + 3) / 4)) * (16.0 * ((tl.ncols + 15) / 16));
+        }
+    }
+    S.max_m = std::max<int64_t>(S.max_m, M);
+    S.max_k = std::max<int64_t>(S.max_k, K);
+    S.max_n = std::max<int64_t>(S.max_n, N);
+    for (auto &pr : sb.pairs) {
+      double m = 1, k = 1, n = 1;
+      for (int q = 0; q < hp.nfa; ++q) m *= double(A.dim(pr.first, hp.fa[q]));
+      for (int c = 0; c < nc; ++c) k *= double(A.dim(pr.first, hp.axes_a[c]));
+      for (int q = 0; q < hp.nfb; ++q) n *= double(B.dim(pr.second, hp.fb[q]));
+      S.useful_flops += 2.0 * m * k * n;
+    }
+  }
+  return YASTN_OK;
+}
+
+void finish_tiles(Plan &plan) {
+  PlanTables &t = plan.t;
+  const size_t in_b = plan.opts.in_dtype == YASTN_DTYPE_F64 ? 8 : 4;
+  const size_t out_b = plan.opts.out_dtype == YASTN_DTYPE_F64 ? 8 : 4;
+  for (auto &hp : plan.probs)
+    hp.stats.alg_bytes = double(hp.a.numel + hp.b.numel) * in_b + double(hp.c_numel) * out_b;
+  // longest tiles first within each launch group: static round-robin over
+  // waves then balances the load
+  const int np = (int)plan.probs.size();
+  plan.prob_t0.push_back((int32_t)t.tiles.size());
+  plan.prob_i0.push_back((int32_t)t.items.size());
+  plan.groups.clear();
+  for (int p0 = 0; p0 < np; p0 += kMaxProbs) {
+    Group g{};
+    g.plo = p0;
+    g.phi = std::min(np, p0 + kMaxProbs);
+    g.t0 = plan.prob_t0[g.plo];
+    g.t1 = plan.prob_t0[g.phi];
+    g.i0 = plan.prob_i0[g.plo];
+    g.i1 = plan.prob_i0[g.phi];
+    std::vector<double> cost(size_t(g.t1 - g.t0));
+    for (int32_t i = g.t0; i < g.t1; ++i) {
+      const DevTile &tl = t.tiles[i];
+      const DevSector &ds = t.sectors[t.rows[tl.rowtuple].sector];
+      double rows = 16.0 * ((tl.nrows + 15) / 16), cols = 16.0 * ((tl.ncols + 15) / 16);
+      double k4 = 4.0 * ((ds.K + 3) / 4);
+      cost[i - g.t0] = 2.0 * rows * k4 * cols / 9.8 + 8.0 * tl.nrows * (double(ds.K) + tl.ncols);
+    }
+    std::vector<size_t> order(cost.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+    std::vector<DevTile> sorted(order.size());
+    for (size_t i = 0; i < order.size(); ++i) sorted[i] = t.tiles[g.t0 + order[i]];
+    std::copy(sorted.begin(), sorted.end(), t.tiles.begin() + g.t0);
+    plan.groups.push_back(g);
+  }
+  const size_t elem = plan.opts.precision == YASTN_F64 ? 8 : 4;
+  plan.ws_bytes = ((size_t(t.bpack_elems) * elem + 255) / 256) * 256;
+}
+
+}  // namespace yastn

@@ -1,0 +1,132 @@
+// Internal plan layout shared by the host planner (host.cpp) and the HIP
+// kernels (device.hip).  Plain structs of fixed-width fields so host and
+// device agree on the layout.
+//
+// Vocabulary (paper Sec. II.B, contraction identity sum_X A_IX B_XJ):
+//   sector X      fused contracted charge, X = sum over A's contracted legs of
+//                 s_i rho_i; one dense GEMM C_X = A_X B_X per sector;
+//   row tuple i   charges on A's free legs (one block-row of A_X / C_X);
+//   ctr tuple s   charges on the contracted legs (one block-column of A_X);
+//   col tuple j   charges on B's free legs (one block-column of B_X / C_X).
+// Output block (i, j) is a C-order array of m_i x n_j elements (A's free legs
+// first, then B's), so the sub-block (i, j) of C_X *is* an output block.
+//
+// A-operand address factorisation.  For A block (i, s) with legs in storage
+// order, the offset of element (row ra, contracted index kd) is
+//     sum_f x_f(ra) * stride_f  +  sum_c y_c(kd) * stride_c,
+// stride_l = product of the dims of the legs after l.  Group the free legs by
+// how many contracted legs follow them ("class" g); legs of one class are
+// contiguous and the class index falls along storage order.  Then
+//     sum_f x_f stride_f = sum_a P_a(s) * RG_a(ra),
+//     RG_a(ra) = (ra mod Lsuf_a) - (ra mod Lsuf_{a+1}),
+// with Lsuf_a = product of the free dims of classes a..end (Lsuf_0 = m_i,
+// Lsuf_nact = 1) and P_a(s) = product of the dims of the last g_a contracted
+// legs (1 for g_a = 0).  The contracted part is
+//     sum_c y_c(kd) * FAc_c(i) * CAc_c(s),
+// FAc_c = product of free dims after leg c, CAc_c = product of contracted
+// dims after leg c.  So every element costs nact multiply-adds on top of a
+// per-k offset table built once per tile.
+#pragma once
+#include <cstdint>
+
+namespace yastn {
+
+constexpr int kMaxRank = 8;
+constexpr int kMaxAct = 4;     // free-leg classes of A (<= min(#free, #contracted + 1))
+constexpr int kMaxJobs = 32;   // plans per launch
+constexpr int kMaxProbs = 64;  // problems per launch (pointer triples in kernel args)
+constexpr int kWaveRows = 64;  // rows per wave tile (4 MFMA row blocks of 16)
+constexpr int kKChunk = 128;   // contracted indices per LDS offset table
+
+struct DevProb {               // one problem of a plan
+  int32_t nact;                // active free-leg classes of A
+  int32_t nc;                  // contracted legs
+  int32_t nfb;                 // free legs of B
+  int32_t pad;
+};
+
+struct DevSector {             // one (problem, sector)
+  int32_t prob;
+  int32_t S, Q;                // contracted tuples, col tuples
+  int32_t K, N;                // K_X, N_X
+  int32_t ctr0, col0;          // first ctr tuple / col tuple (plan-global index)
+  int32_t pad;
+  int64_t bpack;               // element offset of packed B_X (K_X x N_X, row-major) in workspace
+};
+
+struct DevRowTuple {           // one (problem, sector, A free tuple)
+  int32_t sector;              // plan-global sector index
+  int32_t m;                   // rows
+  int64_t agrid;               // first of S entries in agrid (A block or -1)
+  int64_t cgrid;               // first of Q entries in cgrid (C element offset or -1)
+  int32_t lsuf[kMaxAct + 1];   // Lsuf_a, a = 0..nact
+  int32_t fac[kMaxRank];       // FAc_c, contracted legs in axes order
+};
+
+struct DevCtrTuple {           // one (problem, sector, contracted tuple)
+  int32_t k, ko;               // k_s and its first index in the sector's K space
+  int32_t dims[kMaxRank];      // contracted dims in axes order
+  int32_t cac[kMaxRank];       // CAc_c in axes order
+  int32_t p[kMaxAct];          // P_a
+};
+
+struct DevColTuple {           // one (problem, sector, B free tuple)
+  int32_t n, no;               // n_j and its first column in the sector
+  int32_t dims[kMaxRank];      // B free dims (B storage order)
+};
+
+struct DevBBlock {             // one B block, strides for the pack kernel
+  int64_t off;
+  int32_t sc[kMaxRank];        // strides of contracted legs (axes order)
+  int32_t sf[kMaxRank];        // strides of free legs (storage order)
+};
+
+struct DevTile {               // one wave tile
+  int32_t rowtuple;            // plan-global row tuple
+  int32_t m0;                  // first row within the row tuple
+  int32_t n0;                  // first column within the sector
+  int16_t nrows, ncols;        // extent (<= 64 each)
+};
+
+struct DevPackItem {           // one (sector, s, j) sub-block of packed B_X
+  int32_t sector;
+  int32_t s, j;
+  int32_t bblk;                // B block (plan-global) or -1 (absent: zeros)
+};
+
+struct DevPlan {               // device-resident table of the plan's arrays
+  const DevProb *probs;
+  const DevSector *sectors;
+  const DevRowTuple *rows;
+  const DevCtrTuple *ctrs;
+  const DevColTuple *cols;
+  const int32_t *agrid;        // A block (plan-global) or -1
+  const int64_t *aoff;         // element offset of each A block (plan-global)
+  const int64_t *cgrid;        // C element offset or -1
+  const DevBBlock *bblocks;
+  const DevTile *tiles;
+  const DevPackItem *items;
+  int32_t ntiles, nitems;
+};
+
+struct ProbPtrs {
+  const void *a, *b;
+  void *c;
+};
+
+struct JobArg {                // a range of one plan's problems inside a launch
+  const DevPlan *plan;
+  char *ws;                    // job workspace (packed B)
+  int32_t tile0, item0;        // first launch-global tile / pack item of this job
+  int32_t ptile0, pitem0;      // first plan-local tile / pack item of this job
+  int32_t prob0;               // entry of LaunchArgs::p for the plan's problem plo
+  int32_t plo;                 // first plan problem covered by this job
+};
+
+struct LaunchArgs {
+  int32_t njobs, ntiles, nitems, pad;
+  JobArg jobs[kMaxJobs];
+  ProbPtrs p[kMaxProbs];
+};
+
+}  // namespace yastn

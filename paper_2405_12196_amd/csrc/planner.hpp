@@ -1,0 +1,92 @@
+// Host-side plan structures (validation, structure building, tiling).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/yastn.h"
+#include "plan.hpp"
+
+namespace yastn {
+
+struct HostTensor {
+  int rank = 0, nsym = 0;
+  int32_t sym_mod[YASTN_MAX_NSYM] = {0};
+  int8_t sig[YASTN_MAX_RANK] = {0};
+  int32_t n[YASTN_MAX_NSYM] = {0};
+  int64_t nblocks = 0;
+  std::vector<int32_t> charges;  // [nblocks][rank][nsym], Z_m components reduced into [0, m)
+  std::vector<int64_t> shapes;   // [nblocks][rank]
+  std::vector<int64_t> offsets;  // [nblocks]
+  int64_t numel = 0;             // stored elements (sum of block sizes)
+  const int32_t *q(int64_t b, int leg) const { return &charges[(b * rank + leg) * nsym]; }
+  int64_t dim(int64_t b, int leg) const { return shapes[b * rank + leg]; }
+  int64_t size(int64_t b) const;
+};
+
+struct HostProblem {
+  HostTensor a, b;
+  int nc = 0;
+  int axes_a[YASTN_MAX_RANK] = {0}, axes_b[YASTN_MAX_RANK] = {0};
+  int nfa = 0, nfb = 0;
+  int fa[YASTN_MAX_RANK] = {0}, fb[YASTN_MAX_RANK] = {0};
+  // output C (rule: A free legs then B free legs, ascending charge order)
+  int c_rank = 0;
+  int8_t c_sig[YASTN_MAX_RANK] = {0};
+  int32_t c_n[YASTN_MAX_NSYM] = {0};
+  std::vector<int32_t> c_charges;
+  std::vector<int64_t> c_shapes, c_offsets;
+  int64_t c_numel = 0;
+  yastn_stats stats{};
+};
+
+// Device tables of a plan, built on the host and uploaded once.
+struct PlanTables {
+  std::vector<DevProb> probs;
+  std::vector<DevSector> sectors;
+  std::vector<DevRowTuple> rows;
+  std::vector<DevCtrTuple> ctrs;
+  std::vector<DevColTuple> cols;
+  std::vector<int32_t> agrid;
+  std::vector<int64_t> aoff;
+  std::vector<int64_t> cgrid;
+  std::vector<DevBBlock> bblocks;
+  std::vector<DevTile> tiles;
+  std::vector<DevPackItem> items;
+  int64_t bpack_elems = 0;  // packed B elements in the workspace
+};
+
+// Problems are launched in groups of at most kMaxProbs (their device pointers
+// travel as kernel arguments); tiles are cost-sorted within a group.
+struct Group {
+  int32_t plo, phi;          // problems [plo, phi)
+  int32_t t0, t1;            // plan-local tiles
+  int32_t i0, i1;            // plan-local pack items
+};
+
+struct Plan {
+  std::vector<HostProblem> probs;
+  std::vector<int32_t> prob_t0, prob_i0;  // first tile / item of each problem (before sorting)
+  std::vector<Group> groups;
+  yastn_options opts{};
+  PlanTables t;
+  int cb = 4;               // column blocks (16 columns each) per wave tile
+  void *dev_mem = nullptr;  // one device allocation holding every table
+  DevPlan *dplan = nullptr; // device copy of the table of pointers
+  size_t ws_bytes = 0;
+  int device = 0;
+};
+
+// error reporting (thread-local message)
+yastn_status set_error(yastn_status s, const std::string &msg);
+
+// host.cpp
+yastn_status check_options(const yastn_options *o, yastn_options *out);
+yastn_status validate_problem(const yastn_problem &p, HostProblem &hp);
+void contracted_keys(const HostTensor &t, const int *axes, int nc, std::vector<int32_t> &keys);
+yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::pair<int32_t, int32_t>> &pairs,
+                             int64_t a_base, int64_t b_base, PlanTables &t, int cb);
+void finish_tiles(Plan &plan);
+
+}  // namespace yastn

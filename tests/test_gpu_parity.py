@@ -1,0 +1,257 @@
+"""Parity of the HIP path with the CPU oracle (run on an MI355X).
+
+Structure (block list, shapes, offsets, signature, total charge) must match
+the oracle bit for bit; FP64 values within 1e-12 relative Frobenius error
+(per output tensor, and 1e-11 relative per block); reduced precisions within
+the tolerances stated in each test.  Every output element is pre-filled with
+NaN, so an element the kernels fail to write shows up as NaN.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.helpers import random_problem
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU hosts deselect -m gpu
+    pytest.skip("no GPU", allow_module_level=True)
+
+from tests import gpu_util as G  # noqa: E402
+
+TOL_F64 = 1e-12
+TOL = {"f32": 1e-6, "bf16x3": 2e-5, "bf16x6": 1e-6}
+
+
+def check_f64(s, vals, ref, tol=TOL_F64):
+    assert G.structure_equal(s, ref), "structure differs from the oracle"
+    assert not np.any(np.isnan(vals)), "unwritten output elements"
+    err = oracle.rel_frobenius(vals, ref.data)
+    assert err <= tol, f"relative Frobenius error {err:.3e}"
+    for k in range(ref.nblocks):
+        o, n = int(ref.offsets[k]), int(ref.block_sizes[k])
+        r = ref.data[o:o + n]
+        den = max(float(np.sqrt(np.sum(r * r))), 1e-300)
+        assert float(np.sqrt(np.sum((vals[o:o + n] - r) ** 2))) / den <= 1e-11 or np.allclose(vals[o:o + n], r, atol=1e-14)
+    return err
+
+
+# ---------------------------------------------------------------- config 1
+def test_config1_f64():
+    (p,) = W.config1()
+    ref = oracle.tensordot_dense(p.a, p.b, p.axes_a, p.axes_b)
+    pl, (s,), (v,) = G.run([(p.a, p.b, p.axes_a, p.axes_b)])
+    check_f64(s, v, ref)
+    st = pl.stats(0)
+    assert (st["pairs"], st["sectors"], st["c_blocks"], st["c_numel"]) == (325, 9, 85, 17712)
+    assert st["useful_flops"] == 2199168
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "bf16x6"])
+def test_paper_example_exact_all_precisions(prec):
+    H = W.spin_half_pair_hamiltonian()
+    ref = oracle.tensordot_blockpair(H, H, (2, 3), (0, 1))
+    _, (s,), (v,) = G.run([(H, H, (2, 3), (0, 1))], precision=prec)
+    assert G.structure_equal(s, ref)
+    assert np.array_equal(v, ref.data)  # dyadic values: exact in every precision
+
+
+# ------------------------------------------------------- random structures
+@pytest.mark.parametrize("seed", range(48))
+def test_random_structures_f64(seed):
+    sym = ["U1", "Z2", "U1xZ2", "Z3", "U1xU1"][seed % 5]
+    a, b, xa, xb = random_problem(seed + 2000, sym, rank_a=1 + seed % 5, rank_b=1 + (seed // 5) % 5,
+                                  max_sectors=4, max_dim=5 + seed % 7, keep=0.75 if seed % 3 else None,
+                                  shuffle=seed % 4 == 0, drop_partner=seed % 6 == 1)
+    ref = oracle.tensordot_blockpair(a, b, xa, xb)
+    _, (s,), (v,) = G.run([(a, b, xa, xb)])
+    check_f64(s, v, ref)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_batch_one_launch(seed):
+    probs = []
+    for i in range(7):
+        a, b, xa, xb = random_problem(seed * 100 + i + 4000, ["U1", "Z2", "U1xZ2"][i % 3],
+                                      max_sectors=4, max_dim=6, keep=0.8)
+        probs.append((a, b, xa, xb))
+    _, S, V = G.run(probs)
+    for (a, b, xa, xb), s, v in zip(probs, S, V):
+        check_f64(s, v, oracle.tensordot_blockpair(a, b, xa, xb))
+
+
+# ---------------------------------------------------------- edge cases
+def _u1(s, pairs):
+    return W.Leg(s, tuple((q,) for q, _ in pairs), tuple(d for _, d in pairs))
+
+
+def test_large_k_several_chunks_and_tiles():
+    # one big sector: K = 300 (> one 128-entry offset table), M, N > 64 (several tiles)
+    l1 = _u1(1, [(0, 70), (1, 3)])
+    l2 = _u1(1, [(0, 20), (1, 15)])
+    a = W.rand([l1, l2, l2.conj()], (0,), (0,), 5)
+    b = W.rand([l2, l2.conj(), _u1(-1, [(0, 90), (1, 2)])], (0,), (0,), 6)
+    ref = oracle.tensordot_blockpair(a, b, (1, 2), (1, 0))
+    _, (s,), (v,) = G.run([(a, b, (1, 2), (1, 0))])
+    check_f64(s, v, ref)
+
+
+def test_outer_product_and_full_contraction():
+    l = _u1(1, [(-1, 3), (0, 5), (1, 2)])
+    a = W.rand([l, l.conj()], (0,), (0,), 1)
+    b = W.rand([l, l.conj(), l], (1,), (0,), 2)
+    ref = oracle.tensordot_blockpair(a, b, (), ())          # no contracted legs
+    _, (s,), (v,) = G.run([(a, b, (), ())])
+    check_f64(s, v, ref)
+    c = W.rand([l.conj(), l], (0,), (0,), 3)
+    ref = oracle.tensordot_blockpair(a, c, (0, 1), (0, 1))  # rank-0 result
+    _, (s,), (v,) = G.run([(a, c, (0, 1), (0, 1))])
+    check_f64(s, v, ref)
+
+
+def test_empty_inputs_and_no_matches():
+    l = _u1(1, [(0, 2), (1, 3)])
+    a = W.rand([l, l], (7,), (0,), 1)   # no block can carry n = 7: empty tensor
+    b = W.rand([l.conj(), l], (0,), (0,), 2)
+    _, (s,), (v,) = G.run([(a, b, (1,), (0,))])
+    assert s.nblocks == 0 and s.numel == 0
+    a = W.rand([l, _u1(1, [(5, 2)])], (5,), (0,), 3)  # contracted charges never shared
+    b = W.rand([_u1(-1, [(4, 2)]), l], (-4,), (0,), 4)
+    _, (s,), (v,) = G.run([(a, b, (1,), (0,))])
+    assert s.nblocks == 0
+
+
+def test_permuted_legs_and_gapped_buffers():
+    a, b, xa, xb = random_problem(77, "U1xU1", rank_a=6, rank_b=4, ncon=3, max_sectors=3, max_dim=4,
+                                  shuffle=True)
+    ref = oracle.tensordot_blockpair(a, b, xa, xb)
+    _, (s,), (v,) = G.run([(a, b, xa, xb)])
+    check_f64(s, v, ref)
+
+
+# ------------------------------------------------------------ config 2
+def test_config2_chain_f64():
+    t = W.config2()
+    steps = [("C", "T1"), (None, "T4"), (None, "A"), (None, "Ac")]
+    cur_ref, cur_gpu = None, None
+    for (an, bn), (ax, bx) in zip(steps, t["axes"]):
+        a_ref = t[an] if an else cur_ref
+        ref = oracle.tensordot_blockpair(a_ref, t[bn], ax, bx)
+        a_in = t[an] if an else cur_gpu
+        _, (s,), (v,) = G.run([(a_in, t[bn], ax, bx)])
+        check_f64(s, v, ref)
+        cur_ref, cur_gpu = ref, G.as_block_tensor(s, v)
+
+
+# ------------------------------------------------------------ config 3
+def test_config3_batched_one_launch():
+    probs = [(p.a, p.b, p.axes_a, p.axes_b) for p in W.config3()]
+    pl, S, V = G.run(probs)
+    for (a, b, xa, xb), s, v in zip(probs, S, V):
+        check_f64(s, v, oracle.tensordot_blockpair(a, b, xa, xb))
+    assert sum(pl.stats(i)["sectors"] for i in range(len(probs))) == 664
+
+
+# ------------------------------------------------------- reduced precision
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("in_f32", [True, False])
+def test_reduced_precision_config1(prec, in_f32):
+    import paper_2405_12196_amd as Y
+    (p,) = W.config1()
+    ref = oracle.tensordot_dense(p.a, p.b, p.axes_a, p.axes_b)
+    _, (s,), (v,) = G.run([(p.a, p.b, p.axes_a, p.axes_b)], precision=prec,
+                          in_dtype=Y.DTYPE_F32 if in_f32 else Y.DTYPE_F64, out_dtype=Y.DTYPE_F64)
+    assert G.structure_equal(s, ref)
+    err = oracle.rel_frobenius(v, ref.data)
+    assert err <= TOL[prec], f"{prec}: {err:.3e}"
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "bf16x6"])
+def test_reduced_precision_config2_step3(prec):
+    t = W.config2()
+    a = oracle.tensordot_blockpair(oracle.tensordot_blockpair(t["C"], t["T1"], (1,), (0,)), t["T4"], (0,), (0,))
+    ref = oracle.tensordot_blockpair(a, t["A"], (0, 3), (0, 1))
+    _, (s,), (v,) = G.run([(a, t["A"], (0, 3), (0, 1))], precision=prec)
+    assert G.structure_equal(s, ref)
+    assert oracle.rel_frobenius(v, ref.data) <= TOL[prec]
+
+
+# ------------------------------------------------------------ invariants
+def test_repeat_runs_bitwise_identical():
+    t = W.config2()
+    a = oracle.tensordot_blockpair(t["C"], t["T1"], (1,), (0,))
+    _, _, (v1,) = G.run([(a, t["T4"], (0,), (0,))])
+    _, _, (v2,) = G.run([(a, t["T4"], (0,), (0,))], repeat=3)
+    assert np.array_equal(v1, v2)
+
+
+def test_power_of_two_gauge_bitwise():
+    (p,) = W.config1()
+    a, b = p.a.copy(), p.b.copy()
+    for i in range(a.nblocks):  # contracted sector rho = 1 on A's leg 2 (and B's leg 0)
+        if a.charges[i, 2, 0] == 1:
+            a.data[a.offsets[i]:a.offsets[i] + a.block_sizes[i]] *= 4.0
+    for j in range(b.nblocks):
+        if b.charges[j, 0, 0] == 1:
+            b.data[b.offsets[j]:b.offsets[j] + b.block_sizes[j]] *= 0.25
+    _, _, (v0,) = G.run([(p.a, p.b, p.axes_a, p.axes_b)])
+    _, _, (v1,) = G.run([(a, b, p.axes_a, p.axes_b)])
+    assert np.array_equal(v0, v1)
+
+
+def test_fusion_invariance_on_gpu():
+    a, b, xa, xb = random_problem(321, "U1", rank_a=4, rank_b=3, ncon=2, max_sectors=3, max_dim=4, keep=0.8)
+    fa = tuple(i for i in range(a.rank) if i not in xa)
+    fb = tuple(i for i in range(b.rank) if i not in xb)
+
+    def cons(t, legs):
+        return {tuple(tuple(int(v) for v in t.charges[k, x, :]) for x in legs):
+                tuple(int(t.shapes[k, x]) for x in legs) for k in range(t.nblocks)}
+    tmpl = {**cons(a, xa), **cons(b, xb)}
+    A, ra = oracle.fuse_legs(a, (fa, xa), templates=[None, tmpl])
+    B, rb = oracle.fuse_legs(b, (xb, fb), templates=[tmpl, None])
+    _, (s,), (v,) = G.run([(A, B, (1,), (0,))])
+    back = oracle.unfuse_legs(G.as_block_tensor(s, v), [ra[0], rb[1]])
+    _, (s2,), (v2,) = G.run([(a, b, xa, xb)])
+    direct = G.as_block_tensor(s2, v2)
+    idx = {tuple(back.charges[k].ravel()): k for k in range(back.nblocks)}
+    for k in range(direct.nblocks):
+        kk = idx[tuple(direct.charges[k].ravel())]
+        np.testing.assert_allclose(back.block(kk), direct.block(k), rtol=1e-12, atol=1e-13)
+
+
+def test_multi_plan_launch_equals_separate():
+    import paper_2405_12196_amd as Y
+    probs = [random_problem(900 + i, ["U1", "Z2", "U1xU1"][i], max_sectors=4, max_dim=6) for i in range(3)]
+    sep = [G.run([p])[2][0] for p in probs]
+    plans = [Y.plan([p]) for p in probs]
+    jobs, outs = [], []
+    for pl, (a, b, _, _) in zip(plans, probs):
+        c, o = G.alloc_out(pl, 0)
+        jobs.append((pl, [G.upload(a)], [G.upload(b)], [c], G.workspace(pl)))
+        outs.append((c, o))
+    Y.contract_jobs(jobs)
+    torch.cuda.synchronize()
+    for (c, o), v in zip(outs, sep):
+        assert np.array_equal(c.cpu().numpy()[:o.numel], v)
+
+
+# ----------------------------------------------------------------- norms
+@pytest.mark.parametrize("n", [0, 1, 1000, 3994616])
+def test_norm_f64(n):
+    import paper_2405_12196_amd as Y
+    x = np.random.default_rng(n).standard_normal(max(n, 1))[:n]
+    xd = torch.from_numpy(x.copy() if n else np.zeros(1)).to(G.DEV)
+    out = torch.zeros(2, dtype=torch.float64, device=G.DEV)
+    ws = torch.empty(Y.norm_workspace_bytes(), dtype=torch.uint8, device=G.DEV)
+    Y.norm(xd, n, out, ws)
+    torch.cuda.synchronize()
+    fro, mx = out.cpu().numpy()
+    t = W.BlockTensor((0,), np.zeros(1, np.int8), np.zeros(1, np.int32), np.zeros((1, 1, 1), np.int32),
+                      np.array([[max(n, 1)]], np.int64), np.zeros(1, np.int64), x if n else np.zeros(1))
+    rf, rm = oracle.norms(t) if n else (0.0, 0.0)
+    assert abs(fro - rf) <= 1e-13 * max(rf, 1.0)
+    assert mx == rm
