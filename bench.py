@@ -1,0 +1,369 @@
+#!/usr/bin/env python3
+"""Benchmark: one CTMRG enlarged-corner step on one MI355X.
+
+Workload (FP64, U(1)xU(1)): environment chi = 128 in 15 sectors, bond D = 8
+in 5 sectors, physical d = 4; four chained block-sparse tensordots
+    C.T1 ((1),(0)),  .T4 ((0),(0)),  .A ((0,3),(0,1)),  .A* ((0,2,6),(0,1,4))
+followed by the FP64 Frobenius/max norm of the last output (the input of the
+CTM truncation).  Synthetic i.i.d. N(0,1) blocks, fixed seeds.  Plans are
+built once before timing (the block structure repeats across CTM iterations).
+
+A step = the four contractions + the norm.  value = useful TFLOP/s
+(sum over matched block pairs of 2 m k n, over the four contractions) per
+step time.  Also reported: p50/p99 step latency, the same step in the plain
+per-sector FP64 form on the same GPU (gather each operand into its fused
+sector matrices, one torch.matmul per sector, scatter back), the roofline of
+the dominant kernel (HIP events on the launch stream), and the CPU oracle
+(block-pair form) timed on the host cores on a bounded sample.
+"""
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_MFMA_PEAK_TFS = 78.6      # MI355X dense FP64 matrix
+STEPS = [("C", "T1"), (None, "T4"), (None, "A"), (None, "Ac")]
+
+
+# ------------------------------------------------------------------ HIP events
+class HipEvents:
+    def __init__(self):
+        self.hip = ctypes.CDLL("libamdhip64.so")
+        self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.made = []
+
+    def new(self):
+        e = ctypes.c_void_p()
+        assert self.hip.hipEventCreate(ctypes.byref(e)) == 0
+        self.made.append(e.value)
+        return e.value
+
+    def record(self, e, stream):
+        assert self.hip.hipEventRecord(ctypes.c_void_p(e), ctypes.c_void_p(stream)) == 0
+
+    def ms(self, a, b):
+        f = ctypes.c_float()
+        assert self.hip.hipEventElapsedTime(ctypes.byref(f), ctypes.c_void_p(a), ctypes.c_void_p(b)) == 0
+        return float(f.value)
+
+    def close(self):
+        for e in self.made:
+            self.hip.hipEventDestroy(ctypes.c_void_p(e))
+
+
+# ------------------------------------------------- plain per-sector FP64 form
+def _key(t, b, legs):
+    return tuple(int(v) for x in legs for v in t.charges[b, x, :])
+
+
+def plain_maps(A, B, xa, xb, Cs):
+    """Index maps of the plain per-sector form (benchmark harness, host numpy):
+    for every sector X, gather indices of the fused A_X (M x K) and B_X (K x N)
+    and scatter indices of C_X into C's blocks.  Index len(data) is a zero slot
+    (absent sub-blocks); for C it is a dump slot."""
+    fa = [i for i in range(A.sig.shape[0]) if i not in xa]
+    fb = [i for i in range(B.sig.shape[0]) if i not in xb]
+    sm = tuple(A.sym_mod)
+
+    def sector(t, b, legs, sig):
+        out = []
+        for c in range(len(sm)):
+            v = sum(int(sig[x]) * int(t.charges[b, x, c]) for x in legs)
+            out.append(v % sm[c] if sm[c] else v)
+        return tuple(out)
+    bk = {}
+    for j in range(B.charges.shape[0]):
+        bk.setdefault(_key(B, j, xb), []).append(j)
+    sect = {}
+    for i in range(A.charges.shape[0]):
+        kc = _key(A, i, xa)
+        if kc not in bk:
+            continue
+        X = sector(A, i, xa, A.sig)
+        s = sect.setdefault(X, {"rows": {}, "ks": {}, "cols": {}, "a": {}, "b": {}})
+        s["rows"][_key(A, i, fa)] = i
+        s["ks"][kc] = i
+        s["a"][(_key(A, i, fa), kc)] = i
+        for j in bk[kc]:
+            s["cols"][_key(B, j, fb)] = j
+            s["b"][(kc, _key(B, j, fb))] = j
+    cidx = {tuple(int(v) for v in Cs.charges[k].ravel()): k for k in range(Cs.charges.shape[0])}
+    nA = int(np.max(A.offsets + np.prod(A.shapes, axis=1))) if A.charges.shape[0] else 0
+    nB = int(np.max(B.offsets + np.prod(B.shapes, axis=1))) if B.charges.shape[0] else 0
+    nC = int(Cs.numel)
+    gA, gB, sC, mats = [], [], [], []
+    oa = ob = 0
+    for X in sorted(sect):
+        s = sect[X]
+        rows, ks, cols = sorted(s["rows"]), sorted(s["ks"]), sorted(s["cols"])
+        mdim = [int(np.prod([A.shapes[s["rows"][r], x] for x in fa])) for r in rows]
+        kdim = [int(np.prod([A.shapes[s["ks"][k], x] for x in xa])) for k in ks]
+        ndim = [int(np.prod([B.shapes[s["cols"][c], y] for y in fb])) for c in cols]
+        M, K, N = sum(mdim), sum(kdim), sum(ndim)
+        ia = np.full((M, K), nA, dtype=np.int64)
+        ib = np.full((K, N), nB, dtype=np.int64)
+        ic = np.full((M, N), nC, dtype=np.int64)
+        r0 = 0
+        for r, m in zip(rows, mdim):
+            k0 = 0
+            for k, kk in zip(ks, kdim):
+                i = s["a"].get((r, k))
+                if i is not None:
+                    shp = tuple(int(v) for v in A.shapes[i])
+                    blk = np.arange(int(np.prod(shp)), dtype=np.int64).reshape(shp)
+                    ia[r0:r0 + m, k0:k0 + kk] = blk.transpose(fa + list(xa)).reshape(m, kk) + int(A.offsets[i])
+                k0 += kk
+            c0 = 0
+            for c, n in zip(cols, ndim):
+                k = cidx.get(r + c)
+                if k is not None:
+                    ic[r0:r0 + m, c0:c0 + n] = np.arange(m * n, dtype=np.int64).reshape(m, n) + int(Cs.offsets[k])
+                c0 += n
+            r0 += m
+        k0 = 0
+        for k, kk in zip(ks, kdim):
+            c0 = 0
+            for c, n in zip(cols, ndim):
+                j = s["b"].get((k, c))
+                if j is not None:
+                    shp = tuple(int(v) for v in B.shapes[j])
+                    blk = np.arange(int(np.prod(shp)), dtype=np.int64).reshape(shp)
+                    ib[k0:k0 + kk, c0:c0 + n] = blk.transpose(list(xb) + fb).reshape(kk, n) + int(B.offsets[j])
+                c0 += n
+            k0 += kk
+        mats.append((oa, M, K, ob, N))
+        gA.append(ia.ravel())
+        gB.append(ib.ravel())
+        sC.append(ic.ravel())
+        oa += M * K
+        ob += K * N
+    cat = lambda xs: np.concatenate(xs) if xs else np.zeros(0, np.int64)
+    return cat(gA), cat(gB), cat(sC), mats, nA, nB, nC
+
+
+class PlainStep:
+    """One contraction in the plain per-sector form on the GPU (torch FP64)."""
+
+    def __init__(self, A, B, xa, xb, Cs, dev):
+        import torch
+        gA, gB, sC, self.mats, self.nA, self.nB, self.nC = plain_maps(A, B, xa, xb, Cs)
+        self.gA = torch.from_numpy(gA).to(dev)
+        self.gB = torch.from_numpy(gB).to(dev)
+        self.sC = torch.from_numpy(sC).to(dev)
+        self.pc = torch.empty(len(sC), dtype=torch.float64, device=dev)
+
+    def run(self, a_ext, b_ext, c_ext):
+        import torch
+        pa = a_ext[self.gA]                                   # fuse: gather into A_X
+        pb = b_ext[self.gB]                                   # fuse: gather into B_X
+        oc = 0
+        for oa, M, K, ob, N in self.mats:                     # one matmul per sector
+            torch.matmul(pa[oa:oa + M * K].view(M, K), pb[ob:ob + K * N].view(K, N),
+                         out=self.pc[oc:oc + M * N].view(M, N))
+            oc += M * N
+        c_ext.index_copy_(0, self.sC, self.pc)                # unfuse: scatter into C's blocks
+
+
+# --------------------------------------------------------------------- main
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="f64", choices=["f64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--cpu-reps", type=int, default=2)
+    ap.add_argument("--tile-rows", type=int, default=0, help="16, 32, 64 or 0 (plan's choice)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the kernel-variant autotuner")
+    args = ap.parse_args()
+    ws_env = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or ws_env != 1:
+        print("bench.py measures one GPU only: the block-sparse tensordot of this library runs on a single "
+              "MI355X (multi-GPU sharding is described in DESIGN.md, not built). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2405_12196_amd as Y
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    sp = int(stream.cuda_stream)
+    t = W.config2()
+    # ---- plans (once; structure is fixed across CTM iterations)
+    tp0 = time.perf_counter()
+    plans, descs = [], []
+    cur = None
+    for (an, bn), (ax, bx) in zip(STEPS, t["axes"]):
+        a = t[an] if an else cur
+        pl = Y.plan([(a, t[bn], ax, bx)], stream=sp, tile_rows=args.tile_rows)
+        plans.append(pl)
+        descs.append((a, t[bn], ax, bx))
+        cur = pl.output(0)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - tp0) * 1e3
+    stats = [pl.stats(0) for pl in plans]
+    useful = sum(s["useful_flops"] for s in stats)
+    alg_bytes = [s["alg_bytes"] for s in stats]
+
+    # ---- device buffers (resident before timing)
+    up = lambda x: torch.from_numpy(np.ascontiguousarray(x.data)).to(dev)
+    inp = {k: up(t[k]) for k in ("C", "T1", "T4", "A", "Ac")}
+    outs = [torch.empty(max(1, pl.output(0).numel), dtype=torch.float64, device=dev) for pl in plans]
+    wss = [torch.empty(max(256, pl.workspace_bytes), dtype=torch.uint8, device=dev) for pl in plans]
+    nws = torch.empty(Y.norm_workspace_bytes(), dtype=torch.uint8, device=dev)
+    nout = torch.zeros(2, dtype=torch.float64, device=dev)
+    n_last = plans[-1].output(0).numel
+    ops = []
+    for i, ((an, bn), _) in enumerate(zip(STEPS, t["axes"])):
+        ops.append((inp[an] if an else outs[i - 1], inp[bn], outs[i], wss[i]))
+
+    # ---- autotune each contraction's kernel variant (outside the timed region)
+    tuned = []
+    if not args.no_tune:
+        for i, (pl, (a, b, c, w)) in enumerate(zip(plans, ops)):
+            v, times = pl.autotune([a], [b], [c], w, reps=5, stream=sp)
+            tuned.append({"step": i + 1, "variant": v, "ms": [round(x, 4) for x in times]})
+        torch.cuda.synchronize()
+
+    ev = HipEvents()
+
+    def step(evs=None):
+        for i, (pl, (a, b, c, w)) in enumerate(zip(plans, ops)):
+            if evs is None:
+                pl.contract([a], [b], [c], w, stream=sp)
+            else:
+                pl.contract_timed([a], [b], [c], w, [None, evs[2 * i], evs[2 * i + 1]], stream=sp)
+        Y.norm(outs[-1], n_last, nout, nws, stream=sp)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    K = args.steps
+    step_ev = [(ev.new(), ev.new()) for _ in range(K)]
+    kern_ev = [[ev.new() for _ in range(8)] for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        ev.record(step_ev[k][0], sp)
+        step(kern_ev[k])
+        ev.record(step_ev[k][1], sp)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / K
+    lat = np.array([ev.ms(a, b) for a, b in step_ev])
+    gemm_ms = np.array([[ev.ms(kern_ev[k][2 * i], kern_ev[k][2 * i + 1]) for i in range(4)] for k in range(K)])
+    gemm_avg = gemm_ms.mean(axis=0)
+    per_kernel = []
+    for i, pl in enumerate(plans):
+        gbs = alg_bytes[i] / (gemm_avg[i] * 1e-3) / 1e9
+        per_kernel.append({"step": i + 1, "gemm_us": round(gemm_avg[i] * 1e3, 2), "alg_bytes": int(alg_bytes[i]),
+                           "achieved_GBs": round(gbs, 1), "useful_TFs": round(stats[i]["useful_flops"] / (gemm_avg[i] * 1e-3) / 1e12, 2),
+                           "tiles": int(stats[i]["tiles"])})
+    dom = int(np.argmax(gemm_avg))
+    ach = alg_bytes[dom] / (gemm_avg[dom] * 1e-3) / 1e9
+    value = useful / (ms_per_step * 1e-3) / 1e12
+
+    # ---- check the step's result once (norm of the last output vs its values)
+    torch.cuda.synchronize()
+
+    # ---- plain per-sector FP64 form on the same GPU
+    plain = None
+    if not args.no_plain:
+        cur_structs = [d[0] for d in descs]
+        psteps = []
+        for i, (a, b, ax, bx) in enumerate(descs):
+            psteps.append(PlainStep(a if i == 0 else plans[i - 1].output(0), b, ax, bx, plans[i].output(0), dev))
+        del cur_structs
+        ext = lambda n: torch.zeros(n + 1, dtype=torch.float64, device=dev)
+        a_ext = [ext(p.nA) for p in psteps]
+        b_ext = [ext(p.nB) for p in psteps]
+        c_ext = [ext(p.nC) for p in psteps]
+        keys = ["C", "T1", "T4", "A", "Ac"]
+        a_ext[0][:psteps[0].nA].copy_(inp["C"][:psteps[0].nA])
+        for i, (an, bn) in enumerate(STEPS):
+            b_ext[i][:psteps[i].nB].copy_(inp[bn][:psteps[i].nB])
+        del keys
+
+        def pstep():
+            for i, p in enumerate(psteps):
+                if i > 0:
+                    a_ext[i][:p.nA].copy_(c_ext[i - 1][:p.nA])
+                p.run(a_ext[i], b_ext[i], c_ext[i])
+            Y.norm(c_ext[-1], psteps[-1].nC, nout, nws, stream=sp)
+
+        for _ in range(3):
+            pstep()
+        torch.cuda.synchronize()
+        maxdiff = float((c_ext[-1][:n_last] - outs[-1][:n_last]).abs().max()) / float(outs[-1][:n_last].abs().max())
+        KP = max(5, min(50, K // 4))
+        torch.cuda.synchronize()
+        tq = time.perf_counter()
+        for _ in range(KP):
+            pstep()
+        torch.cuda.synchronize()
+        pms = (time.perf_counter() - tq) * 1e3 / KP
+        plain = {"value": round(useful / (pms * 1e-3) / 1e12, 4), "unit": "TFLOP/s", "ms_per_step": round(pms, 4),
+                 "steps": KP, "max_rel_diff_vs_library": maxdiff,
+                 "form": "gather into fused sector matrices, one torch.matmul (FP64) per sector, scatter"}
+
+    # ---- CPU oracle baseline (block-pair form), bounded sample
+    cpu = None
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+
+        import oracle
+        with threadpool_limits(1):
+            tc = time.perf_counter()
+            for _ in range(args.cpu_reps):
+                cur = None
+                for (an, bn), (ax, bx) in zip(STEPS, t["axes"]):
+                    cur = oracle.tensordot_blockpair(t[an] if an else cur, t[bn], ax, bx)
+                oracle.norms(cur)
+            csec = time.perf_counter() - tc
+        cpu = {"value": round(useful * args.cpu_reps / csec / 1e12, 6), "unit": "TFLOP/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{args.cpu_reps} full enlarged-corner steps (4 block-pair tensordots + norm), "
+                         f"{csec:.1f} s, BLAS limited to 1 thread; host has {os.cpu_count()} CPUs"}
+
+    rec = {
+        "metric": "useful TFLOP/s per block-sparse tensordot vs plain per-sector FP64; p50/p99 latency",
+        "value": round(value, 4), "unit": "TFLOP/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "ctmrg_enlarged_corner_u1xu1_chi128_D8_d4", "contractions_per_step": 4,
+                   "useful_flop_per_step": int(useful), "plus": "fp64 norm of the step-4 output",
+                   "parallelism": "single GPU"},
+        "p50_ms": round(float(np.percentile(lat, 50)), 5), "p99_ms": round(float(np.percentile(lat, 99)), 5),
+        "plan_ms": round(plan_ms, 2),
+        "vs_plain_per_sector_f64": round(value / plain["value"], 3) if plain else None,
+        "plain_per_sector_f64": plain,
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": f"grouped gather GEMM of contraction {dom + 1}"},
+        "kernels": per_kernel,
+        "autotune": tuned,
+        "cpu_baseline": cpu,
+    }
+    ev.close()
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -93,9 +93,17 @@ typedef struct {
   yastn_precision precision; /* arithmetic of the sector GEMMs                                  */
   yastn_dtype in_dtype;      /* element type of A and B buffers                                 */
   yastn_dtype out_dtype;     /* element type of C buffers                                       */
-  int32_t tile_rows;         /* rows per wave tile: 16, 32 or 64; 0 = chosen by the autotuner   */
-  int32_t flags;             /* reserved, must be 0                                             */
+  int32_t tile_rows;         /* MFMA rows per wave chunk: 16, 32 or 64; 0 = plan's choice       */
+  int32_t flags;             /* 0, or one of the YASTN_FLAG_* below                             */
 } yastn_options;
+
+/* Kernel family of the sector GEMMs.  By default the plan picks: sectors with
+ * K, N <= 64 (tall-skinny, bound by HBM) run one output row per lane on the
+ * vector FMA units; other shapes run on MFMA tiles.  These flags force one
+ * family (ROWS falls back to MFMA when a sector has K or N above 64, or for
+ * the BF16 precisions, which always use MFMA). */
+#define YASTN_FLAG_MFMA 1
+#define YASTN_FLAG_ROWS 2
 
 typedef struct {
   int64_t blocks_a, blocks_b;  /* stored blocks of A and B                                      */
@@ -145,6 +153,32 @@ yastn_status yastn_plan_stats(yastn_plan_t plan, int32_t prob, yastn_stats *st);
  * deterministic: no atomics, fixed summation order per output element. */
 yastn_status yastn_contract(yastn_plan_t plan, const void *const *a, const void *const *b,
                             void *const *c, void *workspace, void *hip_stream);
+
+/* As yastn_contract, and records HIP events on hip_stream for timing:
+ * events[0] before the B pack kernel, events[1] between the pack kernel and
+ * the grouped GEMM, events[2] after the GEMM ([host] array of 3 hipEvent_t
+ * created by the caller; any entry may be NULL).  The plan must run in one
+ * launch (at most 64 problems), else YASTN_ERR_STATE. */
+yastn_status yastn_contract_timed(yastn_plan_t plan, const void *const *a, const void *const *b,
+                                  void *const *c, void *workspace, void *hip_stream,
+                                  void *const *events);
+
+/* Kernel variants.  A plan starts with variant 0 (the library's heuristic).
+ * yastn_plan_autotune runs every variant that fits the plan `reps` times on
+ * the caller's buffers (same arguments as yastn_contract; C is overwritten),
+ * times them with HIP events, keeps the fastest in the plan and returns its
+ * id in *chosen (may be NULL).  times_ms [host], if not NULL, receives
+ * YASTN_NUM_VARIANTS floats: [0] = best time per contraction, [v] = time of
+ * variant v or -1 if it does not fit.  Synchronises hip_stream.  Results of
+ * different variants agree within rounding, and one plan always uses one
+ * variant, so repeated contractions stay bitwise reproducible.
+ * yastn_plan_set_variant restores a previously tuned choice (e.g. from a
+ * cache keyed by structure). */
+#define YASTN_NUM_VARIANTS 8
+yastn_status yastn_plan_autotune(yastn_plan_t plan, const void *const *a, const void *const *b,
+                                 void *const *c, void *workspace, void *hip_stream, int32_t reps,
+                                 int32_t *chosen, float *times_ms);
+yastn_status yastn_plan_set_variant(yastn_plan_t plan, int32_t variant);
 
 /* One entry of a multi-plan launch (continuous batching across requests). */
 typedef struct {

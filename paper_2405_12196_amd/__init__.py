@@ -25,14 +25,17 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libyastn.so")
 
 F64, F32, BF16X3, BF16X6 = 0, 1, 2, 3
+FLAG_MFMA, FLAG_ROWS = 1, 2
 DTYPE_F64, DTYPE_F32 = 0, 1
 PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3, "bf16x6": BF16X6}
 STATUS = ["OK", "ERR_ARG", "ERR_SYM", "ERR_CHARGE", "ERR_SIGNATURE", "ERR_SHAPE",
           "ERR_DUPLICATE", "ERR_NOMEM", "ERR_HIP", "ERR_STATE"]
 
 EXPORTS = ["yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats",
-           "yastn_contract", "yastn_contract_jobs", "yastn_norm_workspace", "yastn_norm",
-           "yastn_free", "yastn_last_error", "yastn_status_string", "yastn_abi_version"]
+           "yastn_contract", "yastn_contract_timed", "yastn_contract_jobs", "yastn_norm_workspace", "yastn_norm",
+           "yastn_free", "yastn_last_error", "yastn_status_string", "yastn_abi_version",
+           "yastn_plan_autotune", "yastn_plan_set_variant"]
+NUM_VARIANTS = 8
 
 
 class YastnError(RuntimeError):
@@ -92,7 +95,13 @@ def lib():
         L.yastn_plan_stats.argtypes = [C.c_void_p, C.c_int32, C.POINTER(Stats)]
         L.yastn_contract.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                      C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]
+        L.yastn_contract_timed.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                           C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]
         L.yastn_contract_jobs.argtypes = [C.POINTER(Job), C.c_int32, C.c_void_p]
+        L.yastn_plan_autotune.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                          C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p, C.c_int32,
+                                          C.POINTER(C.c_int32), C.POINTER(C.c_float)]
+        L.yastn_plan_set_variant.argtypes = [C.c_void_p, C.c_int32]
         L.yastn_norm_workspace.restype = C.c_size_t
         L.yastn_norm.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
         L.yastn_free.argtypes = [C.c_void_p]
@@ -101,7 +110,8 @@ def lib():
         L.yastn_status_string.restype = C.c_char_p
         L.yastn_status_string.argtypes = [C.c_int32]
         for f in ("yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats",
-                  "yastn_contract", "yastn_contract_jobs", "yastn_norm"):
+                  "yastn_contract", "yastn_contract_timed", "yastn_contract_jobs", "yastn_norm",
+                  "yastn_plan_autotune", "yastn_plan_set_variant"):
             getattr(L, f).restype = C.c_int32
         _LIB = L
     return _LIB
@@ -191,7 +201,8 @@ def _stream(stream) -> int:
 class Plan:
     """A validated, matched and tiled set of tensordot problems (yastn_plan)."""
 
-    def __init__(self, problems, precision="f64", in_dtype=None, out_dtype=None, tile_rows=0, stream=None):
+    def __init__(self, problems, precision="f64", in_dtype=None, out_dtype=None, tile_rows=0, stream=None,
+                 flags=0):
         L = lib()
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         if in_dtype is None:
@@ -208,7 +219,7 @@ class Plan:
             arr[i].ncontract = int(len(axes_a)) if len(axes_a) == len(axes_b) else -1
             arr[i].axes_a = keep.ptr(xa, C.c_int32)
             arr[i].axes_b = keep.ptr(xb, C.c_int32)
-        opts = Options(prec, in_dtype, out_dtype, tile_rows, 0)
+        opts = Options(prec, in_dtype, out_dtype, tile_rows, flags)
         h = C.c_void_p()
         _check(L.yastn_plan(arr, len(problems), C.byref(opts), C.c_void_p(_stream(stream)),
                             C.byref(h)))
@@ -253,6 +264,33 @@ class Plan:
         pc = (C.c_void_p * max(1, n))(*[_ptr(x) for x in c])
         _check(lib().yastn_contract(self._h, pa, pb, pc, C.c_void_p(_ptr(workspace)),
                                     C.c_void_p(_stream(stream))))
+
+    def contract_timed(self, a, b, c, workspace, events, stream=None):
+        """As contract(); records ``events`` (3 raw hipEvent_t handles or None)
+        before the pack kernel, between pack and GEMM, and after the GEMM."""
+        n = self.nprob
+        pa = (C.c_void_p * max(1, n))(*[_ptr(x) for x in a])
+        pb = (C.c_void_p * max(1, n))(*[_ptr(x) for x in b])
+        pc = (C.c_void_p * max(1, n))(*[_ptr(x) for x in c])
+        ev = (C.c_void_p * 3)(*[e or 0 for e in events])
+        _check(lib().yastn_contract_timed(self._h, pa, pb, pc, C.c_void_p(_ptr(workspace)),
+                                          C.c_void_p(_stream(stream)), ev))
+
+    def autotune(self, a, b, c, workspace, reps=5, stream=None):
+        """Time every kernel variant that fits on these buffers, keep the
+        fastest; returns (variant, per-variant ms list, -1 = not applicable)."""
+        n = self.nprob
+        pa = (C.c_void_p * max(1, n))(*[_ptr(x) for x in a])
+        pb = (C.c_void_p * max(1, n))(*[_ptr(x) for x in b])
+        pc = (C.c_void_p * max(1, n))(*[_ptr(x) for x in c])
+        ch = C.c_int32()
+        times = (C.c_float * NUM_VARIANTS)()
+        _check(lib().yastn_plan_autotune(self._h, pa, pb, pc, C.c_void_p(_ptr(workspace)),
+                                         C.c_void_p(_stream(stream)), int(reps), C.byref(ch), times))
+        return int(ch.value), [float(t) for t in times]
+
+    def set_variant(self, v: int):
+        _check(lib().yastn_plan_set_variant(self._h, int(v)))
 
     def free(self):
         if getattr(self, "_h", None) is not None and self._h.value:

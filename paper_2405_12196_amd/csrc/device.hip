@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <type_traits>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -44,11 +45,27 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ void wave_sync() {
+// Wave-uniform reads of plan tables go through the constant address space:
+// the tables are read-only while kernels run, so the compiler may use scalar
+// loads (reads only) and keep the values in SGPRs.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+__device__ __forceinline__ T cst(const T *p) {
+  return *(const __attribute__((address_space(4))) T *)(p);
+}
+#else
+template <typename T> __device__ __forceinline__ T cst(const T *p) { return *p; }  // host pass: unused
+#endif
+
+// LDS written by one lane and read by another lane of the same wave.
+__device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+// A value the compiler cannot prove wave-uniform but that is.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // ---------------------------------------------------------------------------
 // charge-hash join
@@ -163,45 +180,137 @@ __device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(
 // ---------------------------------------------------------------------------
 // B pack: per-sector matrices B_X in the workspace
 // ---------------------------------------------------------------------------
+// One workgroup per item of up to 256 elements of one (s, j) sub-block;
+// consecutive threads write consecutive elements of a B_X row.
 template <typename In, typename Cmp>
 __global__ void __launch_bounds__(256) k_pack_b(LaunchArgs args) {
-  const int lane = threadIdx.x & 63;
-  const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int W = gridDim.x * 4;
-  for (int g = gw; g < args.nitems; g += W) {
+  for (int g = blockIdx.x; g < args.nitems; g += gridDim.x) {
     int jb = 0;
     while (jb + 1 < args.njobs && g >= args.jobs[jb + 1].item0) ++jb;
     const JobArg &job = args.jobs[jb];
-    const DevPlan &P = *job.plan;
-    const DevPackItem it = P.items[g - job.item0 + job.pitem0];
-    const DevSector sec = P.sectors[it.sector];
-    const DevCtrTuple &ct = P.ctrs[sec.ctr0 + it.s];
-    const DevColTuple &cl = P.cols[sec.col0 + it.j];
-    const DevProb pr = P.probs[sec.prob];
-    Cmp *dst = reinterpret_cast<Cmp *>(job.ws) + sec.bpack + (int64_t)ct.ko * sec.N + cl.no;
-    const In *src = reinterpret_cast<const In *>(args.p[job.prob0 + sec.prob - job.plo].b);
-    const int64_t total = (int64_t)ct.k * cl.n;
+    const DevPlan P = cst(job.plan);
+    const DevPackItem it = cst(P.items + (g - job.item0 + job.pitem0));
+    const DevSector sec = cst(P.sectors + it.sector);
+    const DevCtrTuple ct = cst(P.ctrs + (sec.ctr0 + it.s));
+    const DevColTuple cl = cst(P.cols + (sec.col0 + it.j));
+    const int32_t e = it.e0 + (int32_t)threadIdx.x;
+    if (e >= ct.k * cl.n) continue;
+    const int32_t kd = e / cl.n, cb = e - kd * cl.n;
+    Cmp *dst = reinterpret_cast<Cmp *>(job.ws) + sec.bpack + (int64_t)(ct.ko + kd) * sec.N + cl.no + cb;
     if (it.bblk < 0) {
-      for (int64_t e = lane; e < total; e += 64) dst[(e / cl.n) * sec.N + (e % cl.n)] = Cmp(0);
-      continue;
-    }
-    const DevBBlock bb = P.bblocks[it.bblk];
-    for (int64_t e = lane; e < total; e += 64) {
-      const int64_t kd = e / cl.n, cb = e - kd * cl.n;
-      const int64_t o = b_offset(bb, ct, cl, pr, kd, cb);
-      dst[kd * sec.N + cb] = Cmp(src[o]);
+      *dst = Cmp(0);
+    } else {
+      const In *src = reinterpret_cast<const In *>(args.p[job.prob0 + sec.prob - job.plo].b);
+      const DevBBlock bb = cst(P.bblocks + it.bblk);
+      const DevProb pr = cst(P.probs + sec.prob);
+      *dst = Cmp(src[b_offset(bb, ct, cl, pr, kd, cb)]);
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// grouped gather GEMM (FP64 / FP32 MFMA, K = 4 per instruction)
+// operand access: buffer resources or 64-bit pointers
 // ---------------------------------------------------------------------------
-struct KInfo {
-  int64_t off;        // element offset of A(row 0 of the tuple, k) plus the k part; -1: block absent
-  int32_t p[kMaxAct]; // P_a of k's contracted tuple
+// BUF = true: A and C are reached through buffer resources (scalar base,
+// 32-bit byte offsets; the hardware returns 0 for reads past num_records and
+// drops such writes).  Used when both buffers are below 2 GiB.  BUF = false:
+// plain 64-bit addresses, any size.
+typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+constexpr int kBufFlags = 0x00020000;  // raw buffer, gfx9-family descriptor word 3
+
+template <typename T> struct BufIo;
+template <> struct BufIo<double> {
+  __device__ static double ld(__amdgpu_buffer_rsrc_t r, int32_t byte) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte, 0, 0));
+  }
+  __device__ static void st(__amdgpu_buffer_rsrc_t r, int32_t byte, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, v), r, byte, 0, 0);
+  }
+};
+template <> struct BufIo<float> {
+  __device__ static float ld(__amdgpu_buffer_rsrc_t r, int32_t byte) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte, 0, 0));
+  }
+  __device__ static void st(__amdgpu_buffer_rsrc_t r, int32_t byte, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, byte, 0, 0);
+  }
 };
 
+template <typename T, bool BUF> struct Src;
+template <typename T> struct Src<T, true> {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ void init(const void *p, int64_t n) {
+    r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)(n * (int64_t)sizeof(T)), kBufFlags);
+  }
+  __device__ T operator()(int32_t i) const { return BufIo<T>::ld(r, i * (int32_t)sizeof(T)); }
+};
+template <typename T> struct Src<T, false> {
+  const T *__restrict__ p;
+  __device__ void init(const void *q, int64_t) { p = reinterpret_cast<const T *>(q); }
+  __device__ T operator()(int64_t i) const { return p[i]; }
+};
+template <typename T, bool BUF> struct Dst;
+template <typename T> struct Dst<T, true> {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ void init(void *p, int64_t n) {
+    r = __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)(n * (int64_t)sizeof(T)), kBufFlags);
+  }
+  __device__ void put(int64_t i, T v) const { BufIo<T>::st(r, (int32_t)i * (int32_t)sizeof(T), v); }
+};
+template <typename T> struct Dst<T, false> {
+  T *__restrict__ p;
+  __device__ void init(void *q, int64_t) { p = reinterpret_cast<T *>(q); }
+  __device__ void put(int64_t i, T v) const { p[i] = v; }
+};
+
+// Tile context shared by every precision: the tile's row tuple and sector,
+// the problem's operands, and the lane's output columns.
+template <typename In, typename Out, bool BUF, int CB> struct TileCtx {
+  DevTile tile;
+  DevRowTuple rt;
+  DevSector sec;
+  Src<In, BUF> A;
+  Dst<Out, BUF> C;
+  const char *ws;
+  int64_t cbase[CB];        // output block offset of the lane's columns (-1: none)
+  int32_t cnj[CB], ccl[CB];
+  int cbn;
+};
+
+template <typename In, typename Out, bool BUF, int CB>
+__device__ __forceinline__ DevPlan tile_setup(const LaunchArgs &args, int t, int lane, TileCtx<In, Out, BUF, CB> &x) {
+  int jb = 0;
+  while (jb + 1 < args.njobs && t >= args.jobs[jb + 1].tile0) ++jb;
+  const JobArg &job = args.jobs[jb];
+  const DevPlan P = cst(job.plan);
+  x.tile = cst(P.tiles + (t - job.tile0 + job.ptile0));
+  x.rt = cst(P.rows + x.tile.rowtuple);
+  x.sec = cst(P.sectors + x.tile.sector);
+  const ProbPtrs pp = args.p[job.prob0 + x.sec.prob - job.plo];
+  const DevProb pr = cst(P.probs + x.sec.prob);
+  x.A.init(pp.a, pr.a_span);
+  x.C.init(pp.c, pr.c_numel);
+  x.ws = job.ws;
+  x.cbn = (x.tile.ncols + 15) >> 4;
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) {
+    const int lc = 16 * cb + (lane & 15);
+    x.cbase[cb] = -1;
+    x.cnj[cb] = 0;
+    x.ccl[cb] = 0;
+    if (lc < x.tile.ncols) {
+      const DevColMap cm = P.colmap[x.sec.cm0 + x.tile.n0 + lc];
+      x.cbase[cb] = P.cgrid[x.rt.cgrid + cm.j];
+      x.cnj[cb] = cm.nj;
+      x.ccl[cb] = cm.cl;
+    }
+  }
+  return P;
+}
+
+// ---------------------------------------------------------------------------
+// grouped gather GEMM (FP64 / FP32 MFMA, K = 4 per instruction)
+// ---------------------------------------------------------------------------
 template <typename Cmp> struct Mfma4;
 template <> struct Mfma4<double> {
   typedef d4 acc_t;
@@ -216,108 +325,172 @@ template <> struct Mfma4<float> {
   __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
-// Per-wave tile prologue shared by every precision: locate the tile and
-// fill the wave's k-offset table for contracted indices [k0, kend).
-__device__ __forceinline__ void build_kinfo(const DevPlan &P, const DevRowTuple &rt, const DevSector &sec,
-                                            const DevProb &pr, int k0, int kend, int lane, KInfo *ki) {
-  for (int k = k0 + lane; k < kend; k += 64) {
-    KInfo e;
-    e.off = a_koffset(P, rt, sec, pr, k, e.p);
-    ki[k - k0] = e;
-  }
-}
-
-template <typename In, typename Cmp, typename Out, int CB>
+// One wave tile: rows are processed in chunks of 16*RB; the tile's metadata
+// and output columns are set up once.  Within a chunk, KB k-steps of loads
+// are issued before the MFMAs that consume them.
+template <typename In, typename Cmp, typename Out, bool BUF, int RB, int CB, int KB>
 __global__ void __launch_bounds__(256) k_gemm4(LaunchArgs args) {
+  typedef typename std::conditional<BUF, int32_t, int64_t>::type Off;
   typedef Mfma4<Cmp> M;
   typedef typename M::acc_t acc_t;
-  __shared__ KInfo kinfo_all[4][kKChunk];
   const int lane = threadIdx.x & 63;
-  const int wid = threadIdx.x >> 6;
-  KInfo *kinfo = kinfo_all[wid];
-  const int gw = blockIdx.x * 4 + wid;
+  const int gw = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int W = gridDim.x * 4;
   for (int t = gw; t < args.ntiles; t += W) {
-    int jb = 0;
-    while (jb + 1 < args.njobs && t >= args.jobs[jb + 1].tile0) ++jb;
-    const JobArg &job = args.jobs[jb];
-    const DevPlan &P = *job.plan;
-    const DevTile tile = P.tiles[t - job.tile0 + job.ptile0];
-    const DevRowTuple rt = P.rows[tile.rowtuple];
-    const DevSector sec = P.sectors[rt.sector];
-    const DevProb pr = P.probs[sec.prob];
-    const ProbPtrs pp = args.p[job.prob0 + sec.prob - job.plo];
-    const In *__restrict__ A = reinterpret_cast<const In *>(pp.a);
-    Out *__restrict__ C = reinterpret_cast<Out *>(pp.c);
-    const Cmp *__restrict__ Bp = reinterpret_cast<const Cmp *>(job.ws) + sec.bpack;
-    const int rbn = (tile.nrows + 15) >> 4, cbn = (tile.ncols + 15) >> 4;
-
-    // per-row factorised offsets RG_a(ra) of the lane's 4 rows
-    int32_t rg[4][kMaxAct];
-    bool rv[4];
+    TileCtx<In, Out, BUF, CB> x;
+    const DevPlan P = tile_setup<In, Out, BUF, CB>(args, t, lane, x);
+    const Cmp *__restrict__ Bp = reinterpret_cast<const Cmp *>(x.ws) + x.sec.bpack;
+    const int64_t *__restrict__ kofs = P.kofs + x.rt.kofs;
+    const DevKP *__restrict__ kp = P.kp + x.sec.kp0;
+    const int K = x.sec.K, N = x.sec.N;
+    for (int mc = 0; mc < x.tile.nrows; mc += 16 * RB) {
+      const int rows = min(16 * RB, x.tile.nrows - mc);
+      const int rbn = (rows + 15) >> 4;
+      int32_t rg[RB][kMaxAct];
+      bool rv[RB];
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-      const int lr = 16 * rb + (lane & 15);
-      rv[rb] = lr < tile.nrows;
-      const int32_t ra = tile.m0 + lr;
-      a_rowparts(rt, pr.nact, ra, rg[rb]);
-    }
-    acc_t acc[4][CB];
+      for (int rb = 0; rb < RB; ++rb) {
+        const int lr = 16 * rb + (lane & 15);
+        rv[rb] = lr < rows;
+        a_rowparts(x.rt, x.sec.nact, x.tile.m0 + mc + lr, rg[rb]);
+      }
+      acc_t acc[RB][CB];
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+      for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = acc_t{0, 0, 0, 0};
-
-    for (int k0 = 0; k0 < sec.K; k0 += kKChunk) {
-      const int kend = min(sec.K, k0 + kKChunk);
-      build_kinfo(P, rt, sec, pr, k0, kend, lane, kinfo);
-      wave_sync();
-      for (int kk = k0; kk < kend; kk += 4) {
-        const int k = kk + (lane >> 4);
-        Cmp av[4], bv[CB];
-        KInfo e;
-        e.off = -1;
-        if (k < kend) e = kinfo[k - k0];
+        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = acc_t{0, 0, 0, 0};
+      // k metadata of the next batch is fetched while this batch's A loads fly
+      int64_t kon[KB];
+      DevKP pn[KB];
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
-          av[rb] = Cmp(0);
-          if (e.off >= 0 && rv[rb]) {
-            av[rb] = Cmp(A[a_offset(e.off, e.p, rg[rb])]);
+      for (int q = 0; q < KB; ++q) {
+        const int k = 4 * q + (lane >> 4);
+        kon[q] = k < K ? kofs[k] : -1;
+        pn[q] = k < K ? kp[k] : DevKP{};
+      }
+      for (int kk0 = 0; kk0 < K; kk0 += 4 * KB) {
+        Cmp av[KB][RB], bv[KB][CB];
+        int64_t ko[KB];
+        DevKP pc[KB];
+#pragma unroll
+        for (int q = 0; q < KB; ++q) {
+          ko[q] = kon[q];
+          pc[q] = pn[q];
+        }
+#pragma unroll
+        for (int q = 0; q < KB; ++q) {
+          const int k = kk0 + 4 * q + (lane >> 4);
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            av[q][rb] = (ko[q] >= 0 && rv[rb]) ? Cmp(x.A(a_offset_t<Off>(ko[q], pc[q].p, rg[rb]))) : Cmp(0);
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            const int c = x.tile.n0 + 16 * cb + (lane & 15);
+            bv[q][cb] = (k < K && c < N) ? Bp[(int64_t)k * N + c] : Cmp(0);
           }
         }
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-          const int c = tile.n0 + 16 * cb + (lane & 15);
-          bv[cb] = (k < kend && c < sec.N) ? Bp[(int64_t)k * sec.N + c] : Cmp(0);
+        for (int q = 0; q < KB; ++q) {
+          const int k = kk0 + 4 * KB + 4 * q + (lane >> 4);
+          kon[q] = k < K ? kofs[k] : -1;
+          pn[q] = k < K ? kp[k] : DevKP{};
         }
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
-          if (rb < rbn)
+        for (int q = 0; q < KB; ++q)
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
-              if (cb < cbn) acc[rb][cb] = M::run(av[rb], bv[cb], acc[rb][cb]);
+          for (int rb = 0; rb < RB; ++rb)
+            if (rb < rbn)
+#pragma unroll
+              for (int cb = 0; cb < CB; ++cb)
+                if (cb < x.cbn) acc[rb][cb] = M::run(av[q][rb], bv[q][cb], acc[rb][cb]);
       }
-      wave_sync();
+      // element (row, col) of C_X -> output block (i, j_col), row-major m_i x n_j
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        if (cb >= x.cbn || x.cbase[cb] < 0) continue;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          if (rb >= rbn) continue;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int lr = 16 * rb + M::row(lane, v);
+            if (lr < rows)
+              x.C.put(x.cbase[cb] + (int64_t)(x.tile.m0 + mc + lr) * x.cnj[cb] + x.ccl[cb], Out(acc[rb][cb][v]));
+          }
+        }
+      }
     }
-    // epilogue: element (row, col) of C_X -> output block (i, j_col), row-major m_i x n_j
-    const DevColTuple *cols = P.cols + sec.col0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tall-skinny sectors (K, N <= 64): one row of C_X per lane, VALU FMA
+// ---------------------------------------------------------------------------
+// HBM-bound shapes (tens of thousands of rows, K and N of a few tens): each
+// lane gathers its row of A_X (all K values at once, coalesced across the
+// wave's consecutive rows) and accumulates 16 columns at a time with B_X
+// values that are uniform across the wave, so the k offsets, P factors and
+// B_X come from scalar loads.  No padding of K or N.
+template <typename In, typename Cmp, typename Out, bool BUF, int KMAX>
+__global__ void __launch_bounds__(256) k_rows(LaunchArgs args) {
+  typedef typename std::conditional<BUF, int32_t, int64_t>::type Off;
+  __shared__ Cmp bs_all[4][KMAX][16];  // per wave: B_X rows 0..K-1, the 16 columns of one pass
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  Cmp (*bs)[16] = bs_all[wid];
+  const int gw = blockIdx.x * 4 + wid;  // wave-uniform
+  const int W = gridDim.x * 4;
+  for (int t = gw; t < args.ntiles; t += W) {
+    TileCtx<In, Out, BUF, 1> x;
+    const DevPlan P = tile_setup<In, Out, BUF, 1>(args, t, lane, x);
+    const Cmp *__restrict__ Bp = reinterpret_cast<const Cmp *>(x.ws) + x.sec.bpack;
+    const int64_t *kofs = P.kofs + x.rt.kofs;
+    const DevKP *kp = P.kp + x.sec.kp0;
+    const DevColMap *cmap = P.colmap + x.sec.cm0 + x.tile.n0;
+    const int64_t *cgrid = P.cgrid + x.rt.cgrid;
+    const int K = uni(x.sec.K), N = uni(x.sec.N), ncols = uni(x.tile.ncols), nrows = uni(x.tile.nrows);
+    for (int mc = 0; mc < nrows; mc += 64) {
+      const int lr = mc + lane;
+      const bool valid = lr < nrows;
+      const int32_t ra = x.tile.m0 + lr;
+      int32_t rg[kMaxAct];
+      a_rowparts(x.rt, x.sec.nact, ra, rg);
+      Cmp a[KMAX];
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-      if (cb >= cbn) continue;
-      const int c = tile.n0 + 16 * cb + (lane & 15);
-      if (c >= sec.N || c >= tile.n0 + tile.ncols) continue;
-      const int j = find_col(cols, sec.Q, c);
-      const int64_t cbase = P.cgrid[rt.cgrid + j];
-      if (cbase < 0) continue;
-      const int64_t nj = cols[j].n;
-      const int64_t cl = c - cols[j].no;
+      for (int k = 0; k < KMAX; ++k) {
+        a[k] = Cmp(0);
+        if (k < K) {
+          const int64_t ko = cst(kofs + k);
+          const DevKP p = cst(kp + k);
+          if (valid && ko >= 0) a[k] = Cmp(x.A(a_offset_t<Off>(ko, p.p, rg)));
+        }
+      }
+      for (int cc = 0; cc < ncols; cc += 16) {
+        const int nc = min(16, ncols - cc);
+        // stage B_X[k][n0 + cc + c] (zero beyond K and the tile's columns)
+        for (int e = lane; e < KMAX * 16; e += 64) {
+          const int k = e >> 4, c = e & 15;
+          bs[k][c] = (k < K && c < nc) ? Bp[(int64_t)k * N + x.tile.n0 + cc + c] : Cmp(0);
+        }
+        wave_lds_sync();
+        Cmp acc[16];
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb) {
-        if (rb >= rbn) continue;
+        for (int c = 0; c < 16; ++c) acc[c] = Cmp(0);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int lr = 16 * rb + M::row(lane, v);
-          if (lr < tile.nrows) C[cbase + (int64_t)(tile.m0 + lr) * nj + cl] = Out(acc[rb][cb][v]);
+        for (int k = 0; k < KMAX; ++k) {
+          if (k < K) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) acc[c] = fma(a[k], bs[k][c], acc[c]);
+          }
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          if (c < nc) {
+            const DevColMap cm = cst(cmap + cc + c);
+            const int64_t cbase = cst(cgrid + cm.j);
+            if (valid && cbase >= 0) x.C.put(cbase + (int64_t)ra * cm.nj + cm.cl, Out(acc[c]));
+          }
         }
       }
     }
@@ -331,136 +504,118 @@ __global__ void __launch_bounds__(256) k_gemm4(LaunchArgs args) {
 // (round to nearest even).  NT = 3: hi*hi + hi*mid + mid*hi;  NT = 6 adds
 // mid*mid + hi*lo + lo*hi.  FP32 accumulation.
 template <int NT>
-__device__ __forceinline__ void split3(float x, uint16_t &h, uint16_t &m, uint16_t &l) {
-  h = bf16_rne(x);
-  float r = x - bf16_to_f(h);
-  m = bf16_rne(r);
-  if (NT > 3) {
-    float r2 = r - bf16_to_f(m);
-    l = bf16_rne(r2);
-  } else {
-    l = 0;
-  }
+__device__ __forceinline__ void split3(float x, __bf16 &h, __bf16 &m, __bf16 &l) {
+  const uint16_t hb = bf16_rne(x);
+  const float r = x - bf16_to_f(hb);
+  const uint16_t mb = bf16_rne(r);
+  uint16_t lb = 0;
+  if (NT > 3) lb = bf16_rne(r - bf16_to_f(mb));
+  h = __builtin_bit_cast(__bf16, hb);
+  m = __builtin_bit_cast(__bf16, mb);
+  l = __builtin_bit_cast(__bf16, lb);
 }
 
-template <typename In, typename Out, int CB, int NT>
+template <typename In, typename Out, bool BUF, int RB, int CB, int NT>
 __global__ void __launch_bounds__(256) k_gemm_bf16(LaunchArgs args) {
-  __shared__ KInfo kinfo_all[4][kKChunk];
+  typedef typename std::conditional<BUF, int32_t, int64_t>::type Off;
   const int lane = threadIdx.x & 63;
-  const int wid = threadIdx.x >> 6;
-  KInfo *kinfo = kinfo_all[wid];
-  const int gw = blockIdx.x * 4 + wid;
+  const int gw = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int W = gridDim.x * 4;
   for (int t = gw; t < args.ntiles; t += W) {
-    int jb = 0;
-    while (jb + 1 < args.njobs && t >= args.jobs[jb + 1].tile0) ++jb;
-    const JobArg &job = args.jobs[jb];
-    const DevPlan &P = *job.plan;
-    const DevTile tile = P.tiles[t - job.tile0 + job.ptile0];
-    const DevRowTuple rt = P.rows[tile.rowtuple];
-    const DevSector sec = P.sectors[rt.sector];
-    const DevProb pr = P.probs[sec.prob];
-    const ProbPtrs pp = args.p[job.prob0 + sec.prob - job.plo];
-    const In *__restrict__ A = reinterpret_cast<const In *>(pp.a);
-    Out *__restrict__ C = reinterpret_cast<Out *>(pp.c);
-    const float *__restrict__ Bp = reinterpret_cast<const float *>(job.ws) + sec.bpack;
-    const int rbn = (tile.nrows + 15) >> 4, cbn = (tile.ncols + 15) >> 4;
-    int32_t rg[4][kMaxAct];
-    bool rv[4];
+    TileCtx<In, Out, BUF, CB> x;
+    const DevPlan P = tile_setup<In, Out, BUF, CB>(args, t, lane, x);
+    const float *__restrict__ Bp = reinterpret_cast<const float *>(x.ws) + x.sec.bpack;
+    const int64_t *__restrict__ kofs = P.kofs + x.rt.kofs;
+    const DevKP *__restrict__ kp = P.kp + x.sec.kp0;
+    const int K = x.sec.K, N = x.sec.N;
+    for (int mc = 0; mc < x.tile.nrows; mc += 16 * RB) {
+      const int rows = min(16 * RB, x.tile.nrows - mc);
+      const int rbn = (rows + 15) >> 4;
+      int32_t rg[RB][kMaxAct];
+      bool rv[RB];
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-      const int lr = 16 * rb + (lane & 15);
-      rv[rb] = lr < tile.nrows;
-      const int32_t ra = tile.m0 + lr;
-      a_rowparts(rt, pr.nact, ra, rg[rb]);
-    }
-    f4 acc[4][CB];
+      for (int rb = 0; rb < RB; ++rb) {
+        const int lr = 16 * rb + (lane & 15);
+        rv[rb] = lr < rows;
+        a_rowparts(x.rt, x.sec.nact, x.tile.m0 + mc + lr, rg[rb]);
+      }
+      f4 acc[RB][CB];
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+      for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = f4{0, 0, 0, 0};
-    for (int k0 = 0; k0 < sec.K; k0 += kKChunk) {
-      const int kend = min(sec.K, k0 + kKChunk);
-      build_kinfo(P, rt, sec, pr, k0, kend, lane, kinfo);
-      wave_sync();
-      for (int kk = k0; kk < kend; kk += 32) {
-        const int kb = kk + 8 * (lane >> 4);  // this lane's 8 consecutive k
-        uint16_t ah[4][8], am[4][8], al[4][8], bh[CB][8], bm[CB][8], bl[CB][8];
+        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = f4{0, 0, 0, 0};
+      for (int kk = 0; kk < K; kk += 32) {
+        bf8 ah[RB], am[RB], al[RB], bh[CB], bm[CB], bl[CB];
+        float av[8][RB], bv[8][CB];
 #pragma unroll
-        for (int e8 = 0; e8 < 8; ++e8) {
-          const int k = kb + e8;
-          KInfo e;
-          e.off = -1;
-          if (k < kend) e = kinfo[k - k0];
-#pragma unroll
-          for (int rb = 0; rb < 4; ++rb) {
-            float x = 0.f;
-            if (e.off >= 0 && rv[rb]) {
-              x = float(A[a_offset(e.off, e.p, rg[rb])]);
-            }
-            split3<NT>(x, ah[rb][e8], am[rb][e8], al[rb][e8]);
+        for (int e8 = 0; e8 < 8; ++e8) {  // this lane's 8 consecutive k
+          const int k = kk + 8 * (lane >> 4) + e8;
+          int64_t ko = -1;
+          DevKP p{};
+          if (k < K) {
+            ko = kofs[k];
+            p = kp[k];
           }
 #pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            av[e8][rb] = (ko >= 0 && rv[rb]) ? float(x.A(a_offset_t<Off>(ko, p.p, rg[rb]))) : 0.f;
+#pragma unroll
           for (int cb = 0; cb < CB; ++cb) {
-            const int c = tile.n0 + 16 * cb + (lane & 15);
-            float y = (k < kend && c < sec.N) ? Bp[(int64_t)k * sec.N + c] : 0.f;
-            split3<NT>(y, bh[cb][e8], bm[cb][e8], bl[cb][e8]);
+            const int c = x.tile.n0 + 16 * cb + (lane & 15);
+            bv[e8][cb] = (k < K && c < N) ? Bp[(int64_t)k * N + c] : 0.f;
           }
         }
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
-          if (rb >= rbn) continue;
-          bf8 a_h, a_m, a_l;
+        for (int e8 = 0; e8 < 8; ++e8) {
 #pragma unroll
-          for (int e8 = 0; e8 < 8; ++e8) {
-            a_h[e8] = __builtin_bit_cast(__bf16, ah[rb][e8]);
-            a_m[e8] = __builtin_bit_cast(__bf16, am[rb][e8]);
-            a_l[e8] = __builtin_bit_cast(__bf16, al[rb][e8]);
+          for (int rb = 0; rb < RB; ++rb) {
+            __bf16 h, m, l;
+            split3<NT>(av[e8][rb], h, m, l);
+            ah[rb][e8] = h;
+            am[rb][e8] = m;
+            al[rb][e8] = l;
           }
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb) {
-            if (cb >= cbn) continue;
-            bf8 b_h, b_m, b_l;
+            __bf16 h, m, l;
+            split3<NT>(bv[e8][cb], h, m, l);
+            bh[cb][e8] = h;
+            bm[cb][e8] = m;
+            bl[cb][e8] = l;
+          }
+        }
 #pragma unroll
-            for (int e8 = 0; e8 < 8; ++e8) {
-              b_h[e8] = __builtin_bit_cast(__bf16, bh[cb][e8]);
-              b_m[e8] = __builtin_bit_cast(__bf16, bm[cb][e8]);
-              b_l[e8] = __builtin_bit_cast(__bf16, bl[cb][e8]);
-            }
+        for (int rb = 0; rb < RB; ++rb) {
+          if (rb >= rbn) continue;
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            if (cb >= x.cbn) continue;
             f4 c = acc[rb][cb];
             // small terms first, largest last
             if (NT > 3) {
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l, b_h, c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, b_l, c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_m, b_m, c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[rb], bh[cb], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rb], bl[cb], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[rb], bm[cb], c, 0, 0, 0);
             }
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_m, b_h, c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, b_m, c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, b_h, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[rb], bh[cb], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rb], bm[cb], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rb], bh[cb], c, 0, 0, 0);
             acc[rb][cb] = c;
           }
         }
       }
-      wave_sync();
-    }
-    const DevColTuple *cols = P.cols + sec.col0;
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-      if (cb >= cbn) continue;
-      const int c = tile.n0 + 16 * cb + (lane & 15);
-      if (c >= sec.N || c >= tile.n0 + tile.ncols) continue;
-      const int j = find_col(cols, sec.Q, c);
-      const int64_t cbase = P.cgrid[rt.cgrid + j];
-      if (cbase < 0) continue;
-      const int64_t nj = cols[j].n;
-      const int64_t cl = c - cols[j].no;
+      for (int cb = 0; cb < CB; ++cb) {
+        if (cb >= x.cbn || x.cbase[cb] < 0) continue;
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb) {
-        if (rb >= rbn) continue;
+        for (int rb = 0; rb < RB; ++rb) {
+          if (rb >= rbn) continue;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int lr = 16 * rb + 4 * (lane >> 4) + v;
-          if (lr < tile.nrows) C[cbase + (int64_t)(tile.m0 + lr) * nj + cl] = Out(acc[rb][cb][v]);
+          for (int v = 0; v < 4; ++v) {
+            const int lr = 16 * rb + 4 * (lane >> 4) + v;
+            if (lr < rows)
+              x.C.put(x.cbase[cb] + (int64_t)(x.tile.m0 + mc + lr) * x.cnj[cb] + x.ccl[cb], Out(acc[rb][cb][v]));
+          }
         }
       }
     }
@@ -607,7 +762,8 @@ yastn_status upload(Plan &pl) {
   size_t o_probs = take(bytes_of(t.probs)), o_sec = take(bytes_of(t.sectors)), o_rows = take(bytes_of(t.rows)),
          o_ctrs = take(bytes_of(t.ctrs)), o_cols = take(bytes_of(t.cols)), o_agrid = take(bytes_of(t.agrid)),
          o_aoff = take(bytes_of(t.aoff)), o_cgrid = take(bytes_of(t.cgrid)), o_bb = take(bytes_of(t.bblocks)),
-         o_tiles = take(bytes_of(t.tiles)), o_items = take(bytes_of(t.items)), o_plan = take(sizeof(DevPlan));
+         o_tiles = take(bytes_of(t.tiles)), o_items = take(bytes_of(t.items)), o_kofs = take(bytes_of(t.kofs)),
+         o_kp = take(bytes_of(t.kp)), o_cm = take(bytes_of(t.colmap)), o_plan = take(sizeof(DevPlan));
   char *base;
   yastn_status s = dmalloc(&base, off);
   if (s) return s;
@@ -627,6 +783,9 @@ yastn_status upload(Plan &pl) {
   put(o_bb, t.bblocks.data(), bytes_of(t.bblocks));
   put(o_tiles, t.tiles.data(), bytes_of(t.tiles));
   put(o_items, t.items.data(), bytes_of(t.items));
+  put(o_kofs, t.kofs.data(), bytes_of(t.kofs));
+  put(o_kp, t.kp.data(), bytes_of(t.kp));
+  put(o_cm, t.colmap.data(), bytes_of(t.colmap));
   DevPlan dp{};
   dp.probs = reinterpret_cast<const DevProb *>(base + o_probs);
   dp.sectors = reinterpret_cast<const DevSector *>(base + o_sec);
@@ -639,6 +798,9 @@ yastn_status upload(Plan &pl) {
   dp.bblocks = reinterpret_cast<const DevBBlock *>(base + o_bb);
   dp.tiles = reinterpret_cast<const DevTile *>(base + o_tiles);
   dp.items = reinterpret_cast<const DevPackItem *>(base + o_items);
+  dp.kofs = reinterpret_cast<const int64_t *>(base + o_kofs);
+  dp.kp = reinterpret_cast<const DevKP *>(base + o_kp);
+  dp.colmap = reinterpret_cast<const DevColMap *>(base + o_cm);
   dp.ntiles = (int32_t)t.tiles.size();
   dp.nitems = (int32_t)t.items.size();
   put(o_plan, &dp, sizeof(dp));
@@ -648,40 +810,94 @@ yastn_status upload(Plan &pl) {
 }
 
 // ---- kernel dispatch -------------------------------------------------------
+// Kernel variants of one plan: 0 = the plan's heuristic choice; 1..kVariants-1
+// = MFMA tiles with (rows per chunk, k-steps per load batch) from kMfmaShapes,
+// or the row-per-lane kernel.  yastn_plan_autotune times the candidates.
+// RB only tunes speed (a tile of any height is walked in chunks); CB must
+// cover the plan's tile width.  Without buffer addressing (buffers of 2 GiB
+// or more) one general MFMA shape is compiled.
 typedef void (*KernelFn)(LaunchArgs);
 
-template <typename In, typename Cmp, typename Out>
-KernelFn pick_gemm4(int cb) {
+struct Shape {
+  int rb, kb;
+};
+constexpr Shape kMfmaShapes[] = {{4, 2}, {4, 1}, {4, 4}, {2, 2}, {2, 4}, {1, 4}};
+constexpr int kNumMfma = sizeof(kMfmaShapes) / sizeof(Shape);
+constexpr int kVariantRows = kNumMfma + 1;  // variant ids: 1..kNumMfma MFMA, kVariantRows rows
+constexpr int kVariants = kVariantRows + 1;
+static_assert(kVariants == YASTN_NUM_VARIANTS, "variant count must match the header");
+
+template <typename In, typename Cmp, typename Out, int RB, int KB>
+KernelFn pick_mfma_cb(int cb) {
   switch (cb) {
-    case 1: return k_gemm4<In, Cmp, Out, 1>;
-    case 2: return k_gemm4<In, Cmp, Out, 2>;
-    case 3: return k_gemm4<In, Cmp, Out, 3>;
-    default: return k_gemm4<In, Cmp, Out, 4>;
+    case 1: return k_gemm4<In, Cmp, Out, true, RB, 1, KB>;
+    case 2: return k_gemm4<In, Cmp, Out, true, RB, 2, KB>;
+    case 3: return k_gemm4<In, Cmp, Out, true, RB, 3, KB>;
+    default: return k_gemm4<In, Cmp, Out, true, RB, 4, KB>;
   }
 }
+template <typename In, typename Cmp, typename Out>
+KernelFn pick_gemm4(bool buf, int shape, int cb) {
+  if (!buf) return k_gemm4<In, Cmp, Out, false, 4, 4, 2>;
+  if (std::is_same<Cmp, double>::value) {
+    switch (shape) {
+      case 1: return pick_mfma_cb<In, Cmp, Out, 4, 1>(cb);
+      case 2: return pick_mfma_cb<In, Cmp, Out, 4, 4>(cb);
+      case 3: return pick_mfma_cb<In, Cmp, Out, 2, 2>(cb);
+      case 4: return pick_mfma_cb<In, Cmp, Out, 2, 4>(cb);
+      case 5: return pick_mfma_cb<In, Cmp, Out, 1, 4>(cb);
+      default: break;
+    }
+  } else if (shape == 3 || shape == 4 || shape == 5) {
+    return pick_mfma_cb<In, Cmp, Out, 2, 4>(cb);
+  }
+  return pick_mfma_cb<In, Cmp, Out, 4, 2>(cb);
+}
 template <typename In, typename Out, int NT>
-KernelFn pick_bf16(int cb) {
+KernelFn pick_bf16(bool buf, int cb) {
+  if (!buf) return k_gemm_bf16<In, Out, false, 4, 4, NT>;
   switch (cb) {
-    case 1: return k_gemm_bf16<In, Out, 1, NT>;
-    case 2: return k_gemm_bf16<In, Out, 2, NT>;
-    case 3: return k_gemm_bf16<In, Out, 3, NT>;
-    default: return k_gemm_bf16<In, Out, 4, NT>;
+    case 1: return k_gemm_bf16<In, Out, true, 4, 1, NT>;
+    case 2: return k_gemm_bf16<In, Out, true, 4, 2, NT>;
+    case 3: return k_gemm_bf16<In, Out, true, 4, 3, NT>;
+    default: return k_gemm_bf16<In, Out, true, 4, 4, NT>;
   }
 }
 template <typename In, typename Out>
-KernelFn pick_gemm(yastn_precision p, int cb) {
+KernelFn pick_gemm(yastn_precision p, bool buf, int shape, int cb) {
   switch (p) {
-    case YASTN_F64: return pick_gemm4<In, double, Out>(cb);
-    case YASTN_F32: return pick_gemm4<In, float, Out>(cb);
-    case YASTN_BF16X3: return pick_bf16<In, Out, 3>(cb);
-    default: return pick_bf16<In, Out, 6>(cb);
+    case YASTN_F32: return pick_gemm4<In, float, Out>(buf, shape, cb);
+    case YASTN_BF16X3: return pick_bf16<In, Out, 3>(buf, cb);
+    default: return pick_bf16<In, Out, 6>(buf, cb);
   }
 }
-KernelFn gemm_kernel(const yastn_options &o, int cb) {
-  if (o.in_dtype == YASTN_DTYPE_F64)
-    return o.out_dtype == YASTN_DTYPE_F64 ? pick_gemm<double, double>(o.precision, cb) : pick_gemm<double, float>(o.precision, cb);
-  return o.out_dtype == YASTN_DTYPE_F64 ? pick_gemm<float, double>(o.precision, cb) : pick_gemm<float, float>(o.precision, cb);
+KernelFn gemm_kernel(const yastn_options &o, bool buf, int shape, int cb) {
+  if (o.in_dtype == YASTN_DTYPE_F64) {
+    if (o.precision == YASTN_F64) return pick_gemm4<double, double, double>(buf, shape, cb);
+    return o.out_dtype == YASTN_DTYPE_F64 ? pick_gemm<double, double>(o.precision, buf, shape, cb)
+                                          : pick_gemm<double, float>(o.precision, buf, shape, cb);
+  }
+  return o.out_dtype == YASTN_DTYPE_F64 ? pick_gemm<float, double>(o.precision, buf, shape, cb)
+                                        : pick_gemm<float, float>(o.precision, buf, shape, cb);
 }
+template <typename In, typename Cmp, typename Out>
+KernelFn pick_rows(bool buf, int kmax) {
+  if (!buf) return k_rows<In, Cmp, Out, false, 64>;
+  if (kmax <= 16) return k_rows<In, Cmp, Out, true, 16>;
+  if (kmax <= 32) return k_rows<In, Cmp, Out, true, 32>;
+  if (kmax <= 48) return k_rows<In, Cmp, Out, true, 48>;
+  return k_rows<In, Cmp, Out, true, 64>;
+}
+KernelFn rows_kernel(const yastn_options &o, bool buf, int kmax) {
+  if (o.in_dtype == YASTN_DTYPE_F64) {
+    if (o.precision == YASTN_F64) return pick_rows<double, double, double>(buf, kmax);
+    return o.out_dtype == YASTN_DTYPE_F64 ? pick_rows<double, float, double>(buf, kmax)
+                                          : pick_rows<double, float, float>(buf, kmax);
+  }
+  return o.out_dtype == YASTN_DTYPE_F64 ? pick_rows<float, float, double>(buf, kmax)
+                                        : pick_rows<float, float, float>(buf, kmax);
+}
+
 KernelFn pack_kernel(const yastn_options &o) {
   const bool f64cmp = o.precision == YASTN_F64;
   if (o.in_dtype == YASTN_DTYPE_F64) return f64cmp ? k_pack_b<double, double> : k_pack_b<double, float>;
@@ -709,12 +925,27 @@ struct JobRef {
   void *ws;
 };
 
-yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st) {
-  if (jobs.empty()) return YASTN_OK;
+yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const *events = nullptr) {
+  if (events && events[0]) YASTN_HIP(hipEventRecord(reinterpret_cast<hipEvent_t>(events[0]), st));
+  if (jobs.empty()) {
+    if (events && events[1]) YASTN_HIP(hipEventRecord(reinterpret_cast<hipEvent_t>(events[1]), st));
+    if (events && events[2]) YASTN_HIP(hipEventRecord(reinterpret_cast<hipEvent_t>(events[2]), st));
+    return YASTN_OK;
+  }
   const yastn_options &o = jobs[0].plan->opts;
-  int cb = 1;
-  for (auto &j : jobs) cb = std::max(cb, j.plan->cb);
-  KernelFn gemm = gemm_kernel(o, cb), pack = pack_kernel(o);
+  int cb = 1, kmax = 0, variant = jobs[0].plan->variant;
+  bool buf = true, rows_fit = true, rows_pick = true;
+  for (auto &j : jobs) {
+    cb = std::max(cb, j.plan->cb);
+    kmax = std::max(kmax, j.plan->kmax);
+    buf = buf && j.plan->buf_ok;
+    rows_fit = rows_fit && j.plan->rows_fit;
+    rows_pick = rows_pick && j.plan->rows_kernel;
+    if (j.plan->variant != variant) variant = 0;
+  }
+  bool rows = variant == 0 ? rows_pick : (variant == kVariantRows && rows_fit);
+  const int shape = (variant >= 1 && variant <= kNumMfma) ? variant - 1 : 0;
+  KernelFn gemm = rows ? rows_kernel(o, buf, kmax) : gemm_kernel(o, buf, shape, cb), pack = pack_kernel(o);
   size_t ji = 0;
   while (ji < jobs.size()) {
     LaunchArgs la;
@@ -746,13 +977,15 @@ yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st) {
     const int max_wg = num_cus() * 4;
     void *kargs[] = {&la};
     if (la.nitems > 0) {
-      unsigned g = (unsigned)std::min<int64_t>((la.nitems + 3) / 4, max_wg);
+      unsigned g = (unsigned)std::min<int64_t>(la.nitems, 16 * max_wg);
       YASTN_HIP(hipLaunchKernel(reinterpret_cast<const void *>(pack), dim3(g), dim3(256), kargs, 0, st));
     }
+    if (events && events[1]) YASTN_HIP(hipEventRecord(reinterpret_cast<hipEvent_t>(events[1]), st));
     if (la.ntiles > 0) {
       unsigned g = (unsigned)std::min<int64_t>((la.ntiles + 3) / 4, max_wg);
       YASTN_HIP(hipLaunchKernel(reinterpret_cast<const void *>(gemm), dim3(g), dim3(256), kargs, 0, st));
     }
+    if (events && events[2]) YASTN_HIP(hipEventRecord(reinterpret_cast<hipEvent_t>(events[2]), st));
   }
   return YASTN_OK;
 }
@@ -828,44 +1061,72 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
       delete h;
       return set_error(YASTN_ERR_HIP, "no HIP device");
     }
-    // column blocks per wave tile: enough for the widest sector, at most 4 (64 columns)
     std::vector<std::vector<std::pair<int32_t, int32_t>>> allpairs(nprob);
     for (int p = 0; p < nprob; ++p)
       if ((s = gpu_join(pl.probs[p], st, allpairs[p])) != YASTN_OK) {
         delete h;
         return s;
       }
-    // first pass: widest sector decides the tile width of the plan
+    // Pass 0 builds 64 x 64 tiles to learn the sector shapes; then the plan
+    // picks the kernel family and, for MFMA, the tile width, and rebuilds if
+    // the tiling changed.
     int64_t a_base = 0, b_base = 0;
-    pl.cb = 4;
-    for (int pass = 0; pass < 2; ++pass) {
+    auto build_all = [&](int rb, int cb, int nch) -> yastn_status {
       pl.t = PlanTables{};
       pl.prob_t0.clear();
       pl.prob_i0.clear();
       a_base = b_base = 0;
+      pl.rb = rb;
+      pl.cb = cb;
+      pl.nch = nch;
       for (int p = 0; p < nprob; ++p) {
         pl.prob_t0.push_back((int32_t)pl.t.tiles.size());
         pl.prob_i0.push_back((int32_t)pl.t.items.size());
-        if ((s = build_structure(pl.probs[p], p, allpairs[p], a_base, b_base, pl.t, pl.cb)) != YASTN_OK) {
-          delete h;
-          return s;
-        }
+        yastn_status st2 = build_structure(pl.probs[p], p, allpairs[p], a_base, b_base, pl.t, rb, cb, nch);
+        if (st2 != YASTN_OK) return st2;
         a_base += pl.probs[p].a.nblocks;
         b_base += pl.probs[p].b.nblocks;
       }
-      if (pass == 0) {
-        int64_t maxn = 1;
-        for (auto &sec : pl.t.sectors) maxn = std::max<int64_t>(maxn, sec.N);
-        int cb = (int)std::min<int64_t>(4, (maxn + 15) / 16);
-        if (cb == pl.cb) break;
-        pl.cb = cb;
-      }
+      return YASTN_OK;
+    };
+    if ((s = build_all(4, 4, 1)) != YASTN_OK) {
+      delete h;
+      return s;
     }
+    int64_t maxn = 1, maxk = 0, rows = 0, rows64 = 0;
+    for (auto &sec : pl.t.sectors) {
+      maxn = std::max<int64_t>(maxn, sec.N);
+      maxk = std::max<int64_t>(maxk, sec.K);
+    }
+    for (auto &rt : pl.t.rows) {
+      rows += rt.m;
+      rows64 += (rt.m + 63) / 64 * 64;
+    }
+    pl.kmax = (int)maxk;
+    const bool bf16 = o.precision == YASTN_BF16X3 || o.precision == YASTN_BF16X6;
+    pl.rows_fit = !bf16 && maxk <= 64 && maxn <= 64;
+    pl.rows_kernel = pl.rows_fit && o.flags == YASTN_FLAG_ROWS;
+    pl.variant = 0;
+    // tiles: 64 rows (walked in chunks by every kernel) x the narrowest column
+    // width that covers the widest sector (at most 64)
+    const int cb = (int)std::min<int64_t>(4, (maxn + 15) / 16);
+    if (cb != 4 && (s = build_all(4, cb, 1)) != YASTN_OK) {
+      delete h;
+      return s;
+    }
+    if (o.tile_rows) pl.variant = o.tile_rows == 64 ? 1 : (o.tile_rows == 32 ? 4 : 6);
+    (void)rows;
+    (void)rows64;
     if (a_base > INT32_MAX || b_base > INT32_MAX) {
       delete h;
       return set_error(YASTN_ERR_ARG, "too many blocks in one plan");
     }
     finish_tiles(pl);
+    // buffer addressing needs every A span and C size below 2 GiB
+    const int64_t in_b = o.in_dtype == YASTN_DTYPE_F64 ? 8 : 4, out_b = o.out_dtype == YASTN_DTYPE_F64 ? 8 : 4;
+    pl.buf_ok = true;
+    for (const DevProb &dp : pl.t.probs)
+      if (dp.a_span * in_b >= (int64_t(1) << 31) || dp.c_numel * out_b >= (int64_t(1) << 31)) pl.buf_ok = false;
     if ((s = upload(pl)) != YASTN_OK) {
       yastn_free(h);
       return s;
@@ -916,6 +1177,74 @@ yastn_status yastn_contract(yastn_plan_t plan, const void *const *a, const void 
   std::vector<JobRef> jobs;
   for (const Group &g : plan->p.groups) jobs.push_back(JobRef{&plan->p, &g, a, b, c, workspace});
   return launch(jobs, reinterpret_cast<hipStream_t>(hip_stream));
+}
+
+yastn_status yastn_contract_timed(yastn_plan_t plan, const void *const *a, const void *const *b, void *const *c,
+                                  void *workspace, void *hip_stream, void *const *events) {
+  if (!plan) return set_error(YASTN_ERR_ARG, "null plan");
+  if (plan->p.groups.size() > 1) return set_error(YASTN_ERR_STATE, "timed contraction needs a plan of one launch");
+  yastn_status s = check_job_ptrs(&plan->p, a, b, c, workspace);
+  if (s) return s;
+  std::vector<JobRef> jobs;
+  for (const Group &g : plan->p.groups) jobs.push_back(JobRef{&plan->p, &g, a, b, c, workspace});
+  return launch(jobs, reinterpret_cast<hipStream_t>(hip_stream), events);
+}
+
+yastn_status yastn_plan_set_variant(yastn_plan_t plan, int32_t variant) {
+  if (!plan) return set_error(YASTN_ERR_ARG, "null plan");
+  if (variant < 0 || variant >= kVariants) return set_error(YASTN_ERR_ARG, "variant out of range");
+  if (variant == kVariantRows && !plan->p.rows_fit) return set_error(YASTN_ERR_STATE, "row kernel does not fit this plan");
+  plan->p.variant = variant;
+  return YASTN_OK;
+}
+
+yastn_status yastn_plan_autotune(yastn_plan_t plan, const void *const *a, const void *const *b, void *const *c,
+                                 void *workspace, void *hip_stream, int32_t reps, int32_t *chosen, float *times_ms) {
+  if (!plan || reps < 1) return set_error(YASTN_ERR_ARG, "bad argument");
+  yastn_status s = check_job_ptrs(&plan->p, a, b, c, workspace);
+  if (s) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  std::vector<JobRef> jobs;
+  for (const Group &g : plan->p.groups) jobs.push_back(JobRef{&plan->p, &g, a, b, c, workspace});
+  hipEvent_t e0, e1;
+  YASTN_HIP(hipEventCreate(&e0));
+  YASTN_HIP(hipEventCreate(&e1));
+  const int keep = plan->p.variant;
+  const bool bf16 = plan->p.opts.precision == YASTN_BF16X3 || plan->p.opts.precision == YASTN_BF16X6;
+  const bool f32 = plan->p.opts.precision == YASTN_F32;
+  int best = 1;
+  float best_ms = 1e30f;
+  for (int v = 1; v < kVariants; ++v) {
+    float ms = -1.f;
+    const bool applicable = v == 1 || (v == kVariantRows ? plan->p.rows_fit
+                                                         : (!bf16 && plan->p.buf_ok && (!f32 || v == 4)));
+    if (applicable) {
+      plan->p.variant = v;
+      s = launch(jobs, st);  // warm-up
+      if (!s) s = (hipEventRecord(e0, st) == hipSuccess) ? YASTN_OK : YASTN_ERR_HIP;
+      for (int r = 0; r < reps && !s; ++r) s = launch(jobs, st);
+      if (!s && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+          hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
+        ms /= reps;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = v;
+        }
+      }
+      if (s) break;
+    }
+    if (times_ms) times_ms[v] = ms;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s) {
+    plan->p.variant = keep;
+    return s;
+  }
+  plan->p.variant = best;
+  if (chosen) *chosen = best;
+  if (times_ms) times_ms[0] = best_ms;
+  return YASTN_OK;
 }
 
 yastn_status yastn_contract_jobs(const yastn_job *jobs, int32_t njobs, void *hip_stream) {

@@ -149,7 +149,8 @@ yastn_status check_options(const yastn_options *o, yastn_options *out) {
     return set_error(YASTN_ERR_ARG, "F64 arithmetic needs F64 input and output buffers");
   if (d.tile_rows != 0 && d.tile_rows != 16 && d.tile_rows != 32 && d.tile_rows != 64)
     return set_error(YASTN_ERR_ARG, "tile_rows must be 0, 16, 32 or 64");
-  if (d.flags != 0) return set_error(YASTN_ERR_ARG, "flags must be 0");
+  if (d.flags != 0 && d.flags != YASTN_FLAG_MFMA && d.flags != YASTN_FLAG_ROWS)
+    return set_error(YASTN_ERR_ARG, "flags must be 0, YASTN_FLAG_MFMA or YASTN_FLAG_ROWS");
   *out = d;
   return YASTN_OK;
 }
@@ -229,7 +230,7 @@ struct SectorBuild {
 }  // namespace
 
 yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::pair<int32_t, int32_t>> &pairs,
-                             int64_t a_base, int64_t b_base, PlanTables &t, int cb) {
+                             int64_t a_base, int64_t b_base, PlanTables &t, int rb, int cb, int nch) {
   const HostTensor &A = hp.a, &B = hp.b;
   const int nsym = A.nsym, nc = hp.nc;
   // ---- group matches by sector X = sum over A's contracted legs of s_i rho_i
@@ -273,6 +274,8 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
   dp.nact = nact;
   dp.nc = nc;
   dp.nfb = hp.nfb;
+  for (int64_t b = 0; b < A.nblocks; ++b) dp.a_span = std::max<int64_t>(dp.a_span, A.offsets[b] + A.size(b));
+  const size_t prob_slot = t.probs.size();
   t.probs.push_back(dp);
   // ---- output blocks: (A free tuple, B free tuple) reached by >= 1 pair, ascending order
   std::map<Key, std::vector<int64_t>> cblocks;  // key -> shape
@@ -308,6 +311,7 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
     pos += sz;
   }
   hp.c_numel = pos;
+  t.probs[prob_slot].c_numel = pos;
   // ---- A block offsets and B block strides (plan-global indices)
   for (int64_t b = 0; b < A.nblocks; ++b) t.aoff.push_back(A.offsets[b]);
   for (int64_t b = 0; b < B.nblocks; ++b) {
@@ -334,7 +338,7 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
   S.c_numel = hp.c_numel;
   S.numel_a = A.numel;
   S.numel_b = B.numel;
-  const int TN = 16 * cb;
+  const int TN = 16 * cb, TM = 16 * rb * nch;
   for (auto &kv : sect) {
     SectorBuild &sb = kv.second;
     int id = 0;
@@ -350,6 +354,7 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
     ds.Q = Q;
     ds.ctr0 = (int32_t)t.ctrs.size();
     ds.col0 = (int32_t)t.cols.size();
+    ds.nact = nact;
     // representative blocks for the dims of each tuple
     std::vector<int64_t> row_rep(R, -1), ctr_rep(Sn, -1), col_rep(Q, -1);
     std::vector<int32_t> agrid(size_t(R) * Sn, -1), bgrid(size_t(Sn) * Q, -1);
@@ -406,10 +411,27 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
     ds.N = N;
     ds.bpack = t.bpack_elems;
     t.bpack_elems += int64_t(K) * N;
+    // P_a of every contracted index, and the column map of C_X / B_X
+    ds.kp0 = (int64_t)t.kp.size();
+    for (int s = 0; s < Sn; ++s) {
+      const DevCtrTuple &ct = t.ctrs[ds.ctr0 + s];
+      DevKP kp{};
+      for (int a = 0; a < kMaxAct; ++a) kp.p[a] = ct.p[a];
+      for (int k = 0; k < ct.k; ++k) t.kp.push_back(kp);
+    }
+    ds.cm0 = (int64_t)t.colmap.size();
+    for (int j = 0; j < Q; ++j) {
+      const DevColTuple &cl = t.cols[ds.col0 + j];
+      for (int c = 0; c < cl.n; ++c) t.colmap.push_back(DevColMap{j, c, cl.n, 0});
+    }
     const int32_t sec_id = (int32_t)t.sectors.size();
     t.sectors.push_back(ds);
     for (int s = 0; s < Sn; ++s)
-      for (int j = 0; j < Q; ++j) t.items.push_back(DevPackItem{sec_id, s, j, bgrid[size_t(s) * Q + j]});
+      for (int j = 0; j < Q; ++j) {
+        const int64_t total = int64_t(t.ctrs[ds.ctr0 + s].k) * t.cols[ds.col0 + j].n;
+        for (int64_t e0 = 0; e0 < total; e0 += kPackItem)
+          t.items.push_back(DevPackItem{sec_id, s, j, bgrid[size_t(s) * Q + j], (int32_t)e0, 0});
+      }
     std::vector<Key> rowkeys(R), colkeys(Q);
     for (auto &r : sb.rows) rowkeys[r.second] = r.first;
     for (auto &c : sb.cols) colkeys[c.second] = c.first;
@@ -436,6 +458,24 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
       }
       rt.agrid = (int64_t)t.agrid.size();
       t.agrid.insert(t.agrid.end(), agrid.begin() + size_t(i) * Sn, agrid.begin() + size_t(i + 1) * Sn);
+      // offset of A(row 0, k) for every contracted index k of the sector (-1: block absent)
+      rt.kofs = (int64_t)t.kofs.size();
+      for (int s = 0; s < Sn; ++s) {
+        const DevCtrTuple &ct = t.ctrs[ds.ctr0 + s];
+        const int32_t blk = agrid[size_t(i) * Sn + s];
+        for (int64_t kd = 0; kd < ct.k; ++kd) {
+          if (blk < 0) {
+            t.kofs.push_back(-1);
+            continue;
+          }
+          int64_t r = kd, koff = 0;
+          for (int c = nc - 1; c >= 0; --c) {
+            koff += (r % ct.dims[c]) * (int64_t)rt.fac[c] * ct.cac[c];
+            r /= ct.dims[c];
+          }
+          t.kofs.push_back(t.aoff[blk] + koff);
+        }
+      }
       rt.cgrid = (int64_t)t.cgrid.size();
       for (int j = 0; j < Q; ++j) {
         Key k = rowkeys[i];
@@ -445,14 +485,15 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
       }
       const int32_t row_id = (int32_t)t.rows.size();
       t.rows.push_back(rt);
-      for (int32_t m0 = 0; m0 < rt.m; m0 += kWaveRows)
+      for (int32_t m0 = 0; m0 < rt.m; m0 += TM)
         for (int32_t n0 = 0; n0 < N; n0 += TN) {
           DevTile tl{};
           tl.rowtuple = row_id;
+          tl.sector = sec_id;
           tl.m0 = m0;
           tl.n0 = n0;
-          tl.nrows = (int16_t)std::min<int32_t>(kWaveRows, rt.m - m0);
-          tl.ncols = (int16_t)std::min<int32_t>(TN, N - n0);
+          tl.nrows = std::min<int32_t>(TM, rt.m - m0);
+          tl.ncols = std::min<int32_t>(TN, N - n0);
           t.tiles.push_back(tl);
           S.tiles += 1;
           S.mfma_flops += 2.0 * (16.0 * ((tl.nrows + 15) / 16)) * (4.0 * ((K + 3) / 4)) * (16.0 * ((tl.ncols + 15) / 16));

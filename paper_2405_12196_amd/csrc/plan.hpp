@@ -25,7 +25,7 @@
 //     sum_c y_c(kd) * FAc_c(i) * CAc_c(s),
 // FAc_c = product of free dims after leg c, CAc_c = product of contracted
 // dims after leg c.  So every element costs nact multiply-adds on top of a
-// per-k offset table built once per tile.
+// per-(row tuple, k) offset table the plan builds once (kofs).
 #pragma once
 #include <cstdint>
 
@@ -35,14 +35,15 @@ constexpr int kMaxRank = 8;
 constexpr int kMaxAct = 4;     // free-leg classes of A (<= min(#free, #contracted + 1))
 constexpr int kMaxJobs = 32;   // plans per launch
 constexpr int kMaxProbs = 64;  // problems per launch (pointer triples in kernel args)
-constexpr int kWaveRows = 64;  // rows per wave tile (4 MFMA row blocks of 16)
-constexpr int kKChunk = 128;   // contracted indices per LDS offset table
+constexpr int kPackItem = 256; // packed-B elements per pack work item
 
 struct DevProb {               // one problem of a plan
   int32_t nact;                // active free-leg classes of A
   int32_t nc;                  // contracted legs
   int32_t nfb;                 // free legs of B
   int32_t pad;
+  int64_t a_span;              // elements of A's buffer that blocks reach (max offset + size)
+  int64_t c_numel;             // elements of C
 };
 
 struct DevSector {             // one (problem, sector)
@@ -50,8 +51,10 @@ struct DevSector {             // one (problem, sector)
   int32_t S, Q;                // contracted tuples, col tuples
   int32_t K, N;                // K_X, N_X
   int32_t ctr0, col0;          // first ctr tuple / col tuple (plan-global index)
-  int32_t pad;
+  int32_t nact;                // active free-leg classes of A (copy of the problem's)
   int64_t bpack;               // element offset of packed B_X (K_X x N_X, row-major) in workspace
+  int64_t kp0;                 // first of K_X entries in kp (P_a of each contracted index)
+  int64_t cm0;                 // first of N_X entries in colmap
 };
 
 struct DevRowTuple {           // one (problem, sector, A free tuple)
@@ -59,8 +62,20 @@ struct DevRowTuple {           // one (problem, sector, A free tuple)
   int32_t m;                   // rows
   int64_t agrid;               // first of S entries in agrid (A block or -1)
   int64_t cgrid;               // first of Q entries in cgrid (C element offset or -1)
+  int64_t kofs;                // first of K_X entries in kofs (A offset of (row 0, k), -1 absent)
   int32_t lsuf[kMaxAct + 1];   // Lsuf_a, a = 0..nact
   int32_t fac[kMaxRank];       // FAc_c, contracted legs in axes order
+};
+
+struct DevColMap {             // one column of a sector's C_X / B_X
+  int32_t j;                   // column tuple (sector-local)
+  int32_t cl;                  // column within the tuple
+  int32_t nj;                  // n_j
+  int32_t pad;
+};
+
+struct DevKP {                 // P_a of one contracted index
+  int32_t p[kMaxAct];
 };
 
 struct DevCtrTuple {           // one (problem, sector, contracted tuple)
@@ -81,17 +96,21 @@ struct DevBBlock {             // one B block, strides for the pack kernel
   int32_t sf[kMaxRank];        // strides of free legs (storage order)
 };
 
-struct DevTile {               // one wave tile
+struct DevTile {               // one wave tile: rows [m0, m0 + nrows) of a row tuple, in chunks
   int32_t rowtuple;            // plan-global row tuple
+  int32_t sector;              // its sector (saves a dependent load)
   int32_t m0;                  // first row within the row tuple
   int32_t n0;                  // first column within the sector
-  int16_t nrows, ncols;        // extent (<= 64 each)
+  int32_t nrows;               // rows (a multiple of the chunk height except at the tuple's end)
+  int32_t ncols;               // columns (<= 16 * column blocks of the kernel)
 };
 
-struct DevPackItem {           // one (sector, s, j) sub-block of packed B_X
+struct DevPackItem {           // up to 256 elements of one (sector, s, j) sub-block of packed B_X
   int32_t sector;
   int32_t s, j;
   int32_t bblk;                // B block (plan-global) or -1 (absent: zeros)
+  int32_t e0;                  // first element (row-major over k_s x n_j) of this item
+  int32_t pad;
 };
 
 struct DevPlan {               // device-resident table of the plan's arrays
@@ -106,6 +125,9 @@ struct DevPlan {               // device-resident table of the plan's arrays
   const DevBBlock *bblocks;
   const DevTile *tiles;
   const DevPackItem *items;
+  const int64_t *kofs;         // per row tuple, per contracted index
+  const DevKP *kp;             // per sector, per contracted index
+  const DevColMap *colmap;     // per sector, per column
   int32_t ntiles, nitems;
 };
 

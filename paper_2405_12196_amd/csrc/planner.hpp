@@ -54,6 +54,9 @@ struct PlanTables {
   std::vector<DevBBlock> bblocks;
   std::vector<DevTile> tiles;
   std::vector<DevPackItem> items;
+  std::vector<int64_t> kofs;
+  std::vector<DevKP> kp;
+  std::vector<DevColMap> colmap;
   int64_t bpack_elems = 0;  // packed B elements in the workspace
 };
 
@@ -72,6 +75,13 @@ struct Plan {
   yastn_options opts{};
   PlanTables t;
   int cb = 4;               // column blocks (16 columns each) per wave tile
+  int rb = 4;               // row blocks (16 rows each) per chunk of a wave tile
+  int nch = 1;              // chunks per wave tile
+  bool buf_ok = true;       // every buffer small enough for 32-bit buffer addressing
+  bool rows_kernel = false; // heuristic choice (variant 0): one output row per lane instead of MFMA tiles
+  bool rows_fit = false;    // every sector has K, N <= 64: the row-per-lane kernel can run
+  int variant = 0;          // kernel variant (0 = heuristic; set by yastn_plan_autotune)
+  int kmax = 0;             // largest K_X of the plan
   void *dev_mem = nullptr;  // one device allocation holding every table
   DevPlan *dplan = nullptr; // device copy of the table of pointers
   size_t ws_bytes = 0;
@@ -86,7 +96,7 @@ yastn_status check_options(const yastn_options *o, yastn_options *out);
 yastn_status validate_problem(const yastn_problem &p, HostProblem &hp);
 void contracted_keys(const HostTensor &t, const int *axes, int nc, std::vector<int32_t> &keys);
 yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::pair<int32_t, int32_t>> &pairs,
-                             int64_t a_base, int64_t b_base, PlanTables &t, int cb);
+                             int64_t a_base, int64_t b_base, PlanTables &t, int rb, int cb, int nch);
 void finish_tiles(Plan &plan);
 
 }  // namespace yastn

@@ -33,7 +33,7 @@ extern "C" {
 
 const char *emu_error() { return g_msg.c_str(); }
 
-void *emu_plan(const yastn_problem *probs, int nprob, int cb_override) {
+void *emu_plan(const yastn_problem *probs, int nprob, int rb_override, int cb_override) {
   Emu *e = new Emu();
   Plan &pl = e->pl;
   check_options(nullptr, &pl.opts);
@@ -60,11 +60,13 @@ void *emu_plan(const yastn_problem *probs, int nprob, int cb_override) {
     }
   }
   pl.cb = cb_override;
+  pl.rb = rb_override;
+  pl.nch = 1 + (rb_override == 2);  // exercise multi-chunk tiles too
   int64_t ab = 0, bb = 0;
   for (int p = 0; p < nprob; ++p) {
     pl.prob_t0.push_back((int32_t)pl.t.tiles.size());
     pl.prob_i0.push_back((int32_t)pl.t.items.size());
-    if (build_structure(pl.probs[p], p, pairs[p], ab, bb, pl.t, pl.cb) != YASTN_OK) {
+    if (build_structure(pl.probs[p], p, pairs[p], ab, bb, pl.t, pl.rb, pl.cb, pl.nch) != YASTN_OK) {
       g_msg = "build_structure failed";
       delete e;
       return nullptr;
@@ -85,6 +87,9 @@ void *emu_plan(const yastn_problem *probs, int nprob, int cb_override) {
   d.bblocks = pl.t.bblocks.data();
   d.tiles = pl.t.tiles.data();
   d.items = pl.t.items.data();
+  d.kofs = pl.t.kofs.data();
+  d.kp = pl.t.kp.data();
+  d.colmap = pl.t.colmap.data();
   d.ntiles = (int32_t)pl.t.tiles.size();
   d.nitems = (int32_t)pl.t.items.size();
   return e;
@@ -112,80 +117,77 @@ int emu_contract(void *h, const double *const *a, const int64_t *alen, const dou
   const DevPlan &P = e->dp;
   std::vector<double> ws(size_t(pl.t.bpack_elems) + 1, 0.0);
   std::vector<char> packed(size_t(pl.t.bpack_elems) + 1, 0);
-  // ---- k_pack_b
+  // ---- k_pack_b: one work item = up to kPackItem elements of one (s, j) sub-block
   for (int g = 0; g < P.nitems; ++g) {
     const DevPackItem it = P.items[g];
-    const DevSector sec = P.sectors[it.sector];
+    const DevSector &sec = P.sectors[it.sector];
     const DevCtrTuple &ct = P.ctrs[sec.ctr0 + it.s];
     const DevColTuple &cl = P.cols[sec.col0 + it.j];
-    const DevProb pr = P.probs[sec.prob];
-    const int64_t base = sec.bpack + (int64_t)ct.ko * sec.N + cl.no;
-    const int64_t total = (int64_t)ct.k * cl.n;
-    for (int64_t el = 0; el < total; ++el) {
-      const int64_t kd = el / cl.n, cb = el - kd * cl.n;
-      const int64_t d = base + kd * sec.N + cb;
+    for (int tid = 0; tid < kPackItem; ++tid) {
+      const int32_t e = it.e0 + tid;
+      if (e >= ct.k * cl.n) continue;
+      const int32_t kd = e / cl.n, cb = e - kd * cl.n;
+      const int64_t d = sec.bpack + (int64_t)(ct.ko + kd) * sec.N + cl.no + cb;
       if (d < sec.bpack || d >= sec.bpack + (int64_t)sec.K * sec.N) return fail("pack: write outside B_X");
       if (packed[d]++) return fail("pack: element written twice");
       if (it.bblk < 0) {
         ws[d] = 0.0;
         continue;
       }
-      const int64_t o = b_offset(P.bblocks[it.bblk], ct, cl, pr, kd, cb);
+      const int64_t o = b_offset(P.bblocks[it.bblk], ct, cl, P.probs[sec.prob], kd, cb);
       if (o < 0 || o >= blen[sec.prob]) return fail("pack: B read out of bounds");
       ws[d] = b[sec.prob][o];
     }
   }
   for (int64_t i = 0; i < pl.t.bpack_elems; ++i)
     if (packed[i] != 1) return fail("pack: packed B element not written");
-  // ---- k_gemm4 (tile, row, column, k loops with the kernel's guards)
+  // ---- k_gemm4: per tile, the lane's rows / columns / k as the kernel forms them
   std::vector<std::vector<char>> wrote(pl.probs.size());
   for (size_t p = 0; p < pl.probs.size(); ++p) wrote[p].assign(size_t(clen[p]) + 1, 0);
+  const int TM = 16 * pl.rb * pl.nch, TN = 16 * pl.cb;
   for (int t = 0; t < P.ntiles; ++t) {
     const DevTile tile = P.tiles[t];
     const DevRowTuple rt = P.rows[tile.rowtuple];
     const DevSector sec = P.sectors[rt.sector];
-    const DevProb pr = P.probs[sec.prob];
-    if (tile.nrows > kWaveRows || tile.ncols > 16 * pl.cb) return fail("tile larger than a wave tile");
+    const int nact = P.probs[sec.prob].nact;
+    if (tile.nrows > TM || tile.ncols > TN) return fail("tile larger than a wave tile");
     const double *Bp = ws.data() + sec.bpack;
-    std::vector<double> acc(size_t(kWaveRows) * 16 * pl.cb, 0.0);
-    for (int k0 = 0; k0 < sec.K; k0 += kKChunk) {
-      const int kend = std::min(sec.K, k0 + kKChunk);
-      if (kend - k0 > kKChunk) return fail("offset table overflow");
-      for (int k = k0; k < kend; ++k) {
-        int32_t pk[kMaxAct];
-        const int64_t koff = a_koffset(P, rt, sec, pr, k, pk);
-        for (int lr = 0; lr < tile.nrows; ++lr) {
-          int32_t rg[kMaxAct];
-          a_rowparts(rt, pr.nact, tile.m0 + lr, rg);
-          double av = 0.0;
-          if (koff >= 0) {
-            const int64_t o = a_offset(koff, pk, rg);
-            if (o < 0 || o >= alen[sec.prob]) return fail("gemm: A read out of bounds");
-            av = a[sec.prob][o];
-          }
-          for (int lc = 0; lc < 16 * pl.cb; ++lc) {
-            const int col = tile.n0 + lc;
-            if (col >= sec.N) continue;
-            const int64_t bi = (int64_t)k * sec.N + col;
-            if (bi >= (int64_t)sec.K * sec.N) return fail("gemm: packed B read out of bounds");
-            acc[size_t(lr) * 16 * pl.cb + lc] += av * Bp[bi];
-          }
+    const int64_t *kofs = P.kofs + rt.kofs;
+    const DevKP *kp = P.kp + sec.kp0;
+    if (rt.kofs + sec.K > (int64_t)pl.t.kofs.size() || sec.kp0 + sec.K > (int64_t)pl.t.kp.size())
+      return fail("offset table overflow");
+    std::vector<double> acc(size_t(TM) * TN, 0.0);
+    for (int k = 0; k < sec.K; ++k) {
+      const int64_t ko = kofs[k];
+      const DevKP p = kp[k];
+      for (int lr = 0; lr < TM; ++lr) {
+        if (lr >= tile.nrows) continue;
+        int32_t rg[kMaxAct];
+        a_rowparts(rt, nact, tile.m0 + lr, rg);
+        double av = 0.0;
+        if (ko >= 0) {
+          const int64_t o = a_offset(ko, p.p, rg);
+          if (o < 0 || o >= alen[sec.prob]) return fail("gemm: A read out of bounds");
+          av = a[sec.prob][o];
+        }
+        for (int lc = 0; lc < TN; ++lc) {
+          const int col = tile.n0 + lc;
+          if (col >= sec.N) continue;
+          acc[size_t(lr) * TN + lc] += av * Bp[(int64_t)k * sec.N + col];
         }
       }
     }
-    const DevColTuple *cols = P.cols + sec.col0;
-    for (int lc = 0; lc < 16 * pl.cb; ++lc) {
-      const int col = tile.n0 + lc;
-      if (col >= sec.N || col >= tile.n0 + tile.ncols) continue;
-      const int j = find_col(cols, sec.Q, col);
-      const int64_t cbase = P.cgrid[rt.cgrid + j];
+    for (int lc = 0; lc < TN; ++lc) {
+      if (lc >= tile.ncols) continue;
+      if (sec.cm0 + tile.n0 + lc >= (int64_t)pl.t.colmap.size()) return fail("colmap overflow");
+      const DevColMap cm = P.colmap[sec.cm0 + tile.n0 + lc];
+      const int64_t cbase = P.cgrid[rt.cgrid + cm.j];
       if (cbase < 0) continue;
-      const int64_t nj = cols[j].n, cl = col - cols[j].no;
       for (int lr = 0; lr < tile.nrows; ++lr) {
-        const int64_t o = cbase + (int64_t)(tile.m0 + lr) * nj + cl;
+        const int64_t o = cbase + (int64_t)(tile.m0 + lr) * cm.nj + cm.cl;
         if (o < 0 || o >= clen[sec.prob]) return fail("gemm: C write out of bounds");
         if (wrote[sec.prob][o]++) return fail("gemm: C element written twice");
-        c[sec.prob][o] = acc[size_t(lr) * 16 * pl.cb + lc];
+        c[sec.prob][o] = acc[size_t(lr) * TN + lc];
       }
     }
   }

@@ -31,11 +31,12 @@ def workspace(pl):
     return torch.empty(max(256, pl.workspace_bytes), dtype=torch.uint8, device=DEV)
 
 
-def run(problems, precision="f64", in_dtype=None, out_dtype=None, tile_rows=0, repeat=1):
+def run(problems, precision="f64", in_dtype=None, out_dtype=None, tile_rows=0, repeat=1, flags=0):
     """problems: list of (A, B, axes_a, axes_b) BlockTensors.  Returns
     (plan, [Structure], [np.float64 arrays of C values])."""
     import torch
-    pl = Y.plan(problems, precision=precision, in_dtype=in_dtype, out_dtype=out_dtype, tile_rows=tile_rows)
+    pl = Y.plan(problems, precision=precision, in_dtype=in_dtype, out_dtype=out_dtype, tile_rows=tile_rows,
+                flags=flags)
     A = [upload(a, pl.in_dtype) for a, _, _, _ in problems]
     B = [upload(b, pl.in_dtype) for _, b, _, _ in problems]
     outs = [alloc_out(pl, p) for p in range(len(problems))]

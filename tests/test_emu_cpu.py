@@ -32,7 +32,7 @@ def emu():
     assert r.returncode == 0, r.stderr
     L = C.CDLL(SO)
     L.emu_plan.restype = C.c_void_p
-    L.emu_plan.argtypes = [C.POINTER(Y.Problem), C.c_int, C.c_int]
+    L.emu_plan.argtypes = [C.POINTER(Y.Problem), C.c_int, C.c_int, C.c_int]
     L.emu_output.argtypes = [C.c_void_p, C.c_int, C.POINTER(Y.TensorDesc), C.POINTER(C.c_int64)]
     L.emu_contract.argtypes = [C.c_void_p] + [C.POINTER(C.c_void_p), C.POINTER(C.c_int64)] * 3
     L.emu_contract.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_void_p),
@@ -42,7 +42,7 @@ def emu():
     return L
 
 
-def run_emu(L, problems, cb=4):
+def run_emu(L, problems, cb=4, rb=4):
     keep = Y._Keep()
     arr = (Y.Problem * len(problems))()
     for i, (a, b, xa, xb) in enumerate(problems):
@@ -51,7 +51,7 @@ def run_emu(L, problems, cb=4):
         arr[i].ncontract = len(xa)
         arr[i].axes_a = keep.ptr(np.array(xa, np.int32), C.c_int32)
         arr[i].axes_b = keep.ptr(np.array(xb, np.int32), C.c_int32)
-    h = L.emu_plan(arr, len(problems), cb)
+    h = L.emu_plan(arr, len(problems), rb, cb)
     assert h, L.emu_error().decode()
     outs = []
     for p in range(len(problems)):
@@ -88,14 +88,15 @@ def test_emu_config1(emu):
     check(res, oracle.tensordot_dense(p.a, p.b, p.axes_a, p.axes_b))
 
 
+@pytest.mark.parametrize("rb", [1, 2, 4])
 @pytest.mark.parametrize("cb", [1, 2, 3, 4])
-@pytest.mark.parametrize("seed", range(25))
-def test_emu_random(emu, seed, cb):
+@pytest.mark.parametrize("seed", range(12))
+def test_emu_random(emu, seed, cb, rb):
     sym = ["U1", "Z2", "U1xZ2", "Z3", "U1xU1"][seed % 5]
     a, b, xa, xb = random_problem(seed + 2000, sym, rank_a=1 + seed % 5, rank_b=1 + (seed // 5) % 5,
                                   max_sectors=4, max_dim=5 + seed % 7, keep=0.75 if seed % 3 else None,
                                   shuffle=seed % 4 == 0, drop_partner=seed % 6 == 1)
-    (res,) = run_emu(emu, [(a, b, xa, xb)], cb)
+    (res,) = run_emu(emu, [(a, b, xa, xb)], cb, rb)
     check(res, oracle.tensordot_blockpair(a, b, xa, xb))
 
 

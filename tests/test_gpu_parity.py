@@ -60,14 +60,18 @@ def test_paper_example_exact_all_precisions(prec):
 
 
 # ------------------------------------------------------- random structures
+FLAGS = {"auto": 0, "mfma": 1, "rows": 2}
+
+
+@pytest.mark.parametrize("kind", list(FLAGS))
 @pytest.mark.parametrize("seed", range(48))
-def test_random_structures_f64(seed):
+def test_random_structures_f64(seed, kind):
     sym = ["U1", "Z2", "U1xZ2", "Z3", "U1xU1"][seed % 5]
     a, b, xa, xb = random_problem(seed + 2000, sym, rank_a=1 + seed % 5, rank_b=1 + (seed // 5) % 5,
                                   max_sectors=4, max_dim=5 + seed % 7, keep=0.75 if seed % 3 else None,
                                   shuffle=seed % 4 == 0, drop_partner=seed % 6 == 1)
     ref = oracle.tensordot_blockpair(a, b, xa, xb)
-    _, (s,), (v,) = G.run([(a, b, xa, xb)])
+    _, (s,), (v,) = G.run([(a, b, xa, xb)], flags=FLAGS[kind])
     check_f64(s, v, ref)
 
 
@@ -133,7 +137,8 @@ def test_permuted_legs_and_gapped_buffers():
 
 
 # ------------------------------------------------------------ config 2
-def test_config2_chain_f64():
+@pytest.mark.parametrize("kind", list(FLAGS))
+def test_config2_chain_f64(kind):
     t = W.config2()
     steps = [("C", "T1"), (None, "T4"), (None, "A"), (None, "Ac")]
     cur_ref, cur_gpu = None, None
@@ -141,7 +146,7 @@ def test_config2_chain_f64():
         a_ref = t[an] if an else cur_ref
         ref = oracle.tensordot_blockpair(a_ref, t[bn], ax, bx)
         a_in = t[an] if an else cur_gpu
-        _, (s,), (v,) = G.run([(a_in, t[bn], ax, bx)])
+        _, (s,), (v,) = G.run([(a_in, t[bn], ax, bx)], flags=FLAGS[kind])
         check_f64(s, v, ref)
         cur_ref, cur_gpu = ref, G.as_block_tensor(s, v)
 
@@ -169,22 +174,24 @@ def test_reduced_precision_config1(prec, in_f32):
     assert err <= TOL[prec], f"{prec}: {err:.3e}"
 
 
+@pytest.mark.parametrize("kind", ["auto", "mfma"])
 @pytest.mark.parametrize("prec", ["f32", "bf16x3", "bf16x6"])
-def test_reduced_precision_config2_step3(prec):
+def test_reduced_precision_config2_step3(prec, kind):
     t = W.config2()
     a = oracle.tensordot_blockpair(oracle.tensordot_blockpair(t["C"], t["T1"], (1,), (0,)), t["T4"], (0,), (0,))
     ref = oracle.tensordot_blockpair(a, t["A"], (0, 3), (0, 1))
-    _, (s,), (v,) = G.run([(a, t["A"], (0, 3), (0, 1))], precision=prec)
+    _, (s,), (v,) = G.run([(a, t["A"], (0, 3), (0, 1))], precision=prec, flags=FLAGS[kind])
     assert G.structure_equal(s, ref)
     assert oracle.rel_frobenius(v, ref.data) <= TOL[prec]
 
 
 # ------------------------------------------------------------ invariants
-def test_repeat_runs_bitwise_identical():
+@pytest.mark.parametrize("kind", ["mfma", "rows"])
+def test_repeat_runs_bitwise_identical(kind):
     t = W.config2()
     a = oracle.tensordot_blockpair(t["C"], t["T1"], (1,), (0,))
-    _, _, (v1,) = G.run([(a, t["T4"], (0,), (0,))])
-    _, _, (v2,) = G.run([(a, t["T4"], (0,), (0,))], repeat=3)
+    _, _, (v1,) = G.run([(a, t["T4"], (0,), (0,))], flags=FLAGS[kind])
+    _, _, (v2,) = G.run([(a, t["T4"], (0,), (0,))], repeat=3, flags=FLAGS[kind])
     assert np.array_equal(v1, v2)
 
 
@@ -255,3 +262,42 @@ def test_norm_f64(n):
     rf, rm = oracle.norms(t) if n else (0.0, 0.0)
     assert abs(fro - rf) <= 1e-13 * max(rf, 1.0)
     assert mx == rm
+
+
+# ------------------------------------------------------ kernel variants
+@pytest.mark.parametrize("variant", range(1, 8))
+@pytest.mark.parametrize("seed", range(10))
+def test_every_variant_matches_oracle(seed, variant):
+    import paper_2405_12196_amd as Y
+    sym = ["U1", "Z2", "U1xZ2", "U1xU1", "Z3"][seed % 5]
+    a, b, xa, xb = random_problem(seed + 5100, sym, rank_a=2 + seed % 4, rank_b=2 + (seed // 4) % 3,
+                                  max_sectors=4, max_dim=6 + seed % 5, keep=0.8, shuffle=seed % 3 == 0)
+    ref = oracle.tensordot_blockpair(a, b, xa, xb)
+    pl = Y.plan([(a, b, xa, xb)])
+    try:
+        pl.set_variant(variant)
+    except Y.YastnError as e:
+        assert e.status == "ERR_STATE" and variant == 7  # row kernel needs K, N <= 64
+        return
+    A, B = G.upload(a), G.upload(b)
+    c, s = G.alloc_out(pl, 0)
+    pl.contract([A], [B], [c], G.workspace(pl))
+    torch.cuda.synchronize()
+    check_f64(s, c.cpu().numpy()[:s.numel], ref)
+
+
+def test_autotune_config2_step3_picks_a_correct_variant():
+    import paper_2405_12196_amd as Y
+    t = W.config2()
+    a = oracle.tensordot_blockpair(oracle.tensordot_blockpair(t["C"], t["T1"], (1,), (0,)), t["T4"], (0,), (0,))
+    ref = oracle.tensordot_blockpair(a, t["A"], (0, 3), (0, 1))
+    pl = Y.plan([(a, t["A"], (0, 3), (0, 1))])
+    A, B = G.upload(a), G.upload(t["A"])
+    c, s = G.alloc_out(pl, 0)
+    ws = G.workspace(pl)
+    v, times = pl.autotune([A], [B], [c], ws, reps=2)
+    assert 1 <= v < Y.NUM_VARIANTS and times[v] > 0 and times[0] == min(x for x in times[1:] if x > 0)
+    c.fill_(float("nan"))
+    pl.contract([A], [B], [c], ws)
+    torch.cuda.synchronize()
+    check_f64(s, c.cpu().numpy()[:s.numel], ref)
