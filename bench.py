@@ -188,6 +188,8 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=2)
     ap.add_argument("--tile-rows", type=int, default=0, help="16, 32, 64 or 0 (plan's choice)")
     ap.add_argument("--no-tune", action="store_true", help="skip the kernel-variant autotuner")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy three times (scale for HBM byte counters)")
     args = ap.parse_args()
     ws_env = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or ws_env != 1:
@@ -196,6 +198,15 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        x = torch.randn(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": x.numel() * 8, "copies": 3}))
+        return
 
     import paper_2405_12196_amd as Y
     import workloads as W
