@@ -57,6 +57,31 @@ __device__ __forceinline__ T cst(const T *p) {
 template <typename T> __device__ __forceinline__ T cst(const T *p) { return *p; }  // host pass: unused
 #endif
 
+// The plan's table of pointers, one field at a time: copying the whole
+// struct in one aggregate load loses the constant address space of the
+// pointers inside it, and every table read behind them then becomes a
+// per-lane flat load instead of a scalar load.
+__device__ __forceinline__ DevPlan load_plan(const DevPlan *p) {
+  DevPlan d;
+  d.probs = cst(&p->probs);
+  d.sectors = cst(&p->sectors);
+  d.rows = cst(&p->rows);
+  d.ctrs = cst(&p->ctrs);
+  d.cols = cst(&p->cols);
+  d.agrid = cst(&p->agrid);
+  d.aoff = cst(&p->aoff);
+  d.cgrid = cst(&p->cgrid);
+  d.bblocks = cst(&p->bblocks);
+  d.tiles = cst(&p->tiles);
+  d.items = cst(&p->items);
+  d.kofs = cst(&p->kofs);
+  d.kp = cst(&p->kp);
+  d.colmap = cst(&p->colmap);
+  d.ntiles = cst(&p->ntiles);
+  d.nitems = cst(&p->nitems);
+  return d;
+}
+
 // LDS written by one lane and read by another lane of the same wave.
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -66,6 +91,14 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // A value the compiler cannot prove wave-uniform but that is.
 __device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <typename T> __device__ __forceinline__ T *uniptr(T *p) {
+  return reinterpret_cast<T *>(uni64(reinterpret_cast<int64_t>(p)));
+}
 
 // ---------------------------------------------------------------------------
 // charge-hash join
@@ -188,7 +221,7 @@ __global__ void __launch_bounds__(256) k_pack_b(LaunchArgs args) {
     int jb = 0;
     while (jb + 1 < args.njobs && g >= args.jobs[jb + 1].item0) ++jb;
     const JobArg &job = args.jobs[jb];
-    const DevPlan P = cst(job.plan);
+    const DevPlan P = load_plan(job.plan);
     const DevPackItem it = cst(P.items + (g - job.item0 + job.pitem0));
     const DevSector sec = cst(P.sectors + it.sector);
     const DevCtrTuple ct = cst(P.ctrs + (sec.ctr0 + it.s));
@@ -240,7 +273,8 @@ template <typename T, bool BUF> struct Src;
 template <typename T> struct Src<T, true> {
   __amdgpu_buffer_rsrc_t r;
   __device__ void init(const void *p, int64_t n) {
-    r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)(n * (int64_t)sizeof(T)), kBufFlags);
+    r = __builtin_amdgcn_make_buffer_rsrc(uniptr(const_cast<void *>(p)), (short)0, uni((int)(n * (int64_t)sizeof(T))),
+                                          kBufFlags);
   }
   __device__ T operator()(int32_t i) const { return BufIo<T>::ld(r, i * (int32_t)sizeof(T)); }
 };
@@ -253,7 +287,7 @@ template <typename T, bool BUF> struct Dst;
 template <typename T> struct Dst<T, true> {
   __amdgpu_buffer_rsrc_t r;
   __device__ void init(void *p, int64_t n) {
-    r = __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)(n * (int64_t)sizeof(T)), kBufFlags);
+    r = __builtin_amdgcn_make_buffer_rsrc(uniptr(p), (short)0, uni((int)(n * (int64_t)sizeof(T))), kBufFlags);
   }
   __device__ void put(int64_t i, T v) const { BufIo<T>::st(r, (int32_t)i * (int32_t)sizeof(T), v); }
 };
@@ -282,7 +316,7 @@ __device__ __forceinline__ DevPlan tile_setup(const LaunchArgs &args, int t, int
   int jb = 0;
   while (jb + 1 < args.njobs && t >= args.jobs[jb + 1].tile0) ++jb;
   const JobArg &job = args.jobs[jb];
-  const DevPlan P = cst(job.plan);
+  const DevPlan P = load_plan(job.plan);
   x.tile = cst(P.tiles + (t - job.tile0 + job.ptile0));
   x.rt = cst(P.rows + x.tile.rowtuple);
   x.sec = cst(P.sectors + x.tile.sector);
