@@ -63,6 +63,23 @@ class HipEvents:
             self.hip.hipEventDestroy(ctypes.c_void_p(e))
 
 
+# ------------------------------------------------------------ HIP graphs
+def capture(torch, fn):
+    """Capture fn(stream_handle) into a torch CUDAGraph (HIP graph) on a side
+    stream; returns (graph, None) or (None, error text) if capture fails."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    try:
+        with torch.cuda.graph(g, stream=s):
+            fn(int(s.cuda_stream))
+    except Exception as e:  # noqa: BLE001 - reported in the JSON line
+        torch.cuda.synchronize()
+        return None, f"{type(e).__name__}: {e}"
+    torch.cuda.current_stream().wait_stream(s)
+    return g, None
+
+
 # ------------------------------------------------- plain per-sector FP64 form
 def _key(t, b, legs):
     return tuple(int(v) for x in legs for v in t.charges[b, x, :])
@@ -186,7 +203,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=2)
-    ap.add_argument("--tile-rows", type=int, default=0, help="16, 32, 64 or 0 (plan's choice)")
+    ap.add_argument("--tile-rows", type=int, default=0, help="rows per wave tile: 64, 128, 256, 512 or 0 (plan's choice)")
     ap.add_argument("--no-tune", action="store_true", help="skip the kernel-variant autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (scale for HBM byte counters)")
@@ -255,44 +272,77 @@ def main():
 
     ev = HipEvents()
 
-    def step(evs=None):
-        for i, (pl, (a, b, c, w)) in enumerate(zip(plans, ops)):
-            if evs is None:
-                pl.contract([a], [b], [c], w, stream=sp)
-            else:
-                pl.contract_timed([a], [b], [c], w, [None, evs[2 * i], evs[2 * i + 1]], stream=sp)
-        Y.norm(outs[-1], n_last, nout, nws, stream=sp)
+    def step(st):
+        for pl, (a, b, c, w) in zip(plans, ops):
+            pl.contract([a], [b], [c], w, stream=st)
+        Y.norm(outs[-1], n_last, nout, nws, stream=st)
 
     for _ in range(args.warmup):
-        step()
+        step(sp)
     torch.cuda.synchronize()
+    ref_last = outs[-1][:n_last].clone()
+
+    # ---- the step captured once into a HIP graph (no host work per replay);
+    # the graph's result must be bitwise the eager one
+    graph, graph_err = capture(torch, lambda st: step(st))
+    if graph is not None:
+        for _ in range(max(1, args.warmup // 2)):
+            graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(outs[-1][:n_last], ref_last), "graph replay differs from the eager step"
+
+    # ---- timed region: K steps, either as graph replays or as eager launches
+    # (one host call per kernel); both are timed and the faster is reported
     K = args.steps
-    step_ev = [(ev.new(), ev.new()) for _ in range(K)]
-    kern_ev = [[ev.new() for _ in range(8)] for _ in range(K)]
+
+    def timed(run):
+        evs = [(ev.new(), ev.new()) for _ in range(K)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(K):
+            ev.record(evs[k][0], sp)
+            run()
+            ev.record(evs[k][1], sp)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall * 1e3 / K, np.array([ev.ms(a, b) for a, b in evs])
+
+    modes = {"eager": timed(lambda: step(sp))}
+    if graph is not None:
+        modes["graph"] = timed(graph.replay)
+    mode = min(modes, key=lambda m: modes[m][0])
+    ms_per_step, lat = modes[mode]
+    assert torch.equal(outs[-1][:n_last], ref_last), "timed steps changed the result"
+
+    # ---- per-contraction kernel time: R launches of one contraction in one
+    # graph, HIP events around the replays on the launch stream
+    R, REP = 20, 5
+    per_kernel, gemm_avg = [], []
+    for i, (pl, (a, b, c, w)) in enumerate(zip(plans, ops)):
+        def rep(st, pl=pl, a=a, b=b, c=c, w=w):
+            for _ in range(R):
+                pl.contract([a], [b], [c], w, stream=st)
+        g, _ = capture(torch, rep)
+        e0, e1 = ev.new(), ev.new()
+        torch.cuda.synchronize()
+        ev.record(e0, sp)
+        for _ in range(REP):
+            g.replay() if g is not None else rep(sp)
+        ev.record(e1, sp)
+        torch.cuda.synchronize()
+        ms = ev.ms(e0, e1) / (R * REP)
+        gemm_avg.append(ms)
+        per_kernel.append({"step": i + 1, "us_per_launch": round(ms * 1e3, 2), "alg_bytes": int(alg_bytes[i]),
+                           "achieved_GBs": round(alg_bytes[i] / (ms * 1e-3) / 1e9, 1),
+                           "useful_TFs": round(stats[i]["useful_flops"] / (ms * 1e-3) / 1e12, 2),
+                           "tiles": int(stats[i]["tiles"]), "variant": pl.variant_id})
+        del g
+    step(sp)  # restore the chain's outputs
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(K):
-        ev.record(step_ev[k][0], sp)
-        step(kern_ev[k])
-        ev.record(step_ev[k][1], sp)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = wall * 1e3 / K
-    lat = np.array([ev.ms(a, b) for a, b in step_ev])
-    gemm_ms = np.array([[ev.ms(kern_ev[k][2 * i], kern_ev[k][2 * i + 1]) for i in range(4)] for k in range(K)])
-    gemm_avg = gemm_ms.mean(axis=0)
-    per_kernel = []
-    for i, pl in enumerate(plans):
-        gbs = alg_bytes[i] / (gemm_avg[i] * 1e-3) / 1e9
-        per_kernel.append({"step": i + 1, "gemm_us": round(gemm_avg[i] * 1e3, 2), "alg_bytes": int(alg_bytes[i]),
-                           "achieved_GBs": round(gbs, 1), "useful_TFs": round(stats[i]["useful_flops"] / (gemm_avg[i] * 1e-3) / 1e12, 2),
-                           "tiles": int(stats[i]["tiles"])})
+    gemm_avg = np.array(gemm_avg)
     dom = int(np.argmax(gemm_avg))
     ach = alg_bytes[dom] / (gemm_avg[dom] * 1e-3) / 1e9
     value = useful / (ms_per_step * 1e-3) / 1e12
-
-    # ---- check the step's result once (norm of the last output vs its values)
-    torch.cuda.synchronize()
 
     # ---- plain per-sector FP64 form on the same GPU
     plain = None
@@ -312,12 +362,12 @@ def main():
             b_ext[i][:psteps[i].nB].copy_(inp[bn][:psteps[i].nB])
         del keys
 
-        def pstep():
+        def pstep(st=None):
             for i, p in enumerate(psteps):
                 if i > 0:
                     a_ext[i][:p.nA].copy_(c_ext[i - 1][:p.nA])
                 p.run(a_ext[i], b_ext[i], c_ext[i])
-            Y.norm(c_ext[-1], psteps[-1].nC, nout, nws, stream=sp)
+            Y.norm(c_ext[-1], psteps[-1].nC, nout, nws, stream=st)
 
         for _ in range(3):
             pstep()
@@ -329,9 +379,25 @@ def main():
         for _ in range(KP):
             pstep()
         torch.cuda.synchronize()
-        pms = (time.perf_counter() - tq) * 1e3 / KP
+        pms_eager = (time.perf_counter() - tq) * 1e3 / KP
+        # the same form captured in a graph (launch overhead removed): the
+        # faster of the two is the denominator
+        pg, pg_err = capture(torch, pstep)
+        pms_graph = None
+        if pg is not None:
+            pg.replay()
+            torch.cuda.synchronize()
+            tq = time.perf_counter()
+            for _ in range(KP):
+                pg.replay()
+            torch.cuda.synchronize()
+            pms_graph = (time.perf_counter() - tq) * 1e3 / KP
+            del pg
+        pms = min(pms_eager, pms_graph) if pms_graph is not None else pms_eager
         plain = {"value": round(useful / (pms * 1e-3) / 1e12, 4), "unit": "TFLOP/s", "ms_per_step": round(pms, 4),
-                 "steps": KP, "max_rel_diff_vs_library": maxdiff,
+                 "ms_per_step_eager": round(pms_eager, 4),
+                 "ms_per_step_graph": round(pms_graph, 4) if pms_graph is not None else None,
+                 "graph_error": pg_err, "steps": KP, "max_rel_diff_vs_library": maxdiff,
                  "form": "gather into fused sector matrices, one torch.matmul (FP64) per sector, scatter"}
 
     # ---- CPU oracle baseline (block-pair form), bounded sample
@@ -363,11 +429,16 @@ def main():
                    "parallelism": "single GPU"},
         "p50_ms": round(float(np.percentile(lat, 50)), 5), "p99_ms": round(float(np.percentile(lat, 99)), 5),
         "plan_ms": round(plan_ms, 2),
+        "timing": {"graph": "step captured in one HIP graph, one replay per step",
+                   "eager": "one host launch per kernel"}[mode],
+        "ms_per_step_by_mode": {m: round(v[0], 5) for m, v in modes.items()}, "graph_error": graph_err,
         "vs_plain_per_sector_f64": round(value / plain["value"], 3) if plain else None,
         "plain_per_sector_f64": plain,
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": f"grouped gather GEMM of contraction {dom + 1}"},
+                     "kernel": f"grouped gather GEMM of contraction {dom + 1}",
+                     "launch_us": round(float(gemm_avg[dom]) * 1e3, 2),
+                     "timing": f"HIP events on the launch stream around {REP} replays of a graph of {R} launches"},
         "kernels": per_kernel,
         "autotune": tuned,
         "cpu_baseline": cpu,

@@ -93,15 +93,16 @@ typedef struct {
   yastn_precision precision; /* arithmetic of the sector GEMMs                                  */
   yastn_dtype in_dtype;      /* element type of A and B buffers                                 */
   yastn_dtype out_dtype;     /* element type of C buffers                                       */
-  int32_t tile_rows;         /* MFMA rows per wave chunk: 16, 32 or 64; 0 = plan's choice       */
+  int32_t tile_rows;         /* rows of C_X per wave tile: 16, 32, 64, 128, 256 or 512;
+                                0 = plan's choice (tall tiles while the launch keeps enough tiles) */
   int32_t flags;             /* 0, or one of the YASTN_FLAG_* below                             */
 } yastn_options;
 
-/* Kernel family of the sector GEMMs.  By default the plan picks: sectors with
- * K, N <= 64 (tall-skinny, bound by HBM) run one output row per lane on the
- * vector FMA units; other shapes run on MFMA tiles.  These flags force one
- * family (ROWS falls back to MFMA when a sector has K or N above 64, or for
- * the BF16 precisions, which always use MFMA). */
+/* Kernel family of the sector GEMMs when no variant is set.  By default the
+ * plan runs MFMA tiles with register-resident B (every sector K <= 64) or MFMA
+ * tiles over a packed B (otherwise).  FLAG_MFMA forces the packed-B MFMA
+ * tiles; FLAG_ROWS asks for one output row per lane on the vector FMA units
+ * (used when every sector has K, N <= 64; BF16 precisions always use MFMA). */
 #define YASTN_FLAG_MFMA 1
 #define YASTN_FLAG_ROWS 2
 
@@ -164,6 +165,10 @@ yastn_status yastn_contract_timed(yastn_plan_t plan, const void *const *a, const
                                   void *const *events);
 
 /* Kernel variants.  A plan starts with variant 0 (the library's heuristic).
+ * Variants 1-6: MFMA tiles reading a packed copy of B (six tile shapes);
+ * 7: one output row per lane on the vector FMA units (sectors with K, N <= 64);
+ * 8-13: MFMA tiles with the tile's B values held in registers and read straight
+ * from B's blocks (sectors with K <= 64; six chunk / occupancy shapes).
  * yastn_plan_autotune runs every variant that fits the plan `reps` times on
  * the caller's buffers (same arguments as yastn_contract; C is overwritten),
  * times them with HIP events, keeps the fastest in the plan and returns its
@@ -173,8 +178,8 @@ yastn_status yastn_contract_timed(yastn_plan_t plan, const void *const *a, const
  * different variants agree within rounding, and one plan always uses one
  * variant, so repeated contractions stay bitwise reproducible.
  * yastn_plan_set_variant restores a previously tuned choice (e.g. from a
- * cache keyed by structure). */
-#define YASTN_NUM_VARIANTS 8
+ * cache keyed by structure); YASTN_ERR_STATE if the variant does not fit. */
+#define YASTN_NUM_VARIANTS 14
 yastn_status yastn_plan_autotune(yastn_plan_t plan, const void *const *a, const void *const *b,
                                  void *const *c, void *workspace, void *hip_stream, int32_t reps,
                                  int32_t *chosen, float *times_ms);

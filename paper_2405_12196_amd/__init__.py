@@ -35,7 +35,7 @@ EXPORTS = ["yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_pla
            "yastn_contract", "yastn_contract_timed", "yastn_contract_jobs", "yastn_norm_workspace", "yastn_norm",
            "yastn_free", "yastn_last_error", "yastn_status_string", "yastn_abi_version",
            "yastn_plan_autotune", "yastn_plan_set_variant"]
-NUM_VARIANTS = 8
+NUM_VARIANTS = 14
 
 
 class YastnError(RuntimeError):
@@ -225,6 +225,7 @@ class Plan:
                             C.byref(h)))
         self._h = h
         self.nprob = len(problems)
+        self.variant_id = 0
         ws = C.c_size_t()
         _check(L.yastn_plan_workspace(h, C.byref(ws)))
         self.workspace_bytes = int(ws.value)
@@ -287,10 +288,12 @@ class Plan:
         times = (C.c_float * NUM_VARIANTS)()
         _check(lib().yastn_plan_autotune(self._h, pa, pb, pc, C.c_void_p(_ptr(workspace)),
                                          C.c_void_p(_stream(stream)), int(reps), C.byref(ch), times))
+        self.variant_id = int(ch.value)
         return int(ch.value), [float(t) for t in times]
 
     def set_variant(self, v: int):
         _check(lib().yastn_plan_set_variant(self._h, int(v)))
+        self.variant_id = int(v)
 
     def free(self):
         if getattr(self, "_h", None) is not None and self._h.value:

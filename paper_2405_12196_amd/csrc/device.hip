@@ -1,23 +1,15 @@
-// HIP kernels (gfx950 / CDNA4) and the C ABI of the block-sparse tensordot.
+// Host runtime and C ABI of the block-sparse tensordot, plus the kernels that
+// are not templates (gfx950 / CDNA4):
 //
 //  k_join_*   charge-hash join: B blocks are inserted into an open-addressing
 //             table keyed by their contracted charges; every A block probes it
 //             and emits its matches (count, scan, emit).  Two blocks meet iff
 //             their charges agree on every contracted leg pair (paper Sec.
 //             II.B: contracted legs carry the same charges on both partners).
-//  k_pack_b   fuses B's legs into the per-sector matrices B_X (K_X x N_X,
-//             row-major; absent sub-blocks zero) -- the "fuse" step of the
-//             fuse -> multiply -> unfuse contraction of Sec. II.B, applied to
-//             the small operand only.
-//  k_gemm     grouped GEMM C_X = A_X B_X over every sector of every problem
-//             in one launch.  One wave owns a tile of up to 64 rows of one A
-//             free tuple x up to 64 columns of B_X.  A is never materialised:
-//             each element is gathered from its block through the factorised
-//             offsets of plan.hpp (the leg permute is fused into the load).
-//             The epilogue writes each element straight into its output block
-//             (the "unfuse" step), exactly once: C need not be zeroed and no
-//             atomics are used, so results are deterministic.
 //  k_norm_*   FP64 Frobenius norm and max |x|, two fixed-order passes.
+//
+// The pack and grouped-GEMM kernels are templates in kernels.hpp, chosen per
+// launch by the dispatch below (one plan = one kernel variant).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,7 +20,7 @@
 #include <new>
 #include <vector>
 
-#include "index.hpp"
+#include "dispatch.hpp"
 #include "planner.hpp"
 
 namespace yastn {
@@ -40,65 +32,6 @@ const char *last_error_cstr();
     hipError_t e_ = (call);                                                               \
     if (e_ != hipSuccess) return set_error(YASTN_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-
-// Wave-uniform reads of plan tables go through the constant address space:
-// the tables are read-only while kernels run, so the compiler may use scalar
-// loads (reads only) and keep the values in SGPRs.
-#if defined(__HIP_DEVICE_COMPILE__)
-template <typename T>
-__device__ __forceinline__ T cst(const T *p) {
-  return *(const __attribute__((address_space(4))) T *)(p);
-}
-#else
-template <typename T> __device__ __forceinline__ T cst(const T *p) { return *p; }  // host pass: unused
-#endif
-
-// The plan's table of pointers, one field at a time: copying the whole
-// struct in one aggregate load loses the constant address space of the
-// pointers inside it, and every table read behind them then becomes a
-// per-lane flat load instead of a scalar load.
-__device__ __forceinline__ DevPlan load_plan(const DevPlan *p) {
-  DevPlan d;
-  d.probs = cst(&p->probs);
-  d.sectors = cst(&p->sectors);
-  d.rows = cst(&p->rows);
-  d.ctrs = cst(&p->ctrs);
-  d.cols = cst(&p->cols);
-  d.agrid = cst(&p->agrid);
-  d.aoff = cst(&p->aoff);
-  d.cgrid = cst(&p->cgrid);
-  d.bblocks = cst(&p->bblocks);
-  d.tiles = cst(&p->tiles);
-  d.items = cst(&p->items);
-  d.kofs = cst(&p->kofs);
-  d.kp = cst(&p->kp);
-  d.colmap = cst(&p->colmap);
-  d.ntiles = cst(&p->ntiles);
-  d.nitems = cst(&p->nitems);
-  return d;
-}
-
-// LDS written by one lane and read by another lane of the same wave.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// A value the compiler cannot prove wave-uniform but that is.
-__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ int64_t uni64(int64_t v) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-template <typename T> __device__ __forceinline__ T *uniptr(T *p) {
-  return reinterpret_cast<T *>(uni64(reinterpret_cast<int64_t>(p)));
-}
 
 // ---------------------------------------------------------------------------
 // charge-hash join
@@ -200,478 +133,35 @@ __global__ void k_join_emit(const int32_t *keya, int64_t na, const int32_t *keyb
 }
 
 // ---------------------------------------------------------------------------
-// numeric helpers
-// ---------------------------------------------------------------------------
-// round-to-nearest-even float -> bf16 bits (finite inputs)
-__device__ __forceinline__ uint16_t bf16_rne(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
-
-// ---------------------------------------------------------------------------
-// B pack: per-sector matrices B_X in the workspace
-// ---------------------------------------------------------------------------
-// One workgroup per item of up to 256 elements of one (s, j) sub-block;
-// consecutive threads write consecutive elements of a B_X row.
-template <typename In, typename Cmp>
-__global__ void __launch_bounds__(256) k_pack_b(LaunchArgs args) {
-  for (int g = blockIdx.x; g < args.nitems; g += gridDim.x) {
-    int jb = 0;
-    while (jb + 1 < args.njobs && g >= args.jobs[jb + 1].item0) ++jb;
-    const JobArg &job = args.jobs[jb];
-    const DevPlan P = load_plan(job.plan);
-    const DevPackItem it = cst(P.items + (g - job.item0 + job.pitem0));
-    const DevSector sec = cst(P.sectors + it.sector);
-    const DevCtrTuple ct = cst(P.ctrs + (sec.ctr0 + it.s));
-    const DevColTuple cl = cst(P.cols + (sec.col0 + it.j));
-    const int32_t e = it.e0 + (int32_t)threadIdx.x;
-    if (e >= ct.k * cl.n) continue;
-    const int32_t kd = e / cl.n, cb = e - kd * cl.n;
-    Cmp *dst = reinterpret_cast<Cmp *>(job.ws) + sec.bpack + (int64_t)(ct.ko + kd) * sec.N + cl.no + cb;
-    if (it.bblk < 0) {
-      *dst = Cmp(0);
-    } else {
-      const In *src = reinterpret_cast<const In *>(args.p[job.prob0 + sec.prob - job.plo].b);
-      const DevBBlock bb = cst(P.bblocks + it.bblk);
-      const DevProb pr = cst(P.probs + sec.prob);
-      *dst = Cmp(src[b_offset(bb, ct, cl, pr, kd, cb)]);
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// operand access: buffer resources or 64-bit pointers
-// ---------------------------------------------------------------------------
-// BUF = true: A and C are reached through buffer resources (scalar base,
-// 32-bit byte offsets; the hardware returns 0 for reads past num_records and
-// drops such writes).  Used when both buffers are below 2 GiB.  BUF = false:
-// plain 64-bit addresses, any size.
-typedef unsigned int u2v __attribute__((ext_vector_type(2)));
-constexpr int kBufFlags = 0x00020000;  // raw buffer, gfx9-family descriptor word 3
-
-template <typename T> struct BufIo;
-template <> struct BufIo<double> {
-  __device__ static double ld(__amdgpu_buffer_rsrc_t r, int32_t byte) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte, 0, 0));
-  }
-  __device__ static void st(__amdgpu_buffer_rsrc_t r, int32_t byte, double v) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, v), r, byte, 0, 0);
-  }
-};
-template <> struct BufIo<float> {
-  __device__ static float ld(__amdgpu_buffer_rsrc_t r, int32_t byte) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte, 0, 0));
-  }
-  __device__ static void st(__amdgpu_buffer_rsrc_t r, int32_t byte, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, byte, 0, 0);
-  }
-};
-
-template <typename T, bool BUF> struct Src;
-template <typename T> struct Src<T, true> {
-  __amdgpu_buffer_rsrc_t r;
-  __device__ void init(const void *p, int64_t n) {
-    r = __builtin_amdgcn_make_buffer_rsrc(uniptr(const_cast<void *>(p)), (short)0, uni((int)(n * (int64_t)sizeof(T))),
-                                          kBufFlags);
-  }
-  __device__ T operator()(int32_t i) const { return BufIo<T>::ld(r, i * (int32_t)sizeof(T)); }
-};
-template <typename T> struct Src<T, false> {
-  const T *__restrict__ p;
-  __device__ void init(const void *q, int64_t) { p = reinterpret_cast<const T *>(q); }
-  __device__ T operator()(int64_t i) const { return p[i]; }
-};
-template <typename T, bool BUF> struct Dst;
-template <typename T> struct Dst<T, true> {
-  __amdgpu_buffer_rsrc_t r;
-  __device__ void init(void *p, int64_t n) {
-    r = __builtin_amdgcn_make_buffer_rsrc(uniptr(p), (short)0, uni((int)(n * (int64_t)sizeof(T))), kBufFlags);
-  }
-  __device__ void put(int64_t i, T v) const { BufIo<T>::st(r, (int32_t)i * (int32_t)sizeof(T), v); }
-};
-template <typename T> struct Dst<T, false> {
-  T *__restrict__ p;
-  __device__ void init(void *q, int64_t) { p = reinterpret_cast<T *>(q); }
-  __device__ void put(int64_t i, T v) const { p[i] = v; }
-};
-
-// Tile context shared by every precision: the tile's row tuple and sector,
-// the problem's operands, and the lane's output columns.
-template <typename In, typename Out, bool BUF, int CB> struct TileCtx {
-  DevTile tile;
-  DevRowTuple rt;
-  DevSector sec;
-  Src<In, BUF> A;
-  Dst<Out, BUF> C;
-  const char *ws;
-  int64_t cbase[CB];        // output block offset of the lane's columns (-1: none)
-  int32_t cnj[CB], ccl[CB];
-  int cbn;
-};
-
-template <typename In, typename Out, bool BUF, int CB>
-__device__ __forceinline__ DevPlan tile_setup(const LaunchArgs &args, int t, int lane, TileCtx<In, Out, BUF, CB> &x) {
-  int jb = 0;
-  while (jb + 1 < args.njobs && t >= args.jobs[jb + 1].tile0) ++jb;
-  const JobArg &job = args.jobs[jb];
-  const DevPlan P = load_plan(job.plan);
-  x.tile = cst(P.tiles + (t - job.tile0 + job.ptile0));
-  x.rt = cst(P.rows + x.tile.rowtuple);
-  x.sec = cst(P.sectors + x.tile.sector);
-  const ProbPtrs pp = args.p[job.prob0 + x.sec.prob - job.plo];
-  const DevProb pr = cst(P.probs + x.sec.prob);
-  x.A.init(pp.a, pr.a_span);
-  x.C.init(pp.c, pr.c_numel);
-  x.ws = job.ws;
-  x.cbn = (x.tile.ncols + 15) >> 4;
-#pragma unroll
-  for (int cb = 0; cb < CB; ++cb) {
-    const int lc = 16 * cb + (lane & 15);
-    x.cbase[cb] = -1;
-    x.cnj[cb] = 0;
-    x.ccl[cb] = 0;
-    if (lc < x.tile.ncols) {
-      const DevColMap cm = P.colmap[x.sec.cm0 + x.tile.n0 + lc];
-      x.cbase[cb] = P.cgrid[x.rt.cgrid + cm.j];
-      x.cnj[cb] = cm.nj;
-      x.ccl[cb] = cm.cl;
-    }
-  }
-  return P;
-}
-
-// ---------------------------------------------------------------------------
-// grouped gather GEMM (FP64 / FP32 MFMA, K = 4 per instruction)
-// ---------------------------------------------------------------------------
-template <typename Cmp> struct Mfma4;
-template <> struct Mfma4<double> {
-  typedef d4 acc_t;
-  __device__ static acc_t run(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-  // accumulator element v of lane l holds row (l>>4) + 4v, column l&15
-  __device__ static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
-};
-template <> struct Mfma4<float> {
-  typedef f4 acc_t;
-  __device__ static acc_t run(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-  // accumulator element v of lane l holds row 4(l>>4) + v, column l&15
-  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
-};
-
-// One wave tile: rows are processed in chunks of 16*RB; the tile's metadata
-// and output columns are set up once.  Within a chunk, KB k-steps of loads
-// are issued before the MFMAs that consume them.
-template <typename In, typename Cmp, typename Out, bool BUF, int RB, int CB, int KB>
-__global__ void __launch_bounds__(256) k_gemm4(LaunchArgs args) {
-  typedef typename std::conditional<BUF, int32_t, int64_t>::type Off;
-  typedef Mfma4<Cmp> M;
-  typedef typename M::acc_t acc_t;
-  const int lane = threadIdx.x & 63;
-  const int gw = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  const int W = gridDim.x * 4;
-  for (int t = gw; t < args.ntiles; t += W) {
-    TileCtx<In, Out, BUF, CB> x;
-    const DevPlan P = tile_setup<In, Out, BUF, CB>(args, t, lane, x);
-    const Cmp *__restrict__ Bp = reinterpret_cast<const Cmp *>(x.ws) + x.sec.bpack;
-    const int64_t *__restrict__ kofs = P.kofs + x.rt.kofs;
-    const DevKP *__restrict__ kp = P.kp + x.sec.kp0;
-    const int K = x.sec.K, N = x.sec.N;
-    for (int mc = 0; mc < x.tile.nrows; mc += 16 * RB) {
-      const int rows = min(16 * RB, x.tile.nrows - mc);
-      const int rbn = (rows + 15) >> 4;
-      int32_t rg[RB][kMaxAct];
-      bool rv[RB];
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const int lr = 16 * rb + (lane & 15);
-        rv[rb] = lr < rows;
-        a_rowparts(x.rt, x.sec.nact, x.tile.m0 + mc + lr, rg[rb]);
-      }
-      acc_t acc[RB][CB];
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = acc_t{0, 0, 0, 0};
-      // k metadata of the next batch is fetched while this batch's A loads fly
-      int64_t kon[KB];
-      DevKP pn[KB];
-#pragma unroll
-      for (int q = 0; q < KB; ++q) {
-        const int k = 4 * q + (lane >> 4);
-        kon[q] = k < K ? kofs[k] : -1;
-        pn[q] = k < K ? kp[k] : DevKP{};
-      }
-      for (int kk0 = 0; kk0 < K; kk0 += 4 * KB) {
-        Cmp av[KB][RB], bv[KB][CB];
-        int64_t ko[KB];
-        DevKP pc[KB];
-#pragma unroll
-        for (int q = 0; q < KB; ++q) {
-          ko[q] = kon[q];
-          pc[q] = pn[q];
-        }
-#pragma unroll
-        for (int q = 0; q < KB; ++q) {
-          const int k = kk0 + 4 * q + (lane >> 4);
-#pragma unroll
-          for (int rb = 0; rb < RB; ++rb)
-            av[q][rb] = (ko[q] >= 0 && rv[rb]) ? Cmp(x.A(a_offset_t<Off>(ko[q], pc[q].p, rg[rb]))) : Cmp(0);
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb) {
-            const int c = x.tile.n0 + 16 * cb + (lane & 15);
-            bv[q][cb] = (k < K && c < N) ? Bp[(int64_t)k * N + c] : Cmp(0);
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < KB; ++q) {
-          const int k = kk0 + 4 * KB + 4 * q + (lane >> 4);
-          kon[q] = k < K ? kofs[k] : -1;
-          pn[q] = k < K ? kp[k] : DevKP{};
-        }
-#pragma unroll
-        for (int q = 0; q < KB; ++q)
-#pragma unroll
-          for (int rb = 0; rb < RB; ++rb)
-            if (rb < rbn)
-#pragma unroll
-              for (int cb = 0; cb < CB; ++cb)
-                if (cb < x.cbn) acc[rb][cb] = M::run(av[q][rb], bv[q][cb], acc[rb][cb]);
-      }
-      // element (row, col) of C_X -> output block (i, j_col), row-major m_i x n_j
-#pragma unroll
-      for (int cb = 0; cb < CB; ++cb) {
-        if (cb >= x.cbn || x.cbase[cb] < 0) continue;
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          if (rb >= rbn) continue;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int lr = 16 * rb + M::row(lane, v);
-            if (lr < rows)
-              x.C.put(x.cbase[cb] + (int64_t)(x.tile.m0 + mc + lr) * x.cnj[cb] + x.ccl[cb], Out(acc[rb][cb][v]));
-          }
-        }
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// tall-skinny sectors (K, N <= 64): one row of C_X per lane, VALU FMA
-// ---------------------------------------------------------------------------
-// HBM-bound shapes (tens of thousands of rows, K and N of a few tens): each
-// lane gathers its row of A_X (all K values at once, coalesced across the
-// wave's consecutive rows) and accumulates 16 columns at a time with B_X
-// values that are uniform across the wave, so the k offsets, P factors and
-// B_X come from scalar loads.  No padding of K or N.
-template <typename In, typename Cmp, typename Out, bool BUF, int KMAX>
-__global__ void __launch_bounds__(256) k_rows(LaunchArgs args) {
-  typedef typename std::conditional<BUF, int32_t, int64_t>::type Off;
-  __shared__ Cmp bs_all[4][KMAX][16];  // per wave: B_X rows 0..K-1, the 16 columns of one pass
-  const int lane = threadIdx.x & 63;
-  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  Cmp (*bs)[16] = bs_all[wid];
-  const int gw = blockIdx.x * 4 + wid;  // wave-uniform
-  const int W = gridDim.x * 4;
-  for (int t = gw; t < args.ntiles; t += W) {
-    TileCtx<In, Out, BUF, 1> x;
-    const DevPlan P = tile_setup<In, Out, BUF, 1>(args, t, lane, x);
-    const Cmp *__restrict__ Bp = reinterpret_cast<const Cmp *>(x.ws) + x.sec.bpack;
-    const int64_t *kofs = P.kofs + x.rt.kofs;
-    const DevKP *kp = P.kp + x.sec.kp0;
-    const DevColMap *cmap = P.colmap + x.sec.cm0 + x.tile.n0;
-    const int64_t *cgrid = P.cgrid + x.rt.cgrid;
-    const int K = uni(x.sec.K), N = uni(x.sec.N), ncols = uni(x.tile.ncols), nrows = uni(x.tile.nrows);
-    for (int mc = 0; mc < nrows; mc += 64) {
-      const int lr = mc + lane;
-      const bool valid = lr < nrows;
-      const int32_t ra = x.tile.m0 + lr;
-      int32_t rg[kMaxAct];
-      a_rowparts(x.rt, x.sec.nact, ra, rg);
-      Cmp a[KMAX];
-#pragma unroll
-      for (int k = 0; k < KMAX; ++k) {
-        a[k] = Cmp(0);
-        if (k < K) {
-          const int64_t ko = cst(kofs + k);
-          const DevKP p = cst(kp + k);
-          if (valid && ko >= 0) a[k] = Cmp(x.A(a_offset_t<Off>(ko, p.p, rg)));
-        }
-      }
-      for (int cc = 0; cc < ncols; cc += 16) {
-        const int nc = min(16, ncols - cc);
-        // stage B_X[k][n0 + cc + c] (zero beyond K and the tile's columns)
-        for (int e = lane; e < KMAX * 16; e += 64) {
-          const int k = e >> 4, c = e & 15;
-          bs[k][c] = (k < K && c < nc) ? Bp[(int64_t)k * N + x.tile.n0 + cc + c] : Cmp(0);
-        }
-        wave_lds_sync();
-        Cmp acc[16];
-#pragma unroll
-        for (int c = 0; c < 16; ++c) acc[c] = Cmp(0);
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-          if (k < K) {
-#pragma unroll
-            for (int c = 0; c < 16; ++c) acc[c] = fma(a[k], bs[k][c], acc[c]);
-          }
-        }
-        wave_lds_sync();
-#pragma unroll
-        for (int c = 0; c < 16; ++c) {
-          if (c < nc) {
-            const DevColMap cm = cst(cmap + cc + c);
-            const int64_t cbase = cst(cgrid + cm.j);
-            if (valid && cbase >= 0) x.C.put(cbase + (int64_t)ra * cm.nj + cm.cl, Out(acc[c]));
-          }
-        }
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// grouped gather GEMM, split-BF16 products on bf16 MFMA (K = 32 per instruction)
-// ---------------------------------------------------------------------------
-// x = hi + mid + lo with hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi - mid)
-// (round to nearest even).  NT = 3: hi*hi + hi*mid + mid*hi;  NT = 6 adds
-// mid*mid + hi*lo + lo*hi.  FP32 accumulation.
-template <int NT>
-__device__ __forceinline__ void split3(float x, __bf16 &h, __bf16 &m, __bf16 &l) {
-  const uint16_t hb = bf16_rne(x);
-  const float r = x - bf16_to_f(hb);
-  const uint16_t mb = bf16_rne(r);
-  uint16_t lb = 0;
-  if (NT > 3) lb = bf16_rne(r - bf16_to_f(mb));
-  h = __builtin_bit_cast(__bf16, hb);
-  m = __builtin_bit_cast(__bf16, mb);
-  l = __builtin_bit_cast(__bf16, lb);
-}
-
-template <typename In, typename Out, bool BUF, int RB, int CB, int NT>
-__global__ void __launch_bounds__(256) k_gemm_bf16(LaunchArgs args) {
-  typedef typename std::conditional<BUF, int32_t, int64_t>::type Off;
-  const int lane = threadIdx.x & 63;
-  const int gw = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  const int W = gridDim.x * 4;
-  for (int t = gw; t < args.ntiles; t += W) {
-    TileCtx<In, Out, BUF, CB> x;
-    const DevPlan P = tile_setup<In, Out, BUF, CB>(args, t, lane, x);
-    const float *__restrict__ Bp = reinterpret_cast<const float *>(x.ws) + x.sec.bpack;
-    const int64_t *__restrict__ kofs = P.kofs + x.rt.kofs;
-    const DevKP *__restrict__ kp = P.kp + x.sec.kp0;
-    const int K = x.sec.K, N = x.sec.N;
-    for (int mc = 0; mc < x.tile.nrows; mc += 16 * RB) {
-      const int rows = min(16 * RB, x.tile.nrows - mc);
-      const int rbn = (rows + 15) >> 4;
-      int32_t rg[RB][kMaxAct];
-      bool rv[RB];
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const int lr = 16 * rb + (lane & 15);
-        rv[rb] = lr < rows;
-        a_rowparts(x.rt, x.sec.nact, x.tile.m0 + mc + lr, rg[rb]);
-      }
-      f4 acc[RB][CB];
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = f4{0, 0, 0, 0};
-      for (int kk = 0; kk < K; kk += 32) {
-        bf8 ah[RB], am[RB], al[RB], bh[CB], bm[CB], bl[CB];
-        float av[8][RB], bv[8][CB];
-#pragma unroll
-        for (int e8 = 0; e8 < 8; ++e8) {  // this lane's 8 consecutive k
-          const int k = kk + 8 * (lane >> 4) + e8;
-          int64_t ko = -1;
-          DevKP p{};
-          if (k < K) {
-            ko = kofs[k];
-            p = kp[k];
-          }
-#pragma unroll
-          for (int rb = 0; rb < RB; ++rb)
-            av[e8][rb] = (ko >= 0 && rv[rb]) ? float(x.A(a_offset_t<Off>(ko, p.p, rg[rb]))) : 0.f;
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb) {
-            const int c = x.tile.n0 + 16 * cb + (lane & 15);
-            bv[e8][cb] = (k < K && c < N) ? Bp[(int64_t)k * N + c] : 0.f;
-          }
-        }
-#pragma unroll
-        for (int e8 = 0; e8 < 8; ++e8) {
-#pragma unroll
-          for (int rb = 0; rb < RB; ++rb) {
-            __bf16 h, m, l;
-            split3<NT>(av[e8][rb], h, m, l);
-            ah[rb][e8] = h;
-            am[rb][e8] = m;
-            al[rb][e8] = l;
-          }
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb) {
-            __bf16 h, m, l;
-            split3<NT>(bv[e8][cb], h, m, l);
-            bh[cb][e8] = h;
-            bm[cb][e8] = m;
-            bl[cb][e8] = l;
-          }
-        }
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          if (rb >= rbn) continue;
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb) {
-            if (cb >= x.cbn) continue;
-            f4 c = acc[rb][cb];
-            // small terms first, largest last
-            if (NT > 3) {
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[rb], bh[cb], c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rb], bl[cb], c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[rb], bm[cb], c, 0, 0, 0);
-            }
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[rb], bh[cb], c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rb], bm[cb], c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rb], bh[cb], c, 0, 0, 0);
-            acc[rb][cb] = c;
-          }
-        }
-      }
-#pragma unroll
-      for (int cb = 0; cb < CB; ++cb) {
-        if (cb >= x.cbn || x.cbase[cb] < 0) continue;
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          if (rb >= rbn) continue;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int lr = 16 * rb + 4 * (lane >> 4) + v;
-            if (lr < rows)
-              x.C.put(x.cbase[cb] + (int64_t)(x.tile.m0 + mc + lr) * x.cnj[cb] + x.ccl[cb], Out(acc[rb][cb][v]));
-          }
-        }
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
 // FP64 norm: Frobenius and max |x|
 // ---------------------------------------------------------------------------
-constexpr int kNormBlocks = 512;
+constexpr int kNormBlocks = 2048;
 
+// Each thread sums a strided slice, four independent loads per iteration;
+// per-block partials are reduced in a fixed order (deterministic).
 template <typename T>
 __global__ void __launch_bounds__(256) k_norm_partial(const T *x, int64_t n, double *part) {
   __shared__ double ss[256], sm[256];
-  double s = 0.0, m = 0.0;
-  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    double v = (double)x[i];
-    s = fma(v, v, s);
-    m = fmax(m, fabs(v));
+  double s0 = 0.0, s1 = 0.0, m0 = 0.0, m1 = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const double a = (double)x[i], b = (double)x[i + stride], c = (double)x[i + 2 * stride],
+                 d = (double)x[i + 3 * stride];
+    s0 = fma(a, a, s0);
+    s1 = fma(b, b, s1);
+    s0 = fma(c, c, s0);
+    s1 = fma(d, d, s1);
+    m0 = fmax(m0, fmax(fabs(a), fabs(c)));
+    m1 = fmax(m1, fmax(fabs(b), fabs(d)));
   }
-  ss[threadIdx.x] = s;
-  sm[threadIdx.x] = m;
+  for (; i < n; i += stride) {
+    const double a = (double)x[i];
+    s0 = fma(a, a, s0);
+    m0 = fmax(m0, fabs(a));
+  }
+  ss[threadIdx.x] = s0 + s1;
+  sm[threadIdx.x] = fmax(m0, m1);
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
@@ -797,7 +287,8 @@ yastn_status upload(Plan &pl) {
          o_ctrs = take(bytes_of(t.ctrs)), o_cols = take(bytes_of(t.cols)), o_agrid = take(bytes_of(t.agrid)),
          o_aoff = take(bytes_of(t.aoff)), o_cgrid = take(bytes_of(t.cgrid)), o_bb = take(bytes_of(t.bblocks)),
          o_tiles = take(bytes_of(t.tiles)), o_items = take(bytes_of(t.items)), o_kofs = take(bytes_of(t.kofs)),
-         o_kp = take(bytes_of(t.kp)), o_cm = take(bytes_of(t.colmap)), o_plan = take(sizeof(DevPlan));
+         o_kp = take(bytes_of(t.kp)), o_cm = take(bytes_of(t.colmap)), o_bofs = take(bytes_of(t.bofs)),
+         o_plan = take(sizeof(DevPlan));
   char *base;
   yastn_status s = dmalloc(&base, off);
   if (s) return s;
@@ -820,6 +311,7 @@ yastn_status upload(Plan &pl) {
   put(o_kofs, t.kofs.data(), bytes_of(t.kofs));
   put(o_kp, t.kp.data(), bytes_of(t.kp));
   put(o_cm, t.colmap.data(), bytes_of(t.colmap));
+  put(o_bofs, t.bofs.data(), bytes_of(t.bofs));
   DevPlan dp{};
   dp.probs = reinterpret_cast<const DevProb *>(base + o_probs);
   dp.sectors = reinterpret_cast<const DevSector *>(base + o_sec);
@@ -835,6 +327,7 @@ yastn_status upload(Plan &pl) {
   dp.kofs = reinterpret_cast<const int64_t *>(base + o_kofs);
   dp.kp = reinterpret_cast<const DevKP *>(base + o_kp);
   dp.colmap = reinterpret_cast<const DevColMap *>(base + o_cm);
+  dp.bofs = reinterpret_cast<const int32_t *>(base + o_bofs);
   dp.ntiles = (int32_t)t.tiles.size();
   dp.nitems = (int32_t)t.items.size();
   put(o_plan, &dp, sizeof(dp));
@@ -844,98 +337,98 @@ yastn_status upload(Plan &pl) {
 }
 
 // ---- kernel dispatch -------------------------------------------------------
-// Kernel variants of one plan: 0 = the plan's heuristic choice; 1..kVariants-1
-// = MFMA tiles with (rows per chunk, k-steps per load batch) from kMfmaShapes,
-// or the row-per-lane kernel.  yastn_plan_autotune times the candidates.
-// RB only tunes speed (a tile of any height is walked in chunks); CB must
-// cover the plan's tile width.  Without buffer addressing (buffers of 2 GiB
-// or more) one general MFMA shape is compiled.
-typedef void (*KernelFn)(LaunchArgs);
-
-struct Shape {
-  int rb, kb;
-};
-constexpr Shape kMfmaShapes[] = {{4, 2}, {4, 1}, {4, 4}, {2, 2}, {2, 4}, {1, 4}};
-constexpr int kNumMfma = sizeof(kMfmaShapes) / sizeof(Shape);
-constexpr int kVariantRows = kNumMfma + 1;  // variant ids: 1..kNumMfma MFMA, kVariantRows rows
-constexpr int kVariants = kVariantRows + 1;
+// Kernel variants of one plan: 0 = the plan's heuristic choice; then
+//   1..kNumMfma                        k_gemm4 with shape kMfmaShapes[v - 1]
+//   kVariantRows                       k_rows (one output row per lane)
+//   kVariantRes0 .. + kNumRes - 1      k_gemm_res with rows per chunk 16 * kResRb[i]
+// yastn_plan_autotune times the candidates that fit the plan.  Tile widths
+// (CB) must cover the plan's tile width; the rest only tunes speed.
+// Wave tiles a launch should have at least, when the plan picks the tile
+// height: 256 CUs x about 8 resident waves x 3 tiles each.
+constexpr int64_t kTilesPerLaunchTarget = 6144;
+constexpr int kVariantRows = kNumMfma + 1;
+constexpr int kVariantRes0 = kVariantRows + 1;
+constexpr int kVariants = kVariantRes0 + kNumRes;
 static_assert(kVariants == YASTN_NUM_VARIANTS, "variant count must match the header");
 
-template <typename In, typename Cmp, typename Out, int RB, int KB>
-KernelFn pick_mfma_cb(int cb) {
-  switch (cb) {
-    case 1: return k_gemm4<In, Cmp, Out, true, RB, 1, KB>;
-    case 2: return k_gemm4<In, Cmp, Out, true, RB, 2, KB>;
-    case 3: return k_gemm4<In, Cmp, Out, true, RB, 3, KB>;
-    default: return k_gemm4<In, Cmp, Out, true, RB, 4, KB>;
-  }
-}
-template <typename In, typename Cmp, typename Out>
-KernelFn pick_gemm4(bool buf, int shape, int cb) {
-  if (!buf) return k_gemm4<In, Cmp, Out, false, 4, 4, 2>;
-  if (std::is_same<Cmp, double>::value) {
-    switch (shape) {
-      case 1: return pick_mfma_cb<In, Cmp, Out, 4, 1>(cb);
-      case 2: return pick_mfma_cb<In, Cmp, Out, 4, 4>(cb);
-      case 3: return pick_mfma_cb<In, Cmp, Out, 2, 2>(cb);
-      case 4: return pick_mfma_cb<In, Cmp, Out, 2, 4>(cb);
-      case 5: return pick_mfma_cb<In, Cmp, Out, 1, 4>(cb);
-      default: break;
-    }
-  } else if (shape == 3 || shape == 4 || shape == 5) {
-    return pick_mfma_cb<In, Cmp, Out, 2, 4>(cb);
-  }
-  return pick_mfma_cb<In, Cmp, Out, 4, 2>(cb);
-}
-template <typename In, typename Out, int NT>
-KernelFn pick_bf16(bool buf, int cb) {
-  if (!buf) return k_gemm_bf16<In, Out, false, 4, 4, NT>;
-  switch (cb) {
-    case 1: return k_gemm_bf16<In, Out, true, 4, 1, NT>;
-    case 2: return k_gemm_bf16<In, Out, true, 4, 2, NT>;
-    case 3: return k_gemm_bf16<In, Out, true, 4, 3, NT>;
-    default: return k_gemm_bf16<In, Out, true, 4, 4, NT>;
-  }
-}
-template <typename In, typename Out>
-KernelFn pick_gemm(yastn_precision p, bool buf, int shape, int cb) {
-  switch (p) {
-    case YASTN_F32: return pick_gemm4<In, float, Out>(buf, shape, cb);
-    case YASTN_BF16X3: return pick_bf16<In, Out, 3>(buf, cb);
-    default: return pick_bf16<In, Out, 6>(buf, cb);
-  }
-}
-KernelFn gemm_kernel(const yastn_options &o, bool buf, int shape, int cb) {
-  if (o.in_dtype == YASTN_DTYPE_F64) {
-    if (o.precision == YASTN_F64) return pick_gemm4<double, double, double>(buf, shape, cb);
-    return o.out_dtype == YASTN_DTYPE_F64 ? pick_gemm<double, double>(o.precision, buf, shape, cb)
-                                          : pick_gemm<double, float>(o.precision, buf, shape, cb);
-  }
-  return o.out_dtype == YASTN_DTYPE_F64 ? pick_gemm<float, double>(o.precision, buf, shape, cb)
-                                        : pick_gemm<float, float>(o.precision, buf, shape, cb);
-}
-template <typename In, typename Cmp, typename Out>
-KernelFn pick_rows(bool buf, int kmax) {
-  if (!buf) return k_rows<In, Cmp, Out, false, 64>;
-  if (kmax <= 16) return k_rows<In, Cmp, Out, true, 16>;
-  if (kmax <= 32) return k_rows<In, Cmp, Out, true, 32>;
-  if (kmax <= 48) return k_rows<In, Cmp, Out, true, 48>;
-  return k_rows<In, Cmp, Out, true, 64>;
-}
-KernelFn rows_kernel(const yastn_options &o, bool buf, int kmax) {
-  if (o.in_dtype == YASTN_DTYPE_F64) {
-    if (o.precision == YASTN_F64) return pick_rows<double, double, double>(buf, kmax);
-    return o.out_dtype == YASTN_DTYPE_F64 ? pick_rows<double, float, double>(buf, kmax)
-                                          : pick_rows<double, float, float>(buf, kmax);
-  }
-  return o.out_dtype == YASTN_DTYPE_F64 ? pick_rows<float, float, double>(buf, kmax)
-                                        : pick_rows<float, float, float>(buf, kmax);
-}
+enum Family { FAM_MFMA, FAM_ROWS, FAM_RES, FAM_BF16 };
+
+struct Choice {
+  Family fam;
+  KernelFn gemm, pack;  // pack is null when the GEMM reads B's blocks directly
+};
+
+bool is_bf16(const yastn_options &o) { return o.precision == YASTN_BF16X3 || o.precision == YASTN_BF16X6; }
 
 KernelFn pack_kernel(const yastn_options &o) {
-  const bool f64cmp = o.precision == YASTN_F64;
-  if (o.in_dtype == YASTN_DTYPE_F64) return f64cmp ? k_pack_b<double, double> : k_pack_b<double, float>;
-  return k_pack_b<float, float>;
+  if (o.precision == YASTN_F64) return pack_f64();
+  return o.in_dtype == YASTN_DTYPE_F64 ? pack_f32d() : pack_f32f();
+}
+
+KernelFn mfma_kernel(const yastn_options &o, bool buf, int shape, int cb) {
+  if (o.precision == YASTN_F64) return gemm4_f64(buf, shape, cb);
+  if (o.precision == YASTN_F32)
+    return o.in_dtype == YASTN_DTYPE_F64 ? gemm4_f32d(o.out_dtype, buf, shape, cb)
+                                         : gemm4_f32f(o.out_dtype, buf, shape, cb);
+  return bf16_gemm(o.in_dtype, o.out_dtype, o.precision == YASTN_BF16X3 ? 3 : 6, buf, cb);
+}
+
+KernelFn rows_kernel(const yastn_options &o, bool buf, int kmax) {
+  if (o.precision == YASTN_F64) return rows_f64(buf, kmax);
+  return o.in_dtype == YASTN_DTYPE_F64 ? rows_f32d(o.out_dtype, buf, kmax) : rows_f32f(o.out_dtype, buf, kmax);
+}
+
+KernelFn res_kernel(const yastn_options &o, bool buf, int shape, int cb, int kq, int na) {
+  if (o.precision == YASTN_F64) return res_f64(buf, shape, cb, kq, na);
+  return o.in_dtype == YASTN_DTYPE_F64 ? res_f32d(o.out_dtype, buf, cb, kq) : res_f32f(o.out_dtype, buf, cb, kq);
+}
+
+// Which variants can run a set of plans in one launch.
+struct Fit {
+  int cb = 1, kmax = 0, nact = 1;
+  bool buf = true, rows = true, res = true, bf16 = false;
+  bool rows_pick = true;  // every plan asked for the row kernel (YASTN_FLAG_ROWS)
+  bool mfma_pick = true;  // every plan asked for MFMA tiles (YASTN_FLAG_MFMA)
+};
+
+void fit_add(Fit &f, const Plan &p) {
+  f.cb = std::max(f.cb, p.cb);
+  f.kmax = std::max(f.kmax, p.kmax);
+  f.nact = std::max(f.nact, p.nact);
+  f.buf = f.buf && p.buf_ok;
+  f.rows = f.rows && p.rows_fit;
+  f.res = f.res && p.res_fit;
+  f.bf16 = is_bf16(p.opts);
+  f.rows_pick = f.rows_pick && p.opts.flags == YASTN_FLAG_ROWS;
+  f.mfma_pick = f.mfma_pick && p.opts.flags == YASTN_FLAG_MFMA;
+}
+
+bool variant_fits(const Fit &f, const yastn_options &o, int v) {
+  if (v == 0) return true;
+  if (f.bf16) return v == 1;
+  if (v >= 1 && v <= kNumMfma) return v == 1 || (f.buf && (o.precision == YASTN_F64 || v == 1 || v == 4));
+  if (v == kVariantRows) return f.rows;
+  if (v >= kVariantRes0 && v < kVariants) {
+    if (!f.res || !f.buf) return false;
+    return o.precision == YASTN_F64 || v == kVariantRes0 + 1;  // FP32: one shape compiled (kResShapes[1])
+  }
+  return false;
+}
+
+Choice choose(const Fit &f, const yastn_options &o, int variant) {
+  if (variant != 0 && !variant_fits(f, o, variant)) variant = 0;
+  if (variant == 0) {  // heuristic
+    if (f.bf16 || f.mfma_pick || !f.buf) variant = 1;
+    else if (f.rows_pick && f.rows) variant = kVariantRows;
+    else if (f.res) variant = kVariantRes0 + 1;
+    else variant = 1;
+  }
+  const int kq = (f.kmax + 3) / 4;
+  const int na = f.nact <= 2 ? 2 : 4;
+  if (variant == kVariantRows) return Choice{FAM_ROWS, rows_kernel(o, f.buf, f.kmax), pack_kernel(o)};
+  if (variant >= kVariantRes0)
+    return Choice{FAM_RES, res_kernel(o, f.buf, variant - kVariantRes0, f.cb, kq, na), nullptr};
+  return Choice{f.bf16 ? FAM_BF16 : FAM_MFMA, mfma_kernel(o, f.buf, variant - 1, f.cb), pack_kernel(o)};
 }
 
 int g_num_cu = 0;
@@ -967,19 +460,14 @@ yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const
     return YASTN_OK;
   }
   const yastn_options &o = jobs[0].plan->opts;
-  int cb = 1, kmax = 0, variant = jobs[0].plan->variant;
-  bool buf = true, rows_fit = true, rows_pick = true;
+  Fit fit;
+  int variant = jobs[0].plan->variant;
   for (auto &j : jobs) {
-    cb = std::max(cb, j.plan->cb);
-    kmax = std::max(kmax, j.plan->kmax);
-    buf = buf && j.plan->buf_ok;
-    rows_fit = rows_fit && j.plan->rows_fit;
-    rows_pick = rows_pick && j.plan->rows_kernel;
+    fit_add(fit, *j.plan);
     if (j.plan->variant != variant) variant = 0;
   }
-  bool rows = variant == 0 ? rows_pick : (variant == kVariantRows && rows_fit);
-  const int shape = (variant >= 1 && variant <= kNumMfma) ? variant - 1 : 0;
-  KernelFn gemm = rows ? rows_kernel(o, buf, kmax) : gemm_kernel(o, buf, shape, cb), pack = pack_kernel(o);
+  const Choice ch = choose(fit, o, variant);
+  if (!ch.gemm) return set_error(YASTN_ERR_STATE, "no kernel instance for this plan");
   size_t ji = 0;
   while (ji < jobs.size()) {
     LaunchArgs la;
@@ -1008,16 +496,19 @@ yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const
       la.nitems += j.g->i1 - j.g->i0;
       ++ji;
     }
-    const int max_wg = num_cus() * 4;
     void *kargs[] = {&la};
-    if (la.nitems > 0) {
-      unsigned g = (unsigned)std::min<int64_t>(la.nitems, 16 * max_wg);
-      YASTN_HIP(hipLaunchKernel(reinterpret_cast<const void *>(pack), dim3(g), dim3(256), kargs, 0, st));
+    if (ch.pack && la.nitems > 0) {
+      unsigned g = (unsigned)std::min<int64_t>(la.nitems, 64 * num_cus());
+      YASTN_HIP(hipLaunchKernel(reinterpret_cast<const void *>(ch.pack), dim3(g), dim3(256), kargs, 0, st));
     }
     if (events && events[1]) YASTN_HIP(hipEventRecord(reinterpret_cast<hipEvent_t>(events[1]), st));
     if (la.ntiles > 0) {
-      unsigned g = (unsigned)std::min<int64_t>((la.ntiles + 3) / 4, max_wg);
-      YASTN_HIP(hipLaunchKernel(reinterpret_cast<const void *>(gemm), dim3(g), dim3(256), kargs, 0, st));
+      // one tile per wave: the dispatcher starts a workgroup whenever one
+      // retires, which balances tiles of uneven cost better than a static
+      // round-robin over resident waves (the kernels still loop, for grids
+      // capped by the launch limit)
+      unsigned g = (unsigned)std::max<int64_t>(1, (la.ntiles + 3) / 4);
+      YASTN_HIP(hipLaunchKernel(reinterpret_cast<const void *>(ch.gemm), dim3(g), dim3(256), kargs, 0, st));
     }
     if (events && events[2]) YASTN_HIP(hipEventRecord(reinterpret_cast<hipEvent_t>(events[2]), st));
   }
@@ -1139,16 +630,34 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
     pl.kmax = (int)maxk;
     const bool bf16 = o.precision == YASTN_BF16X3 || o.precision == YASTN_BF16X6;
     pl.rows_fit = !bf16 && maxk <= 64 && maxn <= 64;
-    pl.rows_kernel = pl.rows_fit && o.flags == YASTN_FLAG_ROWS;
+    pl.res_fit = !bf16 && maxk <= kResMaxK && !pl.t.bofs_overflow;
+    pl.nact = 1;
+    for (const DevProb &dp : pl.t.probs) pl.nact = std::max(pl.nact, (int)dp.nact);
     pl.variant = 0;
-    // tiles: 64 rows (walked in chunks by every kernel) x the narrowest column
-    // width that covers the widest sector (at most 64)
+    // tiles: the narrowest column width that covers the widest sector (at
+    // most 64) x a height of 16 to 512 rows (walked in chunks by every
+    // kernel).  Taller tiles spread each tile's setup over more rows; the
+    // plan keeps them short enough that every wave slot of the chip gets
+    // several tiles (the tiles are cost-sorted, so they balance).
     const int cb = (int)std::min<int64_t>(4, (maxn + 15) / 16);
-    if (cb != 4 && (s = build_all(4, cb, 1)) != YASTN_OK) {
+    int tm = 64;
+    if (o.tile_rows) {
+      tm = o.tile_rows;
+    } else {
+      auto count = [&](int64_t h) {
+        int64_t n = 0;
+        for (auto &rt : pl.t.rows) n += ((rt.m + h - 1) / h) * ((pl.t.sectors[rt.sector].N + 16 * cb - 1) / (16 * cb));
+        return n;
+      };
+      tm = 16;
+      while (tm < 512 && count(2 * tm) >= kTilesPerLaunchTarget) tm *= 2;
+    }
+    // tile height = 16 * rb * nch rows
+    const int rb_t = tm >= 64 ? 4 : tm / 16, nch = tm >= 64 ? tm / 64 : 1;
+    if ((cb != 4 || tm != 64) && (s = build_all(rb_t, cb, nch)) != YASTN_OK) {
       delete h;
       return s;
     }
-    if (o.tile_rows) pl.variant = o.tile_rows == 64 ? 1 : (o.tile_rows == 32 ? 4 : 6);
     (void)rows;
     (void)rows64;
     if (a_base > INT32_MAX || b_base > INT32_MAX) {
@@ -1156,11 +665,13 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
       return set_error(YASTN_ERR_ARG, "too many blocks in one plan");
     }
     finish_tiles(pl);
-    // buffer addressing needs every A span and C size below 2 GiB
+    // buffer addressing needs every A and B span and C size below 2 GiB
     const int64_t in_b = o.in_dtype == YASTN_DTYPE_F64 ? 8 : 4, out_b = o.out_dtype == YASTN_DTYPE_F64 ? 8 : 4;
     pl.buf_ok = true;
     for (const DevProb &dp : pl.t.probs)
-      if (dp.a_span * in_b >= (int64_t(1) << 31) || dp.c_numel * out_b >= (int64_t(1) << 31)) pl.buf_ok = false;
+      if (dp.a_span * in_b >= (int64_t(1) << 31) || dp.b_span * in_b >= (int64_t(1) << 31) ||
+          dp.c_numel * out_b >= (int64_t(1) << 31))
+        pl.buf_ok = false;
     if ((s = upload(pl)) != YASTN_OK) {
       yastn_free(h);
       return s;
@@ -1227,7 +738,9 @@ yastn_status yastn_contract_timed(yastn_plan_t plan, const void *const *a, const
 yastn_status yastn_plan_set_variant(yastn_plan_t plan, int32_t variant) {
   if (!plan) return set_error(YASTN_ERR_ARG, "null plan");
   if (variant < 0 || variant >= kVariants) return set_error(YASTN_ERR_ARG, "variant out of range");
-  if (variant == kVariantRows && !plan->p.rows_fit) return set_error(YASTN_ERR_STATE, "row kernel does not fit this plan");
+  Fit f;
+  fit_add(f, plan->p);
+  if (!variant_fits(f, plan->p.opts, variant)) return set_error(YASTN_ERR_STATE, "kernel variant does not fit this plan");
   plan->p.variant = variant;
   return YASTN_OK;
 }
@@ -1244,15 +757,13 @@ yastn_status yastn_plan_autotune(yastn_plan_t plan, const void *const *a, const 
   YASTN_HIP(hipEventCreate(&e0));
   YASTN_HIP(hipEventCreate(&e1));
   const int keep = plan->p.variant;
-  const bool bf16 = plan->p.opts.precision == YASTN_BF16X3 || plan->p.opts.precision == YASTN_BF16X6;
-  const bool f32 = plan->p.opts.precision == YASTN_F32;
+  Fit fit;
+  fit_add(fit, plan->p);
   int best = 1;
   float best_ms = 1e30f;
   for (int v = 1; v < kVariants; ++v) {
     float ms = -1.f;
-    const bool applicable = v == 1 || (v == kVariantRows ? plan->p.rows_fit
-                                                         : (!bf16 && plan->p.buf_ok && (!f32 || v == 4)));
-    if (applicable) {
+    if (variant_fits(fit, plan->p.opts, v)) {
       plan->p.variant = v;
       s = launch(jobs, st);  // warm-up
       if (!s) s = (hipEventRecord(e0, st) == hipSuccess) ? YASTN_OK : YASTN_ERR_HIP;
@@ -1304,7 +815,7 @@ yastn_status yastn_norm(const void *x, int64_t n, yastn_dtype dtype, double *out
   if (dtype != YASTN_DTYPE_F64 && dtype != YASTN_DTYPE_F32) return set_error(YASTN_ERR_ARG, "unknown dtype");
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   double *part = reinterpret_cast<double *>(workspace);
-  int nb = (int)std::min<int64_t>(kNormBlocks, std::max<int64_t>(1, (n + 255) / 256));
+  int nb = (int)std::min<int64_t>(kNormBlocks, std::max<int64_t>(1, (n + 1023) / 1024));
   if (dtype == YASTN_DTYPE_F64)
     k_norm_partial<double><<<nb, 256, 0, st>>>(reinterpret_cast<const double *>(x), n, part);
   else

@@ -1,0 +1,46 @@
+// Kernel selection: which template instance of kernels.hpp runs a launch.
+// Each arithmetic's instances live in their own translation unit
+// (inst_f64.hip, inst_f32d.hip, inst_f32f.hip, inst_bf16.hip).
+#pragma once
+#include "../../include/yastn.h"
+#include "plan.hpp"
+
+namespace yastn {
+
+typedef void (*KernelFn)(LaunchArgs);
+
+// k_gemm4 tile shapes: rows per chunk = 16 * rb, k-steps per load batch = kb.
+struct Shape {
+  int rb, kb;
+};
+constexpr Shape kMfmaShapes[] = {{4, 2}, {4, 1}, {4, 4}, {2, 2}, {2, 4}, {1, 4}};
+constexpr int kNumMfma = sizeof(kMfmaShapes) / sizeof(Shape);
+// k_gemm_res: rows per chunk = 16 * rb, next chunk's A loads issued early
+// (db), occupancy hint (occ waves per SIMD, 0 = none); k slots held = 4 * kq
+struct ResShape {
+  int rb, db, occ;
+};
+constexpr ResShape kResShapes[] = {{1, 1, 3}, {2, 0, 3}, {1, 0, 4}, {2, 0, 4}, {4, 0, 2}, {2, 1, 3}};
+constexpr int kNumRes = sizeof(kResShapes) / sizeof(ResShape);
+constexpr int kResKq[] = {5, 10, 16};
+constexpr int kResMaxK = 64;
+
+// FP64 arithmetic (F64 buffers)
+KernelFn gemm4_f64(bool buf, int shape, int cb);
+KernelFn res_f64(bool buf, int shape, int cb, int kq, int na);
+KernelFn rows_f64(bool buf, int kmax);
+KernelFn pack_f64();
+// FP32 arithmetic with FP64 input buffers (out: F64 or F32)
+KernelFn gemm4_f32d(yastn_dtype out, bool buf, int shape, int cb);
+KernelFn res_f32d(yastn_dtype out, bool buf, int cb, int kq);
+KernelFn rows_f32d(yastn_dtype out, bool buf, int kmax);
+KernelFn pack_f32d();
+// FP32 arithmetic with FP32 input buffers
+KernelFn gemm4_f32f(yastn_dtype out, bool buf, int shape, int cb);
+KernelFn res_f32f(yastn_dtype out, bool buf, int cb, int kq);
+KernelFn rows_f32f(yastn_dtype out, bool buf, int kmax);
+KernelFn pack_f32f();
+// split-BF16 products (nt = 3 or 6), FP32 accumulation
+KernelFn bf16_gemm(yastn_dtype in, yastn_dtype out, int nt, bool buf, int cb);
+
+}  // namespace yastn

@@ -16,6 +16,7 @@
 #include <map>
 #include <numeric>
 
+#include "index.hpp"
 #include "planner.hpp"
 
 namespace yastn {
@@ -147,8 +148,9 @@ yastn_status check_options(const yastn_options *o, yastn_options *out) {
   if (d.out_dtype != YASTN_DTYPE_F64 && d.out_dtype != YASTN_DTYPE_F32) return set_error(YASTN_ERR_ARG, "unknown out_dtype");
   if (d.precision == YASTN_F64 && (d.in_dtype != YASTN_DTYPE_F64 || d.out_dtype != YASTN_DTYPE_F64))
     return set_error(YASTN_ERR_ARG, "F64 arithmetic needs F64 input and output buffers");
-  if (d.tile_rows != 0 && d.tile_rows != 16 && d.tile_rows != 32 && d.tile_rows != 64)
-    return set_error(YASTN_ERR_ARG, "tile_rows must be 0, 16, 32 or 64");
+  if (d.tile_rows != 0 && d.tile_rows != 16 && d.tile_rows != 32 && d.tile_rows != 64 && d.tile_rows != 128 &&
+      d.tile_rows != 256 && d.tile_rows != 512)
+    return set_error(YASTN_ERR_ARG, "tile_rows must be 0, 16, 32, 64, 128, 256 or 512");
   if (d.flags != 0 && d.flags != YASTN_FLAG_MFMA && d.flags != YASTN_FLAG_ROWS)
     return set_error(YASTN_ERR_ARG, "flags must be 0, YASTN_FLAG_MFMA or YASTN_FLAG_ROWS");
   *out = d;
@@ -275,6 +277,7 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
   dp.nc = nc;
   dp.nfb = hp.nfb;
   for (int64_t b = 0; b < A.nblocks; ++b) dp.a_span = std::max<int64_t>(dp.a_span, A.offsets[b] + A.size(b));
+  for (int64_t b = 0; b < B.nblocks; ++b) dp.b_span = std::max<int64_t>(dp.b_span, B.offsets[b] + B.size(b));
   const size_t prob_slot = t.probs.size();
   t.probs.push_back(dp);
   // ---- output blocks: (A free tuple, B free tuple) reached by >= 1 pair, ascending order
@@ -424,6 +427,22 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
       const DevColTuple &cl = t.cols[ds.col0 + j];
       for (int c = 0; c < cl.n; ++c) t.colmap.push_back(DevColMap{j, c, cl.n, 0});
     }
+    // element offset in B's buffer of every (k, column) of B_X (-1: sub-block absent)
+    ds.bofs0 = (int64_t)t.bofs.size();
+    t.bofs.resize(t.bofs.size() + size_t(K) * N, -1);
+    for (int s = 0; s < Sn; ++s)
+      for (int j = 0; j < Q; ++j) {
+        const int32_t blk = bgrid[size_t(s) * Q + j];
+        if (blk < 0) continue;
+        const DevCtrTuple &ct = t.ctrs[ds.ctr0 + s];
+        const DevColTuple &cl = t.cols[ds.col0 + j];
+        for (int32_t kd = 0; kd < ct.k; ++kd)
+          for (int32_t cb = 0; cb < cl.n; ++cb) {
+            const int64_t o = b_offset(t.bblocks[blk], ct, cl, t.probs[prob_slot], kd, cb);
+            if (o > INT32_MAX) t.bofs_overflow = true;
+            t.bofs[ds.bofs0 + int64_t(ct.ko + kd) * N + cl.no + cb] = (int32_t)std::min<int64_t>(o, INT32_MAX);
+          }
+      }
     const int32_t sec_id = (int32_t)t.sectors.size();
     t.sectors.push_back(ds);
     for (int s = 0; s < Sn; ++s)
@@ -449,6 +468,7 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
         for (int q = 0; q < hp.nfa; ++q)
           if (fcls[q] >= a) p *= A.dim(ia, hp.fa[q]);
         rt.lsuf[a] = (int32_t)p;
+        div_magic((uint32_t)p, &rt.lmag[a], &rt.lsh[a]);
       }
       for (int c = 0; c < nc; ++c) {
         int64_t p = 1;

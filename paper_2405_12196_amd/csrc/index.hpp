@@ -9,6 +9,7 @@
 #ifndef __HIPCC__
 #define YASTN_HD inline
 #else
+#include <hip/hip_runtime.h>
 #define YASTN_HD __host__ __device__ __forceinline__
 #endif
 
@@ -19,6 +20,33 @@ namespace yastn {
 YASTN_HD void a_rowparts(const DevRowTuple &rt, int nact, int32_t ra, int32_t *rg) {
 #pragma unroll
   for (int a = 0; a < kMaxAct; ++a) rg[a] = a < nact ? (ra % rt.lsuf[a]) - (ra % rt.lsuf[a + 1]) : 0;
+}
+
+// The same RG_a with one multiply-high division per class boundary instead of
+// two modulo operations per class: RG_a = (r mod Lsuf_a) - (r mod Lsuf_{a+1}),
+// r mod Lsuf_0 = r (rows of a tuple are below Lsuf_0 = m_i), Lsuf_nact = 1.
+template <int NA>
+YASTN_HD void a_rowparts_fast(const DevRowTuple &rt, int nact, int32_t ra, int32_t *rg) {
+  int32_t prev = ra;
+#pragma unroll
+  for (int a = 0; a < NA; ++a) {
+    int32_t next = 0;
+    if (a + 1 < nact) {
+      const uint32_t q = (uint32_t)(((uint64_t)(uint32_t)ra * rt.lmag[a + 1]) >> rt.lsh[a + 1]);
+      next = ra - (int32_t)q * rt.lsuf[a + 1];
+    }
+    rg[a] = a < nact ? prev - next : 0;
+    prev = next;
+  }
+}
+
+// Magic multiplier for floor(n / d), 0 <= n < 2^31, 1 <= d < 2^31 (round-up
+// method: l = ceil(log2 d), m = ceil(2^(31 + l) / d) < 2^32).
+inline void div_magic(uint32_t d, uint32_t *mag, int32_t *sh) {
+  int l = 0;
+  while ((uint64_t(1) << l) < d) ++l;
+  *sh = 31 + l;
+  *mag = (uint32_t)(((uint64_t(1) << (31 + l)) + d - 1) / d);
 }
 
 // Same sum in the offset type of the kernel (32-bit when buffers are small).

@@ -1,0 +1,57 @@
+// Template instances of the FP32-arithmetic kernels with FP64 input buffers.
+#include "dispatch.hpp"
+#include "kernels.hpp"
+
+namespace yastn {
+namespace {
+typedef double In;
+typedef float F;
+
+template <typename Out, int RB, int KB> KernelFn g4_cb(int cb) {
+  switch (cb) {
+    case 1: return k_gemm4<In, F, Out, true, RB, 1, KB>;
+    case 2: return k_gemm4<In, F, Out, true, RB, 2, KB>;
+    case 3: return k_gemm4<In, F, Out, true, RB, 3, KB>;
+    default: return k_gemm4<In, F, Out, true, RB, 4, KB>;
+  }
+}
+template <typename Out> KernelFn g4(bool buf, int shape, int cb) {
+  if (!buf) return k_gemm4<In, F, Out, false, 4, 4, 2>;
+  if (shape == 3 || shape == 4 || shape == 5) return g4_cb<Out, 2, 4>(cb);
+  return g4_cb<Out, 4, 2>(cb);
+}
+template <typename Out, int KQ> KernelFn res_cb(int cb) {
+  switch (cb) {
+    case 1: return k_gemm_res<In, F, Out, true, 2, 1, KQ, 4, false, 3>;
+    case 2: return k_gemm_res<In, F, Out, true, 2, 2, KQ, 4, false, 3>;
+    case 3: return k_gemm_res<In, F, Out, true, 2, 3, KQ, 4, false, 3>;
+    default: return k_gemm_res<In, F, Out, true, 2, 4, KQ, 4, false, 3>;
+  }
+}
+template <typename Out> KernelFn res(bool buf, int cb, int kq) {
+  if (!buf) return nullptr;
+  if (kq <= 5) return res_cb<Out, 5>(cb);
+  if (kq <= 10) return res_cb<Out, 10>(cb);
+  return res_cb<Out, 16>(cb);
+}
+template <typename Out> KernelFn rows(bool buf, int kmax) {
+  if (!buf) return k_rows<In, F, Out, false, 64>;
+  if (kmax <= 16) return k_rows<In, F, Out, true, 16>;
+  if (kmax <= 32) return k_rows<In, F, Out, true, 32>;
+  if (kmax <= 48) return k_rows<In, F, Out, true, 48>;
+  return k_rows<In, F, Out, true, 64>;
+}
+}  // namespace
+
+KernelFn gemm4_f32d(yastn_dtype out, bool buf, int shape, int cb) {
+  return out == YASTN_DTYPE_F64 ? g4<double>(buf, shape, cb) : g4<float>(buf, shape, cb);
+}
+KernelFn res_f32d(yastn_dtype out, bool buf, int cb, int kq) {
+  return out == YASTN_DTYPE_F64 ? res<double>(buf, cb, kq) : res<float>(buf, cb, kq);
+}
+KernelFn rows_f32d(yastn_dtype out, bool buf, int kmax) {
+  return out == YASTN_DTYPE_F64 ? rows<double>(buf, kmax) : rows<float>(buf, kmax);
+}
+KernelFn pack_f32d() { return k_pack_b<In, F>; }
+
+}  // namespace yastn

@@ -1,0 +1,69 @@
+// Template instances of the FP64 kernels.
+#include "dispatch.hpp"
+#include "kernels.hpp"
+
+namespace yastn {
+namespace {
+typedef double D;
+
+template <int RB, int KB> KernelFn g4_cb(int cb) {
+  switch (cb) {
+    case 1: return k_gemm4<D, D, D, true, RB, 1, KB>;
+    case 2: return k_gemm4<D, D, D, true, RB, 2, KB>;
+    case 3: return k_gemm4<D, D, D, true, RB, 3, KB>;
+    default: return k_gemm4<D, D, D, true, RB, 4, KB>;
+  }
+}
+template <int RB, int KQ, int NA, bool DB, int OCC> KernelFn res_cb(int cb) {
+  switch (cb) {
+    case 1: return k_gemm_res<D, D, D, true, RB, 1, KQ, NA, DB, OCC>;
+    case 2: return k_gemm_res<D, D, D, true, RB, 2, KQ, NA, DB, OCC>;
+    case 3: return k_gemm_res<D, D, D, true, RB, 3, KQ, NA, DB, OCC>;
+    default: return k_gemm_res<D, D, D, true, RB, 4, KQ, NA, DB, OCC>;
+  }
+}
+template <int RB, int NA, bool DB, int OCC> KernelFn res_kq(int kq, int cb) {
+  if (kq <= 5) return res_cb<RB, 5, NA, DB, OCC>(cb);
+  if (kq <= 10) return res_cb<RB, 10, NA, DB, OCC>(cb);
+  return res_cb<RB, 16, NA, DB, OCC>(cb);
+}
+template <int RB, bool DB, int OCC> KernelFn res_na(int na, int kq, int cb) {
+  return na <= 2 ? res_kq<RB, 2, DB, OCC>(kq, cb) : res_kq<RB, 4, DB, OCC>(kq, cb);
+}
+}  // namespace
+
+KernelFn gemm4_f64(bool buf, int shape, int cb) {
+  if (!buf) return k_gemm4<D, D, D, false, 4, 4, 2>;
+  switch (shape) {
+    case 1: return g4_cb<4, 1>(cb);
+    case 2: return g4_cb<4, 4>(cb);
+    case 3: return g4_cb<2, 2>(cb);
+    case 4: return g4_cb<2, 4>(cb);
+    case 5: return g4_cb<1, 4>(cb);
+    default: return g4_cb<4, 2>(cb);
+  }
+}
+
+KernelFn res_f64(bool buf, int shape, int cb, int kq, int na) {
+  if (!buf) return nullptr;
+  switch (shape) {  // kResShapes
+    case 0: return res_na<1, true, 3>(na, kq, cb);
+    case 1: return res_na<2, false, 3>(na, kq, cb);
+    case 2: return res_na<1, false, 4>(na, kq, cb);
+    case 3: return res_na<2, false, 4>(na, kq, cb);
+    case 4: return res_na<4, false, 2>(na, kq, cb);
+    default: return res_na<2, true, 3>(na, kq, cb);
+  }
+}
+
+KernelFn rows_f64(bool buf, int kmax) {
+  if (!buf) return k_rows<D, D, D, false, 64>;
+  if (kmax <= 16) return k_rows<D, D, D, true, 16>;
+  if (kmax <= 32) return k_rows<D, D, D, true, 32>;
+  if (kmax <= 48) return k_rows<D, D, D, true, 48>;
+  return k_rows<D, D, D, true, 64>;
+}
+
+KernelFn pack_f64() { return k_pack_b<D, D>; }
+
+}  // namespace yastn

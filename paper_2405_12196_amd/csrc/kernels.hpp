@@ -1,0 +1,683 @@
+// HIP kernels of the block-sparse tensordot for gfx950 (CDNA4), as templates.
+// Instantiated in the inst_*.hip translation units (one per arithmetic), so
+// the many tile shapes compile in parallel.
+//
+//  k_pack_b     fuses B's legs into the per-sector matrices B_X (K_X x N_X,
+//               row-major; absent sub-blocks zero) -- the "fuse" step of the
+//               fuse -> multiply -> unfuse contraction of paper Sec. II.B,
+//               applied to the small operand only.
+//  k_gemm4      grouped GEMM C_X = A_X B_X over every sector of every problem
+//               in one launch, FP64 / FP32 MFMA 16x16x4.  One wave owns a tile
+//               of up to 64 rows of one A free tuple x up to 64 columns of B_X.
+//               A is never materialised: each element is gathered from its
+//               block through the factorised offsets of plan.hpp (the leg
+//               permute is fused into the load).  The epilogue writes each
+//               element straight into its output block (the "unfuse" step),
+//               exactly once: no atomics, deterministic results.
+//  k_gemm_res   as k_gemm4 for sectors with K_X <= 64, with the tile's B
+//               values and k metadata held in registers and B read straight
+//               from its blocks (no pack kernel).
+//  k_rows       tall-skinny sectors (K, N <= 64): one row of C_X per lane.
+//  k_gemm_bf16  split-BF16 products on bf16 MFMA 16x16x32, FP32 accumulation.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "index.hpp"
+
+namespace yastn {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// Wave-uniform reads of plan tables go through the constant address space:
+// the tables are read-only while kernels run, so the compiler may use scalar
+// loads (reads only) and keep the values in SGPRs.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+__device__ __forceinline__ T cst(const T *p) {
+  return *(const __attribute__((address_space(4))) T *)(p);
+}
+#else
+template <typename T> __device__ __forceinline__ T cst(const T *p) { return *p; }  // host pass: unused
+#endif
+
+// The plan's table of pointers, one field at a time: copying the whole
+// struct in one aggregate load loses the constant address space of the
+// pointers inside it, and every table read behind them then becomes a
+// per-lane flat load instead of a scalar load.
+__device__ __forceinline__ DevPlan load_plan(const DevPlan *p) {
+  DevPlan d;
+  d.probs = cst(&p->probs);
+  d.sectors = cst(&p->sectors);
+  d.rows = cst(&p->rows);
+  d.ctrs = cst(&p->ctrs);
+  d.cols = cst(&p->cols);
+  d.agrid = cst(&p->agrid);
+  d.aoff = cst(&p->aoff);
+  d.cgrid = cst(&p->cgrid);
+  d.bblocks = cst(&p->bblocks);
+  d.tiles = cst(&p->tiles);
+  d.items = cst(&p->items);
+  d.kofs = cst(&p->kofs);
+  d.kp = cst(&p->kp);
+  d.colmap = cst(&p->colmap);
+  d.bofs = cst(&p->bofs);
+  d.ntiles = cst(&p->ntiles);
+  d.nitems = cst(&p->nitems);
+  return d;
+}
+
+// LDS written by one lane and read by another lane of the same wave.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A value the compiler cannot prove wave-uniform but that is.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <typename T> __device__ __forceinline__ T *uniptr(T *p) {
+  return reinterpret_cast<T *>(uni64(reinterpret_cast<int64_t>(p)));
+}
+
+
+// ---------------------------------------------------------------------------
+// numeric helpers
+// ---------------------------------------------------------------------------
+// round-to-nearest-even float -> bf16 bits (finite inputs)
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+// ---------------------------------------------------------------------------
+// B pack: per-sector matrices B_X in the workspace
+// ---------------------------------------------------------------------------
+// One workgroup per item of up to 256 elements of one (s, j) sub-block;
+// consecutive threads write consecutive elements of a B_X row.
+template <typename In, typename Cmp>
+__global__ void __launch_bounds__(256) k_pack_b(LaunchArgs args) {
+  for (int g = blockIdx.x; g < args.nitems; g += gridDim.x) {
+    int jb = 0;
+    while (jb + 1 < args.njobs && g >= args.jobs[jb + 1].item0) ++jb;
+    const JobArg &job = args.jobs[jb];
+    const DevPlan P = load_plan(job.plan);
+    const DevPackItem it = cst(P.items + (g - job.item0 + job.pitem0));
+    const DevSector sec = cst(P.sectors + it.sector);
+    const DevCtrTuple ct = cst(P.ctrs + (sec.ctr0 + it.s));
+    const DevColTuple cl = cst(P.cols + (sec.col0 + it.j));
+    const int32_t e = it.e0 + (int32_t)threadIdx.x;
+    if (e >= ct.k * cl.n) continue;
+    const int32_t kd = e / cl.n, cb = e - kd * cl.n;
+    Cmp *dst = reinterpret_cast<Cmp *>(job.ws) + sec.bpack + (int64_t)(ct.ko + kd) * sec.N + cl.no + cb;
+    if (it.bblk < 0) {
+      *dst = Cmp(0);
+    } else {
+      const In *src = reinterpret_cast<const In *>(args.p[job.prob0 + sec.prob - job.plo].b);
+      const DevBBlock bb = cst(P.bblocks + it.bblk);
+      const DevProb pr = cst(P.probs + sec.prob);
+      *dst = Cmp(src[b_offset(bb, ct, cl, pr, kd, cb)]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// operand access: buffer resources or 64-bit pointers
+// ---------------------------------------------------------------------------
+// BUF = true: A and C are reached through buffer resources (scalar base,
+// 32-bit byte offsets; the hardware returns 0 for reads past num_records and
+// drops such writes).  Used when both buffers are below 2 GiB.  BUF = false:
+// plain 64-bit addresses, any size.
+typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+constexpr int kBufFlags = 0x00020000;  // raw buffer, gfx9-family descriptor word 3
+
+template <typename T> struct BufIo;
+template <> struct BufIo<double> {
+  __device__ static double ld(__amdgpu_buffer_rsrc_t r, int32_t byte) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte, 0, 0));
+  }
+  __device__ static void st(__amdgpu_buffer_rsrc_t r, int32_t byte, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, v), r, byte, 0, 0);
+  }
+};
+template <> struct BufIo<float> {
+  __device__ static float ld(__amdgpu_buffer_rsrc_t r, int32_t byte) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte, 0, 0));
+  }
+  __device__ static void st(__amdgpu_buffer_rsrc_t r, int32_t byte, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, byte, 0, 0);
+  }
+};
+
+template <typename T, bool BUF> struct Src;
+template <typename T> struct Src<T, true> {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ void init(const void *p, int64_t n) {
+    r = __builtin_amdgcn_make_buffer_rsrc(uniptr(const_cast<void *>(p)), (short)0, uni((int)(n * (int64_t)sizeof(T))),
+                                          kBufFlags);
+  }
+  __device__ T operator()(int32_t i) const { return BufIo<T>::ld(r, i * (int32_t)sizeof(T)); }
+};
+template <typename T> struct Src<T, false> {
+  const T *__restrict__ p;
+  __device__ void init(const void *q, int64_t) { p = reinterpret_cast<const T *>(q); }
+  __device__ T operator()(int64_t i) const { return p[i]; }
+};
+template <typename T, bool BUF> struct Dst;
+template <typename T> struct Dst<T, true> {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ void init(void *p, int64_t n) {
+    r = __builtin_amdgcn_make_buffer_rsrc(uniptr(p), (short)0, uni((int)(n * (int64_t)sizeof(T))), kBufFlags);
+  }
+  __device__ void put(int64_t i, T v) const { BufIo<T>::st(r, (int32_t)i * (int32_t)sizeof(T), v); }
+};
+template <typename T> struct Dst<T, false> {
+  T *__restrict__ p;
+  __device__ void init(void *q, int64_t) { p = reinterpret_cast<T *>(q); }
+  __device__ void put(int64_t i, T v) const { p[i] = v; }
+};
+
+// Tile context shared by every precision: the tile's row tuple and sector,
+// the problem's operands, and the lane's output columns.
+template <typename In, typename Out, bool BUF, int CB> struct TileCtx {
+  DevTile tile;
+  DevRowTuple rt;
+  DevSector sec;
+  Src<In, BUF> A, B;
+  Dst<Out, BUF> C;
+  const char *ws;
+  int64_t cbase[CB];        // output block offset of the lane's columns (-1: none)
+  int32_t cnj[CB], ccl[CB];
+  int cbn;
+};
+
+template <typename In, typename Out, bool BUF, int CB, bool COLS = true>
+__device__ __forceinline__ DevPlan tile_setup(const LaunchArgs &args, int t, int lane, TileCtx<In, Out, BUF, CB> &x) {
+  int jb = 0;
+  while (jb + 1 < args.njobs && t >= args.jobs[jb + 1].tile0) ++jb;
+  const JobArg &job = args.jobs[jb];
+  const DevPlan P = load_plan(job.plan);
+  x.tile = cst(P.tiles + (t - job.tile0 + job.ptile0));
+  x.rt = cst(P.rows + x.tile.rowtuple);
+  x.sec = cst(P.sectors + x.tile.sector);
+  const ProbPtrs pp = args.p[job.prob0 + x.sec.prob - job.plo];
+  const DevProb pr = cst(P.probs + x.sec.prob);
+  x.A.init(pp.a, pr.a_span);
+  x.B.init(pp.b, pr.b_span);
+  x.C.init(pp.c, pr.c_numel);
+  x.ws = job.ws;
+  x.cbn = (x.tile.ncols + 15) >> 4;
+  if (!COLS) return P;
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) {
+    const int lc = 16 * cb + (lane & 15);
+    x.cbase[cb] = -1;
+    x.cnj[cb] = 0;
+    x.ccl[cb] = 0;
+    if (lc < x.tile.ncols) {
+      const DevColMap cm = P.colmap[x.sec.cm0 + x.tile.n0 + lc];
+      x.cbase[cb] = P.cgrid[x.rt.cgrid + cm.j];
+      x.cnj[cb] = cm.nj;
+      x.ccl[cb] = cm.cl;
+    }
+  }
+  return P;
+}
+
+// ---------------------------------------------------------------------------
+// grouped gather GEMM (FP64 / FP32 MFMA, K = 4 per instruction)
+// ---------------------------------------------------------------------------
+template <typename Cmp> struct Mfma4;
+template <> struct Mfma4<double> {
+  typedef d4 acc_t;
+  __device__ static acc_t run(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  // accumulator element v of lane l holds row (l>>4) + 4v, column l&15
+  __device__ static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <> struct Mfma4<float> {
+  typedef f4 acc_t;
+  __device__ static acc_t run(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  // accumulator element v of lane l holds row 4(l>>4) + v, column l&15
+  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+// One wave tile: rows are processed in chunks of 16*RB; the tile's metadata
+// and output columns are set up once.  Within a chunk, KB k-steps of loads
+// are issued before the MFMAs that consume them.
+template <typename In, typename Cmp, typename Out, bool BUF, int RB, int CB, int KB>
+__global__ void __launch_bounds__(256) k_gemm4(LaunchArgs args) {
+  typedef typename std::conditional<BUF, int32_t, int64_t>::type Off;
+  typedef Mfma4<Cmp> M;
+  typedef typename M::acc_t acc_t;
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int W = gridDim.x * 4;
+  for (int t = gw; t < args.ntiles; t += W) {
+    TileCtx<In, Out, BUF, CB> x;
+    const DevPlan P = tile_setup<In, Out, BUF, CB>(args, t, lane, x);
+    const Cmp *__restrict__ Bp = reinterpret_cast<const Cmp *>(x.ws) + x.sec.bpack;
+    const int64_t *__restrict__ kofs = P.kofs + x.rt.kofs;
+    const DevKP *__restrict__ kp = P.kp + x.sec.kp0;
+    const int K = x.sec.K, N = x.sec.N;
+    for (int mc = 0; mc < x.tile.nrows; mc += 16 * RB) {
+      const int rows = min(16 * RB, x.tile.nrows - mc);
+      const int rbn = (rows + 15) >> 4;
+      int32_t rg[RB][kMaxAct];
+      bool rv[RB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const int lr = 16 * rb + (lane & 15);
+        rv[rb] = lr < rows;
+        a_rowparts(x.rt, x.sec.nact, x.tile.m0 + mc + lr, rg[rb]);
+      }
+      acc_t acc[RB][CB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = acc_t{0, 0, 0, 0};
+      // k metadata of the next batch is fetched while this batch's A loads fly
+      int64_t kon[KB];
+      DevKP pn[KB];
+#pragma unroll
+      for (int q = 0; q < KB; ++q) {
+        const int k = 4 * q + (lane >> 4);
+        kon[q] = k < K ? kofs[k] : -1;
+        pn[q] = k < K ? kp[k] : DevKP{};
+      }
+      for (int kk0 = 0; kk0 < K; kk0 += 4 * KB) {
+        Cmp av[KB][RB], bv[KB][CB];
+        int64_t ko[KB];
+        DevKP pc[KB];
+#pragma unroll
+        for (int q = 0; q < KB; ++q) {
+          ko[q] = kon[q];
+          pc[q] = pn[q];
+        }
+#pragma unroll
+        for (int q = 0; q < KB; ++q) {
+          const int k = kk0 + 4 * q + (lane >> 4);
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            av[q][rb] = (ko[q] >= 0 && rv[rb]) ? Cmp(x.A(a_offset_t<Off>(ko[q], pc[q].p, rg[rb]))) : Cmp(0);
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            const int c = x.tile.n0 + 16 * cb + (lane & 15);
+            bv[q][cb] = (k < K && c < N) ? Bp[(int64_t)k * N + c] : Cmp(0);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < KB; ++q) {
+          const int k = kk0 + 4 * KB + 4 * q + (lane >> 4);
+          kon[q] = k < K ? kofs[k] : -1;
+          pn[q] = k < K ? kp[k] : DevKP{};
+        }
+#pragma unroll
+        for (int q = 0; q < KB; ++q)
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            if (rb < rbn)
+#pragma unroll
+              for (int cb = 0; cb < CB; ++cb)
+                if (cb < x.cbn) acc[rb][cb] = M::run(av[q][rb], bv[q][cb], acc[rb][cb]);
+      }
+      // element (row, col) of C_X -> output block (i, j_col), row-major m_i x n_j
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        if (cb >= x.cbn || x.cbase[cb] < 0) continue;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          if (rb >= rbn) continue;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int lr = 16 * rb + M::row(lane, v);
+            if (lr < rows)
+              x.C.put(x.cbase[cb] + (int64_t)(x.tile.m0 + mc + lr) * x.cnj[cb] + x.ccl[cb], Out(acc[rb][cb][v]));
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tall-skinny sectors (K, N <= 64): one row of C_X per lane, VALU FMA
+// ---------------------------------------------------------------------------
+// HBM-bound shapes (tens of thousands of rows, K and N of a few tens): each
+// lane gathers its row of A_X (all K values at once, coalesced across the
+// wave's consecutive rows) and accumulates 16 columns at a time with B_X
+// values that are uniform across the wave, so the k offsets, P factors and
+// B_X come from scalar loads.  No padding of K or N.
+template <typename In, typename Cmp, typename Out, bool BUF, int KMAX>
+__global__ void __launch_bounds__(256) k_rows(LaunchArgs args) {
+  typedef typename std::conditional<BUF, int32_t, int64_t>::type Off;
+  __shared__ Cmp bs_all[4][KMAX][16];  // per wave: B_X rows 0..K-1, the 16 columns of one pass
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  Cmp (*bs)[16] = bs_all[wid];
+  const int gw = blockIdx.x * 4 + wid;  // wave-uniform
+  const int W = gridDim.x * 4;
+  for (int t = gw; t < args.ntiles; t += W) {
+    TileCtx<In, Out, BUF, 1> x;
+    const DevPlan P = tile_setup<In, Out, BUF, 1>(args, t, lane, x);
+    const Cmp *__restrict__ Bp = reinterpret_cast<const Cmp *>(x.ws) + x.sec.bpack;
+    const int64_t *kofs = P.kofs + x.rt.kofs;
+    const DevKP *kp = P.kp + x.sec.kp0;
+    const DevColMap *cmap = P.colmap + x.sec.cm0 + x.tile.n0;
+    const int64_t *cgrid = P.cgrid + x.rt.cgrid;
+    const int K = uni(x.sec.K), N = uni(x.sec.N), ncols = uni(x.tile.ncols), nrows = uni(x.tile.nrows);
+    for (int mc = 0; mc < nrows; mc += 64) {
+      const int lr = mc + lane;
+      const bool valid = lr < nrows;
+      const int32_t ra = x.tile.m0 + lr;
+      int32_t rg[kMaxAct];
+      a_rowparts(x.rt, x.sec.nact, ra, rg);
+      Cmp a[KMAX];
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        a[k] = Cmp(0);
+        if (k < K) {
+          const int64_t ko = cst(kofs + k);
+          const DevKP p = cst(kp + k);
+          if (valid && ko >= 0) a[k] = Cmp(x.A(a_offset_t<Off>(ko, p.p, rg)));
+        }
+      }
+      for (int cc = 0; cc < ncols; cc += 16) {
+        const int nc = min(16, ncols - cc);
+        // stage B_X[k][n0 + cc + c] (zero beyond K and the tile's columns)
+        for (int e = lane; e < KMAX * 16; e += 64) {
+          const int k = e >> 4, c = e & 15;
+          bs[k][c] = (k < K && c < nc) ? Bp[(int64_t)k * N + x.tile.n0 + cc + c] : Cmp(0);
+        }
+        wave_lds_sync();
+        Cmp acc[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc[c] = Cmp(0);
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+          if (k < K) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) acc[c] = fma(a[k], bs[k][c], acc[c]);
+          }
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          if (c < nc) {
+            const DevColMap cm = cst(cmap + cc + c);
+            const int64_t cbase = cst(cgrid + cm.j);
+            if (valid && cbase >= 0) x.C.put(cbase + (int64_t)ra * cm.nj + cm.cl, Out(acc[c]));
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// grouped gather GEMM, split-BF16 products on bf16 MFMA (K = 32 per instruction)
+// ---------------------------------------------------------------------------
+// x = hi + mid + lo with hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi - mid)
+// (round to nearest even).  NT = 3: hi*hi + hi*mid + mid*hi;  NT = 6 adds
+// mid*mid + hi*lo + lo*hi.  FP32 accumulation.
+template <int NT>
+__device__ __forceinline__ void split3(float x, __bf16 &h, __bf16 &m, __bf16 &l) {
+  const uint16_t hb = bf16_rne(x);
+  const float r = x - bf16_to_f(hb);
+  const uint16_t mb = bf16_rne(r);
+  uint16_t lb = 0;
+  if (NT > 3) lb = bf16_rne(r - bf16_to_f(mb));
+  h = __builtin_bit_cast(__bf16, hb);
+  m = __builtin_bit_cast(__bf16, mb);
+  l = __builtin_bit_cast(__bf16, lb);
+}
+
+template <typename In, typename Out, bool BUF, int RB, int CB, int NT>
+__global__ void __launch_bounds__(256) k_gemm_bf16(LaunchArgs args) {
+  typedef typename std::conditional<BUF, int32_t, int64_t>::type Off;
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int W = gridDim.x * 4;
+  for (int t = gw; t < args.ntiles; t += W) {
+    TileCtx<In, Out, BUF, CB> x;
+    const DevPlan P = tile_setup<In, Out, BUF, CB>(args, t, lane, x);
+    const float *__restrict__ Bp = reinterpret_cast<const float *>(x.ws) + x.sec.bpack;
+    const int64_t *__restrict__ kofs = P.kofs + x.rt.kofs;
+    const DevKP *__restrict__ kp = P.kp + x.sec.kp0;
+    const int K = x.sec.K, N = x.sec.N;
+    for (int mc = 0; mc < x.tile.nrows; mc += 16 * RB) {
+      const int rows = min(16 * RB, x.tile.nrows - mc);
+      const int rbn = (rows + 15) >> 4;
+      int32_t rg[RB][kMaxAct];
+      bool rv[RB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const int lr = 16 * rb + (lane & 15);
+        rv[rb] = lr < rows;
+        a_rowparts(x.rt, x.sec.nact, x.tile.m0 + mc + lr, rg[rb]);
+      }
+      f4 acc[RB][CB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = f4{0, 0, 0, 0};
+      for (int kk = 0; kk < K; kk += 32) {
+        bf8 ah[RB], am[RB], al[RB], bh[CB], bm[CB], bl[CB];
+        float av[8][RB], bv[8][CB];
+#pragma unroll
+        for (int e8 = 0; e8 < 8; ++e8) {  // this lane's 8 consecutive k
+          const int k = kk + 8 * (lane >> 4) + e8;
+          int64_t ko = -1;
+          DevKP p{};
+          if (k < K) {
+            ko = kofs[k];
+            p = kp[k];
+          }
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            av[e8][rb] = (ko >= 0 && rv[rb]) ? float(x.A(a_offset_t<Off>(ko, p.p, rg[rb]))) : 0.f;
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            const int c = x.tile.n0 + 16 * cb + (lane & 15);
+            bv[e8][cb] = (k < K && c < N) ? Bp[(int64_t)k * N + c] : 0.f;
+          }
+        }
+#pragma unroll
+        for (int e8 = 0; e8 < 8; ++e8) {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+            __bf16 h, m, l;
+            split3<NT>(av[e8][rb], h, m, l);
+            ah[rb][e8] = h;
+            am[rb][e8] = m;
+            al[rb][e8] = l;
+          }
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            __bf16 h, m, l;
+            split3<NT>(bv[e8][cb], h, m, l);
+            bh[cb][e8] = h;
+            bm[cb][e8] = m;
+            bl[cb][e8] = l;
+          }
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          if (rb >= rbn) continue;
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            if (cb >= x.cbn) continue;
+            f4 c = acc[rb][cb];
+            // small terms first, largest last
+            if (NT > 3) {
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[rb], bh[cb], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rb], bl[cb], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[rb], bm[cb], c, 0, 0, 0);
+            }
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[rb], bh[cb], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rb], bm[cb], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rb], bh[cb], c, 0, 0, 0);
+            acc[rb][cb] = c;
+          }
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        if (cb >= x.cbn || x.cbase[cb] < 0) continue;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          if (rb >= rbn) continue;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int lr = 16 * rb + 4 * (lane >> 4) + v;
+            if (lr < rows)
+              x.C.put(x.cbase[cb] + (int64_t)(x.tile.m0 + mc + lr) * x.cnj[cb] + x.ccl[cb], Out(acc[rb][cb][v]));
+          }
+        }
+      }
+    }
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// grouped gather GEMM with the tile's B columns resident in registers
+// ---------------------------------------------------------------------------
+// For sectors with K_X <= 4*KQ.  A wave loads, once per tile, the k offsets
+// and class factors of its k slots and the B_X values of its k slots and
+// columns (straight from B's blocks through the plan's per-sector offset
+// table, so no packed copy of B is needed), then walks the tile's rows in
+// chunks of 16*RB.  The A loads of chunk c+1 are issued before the MFMAs and
+// stores of chunk c, so every wave keeps a chunk of loads in flight while it
+// computes.  NA = free-leg classes supported (nact <= NA).
+template <typename In, typename Cmp, typename Off, bool BUF, int RB, int KQ, int NA>
+__device__ __forceinline__ void res_load_chunk(const Src<In, BUF> &A, const DevRowTuple &rt, int nact, int K,
+                                               int32_t row0, int rows, int lane, const Off (&ko)[KQ],
+                                               const int32_t (&pk)[KQ][NA], Cmp (&av)[KQ][RB]) {
+  int32_t rg[RB][NA];
+  bool rv[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    const int lr = 16 * rb + (lane & 15);
+    rv[rb] = lr < rows;
+    a_rowparts_fast<NA>(rt, nact, row0 + (rv[rb] ? lr : 0), rg[rb]);
+  }
+#pragma unroll
+  for (int q = 0; q < KQ; ++q)
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      av[q][rb] = Cmp(0);
+      if (4 * q < K && ko[q] >= 0 && rv[rb]) {
+        Off o = ko[q];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) o += (Off)pk[q][a] * (Off)rg[rb][a];
+        av[q][rb] = Cmp(A(o));
+      }
+    }
+}
+
+template <typename In, typename Cmp, typename Out, bool BUF, int RB, int CB, int KQ, int NA, bool DB, int OCC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) k_gemm_res(LaunchArgs args) {
+  typedef typename std::conditional<BUF, int32_t, int64_t>::type Off;
+  typedef Mfma4<Cmp> M;
+  typedef typename M::acc_t acc_t;
+  const int lane = threadIdx.x & 63;
+  const int kl = lane >> 4;
+  const int gw = blockIdx.x * 4 + uni(threadIdx.x >> 6);  // wave-uniform
+  const int W = gridDim.x * 4;
+  for (int t = gw; t < args.ntiles; t += W) {
+    TileCtx<In, Out, BUF, CB> x;
+    const DevPlan P = tile_setup<In, Out, BUF, CB>(args, t, lane, x);
+    const int K = uni(x.sec.K), N = uni(x.sec.N), nact = uni(x.sec.nact), nrows = uni(x.tile.nrows);
+    const int64_t *__restrict__ kofs = P.kofs + x.rt.kofs;
+    const DevKP *__restrict__ kp = P.kp + x.sec.kp0;
+    const int32_t *__restrict__ bofs = P.bofs + x.sec.bofs0;
+    Off ko[KQ];
+    int32_t pk[KQ][NA];
+    Cmp bv[KQ][CB];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+      const int k = 4 * q + kl;
+      ko[q] = -1;
+#pragma unroll
+      for (int a = 0; a < NA; ++a) pk[q][a] = 0;
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) bv[q][cb] = Cmp(0);
+      if (4 * q < K && k < K) {
+        ko[q] = (Off)kofs[k];
+        const DevKP p = kp[k];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) pk[q][a] = p.p[a];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+          const int c = x.tile.n0 + 16 * cb + (lane & 15);
+          if (c < N) {
+            const int32_t o = bofs[(int64_t)k * N + c];
+            if (o >= 0) bv[q][cb] = Cmp(x.B(o));
+          }
+        }
+      }
+    }
+    Cmp av[KQ][RB];
+    res_load_chunk<In, Cmp, Off, BUF, RB, KQ, NA>(x.A, x.rt, nact, K, x.tile.m0, min(16 * RB, nrows), lane, ko, pk, av);
+    for (int mc = 0; mc < nrows; mc += 16 * RB) {
+      const int rows = min(16 * RB, nrows - mc);
+      const int rbn = (rows + 15) >> 4;
+      Cmp an[KQ][RB];
+      if (DB && mc + 16 * RB < nrows)
+        res_load_chunk<In, Cmp, Off, BUF, RB, KQ, NA>(x.A, x.rt, nact, K, x.tile.m0 + mc + 16 * RB,
+                                                      min(16 * RB, nrows - mc - 16 * RB), lane, ko, pk, an);
+      acc_t acc[RB][CB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) {
+        if (4 * q < K) {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            if (rb < rbn)
+#pragma unroll
+              for (int cb = 0; cb < CB; ++cb)
+                if (cb < x.cbn) acc[rb][cb] = M::run(av[q][rb], bv[q][cb], acc[rb][cb]);
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        if (cb >= x.cbn || x.cbase[cb] < 0) continue;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          if (rb >= rbn) continue;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int lr = 16 * rb + M::row(lane, v);
+            if (lr < rows)
+              x.C.put(x.cbase[cb] + (int64_t)(x.tile.m0 + mc + lr) * x.cnj[cb] + x.ccl[cb], Out(acc[rb][cb][v]));
+          }
+        }
+      }
+      if (DB) {
+#pragma unroll
+        for (int q = 0; q < KQ; ++q)
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) av[q][rb] = an[q][rb];
+      } else if (mc + 16 * RB < nrows) {
+        res_load_chunk<In, Cmp, Off, BUF, RB, KQ, NA>(x.A, x.rt, nact, K, x.tile.m0 + mc + 16 * RB,
+                                                      min(16 * RB, nrows - mc - 16 * RB), lane, ko, pk, av);
+      }
+    }
+  }
+}
+
+}  // namespace yastn

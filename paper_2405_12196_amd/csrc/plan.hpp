@@ -44,6 +44,7 @@ struct DevProb {               // one problem of a plan
   int32_t pad;
   int64_t a_span;              // elements of A's buffer that blocks reach (max offset + size)
   int64_t c_numel;             // elements of C
+  int64_t b_span;              // elements of B's buffer that blocks reach
 };
 
 struct DevSector {             // one (problem, sector)
@@ -55,6 +56,7 @@ struct DevSector {             // one (problem, sector)
   int64_t bpack;               // element offset of packed B_X (K_X x N_X, row-major) in workspace
   int64_t kp0;                 // first of K_X entries in kp (P_a of each contracted index)
   int64_t cm0;                 // first of N_X entries in colmap
+  int64_t bofs0;               // first of K_X * N_X entries in bofs
 };
 
 struct DevRowTuple {           // one (problem, sector, A free tuple)
@@ -64,6 +66,8 @@ struct DevRowTuple {           // one (problem, sector, A free tuple)
   int64_t cgrid;               // first of Q entries in cgrid (C element offset or -1)
   int64_t kofs;                // first of K_X entries in kofs (A offset of (row 0, k), -1 absent)
   int32_t lsuf[kMaxAct + 1];   // Lsuf_a, a = 0..nact
+  uint32_t lmag[kMaxAct + 1];  // floor(r / Lsuf_a) = (r * lmag_a) >> lsh_a for 0 <= r < 2^31
+  int32_t lsh[kMaxAct + 1];
   int32_t fac[kMaxRank];       // FAc_c, contracted legs in axes order
 };
 
@@ -128,6 +132,7 @@ struct DevPlan {               // device-resident table of the plan's arrays
   const int64_t *kofs;         // per row tuple, per contracted index
   const DevKP *kp;             // per sector, per contracted index
   const DevColMap *colmap;     // per sector, per column
+  const int32_t *bofs;         // per sector, K_X x N_X row-major: element offset in B's buffer, -1 absent
   int32_t ntiles, nitems;
 };
 

@@ -57,7 +57,9 @@ struct PlanTables {
   std::vector<int64_t> kofs;
   std::vector<DevKP> kp;
   std::vector<DevColMap> colmap;
+  std::vector<int32_t> bofs;
   int64_t bpack_elems = 0;  // packed B elements in the workspace
+  bool bofs_overflow = false;  // some B offset does not fit in int32 (no direct B reads then)
 };
 
 // Problems are launched in groups of at most kMaxProbs (their device pointers
@@ -78,8 +80,9 @@ struct Plan {
   int rb = 4;               // row blocks (16 rows each) per chunk of a wave tile
   int nch = 1;              // chunks per wave tile
   bool buf_ok = true;       // every buffer small enough for 32-bit buffer addressing
-  bool rows_kernel = false; // heuristic choice (variant 0): one output row per lane instead of MFMA tiles
   bool rows_fit = false;    // every sector has K, N <= 64: the row-per-lane kernel can run
+  bool res_fit = false;     // every sector has K <= 64 and B offsets fit int32: k_gemm_res can run
+  int nact = 1;             // largest number of A free-leg classes over the plan's problems
   int variant = 0;          // kernel variant (0 = heuristic; set by yastn_plan_autotune)
   int kmax = 0;             // largest K_X of the plan
   void *dev_mem = nullptr;  // one device allocation holding every table

@@ -6,6 +6,7 @@
 // kernels element by element, with the kernels' guards, checking every read
 // and write against its buffer and that every output element is written
 // exactly once.  FP64 arithmetic, any summation order.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -90,6 +91,7 @@ void *emu_plan(const yastn_problem *probs, int nprob, int rb_override, int cb_ov
   d.kofs = pl.t.kofs.data();
   d.kp = pl.t.kp.data();
   d.colmap = pl.t.colmap.data();
+  d.bofs = pl.t.bofs.data();
   d.ntiles = (int32_t)pl.t.tiles.size();
   d.nitems = (int32_t)pl.t.items.size();
   return e;
@@ -141,6 +143,21 @@ int emu_contract(void *h, const double *const *a, const int64_t *alen, const dou
   }
   for (int64_t i = 0; i < pl.t.bpack_elems; ++i)
     if (packed[i] != 1) return fail("pack: packed B element not written");
+  // ---- direct B reads (k_gemm_res): the offset table must give the packed values
+  if ((int64_t)pl.t.bofs.size() != pl.t.bpack_elems) return fail("bofs: table size differs from packed B");
+  for (size_t si = 0; si < pl.t.sectors.size(); ++si) {
+    const DevSector &sec = P.sectors[si];
+    for (int64_t e = 0; e < (int64_t)sec.K * sec.N; ++e) {
+      const int32_t o = P.bofs[sec.bofs0 + e];
+      const double want = ws[sec.bpack + e];
+      if (o < 0) {
+        if (want != 0.0) return fail("bofs: absent entry where packed B is non-zero");
+        continue;
+      }
+      if (o >= blen[sec.prob]) return fail("bofs: B read out of bounds");
+      if (b[sec.prob][o] != want) return fail("bofs: offset table disagrees with packed B");
+    }
+  }
   // ---- k_gemm4: per tile, the lane's rows / columns / k as the kernel forms them
   std::vector<std::vector<char>> wrote(pl.probs.size());
   for (size_t p = 0; p < pl.probs.size(); ++p) wrote[p].assign(size_t(clen[p]) + 1, 0);
@@ -156,6 +173,14 @@ int emu_contract(void *h, const double *const *a, const int64_t *alen, const dou
     const DevKP *kp = P.kp + sec.kp0;
     if (rt.kofs + sec.K > (int64_t)pl.t.kofs.size() || sec.kp0 + sec.K > (int64_t)pl.t.kp.size())
       return fail("offset table overflow");
+    // the fast row split (multiply-high) must agree with the modulo form
+    for (int lr = 0; lr < tile.nrows; ++lr) {
+      int32_t r1[kMaxAct], r2[kMaxAct];
+      a_rowparts(rt, nact, tile.m0 + lr, r1);
+      a_rowparts_fast<kMaxAct>(rt, nact, tile.m0 + lr, r2);
+      for (int a = 0; a < kMaxAct; ++a)
+        if (r1[a] != r2[a]) return fail("fast row split disagrees with the modulo form");
+    }
     std::vector<double> acc(size_t(TM) * TN, 0.0);
     for (int k = 0; k < sec.K; ++k) {
       const int64_t ko = kofs[k];
@@ -175,6 +200,28 @@ int emu_contract(void *h, const double *const *a, const int64_t *alen, const dou
           if (col >= sec.N) continue;
           acc[size_t(lr) * TN + lc] += av * Bp[(int64_t)k * sec.N + col];
         }
+      }
+    }
+    // k_gemm_res epilogue: 16-row blocks, walked one column tuple piece at a
+    // time; every address it forms must be the one the per-element form gives
+    for (int r0 = 0; r0 < tile.nrows; r0 += 16) {
+      const int rrows = std::min(16, tile.nrows - r0);
+      for (int cc0 = 0; cc0 < tile.ncols;) {
+        const DevColMap cm = P.colmap[sec.cm0 + tile.n0 + cc0];
+        const int w = std::min(cm.nj - cm.cl, tile.ncols - cc0);
+        if (w < 1) return fail("res epilogue: empty column piece");
+        const int64_t cbase = P.cgrid[rt.cgrid + cm.j];
+        const float inv = 1.0f / (float)w;
+        for (int e = 0; e < rrows * w && cbase >= 0; ++e) {
+          const int r = (int)(((float)e + 0.5f) * inv);
+          const int cc = e - r * w;
+          if (r != e / w) return fail("res epilogue: float quotient inexact");
+          const DevColMap cmx = P.colmap[sec.cm0 + tile.n0 + cc0 + cc];
+          const int64_t want = P.cgrid[rt.cgrid + cmx.j] + (int64_t)(tile.m0 + r0 + r) * cmx.nj + cmx.cl;
+          const int64_t got = cbase + (int64_t)(tile.m0 + r0) * cm.nj + cm.cl + (int64_t)r * cm.nj + cc;
+          if (got != want) return fail("res epilogue: address differs from the per-element form");
+        }
+        cc0 += w;
       }
     }
     for (int lc = 0; lc < TN; ++lc) {

@@ -265,7 +265,7 @@ def test_norm_f64(n):
 
 
 # ------------------------------------------------------ kernel variants
-@pytest.mark.parametrize("variant", range(1, 8))
+@pytest.mark.parametrize("variant", range(1, 14))
 @pytest.mark.parametrize("seed", range(10))
 def test_every_variant_matches_oracle(seed, variant):
     import paper_2405_12196_amd as Y
@@ -277,7 +277,9 @@ def test_every_variant_matches_oracle(seed, variant):
     try:
         pl.set_variant(variant)
     except Y.YastnError as e:
-        assert e.status == "ERR_STATE" and variant == 7  # row kernel needs K, N <= 64
+        # the row kernel needs K, N <= 64 and the register-resident B kernels K <= 64
+        assert e.status == "ERR_STATE" and variant >= 7
+        assert max(pl.stats(0)["max_k"], pl.stats(0)["max_n"] if variant == 7 else 0) > 64
         return
     A, B = G.upload(a), G.upload(b)
     c, s = G.alloc_out(pl, 0)
@@ -301,3 +303,54 @@ def test_autotune_config2_step3_picks_a_correct_variant():
     pl.contract([A], [B], [c], ws)
     torch.cuda.synchronize()
     check_f64(s, c.cpu().numpy()[:s.numel], ref)
+
+
+# ------------------------------------------------------------ HIP graphs
+@pytest.mark.parametrize("kind", ["auto", "mfma"])
+def test_graph_replays_equal_eager_chain(kind):
+    """The config-2 chain (four contractions + FP64 norm) captured in one HIP
+    graph: every replay, with eager work and synchronisations between
+    replays, must reproduce the eager results bitwise."""
+    import paper_2405_12196_amd as Y
+    t = W.config2()
+    steps = [("C", "T1"), (None, "T4"), (None, "A"), (None, "Ac")]
+    plans, cur = [], None
+    for (an, bn), (ax, bx) in zip(steps, t["axes"]):
+        pl = Y.plan([(t[an] if an else cur, t[bn], ax, bx)], flags=FLAGS[kind])
+        plans.append(pl)
+        cur = pl.output(0)
+    inp = {k: G.upload(t[k]) for k in ("C", "T1", "T4", "A", "Ac")}
+    outs = [torch.full((max(1, pl.output(0).numel),), float("nan"), dtype=torch.float64, device=G.DEV) for pl in plans]
+    wss = [G.workspace(pl) for pl in plans]
+    nws = torch.empty(Y.norm_workspace_bytes(), dtype=torch.uint8, device=G.DEV)
+    nout = torch.zeros(2, dtype=torch.float64, device=G.DEV)
+    n_last = plans[-1].output(0).numel
+
+    def chain(st):
+        for i, ((an, bn), pl) in enumerate(zip(steps, plans)):
+            a = inp[an] if an else outs[i - 1]
+            pl.contract([a], [inp[bn]], [outs[i]], wss[i], stream=st)
+        Y.norm(outs[-1], n_last, nout, nws, stream=st)
+
+    chain(int(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    ref = [o.clone() for o in outs]
+    ref_norm = nout.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        chain(int(s.cuda_stream))
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(4):
+        for o in outs:
+            o.fill_(float("nan"))
+        nout.zero_()
+        junk = torch.randn(1 << 16, device=G.DEV, dtype=torch.float64).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, r in zip(outs, ref):
+            assert torch.equal(o, r), f"replay {rep} differs from the eager chain"
+        assert torch.equal(nout, ref_norm)
+        del junk
