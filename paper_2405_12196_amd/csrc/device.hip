@@ -288,7 +288,7 @@ yastn_status upload(Plan &pl) {
          o_aoff = take(bytes_of(t.aoff)), o_cgrid = take(bytes_of(t.cgrid)), o_bb = take(bytes_of(t.bblocks)),
          o_tiles = take(bytes_of(t.tiles)), o_items = take(bytes_of(t.items)), o_kofs = take(bytes_of(t.kofs)),
          o_kp = take(bytes_of(t.kp)), o_cm = take(bytes_of(t.colmap)), o_bofs = take(bytes_of(t.bofs)),
-         o_plan = take(sizeof(DevPlan));
+         o_recs = take(t.tiles.size() * sizeof(DevTileRec)), o_plan = take(sizeof(DevPlan));
   char *base;
   yastn_status s = dmalloc(&base, off);
   if (s) return s;
@@ -328,10 +328,15 @@ yastn_status upload(Plan &pl) {
   dp.kp = reinterpret_cast<const DevKP *>(base + o_kp);
   dp.colmap = reinterpret_cast<const DevColMap *>(base + o_cm);
   dp.bofs = reinterpret_cast<const int32_t *>(base + o_bofs);
+  dp.recs = reinterpret_cast<const DevTileRec *>(base + o_recs);
+  std::vector<DevTileRec> recs;
+  build_tile_records(pl, dp, recs);
+  put(o_recs, recs.data(), recs.size() * sizeof(DevTileRec));
   dp.ntiles = (int32_t)t.tiles.size();
   dp.nitems = (int32_t)t.items.size();
   put(o_plan, &dp, sizeof(dp));
   pl.dplan = reinterpret_cast<DevPlan *>(base + o_plan);
+  pl.drecs = dp.recs;
   YASTN_HIP(hipMemcpy(base, host.data(), off, hipMemcpyHostToDevice));
   return YASTN_OK;
 }
@@ -479,6 +484,7 @@ yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const
       if (np + n > kMaxProbs) break;
       JobArg &ja = la.jobs[la.njobs++];
       ja.plan = j.plan->dplan;
+      ja.recs = j.plan->drecs;
       ja.ws = reinterpret_cast<char *>(j.ws);
       ja.tile0 = la.ntiles;
       ja.item0 = la.nitems;

@@ -573,4 +573,37 @@ void finish_tiles(Plan &plan) {
   plan.ws_bytes = ((size_t(t.bpack_elems) * elem + 255) / 256) * 256;
 }
 
+void build_tile_records(const Plan &plan, const DevPlan &at, std::vector<DevTileRec> &recs) {
+  const PlanTables &t = plan.t;
+  recs.assign(t.tiles.size(), DevTileRec{});
+  for (size_t i = 0; i < t.tiles.size(); ++i) {
+    const DevTile &tl = t.tiles[i];
+    const DevRowTuple &rt = t.rows[tl.rowtuple];
+    const DevSector &sec = t.sectors[tl.sector];
+    const DevProb &pr = t.probs[sec.prob];
+    DevTileRec &r = recs[i];
+    r.kofs = at.kofs + rt.kofs;
+    r.kp = at.kp + sec.kp0;
+    r.bofs = at.bofs + sec.bofs0;
+    r.cmap = at.colmap + sec.cm0 + tl.n0;
+    r.cgrid = at.cgrid + rt.cgrid;
+    r.a_span = pr.a_span;
+    r.b_span = pr.b_span;
+    r.c_numel = pr.c_numel;
+    r.m0 = tl.m0;
+    r.nrows = tl.nrows;
+    r.n0 = tl.n0;
+    r.ncols = tl.ncols;
+    r.K = sec.K;
+    r.N = sec.N;
+    r.nact = sec.nact;
+    r.prob = sec.prob;
+    for (int a = 0; a < kRecAct; ++a) {
+      r.lsuf[a] = a + 1 <= sec.nact ? rt.lsuf[a + 1] : 1;
+      r.lsh[a] = a + 1 <= sec.nact ? rt.lsh[a + 1] : 31;
+      r.lmag[a] = a + 1 <= sec.nact ? rt.lmag[a + 1] : (1u << 31);
+    }
+  }
+}
+
 }  // namespace yastn

@@ -586,8 +586,54 @@ __device__ __forceinline__ void res_load_chunk(const Src<In, BUF> &A, const DevR
     }
 }
 
+// One tile's record and operands, read field by field with scalar loads.
+template <typename In, typename Out, bool BUF> struct RecCtx {
+  const int64_t *kofs;
+  const DevKP *kp;
+  const int32_t *bofs;
+  const DevColMap *cmap;
+  const int64_t *cgrid;
+  int32_t m0, nrows, n0, ncols, K, N, nact;
+  DevRowTuple rt;  // only lsuf / lmag / lsh of classes 1..kRecAct are filled
+  Src<In, BUF> A, B;
+  Dst<Out, BUF> C;
+};
+
+template <typename In, typename Out, bool BUF>
+__device__ __forceinline__ void rec_setup(const LaunchArgs &args, int t, RecCtx<In, Out, BUF> &x) {
+  int jb = 0;
+  while (jb + 1 < args.njobs && t >= args.jobs[jb + 1].tile0) ++jb;
+  const JobArg &job = args.jobs[jb];
+  const DevTileRec *r = cst(&job.recs) + (t - job.tile0 + job.ptile0);
+  x.kofs = cst(&r->kofs);
+  x.kp = cst(&r->kp);
+  x.bofs = cst(&r->bofs);
+  x.cmap = cst(&r->cmap);
+  x.cgrid = cst(&r->cgrid);
+  const int64_t a_span = cst(&r->a_span), b_span = cst(&r->b_span), c_numel = cst(&r->c_numel);
+  x.m0 = cst(&r->m0);
+  x.nrows = cst(&r->nrows);
+  x.n0 = cst(&r->n0);
+  x.ncols = cst(&r->ncols);
+  x.K = cst(&r->K);
+  x.N = cst(&r->N);
+  x.nact = cst(&r->nact);
+  const int32_t prob = cst(&r->prob);
+#pragma unroll
+  for (int a = 0; a < kRecAct; ++a) {
+    x.rt.lsuf[a + 1] = cst(&r->lsuf[a]);
+    x.rt.lmag[a + 1] = cst(&r->lmag[a]);
+    x.rt.lsh[a + 1] = cst(&r->lsh[a]);
+  }
+  const ProbPtrs pp = args.p[job.prob0 + prob - job.plo];
+  x.A.init(pp.a, a_span);
+  x.B.init(pp.b, b_span);
+  x.C.init(pp.c, c_numel);
+}
+
 template <typename In, typename Cmp, typename Out, bool BUF, int RB, int CB, int KQ, int NA, bool DB, int OCC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) k_gemm_res(LaunchArgs args) {
+  static_assert(NA <= kRecAct + 1, "tile records carry kRecAct class boundaries");
   typedef typename std::conditional<BUF, int32_t, int64_t>::type Off;
   typedef Mfma4<Cmp> M;
   typedef typename M::acc_t acc_t;
@@ -596,12 +642,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
   const int gw = blockIdx.x * 4 + uni(threadIdx.x >> 6);  // wave-uniform
   const int W = gridDim.x * 4;
   for (int t = gw; t < args.ntiles; t += W) {
-    TileCtx<In, Out, BUF, CB> x;
-    const DevPlan P = tile_setup<In, Out, BUF, CB>(args, t, lane, x);
-    const int K = uni(x.sec.K), N = uni(x.sec.N), nact = uni(x.sec.nact), nrows = uni(x.tile.nrows);
-    const int64_t *__restrict__ kofs = P.kofs + x.rt.kofs;
-    const DevKP *__restrict__ kp = P.kp + x.sec.kp0;
-    const int32_t *__restrict__ bofs = P.bofs + x.sec.bofs0;
+    RecCtx<In, Out, BUF> x;
+    rec_setup<In, Out, BUF>(args, t, x);
+    const int K = x.K, N = x.N, nact = x.nact, nrows = x.nrows;
+    const int cbn = (x.ncols + 15) >> 4;
+    // output columns of this lane (MFMA layout: lane & 15 within each 16-column block)
+    int64_t cbase[CB];
+    int32_t cnj[CB], ccl[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      const int lc = 16 * cb + (lane & 15);
+      cbase[cb] = -1;
+      cnj[cb] = 0;
+      ccl[cb] = 0;
+      if (lc < x.ncols) {
+        const DevColMap cm = x.cmap[lc];
+        cbase[cb] = x.cgrid[cm.j];
+        cnj[cb] = cm.nj;
+        ccl[cb] = cm.cl;
+      }
+    }
     Off ko[KQ];
     int32_t pk[KQ][NA];
     Cmp bv[KQ][CB];
@@ -614,28 +674,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) bv[q][cb] = Cmp(0);
       if (4 * q < K && k < K) {
-        ko[q] = (Off)kofs[k];
-        const DevKP p = kp[k];
+        ko[q] = (Off)x.kofs[k];
+        const DevKP p = x.kp[k];
 #pragma unroll
         for (int a = 0; a < NA; ++a) pk[q][a] = p.p[a];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
-          const int c = x.tile.n0 + 16 * cb + (lane & 15);
+          const int c = x.n0 + 16 * cb + (lane & 15);
           if (c < N) {
-            const int32_t o = bofs[(int64_t)k * N + c];
+            const int32_t o = x.bofs[(int64_t)k * N + c];
             if (o >= 0) bv[q][cb] = Cmp(x.B(o));
           }
         }
       }
     }
     Cmp av[KQ][RB];
-    res_load_chunk<In, Cmp, Off, BUF, RB, KQ, NA>(x.A, x.rt, nact, K, x.tile.m0, min(16 * RB, nrows), lane, ko, pk, av);
+    res_load_chunk<In, Cmp, Off, BUF, RB, KQ, NA>(x.A, x.rt, nact, K, x.m0, min(16 * RB, nrows), lane, ko, pk, av);
     for (int mc = 0; mc < nrows; mc += 16 * RB) {
       const int rows = min(16 * RB, nrows - mc);
       const int rbn = (rows + 15) >> 4;
       Cmp an[KQ][RB];
       if (DB && mc + 16 * RB < nrows)
-        res_load_chunk<In, Cmp, Off, BUF, RB, KQ, NA>(x.A, x.rt, nact, K, x.tile.m0 + mc + 16 * RB,
+        res_load_chunk<In, Cmp, Off, BUF, RB, KQ, NA>(x.A, x.rt, nact, K, x.m0 + mc + 16 * RB,
                                                       min(16 * RB, nrows - mc - 16 * RB), lane, ko, pk, an);
       acc_t acc[RB][CB];
 #pragma unroll
@@ -650,20 +710,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
             if (rb < rbn)
 #pragma unroll
               for (int cb = 0; cb < CB; ++cb)
-                if (cb < x.cbn) acc[rb][cb] = M::run(av[q][rb], bv[q][cb], acc[rb][cb]);
+                if (cb < cbn) acc[rb][cb] = M::run(av[q][rb], bv[q][cb], acc[rb][cb]);
         }
       }
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) {
-        if (cb >= x.cbn || x.cbase[cb] < 0) continue;
+        if (cb >= cbn || cbase[cb] < 0) continue;
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
           if (rb >= rbn) continue;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int lr = 16 * rb + M::row(lane, v);
-            if (lr < rows)
-              x.C.put(x.cbase[cb] + (int64_t)(x.tile.m0 + mc + lr) * x.cnj[cb] + x.ccl[cb], Out(acc[rb][cb][v]));
+            if (lr < rows) x.C.put(cbase[cb] + (int64_t)(x.m0 + mc + lr) * cnj[cb] + ccl[cb], Out(acc[rb][cb][v]));
           }
         }
       }
@@ -673,7 +732,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb) av[q][rb] = an[q][rb];
       } else if (mc + 16 * RB < nrows) {
-        res_load_chunk<In, Cmp, Off, BUF, RB, KQ, NA>(x.A, x.rt, nact, K, x.tile.m0 + mc + 16 * RB,
+        res_load_chunk<In, Cmp, Off, BUF, RB, KQ, NA>(x.A, x.rt, nact, K, x.m0 + mc + 16 * RB,
                                                       min(16 * RB, nrows - mc - 16 * RB), lane, ko, pk, av);
       }
     }

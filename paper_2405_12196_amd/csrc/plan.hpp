@@ -109,6 +109,26 @@ struct DevTile {               // one wave tile: rows [m0, m0 + nrows) of a row 
   int32_t ncols;               // columns (<= 16 * column blocks of the kernel)
 };
 
+// Everything one wave needs to start a tile, in one record of absolute
+// addresses read with a few scalar loads (no chain of dependent table reads).
+// Built at upload time, when the tables' device addresses are known.
+constexpr int kRecAct = 3;     // class boundaries a record carries (nact <= kRecAct + 1)
+struct DevTileRec {
+  const int64_t *kofs;         // the row tuple's A offsets of (row 0, k), K_X entries
+  const DevKP *kp;             // the sector's class factors, K_X entries
+  const int32_t *bofs;         // the sector's B offsets, K_X x N_X row-major
+  const DevColMap *cmap;       // the sector's column map, from column n0
+  const int64_t *cgrid;        // the row tuple's output block offsets, Q_X entries
+  int64_t a_span, b_span, c_numel;  // element bounds of the problem's buffers
+  int32_t m0, nrows, n0, ncols;
+  int32_t K, N, nact, prob;    // prob: plan-local problem index
+  int32_t lsuf[kRecAct];       // Lsuf_1 .. Lsuf_kRecAct of the row tuple
+  int32_t lsh[kRecAct];
+  uint32_t lmag[kRecAct];
+  int32_t pad[7];
+};
+static_assert(sizeof(DevTileRec) == 160, "tile record layout");
+
 struct DevPackItem {           // up to 256 elements of one (sector, s, j) sub-block of packed B_X
   int32_t sector;
   int32_t s, j;
@@ -133,6 +153,7 @@ struct DevPlan {               // device-resident table of the plan's arrays
   const DevKP *kp;             // per sector, per contracted index
   const DevColMap *colmap;     // per sector, per column
   const int32_t *bofs;         // per sector, K_X x N_X row-major: element offset in B's buffer, -1 absent
+  const DevTileRec *recs;      // per tile (same order as tiles)
   int32_t ntiles, nitems;
 };
 
@@ -143,6 +164,7 @@ struct ProbPtrs {
 
 struct JobArg {                // a range of one plan's problems inside a launch
   const DevPlan *plan;
+  const DevTileRec *recs;      // the plan's tile records (device)
   char *ws;                    // job workspace (packed B)
   int32_t tile0, item0;        // first launch-global tile / pack item of this job
   int32_t ptile0, pitem0;      // first plan-local tile / pack item of this job

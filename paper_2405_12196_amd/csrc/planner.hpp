@@ -87,6 +87,7 @@ struct Plan {
   int kmax = 0;             // largest K_X of the plan
   void *dev_mem = nullptr;  // one device allocation holding every table
   DevPlan *dplan = nullptr; // device copy of the table of pointers
+  const DevTileRec *drecs = nullptr;  // device tile records
   size_t ws_bytes = 0;
   int device = 0;
 };
@@ -101,5 +102,8 @@ void contracted_keys(const HostTensor &t, const int *axes, int nc, std::vector<i
 yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::pair<int32_t, int32_t>> &pairs,
                              int64_t a_base, int64_t b_base, PlanTables &t, int rb, int cb, int nch);
 void finish_tiles(Plan &plan);
+// Tile records with absolute addresses: `at` gives the address of each table
+// (device addresses for the GPU, host vector data for the CPU replay).
+void build_tile_records(const Plan &plan, const DevPlan &at, std::vector<DevTileRec> &recs);
 
 }  // namespace yastn

@@ -158,6 +158,8 @@ int emu_contract(void *h, const double *const *a, const int64_t *alen, const dou
       if (b[sec.prob][o] != want) return fail("bofs: offset table disagrees with packed B");
     }
   }
+  std::vector<DevTileRec> recs;
+  build_tile_records(pl, P, recs);
   // ---- k_gemm4: per tile, the lane's rows / columns / k as the kernel forms them
   std::vector<std::vector<char>> wrote(pl.probs.size());
   for (size_t p = 0; p < pl.probs.size(); ++p) wrote[p].assign(size_t(clen[p]) + 1, 0);
@@ -173,11 +175,25 @@ int emu_contract(void *h, const double *const *a, const int64_t *alen, const dou
     const DevKP *kp = P.kp + sec.kp0;
     if (rt.kofs + sec.K > (int64_t)pl.t.kofs.size() || sec.kp0 + sec.K > (int64_t)pl.t.kp.size())
       return fail("offset table overflow");
-    // the fast row split (multiply-high) must agree with the modulo form
+    // the tile record (what k_gemm_res reads) must describe this tile, and the
+    // fast row split (multiply-high, from the record) must agree with the modulo form
+    const DevTileRec &rec = recs[t];
+    if (rec.kofs != P.kofs + rt.kofs || rec.kp != P.kp + sec.kp0 || rec.bofs != P.bofs + sec.bofs0 ||
+        rec.cmap != P.colmap + sec.cm0 + tile.n0 || rec.cgrid != P.cgrid + rt.cgrid || rec.m0 != tile.m0 ||
+        rec.nrows != tile.nrows || rec.n0 != tile.n0 || rec.ncols != tile.ncols || rec.K != sec.K || rec.N != sec.N ||
+        rec.nact != nact || rec.prob != sec.prob || rec.a_span != P.probs[sec.prob].a_span ||
+        rec.b_span != P.probs[sec.prob].b_span || rec.c_numel != P.probs[sec.prob].c_numel)
+      return fail("tile record differs from the tables");
+    DevRowTuple fromrec{};
+    for (int a = 0; a < kRecAct; ++a) {
+      fromrec.lsuf[a + 1] = rec.lsuf[a];
+      fromrec.lmag[a + 1] = rec.lmag[a];
+      fromrec.lsh[a + 1] = rec.lsh[a];
+    }
     for (int lr = 0; lr < tile.nrows; ++lr) {
       int32_t r1[kMaxAct], r2[kMaxAct];
       a_rowparts(rt, nact, tile.m0 + lr, r1);
-      a_rowparts_fast<kMaxAct>(rt, nact, tile.m0 + lr, r2);
+      a_rowparts_fast<kMaxAct>(fromrec, nact, tile.m0 + lr, r2);
       for (int a = 0; a < kMaxAct; ++a)
         if (r1[a] != r2[a]) return fail("fast row split disagrees with the modulo form");
     }
