@@ -142,47 +142,54 @@ __global__ void __launch_bounds__(256) k_pack_b(LaunchArgs args) {
 typedef unsigned int u2v __attribute__((ext_vector_type(2)));
 constexpr int kBufFlags = 0x00020000;  // raw buffer, gfx9-family descriptor word 3
 
+// Cache policy of the streaming operands (A read once, C written once).  The
+// non-temporal hint (bit 1 of the buffer instructions' cache-policy operand)
+// would keep them from evicting the plan tables, but on gfx950 it makes these
+// kernels about 1.5x slower (the C stores are partial lines that the L2 no
+// longer merges), so the default policy is kept.
+constexpr int kStream = 0;
+
 template <typename T> struct BufIo;
 template <> struct BufIo<double> {
-  __device__ static double ld(__amdgpu_buffer_rsrc_t r, int32_t byte) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte, 0, 0));
+  template <int CP> __device__ static double ld(__amdgpu_buffer_rsrc_t r, int32_t byte) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte, 0, CP));
   }
-  __device__ static void st(__amdgpu_buffer_rsrc_t r, int32_t byte, double v) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, v), r, byte, 0, 0);
+  template <int CP> __device__ static void st(__amdgpu_buffer_rsrc_t r, int32_t byte, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, v), r, byte, 0, CP);
   }
 };
 template <> struct BufIo<float> {
-  __device__ static float ld(__amdgpu_buffer_rsrc_t r, int32_t byte) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte, 0, 0));
+  template <int CP> __device__ static float ld(__amdgpu_buffer_rsrc_t r, int32_t byte) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte, 0, CP));
   }
-  __device__ static void st(__amdgpu_buffer_rsrc_t r, int32_t byte, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, byte, 0, 0);
+  template <int CP> __device__ static void st(__amdgpu_buffer_rsrc_t r, int32_t byte, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, byte, 0, CP);
   }
 };
 
-template <typename T, bool BUF> struct Src;
-template <typename T> struct Src<T, true> {
+template <typename T, bool BUF, int CP = 0> struct Src;
+template <typename T, int CP> struct Src<T, true, CP> {
   __amdgpu_buffer_rsrc_t r;
   __device__ void init(const void *p, int64_t n) {
     r = __builtin_amdgcn_make_buffer_rsrc(uniptr(const_cast<void *>(p)), (short)0, uni((int)(n * (int64_t)sizeof(T))),
                                           kBufFlags);
   }
-  __device__ T operator()(int32_t i) const { return BufIo<T>::ld(r, i * (int32_t)sizeof(T)); }
+  __device__ T operator()(int32_t i) const { return BufIo<T>::template ld<CP>(r, i * (int32_t)sizeof(T)); }
 };
-template <typename T> struct Src<T, false> {
+template <typename T, int CP> struct Src<T, false, CP> {
   const T *__restrict__ p;
   __device__ void init(const void *q, int64_t) { p = reinterpret_cast<const T *>(q); }
   __device__ T operator()(int64_t i) const { return p[i]; }
 };
-template <typename T, bool BUF> struct Dst;
-template <typename T> struct Dst<T, true> {
+template <typename T, bool BUF, int CP = 0> struct Dst;
+template <typename T, int CP> struct Dst<T, true, CP> {
   __amdgpu_buffer_rsrc_t r;
   __device__ void init(void *p, int64_t n) {
     r = __builtin_amdgcn_make_buffer_rsrc(uniptr(p), (short)0, uni((int)(n * (int64_t)sizeof(T))), kBufFlags);
   }
-  __device__ void put(int64_t i, T v) const { BufIo<T>::st(r, (int32_t)i * (int32_t)sizeof(T), v); }
+  __device__ void put(int64_t i, T v) const { BufIo<T>::template st<CP>(r, (int32_t)i * (int32_t)sizeof(T), v); }
 };
-template <typename T> struct Dst<T, false> {
+template <typename T, int CP> struct Dst<T, false, CP> {
   T *__restrict__ p;
   __device__ void init(void *q, int64_t) { p = reinterpret_cast<T *>(q); }
   __device__ void put(int64_t i, T v) const { p[i] = v; }
@@ -561,7 +568,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(LaunchArgs args) {
 // stores of chunk c, so every wave keeps a chunk of loads in flight while it
 // computes.  NA = free-leg classes supported (nact <= NA).
 template <typename In, typename Cmp, typename Off, bool BUF, int RB, int KQ, int NA>
-__device__ __forceinline__ void res_load_chunk(const Src<In, BUF> &A, const DevRowTuple &rt, int nact, int K,
+__device__ __forceinline__ void res_load_chunk(const Src<In, BUF, kStream> &A, const DevRowTuple &rt, int nact, int K,
                                                int32_t row0, int rows, int lane, const Off (&ko)[KQ],
                                                const int32_t (&pk)[KQ][NA], Cmp (&av)[KQ][RB]) {
   int32_t rg[RB][NA];
@@ -595,8 +602,9 @@ template <typename In, typename Out, bool BUF> struct RecCtx {
   const int64_t *cgrid;
   int32_t m0, nrows, n0, ncols, K, N, nact;
   DevRowTuple rt;  // only lsuf / lmag / lsh of classes 1..kRecAct are filled
-  Src<In, BUF> A, B;
-  Dst<Out, BUF> C;
+  Src<In, BUF, kStream> A;
+  Src<In, BUF> B;
+  Dst<Out, BUF, kStream> C;
 };
 
 template <typename In, typename Out, bool BUF>
