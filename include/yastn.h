@@ -139,6 +139,10 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
 yastn_status yastn_plan_output(yastn_plan_t plan, int32_t prob, yastn_tensor_desc *c,
                                int64_t *c_numel);
 
+/* Options the plan was built with and its number of problems (either output
+ * may be NULL). */
+yastn_status yastn_plan_info(yastn_plan_t plan, yastn_options *opts, int32_t *nprob);
+
 /* Device workspace yastn_contract needs, in bytes (may be 0). */
 yastn_status yastn_plan_workspace(yastn_plan_t plan, size_t *bytes);
 
@@ -198,6 +202,63 @@ typedef struct {
  * All plans must share precision and dtypes (else YASTN_ERR_STATE).  Each
  * job's results are bitwise equal to running it alone with yastn_contract. */
 yastn_status yastn_contract_jobs(const yastn_job *jobs, int32_t njobs, void *hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of contraction requests from many concurrent
+ * CTM runs.  A request is a chain of up to YASTN_MAX_CHAIN contractions of
+ * resident tensors (an enlarged-corner step: C.T, .T, .A, .A*), step i > 0
+ * taking step i-1's output as its A operand.  The server admits queued
+ * requests in arrival order while its device memory pool (one allocation made
+ * by yastn_server_create; serving never calls hipMalloc) can hold their
+ * intermediate outputs and workspaces; each yastn_server_step merges the next
+ * step of every admitted request into one grouped launch (yastn_contract_jobs)
+ * on the server's stream, so requests that arrive while others run join the
+ * next launch; a request completes when the event after the launch holding
+ * its last step has completed, and its pool memory is reused.  Every result is
+ * bitwise the one yastn_contract gives alone (deterministic kernels).  Not
+ * thread-safe: one host thread drives a server.
+ * ------------------------------------------------------------------------- */
+#define YASTN_MAX_CHAIN 8
+enum { YASTN_REQ_QUEUED = 0, YASTN_REQ_RUNNING = 1, YASTN_REQ_DONE = 2 };
+
+typedef struct {
+  int32_t nsteps;              /* contractions in the chain, 1..YASTN_MAX_CHAIN                   */
+  const yastn_plan_t *plans;   /* [host, nsteps] single-problem plans                             */
+  const void *a0;              /* [device] A operand of step 0 (resident, caller-owned)           */
+  const void *const *b;        /* [host, nsteps] [device] B operand of each step (resident)       */
+  void *out;                   /* [device] output of the last step (caller-owned, c_numel elements) */
+} yastn_request;
+
+typedef struct {
+  int64_t submitted, admitted, completed;  /* requests                                          */
+  int64_t ticks, launched_steps, max_batch; /* grouped launches, steps launched, most per launch */
+  int64_t queued, running;                  /* requests waiting for memory / admitted, now       */
+  size_t pool_bytes, pool_used, pool_peak;  /* device pool                                       */
+} yastn_server_stats;
+
+typedef struct yastn_server_s *yastn_server_t;
+
+/* pool_bytes of device memory for intermediates and workspaces (the HBM
+ * budget); at most max_ahead (1..64) launches outstanding before a step waits
+ * for the oldest; hip_stream: the server's stream. */
+yastn_status yastn_server_create(size_t pool_bytes, int32_t max_ahead, void *hip_stream, yastn_server_t *out);
+/* Queue a request (the arrays are read during the call); *id identifies it.
+ * YASTN_ERR_NOMEM if its footprint exceeds the pool. */
+yastn_status yastn_server_submit(yastn_server_t s, const yastn_request *rq, int64_t *id);
+/* One scheduler tick: retire finished launches, admit queued requests, launch
+ * the next step of every admitted request (one grouped launch per precision);
+ * *launched (may be NULL) = steps launched. */
+yastn_status yastn_server_step(yastn_server_t s, int32_t *launched);
+/* State of request id (YASTN_REQ_*) and, once done, its latency from submit to
+ * the host observing completion, in ms (else -1). */
+yastn_status yastn_server_query(yastn_server_t s, int64_t id, int32_t *state, double *latency_ms);
+/* Drop a finished request's record. */
+yastn_status yastn_server_forget(yastn_server_t s, int64_t id);
+/* Run ticks until every submitted request is done. */
+yastn_status yastn_server_drain(yastn_server_t s);
+yastn_status yastn_server_get_stats(yastn_server_t s, yastn_server_stats *out);
+/* Waits for outstanding launches, frees the pool.  NULL is ignored. */
+void yastn_server_destroy(yastn_server_t s);
 
 /* FP64 Frobenius norm and max |x| of a [device] buffer of n elements
  * (dtype), written as out[0] = ||x||_F, out[1] = max|x| ([device], FP64).

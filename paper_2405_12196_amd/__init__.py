@@ -31,10 +31,14 @@ PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3, "bf16x6": BF16X6}
 STATUS = ["OK", "ERR_ARG", "ERR_SYM", "ERR_CHARGE", "ERR_SIGNATURE", "ERR_SHAPE",
           "ERR_DUPLICATE", "ERR_NOMEM", "ERR_HIP", "ERR_STATE"]
 
-EXPORTS = ["yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats",
+EXPORTS = ["yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats", "yastn_plan_info",
            "yastn_contract", "yastn_contract_timed", "yastn_contract_jobs", "yastn_norm_workspace", "yastn_norm",
            "yastn_free", "yastn_last_error", "yastn_status_string", "yastn_abi_version",
-           "yastn_plan_autotune", "yastn_plan_set_variant"]
+           "yastn_plan_autotune", "yastn_plan_set_variant",
+           "yastn_server_create", "yastn_server_submit", "yastn_server_step", "yastn_server_query",
+           "yastn_server_forget", "yastn_server_drain", "yastn_server_get_stats", "yastn_server_destroy"]
+REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
+MAX_CHAIN = 8
 NUM_VARIANTS = 14
 
 
@@ -72,6 +76,20 @@ class Stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Request(C.Structure):
+    _fields_ = [("nsteps", C.c_int32), ("plans", C.POINTER(C.c_void_p)), ("a0", C.c_void_p),
+                ("b", C.POINTER(C.c_void_p)), ("out", C.c_void_p)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("submitted", "admitted", "completed", "ticks", "launched_steps",
+                                         "max_batch", "queued", "running")] + \
+               [(n, C.c_size_t) for n in ("pool_bytes", "pool_used", "pool_peak")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Job(C.Structure):
     _fields_ = [("plan", C.c_void_p), ("a", C.POINTER(C.c_void_p)), ("b", C.POINTER(C.c_void_p)),
                 ("c", C.POINTER(C.c_void_p)), ("workspace", C.c_void_p)]
@@ -102,6 +120,16 @@ def lib():
                                           C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p, C.c_int32,
                                           C.POINTER(C.c_int32), C.POINTER(C.c_float)]
         L.yastn_plan_set_variant.argtypes = [C.c_void_p, C.c_int32]
+        L.yastn_plan_info.argtypes = [C.c_void_p, C.POINTER(Options), C.POINTER(C.c_int32)]
+        L.yastn_server_create.argtypes = [C.c_size_t, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
+        L.yastn_server_submit.argtypes = [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_int64)]
+        L.yastn_server_step.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
+        L.yastn_server_query.argtypes = [C.c_void_p, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+        L.yastn_server_forget.argtypes = [C.c_void_p, C.c_int64]
+        L.yastn_server_drain.argtypes = [C.c_void_p]
+        L.yastn_server_get_stats.argtypes = [C.c_void_p, C.POINTER(ServerStats)]
+        L.yastn_server_destroy.argtypes = [C.c_void_p]
+        L.yastn_server_destroy.restype = None
         L.yastn_norm_workspace.restype = C.c_size_t
         L.yastn_norm.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
         L.yastn_free.argtypes = [C.c_void_p]
@@ -111,7 +139,9 @@ def lib():
         L.yastn_status_string.argtypes = [C.c_int32]
         for f in ("yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats",
                   "yastn_contract", "yastn_contract_timed", "yastn_contract_jobs", "yastn_norm",
-                  "yastn_plan_autotune", "yastn_plan_set_variant"):
+                  "yastn_plan_autotune", "yastn_plan_set_variant", "yastn_plan_info", "yastn_server_create",
+                  "yastn_server_submit", "yastn_server_step", "yastn_server_query", "yastn_server_forget",
+                  "yastn_server_drain", "yastn_server_get_stats"):
             getattr(L, f).restype = C.c_int32
         _LIB = L
     return _LIB
@@ -337,3 +367,54 @@ def norm(x, n: int, out, workspace, dtype=DTYPE_F64, stream=None):
     """out[0] = ||x[:n]||_F, out[1] = max |x[:n]| (FP64, on the device)."""
     _check(lib().yastn_norm(C.c_void_p(_ptr(x)), int(n), int(dtype), C.c_void_p(_ptr(out)),
                             C.c_void_p(_ptr(workspace)), C.c_void_p(_stream(stream))))
+
+
+class Server:
+    """Continuous-batching request loop (yastn_server_*).  A request is a chain
+    of single-problem plans over resident device tensors; see include/yastn.h."""
+
+    def __init__(self, pool_bytes: int, max_ahead: int = 2, stream=None):
+        h = C.c_void_p()
+        _check(lib().yastn_server_create(int(pool_bytes), int(max_ahead), C.c_void_p(_stream(stream)), C.byref(h)))
+        self._h = h
+
+    def submit(self, plans, a0, bs, out) -> int:
+        n = len(plans)
+        pl = (C.c_void_p * n)(*[p.handle.value for p in plans])
+        pb = (C.c_void_p * n)(*[_ptr(b) for b in bs])
+        rq = Request(n, C.cast(pl, C.POINTER(C.c_void_p)), _ptr(a0), C.cast(pb, C.POINTER(C.c_void_p)), _ptr(out))
+        rid = C.c_int64()
+        _check(lib().yastn_server_submit(self._h, C.byref(rq), C.byref(rid)))
+        return int(rid.value)
+
+    def step(self) -> int:
+        n = C.c_int32()
+        _check(lib().yastn_server_step(self._h, C.byref(n)))
+        return int(n.value)
+
+    def query(self, rid: int):
+        st, lat = C.c_int32(), C.c_double()
+        _check(lib().yastn_server_query(self._h, int(rid), C.byref(st), C.byref(lat)))
+        return int(st.value), float(lat.value)
+
+    def forget(self, rid: int):
+        _check(lib().yastn_server_forget(self._h, int(rid)))
+
+    def drain(self):
+        _check(lib().yastn_server_drain(self._h))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().yastn_server_get_stats(self._h, C.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().yastn_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

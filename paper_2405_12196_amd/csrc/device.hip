@@ -707,6 +707,13 @@ yastn_status yastn_plan_output(yastn_plan_t plan, int32_t prob, yastn_tensor_des
   return YASTN_OK;
 }
 
+yastn_status yastn_plan_info(yastn_plan_t plan, yastn_options *opts, int32_t *nprob) {
+  if (!plan) return set_error(YASTN_ERR_ARG, "null plan");
+  if (opts) *opts = plan->p.opts;
+  if (nprob) *nprob = (int32_t)plan->p.probs.size();
+  return YASTN_OK;
+}
+
 yastn_status yastn_plan_workspace(yastn_plan_t plan, size_t *bytes) {
   if (!plan || !bytes) return set_error(YASTN_ERR_ARG, "null argument");
   *bytes = plan->p.ws_bytes;
