@@ -193,6 +193,234 @@ class PlainStep:
         c_ext.index_copy_(0, self.sC, self.pc)                # unfuse: scatter into C's blocks
 
 
+# ------------------------------------------------------------ chained step
+class Chain:
+    """The four chained contractions of an enlarged-corner step plus the FP64
+    norm of the last output, with resident buffers and plans built (and
+    autotuned) once.  Reduced precisions keep FP32 buffers between steps and
+    write the last output (the truncation input) in FP64."""
+
+    def __init__(self, torch, Y, t, prec="f64", tile_rows=0, tune=True, sp=0):
+        self.torch, self.Y, self.sp = torch, Y, sp
+        f64 = prec == "f64"
+        dt = lambda d: torch.float64 if d == Y.DTYPE_F64 else torch.float32
+        self.plans, cur = [], None
+        tp0 = time.perf_counter()
+        for i, ((an, bn), (ax, bx)) in enumerate(zip(STEPS, t["axes"])):
+            out_dt = Y.DTYPE_F64 if (f64 or i == len(STEPS) - 1) else Y.DTYPE_F32
+            pl = Y.plan([(t[an] if an else cur, t[bn], ax, bx)], precision=prec, stream=sp, tile_rows=tile_rows,
+                        in_dtype=Y.DTYPE_F64 if f64 else Y.DTYPE_F32, out_dtype=out_dt)
+            self.plans.append(pl)
+            cur = pl.output(0)
+        torch.cuda.synchronize()
+        self.plan_ms = (time.perf_counter() - tp0) * 1e3
+        self.stats = [pl.stats(0) for pl in self.plans]
+        self.useful = sum(st["useful_flops"] for st in self.stats)
+        in_dt = torch.float64 if f64 else torch.float32
+        up = lambda x: torch.from_numpy(np.ascontiguousarray(x.data)).to("cuda:0").to(in_dt)
+        self.inp = {k: up(t[k]) for k in ("C", "T1", "T4", "A", "Ac")}
+        self.outs = [torch.empty(max(1, pl.output(0).numel), dtype=dt(pl.out_dtype), device="cuda:0")
+                     for pl in self.plans]
+        self.wss = [torch.empty(max(256, pl.workspace_bytes), dtype=torch.uint8, device="cuda:0") for pl in self.plans]
+        self.nws = torch.empty(Y.norm_workspace_bytes(), dtype=torch.uint8, device="cuda:0")
+        self.nout = torch.zeros(2, dtype=torch.float64, device="cuda:0")
+        self.n_last = self.plans[-1].output(0).numel
+        self.ops = [(self.inp[an] if an else self.outs[i - 1], self.inp[bn], self.outs[i], self.wss[i])
+                    for i, (an, bn) in enumerate(STEPS)]
+        self.tuned = []
+        if tune:
+            for i, (pl, (a, b, c, w)) in enumerate(zip(self.plans, self.ops)):
+                v, times = pl.autotune([a], [b], [c], w, reps=5, stream=sp)
+                self.tuned.append({"step": i + 1, "variant": v, "ms": [round(x, 4) for x in times]})
+            torch.cuda.synchronize()
+
+    def step(self, st):
+        for pl, (a, b, c, w) in zip(self.plans, self.ops):
+            pl.contract([a], [b], [c], w, stream=st)
+        self.Y.norm(self.outs[-1], self.n_last, self.nout, self.nws, dtype=self.plans[-1].out_dtype, stream=st)
+
+    def timed(self, ev, K, warmup=3):
+        """ms per step over K steps, eager and graph-replayed; the faster wins."""
+        torch = self.torch
+        for _ in range(warmup):
+            self.step(self.sp)
+        torch.cuda.synchronize()
+        ref = self.outs[-1][:self.n_last].clone()
+        graph, err = capture(torch, self.step)
+
+        def run(fn):
+            evs = [(ev.new(), ev.new()) for _ in range(K)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(K):
+                ev.record(evs[k][0], self.sp)
+                fn()
+                ev.record(evs[k][1], self.sp)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) * 1e3 / K, np.array([ev.ms(a, b) for a, b in evs])
+
+        modes = {"eager": run(lambda: self.step(self.sp))}
+        if graph is not None:
+            modes["graph"] = run(graph.replay)
+            del graph
+        assert torch.equal(self.outs[-1][:self.n_last], ref), "timed steps changed the result"
+        mode = min(modes, key=lambda m: modes[m][0])
+        return modes[mode][0], modes[mode][1], mode, {m: round(v[0], 5) for m, v in modes.items()}, err
+
+
+def rel_err(torch, got, ref):
+    d = got.to(torch.float64) - ref.to(torch.float64)
+    return float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(ref.to(torch.float64)))
+
+
+# ------------------------------------------------------- other workloads
+FP32_MFMA_PEAK_TFS = 157.3     # MI355X dense FP32 matrix
+
+
+def graph_time(torch, ev, sp, fn, R=10, REP=5):
+    """ms per call of fn(stream), from HIP events around REP replays of a
+    graph of R calls (eager calls if capture fails)."""
+    def rep(st):
+        for _ in range(R):
+            fn(st)
+    rep(sp)
+    torch.cuda.synchronize()
+    g, _ = capture(torch, rep)
+    e0, e1 = ev.new(), ev.new()
+    torch.cuda.synchronize()
+    ev.record(e0, sp)
+    for _ in range(REP):
+        g.replay() if g is not None else rep(sp)
+    ev.record(e1, sp)
+    torch.cuda.synchronize()
+    return ev.ms(e0, e1) / (R * REP)
+
+
+def precision_section(torch, Y, W, ev, sp, K, plain_value):
+    """FP64 / FP32 / split-BF16 x3 / x6 chains on the corner step at chi = 128
+    and at chi = 256, D = 10: throughput and relative Frobenius error of each
+    step's output against the FP64 path (which the tests hold to the CPU
+    oracle within 1e-12)."""
+    out = {}
+    for name, t in (("chi128_D8", W.config2()), ("chi256_D10", W.config4())):
+        ref, rows = None, {}
+        for prec in ("f64", "f32", "bf16x3", "bf16x6"):
+            ch = Chain(torch, Y, t, prec=prec, sp=sp)
+            ms, lat, mode, _, _ = ch.timed(ev, K)
+            val = ch.useful / (ms * 1e-3) / 1e12
+            row = {"ms_per_step": round(ms, 4), "useful_TFs": round(val, 3), "timing": mode,
+                   "p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4)}
+            if prec == "f64":
+                ref = [o.clone() for o in ch.outs]
+            else:
+                row["rel_err_per_step"] = [float("%.3e" % rel_err(torch, o[:r.numel()], r)) for o, r in zip(ch.outs, ref)]
+                row["norm_rel_err"] = float("%.3e" % abs(float(ch.nout[0]) / float(torch.linalg.vector_norm(ref[-1])) - 1))
+            if plain_value and name == "chi128_D8":
+                row["vs_plain_per_sector_f64"] = round(val / plain_value, 2)
+            rows[prec] = row
+            del ch
+            torch.cuda.empty_cache()
+        out[name] = rows
+    return out
+
+
+def batch_section(torch, Y, W, ev, sp):
+    """Config-1 batches (N copies of the U(1) rank-4 tensordot, D = 18) and the
+    64 independent U(1) problems of uneven D in grouped launches."""
+    res = {}
+    cases = [("cfg1_x64", W.config1(64), "f64"), ("cfg1_x512", W.config1(512), "f64"),
+             ("cfg3_64probs", W.config3(), "f64"), ("cfg3_64probs_f32", W.config3(), "f32")]
+    for name, probs, prec in cases:
+        f64 = prec == "f64"
+        dt = torch.float64 if f64 else torch.float32
+        pl = Y.plan([(p.a, p.b, p.axes_a, p.axes_b) for p in probs], precision=prec, stream=sp)
+        A = [torch.from_numpy(p.a.data).to("cuda:0").to(dt) for p in probs]
+        B = [torch.from_numpy(p.b.data).to("cuda:0").to(dt) for p in probs]
+        C = [torch.empty(max(1, pl.output(i).numel), dtype=dt, device="cuda:0") for i in range(len(probs))]
+        ws = torch.empty(max(256, pl.workspace_bytes), dtype=torch.uint8, device="cuda:0")
+        if len(probs) <= 64:
+            pl.autotune(A, B, C, ws, reps=3, stream=sp)
+        st = [pl.stats(i) for i in range(len(probs))]
+        useful = sum(x["useful_flops"] for x in st)
+        byts = sum(x["alg_bytes"] for x in st)
+        ms = graph_time(torch, ev, sp, lambda s_: pl.contract(A, B, C, ws, stream=s_))
+        tf = useful / (ms * 1e-3) / 1e12
+        peak = FP64_MFMA_PEAK_TFS if f64 else FP32_MFMA_PEAK_TFS
+        res[name] = {"problems": len(probs), "precision": prec, "us_per_launch": round(ms * 1e3, 2),
+                     "useful_TFs": round(tf, 3), "frac_of_mfma_peak": round(tf / peak, 4),
+                     "achieved_GBs": round(byts / (ms * 1e-3) / 1e9, 1), "useful_flop": int(useful),
+                     "alg_bytes": int(byts), "launch_groups": (len(probs) + 63) // 64,
+                     "variant": pl.variant_id, "inputs": "resident, warm (repeated launches)"}
+        del pl, A, B, C, ws
+        torch.cuda.empty_cache()
+    return res
+
+
+def serving_section(torch, Y, W, sp, nreq=64, budget_gib=32, seed=5):
+    """32 concurrent CTM runs (16 Z2, 16 U(1); D in {4,6,8,10} x chi in
+    {64,128,192,256}) submit enlarged-corner requests with Poisson arrivals to
+    the continuous-batching server (HBM budget for intermediates); the rate is
+    0.7x the closed-loop saturation rate of a calibration pass."""
+    runs = []
+    for r in range(32):
+        t = W.serving_run(r)
+        plans, cur = [], None
+        for (an, bn), (ax, bx) in zip(STEPS, t["axes"]):
+            pl = Y.plan([(t[an] if an else cur, t[bn], ax, bx)], stream=sp)
+            plans.append(pl)
+            cur = pl.output(0)
+        inp = {k: torch.from_numpy(t[k].data).to("cuda:0") for k in ("C", "T1", "T4", "A", "Ac")}
+        out = torch.empty(max(1, plans[-1].output(0).numel), dtype=torch.float64, device="cuda:0")
+        flops = sum(pl.stats(0)["useful_flops"] for pl in plans)
+        runs.append({"plans": plans, "inp": inp, "out": out, "flops": flops, "name": t["name"]})
+    srv = Y.Server(pool_bytes=budget_gib << 30, max_ahead=2, stream=sp)
+
+    def submit(i):
+        r = runs[i]
+        return srv.submit(r["plans"], r["inp"]["C"], [r["inp"][bn] for _, bn in STEPS], r["out"])
+
+    # calibration: one request of every run, closed loop (all submitted at once)
+    for i in range(32):
+        submit(i)
+    srv.drain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(32):
+        submit(i)
+    srv.drain()
+    torch.cuda.synchronize()
+    sat = 32 / (time.perf_counter() - t0)           # requests per second
+    lam = 0.7 * sat
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=nreq))
+    which = rng.integers(0, 32, size=nreq)
+    ids, flop = [], 0.0
+    torch.cuda.synchronize()
+    base = time.perf_counter()
+    k = 0
+    while k < nreq or srv.stats()["completed"] < srv.stats()["submitted"]:
+        now = time.perf_counter() - base
+        while k < nreq and arrivals[k] <= now:
+            ids.append(submit(int(which[k])))
+            flop += runs[int(which[k])]["flops"]
+            k += 1
+        srv.step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - base
+    lat = np.array([srv.query(i)[1] for i in ids])
+    st = srv.stats()
+    srv.close()
+    del runs
+    torch.cuda.empty_cache()
+    return {"requests": nreq, "runs": 32, "arrival_rate_per_s": round(lam, 2),
+            "saturation_rate_per_s": round(sat, 2), "hbm_budget_GiB": budget_gib,
+            "useful_TFs": round(flop / wall / 1e12, 3), "wall_s": round(wall, 3),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "max_steps_per_launch": int(st["max_batch"]), "launches": int(st["ticks"]),
+            "pool_peak_GiB": round(st["pool_peak"] / 2 ** 30, 2),
+            "latency": "submit to the host observing the completion event"}
+
+
 # --------------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser()
@@ -205,6 +433,9 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=2)
     ap.add_argument("--tile-rows", type=int, default=0, help="rows per wave tile: 64, 128, 256, 512 or 0 (plan's choice)")
     ap.add_argument("--no-tune", action="store_true", help="skip the kernel-variant autotuner")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the precision sweep, the batched configs and the serving loop")
+    ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -419,6 +650,15 @@ def main():
                "sample": f"{args.cpu_reps} full enlarged-corner steps (4 block-pair tensordots + norm), "
                          f"{csec:.1f} s, BLAS limited to 1 thread; host has {os.cpu_count()} CPUs"}
 
+    # ---- the other workloads (not the headline value)
+    extras = None
+    if not args.no_extras:
+        del graph
+        torch.cuda.empty_cache()
+        extras = {"precision": precision_section(torch, Y, W, ev, sp, max(10, K // 10), plain["value"] if plain else None),
+                  "batched": batch_section(torch, Y, W, ev, sp),
+                  "serving": serving_section(torch, Y, W, sp, nreq=args.serve_requests)}
+
     rec = {
         "metric": "useful TFLOP/s per block-sparse tensordot vs plain per-sector FP64; p50/p99 latency",
         "value": round(value, 4), "unit": "TFLOP/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
@@ -442,6 +682,7 @@ def main():
         "kernels": per_kernel,
         "autotune": tuned,
         "cpu_baseline": cpu,
+        "extras": extras,
     }
     ev.close()
     print(json.dumps(rec))
