@@ -338,8 +338,9 @@ def batch_section(torch, Y, W, ev, sp):
         B = [torch.from_numpy(p.b.data).to("cuda:0").to(dt) for p in probs]
         C = [torch.empty(max(1, pl.output(i).numel), dtype=dt, device="cuda:0") for i in range(len(probs))]
         ws = torch.empty(max(256, pl.workspace_bytes), dtype=torch.uint8, device="cuda:0")
+        tune_ms = None
         if len(probs) <= 64:
-            pl.autotune(A, B, C, ws, reps=3, stream=sp)
+            _, tune_ms = pl.autotune(A, B, C, ws, reps=3, stream=sp)
         st = [pl.stats(i) for i in range(len(probs))]
         useful = sum(x["useful_flops"] for x in st)
         byts = sum(x["alg_bytes"] for x in st)
@@ -350,7 +351,8 @@ def batch_section(torch, Y, W, ev, sp):
                      "useful_TFs": round(tf, 3), "frac_of_mfma_peak": round(tf / peak, 4),
                      "achieved_GBs": round(byts / (ms * 1e-3) / 1e9, 1), "useful_flop": int(useful),
                      "alg_bytes": int(byts), "launch_groups": (len(probs) + 63) // 64,
-                     "variant": pl.variant_id, "inputs": "resident, warm (repeated launches)"}
+                     "variant": pl.variant_id, "inputs": "resident, warm (repeated launches)",
+                     "autotune_ms": [round(x, 4) for x in tune_ms] if tune_ms else None}
         del pl, A, B, C, ws
         torch.cuda.empty_cache()
     return res

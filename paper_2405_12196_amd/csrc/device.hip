@@ -353,10 +353,11 @@ yastn_status upload(Plan &pl) {
 constexpr int64_t kTilesPerLaunchTarget = 6144;
 constexpr int kVariantRows = kNumMfma + 1;
 constexpr int kVariantRes0 = kVariantRows + 1;
-constexpr int kVariants = kVariantRes0 + kNumRes;
+constexpr int kVariantPf0 = kVariantRes0 + kNumRes;
+constexpr int kVariants = kVariantPf0 + kNumPf;
 static_assert(kVariants == YASTN_NUM_VARIANTS, "variant count must match the header");
 
-enum Family { FAM_MFMA, FAM_ROWS, FAM_RES, FAM_BF16 };
+enum Family { FAM_MFMA, FAM_ROWS, FAM_RES, FAM_PF, FAM_BF16 };
 
 struct Choice {
   Family fam;
@@ -381,6 +382,11 @@ KernelFn mfma_kernel(const yastn_options &o, bool buf, int shape, int cb) {
 KernelFn rows_kernel(const yastn_options &o, bool buf, int kmax) {
   if (o.precision == YASTN_F64) return rows_f64(buf, kmax);
   return o.in_dtype == YASTN_DTYPE_F64 ? rows_f32d(o.out_dtype, buf, kmax) : rows_f32f(o.out_dtype, buf, kmax);
+}
+
+KernelFn pf_kernel(const yastn_options &o, bool buf, int shape, int cb, int na) {
+  if (o.precision == YASTN_F64) return pf_f64(buf, shape, cb, na);
+  return o.in_dtype == YASTN_DTYPE_F64 ? pf_f32d(o.out_dtype, buf, cb) : pf_f32f(o.out_dtype, buf, cb);
 }
 
 KernelFn res_kernel(const yastn_options &o, bool buf, int shape, int cb, int kq, int na) {
@@ -413,9 +419,13 @@ bool variant_fits(const Fit &f, const yastn_options &o, int v) {
   if (f.bf16) return v == 1;
   if (v >= 1 && v <= kNumMfma) return v == 1 || (f.buf && (o.precision == YASTN_F64 || v == 1 || v == 4));
   if (v == kVariantRows) return f.rows;
-  if (v >= kVariantRes0 && v < kVariants) {
+  if (v >= kVariantRes0 && v < kVariantPf0) {
     if (!f.res || !f.buf) return false;
     return o.precision == YASTN_F64 || v == kVariantRes0 + 1;  // FP32: one shape compiled (kResShapes[1])
+  }
+  if (v >= kVariantPf0 && v < kVariants) {
+    if (!f.buf) return false;
+    return o.precision == YASTN_F64 || v == kVariantPf0;  // FP32: one shape compiled (kPfShapes[0])
   }
   return false;
 }
@@ -426,11 +436,13 @@ Choice choose(const Fit &f, const yastn_options &o, int variant) {
     if (f.bf16 || f.mfma_pick || !f.buf) variant = 1;
     else if (f.rows_pick && f.rows) variant = kVariantRows;
     else if (f.res) variant = kVariantRes0 + 1;
-    else variant = 1;
+    else variant = kVariantPf0;
   }
   const int kq = (f.kmax + 3) / 4;
   const int na = f.nact <= 2 ? 2 : 4;
   if (variant == kVariantRows) return Choice{FAM_ROWS, rows_kernel(o, f.buf, f.kmax), pack_kernel(o)};
+  if (variant >= kVariantPf0)
+    return Choice{FAM_PF, pf_kernel(o, f.buf, variant - kVariantPf0, f.cb, na), pack_kernel(o)};
   if (variant >= kVariantRes0)
     return Choice{FAM_RES, res_kernel(o, f.buf, variant - kVariantRes0, f.cb, kq, na), nullptr};
   return Choice{f.bf16 ? FAM_BF16 : FAM_MFMA, mfma_kernel(o, f.buf, variant - 1, f.cb), pack_kernel(o)};

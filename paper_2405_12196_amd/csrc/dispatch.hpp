@@ -23,22 +23,28 @@ struct ResShape {
 constexpr ResShape kResShapes[] = {{1, 1, 3}, {2, 0, 3}, {1, 0, 4}, {2, 0, 4}, {4, 0, 2}, {2, 1, 3}};
 constexpr int kNumRes = sizeof(kResShapes) / sizeof(ResShape);
 constexpr int kResKq[] = {5, 10, 16};
+// k_gemm_pf: rows per chunk = 16 * rb, k-steps per pipelined batch = kb
+constexpr Shape kPfShapes[] = {{4, 2}, {2, 2}, {4, 1}};
+constexpr int kNumPf = sizeof(kPfShapes) / sizeof(Shape);
 constexpr int kResMaxK = 64;
 
 // FP64 arithmetic (F64 buffers)
 KernelFn gemm4_f64(bool buf, int shape, int cb);
 KernelFn res_f64(bool buf, int shape, int cb, int kq, int na);
 KernelFn rows_f64(bool buf, int kmax);
+KernelFn pf_f64(bool buf, int shape, int cb, int na);
 KernelFn pack_f64();
 // FP32 arithmetic with FP64 input buffers (out: F64 or F32)
 KernelFn gemm4_f32d(yastn_dtype out, bool buf, int shape, int cb);
 KernelFn res_f32d(yastn_dtype out, bool buf, int cb, int kq);
 KernelFn rows_f32d(yastn_dtype out, bool buf, int kmax);
+KernelFn pf_f32d(yastn_dtype out, bool buf, int cb);
 KernelFn pack_f32d();
 // FP32 arithmetic with FP32 input buffers
 KernelFn gemm4_f32f(yastn_dtype out, bool buf, int shape, int cb);
 KernelFn res_f32f(yastn_dtype out, bool buf, int cb, int kq);
 KernelFn rows_f32f(yastn_dtype out, bool buf, int kmax);
+KernelFn pf_f32f(yastn_dtype out, bool buf, int cb);
 KernelFn pack_f32f();
 // split-BF16 products (nt = 3 or 6), FP32 accumulation
 KernelFn bf16_gemm(yastn_dtype in, yastn_dtype out, int nt, bool buf, int cb);

@@ -598,6 +598,7 @@ void build_tile_records(const Plan &plan, const DevPlan &at, std::vector<DevTile
     r.N = sec.N;
     r.nact = sec.nact;
     r.prob = sec.prob;
+    r.bpack = sec.bpack;
     for (int a = 0; a < kRecAct; ++a) {
       r.lsuf[a] = a + 1 <= sec.nact ? rt.lsuf[a + 1] : 1;
       r.lsh[a] = a + 1 <= sec.nact ? rt.lsh[a + 1] : 31;

@@ -41,8 +41,20 @@ template <typename Out> KernelFn rows(bool buf, int kmax) {
   if (kmax <= 48) return k_rows<In, F, Out, true, 48>;
   return k_rows<In, F, Out, true, 64>;
 }
+template <typename Out> KernelFn pf(bool buf, int cb) {
+  if (!buf) return nullptr;
+  switch (cb) {
+    case 1: return k_gemm_pf<In, F, Out, true, 4, 1, 2, 4>;
+    case 2: return k_gemm_pf<In, F, Out, true, 4, 2, 2, 4>;
+    case 3: return k_gemm_pf<In, F, Out, true, 4, 3, 2, 4>;
+    default: return k_gemm_pf<In, F, Out, true, 4, 4, 2, 4>;
+  }
+}
 }  // namespace
 
+KernelFn pf_f32d(yastn_dtype out, bool buf, int cb) {
+  return out == YASTN_DTYPE_F64 ? pf<double>(buf, cb) : pf<float>(buf, cb);
+}
 KernelFn gemm4_f32d(yastn_dtype out, bool buf, int shape, int cb) {
   return out == YASTN_DTYPE_F64 ? g4<double>(buf, shape, cb) : g4<float>(buf, shape, cb);
 }

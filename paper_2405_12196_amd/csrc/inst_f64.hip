@@ -56,6 +56,27 @@ KernelFn res_f64(bool buf, int shape, int cb, int kq, int na) {
   }
 }
 
+namespace {
+template <int RB, int KB, int NA> KernelFn pf_cb(int cb) {
+  switch (cb) {
+    case 1: return k_gemm_pf<D, D, D, true, RB, 1, KB, NA>;
+    case 2: return k_gemm_pf<D, D, D, true, RB, 2, KB, NA>;
+    case 3: return k_gemm_pf<D, D, D, true, RB, 3, KB, NA>;
+    default: return k_gemm_pf<D, D, D, true, RB, 4, KB, NA>;
+  }
+}
+template <int RB, int KB> KernelFn pf_na(int na, int cb) { return na <= 2 ? pf_cb<RB, KB, 2>(cb) : pf_cb<RB, KB, 4>(cb); }
+}  // namespace
+
+KernelFn pf_f64(bool buf, int shape, int cb, int na) {
+  if (!buf) return nullptr;
+  switch (shape) {  // kPfShapes
+    case 1: return pf_na<2, 2>(na, cb);
+    case 2: return pf_na<4, 1>(na, cb);
+    default: return pf_na<4, 2>(na, cb);
+  }
+}
+
 KernelFn rows_f64(bool buf, int kmax) {
   if (!buf) return k_rows<D, D, D, false, 64>;
   if (kmax <= 16) return k_rows<D, D, D, true, 16>;

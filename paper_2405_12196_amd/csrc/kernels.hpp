@@ -17,6 +17,8 @@
 //  k_gemm_res   as k_gemm4 for sectors with K_X <= 64, with the tile's B
 //               values and k metadata held in registers and B read straight
 //               from its blocks (no pack kernel).
+//  k_gemm_pf    sectors of any K, k loop software-pipelined (loads of the
+//               next k batch in flight while the MFMAs of this one run).
 //  k_rows       tall-skinny sectors (K, N <= 64): one row of C_X per lane.
 //  k_gemm_bf16  split-BF16 products on bf16 MFMA 16x16x32, FP32 accumulation.
 #pragma once
@@ -601,6 +603,7 @@ template <typename In, typename Out, bool BUF> struct RecCtx {
   const DevColMap *cmap;
   const int64_t *cgrid;
   int32_t m0, nrows, n0, ncols, K, N, nact;
+  int64_t bpack;   // the sector's packed B_X in the workspace (elements)
   DevRowTuple rt;  // only lsuf / lmag / lsh of classes 1..kRecAct are filled
   Src<In, BUF, kStream> A;
   Src<In, BUF> B;
@@ -626,6 +629,7 @@ __device__ __forceinline__ void rec_setup(const LaunchArgs &args, int t, RecCtx<
   x.K = cst(&r->K);
   x.N = cst(&r->N);
   x.nact = cst(&r->nact);
+  x.bpack = cst(&r->bpack);
   const int32_t prob = cst(&r->prob);
 #pragma unroll
   for (int a = 0; a < kRecAct; ++a) {
@@ -742,6 +746,148 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
       } else if (mc + 16 * RB < nrows) {
         res_load_chunk<In, Cmp, Off, BUF, RB, KQ, NA>(x.A, x.rt, nact, K, x.m0 + mc + 16 * RB,
                                                       min(16 * RB, nrows - mc - 16 * RB), lane, ko, pk, av);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// grouped gather GEMM for sectors of any K, software-pipelined over k
+// ---------------------------------------------------------------------------
+// Tiles start from the flat tile record (as k_gemm_res); B comes from the
+// packed B_X in the workspace.  The k loop runs in batches of KB MFMA k-steps:
+// the A and B loads of batch n+1 are issued before the MFMAs of batch n, and
+// the k offsets of batch n+2 before those, so the matrix cores work while the
+// next operands are in flight (large-K sectors, where the MFMA time per tile
+// is long enough to hide the load latency).
+template <typename In, typename Cmp, typename Out, bool BUF, int RB, int CB, int KB, int NA>
+__global__ void __launch_bounds__(256) k_gemm_pf(LaunchArgs args) {
+  static_assert(NA <= kRecAct + 1, "tile records carry kRecAct class boundaries");
+  typedef typename std::conditional<BUF, int32_t, int64_t>::type Off;
+  typedef Mfma4<Cmp> M;
+  typedef typename M::acc_t acc_t;
+  const int lane = threadIdx.x & 63;
+  const int kl = lane >> 4;
+  const int gw = blockIdx.x * 4 + uni(threadIdx.x >> 6);  // wave-uniform
+  const int W = gridDim.x * 4;
+  for (int t = gw; t < args.ntiles; t += W) {
+    RecCtx<In, Out, BUF> x;
+    rec_setup<In, Out, BUF>(args, t, x);
+    int jb = 0;
+    while (jb + 1 < args.njobs && t >= args.jobs[jb + 1].tile0) ++jb;
+    const Cmp *__restrict__ Bp = reinterpret_cast<const Cmp *>(cst(&args.jobs[jb].ws)) + x.bpack;
+    const int K = x.K, N = x.N, nact = x.nact, nrows = x.nrows;
+    const int cbn = (x.ncols + 15) >> 4;
+    int64_t cbase[CB];
+    int32_t cnj[CB], ccl[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      const int lc = 16 * cb + (lane & 15);
+      cbase[cb] = -1;
+      cnj[cb] = 0;
+      ccl[cb] = 0;
+      if (lc < x.ncols) {
+        const DevColMap cm = x.cmap[lc];
+        cbase[cb] = x.cgrid[cm.j];
+        cnj[cb] = cm.nj;
+        ccl[cb] = cm.cl;
+      }
+    }
+    for (int mc = 0; mc < nrows; mc += 16 * RB) {
+      const int rows = min(16 * RB, nrows - mc);
+      const int rbn = (rows + 15) >> 4;
+      int32_t rg[RB][NA];
+      bool rv[RB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const int lr = 16 * rb + (lane & 15);
+        rv[rb] = lr < rows;
+        a_rowparts_fast<NA>(x.rt, nact, x.m0 + mc + (rv[rb] ? lr : 0), rg[rb]);
+      }
+      // k metadata of a batch: offset of (row 0, k) and class factors
+      Off ko[KB];
+      int32_t pk[KB][NA];
+      auto meta = [&](int kk0, Off (&o)[KB], int32_t (&p)[KB][NA]) {
+#pragma unroll
+        for (int q = 0; q < KB; ++q) {
+          const int k = kk0 + 4 * q + kl;
+          o[q] = -1;
+#pragma unroll
+          for (int a = 0; a < NA; ++a) p[q][a] = 0;
+          if (k < K) {
+            o[q] = (Off)x.kofs[k];
+            const DevKP d = x.kp[k];
+#pragma unroll
+            for (int a = 0; a < NA; ++a) p[q][a] = d.p[a];
+          }
+        }
+      };
+      auto load = [&](int kk0, const Off (&o)[KB], const int32_t (&p)[KB][NA], Cmp (&av)[KB][RB], Cmp (&bv)[KB][CB]) {
+#pragma unroll
+        for (int q = 0; q < KB; ++q) {
+          const int k = kk0 + 4 * q + kl;
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+            av[q][rb] = Cmp(0);
+            if (o[q] >= 0 && rv[rb]) {
+              Off off = o[q];
+#pragma unroll
+              for (int a = 0; a < NA; ++a) off += (Off)p[q][a] * (Off)rg[rb][a];
+              av[q][rb] = Cmp(x.A(off));
+            }
+          }
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            const int c = x.n0 + 16 * cb + (lane & 15);
+            bv[q][cb] = (k < K && c < N) ? Bp[(int64_t)k * N + c] : Cmp(0);
+          }
+        }
+      };
+      acc_t acc[RB][CB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = acc_t{0, 0, 0, 0};
+      Cmp av[KB][RB], bv[KB][CB], an[KB][RB], bn[KB][CB];
+      meta(0, ko, pk);
+      load(0, ko, pk, av, bv);
+      meta(4 * KB, ko, pk);
+      for (int kk0 = 0; kk0 < K; kk0 += 4 * KB) {
+        const bool more = kk0 + 4 * KB < K;
+        if (more) {
+          load(kk0 + 4 * KB, ko, pk, an, bn);
+          meta(kk0 + 8 * KB, ko, pk);
+        }
+#pragma unroll
+        for (int q = 0; q < KB; ++q)
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            if (rb < rbn)
+#pragma unroll
+              for (int cb = 0; cb < CB; ++cb)
+                if (cb < cbn) acc[rb][cb] = M::run(av[q][rb], bv[q][cb], acc[rb][cb]);
+        if (more) {
+#pragma unroll
+          for (int q = 0; q < KB; ++q) {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) av[q][rb] = an[q][rb];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) bv[q][cb] = bn[q][cb];
+          }
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        if (cb >= cbn || cbase[cb] < 0) continue;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          if (rb >= rbn) continue;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int lr = 16 * rb + M::row(lane, v);
+            if (lr < rows) x.C.put(cbase[cb] + (int64_t)(x.m0 + mc + lr) * cnj[cb] + ccl[cb], Out(acc[rb][cb][v]));
+          }
+        }
       }
     }
   }

@@ -125,7 +125,9 @@ struct DevTileRec {
   int32_t lsuf[kRecAct];       // Lsuf_1 .. Lsuf_kRecAct of the row tuple
   int32_t lsh[kRecAct];
   uint32_t lmag[kRecAct];
-  int32_t pad[7];
+  int32_t pad;
+  int64_t bpack;               // the sector's packed B_X in the workspace (elements)
+  int64_t pad2[2];
 };
 static_assert(sizeof(DevTileRec) == 160, "tile record layout");
 

@@ -181,7 +181,7 @@ int emu_contract(void *h, const double *const *a, const int64_t *alen, const dou
     if (rec.kofs != P.kofs + rt.kofs || rec.kp != P.kp + sec.kp0 || rec.bofs != P.bofs + sec.bofs0 ||
         rec.cmap != P.colmap + sec.cm0 + tile.n0 || rec.cgrid != P.cgrid + rt.cgrid || rec.m0 != tile.m0 ||
         rec.nrows != tile.nrows || rec.n0 != tile.n0 || rec.ncols != tile.ncols || rec.K != sec.K || rec.N != sec.N ||
-        rec.nact != nact || rec.prob != sec.prob || rec.a_span != P.probs[sec.prob].a_span ||
+        rec.nact != nact || rec.prob != sec.prob || rec.bpack != sec.bpack || rec.a_span != P.probs[sec.prob].a_span ||
         rec.b_span != P.probs[sec.prob].b_span || rec.c_numel != P.probs[sec.prob].c_numel)
       return fail("tile record differs from the tables");
     DevRowTuple fromrec{};

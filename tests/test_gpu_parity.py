@@ -265,7 +265,7 @@ def test_norm_f64(n):
 
 
 # ------------------------------------------------------ kernel variants
-@pytest.mark.parametrize("variant", range(1, 14))
+@pytest.mark.parametrize("variant", range(1, 17))
 @pytest.mark.parametrize("seed", range(10))
 def test_every_variant_matches_oracle(seed, variant):
     import paper_2405_12196_amd as Y
