@@ -235,9 +235,12 @@ class Chain:
             torch.cuda.synchronize()
 
     def step(self, st):
-        for pl, (a, b, c, w) in zip(self.plans, self.ops):
-            pl.contract([a], [b], [c], w, stream=st)
-        self.Y.norm(self.outs[-1], self.n_last, self.nout, self.nws, dtype=self.plans[-1].out_dtype, stream=st)
+        n = len(self.plans)
+        for i, (pl, (a, b, c, w)) in enumerate(zip(self.plans, self.ops)):
+            if i == n - 1:  # the truncation input's FP64 norm, fused into its contraction
+                pl.contract_norm([a], [b], [c], w, self.nout, stream=st)
+            else:
+                pl.contract([a], [b], [c], w, stream=st)
 
     def timed(self, ev, K, warmup=3):
         """ms per step over K steps, eager and graph-replayed; the faster wins."""
@@ -435,6 +438,8 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=2)
     ap.add_argument("--tile-rows", type=int, default=0, help="rows per wave tile: 64, 128, 256, 512 or 0 (plan's choice)")
     ap.add_argument("--no-tune", action="store_true", help="skip the kernel-variant autotuner")
+    ap.add_argument("--separate-norm", action="store_true",
+                    help="norm of the last output as its own two-pass kernel instead of fused into the contraction")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the precision sweep, the batched configs and the serving loop")
     ap.add_argument("--serve-requests", type=int, default=64)
@@ -506,9 +511,13 @@ def main():
     ev = HipEvents()
 
     def step(st):
-        for pl, (a, b, c, w) in zip(plans, ops):
-            pl.contract([a], [b], [c], w, stream=st)
-        Y.norm(outs[-1], n_last, nout, nws, stream=st)
+        for i, (pl, (a, b, c, w)) in enumerate(zip(plans, ops)):
+            if i == len(plans) - 1 and not args.separate_norm:
+                pl.contract_norm([a], [b], [c], w, nout, stream=st)  # the truncation input's FP64 norm, fused
+            else:
+                pl.contract([a], [b], [c], w, stream=st)
+        if args.separate_norm:
+            Y.norm(outs[-1], n_last, nout, nws, stream=st)
 
     for _ in range(args.warmup):
         step(sp)
@@ -667,7 +676,7 @@ def main():
         "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "ctmrg_enlarged_corner_u1xu1_chi128_D8_d4", "contractions_per_step": 4,
-                   "useful_flop_per_step": int(useful), "plus": "fp64 norm of the step-4 output",
+                   "useful_flop_per_step": int(useful), "plus": "fp64 norm of the step-4 output" + (" (separate kernel)" if args.separate_norm else " (fused into its contraction)"),
                    "parallelism": "single GPU"},
         "p50_ms": round(float(np.percentile(lat, 50)), 5), "p99_ms": round(float(np.percentile(lat, 99)), 5),
         "plan_ms": round(plan_ms, 2),

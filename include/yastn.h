@@ -159,6 +159,17 @@ yastn_status yastn_plan_stats(yastn_plan_t plan, int32_t prob, yastn_stats *st);
 yastn_status yastn_contract(yastn_plan_t plan, const void *const *a, const void *const *b,
                             void *const *c, void *workspace, void *hip_stream);
 
+/* As yastn_contract for a single-problem plan, and also writes the FP64
+ * Frobenius norm and max |x| of the output: norm_out [device] receives
+ * out[0] = ||C||_F, out[1] = max |C| (the truncation input's normalisation).
+ * The register-resident and pipelined kernels accumulate it in their epilogue
+ * (no second pass over C: each tile files its part in the workspace and one
+ * small kernel reduces the parts in tile order, so the result is
+ * deterministic); other kernel variants run a separate two-pass reduction.
+ * The workspace (yastn_plan_workspace bytes) holds the parts. */
+yastn_status yastn_contract_norm(yastn_plan_t plan, const void *const *a, const void *const *b,
+                                 void *const *c, void *workspace, double *norm_out, void *hip_stream);
+
 /* As yastn_contract, and records HIP events on hip_stream for timing:
  * events[0] before the B pack kernel, events[1] between the pack kernel and
  * the grouped GEMM, events[2] after the GEMM ([host] array of 3 hipEvent_t

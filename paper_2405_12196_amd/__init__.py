@@ -32,7 +32,7 @@ STATUS = ["OK", "ERR_ARG", "ERR_SYM", "ERR_CHARGE", "ERR_SIGNATURE", "ERR_SHAPE"
           "ERR_DUPLICATE", "ERR_NOMEM", "ERR_HIP", "ERR_STATE"]
 
 EXPORTS = ["yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats", "yastn_plan_info",
-           "yastn_contract", "yastn_contract_timed", "yastn_contract_jobs", "yastn_norm_workspace", "yastn_norm",
+           "yastn_contract", "yastn_contract_norm", "yastn_contract_timed", "yastn_contract_jobs", "yastn_norm_workspace", "yastn_norm",
            "yastn_free", "yastn_last_error", "yastn_status_string", "yastn_abi_version",
            "yastn_plan_autotune", "yastn_plan_set_variant",
            "yastn_server_create", "yastn_server_submit", "yastn_server_step", "yastn_server_query",
@@ -113,6 +113,8 @@ def lib():
         L.yastn_plan_stats.argtypes = [C.c_void_p, C.c_int32, C.POINTER(Stats)]
         L.yastn_contract.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                      C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]
+        L.yastn_contract_norm.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                          C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p, C.c_void_p]
         L.yastn_contract_timed.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                            C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]
         L.yastn_contract_jobs.argtypes = [C.POINTER(Job), C.c_int32, C.c_void_p]
@@ -138,7 +140,7 @@ def lib():
         L.yastn_status_string.restype = C.c_char_p
         L.yastn_status_string.argtypes = [C.c_int32]
         for f in ("yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats",
-                  "yastn_contract", "yastn_contract_timed", "yastn_contract_jobs", "yastn_norm",
+                  "yastn_contract", "yastn_contract_norm", "yastn_contract_timed", "yastn_contract_jobs", "yastn_norm",
                   "yastn_plan_autotune", "yastn_plan_set_variant", "yastn_plan_info", "yastn_server_create",
                   "yastn_server_submit", "yastn_server_step", "yastn_server_query", "yastn_server_forget",
                   "yastn_server_drain", "yastn_server_get_stats"):
@@ -295,6 +297,15 @@ class Plan:
         pc = (C.c_void_p * max(1, n))(*[_ptr(x) for x in c])
         _check(lib().yastn_contract(self._h, pa, pb, pc, C.c_void_p(_ptr(workspace)),
                                     C.c_void_p(_stream(stream))))
+
+    def contract_norm(self, a, b, c, workspace, norm_out, stream=None):
+        """As contract() for a single-problem plan; also writes norm_out[0] =
+        ||C||_F and norm_out[1] = max |C| (FP64, on the device)."""
+        pa = (C.c_void_p * 1)(_ptr(a[0]))
+        pb = (C.c_void_p * 1)(_ptr(b[0]))
+        pc = (C.c_void_p * 1)(_ptr(c[0]))
+        _check(lib().yastn_contract_norm(self._h, pa, pb, pc, C.c_void_p(_ptr(workspace)),
+                                         C.c_void_p(_ptr(norm_out)), C.c_void_p(_stream(stream))))
 
     def contract_timed(self, a, b, c, workspace, events, stream=None):
         """As contract(); records ``events`` (3 raw hipEvent_t handles or None)

@@ -176,6 +176,10 @@ __global__ void __launch_bounds__(256) k_norm_partial(const T *x, int64_t n, dou
   }
 }
 
+__global__ void k_zero2(double *out) {
+  if (threadIdx.x < 2) out[threadIdx.x] = 0.0;
+}
+
 __global__ void __launch_bounds__(256) k_norm_final(const double *part, int np, double *out) {
   __shared__ double ss[256], sm[256];
   double s = 0.0, m = 0.0;
@@ -469,7 +473,8 @@ struct JobRef {
   void *ws;
 };
 
-yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const *events = nullptr) {
+yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const *events = nullptr,
+                    double *norm_out = nullptr, bool *norm_fused = nullptr) {
   if (events && events[0]) YASTN_HIP(hipEventRecord(reinterpret_cast<hipEvent_t>(events[0]), st));
   if (jobs.empty()) {
     if (events && events[1]) YASTN_HIP(hipEventRecord(reinterpret_cast<hipEvent_t>(events[1]), st));
@@ -485,6 +490,9 @@ yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const
   }
   const Choice ch = choose(fit, o, variant);
   if (!ch.gemm) return set_error(YASTN_ERR_STATE, "no kernel instance for this plan");
+  // the norm rides in the epilogue of the register-resident and pipelined kernels
+  const bool fuse = norm_out && jobs.size() == 1 && (ch.fam == FAM_RES || ch.fam == FAM_PF);
+  if (norm_fused) *norm_fused = fuse;
   size_t ji = 0;
   while (ji < jobs.size()) {
     LaunchArgs la;
@@ -513,6 +521,10 @@ yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const
       la.ntiles += j.g->t1 - j.g->t0;
       la.nitems += j.g->i1 - j.g->i0;
       ++ji;
+    }
+    if (fuse) {
+      const JobRef &j = jobs[0];
+      la.norm.parts = reinterpret_cast<double *>(reinterpret_cast<char *>(j.ws) + j.plan->norm_off);
     }
     void *kargs[] = {&la};
     if (ch.pack && la.nitems > 0) {
@@ -747,6 +759,42 @@ yastn_status yastn_contract(yastn_plan_t plan, const void *const *a, const void 
   std::vector<JobRef> jobs;
   for (const Group &g : plan->p.groups) jobs.push_back(JobRef{&plan->p, &g, a, b, c, workspace});
   return launch(jobs, reinterpret_cast<hipStream_t>(hip_stream));
+}
+
+yastn_status yastn_contract_norm(yastn_plan_t plan, const void *const *a, const void *const *b, void *const *c,
+                                 void *workspace, double *norm_out, void *hip_stream) {
+  if (!plan || !norm_out) return set_error(YASTN_ERR_ARG, "null argument");
+  if (plan->p.probs.size() != 1) return set_error(YASTN_ERR_STATE, "the fused norm needs a single-problem plan");
+  yastn_status s = check_job_ptrs(&plan->p, a, b, c, workspace);
+  if (s) return s;
+  std::vector<JobRef> jobs;
+  for (const Group &g : plan->p.groups) jobs.push_back(JobRef{&plan->p, &g, a, b, c, workspace});
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  bool fused = false;
+  if ((s = launch(jobs, st, nullptr, norm_out, &fused))) return s;
+  if (plan->p.probs[0].c_numel == 0) {  // empty output (no tiles ran): norm 0
+    hipLaunchKernelGGL(k_zero2, dim3(1), dim3(64), 0, st, norm_out);
+    YASTN_HIP(hipGetLastError());
+    return YASTN_OK;
+  }
+  const HostProblem &hp = plan->p.probs[0];
+  double *part = reinterpret_cast<double *>(reinterpret_cast<char *>(workspace) + plan->p.norm_off);
+  if (fused) {  // the epilogue filed one part per tile: reduce them in tile order
+    k_norm_final<<<1, 256, 0, st>>>(part, (int)plan->p.t.tiles.size(), norm_out);
+    YASTN_HIP(hipGetLastError());
+    return YASTN_OK;
+  }
+  // kernel families without the fused epilogue: a separate pass over C, with
+  // the parts in the same workspace slot
+  const int nb = (int)std::min<int64_t>(std::max<int64_t>(1, (int64_t)plan->p.t.tiles.size()),
+                                        std::max<int64_t>(1, (hp.c_numel + 1023) / 1024));
+  if (plan->p.opts.out_dtype == YASTN_DTYPE_F64)
+    k_norm_partial<double><<<nb, 256, 0, st>>>(reinterpret_cast<const double *>(c[0]), hp.c_numel, part);
+  else
+    k_norm_partial<float><<<nb, 256, 0, st>>>(reinterpret_cast<const float *>(c[0]), hp.c_numel, part);
+  k_norm_final<<<1, 256, 0, st>>>(part, nb, norm_out);
+  YASTN_HIP(hipGetLastError());
+  return YASTN_OK;
 }
 
 yastn_status yastn_contract_timed(yastn_plan_t plan, const void *const *a, const void *const *b, void *const *c,

@@ -539,8 +539,10 @@ void finish_tiles(Plan &plan) {
   const size_t out_b = plan.opts.out_dtype == YASTN_DTYPE_F64 ? 8 : 4;
   for (auto &hp : plan.probs)
     hp.stats.alg_bytes = double(hp.a.numel + hp.b.numel) * in_b + double(hp.c_numel) * out_b;
-  // longest tiles first within each launch group: static round-robin over
-  // waves then balances the load
+  // longest tiles first within each launch group, so the waves that start
+  // last get the short tiles.  (Keeping tiles of one sector side by side, for
+  // cache sharing, measured slower: neighbouring waves then stream the same
+  // rows of A and C and contend for the same memory channels.)
   const int np = (int)plan.probs.size();
   plan.prob_t0.push_back((int32_t)t.tiles.size());
   plan.prob_i0.push_back((int32_t)t.items.size());
@@ -570,7 +572,8 @@ void finish_tiles(Plan &plan) {
     plan.groups.push_back(g);
   }
   const size_t elem = plan.opts.precision == YASTN_F64 ? 8 : 4;
-  plan.ws_bytes = ((size_t(t.bpack_elems) * elem + 255) / 256) * 256;
+  plan.norm_off = ((size_t(t.bpack_elems) * elem + 255) / 256) * 256;
+  plan.ws_bytes = plan.norm_off + ((t.tiles.size() * 2 * sizeof(double) + 255) / 256) * 256;
 }
 
 void build_tile_records(const Plan &plan, const DevPlan &at, std::vector<DevTileRec> &recs) {

@@ -80,6 +80,38 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Fused output norm: a lane's running sum of squares and max |x| of the
+// values it stored; at the end of a tile the wave combines them in a fixed
+// butterfly order and lane 0 files the tile's part (a small kernel then
+// reduces the parts in tile order: deterministic, no atomics).
+struct NormAcc {
+  double ss = 0.0, mx = 0.0;
+  __device__ void add(double v) {
+    ss = fma(v, v, ss);
+    mx = fmax(mx, fabs(v));
+  }
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ void norm_file_tile(const NormArgs &na, int t, int lane, NormAcc &acc) {
+  const double ss = wave_sum(acc.ss), mx = wave_max(acc.mx);
+  acc = NormAcc{};
+  if (lane == 0) {
+    na.parts[2 * (int64_t)t] = ss;
+    na.parts[2 * (int64_t)t + 1] = mx;
+  }
+}
+
 // A value the compiler cannot prove wave-uniform but that is.
 __device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ int64_t uni64(int64_t v) {
@@ -653,6 +685,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
   const int kl = lane >> 4;
   const int gw = blockIdx.x * 4 + uni(threadIdx.x >> 6);  // wave-uniform
   const int W = gridDim.x * 4;
+  const bool do_norm = args.norm.parts != nullptr;
+  NormAcc nacc;
   for (int t = gw; t < args.ntiles; t += W) {
     RecCtx<In, Out, BUF> x;
     rec_setup<In, Out, BUF>(args, t, x);
@@ -734,7 +768,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int lr = 16 * rb + M::row(lane, v);
-            if (lr < rows) x.C.put(cbase[cb] + (int64_t)(x.m0 + mc + lr) * cnj[cb] + ccl[cb], Out(acc[rb][cb][v]));
+            if (lr < rows) {
+              const Out val = Out(acc[rb][cb][v]);
+              x.C.put(cbase[cb] + (int64_t)(x.m0 + mc + lr) * cnj[cb] + ccl[cb], val);
+              if (do_norm) nacc.add((double)val);
+            }
           }
         }
       }
@@ -748,6 +786,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
                                                       min(16 * RB, nrows - mc - 16 * RB), lane, ko, pk, av);
       }
     }
+    if (do_norm) norm_file_tile(args.norm, t, lane, nacc);
   }
 }
 
@@ -770,6 +809,8 @@ __global__ void __launch_bounds__(256) k_gemm_pf(LaunchArgs args) {
   const int kl = lane >> 4;
   const int gw = blockIdx.x * 4 + uni(threadIdx.x >> 6);  // wave-uniform
   const int W = gridDim.x * 4;
+  const bool do_norm = args.norm.parts != nullptr;
+  NormAcc nacc;
   for (int t = gw; t < args.ntiles; t += W) {
     RecCtx<In, Out, BUF> x;
     rec_setup<In, Out, BUF>(args, t, x);
@@ -885,11 +926,16 @@ __global__ void __launch_bounds__(256) k_gemm_pf(LaunchArgs args) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int lr = 16 * rb + M::row(lane, v);
-            if (lr < rows) x.C.put(cbase[cb] + (int64_t)(x.m0 + mc + lr) * cnj[cb] + ccl[cb], Out(acc[rb][cb][v]));
+            if (lr < rows) {
+              const Out val = Out(acc[rb][cb][v]);
+              x.C.put(cbase[cb] + (int64_t)(x.m0 + mc + lr) * cnj[cb] + ccl[cb], val);
+              if (do_norm) nacc.add((double)val);
+            }
           }
         }
       }
     }
+    if (do_norm) norm_file_tile(args.norm, t, lane, nacc);
   }
 }
 

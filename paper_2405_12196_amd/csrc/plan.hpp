@@ -174,8 +174,15 @@ struct JobArg {                // a range of one plan's problems inside a launch
   int32_t plo;                 // first plan problem covered by this job
 };
 
+// Norm of the output fused into the GEMM epilogue (single-problem launches):
+// every tile writes its sum of squares and max |x| to parts[tile].
+struct NormArgs {
+  double *parts;               // [ntiles][2] in the workspace, null = no norm
+};
+
 struct LaunchArgs {
   int32_t njobs, ntiles, nitems, pad;
+  NormArgs norm;
   JobArg jobs[kMaxJobs];
   ProbPtrs p[kMaxProbs];
 };

@@ -89,6 +89,7 @@ struct Plan {
   DevPlan *dplan = nullptr; // device copy of the table of pointers
   const DevTileRec *drecs = nullptr;  // device tile records
   size_t ws_bytes = 0;
+  size_t norm_off = 0;      // workspace offset of the fused norm's per-tile parts
   int device = 0;
 };
 

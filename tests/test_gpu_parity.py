@@ -322,15 +322,15 @@ def test_graph_replays_equal_eager_chain(kind):
     inp = {k: G.upload(t[k]) for k in ("C", "T1", "T4", "A", "Ac")}
     outs = [torch.full((max(1, pl.output(0).numel),), float("nan"), dtype=torch.float64, device=G.DEV) for pl in plans]
     wss = [G.workspace(pl) for pl in plans]
-    nws = torch.empty(Y.norm_workspace_bytes(), dtype=torch.uint8, device=G.DEV)
     nout = torch.zeros(2, dtype=torch.float64, device=G.DEV)
-    n_last = plans[-1].output(0).numel
 
     def chain(st):
         for i, ((an, bn), pl) in enumerate(zip(steps, plans)):
             a = inp[an] if an else outs[i - 1]
-            pl.contract([a], [inp[bn]], [outs[i]], wss[i], stream=st)
-        Y.norm(outs[-1], n_last, nout, nws, stream=st)
+            if i == len(steps) - 1:  # the last output's FP64 norm, fused into its contraction
+                pl.contract_norm([a], [inp[bn]], [outs[i]], wss[i], nout, stream=st)
+            else:
+                pl.contract([a], [inp[bn]], [outs[i]], wss[i], stream=st)
 
     chain(int(torch.cuda.current_stream().cuda_stream))
     torch.cuda.synchronize()
@@ -354,3 +354,51 @@ def test_graph_replays_equal_eager_chain(kind):
             assert torch.equal(o, r), f"replay {rep} differs from the eager chain"
         assert torch.equal(nout, ref_norm)
         del junk
+
+
+# ------------------------------------------------------------ fused norm
+@pytest.mark.parametrize("kind", ["auto", "mfma", "rows"])
+def test_fused_norm_matches_oracle_and_repeats_bitwise(kind):
+    """The FP64 norm of the step-4 output, from the contraction's epilogue
+    (register-resident kernel) or from the separate pass (other kernels)."""
+    import paper_2405_12196_amd as Y
+    t = W.config2()
+    a = oracle.tensordot_blockpair(t["C"], t["T1"], (1,), (0,))
+    a = oracle.tensordot_blockpair(a, t["T4"], (0,), (0,))
+    a = oracle.tensordot_blockpair(a, t["A"], (0, 3), (0, 1))
+    ref = oracle.tensordot_blockpair(a, t["Ac"], (0, 2, 6), (0, 1, 4))
+    pl = Y.plan([(a, t["Ac"], (0, 2, 6), (0, 1, 4))], flags=FLAGS[kind])
+    A, B = G.upload(a), G.upload(t["Ac"])
+    c, s = G.alloc_out(pl, 0)
+    ws = G.workspace(pl)
+    nout = torch.full((2,), float("nan"), dtype=torch.float64, device=G.DEV)
+    pl.contract_norm([A], [B], [c], ws, nout)
+    torch.cuda.synchronize()
+    check_f64(s, c.cpu().numpy()[:s.numel], ref)
+    rf, rm = oracle.norms(ref)
+    got = nout.cpu().numpy()
+    # C itself differs from the oracle's by rounding: both norms to 1e-13 relative,
+    # and the max is exactly the max of the library's own output
+    assert abs(got[0] - rf) <= 1e-13 * rf and abs(got[1] - rm) <= 1e-13 * rm
+    assert got[1] == float(c[:s.numel].abs().max())
+    first = nout.clone()
+    for _ in range(3):
+        nout.fill_(float("nan"))
+        pl.contract_norm([A], [B], [c], ws, nout)
+    torch.cuda.synchronize()
+    assert torch.equal(nout, first)
+
+
+def test_fused_norm_empty_output():
+    import paper_2405_12196_amd as Y
+    l = _u1(1, [(0, 2), (1, 3)])
+    a = W.rand([l, _u1(1, [(5, 2)])], (5,), (0,), 3)  # contracted charges never shared
+    b = W.rand([_u1(-1, [(4, 2)]), l], (-4,), (0,), 4)
+    xa, xb = (1,), (0,)
+    pl = Y.plan([(a, b, xa, xb)])
+    assert pl.output(0).numel == 0
+    nout = torch.full((2,), float("nan"), dtype=torch.float64, device=G.DEV)
+    c = torch.zeros(1, dtype=torch.float64, device=G.DEV)
+    pl.contract_norm([G.upload(a)], [G.upload(b)], [c], G.workspace(pl), nout)
+    torch.cuda.synchronize()
+    assert nout.cpu().tolist() == [0.0, 0.0]
