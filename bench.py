@@ -63,6 +63,37 @@ class HipEvents:
             self.hip.hipEventDestroy(ctypes.c_void_p(e))
 
 
+# ------------------------------------------------------- measured traffic
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ctm_corner_chi128_D8_f64_hbm_traffic.json")
+
+
+def kernel_source_hash():
+    """sha256 over the library's kernel and dispatch sources."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2405_12196_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(step, variant):
+    """HBM bytes per launch of contraction `step` (FETCH_SIZE + WRITE_SIZE,
+    scaled by a plain copy), from the committed counter summary; None when the
+    kernels changed since the counters were taken or another variant runs."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    e = rec.get("per_launch", {}).get(f"step{step}_v{variant}")
+    return int(e["fetch_bytes"] + e["write_bytes"]) if e else None
+
+
 # ------------------------------------------------------------ HIP graphs
 def capture(torch, fn):
     """Capture fn(stream_handle) into a torch CUDAGraph (HIP graph) on a side
@@ -438,6 +469,8 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=2)
     ap.add_argument("--tile-rows", type=int, default=0, help="rows per wave tile: 64, 128, 256, 512 or 0 (plan's choice)")
     ap.add_argument("--no-tune", action="store_true", help="skip the kernel-variant autotuner")
+    ap.add_argument("--variants", default="",
+                    help="comma-separated kernel variant per contraction (skips the autotuner), e.g. 8,8,13,8")
     ap.add_argument("--separate-norm", action="store_true",
                     help="norm of the last output as its own two-pass kernel instead of fused into the contraction")
     ap.add_argument("--no-extras", action="store_true",
@@ -502,7 +535,10 @@ def main():
 
     # ---- autotune each contraction's kernel variant (outside the timed region)
     tuned = []
-    if not args.no_tune:
+    if args.variants:
+        for pl, v in zip(plans, [int(x) for x in args.variants.split(",")]):
+            pl.set_variant(v)
+    elif not args.no_tune:
         for i, (pl, (a, b, c, w)) in enumerate(zip(plans, ops)):
             v, times = pl.autotune([a], [b], [c], w, reps=5, stream=sp)
             tuned.append({"step": i + 1, "variant": v, "ms": [round(x, 4) for x in times]})
@@ -686,7 +722,8 @@ def main():
         "vs_plain_per_sector_f64": round(value / plain["value"], 3) if plain else None,
         "plain_per_sector_f64": plain,
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dom + 1, plans[dom].variant_id),
                      "kernel": f"grouped gather GEMM of contraction {dom + 1}",
                      "launch_us": round(float(gemm_avg[dom]) * 1e3, 2),
                      "timing": f"HIP events on the launch stream around {REP} replays of a graph of {R} launches"},

@@ -180,24 +180,37 @@ __global__ void k_zero2(double *out) {
   if (threadIdx.x < 2) out[threadIdx.x] = 0.0;
 }
 
-__global__ void __launch_bounds__(256) k_norm_final(const double *part, int np, double *out) {
-  __shared__ double ss[256], sm[256];
-  double s = 0.0, m = 0.0;
-  for (int i = threadIdx.x; i < np; i += 256) {
-    s += part[2 * i];
-    m = fmax(m, part[2 * i + 1]);
+// Reduces np (sum of squares, max) parts in a fixed order: thread t takes
+// parts t, t + 1024, ... (independent loads, four in flight), then a tree.
+__global__ void __launch_bounds__(1024) k_norm_final(const double *part, int np, double *out) {
+  __shared__ double ss[1024], sm[1024];
+  const int t = threadIdx.x;
+  double s0 = 0.0, s1 = 0.0, m0 = 0.0, m1 = 0.0;
+  int i = t;
+  for (; i + 3 * 1024 < np; i += 4 * 1024) {
+    const double a = part[2 * i], b = part[2 * (i + 1024)], c = part[2 * (i + 2048)], d = part[2 * (i + 3072)];
+    const double ma = part[2 * i + 1], mb = part[2 * (i + 1024) + 1], mc = part[2 * (i + 2048) + 1],
+                 md = part[2 * (i + 3072) + 1];
+    s0 += a + c;
+    s1 += b + d;
+    m0 = fmax(m0, fmax(ma, mc));
+    m1 = fmax(m1, fmax(mb, md));
   }
-  ss[threadIdx.x] = s;
-  sm[threadIdx.x] = m;
+  for (; i < np; i += 1024) {
+    s0 += part[2 * i];
+    m0 = fmax(m0, part[2 * i + 1]);
+  }
+  ss[t] = s0 + s1;
+  sm[t] = fmax(m0, m1);
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      ss[threadIdx.x] += ss[threadIdx.x + w];
-      sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) {
+      ss[t] += ss[t + w];
+      sm[t] = fmax(sm[t], sm[t + w]);
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
+  if (t == 0) {
     out[0] = sqrt(ss[0]);
     out[1] = sm[0];
   }
@@ -780,7 +793,7 @@ yastn_status yastn_contract_norm(yastn_plan_t plan, const void *const *a, const 
   const HostProblem &hp = plan->p.probs[0];
   double *part = reinterpret_cast<double *>(reinterpret_cast<char *>(workspace) + plan->p.norm_off);
   if (fused) {  // the epilogue filed one part per tile: reduce them in tile order
-    k_norm_final<<<1, 256, 0, st>>>(part, (int)plan->p.t.tiles.size(), norm_out);
+    k_norm_final<<<1, 1024, 0, st>>>(part, (int)plan->p.t.tiles.size(), norm_out);
     YASTN_HIP(hipGetLastError());
     return YASTN_OK;
   }
@@ -792,7 +805,7 @@ yastn_status yastn_contract_norm(yastn_plan_t plan, const void *const *a, const 
     k_norm_partial<double><<<nb, 256, 0, st>>>(reinterpret_cast<const double *>(c[0]), hp.c_numel, part);
   else
     k_norm_partial<float><<<nb, 256, 0, st>>>(reinterpret_cast<const float *>(c[0]), hp.c_numel, part);
-  k_norm_final<<<1, 256, 0, st>>>(part, nb, norm_out);
+  k_norm_final<<<1, 1024, 0, st>>>(part, nb, norm_out);
   YASTN_HIP(hipGetLastError());
   return YASTN_OK;
 }
@@ -893,7 +906,7 @@ yastn_status yastn_norm(const void *x, int64_t n, yastn_dtype dtype, double *out
     k_norm_partial<double><<<nb, 256, 0, st>>>(reinterpret_cast<const double *>(x), n, part);
   else
     k_norm_partial<float><<<nb, 256, 0, st>>>(reinterpret_cast<const float *>(x), n, part);
-  k_norm_final<<<1, 256, 0, st>>>(part, nb, out);
+  k_norm_final<<<1, 1024, 0, st>>>(part, nb, out);
   YASTN_HIP(hipGetLastError());
   return YASTN_OK;
 }
