@@ -10,6 +10,7 @@ Implementations (each cites the passage of the paper it follows):
   * ``tensordot_dense``    (O1) embed every block in a dense array, contract
                            with numpy.tensordot, read the blocks back;
   * ``tensordot_blockpair`` (O2) sum numpy.tensordot over matched block pairs;
+  * ``tensordot_blocks``   O2 for chosen output blocks only (full-size samples);
   * ``tensordot_brute``    (O3) pure-Python loops over every dense index;
   * ``fuse_legs`` / ``unfuse_legs`` (O-fuse) leg fusion and its inverse;
   * ``validate_*``         structural checks with the library's status classes;
@@ -24,7 +25,7 @@ plain numpy.tensordot, invariants); see tests/test_oracle_*.py.
 from .blocksparse import (  # noqa: F401
     OracleError, ERR_ARG, ERR_SYM, ERR_CHARGE, ERR_SIGNATURE, ERR_SHAPE,
     ERR_DUPLICATE, normalize, validate_tensor, validate_pair, output_structure,
-    tensordot_dense, tensordot_blockpair, tensordot_brute, to_dense,
+    tensordot_dense, tensordot_blockpair, tensordot_blocks, tensordot_brute, to_dense,
     leg_index_maps, fuse_legs, unfuse_legs, transpose, norms, structure_stats,
     rel_frobenius, same_structure,
 )

@@ -143,7 +143,7 @@ def matched_pairs(a: BlockTensor, b: BlockTensor, axes_a, axes_b):
     return out
 
 
-def output_structure(a: BlockTensor, b: BlockTensor, axes_a, axes_b):
+def output_structure(a: BlockTensor, b: BlockTensor, axes_a, axes_b, with_data=True):
     """Rule R: C's legs are A's free legs then B's free legs (numpy tensordot
     order, as in the paper's listing), n_C = n_A + n_B, and C holds exactly the
     blocks (a_free, b_free) reached by at least one matched pair, sorted in
@@ -170,7 +170,7 @@ def output_structure(a: BlockTensor, b: BlockTensor, axes_a, axes_b):
     sig = np.array([a.sig[x] for x in fa] + [b.sig[y] for y in fb], dtype=np.int8)
     n = np.array(_nq([int(p) + int(q) for p, q in zip(a.n, b.n)], a.sym_mod), dtype=np.int32)
     return BlockTensor(tuple(a.sym_mod), sig, n, charges, shapes, offsets,
-                       np.zeros(int(sizes.sum()), dtype=np.float64))
+                       np.zeros(int(sizes.sum()) if with_data else 0, dtype=np.float64))
 
 
 # ---------------------------------------------------------------------------
@@ -270,6 +270,33 @@ def tensordot_blockpair(a: BlockTensor, b: BlockTensor, axes_a, axes_b):
             acc += np.tensordot(a.block(i), b.block(j), axes=(tuple(axes_a), tuple(axes_b)))
         c.data[c.offsets[k]:c.offsets[k] + acc.size] = acc.ravel()
     return c
+
+
+def tensordot_blocks(a: BlockTensor, b: BlockTensor, axes_a, axes_b, block_ids):
+    """O2 restricted to some output blocks: returns (structure of C without
+    values, {block index: dense block}) for the rule-R output block indices in
+    block_ids, each the sum of numpy.tensordot over its matched block pairs in
+    ascending lexicographic order of the contracted charges -- the same terms
+    in the same order as tensordot_blockpair, for outputs too large to hold on
+    the host (Sec. II.B, block by block)."""
+    validate_pair(a, b, axes_a, axes_b)
+    a, b = normalize(a), normalize(b)
+    c = output_structure(a, b, axes_a, axes_b, with_data=False)
+    want = {int(k) for k in block_ids}
+    fa, fb = _free(a.rank, axes_a), _free(b.rank, axes_b)
+    index = {_block_key(c, k): k for k in range(c.nblocks)}
+    groups = {}
+    for i, j in matched_pairs(a, b, axes_a, axes_b):
+        k = index[_block_key(a, i, fa) + _block_key(b, j, fb)]
+        if k in want:
+            groups.setdefault(k, []).append((_flat(_block_key(a, i, axes_a)), i, j))
+    out = {}
+    for k in sorted(want):
+        acc = np.zeros(tuple(int(x) for x in c.shapes[k]), dtype=np.float64)
+        for _, i, j in sorted(groups.get(k, [])):
+            acc += np.tensordot(a.block(i), b.block(j), axes=(tuple(axes_a), tuple(axes_b)))
+        out[k] = acc
+    return c, out
 
 
 # ---------------------------------------------------------------------------

@@ -310,3 +310,25 @@ def test_z_m_charges_normalised():
     r1 = oracle.tensordot_blockpair(a, b, (1,), (0,))
     r2 = oracle.tensordot_blockpair(a2, b, (1,), (0,))
     assert oracle.same_structure(r1, r2) and np.array_equal(r1.data, r2.data)
+
+
+@pytest.mark.parametrize("step", [0, 1, 2])
+def test_sampled_blocks_equal_full_blockpair(step):
+    """tensordot_blocks (O2 on chosen output blocks) gives exactly the blocks
+    of the full O2 result: same pairs, same order."""
+    import workloads as W
+    t = W.config2()
+    steps = [("C", "T1"), (None, "T4"), (None, "A")]
+    cur = None
+    for i, ((an, bn), (ax, bx)) in enumerate(zip(steps, t["axes"])):
+        a = t[an] if an else cur
+        if i == step:
+            full = oracle.tensordot_blockpair(a, t[bn], ax, bx)
+            rng = np.random.default_rng(step)
+            ids = sorted(set(rng.integers(0, full.nblocks, size=12).tolist()) | {0, full.nblocks - 1})
+            s, blocks = oracle.tensordot_blocks(a, t[bn], ax, bx, ids)
+            assert np.array_equal(s.charges, full.charges) and np.array_equal(s.offsets, full.offsets)
+            for k in ids:
+                assert np.array_equal(blocks[k], full.block(k))
+            return
+        cur = oracle.tensordot_blockpair(a, t[bn], ax, bx)
