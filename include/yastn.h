@@ -182,9 +182,10 @@ yastn_status yastn_contract_timed(yastn_plan_t plan, const void *const *a, const
 /* Kernel variants.  A plan starts with variant 0 (the library's heuristic).
  * Variants 1-6: MFMA tiles reading a packed copy of B (six tile shapes);
  * 7: one output row per lane on the vector FMA units (sectors with K, N <= 64);
- * 8-13: MFMA tiles with the tile's B values held in registers and read straight
- * from B's blocks (sectors with K <= 64; six chunk / occupancy shapes);
- * 14-16: MFMA tiles over a packed B with the k loop software-pipelined (any K;
+ * 8-16: MFMA tiles with the tile's B values held in registers and read straight
+ * from B's blocks (nine chunk / occupancy shapes; sectors with K <= 64, and
+ * K <= 80 for variant 16, which runs one wave per SIMD);
+ * 17-19: MFMA tiles over a packed B with the k loop software-pipelined (any K;
  * three shapes).
  * yastn_plan_autotune runs every variant that fits the plan `reps` times on
  * the caller's buffers (same arguments as yastn_contract; C is overwritten),
@@ -196,7 +197,7 @@ yastn_status yastn_contract_timed(yastn_plan_t plan, const void *const *a, const
  * variant, so repeated contractions stay bitwise reproducible.
  * yastn_plan_set_variant restores a previously tuned choice (e.g. from a
  * cache keyed by structure); YASTN_ERR_STATE if the variant does not fit. */
-#define YASTN_NUM_VARIANTS 17
+#define YASTN_NUM_VARIANTS 20
 yastn_status yastn_plan_autotune(yastn_plan_t plan, const void *const *a, const void *const *b,
                                  void *const *c, void *workspace, void *hip_stream, int32_t reps,
                                  int32_t *chosen, float *times_ms);

@@ -39,7 +39,7 @@ EXPORTS = ["yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_pla
            "yastn_server_forget", "yastn_server_drain", "yastn_server_get_stats", "yastn_server_destroy"]
 REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 MAX_CHAIN = 8
-NUM_VARIANTS = 17
+NUM_VARIANTS = 20
 
 
 class YastnError(RuntimeError):

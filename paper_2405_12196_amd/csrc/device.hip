@@ -362,7 +362,7 @@ yastn_status upload(Plan &pl) {
 // Kernel variants of one plan: 0 = the plan's heuristic choice; then
 //   1..kNumMfma                        k_gemm4 with shape kMfmaShapes[v - 1]
 //   kVariantRows                       k_rows (one output row per lane)
-//   kVariantRes0 .. + kNumRes - 1      k_gemm_res with rows per chunk 16 * kResRb[i]
+//   kVariantRes0 .. + kNumRes - 1      k_gemm_res with shape kResShapes[v - kVariantRes0]
 // yastn_plan_autotune times the candidates that fit the plan.  Tile widths
 // (CB) must cover the plan's tile width; the rest only tunes speed.
 // Wave tiles a launch should have at least, when the plan picks the tile
@@ -437,7 +437,7 @@ bool variant_fits(const Fit &f, const yastn_options &o, int v) {
   if (v >= 1 && v <= kNumMfma) return v == 1 || (f.buf && (o.precision == YASTN_F64 || v == 1 || v == 4));
   if (v == kVariantRows) return f.rows;
   if (v >= kVariantRes0 && v < kVariantPf0) {
-    if (!f.res || !f.buf) return false;
+    if (!f.res || !f.buf || f.kmax > res_max_k(v - kVariantRes0)) return false;
     return o.precision == YASTN_F64 || v == kVariantRes0 + 1;  // FP32: one shape compiled (kResShapes[1])
   }
   if (v >= kVariantPf0 && v < kVariants) {
@@ -452,7 +452,8 @@ Choice choose(const Fit &f, const yastn_options &o, int variant) {
   if (variant == 0) {  // heuristic
     if (f.bf16 || f.mfma_pick || !f.buf) variant = 1;
     else if (f.rows_pick && f.rows) variant = kVariantRows;
-    else if (f.res) variant = kVariantRes0 + 1;
+    else if (f.res && f.kmax <= kResMaxK) variant = kVariantRes0 + 1;
+    else if (f.res && o.precision == YASTN_F64) variant = kVariantRes0 + kNumRes - 1;
     else variant = kVariantPf0;
   }
   const int kq = (f.kmax + 3) / 4;
@@ -673,7 +674,7 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
     pl.kmax = (int)maxk;
     const bool bf16 = o.precision == YASTN_BF16X3 || o.precision == YASTN_BF16X6;
     pl.rows_fit = !bf16 && maxk <= 64 && maxn <= 64;
-    pl.res_fit = !bf16 && maxk <= kResMaxK && !pl.t.bofs_overflow;
+    pl.res_fit = !bf16 && maxk <= kResMaxKWide && !pl.t.bofs_overflow;
     pl.nact = 1;
     for (const DevProb &dp : pl.t.probs) pl.nact = std::max(pl.nact, (int)dp.nact);
     pl.variant = 0;

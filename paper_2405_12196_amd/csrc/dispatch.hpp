@@ -15,18 +15,25 @@ struct Shape {
 };
 constexpr Shape kMfmaShapes[] = {{4, 2}, {4, 1}, {4, 4}, {2, 2}, {2, 4}, {1, 4}};
 constexpr int kNumMfma = sizeof(kMfmaShapes) / sizeof(Shape);
-// k_gemm_res: rows per chunk = 16 * rb, next chunk's A loads issued early
-// (db), occupancy hint (occ waves per SIMD, 0 = none); k slots held = 4 * kq
+// k_gemm_res: rows per chunk = 16 * rb, A loads issued pd chunks ahead of the
+// MFMAs (a ring of pd + 1 register buffers), occupancy hint (occ waves per
+// SIMD); k slots held = 4 * kq.  A higher occupancy hint caps the registers
+// per wave, and wide tiles (more columns, more k slots, deeper rings) then
+// spill to scratch; the autotuner measures the trade.  Occupancy 1 leaves the
+// register file to one wave per SIMD and also takes K up to 80.
 struct ResShape {
-  int rb, db, occ;
+  int rb, pd, occ;
 };
-constexpr ResShape kResShapes[] = {{1, 1, 3}, {2, 0, 3}, {1, 0, 4}, {2, 0, 4}, {4, 0, 2}, {2, 1, 3}};
+constexpr ResShape kResShapes[] = {{1, 1, 3}, {2, 0, 3}, {1, 2, 3}, {2, 1, 3}, {1, 1, 4},
+                                   {1, 2, 2}, {1, 1, 2}, {2, 1, 2}, {1, 1, 1}};
 constexpr int kNumRes = sizeof(kResShapes) / sizeof(ResShape);
-constexpr int kResKq[] = {5, 10, 16};
+constexpr int kResKq[] = {5, 10, 16, 20};
 // k_gemm_pf: rows per chunk = 16 * rb, k-steps per pipelined batch = kb
 constexpr Shape kPfShapes[] = {{4, 2}, {2, 2}, {4, 1}};
 constexpr int kNumPf = sizeof(kPfShapes) / sizeof(Shape);
-constexpr int kResMaxK = 64;
+constexpr int kResMaxK = 64;      // K limit of the shapes with occ > 1
+constexpr int kResMaxKWide = 80;  // K limit of the occupancy-1 shape
+constexpr int res_max_k(int shape) { return kResShapes[shape].occ == 1 ? kResMaxKWide : kResMaxK; }
 
 // FP64 arithmetic (F64 buffers)
 KernelFn gemm4_f64(bool buf, int shape, int cb);

@@ -22,17 +22,18 @@ template <typename Out> KernelFn g4(bool buf, int shape, int cb) {
 }
 template <typename Out, int KQ> KernelFn res_cb(int cb) {
   switch (cb) {
-    case 1: return k_gemm_res<In, F, Out, true, 2, 1, KQ, 4, false, 3>;
-    case 2: return k_gemm_res<In, F, Out, true, 2, 2, KQ, 4, false, 3>;
-    case 3: return k_gemm_res<In, F, Out, true, 2, 3, KQ, 4, false, 3>;
-    default: return k_gemm_res<In, F, Out, true, 2, 4, KQ, 4, false, 3>;
+    case 1: return k_gemm_res<In, F, Out, true, 2, 1, KQ, 4, 0, 3>;
+    case 2: return k_gemm_res<In, F, Out, true, 2, 2, KQ, 4, 0, 3>;
+    case 3: return k_gemm_res<In, F, Out, true, 2, 3, KQ, 4, 0, 3>;
+    default: return k_gemm_res<In, F, Out, true, 2, 4, KQ, 4, 0, 3>;
   }
 }
 template <typename Out> KernelFn res(bool buf, int cb, int kq) {
   if (!buf) return nullptr;
   if (kq <= 5) return res_cb<Out, 5>(cb);
   if (kq <= 10) return res_cb<Out, 10>(cb);
-  return res_cb<Out, 16>(cb);
+  if (kq <= 16) return res_cb<Out, 16>(cb);
+  return nullptr;
 }
 template <typename Out> KernelFn rows(bool buf, int kmax) {
   if (!buf) return k_rows<In, F, Out, false, 64>;

@@ -14,21 +14,25 @@ template <int RB, int KB> KernelFn g4_cb(int cb) {
     default: return k_gemm4<D, D, D, true, RB, 4, KB>;
   }
 }
-template <int RB, int KQ, int NA, bool DB, int OCC> KernelFn res_cb(int cb) {
+template <int RB, int KQ, int NA, int PD, int OCC> KernelFn res_cb(int cb) {
   switch (cb) {
-    case 1: return k_gemm_res<D, D, D, true, RB, 1, KQ, NA, DB, OCC>;
-    case 2: return k_gemm_res<D, D, D, true, RB, 2, KQ, NA, DB, OCC>;
-    case 3: return k_gemm_res<D, D, D, true, RB, 3, KQ, NA, DB, OCC>;
-    default: return k_gemm_res<D, D, D, true, RB, 4, KQ, NA, DB, OCC>;
+    case 1: return k_gemm_res<D, D, D, true, RB, 1, KQ, NA, PD, OCC>;
+    case 2: return k_gemm_res<D, D, D, true, RB, 2, KQ, NA, PD, OCC>;
+    case 3: return k_gemm_res<D, D, D, true, RB, 3, KQ, NA, PD, OCC>;
+    default: return k_gemm_res<D, D, D, true, RB, 4, KQ, NA, PD, OCC>;
   }
 }
-template <int RB, int NA, bool DB, int OCC> KernelFn res_kq(int kq, int cb) {
-  if (kq <= 5) return res_cb<RB, 5, NA, DB, OCC>(cb);
-  if (kq <= 10) return res_cb<RB, 10, NA, DB, OCC>(cb);
-  return res_cb<RB, 16, NA, DB, OCC>(cb);
+template <int RB, int NA, int PD, int OCC> KernelFn res_kq(int kq, int cb) {
+  if (kq <= 5) return res_cb<RB, 5, NA, PD, OCC>(cb);
+  if (kq <= 10) return res_cb<RB, 10, NA, PD, OCC>(cb);
+  if (kq <= 16) return res_cb<RB, 16, NA, PD, OCC>(cb);
+  if constexpr (OCC == 1) {
+    if (kq <= 20) return res_cb<RB, 20, NA, PD, OCC>(cb);
+  }
+  return nullptr;
 }
-template <int RB, bool DB, int OCC> KernelFn res_na(int na, int kq, int cb) {
-  return na <= 2 ? res_kq<RB, 2, DB, OCC>(kq, cb) : res_kq<RB, 4, DB, OCC>(kq, cb);
+template <int RB, int PD, int OCC> KernelFn res_na(int na, int kq, int cb) {
+  return na <= 2 ? res_kq<RB, 2, PD, OCC>(kq, cb) : res_kq<RB, 4, PD, OCC>(kq, cb);
 }
 }  // namespace
 
@@ -46,13 +50,16 @@ KernelFn gemm4_f64(bool buf, int shape, int cb) {
 
 KernelFn res_f64(bool buf, int shape, int cb, int kq, int na) {
   if (!buf) return nullptr;
-  switch (shape) {  // kResShapes
-    case 0: return res_na<1, true, 3>(na, kq, cb);
-    case 1: return res_na<2, false, 3>(na, kq, cb);
-    case 2: return res_na<1, false, 4>(na, kq, cb);
-    case 3: return res_na<2, false, 4>(na, kq, cb);
-    case 4: return res_na<4, false, 2>(na, kq, cb);
-    default: return res_na<2, true, 3>(na, kq, cb);
+  switch (shape) {  // kResShapes {rb, pd, occ}
+    case 0: return res_na<1, 1, 3>(na, kq, cb);
+    case 1: return res_na<2, 0, 3>(na, kq, cb);
+    case 2: return res_na<1, 2, 3>(na, kq, cb);
+    case 3: return res_na<2, 1, 3>(na, kq, cb);
+    case 4: return res_na<1, 1, 4>(na, kq, cb);
+    case 5: return res_na<1, 2, 2>(na, kq, cb);
+    case 6: return res_na<1, 1, 2>(na, kq, cb);
+    case 7: return res_na<2, 1, 2>(na, kq, cb);
+    default: return res_na<1, 1, 1>(na, kq, cb);
   }
 }
 

@@ -209,11 +209,16 @@ template <typename T, int CP> struct Src<T, true, CP> {
                                           kBufFlags);
   }
   __device__ T operator()(int32_t i) const { return BufIo<T>::template ld<CP>(r, i * (int32_t)sizeof(T)); }
+  // element i if v, else 0 (read at a byte offset past any buffer below 2 GiB)
+  __device__ T ld_z(bool v, int32_t i) const {
+    return BufIo<T>::template ld<CP>(r, v ? i * (int32_t)sizeof(T) : (int32_t)(0x80000000u - sizeof(T)));
+  }
 };
 template <typename T, int CP> struct Src<T, false, CP> {
   const T *__restrict__ p;
   __device__ void init(const void *q, int64_t) { p = reinterpret_cast<const T *>(q); }
   __device__ T operator()(int64_t i) const { return p[i]; }
+  __device__ T ld_z(bool v, int64_t i) const { return v ? p[i] : T(0); }
 };
 template <typename T, bool BUF, int CP = 0> struct Dst;
 template <typename T, int CP> struct Dst<T, true, CP> {
@@ -601,10 +606,14 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(LaunchArgs args) {
 // chunks of 16*RB.  The A loads of chunk c+1 are issued before the MFMAs and
 // stores of chunk c, so every wave keeps a chunk of loads in flight while it
 // computes.  NA = free-leg classes supported (nact <= NA).
-template <typename In, typename Cmp, typename Off, bool BUF, int RB, int KQ, int NA>
+template <typename In, typename Off, bool BUF, int RB, int KQ, int NA>
 __device__ __forceinline__ void res_load_chunk(const Src<In, BUF, kStream> &A, const DevRowTuple &rt, int nact, int K,
                                                int32_t row0, int rows, int lane, const Off (&ko)[KQ],
-                                               const int32_t (&pk)[KQ][NA], Cmp (&av)[KQ][RB]) {
+                                               const int32_t (&pk)[KQ][NA], In (&av)[KQ][RB]) {
+  // Loads only (no per-lane branch, no use of a loaded value), so the chunk's
+  // loads stay in flight until its MFMAs: padding rows and k slots past K
+  // read 0 from past the end of the buffer; k quads past K (wave-uniform)
+  // are skipped, their MFMAs too.
   int32_t rg[RB][NA];
   bool rv[RB];
 #pragma unroll
@@ -615,16 +624,40 @@ __device__ __forceinline__ void res_load_chunk(const Src<In, BUF, kStream> &A, c
   }
 #pragma unroll
   for (int q = 0; q < KQ; ++q)
+    if (4 * q < K) {
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      av[q][rb] = Cmp(0);
-      if (4 * q < K && ko[q] >= 0 && rv[rb]) {
+      for (int rb = 0; rb < RB; ++rb) {
         Off o = ko[q];
 #pragma unroll
         for (int a = 0; a < NA; ++a) o += (Off)pk[q][a] * (Off)rg[rb][a];
-        av[q][rb] = Cmp(A(o));
+        av[q][rb] = A.ld_z(ko[q] >= 0 && rv[rb], o);
       }
     }
+}
+
+// The lane's output columns of a tile (MFMA layout: column lane & 15 of each
+// 16-column block): base offset of the column's output block, its width n_j
+// and the column within it; base -1 for padding columns.  Both table reads
+// of every column are issued together.
+template <typename Off, int CB>
+__device__ __forceinline__ void tile_columns(const DevColMap *cmap, const int64_t *cgrid, int ncols, int lane,
+                                             Off (&cbase)[CB], int32_t (&cnj)[CB], int32_t (&ccl)[CB]) {
+  DevColMap cm[CB];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) {
+    const int lc = 16 * cb + (lane & 15);
+    cm[cb] = cmap[lc < ncols ? lc : 0];
+  }
+  int64_t g[CB];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) g[cb] = cgrid[cm[cb].j];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) {
+    const bool v = 16 * cb + (lane & 15) < ncols;
+    cbase[cb] = v ? (Off)g[cb] : (Off)-1;
+    cnj[cb] = cm[cb].nj;
+    ccl[cb] = cm[cb].cl;
+  }
 }
 
 // One tile's record and operands, read field by field with scalar loads.
@@ -675,7 +708,7 @@ __device__ __forceinline__ void rec_setup(const LaunchArgs &args, int t, RecCtx<
   x.C.init(pp.c, c_numel);
 }
 
-template <typename In, typename Cmp, typename Out, bool BUF, int RB, int CB, int KQ, int NA, bool DB, int OCC>
+template <typename In, typename Cmp, typename Out, bool BUF, int RB, int CB, int KQ, int NA, int PD, int OCC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) k_gemm_res(LaunchArgs args) {
   static_assert(NA <= kRecAct + 1, "tile records carry kRecAct class boundaries");
   typedef typename std::conditional<BUF, int32_t, int64_t>::type Off;
@@ -692,57 +725,52 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
     rec_setup<In, Out, BUF>(args, t, x);
     const int K = x.K, N = x.N, nact = x.nact, nrows = x.nrows;
     const int cbn = (x.ncols + 15) >> 4;
-    // output columns of this lane (MFMA layout: lane & 15 within each 16-column block)
-    int64_t cbase[CB];
+    Off cbase[CB];
     int32_t cnj[CB], ccl[CB];
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-      const int lc = 16 * cb + (lane & 15);
-      cbase[cb] = -1;
-      cnj[cb] = 0;
-      ccl[cb] = 0;
-      if (lc < x.ncols) {
-        const DevColMap cm = x.cmap[lc];
-        cbase[cb] = x.cgrid[cm.j];
-        cnj[cb] = cm.nj;
-        ccl[cb] = cm.cl;
-      }
-    }
+    tile_columns<Off, CB>(x.cmap, x.cgrid, x.ncols, lane, cbase, cnj, ccl);
+    // k slots of this lane: offset of (row 0, k), class factors, and the B
+    // values of its columns; every table read is issued before any is used
+    // (k slots past K read entry 0 and are masked afterwards)
     Off ko[KQ];
     int32_t pk[KQ][NA];
     Cmp bv[KQ][CB];
+    {
+      int32_t bo[KQ][CB];
 #pragma unroll
-    for (int q = 0; q < KQ; ++q) {
-      const int k = 4 * q + kl;
-      ko[q] = -1;
+      for (int q = 0; q < KQ; ++q) {
+        const int k = 4 * q + kl;
+        const int kk = k < K ? k : 0;
+        ko[q] = (Off)x.kofs[kk];
 #pragma unroll
-      for (int a = 0; a < NA; ++a) pk[q][a] = 0;
-#pragma unroll
-      for (int cb = 0; cb < CB; ++cb) bv[q][cb] = Cmp(0);
-      if (4 * q < K && k < K) {
-        ko[q] = (Off)x.kofs[k];
-        const DevKP p = x.kp[k];
-#pragma unroll
-        for (int a = 0; a < NA; ++a) pk[q][a] = p.p[a];
+        for (int a = 0; a < NA; ++a) pk[q][a] = x.kp[kk].p[a];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
           const int c = x.n0 + 16 * cb + (lane & 15);
-          if (c < N) {
-            const int32_t o = x.bofs[(int64_t)k * N + c];
-            if (o >= 0) bv[q][cb] = Cmp(x.B(o));
-          }
+          bo[q][cb] = x.bofs[(k < K && c < N) ? (int64_t)kk * N + c : 0];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) {
+        ko[q] = 4 * q + kl < K ? ko[q] : (Off)-1;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+          const int c = x.n0 + 16 * cb + (lane & 15);
+          bv[q][cb] = Cmp(x.B.ld_z(4 * q + kl < K && c < N && bo[q][cb] >= 0, bo[q][cb]));
         }
       }
     }
-    Cmp av[KQ][RB];
-    res_load_chunk<In, Cmp, Off, BUF, RB, KQ, NA>(x.A, x.rt, nact, K, x.m0, min(16 * RB, nrows), lane, ko, pk, av);
-    for (int mc = 0; mc < nrows; mc += 16 * RB) {
+    // rows in chunks of 16 * RB; the A loads of chunk c + PD are issued
+    // before the MFMAs of chunk c (a ring of PD + 1 register buffers)
+    const int nch = (nrows + 16 * RB - 1) / (16 * RB);
+    In ab[PD + 1][KQ][RB];
+    auto load_chunk = [&](int c, In (&dst)[KQ][RB]) {
+      res_load_chunk<In, Off, BUF, RB, KQ, NA>(x.A, x.rt, nact, K, x.m0 + c * 16 * RB,
+                                               min(16 * RB, nrows - c * 16 * RB), lane, ko, pk, dst);
+    };
+    auto compute_chunk = [&](int c, const In (&av)[KQ][RB]) {
+      const int mc = c * 16 * RB;
       const int rows = min(16 * RB, nrows - mc);
       const int rbn = (rows + 15) >> 4;
-      Cmp an[KQ][RB];
-      if (DB && mc + 16 * RB < nrows)
-        res_load_chunk<In, Cmp, Off, BUF, RB, KQ, NA>(x.A, x.rt, nact, K, x.m0 + mc + 16 * RB,
-                                                      min(16 * RB, nrows - mc - 16 * RB), lane, ko, pk, an);
       acc_t acc[RB][CB];
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
@@ -756,7 +784,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
             if (rb < rbn)
 #pragma unroll
               for (int cb = 0; cb < CB; ++cb)
-                if (cb < cbn) acc[rb][cb] = M::run(av[q][rb], bv[q][cb], acc[rb][cb]);
+                if (cb < cbn) acc[rb][cb] = M::run(Cmp(av[q][rb]), bv[q][cb], acc[rb][cb]);
         }
       }
 #pragma unroll
@@ -770,20 +798,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
             const int lr = 16 * rb + M::row(lane, v);
             if (lr < rows) {
               const Out val = Out(acc[rb][cb][v]);
-              x.C.put(cbase[cb] + (int64_t)(x.m0 + mc + lr) * cnj[cb] + ccl[cb], val);
+              x.C.put(cbase[cb] + (Off)(x.m0 + mc + lr) * (Off)cnj[cb] + (Off)ccl[cb], val);
               if (do_norm) nacc.add((double)val);
             }
           }
         }
       }
-      if (DB) {
+    };
 #pragma unroll
-        for (int q = 0; q < KQ; ++q)
+    for (int u = 0; u < PD; ++u)
+      if (u < nch) load_chunk(u, ab[u]);
+    for (int c0 = 0; c0 < nch; c0 += PD + 1) {
 #pragma unroll
-          for (int rb = 0; rb < RB; ++rb) av[q][rb] = an[q][rb];
-      } else if (mc + 16 * RB < nrows) {
-        res_load_chunk<In, Cmp, Off, BUF, RB, KQ, NA>(x.A, x.rt, nact, K, x.m0 + mc + 16 * RB,
-                                                      min(16 * RB, nrows - mc - 16 * RB), lane, ko, pk, av);
+      for (int u = 0; u <= PD; ++u) {
+        const int c = c0 + u;
+        if (c < nch) {
+          if (c + PD < nch) load_chunk(c + PD, ab[(u + PD) % (PD + 1)]);
+          compute_chunk(c, ab[u]);
+        }
       }
     }
     if (do_norm) norm_file_tile(args.norm, t, lane, nacc);
@@ -819,21 +851,9 @@ __global__ void __launch_bounds__(256) k_gemm_pf(LaunchArgs args) {
     const Cmp *__restrict__ Bp = reinterpret_cast<const Cmp *>(cst(&args.jobs[jb].ws)) + x.bpack;
     const int K = x.K, N = x.N, nact = x.nact, nrows = x.nrows;
     const int cbn = (x.ncols + 15) >> 4;
-    int64_t cbase[CB];
+    Off cbase[CB];
     int32_t cnj[CB], ccl[CB];
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-      const int lc = 16 * cb + (lane & 15);
-      cbase[cb] = -1;
-      cnj[cb] = 0;
-      ccl[cb] = 0;
-      if (lc < x.ncols) {
-        const DevColMap cm = x.cmap[lc];
-        cbase[cb] = x.cgrid[cm.j];
-        cnj[cb] = cm.nj;
-        ccl[cb] = cm.cl;
-      }
-    }
+    tile_columns<Off, CB>(x.cmap, x.cgrid, x.ncols, lane, cbase, cnj, ccl);
     for (int mc = 0; mc < nrows; mc += 16 * RB) {
       const int rows = min(16 * RB, nrows - mc);
       const int rbn = (rows + 15) >> 4;
@@ -848,39 +868,38 @@ __global__ void __launch_bounds__(256) k_gemm_pf(LaunchArgs args) {
       // k metadata of a batch: offset of (row 0, k) and class factors
       Off ko[KB];
       int32_t pk[KB][NA];
+      // Loads of a batch are all issued before any is used: k slots past K
+      // and padding rows / columns read entry 0 and are zeroed afterwards.
       auto meta = [&](int kk0, Off (&o)[KB], int32_t (&p)[KB][NA]) {
 #pragma unroll
         for (int q = 0; q < KB; ++q) {
           const int k = kk0 + 4 * q + kl;
-          o[q] = -1;
+          const int kk = k < K ? k : 0;
+          const Off raw = (Off)x.kofs[kk];
 #pragma unroll
-          for (int a = 0; a < NA; ++a) p[q][a] = 0;
-          if (k < K) {
-            o[q] = (Off)x.kofs[k];
-            const DevKP d = x.kp[k];
-#pragma unroll
-            for (int a = 0; a < NA; ++a) p[q][a] = d.p[a];
-          }
+          for (int a = 0; a < NA; ++a) p[q][a] = x.kp[kk].p[a];
+          o[q] = k < K ? raw : (Off)-1;
         }
       };
-      auto load = [&](int kk0, const Off (&o)[KB], const int32_t (&p)[KB][NA], Cmp (&av)[KB][RB], Cmp (&bv)[KB][CB]) {
+      // A reads past K or past the tile's rows return 0 (read past the end of
+      // the buffer); B reads past K or N take entry 0 and the k slots past K
+      // are zeroed where the MFMAs use them, so no loaded value is used before
+      // the MFMAs of the previous batch.
+      auto load = [&](int kk0, const Off (&o)[KB], const int32_t (&p)[KB][NA], In (&av)[KB][RB], Cmp (&bv)[KB][CB]) {
 #pragma unroll
         for (int q = 0; q < KB; ++q) {
           const int k = kk0 + 4 * q + kl;
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb) {
-            av[q][rb] = Cmp(0);
-            if (o[q] >= 0 && rv[rb]) {
-              Off off = o[q];
+            Off off = o[q];
 #pragma unroll
-              for (int a = 0; a < NA; ++a) off += (Off)p[q][a] * (Off)rg[rb][a];
-              av[q][rb] = Cmp(x.A(off));
-            }
+            for (int a = 0; a < NA; ++a) off += (Off)p[q][a] * (Off)rg[rb][a];
+            av[q][rb] = x.A.ld_z(o[q] >= 0 && rv[rb], off);
           }
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb) {
             const int c = x.n0 + 16 * cb + (lane & 15);
-            bv[q][cb] = (k < K && c < N) ? Bp[(int64_t)k * N + c] : Cmp(0);
+            bv[q][cb] = Bp[(k < K && c < N) ? (int64_t)k * N + c : 0];
           }
         }
       };
@@ -889,7 +908,8 @@ __global__ void __launch_bounds__(256) k_gemm_pf(LaunchArgs args) {
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = acc_t{0, 0, 0, 0};
-      Cmp av[KB][RB], bv[KB][CB], an[KB][RB], bn[KB][CB];
+      In av[KB][RB], an[KB][RB];
+      Cmp bv[KB][CB], bn[KB][CB];
       meta(0, ko, pk);
       load(0, ko, pk, av, bv);
       meta(4 * KB, ko, pk);
@@ -900,13 +920,18 @@ __global__ void __launch_bounds__(256) k_gemm_pf(LaunchArgs args) {
           meta(kk0 + 8 * KB, ko, pk);
         }
 #pragma unroll
-        for (int q = 0; q < KB; ++q)
+        for (int q = 0; q < KB; ++q) {
+          const bool kv = kk0 + 4 * q + kl < K;
+          Cmp bq[CB];
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) bq[cb] = kv ? bv[q][cb] : Cmp(0);
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb)
             if (rb < rbn)
 #pragma unroll
               for (int cb = 0; cb < CB; ++cb)
-                if (cb < cbn) acc[rb][cb] = M::run(av[q][rb], bv[q][cb], acc[rb][cb]);
+                if (cb < cbn) acc[rb][cb] = M::run(Cmp(av[q][rb]), bq[cb], acc[rb][cb]);
+        }
         if (more) {
 #pragma unroll
           for (int q = 0; q < KB; ++q) {
@@ -928,7 +953,7 @@ __global__ void __launch_bounds__(256) k_gemm_pf(LaunchArgs args) {
             const int lr = 16 * rb + M::row(lane, v);
             if (lr < rows) {
               const Out val = Out(acc[rb][cb][v]);
-              x.C.put(cbase[cb] + (int64_t)(x.m0 + mc + lr) * cnj[cb] + ccl[cb], val);
+              x.C.put(cbase[cb] + (Off)(x.m0 + mc + lr) * (Off)cnj[cb] + (Off)ccl[cb], val);
               if (do_norm) nacc.add((double)val);
             }
           }

@@ -81,7 +81,7 @@ struct Plan {
   int nch = 1;              // chunks per wave tile
   bool buf_ok = true;       // every buffer small enough for 32-bit buffer addressing
   bool rows_fit = false;    // every sector has K, N <= 64: the row-per-lane kernel can run
-  bool res_fit = false;     // every sector has K <= 64 and B offsets fit int32: k_gemm_res can run
+  bool res_fit = false;     // every sector has K <= 80 and B offsets fit int32: k_gemm_res can run
   int nact = 1;             // largest number of A free-leg classes over the plan's problems
   int variant = 0;          // kernel variant (0 = heuristic; set by yastn_plan_autotune)
   int kmax = 0;             // largest K_X of the plan

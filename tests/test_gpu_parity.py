@@ -265,7 +265,10 @@ def test_norm_f64(n):
 
 
 # ------------------------------------------------------ kernel variants
-@pytest.mark.parametrize("variant", range(1, 17))
+NUM_VARIANTS = 20  # yastn.h YASTN_NUM_VARIANTS
+
+
+@pytest.mark.parametrize("variant", range(1, NUM_VARIANTS))
 @pytest.mark.parametrize("seed", range(10))
 def test_every_variant_matches_oracle(seed, variant):
     import paper_2405_12196_amd as Y
@@ -277,11 +280,34 @@ def test_every_variant_matches_oracle(seed, variant):
     try:
         pl.set_variant(variant)
     except Y.YastnError as e:
-        # the row kernel needs K, N <= 64 and the register-resident B kernels K <= 64
+        # the row kernel needs K, N <= 64, the register-resident B kernels
+        # K <= 64 (variant 16: K <= 80)
         assert e.status == "ERR_STATE" and variant >= 7
-        assert max(pl.stats(0)["max_k"], pl.stats(0)["max_n"] if variant == 7 else 0) > 64
+        limit = 80 if variant == 16 else 64
+        assert max(pl.stats(0)["max_k"], pl.stats(0)["max_n"] if variant == 7 else 0) > limit
         return
     A, B = G.upload(a), G.upload(b)
+    c, s = G.alloc_out(pl, 0)
+    pl.contract([A], [B], [c], G.workspace(pl))
+    torch.cuda.synchronize()
+    check_f64(s, c.cpu().numpy()[:s.numel], ref)
+
+
+@pytest.mark.parametrize("variant", range(0, NUM_VARIANTS))
+def test_config1_every_variant(variant):
+    """Config 1 (K = 76 in its largest sector): every variant that fits,
+    including the occupancy-1 register-resident tiles that take K <= 80."""
+    import paper_2405_12196_amd as Y
+    (p,) = W.config1()
+    ref = oracle.tensordot_dense(p.a, p.b, p.axes_a, p.axes_b)
+    pl = Y.plan([(p.a, p.b, p.axes_a, p.axes_b)])
+    if variant:
+        try:
+            pl.set_variant(variant)
+        except Y.YastnError as e:
+            assert e.status == "ERR_STATE" and 7 <= variant <= 15
+            return
+    A, B = G.upload(p.a), G.upload(p.b)
     c, s = G.alloc_out(pl, 0)
     pl.contract([A], [B], [c], G.workspace(pl))
     torch.cuda.synchronize()
