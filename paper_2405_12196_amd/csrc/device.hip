@@ -408,6 +408,9 @@ KernelFn pf_kernel(const yastn_options &o, bool buf, int shape, int cb, int na) 
 
 KernelFn res_kernel(const yastn_options &o, bool buf, int shape, int cb, int kq, int na) {
   if (o.precision == YASTN_F64) return res_f64(buf, shape, cb, kq, na);
+  if (is_bf16(o))
+    return buf && o.in_dtype == YASTN_DTYPE_F32 ? res_bf16(o.out_dtype, o.precision == YASTN_BF16X3 ? 3 : 6, cb, kq, na)
+                                                 : nullptr;
   return o.in_dtype == YASTN_DTYPE_F64 ? res_f32d(o.out_dtype, buf, cb, kq) : res_f32f(o.out_dtype, buf, cb, kq);
 }
 
@@ -433,7 +436,10 @@ void fit_add(Fit &f, const Plan &p) {
 
 bool variant_fits(const Fit &f, const yastn_options &o, int v) {
   if (v == 0) return true;
-  if (f.bf16) return v == 1;
+  // split-BF16: the packed-B tiles, or register-resident tiles (one shape)
+  // when the operands are FP32 buffers and K <= 64
+  if (f.bf16)
+    return v == 1 || (v == kVariantRes0 && f.res && f.buf && f.kmax <= kResMaxK && o.in_dtype == YASTN_DTYPE_F32);
   if (v >= 1 && v <= kNumMfma) return v == 1 || (f.buf && (o.precision == YASTN_F64 || v == 1 || v == 4));
   if (v == kVariantRows) return f.rows;
   if (v >= kVariantRes0 && v < kVariantPf0) {
@@ -450,9 +456,10 @@ bool variant_fits(const Fit &f, const yastn_options &o, int v) {
 Choice choose(const Fit &f, const yastn_options &o, int variant) {
   if (variant != 0 && !variant_fits(f, o, variant)) variant = 0;
   if (variant == 0) {  // heuristic
-    if (f.bf16 || f.mfma_pick || !f.buf) variant = 1;
+    if (f.mfma_pick || !f.buf) variant = 1;
+    else if (f.bf16) variant = variant_fits(f, o, kVariantRes0) ? kVariantRes0 : 1;
     else if (f.rows_pick && f.rows) variant = kVariantRows;
-    else if (f.res && f.kmax <= kResMaxK) variant = kVariantRes0 + 1;
+    else if (f.res && f.kmax <= kResMaxK) variant = o.precision == YASTN_F64 ? kVariantRes0 : kVariantRes0 + 1;
     else if (f.res && o.precision == YASTN_F64) variant = kVariantRes0 + kNumRes - 1;
     else variant = kVariantPf0;
   }
@@ -674,7 +681,7 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
     pl.kmax = (int)maxk;
     const bool bf16 = o.precision == YASTN_BF16X3 || o.precision == YASTN_BF16X6;
     pl.rows_fit = !bf16 && maxk <= 64 && maxn <= 64;
-    pl.res_fit = !bf16 && maxk <= kResMaxKWide && !pl.t.bofs_overflow;
+    pl.res_fit = maxk <= kResMaxKWide && !pl.t.bofs_overflow;
     pl.nact = 1;
     for (const DevProb &dp : pl.t.probs) pl.nact = std::max(pl.nact, (int)dp.nact);
     pl.variant = 0;

@@ -55,5 +55,7 @@ KernelFn pf_f32f(yastn_dtype out, bool buf, int cb);
 KernelFn pack_f32f();
 // split-BF16 products (nt = 3 or 6), FP32 accumulation
 KernelFn bf16_gemm(yastn_dtype in, yastn_dtype out, int nt, bool buf, int cb);
+// split-BF16 register-resident tiles, FP32 operand buffers, K <= 64 (nullptr otherwise)
+KernelFn res_bf16(yastn_dtype out, int nt, int cb, int kq, int na);
 
 }  // namespace yastn

@@ -708,9 +708,17 @@ __device__ __forceinline__ void rec_setup(const LaunchArgs &args, int t, RecCtx<
   x.C.init(pp.c, c_numel);
 }
 
-template <typename In, typename Cmp, typename Out, bool BUF, int RB, int CB, int KQ, int NA, int PD, int OCC>
+// NT = 0: products in Cmp on the FP64 / FP32 MFMA 16x16x4.  NT = 3 or 6:
+// split-BF16 products (Cmp = float values split into 2 or 3 bf16 terms) on
+// the bf16 MFMA 16x16x32 with FP32 accumulation; eight of the lane's k slots
+// form one instruction's k group (slot q = 8s + j holds k = kl + 4q, the same
+// for A and B, so each group covers k = 32s .. 32s + 31 once).
+template <typename In, typename Cmp, typename Out, bool BUF, int RB, int CB, int KQ, int NA, int PD, int OCC,
+          int NT = 0>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) k_gemm_res(LaunchArgs args) {
   static_assert(NA <= kRecAct + 1, "tile records carry kRecAct class boundaries");
+  static_assert(NT == 0 || (std::is_same<Cmp, float>::value && KQ % 8 == 0), "split-BF16 tiles: FP32 values, 8k slots");
+  constexpr int NS = NT > 3 ? 3 : 2;  // bf16 terms per value
   typedef typename std::conditional<BUF, int32_t, int64_t>::type Off;
   typedef Mfma4<Cmp> M;
   typedef typename M::acc_t acc_t;
@@ -759,6 +767,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
         }
       }
     }
+    // split-BF16: the B terms of each k group, once per tile
+    bf8 bs[NT ? KQ / 8 : 1][CB][NS];
+    if constexpr (NT > 0) {
+#pragma unroll
+      for (int g = 0; g < KQ / 8; ++g)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            __bf16 h, m, l;
+            split3<NT>(bv[8 * g + j][cb], h, m, l);
+            bs[g][cb][0][j] = h;
+            bs[g][cb][1][j] = m;
+            if constexpr (NS > 2) bs[g][cb][NS - 1][j] = l;
+          }
+    }
     // rows in chunks of 16 * RB; the A loads of chunk c + PD are issued
     // before the MFMAs of chunk c (a ring of PD + 1 register buffers)
     const int nch = (nrows + 16 * RB - 1) / (16 * RB);
@@ -776,15 +800,51 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = acc_t{0, 0, 0, 0};
+      if constexpr (NT == 0) {
 #pragma unroll
-      for (int q = 0; q < KQ; ++q) {
-        if (4 * q < K) {
+        for (int q = 0; q < KQ; ++q) {
+          if (4 * q < K) {
 #pragma unroll
-          for (int rb = 0; rb < RB; ++rb)
-            if (rb < rbn)
+            for (int rb = 0; rb < RB; ++rb)
+              if (rb < rbn)
 #pragma unroll
-              for (int cb = 0; cb < CB; ++cb)
-                if (cb < cbn) acc[rb][cb] = M::run(Cmp(av[q][rb]), bv[q][cb], acc[rb][cb]);
+                for (int cb = 0; cb < CB; ++cb)
+                  if (cb < cbn) acc[rb][cb] = M::run(Cmp(av[q][rb]), bv[q][cb], acc[rb][cb]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int g = 0; g < KQ / 8; ++g) {
+          if (32 * g < K) {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+              if (rb >= rbn) continue;
+              bf8 as[NS];
+#pragma unroll
+              for (int j = 0; j < 8; ++j) {
+                __bf16 h, m, l;
+                split3<NT>(Cmp(av[8 * g + j][rb]), h, m, l);
+                as[0][j] = h;
+                as[1][j] = m;
+                if constexpr (NS > 2) as[NS - 1][j] = l;
+              }
+#pragma unroll
+              for (int cb = 0; cb < CB; ++cb) {
+                if (cb >= cbn) continue;
+                acc_t c = acc[rb][cb];
+                // small terms first, the leading product last
+                if constexpr (NS > 2) {
+                  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as[2], bs[g][cb][0], c, 0, 0, 0);
+                  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as[0], bs[g][cb][2], c, 0, 0, 0);
+                  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as[1], bs[g][cb][1], c, 0, 0, 0);
+                }
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as[1], bs[g][cb][0], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as[0], bs[g][cb][1], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as[0], bs[g][cb][0], c, 0, 0, 0);
+                acc[rb][cb] = c;
+              }
+            }
+          }
         }
       }
 #pragma unroll

@@ -185,6 +185,31 @@ def test_reduced_precision_config2_step3(prec, kind):
     assert oracle.rel_frobenius(v, ref.data) <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x6"])
+@pytest.mark.parametrize("variant", [1, 8])
+def test_bf16_tile_kinds_config2_steps(prec, variant):
+    """Split-BF16 with FP32 operand buffers: the packed-B tiles (variant 1)
+    and the register-resident tiles (variant 8, K <= 64) on every corner
+    step, each within the stated error of the FP64 oracle."""
+    import paper_2405_12196_amd as Y
+    t = W.config2()
+    cur = None
+    for i, ((an, bn), (ax, bx)) in enumerate(zip([("C", "T1"), (None, "T4"), (None, "A"), (None, "Ac")], t["axes"])):
+        a = t[an] if an else cur
+        ref = oracle.tensordot_blockpair(a, t[bn], ax, bx)
+        pl = Y.plan([(a, t[bn], ax, bx)], precision=prec, in_dtype=Y.DTYPE_F32, out_dtype=Y.DTYPE_F64)
+        pl.set_variant(variant)
+        A, B = G.upload(a, Y.DTYPE_F32), G.upload(t[bn], Y.DTYPE_F32)
+        c, s = G.alloc_out(pl, 0)
+        pl.contract([A], [B], [c], G.workspace(pl))
+        torch.cuda.synchronize()
+        v = c.cpu().numpy()[:s.numel]
+        assert G.structure_equal(s, ref) and not np.any(np.isnan(v))
+        err = oracle.rel_frobenius(v, ref.data)
+        assert err <= TOL[prec], f"step {i + 1}: {err:.3e}"
+        cur = ref
+
+
 # ------------------------------------------------------------ invariants
 @pytest.mark.parametrize("kind", ["mfma", "rows"])
 def test_repeat_runs_bitwise_identical(kind):
