@@ -700,7 +700,9 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
         for (auto &rt : pl.t.rows) n += ((rt.m + h - 1) / h) * ((pl.t.sectors[rt.sector].N + 16 * cb - 1) / (16 * cb));
         return n;
       };
-      tm = 16;
+      // large-K sectors (K > 64, pipelined kernel) reuse each B batch over at
+      // least 32 rows (measured faster on the 64-problem batches)
+      tm = maxk > kResMaxK ? 32 : 16;
       while (tm < 512 && count(2 * tm) >= kTilesPerLaunchTarget) tm *= 2;
     }
     // tile height = 16 * rb * nch rows

@@ -908,7 +908,9 @@ __global__ void __launch_bounds__(256) k_gemm_pf(LaunchArgs args) {
     rec_setup<In, Out, BUF>(args, t, x);
     int jb = 0;
     while (jb + 1 < args.njobs && t >= args.jobs[jb + 1].tile0) ++jb;
-    const Cmp *__restrict__ Bp = reinterpret_cast<const Cmp *>(cst(&args.jobs[jb].ws)) + x.bpack;
+    // the sector's packed B_X (K x N, row-major) in the workspace
+    Src<Cmp, true> Bq;
+    Bq.init(reinterpret_cast<const Cmp *>(cst(&args.jobs[jb].ws)) + x.bpack, (int64_t)x.K * x.N);
     const int K = x.K, N = x.N, nact = x.nact, nrows = x.nrows;
     const int cbn = (x.ncols + 15) >> 4;
     Off cbase[CB];
@@ -925,26 +927,22 @@ __global__ void __launch_bounds__(256) k_gemm_pf(LaunchArgs args) {
         rv[rb] = lr < rows;
         a_rowparts_fast<NA>(x.rt, nact, x.m0 + mc + (rv[rb] ? lr : 0), rg[rb]);
       }
-      // k metadata of a batch: offset of (row 0, k) and class factors
-      Off ko[KB];
-      int32_t pk[KB][NA];
-      // Loads of a batch are all issued before any is used: k slots past K
-      // and padding rows / columns read entry 0 and are zeroed afterwards.
+      // k metadata of a batch: offset of (row 0, k), -1 where the row tuple
+      // has no A block for k, and class factors (k slots past K read entry
+      // 0; no loaded value is used here)
       auto meta = [&](int kk0, Off (&o)[KB], int32_t (&p)[KB][NA]) {
 #pragma unroll
         for (int q = 0; q < KB; ++q) {
           const int k = kk0 + 4 * q + kl;
           const int kk = k < K ? k : 0;
-          const Off raw = (Off)x.kofs[kk];
+          o[q] = (Off)x.kofs[kk];
 #pragma unroll
           for (int a = 0; a < NA; ++a) p[q][a] = x.kp[kk].p[a];
-          o[q] = k < K ? raw : (Off)-1;
         }
       };
-      // A reads past K or past the tile's rows return 0 (read past the end of
-      // the buffer); B reads past K or N take entry 0 and the k slots past K
-      // are zeroed where the MFMAs use them, so no loaded value is used before
-      // the MFMAs of the previous batch.
+      // A and B reads past K, past the tile's rows or past N return 0 (read
+      // past the end of the buffer), so no loaded value is used before the
+      // MFMAs of the previous batch.
       auto load = [&](int kk0, const Off (&o)[KB], const int32_t (&p)[KB][NA], In (&av)[KB][RB], Cmp (&bv)[KB][CB]) {
 #pragma unroll
         for (int q = 0; q < KB; ++q) {
@@ -954,12 +952,12 @@ __global__ void __launch_bounds__(256) k_gemm_pf(LaunchArgs args) {
             Off off = o[q];
 #pragma unroll
             for (int a = 0; a < NA; ++a) off += (Off)p[q][a] * (Off)rg[rb][a];
-            av[q][rb] = x.A.ld_z(o[q] >= 0 && rv[rb], off);
+            av[q][rb] = x.A.ld_z(k < K && o[q] >= 0 && rv[rb], off);  // kofs < 0: no A block
           }
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb) {
             const int c = x.n0 + 16 * cb + (lane & 15);
-            bv[q][cb] = Bp[(k < K && c < N) ? (int64_t)k * N + c : 0];
+            bv[q][cb] = Bq.ld_z(k < K && c < N, k * N + c);
           }
         }
       };
@@ -968,40 +966,41 @@ __global__ void __launch_bounds__(256) k_gemm_pf(LaunchArgs args) {
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = acc_t{0, 0, 0, 0};
-      In av[KB][RB], an[KB][RB];
-      Cmp bv[KB][CB], bn[KB][CB];
-      meta(0, ko, pk);
-      load(0, ko, pk, av, bv);
-      meta(4 * KB, ko, pk);
-      for (int kk0 = 0; kk0 < K; kk0 += 4 * KB) {
-        const bool more = kk0 + 4 * KB < K;
-        if (more) {
-          load(kk0 + 4 * KB, ko, pk, an, bn);
-          meta(kk0 + 8 * KB, ko, pk);
-        }
+      // Batch n: its k metadata is read two batches ahead, its operands one
+      // batch ahead of its MFMAs, from rings of two register buffers (even /
+      // odd batches).  The loop body is unrolled over one even and one odd
+      // batch and has no load under a branch, so the loads of the next
+      // batches stay in flight during the MFMAs (reads past K are clamped or
+      // zero and feed no MFMA).
+      const int nb = (K + 4 * KB - 1) / (4 * KB);
+      Off mo[2][KB];
+      int32_t mp[2][KB][NA];
+      In ad[2][KB][RB];
+      Cmp bd[2][KB][CB];
+      auto mfma = [&](int kk0, const In (&av)[KB][RB], const Cmp (&bv)[KB][CB]) {
 #pragma unroll
-        for (int q = 0; q < KB; ++q) {
-          const bool kv = kk0 + 4 * q + kl < K;
-          Cmp bq[CB];
+        for (int q = 0; q < KB; ++q)
+          if (kk0 + 4 * q < K)
 #pragma unroll
-          for (int cb = 0; cb < CB; ++cb) bq[cb] = kv ? bv[q][cb] : Cmp(0);
+            for (int rb = 0; rb < RB; ++rb)
+              if (rb < rbn)
 #pragma unroll
-          for (int rb = 0; rb < RB; ++rb)
-            if (rb < rbn)
-#pragma unroll
-              for (int cb = 0; cb < CB; ++cb)
-                if (cb < cbn) acc[rb][cb] = M::run(Cmp(av[q][rb]), bq[cb], acc[rb][cb]);
-        }
-        if (more) {
-#pragma unroll
-          for (int q = 0; q < KB; ++q) {
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) av[q][rb] = an[q][rb];
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb) bv[q][cb] = bn[q][cb];
-          }
-        }
+                for (int cb = 0; cb < CB; ++cb)
+                  if (cb < cbn) acc[rb][cb] = M::run(Cmp(av[q][rb]), bv[q][cb], acc[rb][cb]);
+      };
+      meta(0, mo[0], mp[0]);
+      meta(4 * KB, mo[1], mp[1]);
+      load(0, mo[0], mp[0], ad[0], bd[0]);
+      int n = 0;
+      for (; n + 1 < nb; n += 2) {
+        meta(4 * KB * (n + 2), mo[0], mp[0]);
+        load(4 * KB * (n + 1), mo[1], mp[1], ad[1], bd[1]);
+        mfma(4 * KB * n, ad[0], bd[0]);
+        meta(4 * KB * (n + 3), mo[1], mp[1]);
+        load(4 * KB * (n + 2), mo[0], mp[0], ad[0], bd[0]);
+        mfma(4 * KB * (n + 1), ad[1], bd[1]);
       }
+      if (n < nb) mfma(4 * KB * n, ad[0], bd[0]);
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) {
         if (cb >= cbn || cbase[cb] < 0) continue;

@@ -339,6 +339,31 @@ def test_config1_every_variant(variant):
     check_f64(s, c.cpu().numpy()[:s.numel], ref)
 
 
+@pytest.mark.parametrize("variant", range(0, NUM_VARIANTS))
+def test_missing_a_blocks_every_variant(variant):
+    """Config 1 with every fifth A block absent (lazy storage): rows of a
+    sector then lack A data for part of its k range, which must count as
+    zeros in every kernel."""
+    import paper_2405_12196_amd as Y
+    from workloads import BlockTensor
+    (p,) = W.config1()
+    keep = np.arange(p.a.nblocks) % 5 != 2
+    a = BlockTensor(p.a.sym_mod, p.a.sig, p.a.n, p.a.charges[keep], p.a.shapes[keep], p.a.offsets[keep], p.a.data)
+    ref = oracle.tensordot_dense(a, p.b, p.axes_a, p.axes_b)
+    pl = Y.plan([(a, p.b, p.axes_a, p.axes_b)])
+    if variant:
+        try:
+            pl.set_variant(variant)
+        except Y.YastnError as e:
+            assert e.status == "ERR_STATE" and 7 <= variant <= 15
+            return
+    A, B = G.upload(a), G.upload(p.b)
+    c, s = G.alloc_out(pl, 0)
+    pl.contract([A], [B], [c], G.workspace(pl))
+    torch.cuda.synchronize()
+    check_f64(s, c.cpu().numpy()[:s.numel], ref)
+
+
 def test_autotune_config2_step3_picks_a_correct_variant():
     import paper_2405_12196_amd as Y
     t = W.config2()
