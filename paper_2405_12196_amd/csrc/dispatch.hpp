@@ -28,9 +28,13 @@ constexpr ResShape kResShapes[] = {{1, 1, 3}, {2, 0, 3}, {1, 2, 3}, {2, 1, 3}, {
                                    {1, 2, 2}, {1, 1, 2}, {2, 1, 2}, {1, 1, 1}};
 constexpr int kNumRes = sizeof(kResShapes) / sizeof(ResShape);
 constexpr int kResKq[] = {5, 10, 16, 20};
-// k_gemm_pf: rows per chunk = 16 * rb, k-steps per pipelined batch = kb
-constexpr Shape kPfShapes[] = {{4, 2}, {2, 2}, {4, 1}};
-constexpr int kNumPf = sizeof(kPfShapes) / sizeof(Shape);
+// k_gemm_pf: rows per chunk = 16 * rb, k-steps per pipelined batch = kb,
+// operand loads issued pd batches ahead of the MFMAs
+struct PfShape {
+  int rb, kb, pd;
+};
+constexpr PfShape kPfShapes[] = {{2, 2, 2}, {2, 2, 3}, {4, 1, 3}};
+constexpr int kNumPf = sizeof(kPfShapes) / sizeof(PfShape);
 constexpr int kResMaxK = 64;      // K limit of the shapes with occ > 1
 constexpr int kResMaxKWide = 80;  // K limit of the occupancy-1 shape
 constexpr int res_max_k(int shape) { return kResShapes[shape].occ == 1 ? kResMaxKWide : kResMaxK; }

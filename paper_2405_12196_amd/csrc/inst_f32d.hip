@@ -45,10 +45,10 @@ template <typename Out> KernelFn rows(bool buf, int kmax) {
 template <typename Out> KernelFn pf(bool buf, int cb) {
   if (!buf) return nullptr;
   switch (cb) {
-    case 1: return k_gemm_pf<In, F, Out, true, 4, 1, 2, 4>;
-    case 2: return k_gemm_pf<In, F, Out, true, 4, 2, 2, 4>;
-    case 3: return k_gemm_pf<In, F, Out, true, 4, 3, 2, 4>;
-    default: return k_gemm_pf<In, F, Out, true, 4, 4, 2, 4>;
+    case 1: return k_gemm_pf<In, F, Out, true, 2, 1, 2, 4, 2>;
+    case 2: return k_gemm_pf<In, F, Out, true, 2, 2, 2, 4, 2>;
+    case 3: return k_gemm_pf<In, F, Out, true, 2, 3, 2, 4, 2>;
+    default: return k_gemm_pf<In, F, Out, true, 2, 4, 2, 4, 2>;
   }
 }
 }  // namespace

@@ -64,23 +64,25 @@ KernelFn res_f64(bool buf, int shape, int cb, int kq, int na) {
 }
 
 namespace {
-template <int RB, int KB, int NA> KernelFn pf_cb(int cb) {
+template <int RB, int KB, int NA, int PD> KernelFn pf_cb(int cb) {
   switch (cb) {
-    case 1: return k_gemm_pf<D, D, D, true, RB, 1, KB, NA>;
-    case 2: return k_gemm_pf<D, D, D, true, RB, 2, KB, NA>;
-    case 3: return k_gemm_pf<D, D, D, true, RB, 3, KB, NA>;
-    default: return k_gemm_pf<D, D, D, true, RB, 4, KB, NA>;
+    case 1: return k_gemm_pf<D, D, D, true, RB, 1, KB, NA, PD>;
+    case 2: return k_gemm_pf<D, D, D, true, RB, 2, KB, NA, PD>;
+    case 3: return k_gemm_pf<D, D, D, true, RB, 3, KB, NA, PD>;
+    default: return k_gemm_pf<D, D, D, true, RB, 4, KB, NA, PD>;
   }
 }
-template <int RB, int KB> KernelFn pf_na(int na, int cb) { return na <= 2 ? pf_cb<RB, KB, 2>(cb) : pf_cb<RB, KB, 4>(cb); }
+template <int RB, int KB, int PD> KernelFn pf_na(int na, int cb) {
+  return na <= 2 ? pf_cb<RB, KB, 2, PD>(cb) : pf_cb<RB, KB, 4, PD>(cb);
+}
 }  // namespace
 
 KernelFn pf_f64(bool buf, int shape, int cb, int na) {
   if (!buf) return nullptr;
-  switch (shape) {  // kPfShapes
-    case 1: return pf_na<2, 2>(na, cb);
-    case 2: return pf_na<4, 1>(na, cb);
-    default: return pf_na<4, 2>(na, cb);
+  switch (shape) {  // kPfShapes {rb, kb, pd}
+    case 1: return pf_na<2, 2, 3>(na, cb);
+    case 2: return pf_na<4, 1, 3>(na, cb);
+    default: return pf_na<2, 2, 2>(na, cb);
   }
 }
 

@@ -886,21 +886,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
 // grouped gather GEMM for sectors of any K, software-pipelined over k
 // ---------------------------------------------------------------------------
 // Tiles start from the flat tile record (as k_gemm_res); B comes from the
-// packed B_X in the workspace.  The k loop runs in batches of KB MFMA k-steps:
-// the A and B loads of batch n+1 are issued before the MFMAs of batch n, and
-// the k offsets of batch n+2 before those, so the matrix cores work while the
-// next operands are in flight (large-K sectors, where the MFMA time per tile
-// is long enough to hide the load latency).
-template <typename In, typename Cmp, typename Out, bool BUF, int RB, int CB, int KB, int NA>
+// packed B_X in the workspace.  The k loop runs in batches of KB MFMA k-steps.
+// The tile's k metadata (offset of (row 0, k), -1 where the row tuple has no
+// A block, and the class factors) is staged in LDS once per tile (in segments
+// of kPfSeg entries), so reading it never waits on the operand loads; the A
+// and B loads of batch n + PD are issued before the MFMAs of batch n, from a
+// ring of PD + 1 register buffers, with no load under a branch (reads past K,
+// past the tile's rows or past N return 0 from past the end of the buffer).
+constexpr int kPfSeg = 256;
+
+template <typename In, typename Cmp, typename Out, bool BUF, int RB, int CB, int KB, int NA, int PD>
 __global__ void __launch_bounds__(256) k_gemm_pf(LaunchArgs args) {
   static_assert(NA <= kRecAct + 1, "tile records carry kRecAct class boundaries");
-  typedef typename std::conditional<BUF, int32_t, int64_t>::type Off;
+  static_assert(BUF, "pipelined tiles address every operand through buffer resources");
+  constexpr int R = PD + 1;
   typedef Mfma4<Cmp> M;
   typedef typename M::acc_t acc_t;
+  __shared__ int32_t meta_lds[4][kPfSeg * (1 + NA)];
   const int lane = threadIdx.x & 63;
   const int kl = lane >> 4;
   const int gw = blockIdx.x * 4 + uni(threadIdx.x >> 6);  // wave-uniform
   const int W = gridDim.x * 4;
+  int32_t *const ml = meta_lds[threadIdx.x >> 6];  // this wave's slice
   const bool do_norm = args.norm.parts != nullptr;
   NormAcc nacc;
   for (int t = gw; t < args.ntiles; t += W) {
@@ -913,9 +920,22 @@ __global__ void __launch_bounds__(256) k_gemm_pf(LaunchArgs args) {
     Bq.init(reinterpret_cast<const Cmp *>(cst(&args.jobs[jb].ws)) + x.bpack, (int64_t)x.K * x.N);
     const int K = x.K, N = x.N, nact = x.nact, nrows = x.nrows;
     const int cbn = (x.ncols + 15) >> 4;
-    Off cbase[CB];
-    int32_t cnj[CB], ccl[CB];
-    tile_columns<Off, CB>(x.cmap, x.cgrid, x.ncols, lane, cbase, cnj, ccl);
+    int32_t cbase[CB], cnj[CB], ccl[CB];
+    tile_columns<int32_t, CB>(x.cmap, x.cgrid, x.ncols, lane, cbase, cnj, ccl);
+    // k metadata of k = s0 .. s0 + ks - 1 into LDS (lanes stride the entries;
+    // every lane of the wave reads them after the wave-local fence)
+    auto stage = [&](int s0, int ks) {
+      for (int i = lane; i < ks; i += 64) {
+        ml[i] = (int32_t)x.kofs[s0 + i];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) ml[kPfSeg * (1 + a) + i] = x.kp[s0 + i].p[a];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    const bool one_seg = K <= kPfSeg;
+    if (one_seg) stage(0, K);
     for (int mc = 0; mc < nrows; mc += 16 * RB) {
       const int rows = min(16 * RB, nrows - mc);
       const int rbn = (rows + 15) >> 4;
@@ -927,80 +947,64 @@ __global__ void __launch_bounds__(256) k_gemm_pf(LaunchArgs args) {
         rv[rb] = lr < rows;
         a_rowparts_fast<NA>(x.rt, nact, x.m0 + mc + (rv[rb] ? lr : 0), rg[rb]);
       }
-      // k metadata of a batch: offset of (row 0, k), -1 where the row tuple
-      // has no A block for k, and class factors (k slots past K read entry
-      // 0; no loaded value is used here)
-      auto meta = [&](int kk0, Off (&o)[KB], int32_t (&p)[KB][NA]) {
-#pragma unroll
-        for (int q = 0; q < KB; ++q) {
-          const int k = kk0 + 4 * q + kl;
-          const int kk = k < K ? k : 0;
-          o[q] = (Off)x.kofs[kk];
-#pragma unroll
-          for (int a = 0; a < NA; ++a) p[q][a] = x.kp[kk].p[a];
-        }
-      };
-      // A and B reads past K, past the tile's rows or past N return 0 (read
-      // past the end of the buffer), so no loaded value is used before the
-      // MFMAs of the previous batch.
-      auto load = [&](int kk0, const Off (&o)[KB], const int32_t (&p)[KB][NA], In (&av)[KB][RB], Cmp (&bv)[KB][CB]) {
-#pragma unroll
-        for (int q = 0; q < KB; ++q) {
-          const int k = kk0 + 4 * q + kl;
-#pragma unroll
-          for (int rb = 0; rb < RB; ++rb) {
-            Off off = o[q];
-#pragma unroll
-            for (int a = 0; a < NA; ++a) off += (Off)p[q][a] * (Off)rg[rb][a];
-            av[q][rb] = x.A.ld_z(k < K && o[q] >= 0 && rv[rb], off);  // kofs < 0: no A block
-          }
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb) {
-            const int c = x.n0 + 16 * cb + (lane & 15);
-            bv[q][cb] = Bq.ld_z(k < K && c < N, k * N + c);
-          }
-        }
-      };
       acc_t acc[RB][CB];
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = acc_t{0, 0, 0, 0};
-      // Batch n: its k metadata is read two batches ahead, its operands one
-      // batch ahead of its MFMAs, from rings of two register buffers (even /
-      // odd batches).  The loop body is unrolled over one even and one odd
-      // batch and has no load under a branch, so the loads of the next
-      // batches stay in flight during the MFMAs (reads past K are clamped or
-      // zero and feed no MFMA).
-      const int nb = (K + 4 * KB - 1) / (4 * KB);
-      Off mo[2][KB];
-      int32_t mp[2][KB][NA];
-      In ad[2][KB][RB];
-      Cmp bd[2][KB][CB];
-      auto mfma = [&](int kk0, const In (&av)[KB][RB], const Cmp (&bv)[KB][CB]) {
+      for (int s0 = 0; s0 < K; s0 += kPfSeg) {
+        const int ks = min(kPfSeg, K - s0);
+        if (!one_seg) stage(s0, ks);
+        const int nb = (ks + 4 * KB - 1) / (4 * KB);
+        In ad[R][KB][RB];
+        Cmp bd[R][KB][CB];
+        // operands of batch n (k = s0 + 4 KB n + 4 q + kl)
+        auto load = [&](int n, In (&av)[KB][RB], Cmp (&bv)[KB][CB]) {
 #pragma unroll
-        for (int q = 0; q < KB; ++q)
-          if (kk0 + 4 * q < K)
+          for (int q = 0; q < KB; ++q) {
+            const int ki = 4 * KB * n + 4 * q + kl;  // index within the segment
+            const bool kv = ki < ks;
+            const int kc = kv ? ki : 0;
+            const int32_t o = ml[kc];
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
-              if (rb < rbn)
+            for (int rb = 0; rb < RB; ++rb) {
+              int32_t off = o;
 #pragma unroll
-                for (int cb = 0; cb < CB; ++cb)
-                  if (cb < cbn) acc[rb][cb] = M::run(Cmp(av[q][rb]), bv[q][cb], acc[rb][cb]);
-      };
-      meta(0, mo[0], mp[0]);
-      meta(4 * KB, mo[1], mp[1]);
-      load(0, mo[0], mp[0], ad[0], bd[0]);
-      int n = 0;
-      for (; n + 1 < nb; n += 2) {
-        meta(4 * KB * (n + 2), mo[0], mp[0]);
-        load(4 * KB * (n + 1), mo[1], mp[1], ad[1], bd[1]);
-        mfma(4 * KB * n, ad[0], bd[0]);
-        meta(4 * KB * (n + 3), mo[1], mp[1]);
-        load(4 * KB * (n + 2), mo[0], mp[0], ad[0], bd[0]);
-        mfma(4 * KB * (n + 1), ad[1], bd[1]);
+              for (int a = 0; a < NA; ++a) off += ml[kPfSeg * (1 + a) + kc] * rg[rb][a];
+              av[q][rb] = x.A.ld_z(kv && o >= 0 && rv[rb], off);
+            }
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+              const int c = x.n0 + 16 * cb + (lane & 15);
+              bv[q][cb] = Bq.ld_z(kv && c < N, (s0 + ki) * N + c);
+            }
+          }
+        };
+        auto mfma = [&](int n, const In (&av)[KB][RB], const Cmp (&bv)[KB][CB]) {
+#pragma unroll
+          for (int q = 0; q < KB; ++q)
+            if (4 * KB * n + 4 * q < ks)
+#pragma unroll
+              for (int rb = 0; rb < RB; ++rb)
+                if (rb < rbn)
+#pragma unroll
+                  for (int cb = 0; cb < CB; ++cb)
+                    if (cb < cbn) acc[rb][cb] = M::run(Cmp(av[q][rb]), bv[q][cb], acc[rb][cb]);
+        };
+#pragma unroll
+        for (int u = 0; u < PD; ++u) load(u, ad[u], bd[u]);
+        int n = 0;
+        for (; n + R <= nb; n += R) {
+#pragma unroll
+          for (int u = 0; u < R; ++u) {
+            load(n + u + PD, ad[(u + PD) % R], bd[(u + PD) % R]);
+            mfma(n + u, ad[u], bd[u]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < PD; ++u)
+          if (n + u < nb) mfma(n + u, ad[u], bd[u]);
       }
-      if (n < nb) mfma(4 * KB * n, ad[0], bd[0]);
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) {
         if (cb >= cbn || cbase[cb] < 0) continue;
@@ -1012,7 +1016,7 @@ __global__ void __launch_bounds__(256) k_gemm_pf(LaunchArgs args) {
             const int lr = 16 * rb + M::row(lane, v);
             if (lr < rows) {
               const Out val = Out(acc[rb][cb][v]);
-              x.C.put(cbase[cb] + (Off)(x.m0 + mc + lr) * (Off)cnj[cb] + (Off)ccl[cb], val);
+              x.C.put(cbase[cb] + (x.m0 + mc + lr) * cnj[cb] + ccl[cb], val);
               if (do_norm) nacc.add((double)val);
             }
           }
