@@ -67,15 +67,20 @@ class HipEvents:
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ctm_corner_chi128_D8_f64_hbm_traffic.json")
 
 
+# the sources that define the contraction kernels, their instances, tables
+# and launches (the counters in profiles/ are valid while these are unchanged)
+CONTRACTION_SOURCES = ("device.hip", "dispatch.hpp", "host.cpp", "index.hpp", "inst_f64.hip", "kernels.hpp",
+                       "plan.hpp", "planner.hpp")
+
+
 def kernel_source_hash():
-    """sha256 over the library's kernel and dispatch sources."""
+    """sha256 over the contraction kernels' sources."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2405_12196_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp", ".cpp")):
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
+    for f in CONTRACTION_SOURCES:
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()
 
 
@@ -358,9 +363,26 @@ def precision_section(torch, Y, W, ev, sp, K, plain_value):
     return out
 
 
+def cold_time(torch, ev, sp, fn, reps=10):
+    """Median ms of fn(stream) with the 256 MB Infinity Cache flushed first:
+    a 512 MiB fill runs on the same stream before each timed call."""
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device="cuda:0")
+    evs = [(ev.new(), ev.new()) for _ in range(reps)]
+    for r, (a, b) in enumerate(evs):
+        flush.fill_(r & 0xFF)
+        ev.record(a, sp)
+        fn(sp)
+        ev.record(b, sp)
+    torch.cuda.synchronize()
+    del flush
+    return float(np.median([ev.ms(a, b) for a, b in evs]))
+
+
 def batch_section(torch, Y, W, ev, sp):
     """Config-1 batches (N copies of the U(1) rank-4 tensordot, D = 18) and the
-    64 independent U(1) problems of uneven D in grouped launches."""
+    64 independent U(1) problems of uneven D in grouped launches; warm (inputs
+    resident in the caches from the previous launch) and cold (Infinity Cache
+    flushed before each launch)."""
     res = {}
     cases = [("cfg1_x64", W.config1(64), "f64"), ("cfg1_x512", W.config1(512), "f64"),
              ("cfg3_64probs", W.config3(), "f64"), ("cfg3_64probs_f32", W.config3(), "f32")]
@@ -379,13 +401,16 @@ def batch_section(torch, Y, W, ev, sp):
         useful = sum(x["useful_flops"] for x in st)
         byts = sum(x["alg_bytes"] for x in st)
         ms = graph_time(torch, ev, sp, lambda s_: pl.contract(A, B, C, ws, stream=s_))
+        cold = cold_time(torch, ev, sp, lambda s_: pl.contract(A, B, C, ws, stream=s_))
         tf = useful / (ms * 1e-3) / 1e12
         peak = FP64_MFMA_PEAK_TFS if f64 else FP32_MFMA_PEAK_TFS
         res[name] = {"problems": len(probs), "precision": prec, "us_per_launch": round(ms * 1e3, 2),
                      "useful_TFs": round(tf, 3), "frac_of_mfma_peak": round(tf / peak, 4),
                      "achieved_GBs": round(byts / (ms * 1e-3) / 1e9, 1), "useful_flop": int(useful),
                      "alg_bytes": int(byts), "launch_groups": (len(probs) + 63) // 64,
-                     "variant": pl.variant_id, "inputs": "resident, warm (repeated launches)",
+                     "cold_us_per_launch": round(cold * 1e3, 2),
+                     "cold_useful_TFs": round(useful / (cold * 1e-3) / 1e12, 3),
+                     "variant": pl.variant_id, "inputs": "resident; warm = repeated launches, cold = MALL flushed",
                      "autotune_ms": [round(x, 4) for x in tune_ms] if tune_ms else None}
         del pl, A, B, C, ws
         torch.cuda.empty_cache()
@@ -466,7 +491,7 @@ def main():
     ap.add_argument("--precision", default="f64", choices=["f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--cpu-reps", type=int, default=2)
+    ap.add_argument("--cpu-reps", type=int, default=5)
     ap.add_argument("--tile-rows", type=int, default=0, help="rows per wave tile: 64, 128, 256, 512 or 0 (plan's choice)")
     ap.add_argument("--no-tune", action="store_true", help="skip the kernel-variant autotuner")
     ap.add_argument("--variants", default="",
