@@ -286,6 +286,52 @@ yastn_status yastn_norm(const void *x, int64_t n, yastn_dtype dtype, double *out
  * make sure no launch that uses the plan is still running. */
 void yastn_free(yastn_plan_t plan);
 
+/* ---- leg permutation (transpose) of a block tensor ----------------------
+ * Y = transpose(X, perm): leg i of Y is leg perm[i] of X (numpy convention).
+ * Each block of X with charges (t_0..t_{r-1}) becomes the block of Y with
+ * charges (t_perm[0]..t_perm[r-1]), its elements permuted the same way
+ * (Sec. II.A: a block is a dense array indexed by its legs; permuting legs
+ * permutes the charge tuple and the block's axes together).  Y's blocks are
+ * ordered ascending by charge tuple and stored contiguously; signature and
+ * total charge follow the legs.  yastn_perm_plan validates X as yastn_plan
+ * does (perm must be a permutation of 0..rank-1, else YASTN_ERR_ARG) and
+ * uploads one table; yastn_permute is asynchronous on hip_stream, reads X
+ * [device] (dtype) and overwrites every element of Y [device] (same dtype,
+ * yastn_perm_output numel elements).  X and Y must not overlap.  One
+ * element per thread, writes coalesced, HBM-bound. */
+typedef struct yastn_perm_s *yastn_perm_t;
+yastn_status yastn_perm_plan(const yastn_tensor_desc *x, const int32_t *perm, void *hip_stream, yastn_perm_t *out);
+yastn_status yastn_perm_output(yastn_perm_t p, yastn_tensor_desc *y, int64_t *y_numel);
+yastn_status yastn_permute(yastn_perm_t p, yastn_dtype dtype, const void *x, void *y, void *hip_stream);
+void yastn_perm_free(yastn_perm_t p);
+
+/* ---- gradient of a tensordot (reverse mode, real arithmetic) ------------
+ * For C = tensordot(A, B, axes) and a scalar loss L with dC = dL/dC (C's
+ * structure, as yastn_plan_output gives it), the gradient with respect to
+ * A (wrt = 0) is dA = transpose(tensordot(dC, B*, axes = (dC's B-free legs,
+ * B's free legs)), back to A's leg order), and with respect to B (wrt = 1)
+ * dB = transpose(tensordot(A*, dC, axes = (A's free legs, dC's A-free
+ * legs)), back to B's leg order).  B* is B with flipped signatures and total
+ * charge, the same real data (the conjugate of Sec. II.A), so the contracted
+ * legs are dual and the result carries A's (B's) signature and total charge.
+ * The gradient's block list is the structural output of that contraction:
+ * every block of A's (B's) charge sectors that some pair reaches, in
+ * ascending charge order (blocks of A that no pair reaches are absent, their
+ * gradient is zero).  yastn_grad_plan plans both steps (one contraction with
+ * opts, one permutation when the leg orders differ); yastn_grad runs them on
+ * hip_stream: dc [device] (opts.in_dtype), other = B for wrt 0 or A for
+ * wrt 1 [device] (opts.in_dtype), out [device] (opts.out_dtype,
+ * yastn_grad_output numel elements), workspace [device] of
+ * yastn_grad_workspace bytes. */
+typedef struct yastn_grad_s *yastn_grad_t;
+yastn_status yastn_grad_plan(const yastn_problem *prob, int32_t wrt, const yastn_options *opts, void *hip_stream,
+                             yastn_grad_t *out);
+yastn_status yastn_grad_output(yastn_grad_t g, yastn_tensor_desc *d, int64_t *numel);
+yastn_status yastn_grad_workspace(yastn_grad_t g, size_t *bytes);
+yastn_status yastn_grad(yastn_grad_t g, const void *dc, const void *other, void *out, void *workspace,
+                        void *hip_stream);
+void yastn_grad_free(yastn_grad_t g);
+
 const char *yastn_last_error(void);
 const char *yastn_status_string(yastn_status s);
 int32_t yastn_abi_version(void);

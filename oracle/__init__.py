@@ -13,6 +13,9 @@ Implementations (each cites the passage of the paper it follows):
   * ``tensordot_blocks``   O2 for chosen output blocks only (full-size samples);
   * ``tensordot_brute``    (O3) pure-Python loops over every dense index;
   * ``fuse_legs`` / ``unfuse_legs`` (O-fuse) leg fusion and its inverse;
+  * ``transpose``          leg permutation of a block tensor;
+  * ``dual`` / ``tensordot_grad`` the conjugate and the reverse-mode gradient
+                           of a tensordot with respect to either operand;
   * ``validate_*``         structural checks with the library's status classes;
   * ``norms``              Frobenius norm and max-abs of a block tensor;
   * ``structure_stats``    matched pairs, sectors, useful flops, bytes.
@@ -26,6 +29,6 @@ from .blocksparse import (  # noqa: F401
     OracleError, ERR_ARG, ERR_SYM, ERR_CHARGE, ERR_SIGNATURE, ERR_SHAPE,
     ERR_DUPLICATE, normalize, validate_tensor, validate_pair, output_structure,
     tensordot_dense, tensordot_blockpair, tensordot_blocks, tensordot_brute, to_dense,
-    leg_index_maps, fuse_legs, unfuse_legs, transpose, norms, structure_stats,
+    leg_index_maps, fuse_legs, unfuse_legs, transpose, dual, tensordot_grad, norms, structure_stats,
     rel_frobenius, same_structure,
 )

@@ -493,6 +493,37 @@ def transpose(t: BlockTensor, perm):
                        offsets, np.concatenate(datas) if datas else np.zeros(0))
 
 
+def dual(t: BlockTensor) -> BlockTensor:
+    """The conjugate of a real block tensor: the same blocks and data with
+    every signature and the total charge flipped (Sec. II.A, conjugation), so
+    each of its legs contracts with the matching leg of t."""
+    out = t.copy()
+    out.sig = (-np.asarray(t.sig)).astype(np.int8)
+    out.n = np.array(_nq(-np.asarray(t.n, dtype=np.int64), t.sym_mod), dtype=np.int32)
+    return out
+
+
+def tensordot_grad(a: BlockTensor, b: BlockTensor, axes_a, axes_b, dc: BlockTensor, wrt: int) -> BlockTensor:
+    """Reverse mode of C = tensordot(A, B, axes) for real data: with dC the
+    gradient of a scalar loss with respect to C, dA[i, k] = sum_j dC[i, j]
+    B[k, j] and dB[k, j] = sum_i A[i, k] dC[i, j] (i: free legs of A, j:
+    free legs of B, k: contracted).  Each is a tensordot against the dual of
+    the other operand (Sec. II.B), with its legs then put back in the
+    operand's order."""
+    axes_a, axes_b = list(axes_a), list(axes_b)
+    fa, fb = _free(a.rank, axes_a), _free(b.rank, axes_b)
+    if wrt == 0:
+        r = tensordot_blockpair(dc, dual(b), [len(fa) + i for i in range(len(fb))], fb)
+        # legs of r: A's free legs, then B's contracted legs in B's leg order
+        legs = list(fa) + [axes_a[axes_b.index(l)] for l in sorted(axes_b)]
+    else:
+        r = tensordot_blockpair(dual(a), dc, list(fa), list(range(len(fa))))
+        # legs of r: A's contracted legs in A's leg order (as B's), then B's free legs
+        legs = [axes_b[axes_a.index(l)] for l in sorted(axes_a)] + list(fb)
+    perm = [legs.index(l) for l in range(len(legs))]
+    return transpose(r, perm)
+
+
 # ---------------------------------------------------------------------------
 # norms, comparisons, counts
 # ---------------------------------------------------------------------------

@@ -36,7 +36,9 @@ EXPORTS = ["yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_pla
            "yastn_free", "yastn_last_error", "yastn_status_string", "yastn_abi_version",
            "yastn_plan_autotune", "yastn_plan_set_variant",
            "yastn_server_create", "yastn_server_submit", "yastn_server_step", "yastn_server_query",
-           "yastn_server_forget", "yastn_server_drain", "yastn_server_get_stats", "yastn_server_destroy"]
+           "yastn_server_forget", "yastn_server_drain", "yastn_server_get_stats", "yastn_server_destroy",
+           "yastn_perm_plan", "yastn_perm_output", "yastn_permute", "yastn_perm_free",
+           "yastn_grad_plan", "yastn_grad_output", "yastn_grad_workspace", "yastn_grad", "yastn_grad_free"]
 REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 MAX_CHAIN = 8
 NUM_VARIANTS = 20
@@ -139,6 +141,21 @@ def lib():
         L.yastn_last_error.restype = C.c_char_p
         L.yastn_status_string.restype = C.c_char_p
         L.yastn_status_string.argtypes = [C.c_int32]
+        L.yastn_perm_plan.argtypes = [C.POINTER(TensorDesc), C.POINTER(C.c_int32), C.c_void_p, C.POINTER(C.c_void_p)]
+        L.yastn_perm_output.argtypes = [C.c_void_p, C.POINTER(TensorDesc), C.POINTER(C.c_int64)]
+        L.yastn_permute.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.yastn_perm_free.argtypes = [C.c_void_p]
+        L.yastn_perm_free.restype = None
+        L.yastn_grad_plan.argtypes = [C.POINTER(Problem), C.c_int32, C.POINTER(Options), C.c_void_p,
+                                      C.POINTER(C.c_void_p)]
+        L.yastn_grad_output.argtypes = [C.c_void_p, C.POINTER(TensorDesc), C.POINTER(C.c_int64)]
+        L.yastn_grad_workspace.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
+        L.yastn_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.yastn_grad_free.argtypes = [C.c_void_p]
+        L.yastn_grad_free.restype = None
+        for f in ("yastn_perm_plan", "yastn_perm_output", "yastn_permute", "yastn_grad_plan", "yastn_grad_output",
+                  "yastn_grad_workspace", "yastn_grad"):
+            getattr(L, f).restype = C.c_int32
         for f in ("yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats",
                   "yastn_contract", "yastn_contract_norm", "yastn_contract_timed", "yastn_contract_jobs", "yastn_norm",
                   "yastn_plan_autotune", "yastn_plan_set_variant", "yastn_plan_info", "yastn_server_create",
@@ -230,6 +247,22 @@ def _stream(stream) -> int:
     return int(stream.cuda_stream)
 
 
+def _structure(d, n) -> Structure:
+    """Copy a descriptor the library owns into a Structure."""
+    nb, r, s = d.nblocks, d.rank, d.nsym
+
+    def cp(ptr, count, dtype):
+        if count == 0:
+            return np.zeros(0, dtype=dtype)
+        return np.ctypeslib.as_array(ptr, shape=(count,)).astype(dtype, copy=True)
+    return Structure(tuple(int(v) for v in cp(d.sym_mod, s, np.int32)),
+                     cp(d.sig, r, np.int8) if r else np.zeros(0, np.int8),
+                     cp(d.n, s, np.int32),
+                     cp(d.charges, nb * r * s, np.int32).reshape(nb, r, s),
+                     cp(d.shapes, nb * r, np.int64).reshape(nb, r),
+                     cp(d.offsets, nb, np.int64), int(n.value))
+
+
 class Plan:
     """A validated, matched and tiled set of tensordot problems (yastn_plan)."""
 
@@ -270,18 +303,7 @@ class Plan:
         d = TensorDesc()
         n = C.c_int64()
         _check(lib().yastn_plan_output(self._h, p, C.byref(d), C.byref(n)))
-        nb, r, s = d.nblocks, d.rank, d.nsym
-
-        def cp(ptr, count, dtype):
-            if count == 0:
-                return np.zeros(0, dtype=dtype)
-            return np.ctypeslib.as_array(ptr, shape=(count,)).astype(dtype, copy=True)
-        return Structure(tuple(int(v) for v in cp(d.sym_mod, s, np.int32)),
-                         cp(d.sig, r, np.int8) if r else np.zeros(0, np.int8),
-                         cp(d.n, s, np.int32),
-                         cp(d.charges, nb * r * s, np.int32).reshape(nb, r, s),
-                         cp(d.shapes, nb * r, np.int64).reshape(nb, r),
-                         cp(d.offsets, nb, np.int64), int(n.value))
+        return _structure(d, n)
 
     def stats(self, p: int = 0) -> dict:
         st = Stats()
@@ -350,6 +372,86 @@ class Plan:
 
 def plan(problems, **kw) -> Plan:
     return Plan(problems, **kw)
+
+
+class Perm:
+    """Leg permutation of a block tensor (yastn_perm_plan / yastn_permute)."""
+
+    def __init__(self, x, perm, stream=None):
+        keep = _Keep()
+        d = _desc(x, keep)
+        pa = _arr(list(perm), np.int32)
+        h = C.c_void_p()
+        _check(lib().yastn_perm_plan(C.byref(d), keep.ptr(pa, C.c_int32), C.c_void_p(_stream(stream)),
+                                     C.byref(h)))
+        self._h = h
+
+    def output(self) -> Structure:
+        d, n = TensorDesc(), C.c_int64()
+        _check(lib().yastn_perm_output(self._h, C.byref(d), C.byref(n)))
+        return _structure(d, n)
+
+    def permute(self, x, y, dtype=DTYPE_F64, stream=None):
+        _check(lib().yastn_permute(self._h, int(dtype), C.c_void_p(_ptr(x)), C.c_void_p(_ptr(y)),
+                                   C.c_void_p(_stream(stream))))
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().yastn_perm_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Grad:
+    """Gradient of C = tensordot(A, B, axes) with respect to A (wrt=0) or B
+    (wrt=1), given dC (yastn_grad_plan / yastn_grad)."""
+
+    def __init__(self, a, b, axes_a, axes_b, wrt, precision="f64", in_dtype=None, out_dtype=None, stream=None):
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        if in_dtype is None:
+            in_dtype = DTYPE_F64 if prec == F64 else DTYPE_F32
+        if out_dtype is None:
+            out_dtype = DTYPE_F64 if prec == F64 else DTYPE_F32
+        self.in_dtype, self.out_dtype = in_dtype, out_dtype
+        keep = _Keep()
+        pr = Problem()
+        pr.a, pr.b = _desc(a, keep), _desc(b, keep)
+        xa, xb = _arr(list(axes_a), np.int32), _arr(list(axes_b), np.int32)
+        pr.ncontract = int(len(axes_a)) if len(axes_a) == len(axes_b) else -1
+        pr.axes_a, pr.axes_b = keep.ptr(xa, C.c_int32), keep.ptr(xb, C.c_int32)
+        opts = Options(prec, in_dtype, out_dtype, 0, 0)
+        h = C.c_void_p()
+        _check(lib().yastn_grad_plan(C.byref(pr), int(wrt), C.byref(opts), C.c_void_p(_stream(stream)),
+                                     C.byref(h)))
+        self._h = h
+        ws = C.c_size_t()
+        _check(lib().yastn_grad_workspace(h, C.byref(ws)))
+        self.workspace_bytes = int(ws.value)
+
+    def output(self) -> Structure:
+        d, n = TensorDesc(), C.c_int64()
+        _check(lib().yastn_grad_output(self._h, C.byref(d), C.byref(n)))
+        return _structure(d, n)
+
+    def run(self, dc, other, out, workspace, stream=None):
+        _check(lib().yastn_grad(self._h, C.c_void_p(_ptr(dc)), C.c_void_p(_ptr(other)), C.c_void_p(_ptr(out)),
+                                C.c_void_p(_ptr(workspace)), C.c_void_p(_stream(stream))))
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().yastn_grad_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def contract_jobs(jobs, stream=None):

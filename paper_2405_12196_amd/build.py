@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libyastn.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["device.hip", "host.cpp", "serve.cpp", "inst_f64.hip", "inst_f32d.hip", "inst_f32f.hip", "inst_bf16.hip"]
+SOURCES = ["device.hip", "host.cpp", "serve.cpp", "ops.hip", "inst_f64.hip", "inst_f32d.hip", "inst_f32f.hip",
+           "inst_bf16.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

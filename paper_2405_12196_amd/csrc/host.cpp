@@ -157,6 +157,17 @@ yastn_status check_options(const yastn_options *o, yastn_options *out) {
   return YASTN_OK;
 }
 
+yastn_status validate_tensor(const yastn_tensor_desc &d, const char *name, HostTensor &t) {
+  if (d.nsym < 1 || d.nsym > YASTN_MAX_NSYM) return set_error(YASTN_ERR_ARG, std::string(name) + ": nsym out of range");
+  if (!d.sym_mod) return set_error(YASTN_ERR_ARG, std::string(name) + ": null sym_mod");
+  for (int c = 0; c < d.nsym; ++c)
+    if (d.sym_mod[c] < 0 || d.sym_mod[c] == 1) return set_error(YASTN_ERR_SYM, "sym_mod must be 0 (U(1)) or >= 2 (Z_m)");
+  yastn_status st = copy_tensor(d, t, name);
+  if (st != YASTN_OK) return st;
+  std::vector<std::map<std::vector<int32_t>, int64_t>> dims;
+  return check_tensor(t, name, dims);
+}
+
 yastn_status validate_problem(const yastn_problem &p, HostProblem &hp) {
   const yastn_tensor_desc &A = p.a, &B = p.b;
   if (p.ncontract < 0 || p.ncontract > YASTN_MAX_RANK) return set_error(YASTN_ERR_ARG, "ncontract out of range");

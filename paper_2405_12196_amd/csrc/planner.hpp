@@ -99,6 +99,8 @@ yastn_status set_error(yastn_status s, const std::string &msg);
 // host.cpp
 yastn_status check_options(const yastn_options *o, yastn_options *out);
 yastn_status validate_problem(const yastn_problem &p, HostProblem &hp);
+// one tensor alone: symmetry, signatures, dims, duplicates, conservation, offsets
+yastn_status validate_tensor(const yastn_tensor_desc &d, const char *name, HostTensor &t);
 void contracted_keys(const HostTensor &t, const int *axes, int nc, std::vector<int32_t> &keys);
 yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::pair<int32_t, int32_t>> &pairs,
                              int64_t a_base, int64_t b_base, PlanTables &t, int rb, int cb, int nch);

@@ -332,3 +332,72 @@ def test_sampled_blocks_equal_full_blockpair(step):
                 assert np.array_equal(blocks[k], full.block(k))
             return
         cur = oracle.tensordot_blockpair(a, t[bn], ax, bx)
+
+
+# ---------------------------------------------------------- transpose, gradient
+def _inner(x, y):
+    """Sum over the blocks the two tensors share (matched by charge tuple) of
+    the elementwise products."""
+    xn, yn = oracle.normalize(x), oracle.normalize(y)
+    ky = {tuple(yn.charges[b].ravel().tolist()): b for b in range(yn.nblocks)}
+    s = 0.0
+    for b in range(xn.nblocks):
+        k = tuple(xn.charges[b].ravel().tolist())
+        if k in ky:
+            s += float(np.sum(xn.block(b) * yn.block(ky[k])))
+    return s
+
+
+def _with_data(t, rng):
+    out = t.copy()
+    out.data = rng.standard_normal(int(t.block_sizes.sum()))
+    return out
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_transpose_equals_dense_transpose(seed):
+    a, _, _, _ = random_problem(seed + 7100, ["U1", "Z2", "U1xU1"][seed % 3], rank_a=2 + seed % 3, rank_b=1,
+                                max_sectors=3, max_dim=3, shuffle=True)
+    perm = list(np.random.default_rng(seed).permutation(a.rank))
+    t = oracle.transpose(a, perm)
+    oracle.validate_tensor(t)
+    da = oracle.to_dense(a, oracle.leg_index_maps(a))
+    dt = oracle.to_dense(t, oracle.leg_index_maps(t))
+    assert np.array_equal(np.transpose(da, perm), dt)
+
+
+@pytest.mark.parametrize("wrt", [0, 1])
+@pytest.mark.parametrize("seed", range(8))
+def test_grad_adjoint_identity(seed, wrt):
+    """<E, dA> = <dC, tensordot(E, B)> for any E with A's structure (and the
+    same for B): the defining property of the gradient of a linear map,
+    checked with the dense contraction (O1) on the right-hand side."""
+    sym = ["U1", "Z2", "U1xZ2", "Z3"][seed % 4]
+    a, b, xa, xb = random_problem(seed + 7200, sym, rank_a=1 + seed % 4, rank_b=1 + (seed // 2) % 4,
+                                  max_sectors=3, max_dim=3, shuffle=seed % 2 == 0)
+    rng = np.random.default_rng(seed)
+    dc = _with_data(oracle.tensordot_dense(a, b, xa, xb), rng)
+    g = oracle.tensordot_grad(a, b, xa, xb, dc, wrt)
+    op = a if wrt == 0 else b
+    oracle.validate_tensor(g)
+    assert g.rank == op.rank and list(g.sig) == list(op.sig)
+    assert list(g.n) == list(oracle.normalize(op).n)
+    e = _with_data(op, rng)
+    ce = oracle.tensordot_dense(e, b, xa, xb) if wrt == 0 else oracle.tensordot_dense(a, e, xa, xb)
+    lhs, rhs = _inner(e, g), _inner(ce, dc)
+    assert abs(lhs - rhs) <= 1e-10 * max(1.0, abs(rhs))
+
+
+def test_grad_config1_matches_matrix_form():
+    """Config 1 (A's contracted legs trail, B's lead): the gradient is the
+    plain matrix product in each sector, dA = dC B^T, checked densely."""
+    (p,) = W.config1()
+    rng = np.random.default_rng(1)
+    c = oracle.tensordot_dense(p.a, p.b, p.axes_a, p.axes_b)
+    dc = _with_data(c, rng)
+    ga = oracle.tensordot_grad(p.a, p.b, p.axes_a, p.axes_b, dc, 0)
+    ma = oracle.leg_index_maps(ga)
+    dd = oracle.to_dense(dc, oracle.leg_index_maps(dc))
+    db = oracle.to_dense(p.b, oracle.leg_index_maps(p.b))
+    ref = np.tensordot(dd, db, axes=([2, 3], [2, 3]))
+    assert np.allclose(oracle.to_dense(ga, ma), ref, rtol=0, atol=1e-12)
