@@ -417,6 +417,41 @@ def batch_section(torch, Y, W, ev, sp):
     return res
 
 
+def grad_section(torch, Y, W, ev, sp):
+    """Reverse mode of the chi = 128 corner steps 3 and 4: dA and dB (one
+    contraction with the dual of the other operand, then the permutation back
+    to the operand's leg order), timed as graphs of repeated calls; the step
+    inputs come from the library's own forward chain."""
+    t = W.config2()
+    up = lambda x: torch.from_numpy(np.ascontiguousarray(x.data)).to("cuda:0")
+    res, cur, cur_dev = {}, None, None
+    for i, ((an, bn), (ax, bx)) in enumerate(zip(STEPS, t["axes"])):
+        a, a_dev = (t[an], up(t[an])) if an else (cur, cur_dev)
+        b_dev = up(t[bn])
+        pl = Y.plan([(a, t[bn], ax, bx)], stream=sp)
+        c = torch.empty(max(1, pl.output(0).numel), dtype=torch.float64, device="cuda:0")
+        ws = torch.empty(max(256, pl.workspace_bytes), dtype=torch.uint8, device="cuda:0")
+        pl.contract([a_dev], [b_dev], [c], ws, stream=sp)
+        if i >= 2:
+            flop = pl.stats(0)["useful_flops"]
+            dc = torch.randn(c.numel(), dtype=torch.float64, device="cuda:0")
+            for wrt in (0, 1):
+                g = Y.Grad(a, t[bn], ax, bx, wrt, stream=sp)
+                o = g.output()
+                out = torch.empty(max(1, o.numel), dtype=torch.float64, device="cuda:0")
+                gws = torch.empty(max(256, g.workspace_bytes), dtype=torch.uint8, device="cuda:0")
+                other = b_dev if wrt == 0 else a_dev
+                ms = graph_time(torch, ev, sp, lambda s_: g.run(dc, other, out, gws, stream=s_))
+                res[f"step{i + 1}_d{'AB'[wrt]}"] = {"us": round(ms * 1e3, 2),
+                                                   "useful_TFs": round(flop / (ms * 1e-3) / 1e12, 3),
+                                                   "grad_numel": int(o.numel)}
+                del g, out, gws
+        torch.cuda.synchronize()
+        cur, cur_dev = pl.output(0), c
+    torch.cuda.empty_cache()
+    return res
+
+
 def serving_section(torch, Y, W, sp, nreq=64, budget_gib=32, seed=5):
     """32 concurrent CTM runs (16 Z2, 16 U(1); D in {4,6,8,10} x chi in
     {64,128,192,256}) submit enlarged-corner requests with Poisson arrivals to
@@ -729,6 +764,7 @@ def main():
         torch.cuda.empty_cache()
         extras = {"precision": precision_section(torch, Y, W, ev, sp, max(10, K // 10), plain["value"] if plain else None),
                   "batched": batch_section(torch, Y, W, ev, sp),
+                  "gradient": grad_section(torch, Y, W, ev, sp),
                   "serving": serving_section(torch, Y, W, sp, nreq=args.serve_requests)}
 
     rec = {

@@ -305,7 +305,8 @@ yastn_status upload(Plan &pl) {
          o_aoff = take(bytes_of(t.aoff)), o_cgrid = take(bytes_of(t.cgrid)), o_bb = take(bytes_of(t.bblocks)),
          o_tiles = take(bytes_of(t.tiles)), o_items = take(bytes_of(t.items)), o_kofs = take(bytes_of(t.kofs)),
          o_kp = take(bytes_of(t.kp)), o_cm = take(bytes_of(t.colmap)), o_bofs = take(bytes_of(t.bofs)),
-         o_recs = take(t.tiles.size() * sizeof(DevTileRec)), o_plan = take(sizeof(DevPlan));
+         o_recs = take(t.tiles.size() * sizeof(DevTileRec)), o_red = take(t.red.size() * sizeof(DevRedItem)),
+         o_plan = take(sizeof(DevPlan));
   char *base;
   yastn_status s = dmalloc(&base, off);
   if (s) return s;
@@ -349,6 +350,24 @@ yastn_status upload(Plan &pl) {
   std::vector<DevTileRec> recs;
   build_tile_records(pl, dp, recs);
   put(o_recs, recs.data(), recs.size() * sizeof(DevTileRec));
+  // split-K groups with absolute table addresses
+  std::vector<DevRedItem> red(t.red.size());
+  for (size_t i = 0; i < t.red.size(); ++i) {
+    const RedGroup &g = t.red[i];
+    DevRedItem &d = red[i];
+    d.cmap = dp.colmap + t.sectors[g.sector].cm0 + g.n0;
+    d.cgrid = dp.cgrid + t.rows[g.rowtuple].cgrid;
+    d.off0 = g.off0;
+    d.slot_bytes = g.slot_bytes;
+    d.prob = g.prob;
+    d.m0 = g.m0;
+    d.nrows = g.nrows;
+    d.ncols = g.ncols;
+    d.nslots = g.nslots;
+    d.pad = 0;
+  }
+  put(o_red, red.data(), red.size() * sizeof(DevRedItem));
+  pl.dred = red.empty() ? nullptr : reinterpret_cast<const DevRedItem *>(base + o_red);
   dp.ntiles = (int32_t)t.tiles.size();
   dp.nitems = (int32_t)t.items.size();
   put(o_plan, &dp, sizeof(dp));
@@ -418,6 +437,7 @@ KernelFn res_kernel(const yastn_options &o, bool buf, int shape, int cb, int kq,
 struct Fit {
   int cb = 1, kmax = 0, nact = 1;
   bool buf = true, rows = true, res = true, bf16 = false;
+  bool split = false;     // some plan has split-K tiles (only the pipelined kernel writes partials)
   bool rows_pick = true;  // every plan asked for the row kernel (YASTN_FLAG_ROWS)
   bool mfma_pick = true;  // every plan asked for MFMA tiles (YASTN_FLAG_MFMA)
 };
@@ -430,12 +450,14 @@ void fit_add(Fit &f, const Plan &p) {
   f.rows = f.rows && p.rows_fit;
   f.res = f.res && p.res_fit;
   f.bf16 = is_bf16(p.opts);
+  f.split = f.split || !p.t.red.empty();
   f.rows_pick = f.rows_pick && p.opts.flags == YASTN_FLAG_ROWS;
   f.mfma_pick = f.mfma_pick && p.opts.flags == YASTN_FLAG_MFMA;
 }
 
 bool variant_fits(const Fit &f, const yastn_options &o, int v) {
   if (v == 0) return true;
+  if (f.split && (v < kVariantPf0 || !f.buf)) return false;
   // split-BF16: the packed-B tiles, or register-resident tiles (one shape)
   // when the operands are FP32 buffers and K <= 64
   if (f.bf16)
@@ -511,14 +533,19 @@ yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const
   }
   const Choice ch = choose(fit, o, variant);
   if (!ch.gemm) return set_error(YASTN_ERR_STATE, "no kernel instance for this plan");
+  if (fit.split && ch.fam != FAM_PF)
+    return set_error(YASTN_ERR_STATE, "a plan with split-K sectors runs only on the pipelined kernel (32-bit buffers)");
   // the norm rides in the epilogue of the register-resident and pipelined kernels
-  const bool fuse = norm_out && jobs.size() == 1 && (ch.fam == FAM_RES || ch.fam == FAM_PF);
+  const bool fuse = norm_out && jobs.size() == 1 && !fit.split && (ch.fam == FAM_RES || ch.fam == FAM_PF);
+  // the split-K reduction kernel of this arithmetic (accumulator -> output type)
+  const void *reduce = fit.split ? reinterpret_cast<const void *>(split_reduce(o.precision, o.out_dtype)) : nullptr;
   if (norm_fused) *norm_fused = fuse;
   size_t ji = 0;
   while (ji < jobs.size()) {
     LaunchArgs la;
     std::memset(&la, 0, sizeof(la));
     int np = 0;
+    const size_t j_first = ji;
     while (ji < jobs.size() && la.njobs < kMaxJobs) {
       const JobRef &j = jobs[ji];
       const int n = j.g->phi - j.g->plo;
@@ -560,6 +587,21 @@ yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const
       // capped by the launch limit)
       unsigned g = (unsigned)std::max<int64_t>(1, (la.ntiles + 3) / 4);
       YASTN_HIP(hipLaunchKernel(reinterpret_cast<const void *>(ch.gemm), dim3(g), dim3(256), kargs, 0, st));
+    }
+    // split-K: sum every group's partial slots into C, slot by slot
+    for (size_t k = j_first; reduce && k < ji; ++k) {
+      const JobRef &j = jobs[k];
+      if (j.g->r1 <= j.g->r0) continue;
+      RedArgs ra;
+      std::memset(&ra, 0, sizeof(ra));
+      ra.items = j.plan->dred + j.g->r0;
+      ra.nitems = j.g->r1 - j.g->r0;
+      ra.plo = j.g->plo;
+      ra.ws = reinterpret_cast<const char *>(j.ws);
+      for (int p = j.g->plo; p < j.g->phi; ++p) ra.p[p - j.g->plo] = ProbPtrs{j.a[p], j.b[p], j.c[p]};
+      void *rargs[] = {&ra};
+      unsigned g = (unsigned)std::min<int64_t>(ra.nitems, 4096);
+      YASTN_HIP(hipLaunchKernel(reduce, dim3(g), dim3(256), rargs, 0, st));
     }
     if (events && events[2]) YASTN_HIP(hipEventRecord(reinterpret_cast<hipEvent_t>(events[2]), st));
   }
@@ -658,7 +700,7 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
       for (int p = 0; p < nprob; ++p) {
         pl.prob_t0.push_back((int32_t)pl.t.tiles.size());
         pl.prob_i0.push_back((int32_t)pl.t.items.size());
-        yastn_status st2 = build_structure(pl.probs[p], p, allpairs[p], a_base, b_base, pl.t, rb, cb, nch);
+        yastn_status st2 = build_structure(pl.probs[p], p, allpairs[p], a_base, b_base, pl.t, rb, cb, nch, !is_bf16(o));
         if (st2 != YASTN_OK) return st2;
         a_base += pl.probs[p].a.nblocks;
         b_base += pl.probs[p].b.nblocks;

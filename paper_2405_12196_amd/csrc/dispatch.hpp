@@ -8,6 +8,10 @@
 namespace yastn {
 
 typedef void (*KernelFn)(LaunchArgs);
+typedef void (*ReduceFn)(RedArgs);
+
+// the split-K reduction of an arithmetic (FP64, or FP32 accumulators) into out
+ReduceFn split_reduce(yastn_precision precision, yastn_dtype out);
 
 // k_gemm4 tile shapes: rows per chunk = 16 * rb, k-steps per load batch = kb.
 struct Shape {

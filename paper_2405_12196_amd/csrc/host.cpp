@@ -243,7 +243,7 @@ struct SectorBuild {
 }  // namespace
 
 yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::pair<int32_t, int32_t>> &pairs,
-                             int64_t a_base, int64_t b_base, PlanTables &t, int rb, int cb, int nch) {
+                             int64_t a_base, int64_t b_base, PlanTables &t, int rb, int cb, int nch, bool ksplit) {
   const HostTensor &A = hp.a, &B = hp.b;
   const int nsym = A.nsym, nc = hp.nc;
   // ---- group matches by sector X = sum over A's contracted legs of s_i rho_i
@@ -516,6 +516,15 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
       }
       const int32_t row_id = (int32_t)t.rows.size();
       t.rows.push_back(rt);
+      // split-K: a sector with a long K (few, long tiles: small M and N) is
+      // computed in nslots k ranges by separate tiles (same output tile), each
+      // into its own partial slot, summed afterwards in slot order
+      int32_t nslots = 1, chunk = (int32_t)K;
+      if (ksplit && K > kSplitMinK) {
+        nslots = (int32_t)std::min<int64_t>(kSplitMaxSlots, (K + kSplitChunk - 1) / kSplitChunk);
+        chunk = (int32_t)(((K + nslots - 1) / nslots + 7) / 8 * 8);
+        nslots = (int32_t)((K + chunk - 1) / chunk);
+      }
       for (int32_t m0 = 0; m0 < rt.m; m0 += TM)
         for (int32_t n0 = 0; n0 < N; n0 += TN) {
           DevTile tl{};
@@ -525,9 +534,20 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
           tl.n0 = n0;
           tl.nrows = std::min<int32_t>(TM, rt.m - m0);
           tl.ncols = std::min<int32_t>(TN, N - n0);
-          t.tiles.push_back(tl);
-          S.tiles += 1;
-          S.mfma_flops += 2.0 * (16.0 * ((tl.nrows + 15) / 16)) * (4.0 * ((K + 3) / 4)) * (16.0 * ((tl.ncols + 15) / 16));
+          tl.red = -1;
+          if (nslots > 1) {
+            tl.red = (int32_t)t.red.size();
+            t.red.push_back(RedGroup{prob, row_id, sec_id, m0, n0, tl.nrows, tl.ncols, nslots});
+          }
+          for (int32_t sl = 0; sl < nslots; ++sl) {
+            tl.k0 = sl * chunk;
+            tl.kn = (int32_t)std::min<int64_t>(chunk, K - tl.k0);
+            tl.part = sl;
+            t.tiles.push_back(tl);
+            S.tiles += 1;
+            S.mfma_flops += 2.0 * (16.0 * ((tl.nrows + 15) / 16)) * (4.0 * ((tl.kn + 3) / 4)) *
+                            (16.0 * ((tl.ncols + 15) / 16));
+          }
         }
     }
     S.max_m = std::max<int64_t>(S.max_m, M);
@@ -566,13 +586,16 @@ void finish_tiles(Plan &plan) {
     g.t1 = plan.prob_t0[g.phi];
     g.i0 = plan.prob_i0[g.plo];
     g.i1 = plan.prob_i0[g.phi];
+    g.r0 = g.r1 = 0;
+    while (g.r0 < (int32_t)t.red.size() && t.red[g.r0].prob < g.plo) ++g.r0;
+    g.r1 = g.r0;
+    while (g.r1 < (int32_t)t.red.size() && t.red[g.r1].prob < g.phi) ++g.r1;
     std::vector<double> cost(size_t(g.t1 - g.t0));
     for (int32_t i = g.t0; i < g.t1; ++i) {
       const DevTile &tl = t.tiles[i];
-      const DevSector &ds = t.sectors[t.rows[tl.rowtuple].sector];
       double rows = 16.0 * ((tl.nrows + 15) / 16), cols = 16.0 * ((tl.ncols + 15) / 16);
-      double k4 = 4.0 * ((ds.K + 3) / 4);
-      cost[i - g.t0] = 2.0 * rows * k4 * cols / 9.8 + 8.0 * tl.nrows * (double(ds.K) + tl.ncols);
+      double k4 = 4.0 * ((tl.kn + 3) / 4);
+      cost[i - g.t0] = 2.0 * rows * k4 * cols / 9.8 + 8.0 * tl.nrows * (double(tl.kn) + tl.ncols);
     }
     std::vector<size_t> order(cost.size());
     std::iota(order.begin(), order.end(), 0);
@@ -585,6 +608,12 @@ void finish_tiles(Plan &plan) {
   const size_t elem = plan.opts.precision == YASTN_F64 ? 8 : 4;
   plan.norm_off = ((size_t(t.bpack_elems) * elem + 255) / 256) * 256;
   plan.ws_bytes = plan.norm_off + ((t.tiles.size() * 2 * sizeof(double) + 255) / 256) * 256;
+  // split-K partial slots (accumulators of the compute type, 64 columns a row)
+  for (RedGroup &r : t.red) {
+    r.off0 = (int64_t)plan.ws_bytes;
+    r.slot_bytes = (int64_t)(((size_t(r.nrows) * 64 * elem + 255) / 256) * 256);
+    plan.ws_bytes += size_t(r.slot_bytes) * r.nslots;
+  }
 }
 
 void build_tile_records(const Plan &plan, const DevPlan &at, std::vector<DevTileRec> &recs) {
@@ -596,9 +625,9 @@ void build_tile_records(const Plan &plan, const DevPlan &at, std::vector<DevTile
     const DevSector &sec = t.sectors[tl.sector];
     const DevProb &pr = t.probs[sec.prob];
     DevTileRec &r = recs[i];
-    r.kofs = at.kofs + rt.kofs;
-    r.kp = at.kp + sec.kp0;
-    r.bofs = at.bofs + sec.bofs0;
+    r.kofs = at.kofs + rt.kofs + tl.k0;
+    r.kp = at.kp + sec.kp0 + tl.k0;
+    r.bofs = at.bofs + sec.bofs0 + int64_t(tl.k0) * sec.N;
     r.cmap = at.colmap + sec.cm0 + tl.n0;
     r.cgrid = at.cgrid + rt.cgrid;
     r.a_span = pr.a_span;
@@ -608,11 +637,13 @@ void build_tile_records(const Plan &plan, const DevPlan &at, std::vector<DevTile
     r.nrows = tl.nrows;
     r.n0 = tl.n0;
     r.ncols = tl.ncols;
-    r.K = sec.K;
+    r.K = tl.kn;
     r.N = sec.N;
     r.nact = sec.nact;
     r.prob = sec.prob;
-    r.bpack = sec.bpack;
+    r.bpack = sec.bpack + int64_t(tl.k0) * sec.N;
+    r.split = tl.red >= 0 ? 1 : 0;
+    r.part = tl.red >= 0 ? t.red[tl.red].off0 + int64_t(tl.part) * t.red[tl.red].slot_bytes : 0;
     for (int a = 0; a < kRecAct; ++a) {
       r.lsuf[a] = a + 1 <= sec.nact ? rt.lsuf[a + 1] : 1;
       r.lsh[a] = a + 1 <= sec.nact ? rt.lsh[a + 1] : 31;

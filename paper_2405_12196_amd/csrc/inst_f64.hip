@@ -86,6 +86,11 @@ KernelFn pf_f64(bool buf, int shape, int cb, int na) {
   }
 }
 
+ReduceFn split_reduce(yastn_precision precision, yastn_dtype out) {
+  if (precision == YASTN_F64) return k_split_reduce<double, double>;
+  return out == YASTN_DTYPE_F64 ? k_split_reduce<float, double> : k_split_reduce<float, float>;
+}
+
 KernelFn rows_f64(bool buf, int kmax) {
   if (!buf) return k_rows<D, D, D, false, 64>;
   if (kmax <= 16) return k_rows<D, D, D, true, 16>;

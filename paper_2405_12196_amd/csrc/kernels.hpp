@@ -668,6 +668,8 @@ template <typename In, typename Out, bool BUF> struct RecCtx {
   const DevColMap *cmap;
   const int64_t *cgrid;
   int32_t m0, nrows, n0, ncols, K, N, nact;
+  int32_t split;   // 1: split-K tile, accumulators go to the partial slot at `part`
+  int64_t part;    // workspace byte offset of the partial slot
   int64_t bpack;   // the sector's packed B_X in the workspace (elements)
   DevRowTuple rt;  // only lsuf / lmag / lsh of classes 1..kRecAct are filled
   Src<In, BUF, kStream> A;
@@ -695,6 +697,8 @@ __device__ __forceinline__ void rec_setup(const LaunchArgs &args, int t, RecCtx<
   x.N = cst(&r->N);
   x.nact = cst(&r->nact);
   x.bpack = cst(&r->bpack);
+  x.split = cst(&r->split);
+  x.part = cst(&r->part);
   const int32_t prob = cst(&r->prob);
 #pragma unroll
   for (int a = 0; a < kRecAct; ++a) {
@@ -1005,6 +1009,21 @@ __global__ void __launch_bounds__(256) k_gemm_pf(LaunchArgs args) {
         for (int u = 0; u < PD; ++u)
           if (n + u < nb) mfma(n + u, ad[u], bd[u]);
       }
+      if (x.split) {
+        // split-K tile: the accumulators, row r and column c of the tile at
+        // r * 64 + c of its partial slot (summed into C by k_split_reduce)
+        Cmp *pt = reinterpret_cast<Cmp *>(cst(&args.jobs[jb].ws) + x.part);
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int lr = 16 * rb + M::row(lane, v);
+              if (lr < rows) pt[(mc + lr) * 64 + 16 * cb + (lane & 15)] = acc[rb][cb][v];
+            }
+        continue;
+      }
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) {
         if (cb >= cbn || cbase[cb] < 0) continue;
@@ -1024,6 +1043,31 @@ __global__ void __launch_bounds__(256) k_gemm_pf(LaunchArgs args) {
       }
     }
     if (do_norm) norm_file_tile(args.norm, t, lane, nacc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// split-K reduction: the output tile of each group is the sum of its partial
+// slots, taken in slot order (a fixed order, so results are reproducible),
+// written into C's blocks through the column map as the GEMM epilogue does
+// ---------------------------------------------------------------------------
+template <typename Acc, typename Out>
+__global__ void __launch_bounds__(256) k_split_reduce(RedArgs args) {
+  for (int i = blockIdx.x; i < args.nitems; i += gridDim.x) {
+    const DevRedItem &it = args.items[i];
+    Out *C = reinterpret_cast<Out *>(args.p[it.prob - args.plo].c);
+    const int n = it.nrows * 64;
+    for (int e = threadIdx.x; e < n; e += 256) {
+      const int r = e >> 6, c = e & 63;
+      if (c >= it.ncols) continue;
+      const DevColMap cm = it.cmap[c];
+      const int64_t base = it.cgrid[cm.j];
+      if (base < 0) continue;
+      Acc sum = 0;
+      const char *slot = args.ws + it.off0;
+      for (int s = 0; s < it.nslots; ++s, slot += it.slot_bytes) sum += reinterpret_cast<const Acc *>(slot)[e];
+      C[base + (int64_t)(it.m0 + r) * cm.nj + cm.cl] = Out(sum);
+    }
   }
 }
 

@@ -107,6 +107,19 @@ struct DevTile {               // one wave tile: rows [m0, m0 + nrows) of a row 
   int32_t n0;                  // first column within the sector
   int32_t nrows;               // rows (a multiple of the chunk height except at the tuple's end)
   int32_t ncols;               // columns (<= 16 * column blocks of the kernel)
+  int32_t k0, kn;              // k range [k0, k0 + kn) of the sector (all of K unless split)
+  int32_t red;                 // split-K group (index into the plan's groups) or -1
+  int32_t part;                // this tile's partial slot within its split-K group
+};
+
+// A split-K group: the k ranges of one output tile, computed by separate
+// tiles into partial slots of the workspace and summed in slot order into C.
+struct DevRedItem {
+  const DevColMap *cmap;       // the sector's column map, from the tile's first column
+  const int64_t *cgrid;        // the row tuple's output block offsets
+  int64_t off0;                // workspace byte offset of slot 0
+  int64_t slot_bytes;          // bytes of one slot (nrows x 64 accumulators)
+  int32_t prob, m0, nrows, ncols, nslots, pad;
 };
 
 // Everything one wave needs to start a tile, in one record of absolute
@@ -125,9 +138,10 @@ struct DevTileRec {
   int32_t lsuf[kRecAct];       // Lsuf_1 .. Lsuf_kRecAct of the row tuple
   int32_t lsh[kRecAct];
   uint32_t lmag[kRecAct];
-  int32_t pad;
-  int64_t bpack;               // the sector's packed B_X in the workspace (elements)
-  int64_t pad2[2];
+  int32_t split;               // 1: a split-K tile, accumulators go to its partial slot; 0: to C
+  int64_t bpack;               // the sector's packed B_X from k0 on, in the workspace (elements)
+  int64_t part;                // split-K tiles: workspace byte offset of the partial slot
+  int64_t pad2;
 };
 static_assert(sizeof(DevTileRec) == 160, "tile record layout");
 
@@ -184,6 +198,14 @@ struct LaunchArgs {
   int32_t njobs, ntiles, nitems, pad;
   NormArgs norm;
   JobArg jobs[kMaxJobs];
+  ProbPtrs p[kMaxProbs];
+};
+
+// The split-K reduction of one job: its groups' slots summed into C.
+struct RedArgs {
+  const DevRedItem *items;
+  int32_t nitems, plo;         // plo: plan problem of p[0]
+  const char *ws;
   ProbPtrs p[kMaxProbs];
 };
 

@@ -41,6 +41,13 @@ struct HostProblem {
   yastn_stats stats{};
 };
 
+// A split-K group on the host (see DevRedItem): one output tile whose K range
+// is computed by nslots tiles into partial slots.
+struct RedGroup {
+  int32_t prob, rowtuple, sector, m0, n0, nrows, ncols, nslots;
+  int64_t off0 = 0, slot_bytes = 0;  // set when the workspace is laid out
+};
+
 // Device tables of a plan, built on the host and uploaded once.
 struct PlanTables {
   std::vector<DevProb> probs;
@@ -60,6 +67,7 @@ struct PlanTables {
   std::vector<int32_t> bofs;
   int64_t bpack_elems = 0;  // packed B elements in the workspace
   bool bofs_overflow = false;  // some B offset does not fit in int32 (no direct B reads then)
+  std::vector<RedGroup> red;   // split-K groups, in problem order
 };
 
 // Problems are launched in groups of at most kMaxProbs (their device pointers
@@ -68,6 +76,7 @@ struct Group {
   int32_t plo, phi;          // problems [plo, phi)
   int32_t t0, t1;            // plan-local tiles
   int32_t i0, i1;            // plan-local pack items
+  int32_t r0, r1;            // split-K groups of these problems
 };
 
 struct Plan {
@@ -88,6 +97,7 @@ struct Plan {
   void *dev_mem = nullptr;  // one device allocation holding every table
   DevPlan *dplan = nullptr; // device copy of the table of pointers
   const DevTileRec *drecs = nullptr;  // device tile records
+  const DevRedItem *dred = nullptr;   // device split-K groups (null when none)
   size_t ws_bytes = 0;
   size_t norm_off = 0;      // workspace offset of the fused norm's per-tile parts
   int device = 0;
@@ -102,8 +112,11 @@ yastn_status validate_problem(const yastn_problem &p, HostProblem &hp);
 // one tensor alone: symmetry, signatures, dims, duplicates, conservation, offsets
 yastn_status validate_tensor(const yastn_tensor_desc &d, const char *name, HostTensor &t);
 void contracted_keys(const HostTensor &t, const int *axes, int nc, std::vector<int32_t> &keys);
+// ksplit: sectors with K > kSplitMinK are computed in k ranges (split-K)
+constexpr int64_t kSplitMinK = 4096, kSplitChunk = 2048, kSplitMaxSlots = 128;
 yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::pair<int32_t, int32_t>> &pairs,
-                             int64_t a_base, int64_t b_base, PlanTables &t, int rb, int cb, int nch);
+                             int64_t a_base, int64_t b_base, PlanTables &t, int rb, int cb, int nch,
+                             bool ksplit = false);
 void finish_tiles(Plan &plan);
 // Tile records with absolute addresses: `at` gives the address of each table
 // (device addresses for the GPU, host vector data for the CPU replay).

@@ -478,3 +478,56 @@ def test_fused_norm_empty_output():
     pl.contract_norm([G.upload(a)], [G.upload(b)], [c], G.workspace(pl), nout)
     torch.cuda.synchronize()
     assert nout.cpu().tolist() == [0.0, 0.0]
+
+
+# ------------------------------------------------------------------ split-K
+def _long_k_problem(seed):
+    """A(i, k1, k2) . B(k1, k2, j), U(1): small M and N (i, j: 2 sectors of
+    dims 4 and 3), K per sector up to 3 x 60 x 60 = 10,800 (split into k
+    ranges, summed by the reduction kernel)."""
+    from workloads import Leg, rand
+    li = Leg(1, ((0,), (1,)), (4, 3))
+    lk = Leg(1, ((-1,), (0,), (1,)), (60, 60, 60))
+    lj = Leg(-1, ((0,), (1,)), (3, 4))
+    a = rand([li, lk.conj(), lk.conj()], (0,), (0,), seed)
+    b = rand([lk, lk, lj], (0,), (0,), seed + 1)
+    return a, b, (1, 2), (0, 1)
+
+
+@pytest.mark.parametrize("variant", [0, 17, 18, 19])
+def test_split_k_long_sectors(variant):
+    import paper_2405_12196_amd as Y
+    a, b, xa, xb = _long_k_problem(77)
+    ref = oracle.tensordot_blockpair(a, b, xa, xb)
+    pl = Y.plan([(a, b, xa, xb)])
+    assert pl.stats(0)["max_k"] > 4096 and pl.stats(0)["tiles"] > pl.stats(0)["sectors"]
+    if variant:
+        pl.set_variant(variant)
+    else:
+        with pytest.raises(Y.YastnError) as e:
+            pl.set_variant(8)  # no register-resident tiles for split sectors
+        assert e.value.status == "ERR_STATE"
+    A, B = G.upload(a), G.upload(b)
+    c, s = G.alloc_out(pl, 0)
+    ws = G.workspace(pl)
+    for _ in range(2):  # partial slots are fully rewritten by every call
+        pl.contract([A], [B], [c], ws)
+    torch.cuda.synchronize()
+    check_f64(s, c.cpu().numpy()[:s.numel], ref)
+
+
+def test_split_k_fp32_and_norm():
+    import paper_2405_12196_amd as Y
+    a, b, xa, xb = _long_k_problem(78)
+    ref = oracle.tensordot_blockpair(a, b, xa, xb)
+    _, (s,), (v,) = G.run([(a, b, xa, xb)], precision="f32", in_dtype=Y.DTYPE_F32, out_dtype=Y.DTYPE_F64)
+    assert G.structure_equal(s, ref)
+    assert oracle.rel_frobenius(v, ref.data) <= 1e-6
+    pl = Y.plan([(a, b, xa, xb)])
+    A, B = G.upload(a), G.upload(b)
+    c, s = G.alloc_out(pl, 0)
+    nout = torch.zeros(2, dtype=torch.float64, device=G.DEV)
+    pl.contract_norm([A], [B], [c], G.workspace(pl), nout)
+    torch.cuda.synchronize()
+    rf, rm = oracle.norms(ref)
+    assert abs(float(nout[0]) / rf - 1) <= 1e-13
