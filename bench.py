@@ -536,6 +536,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the precision sweep, the batched configs and the serving loop")
     ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--batch-only", default="", choices=["", "cfg1_x64", "cfg1_x512", "cfg3_64probs"],
+                    help="run only this grouped launch (autotuned, then --steps launches) and print its time; "
+                         "for profiling")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -560,6 +563,27 @@ def main():
     import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.batch_only:
+        probs = {"cfg1_x64": lambda: W.config1(64), "cfg1_x512": lambda: W.config1(512),
+                 "cfg3_64probs": W.config3}[args.batch_only]()
+        sp = int(torch.cuda.current_stream().cuda_stream)
+        pl = Y.plan([(p.a, p.b, p.axes_a, p.axes_b) for p in probs], stream=sp)
+        A = [torch.from_numpy(p.a.data).to("cuda:0") for p in probs]
+        B = [torch.from_numpy(p.b.data).to("cuda:0") for p in probs]
+        C = [torch.empty(max(1, pl.output(i).numel), dtype=torch.float64, device="cuda:0") for i in range(len(probs))]
+        ws = torch.empty(max(256, pl.workspace_bytes), dtype=torch.uint8, device="cuda:0")
+        if len(probs) <= 64:
+            pl.autotune(A, B, C, ws, reps=3, stream=sp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            pl.contract(A, B, C, ws, stream=sp)
+        torch.cuda.synchronize()
+        us = (time.perf_counter() - t0) * 1e6 / args.steps
+        flop = sum(pl.stats(i)["useful_flops"] for i in range(len(probs)))
+        print(json.dumps({"batch": args.batch_only, "variant": pl.variant_id, "us_per_launch_host": round(us, 2),
+                          "useful_flop": flop, "launches": args.steps}))
+        return
     dev = "cuda:0"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()

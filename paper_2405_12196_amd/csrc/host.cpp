@@ -441,6 +441,7 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
     // element offset in B's buffer of every (k, column) of B_X (-1: sub-block absent)
     ds.bofs0 = (int64_t)t.bofs.size();
     t.bofs.resize(t.bofs.size() + size_t(K) * N, -1);
+    bool sec_over = int64_t(K) * N > INT32_MAX || hp.b.numel == 0;  // gathers read B[0] for absent entries
     for (int s = 0; s < Sn; ++s)
       for (int j = 0; j < Q; ++j) {
         const int32_t blk = bgrid[size_t(s) * Q + j];
@@ -450,18 +451,26 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
         for (int32_t kd = 0; kd < ct.k; ++kd)
           for (int32_t cb = 0; cb < cl.n; ++cb) {
             const int64_t o = b_offset(t.bblocks[blk], ct, cl, t.probs[prob_slot], kd, cb);
-            if (o > INT32_MAX) t.bofs_overflow = true;
+            if (o > INT32_MAX) t.bofs_overflow = sec_over = true;
             t.bofs[ds.bofs0 + int64_t(ct.ko + kd) * N + cl.no + cb] = (int32_t)std::min<int64_t>(o, INT32_MAX);
           }
       }
     const int32_t sec_id = (int32_t)t.sectors.size();
     t.sectors.push_back(ds);
-    for (int s = 0; s < Sn; ++s)
-      for (int j = 0; j < Q; ++j) {
-        const int64_t total = int64_t(t.ctrs[ds.ctr0 + s].k) * t.cols[ds.col0 + j].n;
-        for (int64_t e0 = 0; e0 < total; e0 += kPackItem)
-          t.items.push_back(DevPackItem{sec_id, s, j, bgrid[size_t(s) * Q + j], (int32_t)e0, 0});
-      }
+    if (!sec_over) {
+      // gathers through the offset table: long coalesced runs, one table read each
+      const int64_t total = int64_t(K) * N;
+      for (int64_t e0 = 0; e0 < total; e0 += kGatherItem)
+        t.items.push_back(DevPackItem{sec_id, -1, (int32_t)std::min<int64_t>(kGatherItem, total - e0), -1,
+                                      (int32_t)e0, 0});
+    } else {
+      for (int s = 0; s < Sn; ++s)
+        for (int j = 0; j < Q; ++j) {
+          const int64_t total = int64_t(t.ctrs[ds.ctr0 + s].k) * t.cols[ds.col0 + j].n;
+          for (int64_t e0 = 0; e0 < total; e0 += kPackItem)
+            t.items.push_back(DevPackItem{sec_id, s, j, bgrid[size_t(s) * Q + j], (int32_t)e0, 0});
+        }
+    }
     std::vector<Key> rowkeys(R), colkeys(Q);
     for (auto &r : sb.rows) rowkeys[r.second] = r.first;
     for (auto &c : sb.cols) colkeys[c.second] = c.first;

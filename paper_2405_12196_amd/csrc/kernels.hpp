@@ -138,8 +138,11 @@ __device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(
 // ---------------------------------------------------------------------------
 // B pack: per-sector matrices B_X in the workspace
 // ---------------------------------------------------------------------------
-// One workgroup per item of up to 256 elements of one (s, j) sub-block;
-// consecutive threads write consecutive elements of a B_X row.
+// One workgroup per item.  A gather item copies up to 2048 consecutive
+// elements of B_X, 8 per thread: the offset-table reads, then every B read,
+// then the stores (no load waits on a store); an absent entry reads B[0] and
+// stores zero.  A sub-block item writes up to 256 elements of one (s, j)
+// sub-block; consecutive threads write consecutive elements of a B_X row.
 template <typename In, typename Cmp>
 __global__ void __launch_bounds__(256) k_pack_b(LaunchArgs args) {
   for (int g = blockIdx.x; g < args.nitems; g += gridDim.x) {
@@ -149,6 +152,25 @@ __global__ void __launch_bounds__(256) k_pack_b(LaunchArgs args) {
     const DevPlan P = load_plan(job.plan);
     const DevPackItem it = cst(P.items + (g - job.item0 + job.pitem0));
     const DevSector sec = cst(P.sectors + it.sector);
+    if (it.s < 0) {
+      constexpr int R = kGatherItem / 256;
+      const int32_t *bo = P.bofs + sec.bofs0 + it.e0;
+      Cmp *dst = reinterpret_cast<Cmp *>(job.ws) + sec.bpack + it.e0;
+      const In *src = reinterpret_cast<const In *>(args.p[job.prob0 + sec.prob - job.plo].b);
+      const int32_t last = it.j - 1;
+      int32_t o[R];
+      In v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) o[r] = bo[min((int32_t)threadIdx.x + 256 * r, last)];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = src[max(o[r], 0)];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int32_t e = (int32_t)threadIdx.x + 256 * r;
+        if (e <= last) dst[e] = o[r] >= 0 ? Cmp(v[r]) : Cmp(0);
+      }
+      continue;
+    }
     const DevCtrTuple ct = cst(P.ctrs + (sec.ctr0 + it.s));
     const DevColTuple cl = cst(P.cols + (sec.col0 + it.j));
     const int32_t e = it.e0 + (int32_t)threadIdx.x;

@@ -35,7 +35,8 @@ constexpr int kMaxRank = 8;
 constexpr int kMaxAct = 4;     // free-leg classes of A (<= min(#free, #contracted + 1))
 constexpr int kMaxJobs = 32;   // plans per launch
 constexpr int kMaxProbs = 64;  // problems per launch (pointer triples in kernel args)
-constexpr int kPackItem = 256; // packed-B elements per pack work item
+constexpr int kPackItem = 256; // packed-B elements per sub-block pack work item
+constexpr int kGatherItem = 2048;  // packed-B elements per gather pack work item (8 per thread)
 
 struct DevProb {               // one problem of a plan
   int32_t nact;                // active free-leg classes of A
@@ -145,11 +146,17 @@ struct DevTileRec {
 };
 static_assert(sizeof(DevTileRec) == 160, "tile record layout");
 
-struct DevPackItem {           // up to 256 elements of one (sector, s, j) sub-block of packed B_X
+// One pack work item, in one of two forms.
+//  s >= 0: up to kPackItem elements of the (sector, s, j) sub-block of packed
+//          B_X, B offsets computed from the block's strides;
+//  s <  0: a gather of j (<= kGatherItem) consecutive elements of packed B_X
+//          starting at e0, the B offset of each read from the bofs table (used
+//          when every offset of the sector fits int32 and K_X * N_X does too).
+struct DevPackItem {
   int32_t sector;
   int32_t s, j;
-  int32_t bblk;                // B block (plan-global) or -1 (absent: zeros)
-  int32_t e0;                  // first element (row-major over k_s x n_j) of this item
+  int32_t bblk;                // B block (plan-global) or -1 (absent: zeros); unused by gathers
+  int32_t e0;                  // first element (row-major over k_s x n_j, or over K_X x N_X)
   int32_t pad;
 };
 

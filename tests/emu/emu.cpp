@@ -119,10 +119,29 @@ int emu_contract(void *h, const double *const *a, const int64_t *alen, const dou
   const DevPlan &P = e->dp;
   std::vector<double> ws(size_t(pl.t.bpack_elems) + 1, 0.0);
   std::vector<char> packed(size_t(pl.t.bpack_elems) + 1, 0);
-  // ---- k_pack_b: one work item = up to kPackItem elements of one (s, j) sub-block
+  // ---- k_pack_b: a gather item = up to kGatherItem consecutive elements of B_X
+  // through the offset table; a sub-block item = up to kPackItem elements of
+  // one (s, j) sub-block
   for (int g = 0; g < P.nitems; ++g) {
     const DevPackItem it = P.items[g];
     const DevSector &sec = P.sectors[it.sector];
+    if (it.s < 0) {
+      const int64_t total = (int64_t)sec.K * sec.N;
+      if (it.j < 1 || it.j > kGatherItem || it.e0 < 0 || it.e0 + (int64_t)it.j > total)
+        return fail("pack: gather item outside B_X");
+      if (blen[sec.prob] < 1) return fail("pack: gather item over an empty B");
+      for (int tid = 0; tid < 256; ++tid)
+        for (int r = 0; r < kGatherItem / 256; ++r) {
+          const int32_t e = tid + 256 * r, ec = std::min(e, it.j - 1);  // the kernel's clamped read
+          const int32_t o = P.bofs[sec.bofs0 + it.e0 + ec];
+          if (std::max(o, 0) >= blen[sec.prob]) return fail("pack: gather B read out of bounds");
+          if (e >= it.j) continue;
+          const int64_t d = sec.bpack + it.e0 + e;
+          if (packed[d]++) return fail("pack: element written twice");
+          ws[d] = o >= 0 ? b[sec.prob][o] : 0.0;
+        }
+      continue;
+    }
     const DevCtrTuple &ct = P.ctrs[sec.ctr0 + it.s];
     const DevColTuple &cl = P.cols[sec.col0 + it.j];
     for (int tid = 0; tid < kPackItem; ++tid) {
