@@ -69,8 +69,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ctm_corner_chi128_D8_f64_hbm_traf
 
 # the sources that define the contraction kernels, their instances, tables
 # and launches (the counters in profiles/ are valid while these are unchanged)
-CONTRACTION_SOURCES = ("device.hip", "dispatch.hpp", "host.cpp", "index.hpp", "inst_f64.hip", "kernels.hpp",
-                       "plan.hpp", "planner.hpp")
+CONTRACTION_SOURCES = ("device.hip", "dispatch.hpp", "host.cpp", "index.hpp", "inst_f64.hip", "inst_lds.hip",
+                       "kernels.hpp", "plan.hpp", "planner.hpp")
 
 
 def kernel_source_hash():
@@ -567,13 +567,12 @@ def main():
         probs = {"cfg1_x64": lambda: W.config1(64), "cfg1_x512": lambda: W.config1(512),
                  "cfg3_64probs": W.config3}[args.batch_only]()
         sp = int(torch.cuda.current_stream().cuda_stream)
-        pl = Y.plan([(p.a, p.b, p.axes_a, p.axes_b) for p in probs], stream=sp)
+        pl = Y.plan([(p.a, p.b, p.axes_a, p.axes_b) for p in probs], stream=sp, tile_rows=args.tile_rows)
         A = [torch.from_numpy(p.a.data).to("cuda:0") for p in probs]
         B = [torch.from_numpy(p.b.data).to("cuda:0") for p in probs]
         C = [torch.empty(max(1, pl.output(i).numel), dtype=torch.float64, device="cuda:0") for i in range(len(probs))]
         ws = torch.empty(max(256, pl.workspace_bytes), dtype=torch.uint8, device="cuda:0")
-        if len(probs) <= 64:
-            pl.autotune(A, B, C, ws, reps=3, stream=sp)
+        _, tune_ms = pl.autotune(A, B, C, ws, reps=3, stream=sp)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -582,7 +581,8 @@ def main():
         us = (time.perf_counter() - t0) * 1e6 / args.steps
         flop = sum(pl.stats(i)["useful_flops"] for i in range(len(probs)))
         print(json.dumps({"batch": args.batch_only, "variant": pl.variant_id, "us_per_launch_host": round(us, 2),
-                          "useful_flop": flop, "launches": args.steps}))
+                          "useful_flop": flop, "launches": args.steps,
+                          "autotune_ms": [round(x, 4) for x in tune_ms]}))
         return
     dev = "cuda:0"
     torch.cuda.set_device(0)

@@ -186,7 +186,10 @@ yastn_status yastn_contract_timed(yastn_plan_t plan, const void *const *a, const
  * from B's blocks (nine chunk / occupancy shapes; sectors with K <= 64, and
  * K <= 80 for variant 16, which runs one wave per SIMD);
  * 17-19: MFMA tiles over a packed B with the k loop software-pipelined (any K;
- * three shapes).
+ * three shapes);
+ * 20-22: as 8-16, FP64 only, K <= 80, with each workgroup loading the B tile
+ * of up to eight row tiles of one sector column range into shared memory once
+ * (three chunk / occupancy shapes).
  * yastn_plan_autotune runs every variant that fits the plan `reps` times on
  * the caller's buffers (same arguments as yastn_contract; C is overwritten),
  * times them with HIP events, keeps the fastest in the plan and returns its
@@ -197,7 +200,7 @@ yastn_status yastn_contract_timed(yastn_plan_t plan, const void *const *a, const
  * variant, so repeated contractions stay bitwise reproducible.
  * yastn_plan_set_variant restores a previously tuned choice (e.g. from a
  * cache keyed by structure); YASTN_ERR_STATE if the variant does not fit. */
-#define YASTN_NUM_VARIANTS 20
+#define YASTN_NUM_VARIANTS 23
 yastn_status yastn_plan_autotune(yastn_plan_t plan, const void *const *a, const void *const *b,
                                  void *const *c, void *workspace, void *hip_stream, int32_t reps,
                                  int32_t *chosen, float *times_ms);

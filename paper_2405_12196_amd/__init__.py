@@ -41,7 +41,7 @@ EXPORTS = ["yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_pla
            "yastn_grad_plan", "yastn_grad_output", "yastn_grad_workspace", "yastn_grad", "yastn_grad_free"]
 REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 MAX_CHAIN = 8
-NUM_VARIANTS = 20
+NUM_VARIANTS = 23
 
 
 class YastnError(RuntimeError):

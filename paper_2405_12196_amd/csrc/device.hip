@@ -306,7 +306,7 @@ yastn_status upload(Plan &pl) {
          o_tiles = take(bytes_of(t.tiles)), o_items = take(bytes_of(t.items)), o_kofs = take(bytes_of(t.kofs)),
          o_kp = take(bytes_of(t.kp)), o_cm = take(bytes_of(t.colmap)), o_bofs = take(bytes_of(t.bofs)),
          o_recs = take(t.tiles.size() * sizeof(DevTileRec)), o_red = take(t.red.size() * sizeof(DevRedItem)),
-         o_plan = take(sizeof(DevPlan));
+         o_lj = take(bytes_of(t.ljobs)), o_plan = take(sizeof(DevPlan));
   char *base;
   yastn_status s = dmalloc(&base, off);
   if (s) return s;
@@ -330,6 +330,8 @@ yastn_status upload(Plan &pl) {
   put(o_kp, t.kp.data(), bytes_of(t.kp));
   put(o_cm, t.colmap.data(), bytes_of(t.colmap));
   put(o_bofs, t.bofs.data(), bytes_of(t.bofs));
+  put(o_lj, t.ljobs.data(), bytes_of(t.ljobs));
+  pl.dljobs = reinterpret_cast<const DevLdsJob *>(base + o_lj);
   DevPlan dp{};
   dp.probs = reinterpret_cast<const DevProb *>(base + o_probs);
   dp.sectors = reinterpret_cast<const DevSector *>(base + o_sec);
@@ -382,6 +384,8 @@ yastn_status upload(Plan &pl) {
 //   1..kNumMfma                        k_gemm4 with shape kMfmaShapes[v - 1]
 //   kVariantRows                       k_rows (one output row per lane)
 //   kVariantRes0 .. + kNumRes - 1      k_gemm_res with shape kResShapes[v - kVariantRes0]
+//   kVariantPf0 .. + kNumPf - 1        k_gemm_pf with shape kPfShapes[v - kVariantPf0]
+//   kVariantLds0 .. + kNumLds - 1      k_gemm_lds with shape kLdsShapes[v - kVariantLds0]
 // yastn_plan_autotune times the candidates that fit the plan.  Tile widths
 // (CB) must cover the plan's tile width; the rest only tunes speed.
 // Wave tiles a launch should have at least, when the plan picks the tile
@@ -390,10 +394,11 @@ constexpr int64_t kTilesPerLaunchTarget = 6144;
 constexpr int kVariantRows = kNumMfma + 1;
 constexpr int kVariantRes0 = kVariantRows + 1;
 constexpr int kVariantPf0 = kVariantRes0 + kNumRes;
-constexpr int kVariants = kVariantPf0 + kNumPf;
+constexpr int kVariantLds0 = kVariantPf0 + kNumPf;
+constexpr int kVariants = kVariantLds0 + kNumLds;
 static_assert(kVariants == YASTN_NUM_VARIANTS, "variant count must match the header");
 
-enum Family { FAM_MFMA, FAM_ROWS, FAM_RES, FAM_PF, FAM_BF16 };
+enum Family { FAM_MFMA, FAM_ROWS, FAM_RES, FAM_PF, FAM_BF16, FAM_LDS };
 
 struct Choice {
   Family fam;
@@ -468,14 +473,18 @@ bool variant_fits(const Fit &f, const yastn_options &o, int v) {
     if (!f.res || !f.buf || f.kmax > res_max_k(v - kVariantRes0)) return false;
     return o.precision == YASTN_F64 || v == kVariantRes0 + 1;  // FP32: one shape compiled (kResShapes[1])
   }
-  if (v >= kVariantPf0 && v < kVariants) {
+  if (v >= kVariantLds0 && v < kVariants)  // FP64 only; K <= 80
+    return f.res && f.buf && o.precision == YASTN_F64 && f.kmax <= kResMaxKWide;
+  if (v >= kVariantPf0 && v < kVariantLds0) {
     if (!f.buf) return false;
     return o.precision == YASTN_F64 || v == kVariantPf0;  // FP32: one shape compiled (kPfShapes[0])
   }
   return false;
 }
 
-Choice choose(const Fit &f, const yastn_options &o, int variant) {
+// norm: the launch files the fused output norm (kernels with a separate
+// norm-filing instance take it)
+Choice choose(const Fit &f, const yastn_options &o, int variant, bool norm = false) {
   if (variant != 0 && !variant_fits(f, o, variant)) variant = 0;
   if (variant == 0) {  // heuristic
     if (f.mfma_pick || !f.buf) variant = 1;
@@ -488,6 +497,8 @@ Choice choose(const Fit &f, const yastn_options &o, int variant) {
   const int kq = (f.kmax + 3) / 4;
   const int na = f.nact <= 2 ? 2 : 4;
   if (variant == kVariantRows) return Choice{FAM_ROWS, rows_kernel(o, f.buf, f.kmax), pack_kernel(o)};
+  if (variant >= kVariantLds0)
+    return Choice{FAM_LDS, lds_f64(variant - kVariantLds0, f.cb, kq, na, norm), nullptr};
   if (variant >= kVariantPf0)
     return Choice{FAM_PF, pf_kernel(o, f.buf, variant - kVariantPf0, f.cb, na), pack_kernel(o)};
   if (variant >= kVariantRes0)
@@ -531,12 +542,14 @@ yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const
     fit_add(fit, *j.plan);
     if (j.plan->variant != variant) variant = 0;
   }
-  const Choice ch = choose(fit, o, variant);
+  const bool norm_one = norm_out && jobs.size() == 1 && !fit.split;
+  const Choice ch = choose(fit, o, variant, norm_one);
   if (!ch.gemm) return set_error(YASTN_ERR_STATE, "no kernel instance for this plan");
   if (fit.split && ch.fam != FAM_PF)
     return set_error(YASTN_ERR_STATE, "a plan with split-K sectors runs only on the pipelined kernel (32-bit buffers)");
-  // the norm rides in the epilogue of the register-resident and pipelined kernels
-  const bool fuse = norm_out && jobs.size() == 1 && !fit.split && (ch.fam == FAM_RES || ch.fam == FAM_PF);
+  // the norm rides in the epilogue of the register-resident, shared-B and pipelined kernels
+  const bool fuse = norm_one && (ch.fam == FAM_RES || ch.fam == FAM_PF || ch.fam == FAM_LDS);
+  const bool lds = ch.fam == FAM_LDS;  // grid over shared-B jobs, one workgroup each
   // the split-K reduction kernel of this arithmetic (accumulator -> output type)
   const void *reduce = fit.split ? reinterpret_cast<const void *>(split_reduce(o.precision, o.out_dtype)) : nullptr;
   if (norm_fused) *norm_fused = fuse;
@@ -553,10 +566,11 @@ yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const
       JobArg &ja = la.jobs[la.njobs++];
       ja.plan = j.plan->dplan;
       ja.recs = j.plan->drecs;
+      ja.ljobs = j.plan->dljobs;
       ja.ws = reinterpret_cast<char *>(j.ws);
       ja.tile0 = la.ntiles;
       ja.item0 = la.nitems;
-      ja.ptile0 = j.g->t0;
+      ja.ptile0 = lds ? j.g->l0 : j.g->t0;
       ja.pitem0 = j.g->i0;
       ja.prob0 = np;
       ja.plo = j.g->plo;
@@ -566,7 +580,7 @@ yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const
         la.p[np].c = j.c[p];
         ++np;
       }
-      la.ntiles += j.g->t1 - j.g->t0;
+      la.ntiles += lds ? j.g->l1 - j.g->l0 : j.g->t1 - j.g->t0;
       la.nitems += j.g->i1 - j.g->i0;
       ++ji;
     }
@@ -585,7 +599,7 @@ yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const
       // retires, which balances tiles of uneven cost better than a static
       // round-robin over resident waves (the kernels still loop, for grids
       // capped by the launch limit)
-      unsigned g = (unsigned)std::max<int64_t>(1, (la.ntiles + 3) / 4);
+      unsigned g = (unsigned)std::max<int64_t>(1, lds ? la.ntiles : (la.ntiles + 3) / 4);
       YASTN_HIP(hipLaunchKernel(reinterpret_cast<const void *>(ch.gemm), dim3(g), dim3(256), kargs, 0, st));
     }
     // split-K: sum every group's partial slots into C, slot by slot

@@ -39,6 +39,13 @@ struct PfShape {
 };
 constexpr PfShape kPfShapes[] = {{2, 2, 2}, {2, 2, 3}, {4, 1, 3}};
 constexpr int kNumPf = sizeof(kPfShapes) / sizeof(PfShape);
+// k_gemm_lds: rows per chunk = 16 * rb, A loads pd chunks ahead, occupancy
+// hint occ; K <= 80
+struct LdsShape {
+  int rb, pd, occ;
+};
+constexpr LdsShape kLdsShapes[] = {{1, 1, 2}, {1, 0, 3}, {2, 0, 2}};
+constexpr int kNumLds = sizeof(kLdsShapes) / sizeof(LdsShape);
 constexpr int kResMaxK = 64;      // K limit of the shapes with occ > 1
 constexpr int kResMaxKWide = 80;  // K limit of the occupancy-1 shape
 constexpr int res_max_k(int shape) { return kResShapes[shape].occ == 1 ? kResMaxKWide : kResMaxK; }
@@ -49,6 +56,7 @@ KernelFn res_f64(bool buf, int shape, int cb, int kq, int na);
 KernelFn rows_f64(bool buf, int kmax);
 KernelFn pf_f64(bool buf, int shape, int cb, int na);
 KernelFn pack_f64();
+KernelFn lds_f64(int shape, int cb, int kq, int na, bool norm);  // kq <= 20; norm: files the fused norm
 // FP32 arithmetic with FP64 input buffers (out: F64 or F32)
 KernelFn gemm4_f32d(yastn_dtype out, bool buf, int shape, int cb);
 KernelFn res_f32d(yastn_dtype out, bool buf, int cb, int kq);

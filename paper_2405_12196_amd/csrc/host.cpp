@@ -15,6 +15,7 @@
 #include <cstring>
 #include <map>
 #include <numeric>
+#include <tuple>
 
 #include "index.hpp"
 #include "planner.hpp"
@@ -243,7 +244,8 @@ struct SectorBuild {
 }  // namespace
 
 yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::pair<int32_t, int32_t>> &pairs,
-                             int64_t a_base, int64_t b_base, PlanTables &t, int rb, int cb, int nch, bool ksplit) {
+                             int64_t a_base, int64_t b_base, PlanTables &t, int rb, int cb, int nch, bool ksplit,
+                             bool gather) {
   const HostTensor &A = hp.a, &B = hp.b;
   const int nsym = A.nsym, nc = hp.nc;
   // ---- group matches by sector X = sum over A's contracted legs of s_i rho_i
@@ -441,7 +443,7 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
     // element offset in B's buffer of every (k, column) of B_X (-1: sub-block absent)
     ds.bofs0 = (int64_t)t.bofs.size();
     t.bofs.resize(t.bofs.size() + size_t(K) * N, -1);
-    bool sec_over = int64_t(K) * N > INT32_MAX || hp.b.numel == 0;  // gathers read B[0] for absent entries
+    bool sec_over = !gather || int64_t(K) * N > INT32_MAX || hp.b.numel == 0;  // gathers read B[0] for absent entries
     for (int s = 0; s < Sn; ++s)
       for (int j = 0; j < Q; ++j) {
         const int32_t blk = bgrid[size_t(s) * Q + j];
@@ -587,6 +589,7 @@ void finish_tiles(Plan &plan) {
   plan.prob_t0.push_back((int32_t)t.tiles.size());
   plan.prob_i0.push_back((int32_t)t.items.size());
   plan.groups.clear();
+  t.ljobs.clear();
   for (int p0 = 0; p0 < np; p0 += kMaxProbs) {
     Group g{};
     g.plo = p0;
@@ -612,6 +615,43 @@ void finish_tiles(Plan &plan) {
     std::vector<DevTile> sorted(order.size());
     for (size_t i = 0; i < order.size(); ++i) sorted[i] = t.tiles[g.t0 + order[i]];
     std::copy(sorted.begin(), sorted.end(), t.tiles.begin() + g.t0);
+    // shared-B jobs: the tiles of each (sector, k range, column range) in
+    // runs of kLdsJobTiles (costliest first, so wave w's two tiles are the
+    // w-th and (w+4)-th costliest of the run); jobs costliest first
+    {
+      std::vector<double> tcost(order.size());
+      for (size_t i = 0; i < order.size(); ++i) tcost[i] = cost[order[i]];
+      std::vector<int32_t> byk(order.size());
+      std::iota(byk.begin(), byk.end(), 0);
+      auto key = [&](int32_t i) {
+        const DevTile &tl = t.tiles[g.t0 + i];
+        return std::make_tuple(tl.sector, tl.k0, tl.n0);
+      };
+      std::stable_sort(byk.begin(), byk.end(), [&](int32_t x, int32_t y) { return key(x) < key(y); });
+      std::vector<std::pair<double, DevLdsJob>> jobs;
+      for (size_t i = 0; i < byk.size();) {
+        size_t e = i;
+        while (e < byk.size() && key(byk[e]) == key(byk[i])) ++e;
+        for (size_t s0 = i; s0 < e; s0 += kLdsJobTiles) {
+          DevLdsJob lj;
+          double wave[4] = {0, 0, 0, 0};
+          for (int u = 0; u < kLdsJobTiles; ++u) {
+            const bool in = s0 + u < e;
+            lj.t[u] = in ? g.t0 + byk[s0 + u] : -1;
+            if (in) wave[u % 4] += tcost[byk[s0 + u]];
+          }
+          jobs.push_back({*std::max_element(wave, wave + 4), lj});
+        }
+        i = e;
+      }
+      std::stable_sort(jobs.begin(), jobs.end(),
+                       [](const std::pair<double, DevLdsJob> &x, const std::pair<double, DevLdsJob> &y) {
+                         return x.first > y.first;
+                       });
+      g.l0 = (int32_t)t.ljobs.size();
+      for (auto &jj : jobs) t.ljobs.push_back(jj.second);
+      g.l1 = (int32_t)t.ljobs.size();
+    }
     plan.groups.push_back(g);
   }
   const size_t elem = plan.opts.precision == YASTN_F64 ? 8 : 4;

@@ -17,6 +17,8 @@
 //  k_gemm_res   as k_gemm4 for sectors with K_X <= 64, with the tile's B
 //               values and k metadata held in registers and B read straight
 //               from its blocks (no pack kernel).
+//  k_gemm_lds   as k_gemm_res, the B tile loaded once per workgroup job of
+//               up to eight tiles of one sector column range and read from LDS.
 //  k_gemm_pf    sectors of any K, k loop software-pipelined (loads of the
 //               next k batch in flight while the MFMAs of this one run).
 //  k_rows       tall-skinny sectors (K, N <= 64): one row of C_X per lane.
@@ -700,11 +702,21 @@ template <typename In, typename Out, bool BUF> struct RecCtx {
 };
 
 template <typename In, typename Out, bool BUF>
+__device__ __forceinline__ void rec_setup(const LaunchArgs &args, const JobArg &job, const DevTileRec *r,
+                                          RecCtx<In, Out, BUF> &x);
+
+template <typename In, typename Out, bool BUF>
 __device__ __forceinline__ void rec_setup(const LaunchArgs &args, int t, RecCtx<In, Out, BUF> &x) {
   int jb = 0;
   while (jb + 1 < args.njobs && t >= args.jobs[jb + 1].tile0) ++jb;
   const JobArg &job = args.jobs[jb];
-  const DevTileRec *r = cst(&job.recs) + (t - job.tile0 + job.ptile0);
+  rec_setup<In, Out, BUF>(args, job, cst(&job.recs) + (t - job.tile0 + job.ptile0), x);
+}
+
+// The record r of a tile of `job`.
+template <typename In, typename Out, bool BUF>
+__device__ __forceinline__ void rec_setup(const LaunchArgs &args, const JobArg &job, const DevTileRec *r,
+                                          RecCtx<In, Out, BUF> &x) {
   x.kofs = cst(&r->kofs);
   x.kp = cst(&r->kp);
   x.bofs = cst(&r->bofs);
@@ -905,6 +917,204 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
       }
     }
     if (do_norm) norm_file_tile(args.norm, t, lane, nacc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// grouped gather GEMM with the B tile shared in LDS by a workgroup
+// ---------------------------------------------------------------------------
+// For sectors with K_X <= 4*KQ.  A workgroup takes a job of up to eight wave
+// tiles of one (sector, column range): its 256 threads load the B_X tile
+// (4*KQ k rows x 16*CB columns, zero past K and N, straight from B's blocks
+// through the offset table) into LDS once, then each wave computes its tiles
+// as k_gemm_res does, reading the B operand of every MFMA from LDS.  The B
+// load is paid once per job instead of once per tile, and the registers it
+// held in k_gemm_res are free for more resident waves.
+// res_load_chunk with the k metadata read from the wave's LDS slice
+// (kw[k] = {A offset of (row 0, k) or -1, class factors}).
+template <typename In, int RB, int KQ, int NA>
+__device__ __forceinline__ void lds_load_chunk(const Src<In, true, kStream> &A, const DevRowTuple &rt, int nact,
+                                               int K, int32_t row0, int rows, int lane, const int32_t (*kw)[1 + NA],
+                                               In (&av)[KQ][RB]) {
+  int32_t rg[RB][NA];
+  bool rv[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    const int lr = 16 * rb + (lane & 15);
+    rv[rb] = lr < rows;
+    a_rowparts_fast<NA>(rt, nact, row0 + (rv[rb] ? lr : 0), rg[rb]);
+  }
+  const int kl = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < KQ; ++q)
+    if (4 * q < K) {
+      const int32_t *m = kw[4 * q + kl];
+      const int32_t ko = m[0];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        int32_t o = ko;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) o += m[1 + a] * rg[rb][a];
+        av[q][rb] = A.ld_z(ko >= 0 && rv[rb], o);
+      }
+    }
+}
+
+// NORM: the instance that files the fused output norm (the others carry none
+// of its code).
+template <typename In, typename Cmp, typename Out, int RB, int CB, int KQ, int NA, int PD, int OCC, bool NORM>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) k_gemm_lds(LaunchArgs args) {
+  static_assert(NA <= kRecAct + 1, "tile records carry kRecAct class boundaries");
+  constexpr bool BUF = true;
+  typedef int32_t Off;
+  typedef Mfma4<Cmp> M;
+  typedef typename M::acc_t acc_t;
+  constexpr int BW = 16 * CB;                  // tile columns
+  constexpr int BE = 4 * KQ * BW;              // B tile elements
+  constexpr int BR = (BE + 255) / 256;         // per thread
+  __shared__ Cmp bl[4 * KQ][BW];
+  __shared__ int32_t kls[4][4 * KQ][1 + NA];  // per wave: A offset of (row 0, k) (-1 past K), class factors
+  const int lane = threadIdx.x & 63;
+  const int kl = lane >> 4;
+  const int w = uni(threadIdx.x >> 6);
+  NormAcc nacc;
+  // one wave tile: its record, output columns and k metadata (into the
+  // wave's LDS slice, where it stays through the row chunks)
+  struct Tile {
+    RecCtx<In, Out, BUF> x;
+    Off cbase[CB];
+    int32_t cnj[CB], ccl[CB];
+  };
+  auto setup = [&](const JobArg &job, int32_t tl, Tile &T) {
+    rec_setup<In, Out, BUF>(args, job, cst(&job.recs) + tl, T.x);
+    tile_columns<Off, CB>(T.x.cmap, T.x.cgrid, T.x.ncols, lane, T.cbase, T.cnj, T.ccl);
+    const int K = T.x.K;
+    wave_lds_sync();
+#pragma unroll
+    for (int k0 = 0; k0 < 4 * KQ; k0 += 64) {
+      const int k = k0 + lane;
+      const int kk = k < K ? k : 0;
+      const int64_t o = T.x.kofs[kk];
+      int32_t pa[NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) pa[a] = T.x.kp[kk].p[a];
+      if (k < 4 * KQ) {
+        kls[w][k][0] = k < K ? (int32_t)o : -1;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) kls[w][k][1 + a] = pa[a];
+      }
+    }
+    wave_lds_sync();
+  };
+  // the tile's rows in chunks of 16 * RB, A loads PD chunks ahead
+  auto run = [&](int32_t tl, const Tile &T) {
+    const RecCtx<In, Out, BUF> &x = T.x;
+    const int K = x.K, nact = x.nact, nrows = x.nrows;
+    const int cbn = (x.ncols + 15) >> 4;
+    const int nch = (nrows + 16 * RB - 1) / (16 * RB);
+    In ab[PD + 1][KQ][RB];
+    auto load_chunk = [&](int c, In (&dst)[KQ][RB]) {
+      lds_load_chunk<In, RB, KQ, NA>(x.A, x.rt, nact, K, x.m0 + c * 16 * RB, min(16 * RB, nrows - c * 16 * RB),
+                                     lane, kls[w], dst);
+    };
+    auto compute_chunk = [&](int c, const In (&av)[KQ][RB]) {
+      const int mc = c * 16 * RB;
+      const int rows = min(16 * RB, nrows - mc);
+      const int rbn = (rows + 15) >> 4;
+      acc_t acc[RB][CB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) {
+        if (4 * q < K) {
+          Cmp b[CB];
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) b[cb] = bl[4 * q + kl][16 * cb + (lane & 15)];
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            if (rb < rbn)
+#pragma unroll
+              for (int cb = 0; cb < CB; ++cb)
+                if (cb < cbn) acc[rb][cb] = M::run(Cmp(av[q][rb]), b[cb], acc[rb][cb]);
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        if (cb >= cbn || T.cbase[cb] < 0) continue;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          if (rb >= rbn) continue;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int lr = 16 * rb + M::row(lane, v);
+            if (lr < rows) {
+              const Out val = Out(acc[rb][cb][v]);
+              x.C.put(T.cbase[cb] + (Off)(x.m0 + mc + lr) * (Off)T.cnj[cb] + (Off)T.ccl[cb], val);
+              if constexpr (NORM) nacc.add((double)val);
+            }
+          }
+        }
+      }
+    };
+#pragma unroll
+    for (int u = 0; u < PD; ++u)
+      if (u < nch) load_chunk(u, ab[u]);
+    for (int c0 = 0; c0 < nch; c0 += PD + 1) {
+#pragma unroll
+      for (int u = 0; u <= PD; ++u) {
+        const int c = c0 + u;
+        if (c < nch) {
+          if (c + PD < nch) load_chunk(c + PD, ab[(u + PD) % (PD + 1)]);
+          compute_chunk(c, ab[u]);
+        }
+      }
+    }
+    // single-problem launches: plan-local tile index = part index
+    if constexpr (NORM) norm_file_tile(args.norm, tl, lane, nacc);
+  };
+  for (int j = blockIdx.x; j < args.ntiles; j += gridDim.x) {
+    int jb = 0;
+    while (jb + 1 < args.njobs && j >= args.jobs[jb + 1].tile0) ++jb;
+    const JobArg &job = args.jobs[jb];
+    const DevLdsJob *lj = cst(&job.ljobs) + (j - job.tile0 + job.ptile0);
+    {
+      // the B tile, from the job's first tile record: every offset-table
+      // read, then every B read, then the LDS stores
+      const DevTileRec *r = cst(&job.recs) + cst(&lj->t[0]);
+      const int32_t *bofs = cst(&r->bofs);
+      const int32_t K = cst(&r->K), N = cst(&r->N), n0 = cst(&r->n0);
+      Src<In, BUF> B;
+      B.init(args.p[job.prob0 + cst(&r->prob) - job.plo].b, cst(&r->b_span));
+      int32_t bo[BR];
+      bool bv[BR];
+#pragma unroll
+      for (int i = 0; i < BR; ++i) {
+        const int e = min((int)threadIdx.x + 256 * i, BE - 1);
+        const int k = e / BW, c = n0 + e % BW;
+        bv[i] = k < K && c < N;
+        bo[i] = bofs[bv[i] ? k * N + c : 0];
+      }
+      In v[BR];
+#pragma unroll
+      for (int i = 0; i < BR; ++i) v[i] = B.ld_z(bv[i] && bo[i] >= 0, bo[i]);
+#pragma unroll
+      for (int i = 0; i < BR; ++i) {
+        const int e = (int)threadIdx.x + 256 * i;
+        if (e < BE) bl[e / BW][e % BW] = Cmp(v[i]);
+      }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+      const int32_t tl = uni(cst(&lj->t[w + 4 * h]));
+      if (tl < 0) continue;
+      Tile T;
+      setup(job, tl, T);
+      run(tl, T);
+    }
+    __syncthreads();  // the next job overwrites the B tile
   }
 }
 

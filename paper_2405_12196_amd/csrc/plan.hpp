@@ -180,6 +180,14 @@ struct DevPlan {               // device-resident table of the plan's arrays
   int32_t ntiles, nitems;
 };
 
+// A shared-B workgroup job: wave tiles of one (sector, column range) of one
+// problem (plan-local tile indices; -1 = none, t[0] always a tile).  Wave w of
+// the workgroup computes t[w] and then t[w + 4].
+constexpr int kLdsJobTiles = 8;
+struct DevLdsJob {
+  int32_t t[kLdsJobTiles];
+};
+
 struct ProbPtrs {
   const void *a, *b;
   void *c;
@@ -188,9 +196,10 @@ struct ProbPtrs {
 struct JobArg {                // a range of one plan's problems inside a launch
   const DevPlan *plan;
   const DevTileRec *recs;      // the plan's tile records (device)
+  const DevLdsJob *ljobs;      // the plan's shared-B jobs (device)
   char *ws;                    // job workspace (packed B)
-  int32_t tile0, item0;        // first launch-global tile / pack item of this job
-  int32_t ptile0, pitem0;      // first plan-local tile / pack item of this job
+  int32_t tile0, item0;        // first launch-global tile (shared-B job) / pack item of this job
+  int32_t ptile0, pitem0;      // first plan-local tile (shared-B job) / pack item of this job
   int32_t prob0;               // entry of LaunchArgs::p for the plan's problem plo
   int32_t plo;                 // first plan problem covered by this job
 };
@@ -207,6 +216,7 @@ struct LaunchArgs {
   JobArg jobs[kMaxJobs];
   ProbPtrs p[kMaxProbs];
 };
+static_assert(sizeof(LaunchArgs) <= 4096, "kernel arguments are limited to 4 KiB");
 
 // The split-K reduction of one job: its groups' slots summed into C.
 struct RedArgs {

@@ -68,6 +68,7 @@ struct PlanTables {
   int64_t bpack_elems = 0;  // packed B elements in the workspace
   bool bofs_overflow = false;  // some B offset does not fit in int32 (no direct B reads then)
   std::vector<RedGroup> red;   // split-K groups, in problem order
+  std::vector<DevLdsJob> ljobs;  // shared-B workgroup jobs, per group
 };
 
 // Problems are launched in groups of at most kMaxProbs (their device pointers
@@ -77,6 +78,7 @@ struct Group {
   int32_t t0, t1;            // plan-local tiles
   int32_t i0, i1;            // plan-local pack items
   int32_t r0, r1;            // split-K groups of these problems
+  int32_t l0, l1;            // shared-B jobs of these problems
 };
 
 struct Plan {
@@ -98,6 +100,7 @@ struct Plan {
   DevPlan *dplan = nullptr; // device copy of the table of pointers
   const DevTileRec *drecs = nullptr;  // device tile records
   const DevRedItem *dred = nullptr;   // device split-K groups (null when none)
+  const DevLdsJob *dljobs = nullptr;  // device shared-B jobs
   size_t ws_bytes = 0;
   size_t norm_off = 0;      // workspace offset of the fused norm's per-tile parts
   int device = 0;
@@ -113,10 +116,11 @@ yastn_status validate_problem(const yastn_problem &p, HostProblem &hp);
 yastn_status validate_tensor(const yastn_tensor_desc &d, const char *name, HostTensor &t);
 void contracted_keys(const HostTensor &t, const int *axes, int nc, std::vector<int32_t> &keys);
 // ksplit: sectors with K > kSplitMinK are computed in k ranges (split-K)
+// gather: pack B through the offset table where it fits (else sub-block items)
 constexpr int64_t kSplitMinK = 4096, kSplitChunk = 2048, kSplitMaxSlots = 128;
 yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::pair<int32_t, int32_t>> &pairs,
                              int64_t a_base, int64_t b_base, PlanTables &t, int rb, int cb, int nch,
-                             bool ksplit = false);
+                             bool ksplit = false, bool gather = true);
 void finish_tiles(Plan &plan);
 // Tile records with absolute addresses: `at` gives the address of each table
 // (device addresses for the GPU, host vector data for the CPU replay).

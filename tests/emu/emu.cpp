@@ -20,6 +20,7 @@ using namespace yastn;
 
 namespace {
 std::string g_msg;
+bool g_gather = true;  // pack form of the plans built next
 struct Emu {
   Plan pl;
   DevPlan dp;
@@ -33,6 +34,7 @@ int fail(const std::string &m) {
 extern "C" {
 
 const char *emu_error() { return g_msg.c_str(); }
+void emu_set_pack_gather(int on) { g_gather = on != 0; }
 
 void *emu_plan(const yastn_problem *probs, int nprob, int rb_override, int cb_override) {
   Emu *e = new Emu();
@@ -67,7 +69,7 @@ void *emu_plan(const yastn_problem *probs, int nprob, int rb_override, int cb_ov
   for (int p = 0; p < nprob; ++p) {
     pl.prob_t0.push_back((int32_t)pl.t.tiles.size());
     pl.prob_i0.push_back((int32_t)pl.t.items.size());
-    if (build_structure(pl.probs[p], p, pairs[p], ab, bb, pl.t, pl.rb, pl.cb, pl.nch) != YASTN_OK) {
+    if (build_structure(pl.probs[p], p, pairs[p], ab, bb, pl.t, pl.rb, pl.cb, pl.nch, false, g_gather) != YASTN_OK) {
       g_msg = "build_structure failed";
       delete e;
       return nullptr;
@@ -76,6 +78,37 @@ void *emu_plan(const yastn_problem *probs, int nprob, int rb_override, int cb_ov
     bb += pl.probs[p].b.nblocks;
   }
   finish_tiles(pl);
+  // shared-B jobs (k_gemm_lds): per group, every tile exactly once, the tiles
+  // of a job on one (sector, k range, column range), its first slot filled
+  for (const Group &g : pl.groups) {
+    std::vector<int> seen(size_t(g.t1 - g.t0), 0);
+    for (int32_t j = g.l0; j < g.l1; ++j) {
+      const DevLdsJob &lj = pl.t.ljobs[j];
+      if (lj.t[0] < 0) {
+        g_msg = "ljobs: empty first slot";
+        delete e;
+        return nullptr;
+      }
+      const DevTile &t0 = pl.t.tiles[lj.t[0]];
+      for (int u = 0; u < kLdsJobTiles; ++u) {
+        const int32_t ti = lj.t[u];
+        if (ti < 0) continue;
+        const DevTile &tu = pl.t.tiles[ti];
+        if (ti < g.t0 || ti >= g.t1 || seen[ti - g.t0]++ || tu.sector != t0.sector || tu.k0 != t0.k0 ||
+            tu.n0 != t0.n0 || tu.ncols != t0.ncols) {
+          g_msg = "ljobs: tile outside its group, repeated, or on another B tile";
+          delete e;
+          return nullptr;
+        }
+      }
+    }
+    for (int v : seen)
+      if (v != 1) {
+        g_msg = "ljobs: a tile of the group is in no job";
+        delete e;
+        return nullptr;
+      }
+  }
   DevPlan &d = e->dp;
   d.probs = pl.t.probs.data();
   d.sectors = pl.t.sectors.data();

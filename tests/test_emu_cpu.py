@@ -38,6 +38,7 @@ def emu():
     L.emu_contract.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_void_p),
                                C.POINTER(C.c_int64), C.POINTER(C.c_void_p), C.POINTER(C.c_int64)]
     L.emu_error.restype = C.c_char_p
+    L.emu_set_pack_gather.argtypes = [C.c_int]
     L.emu_free.argtypes = [C.c_void_p]
     return L
 
@@ -123,3 +124,19 @@ def test_emu_config3_batch(emu):
     probs = [(p.a, p.b, p.axes_a, p.axes_b) for p in W.config3(12)]
     for res, (a, b, xa, xb) in zip(run_emu(emu, probs), probs):
         check(res, oracle.tensordot_blockpair(a, b, xa, xb))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_emu_subblock_pack(emu, seed):
+    # the stride-computed pack items (taken when B offsets overflow int32)
+    emu.emu_set_pack_gather(0)
+    try:
+        sym = ["U1", "Z2", "U1xU1"][seed % 3]
+        a, b, xa, xb = random_problem(seed + 4000, sym, rank_a=2 + seed % 3, rank_b=2 + (seed // 3) % 3,
+                                      max_sectors=4, max_dim=6, keep=0.75 if seed % 2 else None,
+                                      shuffle=seed % 2 == 0, drop_partner=seed == 3)
+        probs = [(a, b, xa, xb)] + [(p.a, p.b, p.axes_a, p.axes_b) for p in W.config3(3, seed=seed)]
+        for res, (a, b, xa, xb) in zip(run_emu(emu, probs), probs):
+            check(res, oracle.tensordot_blockpair(a, b, xa, xb))
+    finally:
+        emu.emu_set_pack_gather(1)

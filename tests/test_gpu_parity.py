@@ -290,7 +290,7 @@ def test_norm_f64(n):
 
 
 # ------------------------------------------------------ kernel variants
-NUM_VARIANTS = 20  # yastn.h YASTN_NUM_VARIANTS
+NUM_VARIANTS = 23  # yastn.h YASTN_NUM_VARIANTS
 
 
 @pytest.mark.parametrize("variant", range(1, NUM_VARIANTS))
@@ -433,17 +433,20 @@ def test_graph_replays_equal_eager_chain(kind):
 
 
 # ------------------------------------------------------------ fused norm
-@pytest.mark.parametrize("kind", ["auto", "mfma", "rows"])
+@pytest.mark.parametrize("kind", ["auto", "mfma", "rows", 8, 17, 20, 21, 22])
 def test_fused_norm_matches_oracle_and_repeats_bitwise(kind):
     """The FP64 norm of the step-4 output, from the contraction's epilogue
-    (register-resident kernel) or from the separate pass (other kernels)."""
+    (register-resident, shared-B and pipelined kernels) or from the separate
+    pass (other kernels); an int kind is a kernel variant."""
     import paper_2405_12196_amd as Y
     t = W.config2()
     a = oracle.tensordot_blockpair(t["C"], t["T1"], (1,), (0,))
     a = oracle.tensordot_blockpair(a, t["T4"], (0,), (0,))
     a = oracle.tensordot_blockpair(a, t["A"], (0, 3), (0, 1))
     ref = oracle.tensordot_blockpair(a, t["Ac"], (0, 2, 6), (0, 1, 4))
-    pl = Y.plan([(a, t["Ac"], (0, 2, 6), (0, 1, 4))], flags=FLAGS[kind])
+    pl = Y.plan([(a, t["Ac"], (0, 2, 6), (0, 1, 4))], flags=FLAGS[kind] if isinstance(kind, str) else 0)
+    if not isinstance(kind, str):
+        pl.set_variant(kind)
     A, B = G.upload(a), G.upload(t["Ac"])
     c, s = G.alloc_out(pl, 0)
     ws = G.workspace(pl)
