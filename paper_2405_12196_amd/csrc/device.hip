@@ -491,7 +491,7 @@ Choice choose(const Fit &f, const yastn_options &o, int variant, bool norm = fal
     else if (f.bf16) variant = variant_fits(f, o, kVariantRes0) ? kVariantRes0 : 1;
     else if (f.rows_pick && f.rows) variant = kVariantRows;
     else if (f.res && f.kmax <= kResMaxK) variant = o.precision == YASTN_F64 ? kVariantRes0 : kVariantRes0 + 1;
-    else if (f.res && o.precision == YASTN_F64) variant = kVariantRes0 + kNumRes - 1;
+    else if (f.res && o.precision == YASTN_F64) variant = kVariantLds0;
     else variant = kVariantPf0;
   }
   const int kq = (f.kmax + 3) / 4;
@@ -756,10 +756,17 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
         for (auto &rt : pl.t.rows) n += ((rt.m + h - 1) / h) * ((pl.t.sectors[rt.sector].N + 16 * cb - 1) / (16 * cb));
         return n;
       };
-      // large-K sectors (K > 64, pipelined kernel) reuse each B batch over at
-      // least 32 rows (measured faster on the 64-problem batches)
-      tm = maxk > kResMaxK ? 32 : 16;
-      while (tm < 512 && count(2 * tm) >= kTilesPerLaunchTarget) tm *= 2;
+      // large-K sectors (K > 80, pipelined kernel) reuse each B batch over at
+      // least 32 rows (measured faster on the 64-problem batches); sectors
+      // with 64 < K <= 80 run on the shared-B kernel, whose jobs share one B
+      // tile among up to eight tiles: 16-row tiles balance its waves best
+      // (measured on batches of the rank-4 U(1) D=18 contraction)
+      if (maxk > kResMaxK && maxk <= kResMaxKWide && o.precision == YASTN_F64 && !bf16) {
+        tm = 16;
+      } else {
+        tm = maxk > kResMaxK ? 32 : 16;
+        while (tm < 512 && count(2 * tm) >= kTilesPerLaunchTarget) tm *= 2;
+      }
     }
     // tile height = 16 * rb * nch rows
     const int rb_t = tm >= 64 ? 4 : tm / 16, nch = tm >= 64 ? tm / 64 : 1;
