@@ -1107,7 +1107,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
     }
     __syncthreads();
 #pragma unroll 1
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < kLdsJobTiles / 4; ++h) {
       const int32_t tl = uni(cst(&lj->t[w + 4 * h]));
       if (tl < 0) continue;
       Tile T;

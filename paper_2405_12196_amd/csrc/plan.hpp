@@ -182,8 +182,9 @@ struct DevPlan {               // device-resident table of the plan's arrays
 
 // A shared-B workgroup job: wave tiles of one (sector, column range) of one
 // problem (plan-local tile indices; -1 = none, t[0] always a tile).  Wave w of
-// the workgroup computes t[w] and then t[w + 4].
-constexpr int kLdsJobTiles = 8;
+// the workgroup computes t[w], t[w + 4], ...
+constexpr int kLdsJobTiles = 4;
+static_assert(kLdsJobTiles % 4 == 0, "four waves per job");
 struct DevLdsJob {
   int32_t t[kLdsJobTiles];
 };
