@@ -99,6 +99,27 @@ def measured_traffic(step, variant):
     return int(e["fetch_bytes"] + e["write_bytes"]) if e else None
 
 
+def steps_timed(torch, ev, sp, fn, K):
+    """(ms per step, per-step latencies in ms): K steps back to back between
+    two synchronisations, wall clock (a HIP event recorded between steps
+    stalls the queue for ~10 us, so none is recorded in this pass); then K
+    more steps, each bracketed by HIP events on the launch stream, for the
+    latency percentiles."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        fn()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / K
+    evs = [(ev.new(), ev.new()) for _ in range(K)]
+    for k in range(K):
+        ev.record(evs[k][0], sp)
+        fn()
+        ev.record(evs[k][1], sp)
+    torch.cuda.synchronize()
+    return ms, np.array([ev.ms(a, b) for a, b in evs])
+
+
 # ------------------------------------------------------------ HIP graphs
 def capture(torch, fn):
     """Capture fn(stream_handle) into a torch CUDAGraph (HIP graph) on a side
@@ -288,15 +309,7 @@ class Chain:
         graph, err = capture(torch, self.step)
 
         def run(fn):
-            evs = [(ev.new(), ev.new()) for _ in range(K)]
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for k in range(K):
-                ev.record(evs[k][0], self.sp)
-                fn()
-                ev.record(evs[k][1], self.sp)
-            torch.cuda.synchronize()
-            return (time.perf_counter() - t0) * 1e3 / K, np.array([ev.ms(a, b) for a, b in evs])
+            return steps_timed(torch, ev, self.sp, fn, K)
 
         modes = {"eager": run(lambda: self.step(self.sp))}
         if graph is not None:
@@ -394,9 +407,7 @@ def batch_section(torch, Y, W, ev, sp):
         B = [torch.from_numpy(p.b.data).to("cuda:0").to(dt) for p in probs]
         C = [torch.empty(max(1, pl.output(i).numel), dtype=dt, device="cuda:0") for i in range(len(probs))]
         ws = torch.empty(max(256, pl.workspace_bytes), dtype=torch.uint8, device="cuda:0")
-        tune_ms = None
-        if len(probs) <= 64:
-            _, tune_ms = pl.autotune(A, B, C, ws, reps=3, stream=sp)
+        _, tune_ms = pl.autotune(A, B, C, ws, reps=3, stream=sp)
         st = [pl.stats(i) for i in range(len(probs))]
         useful = sum(x["useful_flops"] for x in st)
         byts = sum(x["alg_bytes"] for x in st)
@@ -658,16 +669,7 @@ def main():
     K = args.steps
 
     def timed(run):
-        evs = [(ev.new(), ev.new()) for _ in range(K)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(K):
-            ev.record(evs[k][0], sp)
-            run()
-            ev.record(evs[k][1], sp)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        return wall * 1e3 / K, np.array([ev.ms(a, b) for a, b in evs])
+        return steps_timed(torch, ev, sp, run, K)
 
     modes = {"eager": timed(lambda: step(sp))}
     if graph is not None:
