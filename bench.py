@@ -418,7 +418,7 @@ def batch_section(torch, Y, W, ev, sp):
         res[name] = {"problems": len(probs), "precision": prec, "us_per_launch": round(ms * 1e3, 2),
                      "useful_TFs": round(tf, 3), "frac_of_mfma_peak": round(tf / peak, 4),
                      "achieved_GBs": round(byts / (ms * 1e-3) / 1e9, 1), "useful_flop": int(useful),
-                     "alg_bytes": int(byts), "launch_groups": (len(probs) + 63) // 64,
+                     "alg_bytes": int(byts), "launch_groups": 1 + (len(probs) - 1) // 65536,
                      "cold_us_per_launch": round(cold * 1e3, 2),
                      "cold_useful_TFs": round(useful / (cold * 1e-3) / 1e12, 3),
                      "variant": pl.variant_id, "inputs": "resident; warm = repeated launches, cold = MALL flushed",

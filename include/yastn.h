@@ -152,7 +152,9 @@ yastn_status yastn_plan_stats(yastn_plan_t plan, int32_t prob, yastn_stats *st);
  * hip_stream.  a[p], b[p] [device] are the input buffers of problem p (any
  * values with the planned structure; in_dtype elements), c[p] [device] its
  * output buffer of c_numel elements (out_dtype), fully overwritten: C need
- * not be zeroed.  The host arrays a, b, c are read during the call.
+ * not be zeroed.  The host arrays a, b, c are read during the call (plans of
+ * more than 64 problems: a small kernel first copies the pointers into a
+ * table in the workspace; up to 65536 problems run in one grouped launch).
  * workspace [device] must hold yastn_plan_workspace bytes (256-byte aligned)
  * and must not be shared by calls that may overlap.  Results are
  * deterministic: no atomics, fixed summation order per output element. */
@@ -174,7 +176,7 @@ yastn_status yastn_contract_norm(yastn_plan_t plan, const void *const *a, const 
  * events[0] before the B pack kernel, events[1] between the pack kernel and
  * the grouped GEMM, events[2] after the GEMM ([host] array of 3 hipEvent_t
  * created by the caller; any entry may be NULL).  The plan must run in one
- * launch (at most 64 problems), else YASTN_ERR_STATE. */
+ * launch (at most 65536 problems), else YASTN_ERR_STATE. */
 yastn_status yastn_contract_timed(yastn_plan_t plan, const void *const *a, const void *const *b,
                                   void *const *c, void *workspace, void *hip_stream,
                                   void *const *events);

@@ -180,6 +180,12 @@ __global__ void k_zero2(double *out) {
   if (threadIdx.x < 2) out[threadIdx.x] = 0.0;
 }
 
+// Copies one chunk of a launch's problem pointers into its device table.
+__global__ void __launch_bounds__(256) k_put_ptrs(PtrChunk c) {
+  const int i = threadIdx.x;
+  if (i < c.n) c.dst[i] = c.p[i];
+}
+
 // Reduces np (sum of squares, max) parts in a fixed order: thread t takes
 // parts t, t + 1024, ... (independent loads, four in flight), then a tree.
 __global__ void __launch_bounds__(1024) k_norm_final(const double *part, int np, double *out) {
@@ -559,10 +565,28 @@ yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const
     std::memset(&la, 0, sizeof(la));
     int np = 0;
     const size_t j_first = ji;
+    // a group of more than kMaxProbs problems launches alone, its problem
+    // pointers in a table in its workspace (written by k_put_ptrs first)
+    const bool table = jobs[ji].g->phi - jobs[ji].g->plo > kMaxProbs;
+    if (table) {
+      const JobRef &j = jobs[ji];
+      ProbPtrs *tab = reinterpret_cast<ProbPtrs *>(reinterpret_cast<char *>(j.ws) + j.plan->ptab_off);
+      for (int p0 = j.g->plo; p0 < j.g->phi; p0 += kPtrChunk) {
+        PtrChunk pc;
+        std::memset(&pc, 0, sizeof(pc));
+        pc.dst = tab + (p0 - j.g->plo);
+        pc.n = std::min(kPtrChunk, j.g->phi - p0);
+        for (int i = 0; i < pc.n; ++i) pc.p[i] = ProbPtrs{j.a[p0 + i], j.b[p0 + i], j.c[p0 + i]};
+        void *pargs[] = {&pc};
+        YASTN_HIP(hipLaunchKernel(reinterpret_cast<const void *>(k_put_ptrs), dim3(1), dim3(256), pargs, 0, st));
+      }
+      la.ptab = tab;
+    }
     while (ji < jobs.size() && la.njobs < kMaxJobs) {
       const JobRef &j = jobs[ji];
       const int n = j.g->phi - j.g->plo;
-      if (np + n > kMaxProbs) break;
+      if (!table && np + n > kMaxProbs) break;
+      if (table && la.njobs == 1) break;
       JobArg &ja = la.jobs[la.njobs++];
       ja.plan = j.plan->dplan;
       ja.recs = j.plan->drecs;
@@ -574,7 +598,7 @@ yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const
       ja.pitem0 = j.g->i0;
       ja.prob0 = np;
       ja.plo = j.g->plo;
-      for (int p = j.g->plo; p < j.g->phi; ++p) {
+      for (int p = j.g->plo; p < j.g->phi && !table; ++p) {
         la.p[np].a = j.a[p];
         la.p[np].b = j.b[p];
         la.p[np].c = j.c[p];
@@ -612,7 +636,8 @@ yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const
       ra.nitems = j.g->r1 - j.g->r0;
       ra.plo = j.g->plo;
       ra.ws = reinterpret_cast<const char *>(j.ws);
-      for (int p = j.g->plo; p < j.g->phi; ++p) ra.p[p - j.g->plo] = ProbPtrs{j.a[p], j.b[p], j.c[p]};
+      ra.ptab = la.ptab;
+      for (int p = j.g->plo; p < j.g->phi && !table; ++p) ra.p[p - j.g->plo] = ProbPtrs{j.a[p], j.b[p], j.c[p]};
       void *rargs[] = {&ra};
       unsigned g = (unsigned)std::min<int64_t>(ra.nitems, 4096);
       YASTN_HIP(hipLaunchKernel(reduce, dim3(g), dim3(256), rargs, 0, st));

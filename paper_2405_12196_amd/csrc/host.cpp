@@ -590,10 +590,10 @@ void finish_tiles(Plan &plan) {
   plan.prob_i0.push_back((int32_t)t.items.size());
   plan.groups.clear();
   t.ljobs.clear();
-  for (int p0 = 0; p0 < np; p0 += kMaxProbs) {
+  for (int p0 = 0; p0 < np; p0 += kMaxTableProbs) {
     Group g{};
     g.plo = p0;
-    g.phi = std::min(np, p0 + kMaxProbs);
+    g.phi = std::min(np, p0 + kMaxTableProbs);
     g.t0 = plan.prob_t0[g.plo];
     g.t1 = plan.prob_t0[g.phi];
     g.i0 = plan.prob_i0[g.plo];
@@ -657,6 +657,9 @@ void finish_tiles(Plan &plan) {
   const size_t elem = plan.opts.precision == YASTN_F64 ? 8 : 4;
   plan.norm_off = ((size_t(t.bpack_elems) * elem + 255) / 256) * 256;
   plan.ws_bytes = plan.norm_off + ((t.tiles.size() * 2 * sizeof(double) + 255) / 256) * 256;
+  // problem pointer table of a group of more than kMaxProbs problems
+  plan.ptab_off = plan.ws_bytes;
+  if (np > kMaxProbs) plan.ws_bytes += ((size_t(std::min(np, kMaxTableProbs)) * sizeof(ProbPtrs) + 255) / 256) * 256;
   // split-K partial slots (accumulators of the compute type, 64 columns a row)
   for (RedGroup &r : t.red) {
     r.off0 = (int64_t)plan.ws_bytes;

@@ -75,6 +75,11 @@ __device__ __forceinline__ DevPlan load_plan(const DevPlan *p) {
   return d;
 }
 
+// The pointers of launch problem i (kernel arguments or the device table).
+__device__ __forceinline__ ProbPtrs prob_ptrs(const LaunchArgs &a, int i) {
+  return a.ptab ? cst(a.ptab + i) : a.p[i];
+}
+
 // LDS written by one lane and read by another lane of the same wave.
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -158,7 +163,7 @@ __global__ void __launch_bounds__(256) k_pack_b(LaunchArgs args) {
       constexpr int R = kGatherItem / 256;
       const int32_t *bo = P.bofs + sec.bofs0 + it.e0;
       Cmp *dst = reinterpret_cast<Cmp *>(job.ws) + sec.bpack + it.e0;
-      const In *src = reinterpret_cast<const In *>(args.p[job.prob0 + sec.prob - job.plo].b);
+      const In *src = reinterpret_cast<const In *>(prob_ptrs(args, job.prob0 + sec.prob - job.plo).b);
       const int32_t last = it.j - 1;
       int32_t o[R];
       In v[R];
@@ -182,7 +187,7 @@ __global__ void __launch_bounds__(256) k_pack_b(LaunchArgs args) {
     if (it.bblk < 0) {
       *dst = Cmp(0);
     } else {
-      const In *src = reinterpret_cast<const In *>(args.p[job.prob0 + sec.prob - job.plo].b);
+      const In *src = reinterpret_cast<const In *>(prob_ptrs(args, job.prob0 + sec.prob - job.plo).b);
       const DevBBlock bb = cst(P.bblocks + it.bblk);
       const DevProb pr = cst(P.probs + sec.prob);
       *dst = Cmp(src[b_offset(bb, ct, cl, pr, kd, cb)]);
@@ -281,7 +286,7 @@ __device__ __forceinline__ DevPlan tile_setup(const LaunchArgs &args, int t, int
   x.tile = cst(P.tiles + (t - job.tile0 + job.ptile0));
   x.rt = cst(P.rows + x.tile.rowtuple);
   x.sec = cst(P.sectors + x.tile.sector);
-  const ProbPtrs pp = args.p[job.prob0 + x.sec.prob - job.plo];
+  const ProbPtrs pp = prob_ptrs(args, job.prob0 + x.sec.prob - job.plo);
   const DevProb pr = cst(P.probs + x.sec.prob);
   x.A.init(pp.a, pr.a_span);
   x.B.init(pp.b, pr.b_span);
@@ -740,7 +745,7 @@ __device__ __forceinline__ void rec_setup(const LaunchArgs &args, const JobArg &
     x.rt.lmag[a + 1] = cst(&r->lmag[a]);
     x.rt.lsh[a + 1] = cst(&r->lsh[a]);
   }
-  const ProbPtrs pp = args.p[job.prob0 + prob - job.plo];
+  const ProbPtrs pp = prob_ptrs(args, job.prob0 + prob - job.plo);
   x.A.init(pp.a, a_span);
   x.B.init(pp.b, b_span);
   x.C.init(pp.c, c_numel);
@@ -1086,7 +1091,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
       const int32_t *bofs = cst(&r->bofs);
       const int32_t K = cst(&r->K), N = cst(&r->N), n0 = cst(&r->n0);
       Src<In, BUF> B;
-      B.init(args.p[job.prob0 + cst(&r->prob) - job.plo].b, cst(&r->b_span));
+      B.init(prob_ptrs(args, job.prob0 + cst(&r->prob) - job.plo).b, cst(&r->b_span));
       int32_t bo[BR];
       bool bv[BR];
 #pragma unroll
@@ -1287,7 +1292,7 @@ template <typename Acc, typename Out>
 __global__ void __launch_bounds__(256) k_split_reduce(RedArgs args) {
   for (int i = blockIdx.x; i < args.nitems; i += gridDim.x) {
     const DevRedItem &it = args.items[i];
-    Out *C = reinterpret_cast<Out *>(args.p[it.prob - args.plo].c);
+    Out *C = reinterpret_cast<Out *>((args.ptab ? cst(args.ptab + (it.prob - args.plo)) : args.p[it.prob - args.plo]).c);
     const int n = it.nrows * 64;
     for (int e = threadIdx.x; e < n; e += 256) {
       const int r = e >> 6, c = e & 63;

@@ -34,7 +34,8 @@ namespace yastn {
 constexpr int kMaxRank = 8;
 constexpr int kMaxAct = 4;     // free-leg classes of A (<= min(#free, #contracted + 1))
 constexpr int kMaxJobs = 32;   // plans per launch
-constexpr int kMaxProbs = 64;  // problems per launch (pointer triples in kernel args)
+constexpr int kMaxProbs = 64;  // problems per launch with the pointer triples in kernel args
+constexpr int kMaxTableProbs = 1 << 16;  // problems per launch group with a device pointer table
 constexpr int kPackItem = 256; // packed-B elements per sub-block pack work item
 constexpr int kGatherItem = 2048;  // packed-B elements per gather pack work item (8 per thread)
 
@@ -211,9 +212,13 @@ struct NormArgs {
   double *parts;               // [ntiles][2] in the workspace, null = no norm
 };
 
+// Problem pointers: p[] in the kernel arguments, or (a launch of one group of
+// more than kMaxProbs problems) the table ptab in the job's workspace, written
+// by k_put_ptrs before the launch.
 struct LaunchArgs {
   int32_t njobs, ntiles, nitems, pad;
   NormArgs norm;
+  const ProbPtrs *ptab;
   JobArg jobs[kMaxJobs];
   ProbPtrs p[kMaxProbs];
 };
@@ -224,7 +229,18 @@ struct RedArgs {
   const DevRedItem *items;
   int32_t nitems, plo;         // plo: plan problem of p[0]
   const char *ws;
+  const ProbPtrs *ptab;        // as LaunchArgs::ptab
   ProbPtrs p[kMaxProbs];
 };
+
+// One chunk of a device pointer table, written by k_put_ptrs.
+constexpr int kPtrChunk = 160;
+struct PtrChunk {
+  ProbPtrs *dst;
+  int32_t n, pad;
+  ProbPtrs p[kPtrChunk];
+};
+static_assert(sizeof(PtrChunk) <= 4096, "kernel arguments are limited to 4 KiB");
+static_assert(sizeof(RedArgs) <= 4096, "kernel arguments are limited to 4 KiB");
 
 }  // namespace yastn

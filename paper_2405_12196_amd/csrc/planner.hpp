@@ -71,8 +71,10 @@ struct PlanTables {
   std::vector<DevLdsJob> ljobs;  // shared-B workgroup jobs, per group
 };
 
-// Problems are launched in groups of at most kMaxProbs (their device pointers
-// travel as kernel arguments); tiles are cost-sorted within a group.
+// Problems are launched in groups: all of a plan's problems in one group (up
+// to kMaxTableProbs); a group of at most kMaxProbs problems takes its device
+// pointers as kernel arguments, a larger one from a table in the workspace.
+// Tiles are cost-sorted within a group.
 struct Group {
   int32_t plo, phi;          // problems [plo, phi)
   int32_t t0, t1;            // plan-local tiles
@@ -103,6 +105,7 @@ struct Plan {
   const DevLdsJob *dljobs = nullptr;  // device shared-B jobs
   size_t ws_bytes = 0;
   size_t norm_off = 0;      // workspace offset of the fused norm's per-tile parts
+  size_t ptab_off = 0;      // workspace offset of the problem pointer table (groups of > kMaxProbs problems)
   int device = 0;
 };
 

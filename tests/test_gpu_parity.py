@@ -306,9 +306,9 @@ def test_every_variant_matches_oracle(seed, variant):
         pl.set_variant(variant)
     except Y.YastnError as e:
         # the row kernel needs K, N <= 64, the register-resident B kernels
-        # K <= 64 (variant 16: K <= 80)
-        assert e.status == "ERR_STATE" and variant >= 7
-        limit = 80 if variant == 16 else 64
+        # K <= 64 (variant 16 and the shared-B variants 20-22: K <= 80)
+        assert e.status == "ERR_STATE" and variant >= 7 and not 17 <= variant <= 19
+        limit = 80 if variant in (16, 20, 21, 22) else 64
         assert max(pl.stats(0)["max_k"], pl.stats(0)["max_n"] if variant == 7 else 0) > limit
         return
     A, B = G.upload(a), G.upload(b)
@@ -316,6 +316,32 @@ def test_every_variant_matches_oracle(seed, variant):
     pl.contract([A], [B], [c], G.workspace(pl))
     torch.cuda.synchronize()
     check_f64(s, c.cpu().numpy()[:s.numel], ref)
+
+
+@pytest.mark.parametrize("variant", [20, 21, 22])
+def test_shared_b_kernel_interleaved_legs_in_one_batch(variant):
+    """The shared-B kernel on a batch mixing rank-7 operands with contracted
+    legs spread out (up to four free-leg classes of A), Z2 and U(1)xU(1)
+    problems and the D = 18 contraction, in one launch: every problem
+    against the oracle."""
+    import paper_2405_12196_amd as Y
+    probs = [random_problem(seed, sym, rank_a=7, rank_b=4, ncon=3, max_sectors=2, max_dim=3)
+             for sym, seed in [("Z2", 7100), ("Z2", 7103), ("Z2", 7105), ("Z2", 7108), ("Z3", 7103), ("Z3", 7107)]]
+    probs += [random_problem(seed + 7200, sym, rank_a=4, rank_b=3, ncon=2, max_sectors=3, max_dim=5, keep=0.7)
+              for seed, sym in enumerate(["Z2", "U1xU1", "U1xZ2"])]
+    c1 = W.config1(2)
+    probs += [(p.a, p.b, p.axes_a, p.axes_b) for p in c1]
+    pl = Y.plan(probs)
+    if max(pl.stats(i)["max_k"] for i in range(len(probs))) > 80:
+        pytest.skip("a sector with K > 80 (the kernel's limit)")
+    pl.set_variant(variant)
+    A = [G.upload(p[0]) for p in probs]
+    B = [G.upload(p[1]) for p in probs]
+    outs = [G.alloc_out(pl, i) for i in range(len(probs))]
+    pl.contract(A, B, [c for c, _ in outs], G.workspace(pl))
+    torch.cuda.synchronize()
+    for (a, b, xa, xb), (c, s) in zip(probs, outs):
+        check_f64(s, c.cpu().numpy()[:s.numel], oracle.tensordot_blockpair(a, b, xa, xb))
 
 
 @pytest.mark.parametrize("variant", range(0, NUM_VARIANTS))
