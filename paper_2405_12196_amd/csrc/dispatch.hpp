@@ -57,6 +57,7 @@ KernelFn rows_f64(bool buf, int kmax);
 KernelFn pf_f64(bool buf, int shape, int cb, int na);
 KernelFn pack_f64();
 KernelFn lds_f64(int shape, int cb, int kq, int na, bool norm);  // kq <= 20; norm: files the fused norm
+KernelFn lds_f64_norm(int shape, int cb, int kq, int na);
 // FP32 arithmetic with FP64 input buffers (out: F64 or F32)
 KernelFn gemm4_f32d(yastn_dtype out, bool buf, int shape, int cb);
 KernelFn res_f32d(yastn_dtype out, bool buf, int cb, int kq);

@@ -1,39 +1,11 @@
-// Template instances of the FP64 shared-B kernel (k_gemm_lds).
-#include "dispatch.hpp"
-#include "kernels.hpp"
+// Template instances of the FP64 shared-B kernel (k_gemm_lds) without the
+// fused norm, and the selection between the two instance sets.
+#include "lds_select.hpp"
 
 namespace yastn {
-namespace {
-typedef double D;
-template <int RB, int KQ, int NA, int PD, int OCC, bool NORM> KernelFn lds_cb(int cb) {
-  switch (cb) {
-    case 1: return k_gemm_lds<D, D, D, RB, 1, KQ, NA, PD, OCC, NORM>;
-    case 2: return k_gemm_lds<D, D, D, RB, 2, KQ, NA, PD, OCC, NORM>;
-    case 3: return k_gemm_lds<D, D, D, RB, 3, KQ, NA, PD, OCC, NORM>;
-    default: return k_gemm_lds<D, D, D, RB, 4, KQ, NA, PD, OCC, NORM>;
-  }
-}
-template <int RB, int NA, int PD, int OCC, bool NORM> KernelFn lds_kq(int kq, int cb) {
-  if (kq <= 5) return lds_cb<RB, 5, NA, PD, OCC, NORM>(cb);
-  if (kq <= 10) return lds_cb<RB, 10, NA, PD, OCC, NORM>(cb);
-  if (kq <= 16) return lds_cb<RB, 16, NA, PD, OCC, NORM>(cb);
-  return lds_cb<RB, 20, NA, PD, OCC, NORM>(cb);
-}
-template <int RB, int PD, int OCC, bool NORM> KernelFn lds_na(int na, int kq, int cb) {
-  return na <= 2 ? lds_kq<RB, 2, PD, OCC, NORM>(kq, cb) : lds_kq<RB, 4, PD, OCC, NORM>(kq, cb);
-}
-template <bool NORM> KernelFn lds_shape(int shape, int cb, int kq, int na) {
-  switch (shape) {  // kLdsShapes {rb, pd, occ}
-    case 1: return lds_na<1, 0, 3, NORM>(na, kq, cb);
-    case 2: return lds_na<2, 0, 2, NORM>(na, kq, cb);
-    default: return lds_na<1, 1, 2, NORM>(na, kq, cb);
-  }
-}
-}  // namespace
 
 KernelFn lds_f64(int shape, int cb, int kq, int na, bool norm) {
-  if (kq > 20) return nullptr;
-  return norm ? lds_shape<true>(shape, cb, kq, na) : lds_shape<false>(shape, cb, kq, na);
+  return norm ? lds_f64_norm(shape, cb, kq, na) : lds_inst::lds_shape<false>(shape, cb, kq, na);
 }
 
 }  // namespace yastn
