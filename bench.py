@@ -397,9 +397,11 @@ def batch_section(torch, Y, W, ev, sp):
     resident in the caches from the previous launch) and cold (Infinity Cache
     flushed before each launch)."""
     res = {}
-    cases = [("cfg1_x64", W.config1(64), "f64"), ("cfg1_x512", W.config1(512), "f64"),
-             ("cfg3_64probs", W.config3(), "f64"), ("cfg3_64probs_f32", W.config3(), "f32")]
-    for name, probs, prec in cases:
+    cases = [("cfg1_x1", lambda: W.config1(1), "f64"), ("cfg1_x64", lambda: W.config1(64), "f64"),
+             ("cfg1_x512", lambda: W.config1(512), "f64"), ("cfg1_x4096", lambda: W.config1(4096), "f64"),
+             ("cfg3_64probs", W.config3, "f64"), ("cfg3_64probs_f32", W.config3, "f32")]
+    for name, make, prec in cases:
+        probs = make()
         f64 = prec == "f64"
         dt = torch.float64 if f64 else torch.float32
         pl = Y.plan([(p.a, p.b, p.axes_a, p.axes_b) for p in probs], precision=prec, stream=sp)
