@@ -189,9 +189,9 @@ yastn_status yastn_contract_timed(yastn_plan_t plan, const void *const *a, const
  * K <= 80 for variant 16, which runs one wave per SIMD);
  * 17-19: MFMA tiles over a packed B with the k loop software-pipelined (any K;
  * three shapes);
- * 20-22: as 8-16, FP64 only, K <= 80, with each workgroup loading the B tile
- * of up to four row tiles of one sector column range into shared memory once
- * (three chunk / occupancy shapes).
+ * 20-22: as 8-16 for K <= 80, with each workgroup loading the B tile of up
+ * to four row tiles of one sector column range into shared memory once
+ * (three chunk / occupancy shapes; FP32 arithmetic: variant 22 only).
  * yastn_plan_autotune runs every variant that fits the plan `reps` times on
  * the caller's buffers (same arguments as yastn_contract; C is overwritten),
  * times them with HIP events, keeps the fastest in the plan and returns its

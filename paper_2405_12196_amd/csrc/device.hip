@@ -479,8 +479,10 @@ bool variant_fits(const Fit &f, const yastn_options &o, int v) {
     if (!f.res || !f.buf || f.kmax > res_max_k(v - kVariantRes0)) return false;
     return o.precision == YASTN_F64 || v == kVariantRes0 + 1;  // FP32: one shape compiled (kResShapes[1])
   }
-  if (v >= kVariantLds0 && v < kVariants)  // FP64 only; K <= 80
-    return f.res && f.buf && o.precision == YASTN_F64 && f.kmax <= kResMaxKWide;
+  if (v >= kVariantLds0 && v < kVariants) {  // K <= 80; FP32: one shape compiled (kLdsShapes[2])
+    if (!f.res || !f.buf || f.kmax > kResMaxKWide) return false;
+    return o.precision == YASTN_F64 || v == kVariantLds0 + 2;
+  }
   if (v >= kVariantPf0 && v < kVariantLds0) {
     if (!f.buf) return false;
     return o.precision == YASTN_F64 || v == kVariantPf0;  // FP32: one shape compiled (kPfShapes[0])
@@ -497,14 +499,18 @@ Choice choose(const Fit &f, const yastn_options &o, int variant, bool norm = fal
     else if (f.bf16) variant = variant_fits(f, o, kVariantRes0) ? kVariantRes0 : 1;
     else if (f.rows_pick && f.rows) variant = kVariantRows;
     else if (f.res && f.kmax <= kResMaxK) variant = o.precision == YASTN_F64 ? kVariantRes0 : kVariantRes0 + 1;
-    else if (f.res && o.precision == YASTN_F64) variant = kVariantLds0;
+    else if (f.res) variant = o.precision == YASTN_F64 ? kVariantLds0 : kVariantLds0 + 2;
     else variant = kVariantPf0;
   }
   const int kq = (f.kmax + 3) / 4;
   const int na = f.nact <= 2 ? 2 : 4;
   if (variant == kVariantRows) return Choice{FAM_ROWS, rows_kernel(o, f.buf, f.kmax), pack_kernel(o)};
-  if (variant >= kVariantLds0)
-    return Choice{FAM_LDS, lds_f64(variant - kVariantLds0, f.cb, kq, na, norm), nullptr};
+  if (variant >= kVariantLds0) {
+    KernelFn fn = o.precision == YASTN_F64          ? lds_f64(variant - kVariantLds0, f.cb, kq, na, norm)
+                  : o.in_dtype == YASTN_DTYPE_F64 ? lds_f32d(o.out_dtype, f.cb, kq, norm)
+                                                  : lds_f32f(o.out_dtype, f.cb, kq, norm);
+    return Choice{FAM_LDS, fn, nullptr};
+  }
   if (variant >= kVariantPf0)
     return Choice{FAM_PF, pf_kernel(o, f.buf, variant - kVariantPf0, f.cb, na), pack_kernel(o)};
   if (variant >= kVariantRes0)
@@ -786,7 +792,7 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
       // with 64 < K <= 80 run on the shared-B kernel, whose jobs share one B
       // tile among up to eight tiles: 16-row tiles balance its waves best
       // (measured on batches of the rank-4 U(1) D=18 contraction)
-      if (maxk > kResMaxK && maxk <= kResMaxKWide && o.precision == YASTN_F64 && !bf16) {
+      if (maxk > kResMaxK && maxk <= kResMaxKWide && !bf16) {
         tm = 16;
       } else {
         tm = maxk > kResMaxK ? 32 : 16;

@@ -64,12 +64,14 @@ KernelFn res_f32d(yastn_dtype out, bool buf, int cb, int kq);
 KernelFn rows_f32d(yastn_dtype out, bool buf, int kmax);
 KernelFn pf_f32d(yastn_dtype out, bool buf, int cb);
 KernelFn pack_f32d();
+KernelFn lds_f32d(yastn_dtype out, int cb, int kq, bool norm);  // shape kLdsShapes[2], kq <= 20
 // FP32 arithmetic with FP32 input buffers
 KernelFn gemm4_f32f(yastn_dtype out, bool buf, int shape, int cb);
 KernelFn res_f32f(yastn_dtype out, bool buf, int cb, int kq);
 KernelFn rows_f32f(yastn_dtype out, bool buf, int kmax);
 KernelFn pf_f32f(yastn_dtype out, bool buf, int cb);
 KernelFn pack_f32f();
+KernelFn lds_f32f(yastn_dtype out, int cb, int kq, bool norm);  // shape kLdsShapes[2], kq <= 20
 // split-BF16 products (nt = 3 or 6), FP32 accumulation
 KernelFn bf16_gemm(yastn_dtype in, yastn_dtype out, int nt, bool buf, int cb);
 // split-BF16 register-resident tiles, FP32 operand buffers, K <= 64 (nullptr otherwise)

@@ -51,8 +51,28 @@ template <typename Out> KernelFn pf(bool buf, int cb) {
     default: return k_gemm_pf<In, F, Out, true, 2, 4, 2, 4, 2>;
   }
 }
+// shared-B tiles: one shape (rows per chunk 32, no chunk prefetch, 2+ waves per SIMD)
+template <typename Out, int KQ, bool NORM> KernelFn lds_cb(int cb) {
+  switch (cb) {
+    case 1: return k_gemm_lds<In, F, Out, 2, 1, KQ, 4, 0, 2, NORM>;
+    case 2: return k_gemm_lds<In, F, Out, 2, 2, KQ, 4, 0, 2, NORM>;
+    case 3: return k_gemm_lds<In, F, Out, 2, 3, KQ, 4, 0, 2, NORM>;
+    default: return k_gemm_lds<In, F, Out, 2, 4, KQ, 4, 0, 2, NORM>;
+  }
+}
+template <typename Out, bool NORM> KernelFn lds(int cb, int kq) {
+  if (kq <= 5) return lds_cb<Out, 5, NORM>(cb);
+  if (kq <= 10) return lds_cb<Out, 10, NORM>(cb);
+  if (kq <= 16) return lds_cb<Out, 16, NORM>(cb);
+  if (kq <= 20) return lds_cb<Out, 20, NORM>(cb);
+  return nullptr;
+}
 }  // namespace
 
+KernelFn lds_f32d(yastn_dtype out, int cb, int kq, bool norm) {
+  if (out == YASTN_DTYPE_F64) return norm ? lds<double, true>(cb, kq) : lds<double, false>(cb, kq);
+  return norm ? lds<float, true>(cb, kq) : lds<float, false>(cb, kq);
+}
 KernelFn pf_f32d(yastn_dtype out, bool buf, int cb) {
   return out == YASTN_DTYPE_F64 ? pf<double>(buf, cb) : pf<float>(buf, cb);
 }

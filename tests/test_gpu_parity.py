@@ -185,6 +185,45 @@ def test_reduced_precision_config2_step3(prec, kind):
     assert oracle.rel_frobenius(v, ref.data) <= TOL[prec]
 
 
+@pytest.mark.parametrize("in_f32,out_f32", [(False, False), (True, False), (True, True)])
+def test_fp32_shared_b_kernel(in_f32, out_f32):
+    """FP32 arithmetic on the shared-B kernel (variant 22): the D = 18
+    contraction and every corner step, each within the FP32 tolerance of the
+    FP64 oracle; the fused norm of the last step against the oracle's."""
+    import paper_2405_12196_amd as Y
+    ind = Y.DTYPE_F32 if in_f32 else Y.DTYPE_F64
+    outd = Y.DTYPE_F32 if out_f32 else Y.DTYPE_F64
+    t = W.config2()
+    (p1,) = W.config1()
+    cases, cur = [(p1.a, p1.b, p1.axes_a, p1.axes_b)], None
+    for (an, bn), (ax, bx) in zip([("C", "T1"), (None, "T4"), (None, "A"), (None, "Ac")], t["axes"]):
+        a = t[an] if an else cur
+        cases.append((a, t[bn], ax, bx))
+        cur = oracle.tensordot_blockpair(a, t[bn], ax, bx)
+    for i, (a, b, xa, xb) in enumerate(cases):
+        ref = oracle.tensordot_blockpair(a, b, xa, xb)
+        pl = Y.plan([(a, b, xa, xb)], precision="f32", in_dtype=ind, out_dtype=outd)
+        pl.set_variant(22)
+        A, B = G.upload(a, ind), G.upload(b, ind)
+        c = torch.empty(max(1, pl.output(0).numel), dtype=torch.float32 if out_f32 else torch.float64, device=G.DEV)
+        ws = G.workspace(pl)
+        last = i == len(cases) - 1
+        nout = torch.full((2,), float("nan"), dtype=torch.float64, device=G.DEV)
+        if last:
+            pl.contract_norm([A], [B], [c], ws, nout)
+        else:
+            pl.contract([A], [B], [c], ws)
+        torch.cuda.synchronize()
+        v = c.double().cpu().numpy()[:pl.output(0).numel]
+        assert not np.any(np.isnan(v))
+        err = oracle.rel_frobenius(v, ref.data)
+        assert err <= TOL["f32"], f"case {i}: {err:.3e}"
+        if last:
+            rf, rm = oracle.norms(ref)
+            got = nout.cpu().numpy()
+            assert abs(got[0] - rf) <= TOL["f32"] * rf and abs(got[1] - rm) <= TOL["f32"] * rm
+
+
 @pytest.mark.parametrize("prec", ["bf16x3", "bf16x6"])
 @pytest.mark.parametrize("variant", [1, 8])
 def test_bf16_tile_kinds_config2_steps(prec, variant):
