@@ -336,7 +336,6 @@ yastn_status upload(Plan &pl) {
   put(o_kp, t.kp.data(), bytes_of(t.kp));
   put(o_cm, t.colmap.data(), bytes_of(t.colmap));
   put(o_bofs, t.bofs.data(), bytes_of(t.bofs));
-  put(o_lj, t.ljobs.data(), bytes_of(t.ljobs));
   pl.dljobs = reinterpret_cast<const DevLdsJob *>(base + o_lj);
   DevPlan dp{};
   dp.probs = reinterpret_cast<const DevProb *>(base + o_probs);
@@ -358,6 +357,17 @@ yastn_status upload(Plan &pl) {
   std::vector<DevTileRec> recs;
   build_tile_records(pl, dp, recs);
   put(o_recs, recs.data(), recs.size() * sizeof(DevTileRec));
+  // shared-B jobs with their B tile's fields
+  for (DevLdsJob &lj : t.ljobs) {
+    const DevTileRec &r = recs[size_t(lj.t[0])];
+    lj.bofs = r.bofs;
+    lj.b_span = r.b_span;
+    lj.K = r.K;
+    lj.N = r.N;
+    lj.n0 = r.n0;
+    lj.prob = r.prob;
+  }
+  put(o_lj, t.ljobs.data(), bytes_of(t.ljobs));
   // split-K groups with absolute table addresses
   std::vector<DevRedItem> red(t.red.size());
   for (size_t i = 0; i < t.red.size(); ++i) {
@@ -498,7 +508,11 @@ Choice choose(const Fit &f, const yastn_options &o, int variant, bool norm = fal
     if (f.mfma_pick || !f.buf) variant = 1;
     else if (f.bf16) variant = variant_fits(f, o, kVariantRes0) ? kVariantRes0 : 1;
     else if (f.rows_pick && f.rows) variant = kVariantRows;
-    else if (f.res && f.kmax <= kResMaxK) variant = o.precision == YASTN_F64 ? kVariantRes0 : kVariantRes0 + 1;
+    // K <= 64: the register-resident tiles, or for FP64 plans whose tiles are
+    // at most 48 columns wide the shared-B kernel (the faster of the two on
+    // every measured corner step)
+    else if (f.res && f.kmax <= kResMaxK)
+      variant = o.precision != YASTN_F64 ? kVariantRes0 + 1 : f.cb <= 3 ? kVariantLds0 + 2 : kVariantRes0;
     else if (f.res) variant = o.precision == YASTN_F64 ? kVariantLds0 : kVariantLds0 + 2;
     else variant = kVariantPf0;
   }

@@ -633,7 +633,7 @@ void finish_tiles(Plan &plan) {
         size_t e = i;
         while (e < byk.size() && key(byk[e]) == key(byk[i])) ++e;
         for (size_t s0 = i; s0 < e; s0 += kLdsJobTiles) {
-          DevLdsJob lj;
+          DevLdsJob lj{};
           double wave[4] = {0, 0, 0, 0};
           for (int u = 0; u < kLdsJobTiles; ++u) {
             const bool in = s0 + u < e;

@@ -1085,13 +1085,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
     const JobArg &job = args.jobs[jb];
     const DevLdsJob *lj = cst(&job.ljobs) + (j - job.tile0 + job.ptile0);
     {
-      // the B tile, from the job's first tile record: every offset-table
-      // read, then every B read, then the LDS stores
-      const DevTileRec *r = cst(&job.recs) + cst(&lj->t[0]);
-      const int32_t *bofs = cst(&r->bofs);
-      const int32_t K = cst(&r->K), N = cst(&r->N), n0 = cst(&r->n0);
+      // the B tile: every offset-table read, then every B read, then the
+      // LDS stores
+      const int32_t *bofs = cst(&lj->bofs);
+      const int32_t K = cst(&lj->K), N = cst(&lj->N), n0 = cst(&lj->n0);
       Src<In, BUF> B;
-      B.init(prob_ptrs(args, job.prob0 + cst(&r->prob) - job.plo).b, cst(&r->b_span));
+      B.init(prob_ptrs(args, job.prob0 + cst(&lj->prob) - job.plo).b, cst(&lj->b_span));
       int32_t bo[BR];
       bool bv[BR];
 #pragma unroll

@@ -184,10 +184,15 @@ struct DevPlan {               // device-resident table of the plan's arrays
 // A shared-B workgroup job: wave tiles of one (sector, column range) of one
 // problem (plan-local tile indices; -1 = none, t[0] always a tile).  Wave w of
 // the workgroup computes t[w], t[w + 4], ...
+// The B tile's fields (those of the first tile's record) are copied in at
+// upload, so the B loads start one dependent read earlier.
 constexpr int kLdsJobTiles = 4;
 static_assert(kLdsJobTiles % 4 == 0, "four waves per job");
 struct DevLdsJob {
   int32_t t[kLdsJobTiles];
+  const int32_t *bofs;         // the sector's B offsets from the tiles' k0, K x N row-major
+  int64_t b_span;              // element bound of the problem's B buffer
+  int32_t K, N, n0, prob;      // the tiles' K range length, N_X, first column, plan-local problem
 };
 
 struct ProbPtrs {
