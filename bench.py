@@ -354,7 +354,7 @@ def precision_section(torch, Y, W, ev, sp, K, plain_value):
     step's output against the FP64 path (which the tests hold to the CPU
     oracle within 1e-12)."""
     out = {}
-    for name, t in (("chi128_D8", W.config2()), ("chi256_D10", W.config4())):
+    for name, t in (("chi128_D8", W.ctm()), ("chi256_D10", W.ctm_chi256())):
         ref, rows = None, {}
         for prec in ("f64", "f32", "bf16x3", "bf16x6"):
             ch = Chain(torch, Y, t, prec=prec, sp=sp)
@@ -397,9 +397,9 @@ def batch_section(torch, Y, W, ev, sp):
     resident in the caches from the previous launch) and cold (Infinity Cache
     flushed before each launch)."""
     res = {}
-    cases = [("cfg1_x1", lambda: W.config1(1), "f64"), ("cfg1_x64", lambda: W.config1(64), "f64"),
-             ("cfg1_x512", lambda: W.config1(512), "f64"), ("cfg1_x4096", lambda: W.config1(4096), "f64"),
-             ("cfg3_64probs", W.config3, "f64"), ("cfg3_64probs_f32", W.config3, "f32")]
+    cases = [("u1_d18_x1", lambda: W.u1_d18(1), "f64"), ("u1_d18_x64", lambda: W.u1_d18(64), "f64"),
+             ("u1_d18_x512", lambda: W.u1_d18(512), "f64"), ("u1_d18_x4096", lambda: W.u1_d18(4096), "f64"),
+             ("u1_uneven_x64", W.u1_uneven, "f64"), ("u1_uneven_x64_f32", W.u1_uneven, "f32")]
     for name, make, prec in cases:
         probs = make()
         f64 = prec == "f64"
@@ -435,7 +435,7 @@ def grad_section(torch, Y, W, ev, sp):
     contraction with the dual of the other operand, then the permutation back
     to the operand's leg order), timed as graphs of repeated calls; the step
     inputs come from the library's own forward chain."""
-    t = W.config2()
+    t = W.ctm()
     up = lambda x: torch.from_numpy(np.ascontiguousarray(x.data)).to("cuda:0")
     res, cur, cur_dev = {}, None, None
     for i, ((an, bn), (ax, bx)) in enumerate(zip(STEPS, t["axes"])):
@@ -549,7 +549,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the precision sweep, the batched configs and the serving loop")
     ap.add_argument("--serve-requests", type=int, default=64)
-    ap.add_argument("--batch-only", default="", choices=["", "cfg1_x64", "cfg1_x512", "cfg3_64probs"],
+    ap.add_argument("--batch-only", default="", choices=["", "u1_d18_x64", "u1_d18_x512", "u1_uneven_x64"],
                     help="run only this grouped launch (autotuned, then --steps launches) and print its time; "
                          "for profiling")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -577,8 +577,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.batch_only:
-        probs = {"cfg1_x64": lambda: W.config1(64), "cfg1_x512": lambda: W.config1(512),
-                 "cfg3_64probs": W.config3}[args.batch_only]()
+        probs = {"u1_d18_x64": lambda: W.u1_d18(64), "u1_d18_x512": lambda: W.u1_d18(512),
+                 "u1_uneven_x64": W.u1_uneven}[args.batch_only]()
         sp = int(torch.cuda.current_stream().cuda_stream)
         pl = Y.plan([(p.a, p.b, p.axes_a, p.axes_b) for p in probs], stream=sp, tile_rows=args.tile_rows)
         A = [torch.from_numpy(p.a.data).to("cuda:0") for p in probs]
@@ -601,7 +601,7 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     sp = int(stream.cuda_stream)
-    t = W.config2()
+    t = W.ctm()
     # ---- plans (once; structure is fixed across CTM iterations)
     tp0 = time.perf_counter()
     plans, descs = [], []

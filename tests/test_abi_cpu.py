@@ -52,7 +52,7 @@ def _oracle_status(a, b, xa, xb):
 
 
 def _cases():
-    (p,) = W.config1()
+    (p,) = W.u1_d18()
     a, b = p.a, p.b
     out = [("axes length", a, b, (2, 3), (0,)), ("axes repeated", a, b, (2, 2), (0, 1)),
            ("axes range", a, b, (2, 7), (0, 1)), ("equal signature", a, b, (0, 1), (0, 1))]
@@ -88,7 +88,7 @@ def test_status_class_matches_oracle(case):
 def test_valid_problem_without_gpu_is_hip_error_or_ok():
     # validation passes; without a device the join cannot run
     import torch
-    (p,) = W.config1()
+    (p,) = W.u1_d18()
     st = _status(p.a, p.b, p.axes_a, p.axes_b)
     if torch.cuda.is_available():
         assert st == "OK"
@@ -104,7 +104,7 @@ def test_random_valid_problems_pass_host_validation(seed):
 
 
 def test_bad_options_rejected():
-    (p,) = W.config1()
+    (p,) = W.u1_d18()
     with pytest.raises(Y.YastnError) as e:
         Y.plan([(p.a, p.b, p.axes_a, p.axes_b)], precision="f64", in_dtype=Y.DTYPE_F32, stream=0)
     assert e.value.status == "ERR_ARG"

@@ -83,8 +83,8 @@ def check(res, ref):
     assert oracle.rel_frobenius(vals, ref.data) <= 1e-12
 
 
-def test_emu_config1(emu):
-    (p,) = W.config1()
+def test_emu_u1_d18(emu):
+    (p,) = W.u1_d18()
     (res,) = run_emu(emu, [(p.a, p.b, p.axes_a, p.axes_b)])
     check(res, oracle.tensordot_dense(p.a, p.b, p.axes_a, p.axes_b))
 
@@ -109,8 +109,8 @@ def test_emu_interleaved_legs(emu):
         check(res, oracle.tensordot_blockpair(a, b, xa, xb))
 
 
-def test_emu_config2_steps_1_to_3(emu):
-    t = W.config2()
+def test_emu_ctm_steps_1_to_3(emu):
+    t = W.ctm()
     cur = None
     for (an, bn), (ax, bx) in zip([("C", "T1"), (None, "T4"), (None, "A")], t["axes"][:3]):
         a = t[an] if an else cur
@@ -120,8 +120,8 @@ def test_emu_config2_steps_1_to_3(emu):
         cur = ref
 
 
-def test_emu_config3_batch(emu):
-    probs = [(p.a, p.b, p.axes_a, p.axes_b) for p in W.config3(12)]
+def test_emu_u1_uneven_batch(emu):
+    probs = [(p.a, p.b, p.axes_a, p.axes_b) for p in W.u1_uneven(12)]
     for res, (a, b, xa, xb) in zip(run_emu(emu, probs), probs):
         check(res, oracle.tensordot_blockpair(a, b, xa, xb))
 
@@ -135,7 +135,7 @@ def test_emu_subblock_pack(emu, seed):
         a, b, xa, xb = random_problem(seed + 4000, sym, rank_a=2 + seed % 3, rank_b=2 + (seed // 3) % 3,
                                       max_sectors=4, max_dim=6, keep=0.75 if seed % 2 else None,
                                       shuffle=seed % 2 == 0, drop_partner=seed == 3)
-        probs = [(a, b, xa, xb)] + [(p.a, p.b, p.axes_a, p.axes_b) for p in W.config3(3, seed=seed)]
+        probs = [(a, b, xa, xb)] + [(p.a, p.b, p.axes_a, p.axes_b) for p in W.u1_uneven(3, seed=seed)]
         for res, (a, b, xa, xb) in zip(run_emu(emu, probs), probs):
             check(res, oracle.tensordot_blockpair(a, b, xa, xb))
     finally:

@@ -80,7 +80,7 @@ def chain_check(t, ch, nsample, seed):
 
 def test_headline_chain_autotuned_full_oracle():
     """chi = 128, D = 8: the timed chain, every element against the oracle."""
-    t = W.config2()
+    t = W.ctm()
     ch = Chain(torch, Y, t)
     for o in ch.outs:
         o.fill_(float("nan"))
@@ -99,7 +99,7 @@ def test_headline_chain_autotuned_full_oracle():
 
 @pytest.fixture(scope="module")
 def chi256():
-    t = W.config4()
+    t = W.ctm_chi256()
     ch = Chain(torch, Y, t)
     ref = chain_check(t, ch, nsample=16, seed=40)
     del ch
@@ -127,12 +127,12 @@ def test_chi256_D10_reduced_precision(chi256, prec):
     assert abs(float(ch.nout[0]) / float(torch.linalg.vector_norm(got)) - 1) <= 1e-13
 
 
-@pytest.mark.parametrize("name", ["cfg1_x64", "cfg1_x512", "cfg3", "cfg3_f32"])
+@pytest.mark.parametrize("name", ["u1_d18_x64", "u1_d18_x512", "u1_uneven", "u1_uneven_f32"])
 def test_grouped_batches(name):
     """The grouped launches of the batch workloads (autotuned up to 64
     problems, as timed): sampled problems in full against the oracle."""
-    probs = {"cfg1_x64": lambda: W.config1(64), "cfg1_x512": lambda: W.config1(512),
-             "cfg3": W.config3, "cfg3_f32": W.config3}[name]()
+    probs = {"u1_d18_x64": lambda: W.u1_d18(64), "u1_d18_x512": lambda: W.u1_d18(512),
+             "u1_uneven": W.u1_uneven, "u1_uneven_f32": W.u1_uneven}[name]()
     prec = "f32" if name.endswith("f32") else "f64"
     dt = torch.float32 if prec == "f32" else torch.float64
     pl = Y.plan([(p.a, p.b, p.axes_a, p.axes_b) for p in probs], precision=prec)

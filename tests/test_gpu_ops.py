@@ -44,9 +44,9 @@ def test_permute_matches_oracle(seed):
         assert np.array_equal(v, want)
 
 
-def test_permute_config2_intermediate():
+def test_permute_ctm_intermediate():
     """The chi = 128 step-3 output (rank 7, 15,643 blocks): reverse its legs."""
-    t = W.config2()
+    t = W.ctm()
     cur = None
     for (an, bn), (ax, bx) in zip([("C", "T1"), (None, "T4"), (None, "A")], t["axes"][:3]):
         cur = oracle.tensordot_blockpair(t[an] if an else cur, t[bn], ax, bx)
@@ -101,10 +101,10 @@ def test_grad_random_matches_oracle(seed, wrt):
 
 @pytest.mark.parametrize("wrt", [0, 1])
 @pytest.mark.parametrize("step", [2, 3])
-def test_grad_config2_steps(step, wrt):
+def test_grad_ctm_steps(step, wrt):
     """Corner steps 3 (A's contracted legs 0, 3) and 4 (0, 2, 6): gradients
     that need the permutation back to the operand's leg order."""
-    t = W.config2()
+    t = W.ctm()
     cur = None
     steps = [("C", "T1"), (None, "T4"), (None, "A"), (None, "Ac")]
     for i, ((an, bn), (ax, bx)) in enumerate(zip(steps, t["axes"])):
@@ -119,8 +119,8 @@ def test_grad_config2_steps(step, wrt):
         cur = oracle.tensordot_blockpair(a, t[bn], ax, bx)
 
 
-def test_grad_config1_fp32():
-    (p,) = W.config1()
+def test_grad_u1_d18_fp32():
+    (p,) = W.u1_d18()
     dc = _dc(p.a, p.b, p.axes_a, p.axes_b, 5)
     ref = oracle.tensordot_grad(p.a, p.b, p.axes_a, p.axes_b, dc, 0)
     s, v = run_grad(p.a, p.b, p.axes_a, p.axes_b, dc, 0, precision="f32")

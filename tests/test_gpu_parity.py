@@ -39,9 +39,9 @@ def check_f64(s, vals, ref, tol=TOL_F64):
     return err
 
 
-# ---------------------------------------------------------------- config 1
-def test_config1_f64():
-    (p,) = W.config1()
+# ------------------------------------------------- rank-4 U(1), D = 18
+def test_u1_d18_f64():
+    (p,) = W.u1_d18()
     ref = oracle.tensordot_dense(p.a, p.b, p.axes_a, p.axes_b)
     pl, (s,), (v,) = G.run([(p.a, p.b, p.axes_a, p.axes_b)])
     check_f64(s, v, ref)
@@ -136,10 +136,10 @@ def test_permuted_legs_and_gapped_buffers():
     check_f64(s, v, ref)
 
 
-# ------------------------------------------------------------ config 2
+# ------------------------------------------------ CTM enlarged corner
 @pytest.mark.parametrize("kind", list(FLAGS))
-def test_config2_chain_f64(kind):
-    t = W.config2()
+def test_ctm_chain_f64(kind):
+    t = W.ctm()
     steps = [("C", "T1"), (None, "T4"), (None, "A"), (None, "Ac")]
     cur_ref, cur_gpu = None, None
     for (an, bn), (ax, bx) in zip(steps, t["axes"]):
@@ -151,9 +151,9 @@ def test_config2_chain_f64(kind):
         cur_ref, cur_gpu = ref, G.as_block_tensor(s, v)
 
 
-# ------------------------------------------------------------ config 3
-def test_config3_batched_one_launch():
-    probs = [(p.a, p.b, p.axes_a, p.axes_b) for p in W.config3()]
+# ------------------------------------------- 64 uneven U(1) problems
+def test_u1_uneven_batched_one_launch():
+    probs = [(p.a, p.b, p.axes_a, p.axes_b) for p in W.u1_uneven()]
     pl, S, V = G.run(probs)
     for (a, b, xa, xb), s, v in zip(probs, S, V):
         check_f64(s, v, oracle.tensordot_blockpair(a, b, xa, xb))
@@ -163,9 +163,9 @@ def test_config3_batched_one_launch():
 # ------------------------------------------------------- reduced precision
 @pytest.mark.parametrize("prec", ["f32", "bf16x3", "bf16x6"])
 @pytest.mark.parametrize("in_f32", [True, False])
-def test_reduced_precision_config1(prec, in_f32):
+def test_reduced_precision_u1_d18(prec, in_f32):
     import paper_2405_12196_amd as Y
-    (p,) = W.config1()
+    (p,) = W.u1_d18()
     ref = oracle.tensordot_dense(p.a, p.b, p.axes_a, p.axes_b)
     _, (s,), (v,) = G.run([(p.a, p.b, p.axes_a, p.axes_b)], precision=prec,
                           in_dtype=Y.DTYPE_F32 if in_f32 else Y.DTYPE_F64, out_dtype=Y.DTYPE_F64)
@@ -176,8 +176,8 @@ def test_reduced_precision_config1(prec, in_f32):
 
 @pytest.mark.parametrize("kind", ["auto", "mfma"])
 @pytest.mark.parametrize("prec", ["f32", "bf16x3", "bf16x6"])
-def test_reduced_precision_config2_step3(prec, kind):
-    t = W.config2()
+def test_reduced_precision_ctm_step3(prec, kind):
+    t = W.ctm()
     a = oracle.tensordot_blockpair(oracle.tensordot_blockpair(t["C"], t["T1"], (1,), (0,)), t["T4"], (0,), (0,))
     ref = oracle.tensordot_blockpair(a, t["A"], (0, 3), (0, 1))
     _, (s,), (v,) = G.run([(a, t["A"], (0, 3), (0, 1))], precision=prec, flags=FLAGS[kind])
@@ -193,8 +193,8 @@ def test_fp32_shared_b_kernel(in_f32, out_f32):
     import paper_2405_12196_amd as Y
     ind = Y.DTYPE_F32 if in_f32 else Y.DTYPE_F64
     outd = Y.DTYPE_F32 if out_f32 else Y.DTYPE_F64
-    t = W.config2()
-    (p1,) = W.config1()
+    t = W.ctm()
+    (p1,) = W.u1_d18()
     cases, cur = [(p1.a, p1.b, p1.axes_a, p1.axes_b)], None
     for (an, bn), (ax, bx) in zip([("C", "T1"), (None, "T4"), (None, "A"), (None, "Ac")], t["axes"]):
         a = t[an] if an else cur
@@ -226,12 +226,12 @@ def test_fp32_shared_b_kernel(in_f32, out_f32):
 
 @pytest.mark.parametrize("prec", ["bf16x3", "bf16x6"])
 @pytest.mark.parametrize("variant", [1, 8])
-def test_bf16_tile_kinds_config2_steps(prec, variant):
+def test_bf16_tile_kinds_ctm_steps(prec, variant):
     """Split-BF16 with FP32 operand buffers: the packed-B tiles (variant 1)
     and the register-resident tiles (variant 8, K <= 64) on every corner
     step, each within the stated error of the FP64 oracle."""
     import paper_2405_12196_amd as Y
-    t = W.config2()
+    t = W.ctm()
     cur = None
     for i, ((an, bn), (ax, bx)) in enumerate(zip([("C", "T1"), (None, "T4"), (None, "A"), (None, "Ac")], t["axes"])):
         a = t[an] if an else cur
@@ -252,7 +252,7 @@ def test_bf16_tile_kinds_config2_steps(prec, variant):
 # ------------------------------------------------------------ invariants
 @pytest.mark.parametrize("kind", ["mfma", "rows"])
 def test_repeat_runs_bitwise_identical(kind):
-    t = W.config2()
+    t = W.ctm()
     a = oracle.tensordot_blockpair(t["C"], t["T1"], (1,), (0,))
     _, _, (v1,) = G.run([(a, t["T4"], (0,), (0,))], flags=FLAGS[kind])
     _, _, (v2,) = G.run([(a, t["T4"], (0,), (0,))], repeat=3, flags=FLAGS[kind])
@@ -260,7 +260,7 @@ def test_repeat_runs_bitwise_identical(kind):
 
 
 def test_power_of_two_gauge_bitwise():
-    (p,) = W.config1()
+    (p,) = W.u1_d18()
     a, b = p.a.copy(), p.b.copy()
     for i in range(a.nblocks):  # contracted sector rho = 1 on A's leg 2 (and B's leg 0)
         if a.charges[i, 2, 0] == 1:
@@ -368,7 +368,7 @@ def test_shared_b_kernel_interleaved_legs_in_one_batch(variant):
              for sym, seed in [("Z2", 7100), ("Z2", 7103), ("Z2", 7105), ("Z2", 7108), ("Z3", 7103), ("Z3", 7107)]]
     probs += [random_problem(seed + 7200, sym, rank_a=4, rank_b=3, ncon=2, max_sectors=3, max_dim=5, keep=0.7)
               for seed, sym in enumerate(["Z2", "U1xU1", "U1xZ2"])]
-    c1 = W.config1(2)
+    c1 = W.u1_d18(2)
     probs += [(p.a, p.b, p.axes_a, p.axes_b) for p in c1]
     pl = Y.plan(probs)
     if max(pl.stats(i)["max_k"] for i in range(len(probs))) > 80:
@@ -384,11 +384,11 @@ def test_shared_b_kernel_interleaved_legs_in_one_batch(variant):
 
 
 @pytest.mark.parametrize("variant", range(0, NUM_VARIANTS))
-def test_config1_every_variant(variant):
-    """Config 1 (K = 76 in its largest sector): every variant that fits,
+def test_u1_d18_every_variant(variant):
+    """The D = 18 contraction (K = 76 in its largest sector): every variant that fits,
     including the occupancy-1 register-resident tiles that take K <= 80."""
     import paper_2405_12196_amd as Y
-    (p,) = W.config1()
+    (p,) = W.u1_d18()
     ref = oracle.tensordot_dense(p.a, p.b, p.axes_a, p.axes_b)
     pl = Y.plan([(p.a, p.b, p.axes_a, p.axes_b)])
     if variant:
@@ -406,12 +406,12 @@ def test_config1_every_variant(variant):
 
 @pytest.mark.parametrize("variant", range(0, NUM_VARIANTS))
 def test_missing_a_blocks_every_variant(variant):
-    """Config 1 with every fifth A block absent (lazy storage): rows of a
+    """The D = 18 contraction with every fifth A block absent (lazy storage): rows of a
     sector then lack A data for part of its k range, which must count as
     zeros in every kernel."""
     import paper_2405_12196_amd as Y
     from workloads import BlockTensor
-    (p,) = W.config1()
+    (p,) = W.u1_d18()
     keep = np.arange(p.a.nblocks) % 5 != 2
     a = BlockTensor(p.a.sym_mod, p.a.sig, p.a.n, p.a.charges[keep], p.a.shapes[keep], p.a.offsets[keep], p.a.data)
     ref = oracle.tensordot_dense(a, p.b, p.axes_a, p.axes_b)
@@ -429,9 +429,9 @@ def test_missing_a_blocks_every_variant(variant):
     check_f64(s, c.cpu().numpy()[:s.numel], ref)
 
 
-def test_autotune_config2_step3_picks_a_correct_variant():
+def test_autotune_ctm_step3_picks_a_correct_variant():
     import paper_2405_12196_amd as Y
-    t = W.config2()
+    t = W.ctm()
     a = oracle.tensordot_blockpair(oracle.tensordot_blockpair(t["C"], t["T1"], (1,), (0,)), t["T4"], (0,), (0,))
     ref = oracle.tensordot_blockpair(a, t["A"], (0, 3), (0, 1))
     pl = Y.plan([(a, t["A"], (0, 3), (0, 1))])
@@ -449,11 +449,11 @@ def test_autotune_config2_step3_picks_a_correct_variant():
 # ------------------------------------------------------------ HIP graphs
 @pytest.mark.parametrize("kind", ["auto", "mfma"])
 def test_graph_replays_equal_eager_chain(kind):
-    """The config-2 chain (four contractions + FP64 norm) captured in one HIP
+    """The enlarged-corner chain (four contractions + FP64 norm) captured in one HIP
     graph: every replay, with eager work and synchronisations between
     replays, must reproduce the eager results bitwise."""
     import paper_2405_12196_amd as Y
-    t = W.config2()
+    t = W.ctm()
     steps = [("C", "T1"), (None, "T4"), (None, "A"), (None, "Ac")]
     plans, cur = [], None
     for (an, bn), (ax, bx) in zip(steps, t["axes"]):
@@ -504,7 +504,7 @@ def test_fused_norm_matches_oracle_and_repeats_bitwise(kind):
     (register-resident, shared-B and pipelined kernels) or from the separate
     pass (other kernels); an int kind is a kernel variant."""
     import paper_2405_12196_amd as Y
-    t = W.config2()
+    t = W.ctm()
     a = oracle.tensordot_blockpair(t["C"], t["T1"], (1,), (0,))
     a = oracle.tensordot_blockpair(a, t["T4"], (0,), (0,))
     a = oracle.tensordot_blockpair(a, t["A"], (0, 3), (0, 1))

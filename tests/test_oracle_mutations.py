@@ -17,8 +17,8 @@ CAUGHT = (AssertionError, oracle.OracleError, KeyError, ValueError, IndexError)
 
 
 def _run_pins():
-    P.test_config1_closed_form_structure()
-    P.test_config1_dense_equals_blockpair()
+    P.test_u1_d18_closed_form_structure()
+    P.test_u1_d18_dense_equals_blockpair()
     P.test_paper_example_h_squared_exact("dense")
     P.test_paper_example_h_squared_exact("blockpair")
     P.test_paper_example_h_squared_exact("brute")
@@ -127,10 +127,10 @@ def test_mutation_is_caught(name, monkeypatch):
         _run_pins()
 
 
-def test_config2_structure_counts():
+def test_ctm_structure_counts():
     """Counts of the four enlarged-corner steps at chi=128, D=8, derived by
     an independent enumeration of the workload recipe."""
-    t = W.config2()
+    t = W.ctm()
     steps = [("C", "T1"), (None, "T4"), (None, "A"), (None, "Ac")]
     expect = [(255, 15, 255), (4489, 15, 4489), (33145, 13, 15643), (32647, 13, 5113)]
     cur = None

@@ -1,7 +1,7 @@
 """Pins of the CPU oracle against facts fixed by the paper and by mathematics.
 
 None of these re-types the oracle's own formulas: they use closed forms
-(convolution counts of config 1), the paper's worked example with its physical
+(convolution counts of the D = 18 contraction), the paper's worked example with its physical
 values, brute force over dense indices, special cases that reduce to plain
 numpy.tensordot, and bitwise invariants.
 """
@@ -18,8 +18,8 @@ from tests.helpers import random_problem
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
-# ---------------------------------------------------------------- config 1
-def test_config1_closed_form_structure():
+# ------------------------------------------------- rank-4 U(1), D = 18
+def test_u1_d18_closed_form_structure():
     # Leg {-2:2,-1:4,0:6,1:4,2:2}, signature (+,+,-,-), n=0.  A block (q0,q1,q2,q3)
     # is allowed iff q0+q1 = q2+q3 =: s.  For each s the number of (q0,q1) pairs is
     # c_s = (1,2,3,4,5,4,3,2,1) and the elements per side conv_s = (d*d)[s]
@@ -29,7 +29,7 @@ def test_config1_closed_form_structure():
     cnt = np.convolve([1] * 5, [1] * 5)
     assert conv.tolist() == [4, 16, 40, 64, 76, 64, 40, 16, 4]
     assert cnt.tolist() == [1, 2, 3, 4, 5, 4, 3, 2, 1]
-    (p,) = W.config1()
+    (p,) = W.u1_d18()
     a, b = p.a, p.b
     assert a.nblocks == int(np.sum(cnt ** 2)) == 85
     assert int(a.block_sizes.sum()) == int(np.sum(conv ** 2)) == 17712
@@ -47,8 +47,8 @@ def test_config1_closed_form_structure():
     assert int(c.block_sizes.sum()) == 17712
 
 
-def test_config1_dense_equals_blockpair():
-    (p,) = W.config1()
+def test_u1_d18_dense_equals_blockpair():
+    (p,) = W.u1_d18()
     c1 = oracle.tensordot_dense(p.a, p.b, p.axes_a, p.axes_b)
     c2 = oracle.tensordot_blockpair(p.a, p.b, p.axes_a, p.axes_b)
     assert oracle.same_structure(c1, c2)
@@ -252,13 +252,13 @@ def test_fusion_invariance(seed):
 
 
 # ------------------------------------------------------------ validation
-def _cfg1():
-    (p,) = W.config1()
+def _u1_d18():
+    (p,) = W.u1_d18()
     return p.a, p.b
 
 
 def test_validation_status_classes():
-    a, b = _cfg1()
+    a, b = _u1_d18()
     with pytest.raises(oracle.OracleError) as e:
         oracle.validate_pair(a, b, (2, 3), (0,))
     assert e.value.status == oracle.ERR_ARG
@@ -317,7 +317,7 @@ def test_sampled_blocks_equal_full_blockpair(step):
     """tensordot_blocks (O2 on chosen output blocks) gives exactly the blocks
     of the full O2 result: same pairs, same order."""
     import workloads as W
-    t = W.config2()
+    t = W.ctm()
     steps = [("C", "T1"), (None, "T4"), (None, "A")]
     cur = None
     for i, ((an, bn), (ax, bx)) in enumerate(zip(steps, t["axes"])):
@@ -388,10 +388,10 @@ def test_grad_adjoint_identity(seed, wrt):
     assert abs(lhs - rhs) <= 1e-10 * max(1.0, abs(rhs))
 
 
-def test_grad_config1_matches_matrix_form():
-    """Config 1 (A's contracted legs trail, B's lead): the gradient is the
+def test_grad_u1_d18_matches_matrix_form():
+    """The D = 18 contraction (A's contracted legs trail, B's lead): the gradient is the
     plain matrix product in each sector, dA = dC B^T, checked densely."""
-    (p,) = W.config1()
+    (p,) = W.u1_d18()
     rng = np.random.default_rng(1)
     c = oracle.tensordot_dense(p.a, p.b, p.axes_a, p.axes_b)
     dc = _with_data(c, rng)

@@ -197,8 +197,8 @@ def _leg2(s, pairs):
     return Leg(s, tuple(tuple(q) for q, _ in pairs), tuple(d for _, d in pairs))
 
 
-# ---- config 1: single U(1) rank-4 tensordot (D = 18) ----------------------
-CFG1_LEG = [(-2, 2), (-1, 4), (0, 6), (1, 4), (2, 2)]
+# ---- single U(1) rank-4 tensordot (D = 18) -------------------------------
+D18_LEG = [(-2, 2), (-1, 4), (0, 6), (1, 4), (2, 2)]
 SIG_PPMM = (1, 1, -1, -1)
 
 
@@ -209,14 +209,14 @@ def rank4_u1_problem(leg_pairs, seed_a, seed_b, name=""):
     return Contraction(a, b, (2, 3), (0, 1), name)
 
 
-def config1(batch: int = 1):
+def u1_d18(batch: int = 1):
     """U(1) rank-4, signature (+,+,-,-), legs {-2:2,-1:4,0:6,1:4,2:2};
     A seed 101+2i, B seed 102+2i; contract A's legs (2,3) with B's (0,1)."""
-    return [rank4_u1_problem(CFG1_LEG, 101 + 2 * i, 102 + 2 * i, f"cfg1[{i}]")
+    return [rank4_u1_problem(D18_LEG, 101 + 2 * i, 102 + 2 * i, f"u1_d18[{i}]")
             for i in range(batch)]
 
 
-# ---- config 2 / 4: CTMRG enlarged corner, U(1)xU(1) ------------------------
+# ---- CTMRG enlarged corner, U(1)xU(1), chi = 128 / 256 ------------------------
 def _ctm_legs_u1u1(chi):
     if chi == 128:
         e = [((0, 0), 20)]
@@ -263,7 +263,7 @@ def ctm_tensors(E, V, P, sym_mod, seeds, mk):
     return {"C": C, "T1": T1, "T4": T4, "A": A, "Ac": conj(A)}
 
 
-def config2(chi: int = 128, seeds=(201, 202, 203, 204)):
+def ctm(chi: int = 128, seeds=(201, 202, 203, 204)):
     """CTMRG enlarged-corner step, U(1)xU(1), FP64: chi=128 (15 sectors),
     D=8 (5 sectors), d=4.  Returns the tensors; the four chained steps are
     C.T1 ((1),(0)), .T4 ((0),(0)), .A ((0,3),(0,1)), .A* ((0,2,6),(0,1,4))."""
@@ -274,13 +274,13 @@ def config2(chi: int = 128, seeds=(201, 202, 203, 204)):
     return t
 
 
-def config4():
-    """The config-2 step at chi=256, D=10 (precision sweep), seeds 401-404."""
-    return config2(256, seeds=(401, 402, 403, 404))
+def ctm_chi256():
+    """The enlarged-corner step at chi=256, D=10 (precision sweep), seeds 401-404."""
+    return ctm(256, seeds=(401, 402, 403, 404))
 
 
-# ---- config 3: 64 independent U(1) contractions ----------------------------
-def config3(nprob: int = 64, seed: int = 3):
+# ---- 64 independent U(1) contractions, uneven D ----------------------------
+def u1_uneven(nprob: int = 64, seed: int = 3):
     rng = np.random.default_rng(seed)
     probs = []
     for i in range(nprob):
@@ -292,11 +292,11 @@ def config3(nprob: int = 64, seed: int = 3):
             dims[j] += 1
         q0 = -((k - 1) // 2)
         pairs = [(q0 + j, dims[j]) for j in range(k)]
-        probs.append(rank4_u1_problem(pairs, 3000 + 2 * i, 3001 + 2 * i, f"cfg3[{i}]"))
+        probs.append(rank4_u1_problem(pairs, 3000 + 2 * i, 3001 + 2 * i, f"u1_uneven[{i}]"))
     return probs
 
 
-# ---- config 5: serving mix -------------------------------------------------
+# ---- serving mix of 32 CTMRG runs -------------------------------------------------
 U1_E = {64: [2, 4, 7, 11, 16, 11, 7, 4, 2], 128: [4, 8, 15, 22, 30, 22, 15, 8, 4],
         192: [6, 11, 23, 33, 46, 33, 23, 11, 6], 256: [8, 15, 30, 45, 60, 45, 30, 15, 8]}
 U1_V = {4: [(-1, 1), (0, 2), (1, 1)], 6: [(-1, 2), (0, 2), (1, 2)],
