@@ -256,11 +256,19 @@ template <typename T, int CP> struct Dst<T, true, CP> {
     r = __builtin_amdgcn_make_buffer_rsrc(uniptr(p), (short)0, uni((int)(n * (int64_t)sizeof(T))), kBufFlags);
   }
   __device__ void put(int64_t i, T v) const { BufIo<T>::template st<CP>(r, (int32_t)i * (int32_t)sizeof(T), v); }
+  // element i if v, else a byte offset past any buffer below 2 GiB (the
+  // store is dropped): no per-lane branch around the store
+  __device__ void put_if(bool v, int32_t i, T x) const {
+    BufIo<T>::template st<CP>(r, v ? i * (int32_t)sizeof(T) : (int32_t)(0x80000000u - sizeof(T)), x);
+  }
 };
 template <typename T, int CP> struct Dst<T, false, CP> {
   T *__restrict__ p;
   __device__ void init(void *q, int64_t) { p = reinterpret_cast<T *>(q); }
   __device__ void put(int64_t i, T v) const { p[i] = v; }
+  __device__ void put_if(bool v, int64_t i, T x) const {
+    if (v) p[i] = x;
+  }
 };
 
 // Tile context shared by every precision: the tile's row tuple and sector,
@@ -890,20 +898,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
           }
         }
       }
+      // stores without per-lane branches (padding rows and columns: dropped)
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) {
-        if (cb >= cbn || cbase[cb] < 0) continue;
+        if (cb >= cbn) continue;
+        const bool cv = cbase[cb] >= 0;
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
           if (rb >= rbn) continue;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int lr = 16 * rb + M::row(lane, v);
-            if (lr < rows) {
-              const Out val = Out(acc[rb][cb][v]);
-              x.C.put(cbase[cb] + (Off)(x.m0 + mc + lr) * (Off)cnj[cb] + (Off)ccl[cb], val);
-              if (do_norm) nacc.add((double)val);
-            }
+            const bool ok = cv && lr < rows;
+            const Out val = Out(acc[rb][cb][v]);
+            x.C.put_if(ok, cbase[cb] + (Off)(x.m0 + mc + lr) * (Off)cnj[cb] + (Off)ccl[cb], val);
+            if (do_norm) nacc.add(ok ? (double)val : 0.0);
           }
         }
       }
@@ -1045,20 +1054,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
                 if (cb < cbn) acc[rb][cb] = M::run(Cmp(av[q][rb]), b[cb], acc[rb][cb]);
         }
       }
+      // stores without per-lane branches: padding rows and columns store past
+      // the end of C (dropped) and add 0 to the norm
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) {
-        if (cb >= cbn || T.cbase[cb] < 0) continue;
+        if (cb >= cbn) continue;
+        const bool cv = T.cbase[cb] >= 0;
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
           if (rb >= rbn) continue;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int lr = 16 * rb + M::row(lane, v);
-            if (lr < rows) {
-              const Out val = Out(acc[rb][cb][v]);
-              x.C.put(T.cbase[cb] + (Off)(x.m0 + mc + lr) * (Off)T.cnj[cb] + (Off)T.ccl[cb], val);
-              if constexpr (NORM) nacc.add((double)val);
-            }
+            const bool ok = cv && lr < rows;
+            const Out val = Out(acc[rb][cb][v]);
+            x.C.put_if(ok, T.cbase[cb] + (Off)(x.m0 + mc + lr) * (Off)T.cnj[cb] + (Off)T.ccl[cb], val);
+            if constexpr (NORM) nacc.add(ok ? (double)val : 0.0);
           }
         }
       }
@@ -1262,18 +1273,18 @@ __global__ void __launch_bounds__(256) k_gemm_pf(LaunchArgs args) {
       }
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) {
-        if (cb >= cbn || cbase[cb] < 0) continue;
+        if (cb >= cbn) continue;
+        const bool cv = cbase[cb] >= 0;
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
           if (rb >= rbn) continue;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int lr = 16 * rb + M::row(lane, v);
-            if (lr < rows) {
-              const Out val = Out(acc[rb][cb][v]);
-              x.C.put(cbase[cb] + (x.m0 + mc + lr) * cnj[cb] + ccl[cb], val);
-              if (do_norm) nacc.add((double)val);
-            }
+            const bool ok = cv && lr < rows;
+            const Out val = Out(acc[rb][cb][v]);
+            x.C.put_if(ok, cbase[cb] + (x.m0 + mc + lr) * cnj[cb] + ccl[cb], val);
+            if (do_norm) nacc.add(ok ? (double)val : 0.0);
           }
         }
       }
