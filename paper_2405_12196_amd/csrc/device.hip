@@ -809,8 +809,12 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
       if (maxk > kResMaxK && maxk <= kResMaxKWide && !bf16) {
         tm = 16;
       } else {
+        // wide tiles (64 columns) with K <= 64 stop at half the tile target:
+        // their per-tile work is short, and taller tiles reuse each B load
+        // over more rows (measured on the corner step with N up to 924)
+        const int64_t target = cb == 4 && maxk <= kResMaxK ? kTilesPerLaunchTarget / 2 : kTilesPerLaunchTarget;
         tm = maxk > kResMaxK ? 32 : 16;
-        while (tm < 512 && count(2 * tm) >= kTilesPerLaunchTarget) tm *= 2;
+        while (tm < 512 && count(2 * tm) >= target) tm *= 2;
       }
     }
     // tile height = 16 * rb * nch rows
