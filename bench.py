@@ -558,7 +558,7 @@ def main():
     ws_env = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or ws_env != 1:
         print("bench.py measures one GPU only: the block-sparse tensordot of this library runs on a single "
-              "MI355X (multi-GPU sharding is described in DESIGN.md, not built). Use --gpus 1.", file=sys.stderr)
+              "MI355X (sharding over several GPUs is not built). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
