@@ -310,6 +310,28 @@ def test_multi_plan_launch_equals_separate():
         assert np.array_equal(c.cpu().numpy()[:o.numel], v)
 
 
+def test_multi_plan_launch_with_pointer_table_plan():
+    """A merged launch list holding a plan of 70 problems (its pointers go
+    through the workspace table, in a launch of its own) between two small
+    plans: every problem of every plan against the oracle."""
+    import paper_2405_12196_amd as Y
+    small = [random_problem(950 + i, ["U1", "Z2"][i], max_sectors=4, max_dim=6) for i in range(2)]
+    big = [(p.a, p.b, p.axes_a, p.axes_b) for p in W.u1_d18(70)]
+    groups = [[small[0]], big, [small[1]]]
+    jobs, outs = [], []
+    for probs in groups:
+        pl = Y.plan(probs)
+        cs = [G.alloc_out(pl, i) for i in range(len(probs))]
+        jobs.append((pl, [G.upload(p[0]) for p in probs], [G.upload(p[1]) for p in probs], [c for c, _ in cs],
+                     G.workspace(pl)))
+        outs.append((probs, cs))
+    Y.contract_jobs(jobs)
+    torch.cuda.synchronize()
+    for probs, cs in outs:
+        for (a, b, xa, xb), (c, s) in zip(probs, cs):
+            check_f64(s, c.cpu().numpy()[:s.numel], oracle.tensordot_blockpair(a, b, xa, xb))
+
+
 # ----------------------------------------------------------------- norms
 @pytest.mark.parametrize("n", [0, 1, 1000, 3994616])
 def test_norm_f64(n):
