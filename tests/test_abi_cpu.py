@@ -120,3 +120,21 @@ def test_null_arguments_rejected():
     assert L.yastn_plan_workspace(None, None) == 1
     assert L.yastn_norm(None, 10, 0, None, None, None) == 1
     L.yastn_free(None)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus 2 exits with status 2 and says so,
+    before touching any device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_variant_count_matches_header():
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with open(os.path.join(root, "include", "yastn.h")) as f:
+        n = int(re.search(r"#define YASTN_NUM_VARIANTS (\d+)", f.read()).group(1))
+    assert Y.NUM_VARIANTS == n
