@@ -32,7 +32,8 @@ STATUS = ["OK", "ERR_ARG", "ERR_SYM", "ERR_CHARGE", "ERR_SIGNATURE", "ERR_SHAPE"
           "ERR_DUPLICATE", "ERR_NOMEM", "ERR_HIP", "ERR_STATE"]
 
 EXPORTS = ["yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats", "yastn_plan_info",
-           "yastn_contract", "yastn_contract_norm", "yastn_contract_timed", "yastn_contract_jobs", "yastn_norm_workspace", "yastn_norm",
+           "yastn_contract", "yastn_contract_norm", "yastn_contract_timed",
+           "yastn_contract_jobs", "yastn_norm_workspace", "yastn_norm",
            "yastn_free", "yastn_last_error", "yastn_status_string", "yastn_abi_version",
            "yastn_plan_autotune", "yastn_plan_set_variant",
            "yastn_server_create", "yastn_server_submit", "yastn_server_step", "yastn_server_query",
@@ -157,7 +158,8 @@ def lib():
                   "yastn_grad_workspace", "yastn_grad"):
             getattr(L, f).restype = C.c_int32
         for f in ("yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats",
-                  "yastn_contract", "yastn_contract_norm", "yastn_contract_timed", "yastn_contract_jobs", "yastn_norm",
+                  "yastn_contract", "yastn_contract_norm", "yastn_contract_timed",
+                  "yastn_contract_jobs", "yastn_norm",
                   "yastn_plan_autotune", "yastn_plan_set_variant", "yastn_plan_info", "yastn_server_create",
                   "yastn_server_submit", "yastn_server_step", "yastn_server_query", "yastn_server_forget",
                   "yastn_server_drain", "yastn_server_get_stats"):
@@ -484,12 +486,18 @@ def norm(x, n: int, out, workspace, dtype=DTYPE_F64, stream=None):
 
 class Server:
     """Continuous-batching request loop (yastn_server_*).  A request is a chain
-    of single-problem plans over resident device tensors; see include/yastn.h."""
+    of single-problem plans over resident device tensors; see include/yastn.h.
+
+    Lifetime: the C server holds the plans' handles and the device addresses
+    of a0, bs and out until the request completes, so ``submit`` keeps a
+    reference to every one of them (plans and tensors) until ``query`` reports
+    the request done, ``forget`` drops it, or the server is closed."""
 
     def __init__(self, pool_bytes: int, max_ahead: int = 2, stream=None):
         h = C.c_void_p()
         _check(lib().yastn_server_create(int(pool_bytes), int(max_ahead), C.c_void_p(_stream(stream)), C.byref(h)))
         self._h = h
+        self._held = {}
 
     def submit(self, plans, a0, bs, out) -> int:
         n = len(plans)
@@ -498,7 +506,12 @@ class Server:
         rq = Request(n, C.cast(pl, C.POINTER(C.c_void_p)), _ptr(a0), C.cast(pb, C.POINTER(C.c_void_p)), _ptr(out))
         rid = C.c_int64()
         _check(lib().yastn_server_submit(self._h, C.byref(rq), C.byref(rid)))
+        self._held[int(rid.value)] = (list(plans), a0, list(bs), out)
         return int(rid.value)
+
+    def held(self) -> int:
+        """Requests whose plans and tensors this object still keeps alive."""
+        return len(self._held)
 
     def step(self) -> int:
         n = C.c_int32()
@@ -508,10 +521,13 @@ class Server:
     def query(self, rid: int):
         st, lat = C.c_int32(), C.c_double()
         _check(lib().yastn_server_query(self._h, int(rid), C.byref(st), C.byref(lat)))
+        if st.value == REQ_DONE:
+            self._held.pop(int(rid), None)
         return int(st.value), float(lat.value)
 
     def forget(self, rid: int):
         _check(lib().yastn_server_forget(self._h, int(rid)))
+        self._held.pop(int(rid), None)
 
     def drain(self):
         _check(lib().yastn_server_drain(self._h))
@@ -523,8 +539,9 @@ class Server:
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
-            lib().yastn_server_destroy(self._h)
+            lib().yastn_server_destroy(self._h)  # waits for outstanding launches
             self._h = C.c_void_p()
+        self._held = {}
 
     def __del__(self):
         try:

@@ -17,6 +17,7 @@
 #include <type_traits>
 #include <cstring>
 #include <mutex>
+#include <string>
 #include <new>
 #include <vector>
 
@@ -55,19 +56,21 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
+// The join kernels loop over their blocks with a grid stride, so a grid
+// capped at the launch limit still covers any block count.
 __global__ void k_join_build(const int32_t *keyb, int64_t nb, int klen, int32_t *owner, int32_t *head,
                              int32_t *next, uint64_t mask) {
-  int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (j >= nb) return;
-  const int32_t *kj = keyb + j * klen;
-  uint64_t h = key_hash(kj, klen) & mask;
-  for (;;) {
-    int32_t o = atomicCAS(&owner[h], -1, (int32_t)j);
-    if (o == -1 || key_eq(keyb + (int64_t)o * klen, kj, klen)) {
-      next[j] = atomicExch(&head[h], (int32_t)j);
-      return;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nb; j += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t *kj = keyb + j * klen;
+    uint64_t h = key_hash(kj, klen) & mask;
+    for (;;) {
+      int32_t o = atomicCAS(&owner[h], -1, (int32_t)j);
+      if (o == -1 || key_eq(keyb + (int64_t)o * klen, kj, klen)) {
+        next[j] = atomicExch(&head[h], (int32_t)j);
+        break;
+      }
+      h = (h + 1) & mask;
     }
-    h = (h + 1) & mask;
   }
 }
 
@@ -84,13 +87,13 @@ __device__ __forceinline__ int64_t probe_slot(const int32_t *ki, const int32_t *
 
 __global__ void k_join_count(const int32_t *keya, int64_t na, const int32_t *keyb, int klen, const int32_t *owner,
                              const int32_t *head, const int32_t *next, uint64_t mask, int64_t *cnt) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= na) return;
-  int64_t slot = probe_slot(keya + i * klen, keyb, klen, owner, mask);
-  int64_t c = 0;
-  if (slot >= 0)
-    for (int32_t j = head[slot]; j >= 0; j = next[j]) ++c;
-  cnt[i] = c;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < na; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t slot = probe_slot(keya + i * klen, keyb, klen, owner, mask);
+    int64_t c = 0;
+    if (slot >= 0)
+      for (int32_t j = head[slot]; j >= 0; j = next[j]) ++c;
+    cnt[i] = c;
+  }
 }
 
 // exclusive scan of n counts by one workgroup of 1024 threads; out[n] = total
@@ -120,15 +123,15 @@ __global__ void __launch_bounds__(1024) k_scan_one(const int64_t *cnt, int64_t n
 __global__ void k_join_emit(const int32_t *keya, int64_t na, const int32_t *keyb, int klen, const int32_t *owner,
                             const int32_t *head, const int32_t *next, uint64_t mask, const int64_t *off,
                             int32_t *pa, int32_t *pb) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= na) return;
-  int64_t slot = probe_slot(keya + i * klen, keyb, klen, owner, mask);
-  if (slot < 0) return;
-  int64_t p = off[i];
-  for (int32_t j = head[slot]; j >= 0; j = next[j]) {
-    pa[p] = (int32_t)i;
-    pb[p] = j;
-    ++p;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < na; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t slot = probe_slot(keya + i * klen, keyb, klen, owner, mask);
+    if (slot < 0) continue;
+    int64_t p = off[i];
+    for (int32_t j = head[slot]; j >= 0; j = next[j]) {
+      pa[p] = (int32_t)i;
+      pb[p] = j;
+      ++p;
+    }
   }
 }
 
@@ -553,10 +556,12 @@ struct JobRef {
   void *ws;
 };
 
-yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const *events = nullptr,
+// jobs: njobs entries (a pointer and a count, so a caller may pass an array
+// on its stack and no host allocation happens here)
+yastn_status launch(const JobRef *jobs, size_t njobs, hipStream_t st, void *const *events = nullptr,
                     double *norm_out = nullptr, bool *norm_fused = nullptr) {
   if (events && events[0]) YASTN_HIP(hipEventRecord(reinterpret_cast<hipEvent_t>(events[0]), st));
-  if (jobs.empty()) {
+  if (njobs == 0) {
     if (events && events[1]) YASTN_HIP(hipEventRecord(reinterpret_cast<hipEvent_t>(events[1]), st));
     if (events && events[2]) YASTN_HIP(hipEventRecord(reinterpret_cast<hipEvent_t>(events[2]), st));
     return YASTN_OK;
@@ -564,11 +569,11 @@ yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const
   const yastn_options &o = jobs[0].plan->opts;
   Fit fit;
   int variant = jobs[0].plan->variant;
-  for (auto &j : jobs) {
-    fit_add(fit, *j.plan);
-    if (j.plan->variant != variant) variant = 0;
+  for (size_t k = 0; k < njobs; ++k) {
+    fit_add(fit, *jobs[k].plan);
+    if (jobs[k].plan->variant != variant) variant = 0;
   }
-  const bool norm_one = norm_out && jobs.size() == 1 && !fit.split;
+  const bool norm_one = norm_out && njobs == 1 && !fit.split;
   const Choice ch = choose(fit, o, variant, norm_one);
   if (!ch.gemm) return set_error(YASTN_ERR_STATE, "no kernel instance for this plan");
   if (fit.split && ch.fam != FAM_PF)
@@ -580,7 +585,7 @@ yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const
   const void *reduce = fit.split ? reinterpret_cast<const void *>(split_reduce(o.precision, o.out_dtype)) : nullptr;
   if (norm_fused) *norm_fused = fuse;
   size_t ji = 0;
-  while (ji < jobs.size()) {
+  while (ji < njobs) {
     LaunchArgs la;
     std::memset(&la, 0, sizeof(la));
     int np = 0;
@@ -602,7 +607,7 @@ yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const
       }
       la.ptab = tab;
     }
-    while (ji < jobs.size() && la.njobs < kMaxJobs) {
+    while (ji < njobs && la.njobs < kMaxJobs) {
       const JobRef &j = jobs[ji];
       const int n = j.g->phi - j.g->plo;
       if (!table && np + n > kMaxProbs) break;
@@ -665,6 +670,11 @@ yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const
     if (events && events[2]) YASTN_HIP(hipEventRecord(reinterpret_cast<hipEvent_t>(events[2]), st));
   }
   return YASTN_OK;
+}
+
+yastn_status launch(const std::vector<JobRef> &jobs, hipStream_t st, void *const *events = nullptr,
+                    double *norm_out = nullptr, bool *norm_fused = nullptr) {
+  return launch(jobs.data(), jobs.size(), st, events, norm_out, norm_fused);
 }
 
 yastn_status check_job_ptrs(const Plan *pl, const void *const *a, const void *const *b, void *const *c, void *ws) {
@@ -738,6 +748,7 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
       delete h;
       return set_error(YASTN_ERR_HIP, "no HIP device");
     }
+    const bool bf16 = is_bf16(o);
     std::vector<std::vector<std::pair<int32_t, int32_t>>> allpairs(nprob);
     for (int p = 0; p < nprob; ++p)
       if ((s = gpu_join(pl.probs[p], st, allpairs[p])) != YASTN_OK) {
@@ -748,7 +759,7 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
     // picks the kernel family and, for MFMA, the tile width, and rebuilds if
     // the tiling changed.
     int64_t a_base = 0, b_base = 0;
-    auto build_all = [&](int rb, int cb, int nch) -> yastn_status {
+    auto build_all = [&](int rb, int cb, int nch, bool ksplit) -> yastn_status {
       pl.t = PlanTables{};
       pl.prob_t0.clear();
       pl.prob_i0.clear();
@@ -759,17 +770,28 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
       for (int p = 0; p < nprob; ++p) {
         pl.prob_t0.push_back((int32_t)pl.t.tiles.size());
         pl.prob_i0.push_back((int32_t)pl.t.items.size());
-        yastn_status st2 = build_structure(pl.probs[p], p, allpairs[p], a_base, b_base, pl.t, rb, cb, nch, !is_bf16(o));
+        yastn_status st2 = build_structure(pl.probs[p], p, allpairs[p], a_base, b_base, pl.t, rb, cb, nch, ksplit);
         if (st2 != YASTN_OK) return st2;
         a_base += pl.probs[p].a.nblocks;
         b_base += pl.probs[p].b.nblocks;
       }
       return YASTN_OK;
     };
-    if ((s = build_all(4, 4, 1)) != YASTN_OK) {
+    if ((s = build_all(4, 4, 1, false)) != YASTN_OK) {
       delete h;
       return s;
     }
+    // buffer addressing needs every A and B span and C size below 2 GiB
+    const int64_t in_b = o.in_dtype == YASTN_DTYPE_F64 ? 8 : 4, out_b = o.out_dtype == YASTN_DTYPE_F64 ? 8 : 4;
+    pl.buf_ok = true;
+    for (const DevProb &dp : pl.t.probs)
+      if (dp.a_span * in_b >= (int64_t(1) << 31) || dp.b_span * in_b >= (int64_t(1) << 31) ||
+          dp.c_numel * out_b >= (int64_t(1) << 31))
+        pl.buf_ok = false;
+    // split-K tiles run only on the pipelined kernel, which addresses every
+    // operand through 32-bit buffer offsets: split only where that kernel can
+    // run (buffers below 2 GiB, no forced kernel family, not split-BF16)
+    const bool ksplit = !bf16 && pl.buf_ok && o.flags == 0;
     int64_t maxn = 1, maxk = 0, rows = 0, rows64 = 0;
     for (auto &sec : pl.t.sectors) {
       maxn = std::max<int64_t>(maxn, sec.N);
@@ -780,7 +802,6 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
       rows64 += (rt.m + 63) / 64 * 64;
     }
     pl.kmax = (int)maxk;
-    const bool bf16 = o.precision == YASTN_BF16X3 || o.precision == YASTN_BF16X6;
     pl.rows_fit = !bf16 && maxk <= 64 && maxn <= 64;
     pl.res_fit = maxk <= kResMaxKWide && !pl.t.bofs_overflow;
     pl.nact = 1;
@@ -819,7 +840,7 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
     }
     // tile height = 16 * rb * nch rows
     const int rb_t = tm >= 64 ? 4 : tm / 16, nch = tm >= 64 ? tm / 64 : 1;
-    if ((cb != 4 || tm != 64) && (s = build_all(rb_t, cb, nch)) != YASTN_OK) {
+    if ((cb != 4 || tm != 64 || (ksplit && maxk > kSplitMinK)) && (s = build_all(rb_t, cb, nch, ksplit)) != YASTN_OK) {
       delete h;
       return s;
     }
@@ -830,13 +851,6 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
       return set_error(YASTN_ERR_ARG, "too many blocks in one plan");
     }
     finish_tiles(pl);
-    // buffer addressing needs every A and B span and C size below 2 GiB
-    const int64_t in_b = o.in_dtype == YASTN_DTYPE_F64 ? 8 : 4, out_b = o.out_dtype == YASTN_DTYPE_F64 ? 8 : 4;
-    pl.buf_ok = true;
-    for (const DevProb &dp : pl.t.probs)
-      if (dp.a_span * in_b >= (int64_t(1) << 31) || dp.b_span * in_b >= (int64_t(1) << 31) ||
-          dp.c_numel * out_b >= (int64_t(1) << 31))
-        pl.buf_ok = false;
     if ((s = upload(pl)) != YASTN_OK) {
       yastn_free(h);
       return s;

@@ -476,6 +476,16 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
     std::vector<Key> rowkeys(R), colkeys(Q);
     for (auto &r : sb.rows) rowkeys[r.second] = r.first;
     for (auto &c : sb.cols) colkeys[c.second] = c.first;
+    // split-K only for sectors with few output tiles (small M_X x N_X, e.g.
+    // the gradient with respect to a site tensor): the partial slots cost
+    // nslots x the tile's accumulators of workspace and a reduction pass
+    int64_t Msec = 0;
+    for (int i = 0; i < R; ++i) {
+      int64_t m = 1;
+      for (int q = 0; q < hp.nfa; ++q) m *= A.dim(row_rep[i], hp.fa[q]);
+      Msec += m;
+    }
+    const bool split_sec = ksplit && K > kSplitMinK && Msec * int64_t(N) <= kSplitMaxMN;
     int64_t M = 0;
     for (int i = 0; i < R; ++i) {
       DevRowTuple rt{};
@@ -531,7 +541,7 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
       // computed in nslots k ranges by separate tiles (same output tile), each
       // into its own partial slot, summed afterwards in slot order
       int32_t nslots = 1, chunk = (int32_t)K;
-      if (ksplit && K > kSplitMinK) {
+      if (split_sec) {
         nslots = (int32_t)std::min<int64_t>(kSplitMaxSlots, (K + kSplitChunk - 1) / kSplitChunk);
         chunk = (int32_t)(((K + nslots - 1) / nslots + 7) / 8 * 8);
         nslots = (int32_t)((K + chunk - 1) / chunk);

@@ -118,9 +118,11 @@ yastn_status validate_problem(const yastn_problem &p, HostProblem &hp);
 // one tensor alone: symmetry, signatures, dims, duplicates, conservation, offsets
 yastn_status validate_tensor(const yastn_tensor_desc &d, const char *name, HostTensor &t);
 void contracted_keys(const HostTensor &t, const int *axes, int nc, std::vector<int32_t> &keys);
-// ksplit: sectors with K > kSplitMinK are computed in k ranges (split-K)
+// ksplit: sectors with K > kSplitMinK and M_X * N_X <= kSplitMaxMN are
+// computed in k ranges (split-K); the caller passes ksplit only when the
+// pipelined kernel (the one that writes partial slots) can run the plan.
 // gather: pack B through the offset table where it fits (else sub-block items)
-constexpr int64_t kSplitMinK = 4096, kSplitChunk = 2048, kSplitMaxSlots = 128;
+constexpr int64_t kSplitMinK = 4096, kSplitChunk = 2048, kSplitMaxSlots = 128, kSplitMaxMN = 64 * 64 * 16;
 yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::pair<int32_t, int32_t>> &pairs,
                              int64_t a_base, int64_t b_base, PlanTables &t, int rb, int cb, int nch,
                              bool ksplit = false, bool gather = true);

@@ -2,11 +2,15 @@
 times (plans built and autotuned as there, the FP64 norm fused into the last
 contraction, grouped launches over many problems, the serving loop).
 
-The oracle computes sampled output blocks one by one (every matched block pair
-of those blocks, Sec. II.B) from the GPU's own input of that step; the
-structure of every output is compared in full, bit for bit.  Properties that
-hold at any size cover the rest: every output element is written (outputs are
-pre-filled with NaN) and the fused norm agrees with an independent reduction.
+The corner chains at chi = 128 and chi = 256 are compared element by element
+with the oracle's chain (block-pair form), in FP64 and in the reduced
+precisions; where an output is too large for the oracle in full (the serving
+mix's largest runs) it computes sampled output blocks one by one (every
+matched block pair of those blocks, Sec. II.B) from the GPU's own input of
+that step.  The structure of every output is compared in full, bit for bit.
+Properties that hold at any size cover the rest: every output element is
+written (outputs are pre-filled with NaN) and the fused norm agrees with an
+independent reduction.
 """
 
 import numpy as np
@@ -58,26 +62,6 @@ def all_written(x, n):
     return bool(torch.isfinite(x[:n]).all())
 
 
-def chain_check(t, ch, nsample, seed):
-    """Run the benchmark's chain once and check every step on sampled blocks."""
-    for o in ch.outs:
-        o.fill_(float("nan"))
-    ch.step(0)
-    torch.cuda.synchronize()
-    cur = None
-    for i, ((an, bn), (ax, bx), pl, o) in enumerate(zip(STEPS, t["axes"], ch.plans, ch.outs)):
-        s = pl.output(0)
-        assert all_written(o, s.numel), f"step {i + 1}: unwritten output elements"
-        vals = o[:s.numel].double().cpu().numpy()
-        check_sampled(t[an] if an else cur, t[bn], ax, bx, s, vals, nsample, seed + i)
-        cur = G.as_block_tensor(s, vals)
-    last = ch.outs[-1][:ch.n_last]
-    ref_norm = float(torch.linalg.vector_norm(last))
-    assert abs(float(ch.nout[0]) / ref_norm - 1) <= 1e-13
-    assert float(ch.nout[1]) == float(last.abs().max())
-    return ch.outs[-1][:ch.n_last].clone()
-
-
 def test_headline_chain_autotuned_full_oracle():
     """chi = 128, D = 8: the timed chain, every element against the oracle."""
     t = W.ctm()
@@ -98,33 +82,103 @@ def test_headline_chain_autotuned_full_oracle():
 
 
 @pytest.fixture(scope="module")
-def chi256():
+def chi256_oracle():
+    """The oracle's chain at chi = 256, D = 10: every output of the four steps
+    in full (block-pair form; the largest output has 69.2 M elements)."""
     t = W.ctm_chi256()
+    refs, cur = [], None
+    for (an, bn), (ax, bx) in zip(STEPS, t["axes"]):
+        cur = oracle.tensordot_blockpair(t[an] if an else cur, t[bn], ax, bx)
+        refs.append(cur)
+    return t, refs
+
+
+def _full_step_check(i, pl, out, ref, tol):
+    s = pl.output(0)
+    assert G.structure_equal(s, ref), f"step {i + 1}: structure differs from the oracle"
+    assert all_written(out, s.numel), f"step {i + 1}: unwritten output elements"
+    err = oracle.rel_frobenius(out[:s.numel].double().cpu().numpy(), ref.data)
+    assert err <= tol, f"step {i + 1}: relative Frobenius error {err:.3e} > {tol:.0e}"
+    return err
+
+
+def test_chi256_D10_f64_full_oracle(chi256_oracle):
+    """chi = 256, D = 10, FP64: the benchmark's autotuned chain, every element
+    of every step against the oracle's chain, and the fused norm."""
+    t, refs = chi256_oracle
     ch = Chain(torch, Y, t)
-    ref = chain_check(t, ch, nsample=16, seed=40)
-    del ch
-    torch.cuda.empty_cache()
-    return t, ref
-
-
-def test_chi256_D10_f64_sampled(chi256):
-    assert chi256[1].numel() == 22334656
+    for o in ch.outs:
+        o.fill_(float("nan"))
+    ch.step(0)
+    torch.cuda.synchronize()
+    for i, (pl, o, ref) in enumerate(zip(ch.plans, ch.outs, refs)):
+        _full_step_check(i, pl, o, ref, TOL_F64)
+    nrm = float(np.linalg.norm(refs[-1].data))
+    assert abs(float(ch.nout[0]) / nrm - 1) <= 1e-13
+    mx = float(np.abs(refs[-1].data).max())
+    assert abs(float(ch.nout[1]) / mx - 1) <= TOL_F64
+    assert float(ch.nout[1]) == float(ch.outs[-1][:ch.n_last].abs().max())
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16x3", "bf16x6"])
-def test_chi256_D10_reduced_precision(chi256, prec):
-    """The reduced-precision chains (FP32 intermediates, FP64 last output and
-    norm) within their stated error of the FP64 result the oracle checked."""
-    t, ref = chi256
+def test_chi256_D10_reduced_precision_chain(chi256_oracle, prec):
+    """The reduced-precision chains (FP32 intermediates, the last output and
+    its norm in FP64) end to end: every step's output against the oracle's
+    FP64 chain, within the precision's stated tolerance."""
+    t, refs = chi256_oracle
     ch = Chain(torch, Y, t, prec=prec)
-    ch.outs[-1].fill_(float("nan"))
+    for o in ch.outs:
+        o.fill_(float("nan"))
     ch.step(0)
     torch.cuda.synchronize()
+    for i, (pl, o, ref) in enumerate(zip(ch.plans, ch.outs, refs)):
+        _full_step_check(i, pl, o, ref, TOL[prec])
     got = ch.outs[-1][:ch.n_last]
-    assert all_written(got, ch.n_last)
-    err = float(torch.linalg.vector_norm(got - ref) / torch.linalg.vector_norm(ref))
-    assert err <= TOL[prec], f"{prec}: {err:.3e}"
     assert abs(float(ch.nout[0]) / float(torch.linalg.vector_norm(got)) - 1) <= 1e-13
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "bf16x6"])
+def test_chi256_D10_reduced_precision_isolated_steps(chi256_oracle, prec):
+    """Each step alone on the oracle's FP64 input of that step (rounded to
+    FP32 for the operand buffers), against the oracle's output of that step."""
+    t, refs = chi256_oracle
+    for i, ((an, bn), (ax, bx)) in enumerate(zip(STEPS, t["axes"])):
+        a = t[an] if an else refs[i - 1]
+        last = i == len(STEPS) - 1
+        pl = Y.plan([(a, t[bn], ax, bx)], precision=prec, in_dtype=Y.DTYPE_F32,
+                    out_dtype=Y.DTYPE_F64 if last else Y.DTYPE_F32)
+        c, _ = G.alloc_out(pl, 0)
+        pl.contract([G.upload(a, Y.DTYPE_F32)], [G.upload(t[bn], Y.DTYPE_F32)], [c], G.workspace(pl))
+        torch.cuda.synchronize()
+        _full_step_check(i, pl, c, refs[i], TOL[prec])
+        del pl, c
+        torch.cuda.empty_cache()
+
+
+def test_u1_d18_x4096_batch():
+    """The benchmark's 4096-problem batch of the rank-4 U(1) D = 18 contraction
+    in one grouped launch: the structure of all 4096 outputs against the
+    oracle's, every element written, and 66 problems (64 seeded, the first and
+    the last) in full against the oracle."""
+    probs = W.u1_d18(4096)
+    pl = Y.plan([(p.a, p.b, p.axes_a, p.axes_b) for p in probs])
+    A = [G.upload(p.a) for p in probs]
+    B = [G.upload(p.b) for p in probs]
+    C = [G.alloc_out(pl, i)[0] for i in range(len(probs))]
+    pl.contract(A, B, C, G.workspace(pl))
+    torch.cuda.synchronize()
+    ref_s = oracle.output_structure(probs[0].a, probs[0].b, probs[0].axes_a, probs[0].axes_b, with_data=False)
+    for i in range(len(probs)):
+        s = pl.output(i)
+        assert G.structure_equal(s, ref_s), f"problem {i}: structure"
+        assert all_written(C[i], s.numel), f"problem {i}: unwritten output elements"
+    rng = np.random.default_rng(4096)
+    pick = sorted(set(rng.choice(len(probs), size=64, replace=False).tolist()) | {0, len(probs) - 1})
+    for i in pick:
+        p = probs[i]
+        ref = oracle.tensordot_blockpair(p.a, p.b, p.axes_a, p.axes_b)
+        err = oracle.rel_frobenius(C[i][:ref.data.size].cpu().numpy(), ref.data)
+        assert err <= TOL_F64, f"problem {i}: {err:.3e}"
 
 
 @pytest.mark.parametrize("name", ["u1_d18_x64", "u1_d18_x512", "u1_uneven", "u1_uneven_f32"])
@@ -162,8 +216,8 @@ def test_grouped_batches(name):
 def test_serving_mix_full_sizes():
     """All 32 serving runs (Z2 and U(1), D up to 10, chi up to 256) through the
     server with the benchmark's memory budget: each result bitwise equal to
-    the same plans run alone, and the largest runs checked against the oracle
-    on sampled blocks of every step."""
+    the same plans run alone, and every run checked against the oracle on
+    sampled blocks of every step."""
     runs = []
     for r in range(32):
         t = W.serving_run(r)
@@ -194,15 +248,17 @@ def test_serving_mix_full_sizes():
             outs.append(c)
         torch.cuda.synchronize()
         assert torch.equal(out[:n], outs[-1][:n]), f"run {r}: result in the mix differs from alone"
-        if r in (15, 31):  # D = 10, chi = 256, Z2 and U(1)
-            cur = None
-            for i, ((an, bn), (ax, bx), pl, c) in enumerate(zip(STEPS, t["axes"], plans, outs)):
-                s = pl.output(0)
-                assert all_written(c, s.numel)
-                vals = c[:s.numel].cpu().numpy()
-                check_sampled(t[an] if an else cur, t[bn], ax, bx, s, vals, 4, 100 * r + i)
-                cur = G.as_block_tensor(s, vals)
-                del vals
+        # every run, every step: structure in full and sampled blocks against
+        # the oracle (on the GPU's input of that step; the D = 10 runs' largest
+        # intermediates are too large for the oracle in full)
+        cur = None
+        for i, ((an, bn), (ax, bx), pl, c) in enumerate(zip(STEPS, t["axes"], plans, outs)):
+            s = pl.output(0)
+            assert all_written(c, s.numel)
+            vals = c[:s.numel].cpu().numpy()
+            check_sampled(t[an] if an else cur, t[bn], ax, bx, s, vals, 4, 100 * r + i)
+            cur = G.as_block_tensor(s, vals)
+            del vals
         del outs, inp
         torch.cuda.empty_cache()
     srv.close()

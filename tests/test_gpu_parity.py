@@ -621,3 +621,36 @@ def test_split_k_fp32_and_norm():
     torch.cuda.synchronize()
     rf, rm = oracle.norms(ref)
     assert abs(float(nout[0]) / rf - 1) <= 1e-13
+
+
+@pytest.mark.parametrize("flags", ["mfma", "rows"])
+def test_long_k_with_forced_kernel_family(flags):
+    """A plan that forces a kernel family (packed-B MFMA tiles, or the row
+    kernel request) is not split into k ranges (only the pipelined kernel
+    writes partial slots): it contracts without error and matches the oracle."""
+    import paper_2405_12196_amd as Y
+    a, b, xa, xb = _long_k_problem(79)
+    ref = oracle.tensordot_blockpair(a, b, xa, xb)
+    f = Y.FLAG_MFMA if flags == "mfma" else Y.FLAG_ROWS
+    pl, (s,), (v,) = G.run([(a, b, xa, xb)], flags=f)
+    assert pl.stats(0)["max_k"] > 4096 and pl.stats(0)["tiles"] == pl.stats(0)["sectors"]
+    check_f64(s, v, ref)
+
+
+def test_long_k_wide_sector_not_split():
+    """K > 4096 with an output sector of more than 16 64 x 64 tiles: computed
+    without k ranges (no partial-slot workspace), still exact."""
+    import paper_2405_12196_amd as Y
+    from workloads import Leg, rand
+    li = Leg(1, ((0,),), (300,))
+    lk = Leg(1, ((-1,), (0,), (1,)), (50, 60, 50))
+    lj = Leg(-1, ((0,),), (260,))
+    a = rand([li, lk.conj(), lk.conj()], (0,), (0,), 81)
+    b = rand([lk, lk, lj], (0,), (0,), 82)
+    ref = oracle.tensordot_blockpair(a, b, (1, 2), (0, 1))
+    pl, (s,), (v,) = G.run([(a, b, (1, 2), (0, 1))])
+    st = pl.stats(0)
+    assert st["max_k"] > 4096 and st["max_m"] * st["max_n"] > 64 * 64 * 16
+    # packed B (K x N FP64) and the norm parts only: no partial slots
+    assert pl.workspace_bytes < st["max_k"] * st["max_n"] * 8 + (1 << 20)
+    check_f64(s, v, ref)
