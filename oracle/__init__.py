@@ -18,7 +18,10 @@ Implementations (each cites the passage of the paper it follows):
                            of a tensordot with respect to either operand;
   * ``validate_*``         structural checks with the library's status classes;
   * ``norms``              Frobenius norm and max-abs of a block tensor;
-  * ``structure_stats``    matched pairs, sectors, useful flops, bytes.
+  * ``structure_stats``    matched pairs, sectors, useful flops, bytes;
+  * ``svd.*``              the block-sparse truncated SVD of a block tensor
+                           (sector matrices, per-sector SVD, the global
+                           truncation rule, the kept factors as block tensors).
 
 Every function is pinned by tests that do not re-use its own formula (closed
 forms, the paper's worked example, brute force, special cases that reduce to
@@ -32,3 +35,4 @@ from .blocksparse import (  # noqa: F401
     leg_index_maps, fuse_legs, unfuse_legs, transpose, dual, tensordot_grad, norms, structure_stats,
     rel_frobenius, same_structure,
 )
+from . import svd  # noqa: F401
