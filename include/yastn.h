@@ -161,6 +161,23 @@ yastn_status yastn_plan_stats(yastn_plan_t plan, int32_t prob, yastn_stats *st);
 yastn_status yastn_contract(yastn_plan_t plan, const void *const *a, const void *const *b,
                             void *const *c, void *workspace, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * yastn_contract, with the workspace taken from a fixed device array of
+ * YASTN_SCRATCH_BYTES that the library holds on every GPU it runs on (from
+ * the first call on that GPU until the process ends), so the call passes no
+ * workspace and allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine).  The plan's workspace (yastn_plan_workspace) must fit:
+ * larger plans get YASTN_ERR_STATE; so does a call whose current device is
+ * not the plan's.  Every call on one GPU shares that GPU's array and leaves
+ * its contents behind (each call writes every scratch byte it reads first),
+ * so calls that may overlap on one GPU -- on different streams, or on one
+ * stream with a plan still running that uses yastn_contract_noalloc -- race:
+ * serialise them.  Results are bitwise those of yastn_contract. */
+#define YASTN_SCRATCH_BYTES ((size_t)64 << 20)
+yastn_status yastn_contract_noalloc(yastn_plan_t plan, const void *const *a, const void *const *b,
+                                    void *const *c, void *hip_stream);
+
 /* As yastn_contract for a single-problem plan, and also writes the FP64
  * Frobenius norm and max |x| of the output: norm_out [device] receives
  * out[0] = ||C||_F, out[1] = max |C| (the truncation input's normalisation).

@@ -9,6 +9,7 @@ Names follow the C ABI in include/yastn.h:
     plan(problems, ...)        -> Plan            (yastn_plan)
     Plan.output(p)             -> structure of C  (yastn_plan_output)
     Plan.contract(a, b, c, ws) -> None, async     (yastn_contract)
+    Plan.contract_noalloc(a, b, c) -> None, async (yastn_contract_noalloc)
     contract_jobs(jobs)        -> None, async     (yastn_contract_jobs)
     norm(x, out, ws)           -> None, async     (yastn_norm)
 """
@@ -32,7 +33,7 @@ STATUS = ["OK", "ERR_ARG", "ERR_SYM", "ERR_CHARGE", "ERR_SIGNATURE", "ERR_SHAPE"
           "ERR_DUPLICATE", "ERR_NOMEM", "ERR_HIP", "ERR_STATE"]
 
 EXPORTS = ["yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats", "yastn_plan_info",
-           "yastn_contract", "yastn_contract_norm", "yastn_contract_timed",
+           "yastn_contract", "yastn_contract_noalloc", "yastn_contract_norm", "yastn_contract_timed",
            "yastn_contract_jobs", "yastn_norm_workspace", "yastn_norm",
            "yastn_free", "yastn_last_error", "yastn_status_string", "yastn_abi_version",
            "yastn_plan_autotune", "yastn_plan_set_variant",
@@ -43,6 +44,7 @@ EXPORTS = ["yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_pla
 REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 MAX_CHAIN = 8
 NUM_VARIANTS = 23
+SCRATCH_BYTES = 64 << 20
 
 
 class YastnError(RuntimeError):
@@ -116,6 +118,8 @@ def lib():
         L.yastn_plan_stats.argtypes = [C.c_void_p, C.c_int32, C.POINTER(Stats)]
         L.yastn_contract.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                      C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]
+        L.yastn_contract_noalloc.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                             C.POINTER(C.c_void_p), C.c_void_p]
         L.yastn_contract_norm.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                           C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p, C.c_void_p]
         L.yastn_contract_timed.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
@@ -158,7 +162,7 @@ def lib():
                   "yastn_grad_workspace", "yastn_grad"):
             getattr(L, f).restype = C.c_int32
         for f in ("yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats",
-                  "yastn_contract", "yastn_contract_norm", "yastn_contract_timed",
+                  "yastn_contract", "yastn_contract_noalloc", "yastn_contract_norm", "yastn_contract_timed",
                   "yastn_contract_jobs", "yastn_norm",
                   "yastn_plan_autotune", "yastn_plan_set_variant", "yastn_plan_info", "yastn_server_create",
                   "yastn_server_submit", "yastn_server_step", "yastn_server_query", "yastn_server_forget",
@@ -321,6 +325,16 @@ class Plan:
         pc = (C.c_void_p * max(1, n))(*[_ptr(x) for x in c])
         _check(lib().yastn_contract(self._h, pa, pb, pc, C.c_void_p(_ptr(workspace)),
                                     C.c_void_p(_stream(stream))))
+
+    def contract_noalloc(self, a, b, c, stream=None):
+        """As contract(), with the library's fixed per-GPU scratch as the
+        workspace (yastn_contract_noalloc: no device allocation; calls that
+        may overlap on one GPU race on the scratch)."""
+        n = self.nprob
+        pa = (C.c_void_p * max(1, n))(*[_ptr(x) for x in a])
+        pb = (C.c_void_p * max(1, n))(*[_ptr(x) for x in b])
+        pc = (C.c_void_p * max(1, n))(*[_ptr(x) for x in c])
+        _check(lib().yastn_contract_noalloc(self._h, pa, pb, pc, C.c_void_p(_stream(stream))))
 
     def contract_norm(self, a, b, c, workspace, norm_out, stream=None):
         """As contract() for a single-problem plan; also writes norm_out[0] =

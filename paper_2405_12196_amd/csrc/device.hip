@@ -690,6 +690,39 @@ yastn_status check_job_ptrs(const Plan *pl, const void *const *a, const void *co
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// fixed device scratch for yastn_contract_noalloc
+// ---------------------------------------------------------------------------
+// Every GPU the library runs on holds its own copy of this array until the
+// process ends.  In host code `scratch` is only a stand-in for the symbol:
+// kernels receive the device address that hipGetSymbolAddress returns (kept
+// per device below), never the array's name.
+static __device__ __align__(256) char scratch[YASTN_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// The scratch address on the current device, looked up once per device with
+// that device current (the first call of the entry point on it).
+yastn_status scratch_ptr(int dev, void **out) {
+  if (dev < 0 || dev >= kMaxDevices) return set_error(YASTN_ERR_STATE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return set_error(YASTN_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return YASTN_OK;
+}
+}  // namespace
 }  // namespace yastn
 
 // ===========================================================================
@@ -908,6 +941,30 @@ yastn_status yastn_contract(yastn_plan_t plan, const void *const *a, const void 
   std::vector<JobRef> jobs;
   for (const Group &g : plan->p.groups) jobs.push_back(JobRef{&plan->p, &g, a, b, c, workspace});
   return launch(jobs, reinterpret_cast<hipStream_t>(hip_stream));
+}
+
+yastn_status yastn_contract_noalloc(yastn_plan_t plan, const void *const *a, const void *const *b, void *const *c,
+                                    void *hip_stream) {
+  if (!plan) return set_error(YASTN_ERR_ARG, "null plan");
+  if (plan->p.ws_bytes > YASTN_SCRATCH_BYTES)
+    return set_error(YASTN_ERR_STATE, "plan workspace (" + std::to_string(plan->p.ws_bytes) +
+                                          " bytes) exceeds the fixed scratch of YASTN_SCRATCH_BYTES");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(YASTN_ERR_HIP, "no current HIP device");
+  }
+  if (dev != plan->p.device) return set_error(YASTN_ERR_STATE, "the current device is not the plan's device");
+  void *ws = nullptr;
+  yastn_status s = scratch_ptr(dev, &ws);
+  if (s) return s;
+  if ((s = check_job_ptrs(&plan->p, a, b, c, ws))) return s;
+  // one launch per problem group, from an array on the stack
+  for (const Group &g : plan->p.groups) {
+    const JobRef j{&plan->p, &g, a, b, c, ws};
+    if ((s = launch(&j, 1, reinterpret_cast<hipStream_t>(hip_stream)))) return s;
+  }
+  return YASTN_OK;
 }
 
 yastn_status yastn_contract_norm(yastn_plan_t plan, const void *const *a, const void *const *b, void *const *c,
