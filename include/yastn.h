@@ -354,6 +354,59 @@ yastn_status yastn_grad(yastn_grad_t g, const void *dc, const void *other, void 
                         void *hip_stream);
 void yastn_grad_free(yastn_grad_t g);
 
+/* ---- block-sparse truncated SVD (the CTM truncation) --------------------
+ * T (FP64) viewed as a matrix: rows = the legs row_legs[0..nrow) (in that
+ * order), columns = the other legs in leg order.  Its blocks group into
+ * sectors X = sum over the row legs of s_i rho_i (Z_m components reduced
+ * into [0, m)); by the block form of charge conservation (Sec. II.A) the
+ * column legs of a sector carry n - X, so the matrix is block diagonal, one
+ * dense matrix M_X per sector (Sec. II.B fusion of the row legs and of the
+ * column legs; constituent charge tuples ascending, each block's row index in
+ * C order over its row legs, its column index over its column legs; absent
+ * blocks are zeros).  The CTM move truncates the SVD of this block-diagonal
+ * matrix to the environment dimension chi (Sec. III, Fig. 3 (c)-(d)).
+ *
+ * yastn_svd_plan validates T as yastn_plan does (row legs: a non-empty proper
+ * subset, no repeats, else YASTN_ERR_ARG) and uploads the sector tables.
+ * Sectors are numbered in ascending order of X; yastn_svd_sector gives sector
+ * k's charge X ([host] nsym ints), its matrix dims m x n and the index of its
+ * first singular value (sector k has min(m, n) of them, sv0 .. sv0 + min - 1).
+ *
+ * yastn_svd computes every M_X = U_X diag(S_X) V_X^T on the device (FP64
+ * block one-sided Jacobi: the columns of the tall orientation of M_X are
+ * rotated in blocks of 8 until every pair is orthogonal to working
+ * precision) and applies one global truncation: values at or below
+ * tol * (largest value) are dropped; if more than chi remain and c is the
+ * (chi+1)-th largest of them, a value is kept iff it exceeds c (1 + deg_tol),
+ * so at most chi are kept and a multiplet within deg_tol of the first dropped
+ * value is never split.  sv [device] receives all nsv singular values, each
+ * sector's descending; kept [host] (nsectors) the kept count of each sector
+ * (a prefix of its values); sweeps [host, may be NULL] the Jacobi sweeps run.
+ * t [device]: T's buffer; workspace [device]: yastn_svd_info bytes, 256-byte
+ * aligned, which also holds the factors until the next yastn_svd.  Runs on
+ * hip_stream and synchronises it once per sweep (it returns when done);
+ * YASTN_ERR_STATE if the sweeps do not converge.
+ *
+ * yastn_svd_output: the structure of the kept factors of the last yastn_svd:
+ * U with legs (row legs..., v), v carrying charge X with signature -1, total
+ * charge 0, block (row tuple, X) of dims (row dims..., kept_X); V^T with legs
+ * (v', column legs...), v' carrying X with signature +1, T's total charge,
+ * block (X, column tuple) of dims (kept_X, column dims...).  Blocks ascending,
+ * contiguous; sectors with nothing kept have none.  Arrays owned by the plan.
+ * yastn_svd_factors writes them (async on hip_stream) into u and vt [device]
+ * from the workspace of the last yastn_svd. */
+typedef struct yastn_svd_s *yastn_svd_t;
+yastn_status yastn_svd_plan(const yastn_tensor_desc *t, int32_t nrow, const int32_t *row_legs, void *hip_stream,
+                            yastn_svd_t *out);
+yastn_status yastn_svd_info(yastn_svd_t s, int32_t *nsectors, int64_t *nsv, size_t *workspace_bytes);
+yastn_status yastn_svd_sector(yastn_svd_t s, int32_t k, int32_t *charge, int64_t *m, int64_t *n, int64_t *sv0);
+yastn_status yastn_svd(yastn_svd_t s, const void *t, int32_t chi, double tol, double deg_tol, double *sv,
+                       int32_t *kept, int32_t *sweeps, void *workspace, void *hip_stream);
+yastn_status yastn_svd_output(yastn_svd_t s, yastn_tensor_desc *u, int64_t *u_numel, yastn_tensor_desc *vt,
+                              int64_t *vt_numel);
+yastn_status yastn_svd_factors(yastn_svd_t s, void *u, void *vt, const void *workspace, void *hip_stream);
+void yastn_svd_free(yastn_svd_t s);
+
 const char *yastn_last_error(void);
 const char *yastn_status_string(yastn_status s);
 int32_t yastn_abi_version(void);

@@ -40,7 +40,9 @@ EXPORTS = ["yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_pla
            "yastn_server_create", "yastn_server_submit", "yastn_server_step", "yastn_server_query",
            "yastn_server_forget", "yastn_server_drain", "yastn_server_get_stats", "yastn_server_destroy",
            "yastn_perm_plan", "yastn_perm_output", "yastn_permute", "yastn_perm_free",
-           "yastn_grad_plan", "yastn_grad_output", "yastn_grad_workspace", "yastn_grad", "yastn_grad_free"]
+           "yastn_grad_plan", "yastn_grad_output", "yastn_grad_workspace", "yastn_grad", "yastn_grad_free",
+           "yastn_svd_plan", "yastn_svd_info", "yastn_svd_sector", "yastn_svd", "yastn_svd_output",
+           "yastn_svd_factors", "yastn_svd_free"]
 REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 MAX_CHAIN = 8
 NUM_VARIANTS = 23
@@ -158,8 +160,21 @@ def lib():
         L.yastn_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.yastn_grad_free.argtypes = [C.c_void_p]
         L.yastn_grad_free.restype = None
+        L.yastn_svd_plan.argtypes = [C.POINTER(TensorDesc), C.c_int32, C.POINTER(C.c_int32), C.c_void_p,
+                                     C.POINTER(C.c_void_p)]
+        L.yastn_svd_info.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]
+        L.yastn_svd_sector.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.yastn_svd.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_void_p,
+                                C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_void_p, C.c_void_p]
+        L.yastn_svd_output.argtypes = [C.c_void_p, C.POINTER(TensorDesc), C.POINTER(C.c_int64),
+                                       C.POINTER(TensorDesc), C.POINTER(C.c_int64)]
+        L.yastn_svd_factors.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.yastn_svd_free.argtypes = [C.c_void_p]
+        L.yastn_svd_free.restype = None
         for f in ("yastn_perm_plan", "yastn_perm_output", "yastn_permute", "yastn_grad_plan", "yastn_grad_output",
-                  "yastn_grad_workspace", "yastn_grad"):
+                  "yastn_grad_workspace", "yastn_grad", "yastn_svd_plan", "yastn_svd_info", "yastn_svd_sector",
+                  "yastn_svd", "yastn_svd_output", "yastn_svd_factors"):
             getattr(L, f).restype = C.c_int32
         for f in ("yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats",
                   "yastn_contract", "yastn_contract_noalloc", "yastn_contract_norm", "yastn_contract_timed",
@@ -461,6 +476,62 @@ class Grad:
     def free(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().yastn_grad_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Svd:
+    """Block-sparse truncated SVD of a block tensor (yastn_svd_*): rows = the
+    legs ``row_legs`` (in that order), columns = the others; one sector per
+    row-leg charge X = sum s_i rho_i.  ``sectors``: [(X, m, n, sv0)]."""
+
+    def __init__(self, t, row_legs, stream=None):
+        keep = _Keep()
+        d = _desc(t, keep)
+        rl = _arr(list(row_legs), np.int32)
+        h = C.c_void_p()
+        _check(lib().yastn_svd_plan(C.byref(d), len(rl), keep.ptr(rl, C.c_int32), C.c_void_p(_stream(stream)),
+                                    C.byref(h)))
+        self._h = h
+        ns, nsv, ws = C.c_int32(), C.c_int64(), C.c_size_t()
+        _check(lib().yastn_svd_info(h, C.byref(ns), C.byref(nsv), C.byref(ws)))
+        self.nsectors, self.nsv, self.workspace_bytes = int(ns.value), int(nsv.value), int(ws.value)
+        nsym = len(t.sym_mod)
+        self.sectors = []
+        for k in range(self.nsectors):
+            q = (C.c_int32 * nsym)()
+            m, n, s0 = C.c_int64(), C.c_int64(), C.c_int64()
+            _check(lib().yastn_svd_sector(h, k, q, C.byref(m), C.byref(n), C.byref(s0)))
+            self.sectors.append((tuple(int(v) for v in q), int(m.value), int(n.value), int(s0.value)))
+
+    def run(self, t, sv, workspace, chi, tol=0.0, deg_tol=1e-10, stream=None):
+        """Singular values into ``sv`` (device, nsv FP64), each sector's
+        descending; returns (kept per sector, sweeps).  Synchronises."""
+        kept = (C.c_int32 * max(1, self.nsectors))()
+        sweeps = C.c_int32()
+        _check(lib().yastn_svd(self._h, C.c_void_p(_ptr(t)), int(chi), float(tol), float(deg_tol),
+                               C.c_void_p(_ptr(sv)), kept, C.byref(sweeps), C.c_void_p(_ptr(workspace)),
+                               C.c_void_p(_stream(stream))))
+        return [int(kept[k]) for k in range(self.nsectors)], int(sweeps.value)
+
+    def output(self):
+        """(U structure, V^T structure) of the last run's kept factors."""
+        du, dv, nu, nv = TensorDesc(), TensorDesc(), C.c_int64(), C.c_int64()
+        _check(lib().yastn_svd_output(self._h, C.byref(du), C.byref(nu), C.byref(dv), C.byref(nv)))
+        return _structure(du, nu), _structure(dv, nv)
+
+    def factors(self, u, vt, workspace, stream=None):
+        _check(lib().yastn_svd_factors(self._h, C.c_void_p(_ptr(u)), C.c_void_p(_ptr(vt)),
+                                       C.c_void_p(_ptr(workspace)), C.c_void_p(_stream(stream))))
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().yastn_svd_free(self._h)
             self._h = C.c_void_p()
 
     def __del__(self):

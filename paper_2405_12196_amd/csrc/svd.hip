@@ -1,0 +1,932 @@
+// Block-sparse truncated SVD of a block tensor viewed as a matrix (row legs x
+// column legs): the truncation step of the CTM move (paper Sec. III, Fig. 3
+// (c)-(d): the enlarged corner fused into a block-diagonal matrix, its SVD
+// truncated to the environment dimension chi).  gfx950 / CDNA4, FP64.
+//
+//  k_svd_init    W = 0 and V = identity for every sector.
+//  k_svd_gather  fuse the blocks into one dense matrix per sector X (X = sum
+//                over the row legs of s_i rho_i), Sec. II.B fusion: the
+//                constituent tuples of a sector in ascending charge order,
+//                each block's row index in C order over its row legs, its
+//                column index over its column legs.  One thread per block
+//                element: contiguous reads, each element's place in W from
+//                per-leg strides.  A sector with fewer rows than columns is
+//                stored transposed, so every working matrix W is tall.
+//  k_svd_round   one round of a block one-sided Jacobi sweep, all sectors in
+//                one launch: W's columns form blocks of 8; the round pairs
+//                the blocks of each sector (round-robin: every pair once per
+//                sweep), and one workgroup per block pair forms the 16 x 16
+//                Gram matrix of its 16 columns on the FP64 MFMA, diagonalises
+//                it with cyclic Jacobi rotations in LDS, and applies the
+//                rotation to those columns of W and of V on the MFMA (V
+//                accumulates the rotations, so W V stays M V with M the
+//                sector matrix).  The largest scaled off-diagonal Gram entry
+//                seen in a sweep decides convergence.
+//  k_svd_norms   singular values = column norms of the converged W; W's
+//                columns scaled to unit norm (the left vectors).
+//  k_svd_sort    each sector's values in descending order (rank by count).
+//  k_svd_*       the global truncation: values at or below tol x max are
+//                dropped; if more than chi remain and c is the (chi+1)-th
+//                largest, a value is kept iff it exceeds c (1 + deg_tol).
+//  k_svd_write   the kept columns of U and rows of V^T as block tensors.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/yastn.h"
+#include "index.hpp"
+#include "planner.hpp"
+
+#define SVD_HIP(call)                                                                                            \
+  do {                                                                                                           \
+    hipError_t e_ = (call);                                                                                      \
+    if (e_ != hipSuccess) return set_error(YASTN_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+namespace yastn {
+namespace {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+constexpr int kSvdW = 8;           // columns per block (a block pair is 16 columns: one MFMA tile)
+constexpr int kSvdMaxSweeps = 40;  // outer sweeps before giving up
+constexpr int kSvdInnerSweeps = 4; // cyclic Jacobi sweeps on a pair's 16 x 16 Gram matrix
+
+struct DevSvdSector {
+  int64_t w_off;   // W: rows x ld, row-major, elements from the workspace base
+  int64_t v_off;   // V: ld x ld, row-major
+  int32_t rows;    // W's rows (>= cols)
+  int32_t cols;    // W's columns
+  int32_t ld;      // kSvdW * nb
+  int32_t nb;      // column blocks, even, >= 2
+  int32_t wg0;     // first workgroup of this sector in a round
+  int32_t sv0;     // first of the sector's cols singular values (global index)
+  int32_t trans;   // 1: W = M^T
+  int32_t pad;
+};
+
+struct DevSvdGather {  // one block of T: element e (C order over T's legs) -> W
+  int64_t t_off;       // first element in T's buffer
+  int64_t w_base;      // W offset of the block's element 0
+  int32_t numel, rank;
+  int32_t dim[YASTN_MAX_RANK];
+  uint32_t mag[YASTN_MAX_RANK];
+  int32_t sh[YASTN_MAX_RANK];
+  int64_t wstr[YASTN_MAX_RANK];  // W stride of each leg's index
+};
+struct DevSvdTile {
+  int32_t blk, start;
+};
+constexpr int kSvdTile = 1024;
+
+struct DevSvdOut {     // one output block: U (kind 0) or V^T (kind 1)
+  int64_t out_off;     // first element in the output buffer
+  int64_t src_off;     // workspace offset of the source row of the block's first row / column
+  int32_t a, b;        // U: m_i x t; V^T: t x n_j
+  int32_t ld, sv0;     // source row stride; the sector's first sorted index (perm)
+  int32_t kind, pad;
+};
+
+// ------------------------------------------------------------------ kernels
+__global__ void __launch_bounds__(256) k_svd_init(const DevSvdSector *sec, int nsec, double *ws) {
+  for (int k = blockIdx.y; k < nsec; k += gridDim.y) {
+    const DevSvdSector s = sec[k];
+    const int64_t nw = (int64_t)s.rows * s.ld, nv = (int64_t)s.ld * s.ld;
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < nw + nv; i += (int64_t)gridDim.x * 256) {
+      if (i < nw) {
+        ws[s.w_off + i] = 0.0;
+      } else {
+        const int64_t j = i - nw;
+        ws[s.v_off + j] = (j / s.ld == j % s.ld) ? 1.0 : 0.0;
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_svd_gather(const DevSvdGather *__restrict__ blocks,
+                                                    const DevSvdTile *__restrict__ tiles, int ntiles,
+                                                    const double *__restrict__ t, double *__restrict__ ws) {
+  for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+    const DevSvdTile tl = tiles[ti];
+    const DevSvdGather &b = blocks[tl.blk];
+    const int end = min(tl.start + kSvdTile, b.numel);
+    for (int e = tl.start + (int)threadIdx.x; e < end; e += 256) {
+      uint32_t r = (uint32_t)e;
+      int64_t dst = b.w_base;
+      for (int d = b.rank - 1; d >= 0; --d) {
+        const uint32_t q = (uint32_t)(((uint64_t)r * b.mag[d]) >> b.sh[d]);
+        dst += (int64_t)(r - q * (uint32_t)b.dim[d]) * b.wstr[d];
+        r = q;
+      }
+      ws[dst] = t[b.t_off + e];
+    }
+  }
+}
+
+struct SvdRoundArgs {
+  const DevSvdSector *sec;
+  double *ws;
+  unsigned long long *conv;  // per sector: largest scaled off-diagonal Gram entry this sweep (bits of a double >= 0)
+  const int32_t *done;       // per sector: converged, skip
+  int32_t nsec, round;
+  double rot_tol;            // rotate a pair only above this scaled off-diagonal entry
+};
+
+// The round-robin pairing of nb blocks (nb even): round rr in [0, nb - 1),
+// pair p in [0, nb / 2); every unordered pair of blocks once per nb - 1 rounds.
+__device__ __forceinline__ void rr_pair(int nb, int rr, int p, int &P, int &Q) {
+  const int n1 = nb - 1;
+  if (p == 0) {
+    P = n1;
+    Q = rr;
+  } else {
+    P = (rr + p) % n1;
+    Q = (rr - p + n1) % n1;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_svd_round(SvdRoundArgs a) {
+  __shared__ double gpart[4][16][16];
+  __shared__ double g[16][17];
+  __shared__ double q[16][17];
+  __shared__ int rotated;
+  const int bid = blockIdx.x;
+  int lo = 0, hi = a.nsec - 1;
+  while (lo < hi) {  // last sector whose first workgroup is <= bid
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.sec[mid].wg0 <= bid) lo = mid;
+    else hi = mid - 1;
+  }
+  if (a.done[lo]) return;
+  const DevSvdSector S = a.sec[lo];
+  const int p = bid - S.wg0;
+  if (p >= S.nb / 2) return;
+  int P, Q;
+  rr_pair(S.nb, a.round % (S.nb - 1), p, P, Q);
+  double *W = a.ws + S.w_off;
+  double *V = a.ws + S.v_off;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int c16 = lane & 15, kq = lane >> 4;
+  auto colof = [&](int c) { return c < kSvdW ? kSvdW * P + c : kSvdW * Q + c - kSvdW; };
+  // ---- Gram matrix of the 16 columns: wave w takes rows 4w.. in steps of 16
+  {
+    const int col = colof(c16);
+    d4v acc = {0, 0, 0, 0};
+    int r0 = 4 * wid;
+    for (; r0 + 51 < S.rows; r0 += 64) {  // four independent loads in flight
+      double x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = W[(int64_t)(r0 + 16 * u + kq) * S.ld + col];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], x[u], acc, 0, 0, 0);
+    }
+    for (; r0 < S.rows; r0 += 16) {
+      const int r = r0 + kq;
+      const double x = r < S.rows ? W[(int64_t)r * S.ld + col] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) gpart[wid][kq + 4 * v][c16] = acc[v];
+  }
+  __syncthreads();
+  if (wid == 0) {
+    // sum the four waves' parts in a fixed order, Q = I
+    for (int e = lane; e < 256; e += 64) {
+      const int i = e >> 4, j = e & 15;
+      g[i][j] = ((gpart[0][i][j] + gpart[1][i][j]) + gpart[2][i][j]) + gpart[3][i][j];
+      q[i][j] = i == j ? 1.0 : 0.0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // convergence measure: largest |g_ij| / sqrt(g_ii g_jj) over i != j
+    double off = 0.0;
+    for (int e = lane; e < 256; e += 64) {
+      const int i = e >> 4, j = e & 15;
+      const double d = g[i][i] * g[j][j];
+      if (i != j && d > 0.0) off = fmax(off, fabs(g[i][j]) / sqrt(d));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o, 64));
+    if (lane == 0) atomicMax(a.conv + lo, (unsigned long long)__double_as_longlong(off));
+    int any = 0;
+    if (off > a.rot_tol) {
+      // cyclic Jacobi on g (16 x 16): 15 rounds of 8 disjoint rotations; a
+      // rotation (i, j) uses lanes 8 rot .. 8 rot + 7, each lane two of the
+      // 16 rows (column phase) or columns (row phase)
+      const int rot = lane >> 3, e2 = 2 * (lane & 7);
+      for (int sw = 0; sw < kSvdInnerSweeps; ++sw) {
+        int applied = 0;
+        for (int rr = 0; rr < 15; ++rr) {
+          int i, j;
+          rr_pair(16, rr, rot, i, j);
+          const double gii = g[i][i], gjj = g[j][j], gij = g[i][j];
+          double c = 1.0, s = 0.0;
+          const double d = gii * gjj;
+          const bool go = gij != 0.0 && d > 0.0 && fabs(gij) > a.rot_tol * sqrt(d);
+          if (go) {
+            // zero g_ij of J^T g J, J = [[c, s], [-s, c]] on (i, j)
+            const double zeta = (gjj - gii) / (2.0 * gij);
+            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+          }
+          applied |= go;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          // columns i, j of g and q: g <- g J, q <- q J
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int x = e2 + u;
+            const double gi = g[x][i], gj = g[x][j], qi = q[x][i], qj = q[x][j];
+            g[x][i] = c * gi - s * gj;
+            g[x][j] = s * gi + c * gj;
+            q[x][i] = c * qi - s * qj;
+            q[x][j] = s * qi + c * qj;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          // rows i, j of g: g <- J^T g
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int x = e2 + u;
+            const double gi = g[i][x], gj = g[j][x];
+            g[i][x] = c * gi - s * gj;
+            g[j][x] = s * gi + c * gj;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        applied = __any(applied);
+        any |= applied;
+        if (!applied) break;
+      }
+    }
+    if (lane == 0) rotated = any;
+  }
+  __syncthreads();
+  if (!rotated) return;
+  // ---- [W_P W_Q] <- [W_P W_Q] q and [V_P V_Q] <- [V_P V_Q] q: wave w takes
+  // 16-row chunks w, w + 4, ...; A operand = 16 rows x 4 of the 16 columns,
+  // B operand = 4 rows of q
+  double qb[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) qb[kk] = q[4 * kk + kq][c16];
+  auto rotate = [&](double *X, int nrows) {
+    const int cout = colof(c16);
+    for (int r0 = 16 * wid; r0 < nrows; r0 += 64) {
+      const int ra = r0 + c16;
+      double x[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) x[kk] = ra < nrows ? X[(int64_t)ra * S.ld + colof(4 * kk + kq)] : 0.0;
+      d4v acc = {0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[kk], qb[kk], acc, 0, 0, 0);
+      // every lane has read its rows before any lane of the wave writes them
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + kq + 4 * v;
+        if (r < nrows) X[(int64_t)r * S.ld + cout] = acc[v];
+      }
+    }
+  };
+  rotate(W, S.rows);
+  rotate(V, S.cols);
+}
+
+// conv[k] = 0 (every sweep); done[k] = 0 too when done is given (first sweep)
+__global__ void k_svd_sweep_begin(unsigned long long *conv, int32_t *done, int nsec) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nsec; k += gridDim.x * blockDim.x) {
+    conv[k] = 0ull;
+    if (done) done[k] = 0;
+  }
+}
+
+// done[k] = 1 once sector k's sweep saw no scaled off-diagonal entry above
+// tol; *alldone = every sector done (one workgroup)
+__global__ void __launch_bounds__(256) k_svd_sweep_end(const unsigned long long *conv, int32_t *done, int nsec,
+                                                       const DevSvdSector *sec, double eps_scale, int32_t *alldone) {
+  __shared__ int notdone;
+  if (threadIdx.x == 0) notdone = 0;
+  __syncthreads();
+  for (int k = threadIdx.x; k < nsec; k += 256) {
+    const double off = __longlong_as_double((long long)conv[k]);
+    const double tol = fmax(1e-14, eps_scale * sqrt((double)sec[k].rows));
+    if (!done[k] && off <= tol) done[k] = 1;
+    if (!done[k]) atomicOr(&notdone, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *alldone = notdone ? 0 : 1;
+}
+
+// singular value j of a sector = norm of W's column j; the column scaled to
+// unit norm.  One wave per column, lanes stride the rows (fixed order).
+__global__ void __launch_bounds__(256) k_svd_norms(const DevSvdSector *sec, int nsec, double *ws, double *sv_raw) {
+  const int lane = threadIdx.x & 63;
+  int k = blockIdx.y;
+  for (; k < nsec; k += gridDim.y) {
+    const DevSvdSector S = sec[k];
+    double *W = ws + S.w_off;
+    for (int j = blockIdx.x * 4 + (threadIdx.x >> 6); j < S.cols; j += gridDim.x * 4) {
+      double ss = 0.0;
+      for (int r = lane; r < S.rows; r += 64) {
+        const double x = W[(int64_t)r * S.ld + j];
+        ss = fma(x, x, ss);
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
+      const double sig = sqrt(ss);
+      const double inv = sig > 0.0 ? 1.0 / sig : 0.0;
+      for (int r = lane; r < S.rows; r += 64) W[(int64_t)r * S.ld + j] *= inv;
+      if (lane == 0) sv_raw[S.sv0 + j] = sig;
+    }
+  }
+}
+
+// descending order within each sector: rank of value j = values that are
+// larger, or equal with a smaller index; sv[sv0 + rank] and perm
+__global__ void __launch_bounds__(256) k_svd_sort(const DevSvdSector *sec, int nsec, const double *sv_raw, double *sv,
+                                                  int32_t *perm) {
+  for (int k = blockIdx.x; k < nsec; k += gridDim.x) {
+    const DevSvdSector S = sec[k];
+    const double *x = sv_raw + S.sv0;
+    for (int j = threadIdx.x; j < S.cols; j += 256) {
+      const double v = x[j];
+      int rank = 0;
+      for (int i = 0; i < S.cols; ++i) rank += (x[i] > v) || (x[i] == v && i < j);
+      sv[S.sv0 + rank] = v;
+      perm[S.sv0 + rank] = j;
+    }
+  }
+}
+
+// largest value and how many exceed tol x largest (one workgroup)
+__global__ void __launch_bounds__(1024) k_svd_stats(const double *sv, int n, double tol, double *stat) {
+  __shared__ double mx[1024];
+  __shared__ int cnt[1024];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) m = fmax(m, sv[i]);
+  mx[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double floor_v = tol * mx[0];
+  int c = 0;
+  for (int i = threadIdx.x; i < n; i += 1024) c += sv[i] > floor_v;
+  cnt[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) cnt[threadIdx.x] += cnt[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    stat[0] = mx[0];
+    stat[1] = floor_v;
+    stat[2] = (double)cnt[0];
+    stat[3] = floor_v;  // the cut, raised by k_svd_cut when more than chi remain
+  }
+}
+
+// the (chi+1)-th largest value c among those above the floor: the value v
+// with (# larger) <= chi < (# larger or equal); cut = c (1 + deg_tol)
+__global__ void __launch_bounds__(256) k_svd_cut(const double *sv, int n, int chi, double deg_tol, double *stat) {
+  __shared__ double tile[256];
+  const double floor_v = stat[1];
+  const bool need = stat[2] > (double)chi;
+  if (!need) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const double v = i < n ? sv[i] : -1.0;
+  int gt = 0, ge = 0;
+  for (int j0 = 0; j0 < n; j0 += 256) {
+    __syncthreads();
+    tile[threadIdx.x] = j0 + (int)threadIdx.x < n ? sv[j0 + threadIdx.x] : -1.0;
+    __syncthreads();
+    const int m = min(256, n - j0);
+    for (int j = 0; j < m; ++j) {
+      const double w = tile[j];
+      gt += w > floor_v && w > v;
+      ge += w > floor_v && w >= v;
+    }
+  }
+  if (i < n && v > floor_v && gt <= chi && chi < ge) stat[3] = v * (1.0 + deg_tol);
+}
+
+__global__ void __launch_bounds__(256) k_svd_kept(const DevSvdSector *sec, int nsec, const double *sv,
+                                                  const double *stat, int32_t *kept) {
+  for (int k = blockIdx.x * 256 + threadIdx.x; k < nsec; k += gridDim.x * 256) {
+    const DevSvdSector S = sec[k];
+    const double cut = stat[3];
+    int c = 0;
+    for (int j = 0; j < S.cols; ++j) c += sv[S.sv0 + j] > cut;
+    kept[k] = c;
+  }
+}
+
+// U block (kind 0): element (r, t) = src[r * ld + perm[t]], out row-major
+// a x b (b = t kept); V^T block (kind 1): element (t, c) = src[c * ld +
+// perm[t]], out row-major a x b (a = kept)
+__global__ void __launch_bounds__(256) k_svd_write(const DevSvdOut *__restrict__ items, int nitems,
+                                                   const double *__restrict__ ws, const int32_t *__restrict__ perm,
+                                                   double *__restrict__ u, double *__restrict__ vt) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const DevSvdOut o = items[it];
+    const int64_t n = (int64_t)o.a * o.b;
+    double *out = o.kind == 0 ? u : vt;
+    for (int64_t e = threadIdx.x; e < n; e += 256) {
+      const int32_t x = (int32_t)(e / o.b), y = (int32_t)(e - (int64_t)x * o.b);
+      const int32_t r = o.kind == 0 ? x : y, t = o.kind == 0 ? y : x;
+      out[o.out_off + e] = ws[o.src_off + (int64_t)r * o.ld + perm[o.sv0 + t]];
+    }
+  }
+}
+
+unsigned grid1(int64_t n, int per) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, 65535)); }
+
+using Key = std::vector<int32_t>;
+
+}  // namespace
+
+struct SvdPlanImpl {
+  HostTensor t;
+  std::vector<int32_t> row_legs, col_legs;
+  struct Tuple {
+    Key key;
+    std::vector<int64_t> dims;
+    int64_t size, off;  // elements (product of dims) and first row / column in the sector matrix
+  };
+  struct Sector {
+    Key x;
+    std::vector<Tuple> rows, cols;
+    int64_t m = 0, n = 0;
+  };
+  std::vector<Sector> sectors;
+  std::vector<DevSvdSector> dsec;
+  int64_t nsv = 0;
+  int max_rounds = 1, total_pairs = 0;
+  size_t ws_bytes = 0;
+  size_t off_sv_raw = 0, off_perm = 0, off_conv = 0, off_done = 0, off_stat = 0, off_flag = 0;
+  void *dev_mem = nullptr;  // sectors, gather blocks and tiles
+  DevSvdSector *d_sec = nullptr;
+  DevSvdGather *d_gather = nullptr;
+  DevSvdTile *d_tiles = nullptr;
+  int ngather = 0, ntiles = 0;
+  int device = 0;
+  // after yastn_svd: kept counts and the output structures
+  std::vector<int32_t> kept;
+  bool have_kept = false;
+  std::vector<int32_t> u_q, v_q;
+  std::vector<int64_t> u_sh, v_sh, u_off, v_off;
+  std::vector<int8_t> u_sig, v_sig;
+  std::vector<int32_t> u_n, v_n;
+  int64_t u_numel = 0, v_numel = 0;
+  std::vector<DevSvdOut> outs;
+  void *out_mem = nullptr;
+  int sweeps = 0;
+};
+
+}  // namespace yastn
+
+using namespace yastn;
+
+struct yastn_svd_s {
+  SvdPlanImpl p;
+};
+
+namespace {
+
+int64_t norm_q(int64_t v, int32_t m) {
+  if (m == 0) return v;
+  int64_t r = v % m;
+  return r < 0 ? r + m : r;
+}
+
+}  // namespace
+
+extern "C" {
+
+yastn_status yastn_svd_plan(const yastn_tensor_desc *t, int32_t nrow, const int32_t *row_legs, void *hip_stream,
+                            yastn_svd_t *out) {
+  if (!t || !out || (nrow > 0 && !row_legs)) return set_error(YASTN_ERR_ARG, "null argument");
+  *out = nullptr;
+  yastn_svd_t h = nullptr;
+  try {
+    h = new yastn_svd_s;
+    SvdPlanImpl &P = h->p;
+    yastn_status st = validate_tensor(*t, "T", P.t);
+    if (st != YASTN_OK) {
+      delete h;
+      return st;
+    }
+    const HostTensor &T = P.t;
+    const int r = T.rank, ns = T.nsym;
+    if (nrow < 1 || nrow >= r) {
+      delete h;
+      return set_error(YASTN_ERR_ARG, "row legs must be a non-empty proper subset of the legs");
+    }
+    bool isrow[YASTN_MAX_RANK] = {false};
+    for (int i = 0; i < nrow; ++i) {
+      if (row_legs[i] < 0 || row_legs[i] >= r || isrow[row_legs[i]]) {
+        delete h;
+        return set_error(YASTN_ERR_ARG, "row legs out of range or repeated");
+      }
+      isrow[row_legs[i]] = true;
+      P.row_legs.push_back(row_legs[i]);
+    }
+    for (int i = 0; i < r; ++i)
+      if (!isrow[i]) P.col_legs.push_back(i);
+    // ---- sectors: X = sum over row legs of s_i rho_i; tuples ascending
+    std::map<Key, std::map<Key, std::vector<int64_t>>> rows, cols;
+    std::vector<Key> bx(size_t(T.nblocks)), brk(size_t(T.nblocks)), bck(size_t(T.nblocks));
+    for (int64_t b = 0; b < T.nblocks; ++b) {
+      Key x(ns, 0);
+      for (int c = 0; c < ns; ++c) {
+        int64_t v = 0;
+        for (int l : P.row_legs) v += int64_t(T.sig[l]) * T.q(b, l)[c];
+        x[c] = (int32_t)norm_q(v, T.sym_mod[c]);
+      }
+      Key rk, ck;
+      std::vector<int64_t> rd, cd;
+      for (int l : P.row_legs) {
+        rk.insert(rk.end(), T.q(b, l), T.q(b, l) + ns);
+        rd.push_back(T.dim(b, l));
+      }
+      for (int l : P.col_legs) {
+        ck.insert(ck.end(), T.q(b, l), T.q(b, l) + ns);
+        cd.push_back(T.dim(b, l));
+      }
+      rows[x][rk] = rd;
+      cols[x][ck] = cd;
+      bx[b] = x;
+      brk[b] = rk;
+      bck[b] = ck;
+    }
+    std::map<Key, int> sec_id;
+    for (auto &kv : rows) {
+      SvdPlanImpl::Sector s;
+      s.x = kv.first;
+      for (auto &rv : kv.second) {
+        int64_t sz = 1;
+        for (int64_t d : rv.second) sz *= d;
+        s.rows.push_back({rv.first, rv.second, sz, s.m});
+        s.m += sz;
+      }
+      for (auto &cv : cols[kv.first]) {
+        int64_t sz = 1;
+        for (int64_t d : cv.second) sz *= d;
+        s.cols.push_back({cv.first, cv.second, sz, s.n});
+        s.n += sz;
+      }
+      if (std::max(s.m, s.n) > (int64_t(1) << 15)) {
+        delete h;
+        return set_error(YASTN_ERR_ARG, "sector matrix side above 32768");
+      }
+      sec_id[kv.first] = (int)P.sectors.size();
+      P.sectors.push_back(std::move(s));
+    }
+    // ---- device sector table and workspace layout
+    int64_t welems = 0;
+    int wg = 0;
+    for (auto &s : P.sectors) {
+      DevSvdSector d{};
+      d.trans = s.m < s.n;
+      d.rows = (int32_t)std::max(s.m, s.n);
+      d.cols = (int32_t)std::min(s.m, s.n);
+      int nb = (d.cols + kSvdW - 1) / kSvdW;
+      nb = std::max(2, nb + (nb & 1));
+      d.nb = nb;
+      d.ld = kSvdW * nb;
+      d.w_off = welems;
+      welems += int64_t(d.rows) * d.ld;
+      d.v_off = welems;
+      welems += int64_t(d.ld) * d.ld;
+      d.wg0 = wg;
+      wg += nb / 2;
+      d.sv0 = (int32_t)P.nsv;
+      P.nsv += d.cols;
+      P.max_rounds = std::max(P.max_rounds, nb - 1);
+      P.dsec.push_back(d);
+    }
+    P.total_pairs = wg;
+    const int nsec = (int)P.sectors.size();
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    size_t off = al(size_t(welems) * 8);
+    P.off_sv_raw = off;
+    off += al(size_t(std::max<int64_t>(1, P.nsv)) * 8);
+    P.off_perm = off;
+    off += al(size_t(std::max<int64_t>(1, P.nsv)) * 4);
+    P.off_conv = off;
+    off += al(size_t(std::max(1, nsec)) * 8);
+    P.off_done = off;
+    off += al(size_t(std::max(1, nsec)) * 4);
+    P.off_stat = off;
+    off += al(4 * 8);
+    P.off_flag = off;
+    off += al(8);
+    P.ws_bytes = off;
+    // ---- gather items: one per block of T, W strides per leg
+    std::vector<DevSvdGather> gat;
+    std::vector<DevSvdTile> tiles;
+    for (int64_t b = 0; b < T.nblocks; ++b) {
+      const int k = sec_id.at(bx[b]);
+      const SvdPlanImpl::Sector &s = P.sectors[k];
+      const DevSvdSector &d = P.dsec[k];
+      int64_t ro = -1, co = -1;
+      for (auto &tp : s.rows)
+        if (tp.key == brk[b]) ro = tp.off;
+      for (auto &tp : s.cols)
+        if (tp.key == bck[b]) co = tp.off;
+      DevSvdGather g{};
+      g.t_off = T.offsets[b];
+      g.numel = (int32_t)T.size(b);
+      g.rank = r;
+      // index weights within the block's row (column) of the sector matrix
+      int64_t wrow[YASTN_MAX_RANK] = {0}, wcol[YASTN_MAX_RANK] = {0};
+      int64_t acc = 1;
+      for (int i = (int)P.row_legs.size() - 1; i >= 0; --i) {
+        wrow[P.row_legs[i]] = acc;
+        acc *= T.dim(b, P.row_legs[i]);
+      }
+      acc = 1;
+      for (int i = (int)P.col_legs.size() - 1; i >= 0; --i) {
+        wcol[P.col_legs[i]] = acc;
+        acc *= T.dim(b, P.col_legs[i]);
+      }
+      // M[ro + rowidx][co + colidx]; W = M (row-major, ld) or W = M^T
+      const int64_t ld = d.ld;
+      g.w_base = d.w_off + (d.trans ? co * ld + ro : ro * ld + co);
+      for (int l = 0; l < r; ++l) {
+        g.dim[l] = (int32_t)T.dim(b, l);
+        div_magic((uint32_t)g.dim[l], &g.mag[l], &g.sh[l]);
+        const bool rl = wrow[l] != 0;
+        const int64_t w = rl ? wrow[l] : wcol[l];
+        g.wstr[l] = (rl != (d.trans != 0)) ? w * ld : w;
+      }
+      for (int32_t s0 = 0; s0 < g.numel; s0 += kSvdTile) tiles.push_back(DevSvdTile{(int32_t)gat.size(), s0});
+      gat.push_back(g);
+    }
+    P.ngather = (int)gat.size();
+    P.ntiles = (int)tiles.size();
+    const size_t o_sec = 0, o_gat = al(P.dsec.size() * sizeof(DevSvdSector)),
+                 o_til = o_gat + al(gat.size() * sizeof(DevSvdGather)), tot = o_til + al(tiles.size() * sizeof(DevSvdTile));
+    std::vector<char> host(std::max<size_t>(tot, 256), 0);
+    if (!P.dsec.empty()) std::memcpy(host.data() + o_sec, P.dsec.data(), P.dsec.size() * sizeof(DevSvdSector));
+    if (!gat.empty()) std::memcpy(host.data() + o_gat, gat.data(), gat.size() * sizeof(DevSvdGather));
+    if (!tiles.empty()) std::memcpy(host.data() + o_til, tiles.data(), tiles.size() * sizeof(DevSvdTile));
+    if (hipGetDevice(&P.device) != hipSuccess || hipMalloc(&P.dev_mem, host.size()) != hipSuccess) {
+      (void)hipGetLastError();
+      delete h;
+      return set_error(YASTN_ERR_NOMEM, "device tables of the SVD plan");
+    }
+    char *base = reinterpret_cast<char *>(P.dev_mem);
+    P.d_sec = reinterpret_cast<DevSvdSector *>(base + o_sec);
+    P.d_gather = reinterpret_cast<DevSvdGather *>(base + o_gat);
+    P.d_tiles = reinterpret_cast<DevSvdTile *>(base + o_til);
+    hipStream_t stm = reinterpret_cast<hipStream_t>(hip_stream);
+    if (hipMemcpyAsync(P.dev_mem, host.data(), host.size(), hipMemcpyHostToDevice, stm) != hipSuccess ||
+        hipStreamSynchronize(stm) != hipSuccess) {
+      (void)hipGetLastError();
+      yastn_svd_free(h);
+      return set_error(YASTN_ERR_HIP, "upload of the SVD plan");
+    }
+  } catch (const std::bad_alloc &) {
+    delete h;
+    return set_error(YASTN_ERR_NOMEM, "host allocation");
+  }
+  *out = h;
+  return YASTN_OK;
+}
+
+yastn_status yastn_svd_info(yastn_svd_t h, int32_t *nsectors, int64_t *nsv, size_t *workspace_bytes) {
+  if (!h) return set_error(YASTN_ERR_ARG, "null plan");
+  if (nsectors) *nsectors = (int32_t)h->p.sectors.size();
+  if (nsv) *nsv = h->p.nsv;
+  if (workspace_bytes) *workspace_bytes = h->p.ws_bytes;
+  return YASTN_OK;
+}
+
+yastn_status yastn_svd_sector(yastn_svd_t h, int32_t k, int32_t *charge, int64_t *m, int64_t *n, int64_t *sv0) {
+  if (!h) return set_error(YASTN_ERR_ARG, "null plan");
+  if (k < 0 || k >= (int32_t)h->p.sectors.size()) return set_error(YASTN_ERR_ARG, "sector index out of range");
+  const auto &s = h->p.sectors[k];
+  if (charge)
+    for (size_t c = 0; c < s.x.size(); ++c) charge[c] = s.x[c];
+  if (m) *m = s.m;
+  if (n) *n = s.n;
+  if (sv0) *sv0 = h->p.dsec[k].sv0;
+  return YASTN_OK;
+}
+
+yastn_status yastn_svd(yastn_svd_t h, const void *t, int32_t chi, double tol, double deg_tol, double *sv,
+                       int32_t *kept, int32_t *sweeps, void *workspace, void *hip_stream) {
+  if (!h || !kept || (h->p.nsv > 0 && (!t || !sv || !workspace))) return set_error(YASTN_ERR_ARG, "null argument");
+  if (chi < 0 || !(tol >= 0.0) || !(deg_tol >= 0.0)) return set_error(YASTN_ERR_ARG, "chi, tol and deg_tol must be >= 0");
+  if (reinterpret_cast<uintptr_t>(workspace) & 255u) return set_error(YASTN_ERR_ARG, "workspace must be 256-byte aligned");
+  SvdPlanImpl &P = h->p;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const int nsec = (int)P.sectors.size();
+  P.have_kept = false;
+  P.kept.assign(size_t(nsec), 0);
+  if (sweeps) *sweeps = 0;
+  if (nsec == 0) return YASTN_OK;
+  char *ws = reinterpret_cast<char *>(workspace);
+  double *W = reinterpret_cast<double *>(ws);
+  double *sv_raw = reinterpret_cast<double *>(ws + P.off_sv_raw);
+  int32_t *perm = reinterpret_cast<int32_t *>(ws + P.off_perm);
+  unsigned long long *conv = reinterpret_cast<unsigned long long *>(ws + P.off_conv);
+  int32_t *done = reinterpret_cast<int32_t *>(ws + P.off_done);
+  double *stat = reinterpret_cast<double *>(ws + P.off_stat);
+  int32_t *flag = reinterpret_cast<int32_t *>(ws + P.off_flag);
+  // ---- W = fused sector matrices, V = I, no sector done
+  hipLaunchKernelGGL(k_svd_init, dim3(64, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, W);
+  hipLaunchKernelGGL(k_svd_sweep_begin, dim3(grid1(nsec, 256)), dim3(256), 0, st, conv, done, nsec);
+  if (P.ntiles > 0)
+    hipLaunchKernelGGL(k_svd_gather, dim3(std::min(P.ntiles, 65535)), dim3(256), 0, st, P.d_gather, P.d_tiles,
+                       P.ntiles, reinterpret_cast<const double *>(t), W);
+  SVD_HIP(hipGetLastError());
+  // ---- sweeps of rounds until every sector is converged
+  SvdRoundArgs ra{};
+  ra.sec = P.d_sec;
+  ra.ws = W;
+  ra.conv = conv;
+  ra.done = done;
+  ra.nsec = nsec;
+  const double eps = 2.220446049250313e-16;
+  const double eps_scale = 64.0 * eps;  // convergence: off <= max(1e-14, 64 eps sqrt(rows))
+  ra.rot_tol = 4.0 * eps;
+  int32_t all = 0;
+  int sw = 0;
+  for (; sw < kSvdMaxSweeps && !all; ++sw) {
+    hipLaunchKernelGGL(k_svd_sweep_begin, dim3(grid1(nsec, 256)), dim3(256), 0, st, conv, (int32_t *)nullptr, nsec);
+    for (int rr = 0; rr < P.max_rounds; ++rr) {
+      ra.round = rr;
+      hipLaunchKernelGGL(k_svd_round, dim3(P.total_pairs), dim3(256), 0, st, ra);
+    }
+    hipLaunchKernelGGL(k_svd_sweep_end, dim3(1), dim3(256), 0, st, conv, done, nsec, P.d_sec, eps_scale, flag);
+    SVD_HIP(hipGetLastError());
+    SVD_HIP(hipMemcpyAsync(&all, flag, 4, hipMemcpyDeviceToHost, st));
+    SVD_HIP(hipStreamSynchronize(st));
+  }
+  P.sweeps = sw;
+  if (sweeps) *sweeps = sw;
+  if (!all) return set_error(YASTN_ERR_STATE, "Jacobi sweeps did not converge");
+  // ---- singular values, sorted per sector; global truncation
+  hipLaunchKernelGGL(k_svd_norms, dim3(16, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, W, sv_raw);
+  hipLaunchKernelGGL(k_svd_sort, dim3(std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, sv_raw, sv, perm);
+  hipLaunchKernelGGL(k_svd_stats, dim3(1), dim3(1024), 0, st, sv, (int)P.nsv, tol, stat);
+  hipLaunchKernelGGL(k_svd_cut, dim3(grid1(P.nsv, 256)), dim3(256), 0, st, sv, (int)P.nsv, chi, deg_tol, stat);
+  int32_t *dkept = reinterpret_cast<int32_t *>(ws + P.off_done);  // done[] is free again
+  hipLaunchKernelGGL(k_svd_kept, dim3(grid1(nsec, 256)), dim3(256), 0, st, P.d_sec, nsec, sv, stat, dkept);
+  SVD_HIP(hipGetLastError());
+  SVD_HIP(hipMemcpyAsync(P.kept.data(), dkept, size_t(nsec) * 4, hipMemcpyDeviceToHost, st));
+  SVD_HIP(hipStreamSynchronize(st));
+  std::memcpy(kept, P.kept.data(), size_t(nsec) * 4);
+  P.have_kept = true;
+  // ---- output structures for these kept counts
+  const HostTensor &T = P.t;
+  const int ns = T.nsym;
+  P.u_sig.clear();
+  P.v_sig.clear();
+  for (int l : P.row_legs) P.u_sig.push_back(T.sig[l]);
+  P.u_sig.push_back(-1);
+  P.v_sig.push_back(1);
+  for (int l : P.col_legs) P.v_sig.push_back(T.sig[l]);
+  P.u_n.assign(size_t(ns), 0);
+  P.v_n.assign(T.n, T.n + ns);
+  struct Blk {
+    Key key;
+    std::vector<int64_t> shape;
+    DevSvdOut o;
+  };
+  std::vector<Blk> ub, vb;
+  for (int k = 0; k < nsec; ++k) {
+    const int32_t tk = P.kept[k];
+    if (tk == 0) continue;
+    const auto &s = P.sectors[k];
+    const DevSvdSector &d = P.dsec[k];
+    // U = W (normalised) or V (transposed sector); V^T's source the other
+    const int64_t usrc = d.trans ? d.v_off : d.w_off, vsrc = d.trans ? d.w_off : d.v_off;
+    for (auto &tp : s.rows) {
+      Blk b;
+      b.key = tp.key;
+      b.key.insert(b.key.end(), s.x.begin(), s.x.end());
+      b.shape = tp.dims;
+      b.shape.push_back(tk);
+      b.o = DevSvdOut{0, usrc + tp.off * d.ld, (int32_t)tp.size, tk, d.ld, d.sv0, 0, 0};
+      ub.push_back(std::move(b));
+    }
+    for (auto &tp : s.cols) {
+      Blk b;
+      b.key = s.x;
+      b.key.insert(b.key.end(), tp.key.begin(), tp.key.end());
+      b.shape.push_back(tk);
+      b.shape.insert(b.shape.end(), tp.dims.begin(), tp.dims.end());
+      b.o = DevSvdOut{0, vsrc + tp.off * d.ld, tk, (int32_t)tp.size, d.ld, d.sv0, 1, 0};
+      vb.push_back(std::move(b));
+    }
+  }
+  auto lay = [&](std::vector<Blk> &bs, std::vector<int32_t> &q, std::vector<int64_t> &sh, std::vector<int64_t> &of,
+                 int64_t &numel) {
+    std::sort(bs.begin(), bs.end(), [](const Blk &x, const Blk &y) { return x.key < y.key; });
+    q.clear();
+    sh.clear();
+    of.clear();
+    numel = 0;
+    for (auto &b : bs) {
+      q.insert(q.end(), b.key.begin(), b.key.end());
+      sh.insert(sh.end(), b.shape.begin(), b.shape.end());
+      of.push_back(numel);
+      b.o.out_off = numel;
+      numel += int64_t(b.o.a) * b.o.b;
+    }
+  };
+  lay(ub, P.u_q, P.u_sh, P.u_off, P.u_numel);
+  lay(vb, P.v_q, P.v_sh, P.v_off, P.v_numel);
+  P.outs.clear();
+  for (auto &b : ub) P.outs.push_back(b.o);
+  for (auto &b : vb) P.outs.push_back(b.o);
+  // Charge tuples are compared as stored (normalised); ascending order.
+  if (P.out_mem) {
+    (void)hipFree(P.out_mem);
+    P.out_mem = nullptr;
+  }
+  if (!P.outs.empty()) {
+    if (hipMalloc(&P.out_mem, P.outs.size() * sizeof(DevSvdOut)) != hipSuccess) {
+      (void)hipGetLastError();
+      return set_error(YASTN_ERR_NOMEM, "output table of the SVD");
+    }
+    SVD_HIP(hipMemcpyAsync(P.out_mem, P.outs.data(), P.outs.size() * sizeof(DevSvdOut), hipMemcpyHostToDevice, st));
+    SVD_HIP(hipStreamSynchronize(st));
+  }
+  return YASTN_OK;
+}
+
+yastn_status yastn_svd_output(yastn_svd_t h, yastn_tensor_desc *u, int64_t *u_numel, yastn_tensor_desc *vt,
+                              int64_t *vt_numel) {
+  if (!h) return set_error(YASTN_ERR_ARG, "null plan");
+  SvdPlanImpl &P = h->p;
+  if (!P.have_kept) return set_error(YASTN_ERR_STATE, "no yastn_svd result yet");
+  const int ns = P.t.nsym;
+  if (u) {
+    u->rank = (int32_t)P.u_sig.size();
+    u->nsym = ns;
+    u->sym_mod = P.t.sym_mod;
+    u->sig = P.u_sig.data();
+    u->n = P.u_n.data();
+    u->nblocks = (int64_t)P.u_off.size();
+    u->charges = P.u_q.data();
+    u->shapes = P.u_sh.data();
+    u->offsets = P.u_off.data();
+  }
+  if (u_numel) *u_numel = P.u_numel;
+  if (vt) {
+    vt->rank = (int32_t)P.v_sig.size();
+    vt->nsym = ns;
+    vt->sym_mod = P.t.sym_mod;
+    vt->sig = P.v_sig.data();
+    vt->n = P.v_n.data();
+    vt->nblocks = (int64_t)P.v_off.size();
+    vt->charges = P.v_q.data();
+    vt->shapes = P.v_sh.data();
+    vt->offsets = P.v_off.data();
+  }
+  if (vt_numel) *vt_numel = P.v_numel;
+  return YASTN_OK;
+}
+
+yastn_status yastn_svd_factors(yastn_svd_t h, void *u, void *vt, const void *workspace, void *hip_stream) {
+  if (!h) return set_error(YASTN_ERR_ARG, "null plan");
+  SvdPlanImpl &P = h->p;
+  if (!P.have_kept) return set_error(YASTN_ERR_STATE, "no yastn_svd result yet");
+  if ((P.u_numel > 0 && !u) || (P.v_numel > 0 && !vt) || (!P.outs.empty() && !workspace))
+    return set_error(YASTN_ERR_ARG, "null buffer");
+  if (P.outs.empty()) return YASTN_OK;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const char *ws = reinterpret_cast<const char *>(workspace);
+  hipLaunchKernelGGL(k_svd_write, dim3(std::min<int>((int)P.outs.size(), 65535)), dim3(256), 0, st,
+                     reinterpret_cast<const DevSvdOut *>(P.out_mem), (int)P.outs.size(),
+                     reinterpret_cast<const double *>(ws), reinterpret_cast<const int32_t *>(ws + P.off_perm),
+                     reinterpret_cast<double *>(u), reinterpret_cast<double *>(vt));
+  SVD_HIP(hipGetLastError());
+  return YASTN_OK;
+}
+
+void yastn_svd_free(yastn_svd_t h) {
+  if (!h) return;
+  if (h->p.dev_mem) (void)hipFree(h->p.dev_mem);
+  if (h->p.out_mem) (void)hipFree(h->p.out_mem);
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,137 @@
+"""Parity of the block-sparse truncated SVD (yastn_svd_*) with the oracle
+(oracle/svd.py): every singular value of every sector within 1e-12 of the
+largest, the kept counts exactly, the kept factors' structure bit for bit,
+the truncated product U_X diag(S_X) V_X^T of every sector within 1e-11, and
+orthonormal kept columns.  Singular vectors are unique up to sign (and
+rotations inside a multiplet), so the vectors are compared through that
+product, which the truncation rule keeps unique (it never splits a multiplet).
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import svd as OS
+import workloads as W
+from tests.test_oracle_svd import CASES, _random_tensor
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU hosts deselect -m gpu
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2405_12196_amd as Y  # noqa: E402
+from tests import gpu_util as G  # noqa: E402
+
+
+def gpu_svd(t, rows, chi, tol=0.0, deg_tol=1e-10):
+    sv = Y.Svd(t, rows)
+    tdev = G.upload(t)
+    ws = torch.empty(max(256, sv.workspace_bytes), dtype=torch.uint8, device=G.DEV)
+    svals = torch.full((max(1, sv.nsv),), float("nan"), dtype=torch.float64, device=G.DEV)
+    kept, sweeps = sv.run(tdev, svals, ws, chi, tol, deg_tol)
+    us, vs = sv.output()
+    u = torch.full((max(1, us.numel),), float("nan"), dtype=torch.float64, device=G.DEV)
+    vt = torch.full((max(1, vs.numel),), float("nan"), dtype=torch.float64, device=G.DEV)
+    sv.factors(u, vt, ws)
+    torch.cuda.synchronize()
+    return sv, svals.cpu().numpy()[:sv.nsv], kept, sweeps, (us, u.cpu().numpy()[:us.numel]), \
+        (vs, vt.cpu().numpy()[:vs.numel])
+
+
+def _blocks(s, vals):
+    out = {}
+    for b in range(s.nblocks):
+        key = tuple(tuple(int(v) for v in s.charges[b, l]) for l in range(s.charges.shape[1]))
+        o, sh = int(s.offsets[b]), tuple(int(x) for x in s.shapes[b])
+        out[key] = vals[o:o + int(np.prod(sh))].reshape(sh)
+    return out
+
+
+def check_svd(t, rows, chi, tol=0.0, deg_tol=1e-10, tol_sv=1e-12, tol_rec=1e-11):
+    sv, svals, kept, sweeps, (us, u), (vs, vt) = gpu_svd(t, rows, chi, tol, deg_tol)
+    mats = OS.sector_matrices(t, rows)
+    dec = OS.svd_sectors(t, rows)
+    assert [X for X, *_ in sv.sectors] == list(mats), "sector order differs from the oracle"
+    smax = max(float(d[1][0]) for d in dec.values())
+    # every singular value
+    for (X, m, n, s0), (Xr, (M, rl, cl)) in zip(sv.sectors, mats.items()):
+        assert (m, n) == M.shape
+        ref = dec[X][1]
+        got = svals[s0:s0 + min(m, n)]
+        assert np.all(np.diff(got) <= 0), f"sector {X}: not descending"
+        err = float(np.max(np.abs(got - ref)))
+        assert err <= tol_sv * smax, f"sector {X}: singular values off by {err:.3e} (max {smax:.3e})"
+    # kept counts: the oracle's rule on the oracle's values
+    ref_kept = OS.truncation({X: d[1] for X, d in dec.items()}, chi, tol, deg_tol)
+    assert kept == [ref_kept[X] for X in mats], "kept counts differ"
+    # structure of the factors
+    u_ref, S_ref, vt_ref, _ = OS.svd_truncated(t, rows, chi, tol, deg_tol)
+    assert G.structure_equal(us, u_ref), "U structure differs"
+    assert G.structure_equal(vs, vt_ref), "V^T structure differs"
+    ub, vb = _blocks(us, u), _blocks(vs, vt)
+    for k, (X, (M, rl, cl)) in enumerate(mats.items()):
+        kx = kept[k]
+        if kx == 0:
+            continue
+        Uk = np.concatenate([ub[tuple(key) + (X,)].reshape(-1, kx) for key, dims, o in rl], axis=0)
+        Vk = np.concatenate([vb[(X,) + tuple(key)].reshape(kx, -1) for key, dims, o in cl], axis=1)
+        s0 = sv.sectors[k][3]
+        Sk = svals[s0:s0 + kx]
+        U, s, Vt = dec[X]
+        ref = (U[:, :kx] * s[:kx]) @ Vt[:kx]
+        got = (Uk * Sk) @ Vk
+        den = max(float(np.linalg.norm(ref)), 1e-300)
+        assert float(np.linalg.norm(got - ref)) / den <= tol_rec, f"sector {X}: truncated product"
+        assert np.allclose(Uk.T @ Uk, np.eye(kx), atol=tol_rec)
+        assert np.allclose(Vk @ Vk.T, np.eye(kx), atol=tol_rec)
+    return sv, kept, sweeps
+
+
+@pytest.mark.parametrize("seed,sym,rank,rows,n", CASES)
+def test_svd_small_random(seed, sym, rank, rows, n):
+    t = _random_tensor(seed, sym, rank, n)
+    total = sum(min(M.shape) for M, _, _ in OS.sector_matrices(t, rows).values())
+    for chi in (0, 1, max(1, total // 2), total, total + 5):
+        check_svd(t, rows, chi)
+
+
+def test_svd_wide_and_tall_sectors_and_tol():
+    """Sectors with fewer rows than columns (stored transposed) next to tall
+    ones, several column blocks of 8 (dims up to 40), and a tol floor."""
+    from workloads import Leg, rand
+    l1 = Leg(1, ((-1,), (0,), (1,)), (3, 9, 2))
+    l2 = Leg(1, ((0,), (1,)), (5, 4))
+    l3 = Leg(-1, ((-1,), (0,), (1,), (2,)), (7, 11, 6, 3))
+    t = rand([l1, l2, l3], (0,), (0,), 909)
+    for rows in ((0, 1), (2,), (0,), (1, 2)):
+        check_svd(t, rows, chi=17)
+        check_svd(t, rows, chi=1000, tol=1e-2)
+
+
+def test_svd_ctm_corner_chi128():
+    """The chi = 128, D = 8 enlarged corner (the oracle's chain output) split
+    as rows (r1, A_r, A*_r) x columns (bot4, A_b, A*_b): 51 sectors up to
+    924 x 924, truncated to chi = 128."""
+    from bench import STEPS
+    t = W.ctm()
+    cur = None
+    for (an, bn), (ax, bx) in zip(STEPS, t["axes"]):
+        cur = oracle.tensordot_blockpair(t[an] if an else cur, t[bn], ax, bx)
+    dec = OS.svd_sectors(cur, (0, 3, 5))
+    allv = np.sort(np.concatenate([d[1] for d in dec.values()]))[::-1]
+    assert (allv[127] - allv[128]) / allv[127] > 1e-6  # a clean cut: the kept set is unique
+    sv, kept, sweeps = check_svd(cur, (0, 3, 5), chi=128)
+    assert sum(kept) == 128
+    print(f"corner SVD: {sv.nsectors} sectors, {sv.nsv} values, {sweeps} sweeps", flush=True)
+
+
+def test_svd_repeat_bitwise():
+    """Two runs on the same input give the same bits (no atomics in the
+    arithmetic, fixed reduction orders)."""
+    t = _random_tensor(5, "U1", 5, None)
+    a = gpu_svd(t, (4, 0), 10)
+    b = gpu_svd(t, (4, 0), 10)
+    assert np.array_equal(a[1], b[1]) and a[2] == b[2]
+    assert np.array_equal(a[4][1], b[4][1]) and np.array_equal(a[5][1], b[5][1])
