@@ -467,6 +467,49 @@ def grad_section(torch, Y, W, ev, sp):
     return res
 
 
+def svd_section(torch, Y, last, last_struct, sp, chi=128, reps=5):
+    """The CTM truncation of the chi = 128 step's output (the enlarged corner,
+    FP64): rows (r1, A_r, A*_r) x columns (bot4, A_b, A*_b), block-sparse SVD
+    on the GPU (yastn_svd: fuse, Jacobi sweeps, sort, global truncation to
+    chi) and the kept factors (yastn_svd_factors); median wall time of
+    ``reps`` runs on resident data, synchronised (the SVD syncs per sweep)."""
+    rows = (0, 3, 5)
+    sv = Y.Svd(last_struct, rows, stream=sp)
+    ws = torch.empty(max(256, sv.workspace_bytes), dtype=torch.uint8, device="cuda:0")
+    svals = torch.empty(max(1, sv.nsv), dtype=torch.float64, device="cuda:0")
+    kept, sweeps = sv.run(last, svals, ws, chi, stream=sp)
+    us, vs = sv.output()
+    u = torch.empty(max(1, us.numel), dtype=torch.float64, device="cuda:0")
+    vt = torch.empty(max(1, vs.numel), dtype=torch.float64, device="cuda:0")
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kept, sweeps = sv.run(last, svals, ws, chi, stream=sp)
+        sv.factors(u, vt, ws, stream=sp)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    ms = float(np.median(times))
+    # MFMA work of the sweeps: per block pair and round, the 16 x 16 Gram
+    # matrix over the W rows and the rotation of W's and V's 16 columns
+    flop = 0.0
+    for X, m, n, s0 in sv.sectors:
+        r, c = max(m, n), min(m, n)
+        nb = max(2, -(-c // 8))
+        nb += nb & 1
+        per_round = (nb // 2) * 2.0 * 16 * 16 * (2 * r + c)
+        flop += per_round * (nb - 1) * sweeps
+    dims = sorted(((max(m, n), min(m, n)) for _, m, n, _ in sv.sectors), reverse=True)
+    res = {"ms": round(ms, 3), "sweeps": sweeps, "sectors": sv.nsectors, "singular_values": sv.nsv,
+           "largest_sectors": dims[:4], "chi": chi, "kept": int(sum(kept)),
+           "jacobi_mfma_GFLOP": round(flop / 1e9, 2), "jacobi_mfma_TFs": round(flop / (ms * 1e-3) / 1e12, 3),
+           "frac_of_fp64_mfma_peak": round(flop / (ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFS, 4),
+           "timing": f"median of {reps} synchronised runs (fuse, sweeps, sort, truncation, factors)"}
+    del sv, ws, svals, u, vt
+    torch.cuda.empty_cache()
+    return res
+
+
 def serving_section(torch, Y, W, sp, nreq=64, budget_gib=32, seed=5):
     """32 concurrent CTM runs (16 Z2, 16 U(1); D in {4,6,8,10} x chi in
     {64,128,192,256}) submit enlarged-corner requests with Poisson arrivals to
@@ -554,6 +597,8 @@ def main():
     ap.add_argument("--batch-only", default="", choices=["", "u1_d18_x64", "u1_d18_x512", "u1_uneven_x64"],
                     help="run only this grouped launch (autotuned, then --steps launches) and print its time; "
                          "for profiling")
+    ap.add_argument("--svd-only", action="store_true",
+                    help="run only the truncated SVD of the chi = 128 corner and print its record; for profiling")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -598,6 +643,14 @@ def main():
         print(json.dumps({"batch": args.batch_only, "variant": pl.variant_id, "us_per_launch_host": round(us, 2),
                           "useful_flop": flop, "launches": args.steps,
                           "autotune_ms": [round(x, 4) for x in tune_ms]}))
+        return
+    if args.svd_only:
+        sp = int(torch.cuda.current_stream().cuda_stream)
+        t = W.ctm()
+        ch = Chain(torch, Y, t, tune=False, sp=sp)
+        ch.step(sp)
+        torch.cuda.synchronize()
+        print(json.dumps({"svd": svd_section(torch, Y, ch.outs[-1], ch.plans[-1].output(0), sp)}))
         return
     dev = "cuda:0"
     torch.cuda.set_device(0)
@@ -795,6 +848,7 @@ def main():
         extras = {"precision": precision_section(torch, Y, W, ev, sp, max(10, K // 10), plain["value"] if plain else None),
                   "batched": batch_section(torch, Y, W, ev, sp),
                   "gradient": grad_section(torch, Y, W, ev, sp),
+                  "svd": svd_section(torch, Y, outs[-1], plans[-1].output(0), sp),
                   "serving": serving_section(torch, Y, W, sp, nreq=args.serve_requests)}
 
     rec = {

@@ -56,7 +56,7 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 
 constexpr int kSvdW = 8;           // columns per block (a block pair is 16 columns: one MFMA tile)
 constexpr int kSvdMaxSweeps = 40;  // outer sweeps before giving up
-constexpr int kSvdInnerSweeps = 4; // cyclic Jacobi sweeps on a pair's 16 x 16 Gram matrix
+constexpr int kSvdInnerSweeps = 1; // cyclic Jacobi sweeps on a pair's 16 x 16 Gram matrix per round
 
 struct DevSvdSector {
   int64_t w_off;   // W: rows x ld, row-major, elements from the workspace base
@@ -174,22 +174,22 @@ __global__ void __launch_bounds__(256) k_svd_round(SvdRoundArgs a) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int c16 = lane & 15, kq = lane >> 4;
   auto colof = [&](int c) { return c < kSvdW ? kSvdW * P + c : kSvdW * Q + c - kSvdW; };
-  // ---- Gram matrix of the 16 columns: wave w takes rows 4w.. in steps of 16
+  // ---- Gram matrix of the 16 columns: wave w takes the 4-row groups w,
+  // w + 4, ...; eight groups' loads are issued before their MFMAs (row
+  // indices clamped, values past the last row zeroed after the load, so no
+  // load sits under a branch)
   {
     const int col = colof(c16);
     d4v acc = {0, 0, 0, 0};
-    int r0 = 4 * wid;
-    for (; r0 + 51 < S.rows; r0 += 64) {  // four independent loads in flight
-      double x[4];
+    for (int r0 = 4 * wid; r0 < S.rows; r0 += 16 * 8) {
+      double x[8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = W[(int64_t)(r0 + 16 * u + kq) * S.ld + col];
+      for (int u = 0; u < 8; ++u) x[u] = W[(int64_t)min(r0 + 16 * u + kq, S.rows - 1) * S.ld + col];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], x[u], acc, 0, 0, 0);
-    }
-    for (; r0 < S.rows; r0 += 16) {
-      const int r = r0 + kq;
-      const double x = r < S.rows ? W[(int64_t)r * S.ld + col] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, acc, 0, 0, 0);
+      for (int u = 0; u < 8; ++u) {
+        const double xv = r0 + 16 * u + kq < S.rows ? x[u] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, xv, acc, 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) gpart[wid][kq + 4 * v][c16] = acc[v];
@@ -224,8 +224,14 @@ __global__ void __launch_bounds__(256) k_svd_round(SvdRoundArgs a) {
       for (int sw = 0; sw < kSvdInnerSweeps; ++sw) {
         int applied = 0;
         for (int rr = 0; rr < 15; ++rr) {
-          int i, j;
-          rr_pair(16, rr, rot, i, j);
+          // round-robin pair of 16 indices without a division
+          int i = 15, j = rr;
+          if (rot != 0) {
+            i = rr + rot;
+            i -= i >= 15 ? 15 : 0;
+            j = rr - rot;
+            j += j < 0 ? 15 : 0;
+          }
           const double gii = g[i][i], gjj = g[j][j], gij = g[i][j];
           double c = 1.0, s = 0.0;
           const double d = gii * gjj;
@@ -281,27 +287,40 @@ __global__ void __launch_bounds__(256) k_svd_round(SvdRoundArgs a) {
   double qb[4];
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) qb[kk] = q[4 * kk + kq][c16];
-  auto rotate = [&](double *X, int nrows) {
-    const int cout = colof(c16);
-    for (int r0 = 16 * wid; r0 < nrows; r0 += 64) {
-      const int ra = r0 + c16;
-      double x[4];
+  // W's rows, then V's rows (the same row stride), in 16-row chunks: four
+  // chunks of a wave in flight at once (clamped loads; stores past the last
+  // row skipped), so V's loads overlap W's
+  const int nw = S.rows, nt = S.rows + S.cols;
+  const int cout = colof(c16);
+  int cin[4];
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) x[kk] = ra < nrows ? X[(int64_t)ra * S.ld + colof(4 * kk + kq)] : 0.0;
-      d4v acc = {0, 0, 0, 0};
+  for (int kk = 0; kk < 4; ++kk) cin[kk] = colof(4 * kk + kq);
+  auto rowptr = [&](int r) { return r < nw ? W + (int64_t)r * S.ld : V + (int64_t)(r - nw) * S.ld; };
+  for (int rb = 16 * wid; rb < nt; rb += 64 * 4) {
+    double x[4][4];
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[kk], qb[kk], acc, 0, 0, 0);
-      // every lane has read its rows before any lane of the wave writes them
-      __builtin_amdgcn_wave_barrier();
+    for (int u = 0; u < 4; ++u) {
+      const double *src = rowptr(min(rb + 64 * u + c16, nt - 1));
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) x[u][kk] = src[cin[kk]];
+    }
+    d4v acc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      acc[u] = d4v{0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u][kk], qb[kk], acc[u], 0, 0, 0);
+    }
+    // every lane has read its rows before any lane of the wave writes them
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = r0 + kq + 4 * v;
-        if (r < nrows) X[(int64_t)r * S.ld + cout] = acc[v];
+        const int r = rb + 64 * u + kq + 4 * v;
+        if (r < nt) rowptr(r)[cout] = acc[u][v];
       }
-    }
-  };
-  rotate(W, S.rows);
-  rotate(V, S.cols);
+  }
 }
 
 // conv[k] = 0 (every sweep); done[k] = 0 too when done is given (first sweep)
