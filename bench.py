@@ -467,6 +467,52 @@ def grad_section(torch, Y, W, ev, sp):
     return res
 
 
+SPLIT = ("validate", "join", "host_tables", "upload")
+
+
+def plan_costs(torch, Y, W, descs, plans, first_ms, sp, tile_rows, reps=5):
+    """Planning cost of the four corner contractions: the first plans (code
+    objects loaded then, the structure cache empty), the same requests again
+    (structure-cache hits: a CTM iteration after the first), and afresh with
+    the cache bypassed (median of reps), each split into validation, the
+    device join, the host tables and the upload; then the same at chi = 256."""
+    def split(pls):
+        tot = [0.0] * 4
+        for pl in pls:
+            for i, v in enumerate(pl.profile()[0]):
+                tot[i] += v
+        return {k: round(v, 3) for k, v in zip(SPLIT, tot)}
+
+    def timed(ds, flags):
+        t0 = time.perf_counter()
+        pls = [Y.plan([d], stream=sp, tile_rows=tile_rows, flags=flags) for d in ds]
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3, pls
+
+    rec = {"first_ms": round(first_ms, 2), "first_split_ms": split(plans)}
+    cached = [timed(descs, 0) for _ in range(reps)]
+    rec["cached_ms"] = round(float(np.median([c[0] for c in cached])), 3)
+    rec["cached_hits"] = all(pl.profile()[1] for pl in cached[-1][1])
+    fresh = [timed(descs, Y.FLAG_NOCACHE) for _ in range(reps)]
+    k = int(np.argsort([f[0] for f in fresh])[reps // 2])
+    rec["uncached_ms"] = round(fresh[k][0], 2)
+    rec["uncached_split_ms"] = split(fresh[k][1])
+    t = W.ctm_chi256()
+    d256, cur = [], None
+    for (an, bn), (ax, bx) in zip(STEPS, t["axes"]):
+        a = t[an] if an else cur
+        pl = Y.plan([(a, t[bn], ax, bx)], stream=sp, flags=Y.FLAG_NOCACHE)
+        d256.append((a, t[bn], ax, bx))
+        cur = pl.output(0)
+    f256 = [timed(d256, Y.FLAG_NOCACHE) for _ in range(3)]
+    k = int(np.argsort([f[0] for f in f256])[1])
+    rec["chi256_uncached_ms"] = round(f256[k][0], 2)
+    rec["chi256_uncached_split_ms"] = split(f256[k][1])
+    rec["what"] = ("four single-problem plans; first = cold process; cached = the same requests again "
+                   "(structure cache); uncached = planned afresh (FLAG_NOCACHE), median")
+    return rec
+
+
 def svd_section(torch, Y, last, last_struct, sp, chi=128, reps=5):
     """The CTM truncation of the chi = 128 step's output (the enlarged corner,
     FP64): rows (r1, A_r, A*_r) x columns (bot4, A_b, A*_b), block-sparse SVD
@@ -510,11 +556,13 @@ def svd_section(torch, Y, last, last_struct, sp, chi=128, reps=5):
     return res
 
 
-def serving_section(torch, Y, W, sp, nreq=64, budget_gib=32, seed=5):
+def serving_section(torch, Y, W, sp, nreq=2000, warm=200, budget_gib=32, seed=5):
     """32 concurrent CTM runs (16 Z2, 16 U(1); D in {4,6,8,10} x chi in
     {64,128,192,256}) submit enlarged-corner requests with Poisson arrivals to
     the continuous-batching server (HBM budget for intermediates); the rate is
-    0.7x the closed-loop saturation rate of a calibration pass."""
+    0.7x the closed-loop saturation rate of a calibration pass.  ``warm``
+    requests first, then ``nreq`` measured ones (latency percentiles and
+    throughput over those)."""
     runs = []
     for r in range(32):
         t = W.serving_run(r)
@@ -546,33 +594,105 @@ def serving_section(torch, Y, W, sp, nreq=64, budget_gib=32, seed=5):
     sat = 32 / (time.perf_counter() - t0)           # requests per second
     lam = 0.7 * sat
     rng = np.random.default_rng(seed)
-    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=nreq))
-    which = rng.integers(0, 32, size=nreq)
+    ntot = warm + nreq
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=ntot))
+    which = rng.integers(0, 32, size=ntot)
     ids, flop = [], 0.0
+    queued_at_submit = []
     torch.cuda.synchronize()
+    st0 = srv.stats()
     base = time.perf_counter()
+    t_meas = None
     k = 0
-    while k < nreq or srv.stats()["completed"] < srv.stats()["submitted"]:
+    while k < ntot or srv.stats()["completed"] < srv.stats()["submitted"]:
         now = time.perf_counter() - base
-        while k < nreq and arrivals[k] <= now:
-            ids.append(submit(int(which[k])))
-            flop += runs[int(which[k])]["flops"]
+        while k < ntot and arrivals[k] <= now:
+            if k == warm:
+                t_meas = time.perf_counter()
+                st0 = srv.stats()
+            rid = submit(int(which[k]))
+            if k >= warm:
+                ids.append(rid)
+                flop += runs[int(which[k])]["flops"]
+                queued_at_submit.append(srv.stats()["queued"])
             k += 1
         srv.step()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - base
+    wall = time.perf_counter() - (t_meas if t_meas is not None else base)
     lat = np.array([srv.query(i)[1] for i in ids])
     st = srv.stats()
     srv.close()
     del runs
     torch.cuda.empty_cache()
-    return {"requests": nreq, "runs": 32, "arrival_rate_per_s": round(lam, 2),
+    q = np.array(queued_at_submit)
+    return {"requests": nreq, "warmup_requests": warm, "runs": 32, "arrival_rate_per_s": round(lam, 2),
             "saturation_rate_per_s": round(sat, 2), "hbm_budget_GiB": budget_gib,
             "useful_TFs": round(flop / wall / 1e12, 3), "wall_s": round(wall, 3),
             "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
-            "max_steps_per_launch": int(st["max_batch"]), "launches": int(st["ticks"]),
+            "max_steps_per_launch": int(st["max_batch"]), "launches": int(st["ticks"] - st0["ticks"]),
+            "admitted": int(st["admitted"] - st0["admitted"]), "completed": int(st["completed"] - st0["completed"]),
+            "bypasses": int(st["bypasses"] - st0["bypasses"]), "queued_peak": int(st["queued_peak"]),
+            "queued_at_submit_p50": float(np.percentile(q, 50)), "queued_at_submit_max": int(q.max()),
             "pool_peak_GiB": round(st["pool_peak"] / 2 ** 30, 2),
-            "latency": "submit to the host observing the completion event"}
+            "latency": "submit to the host observing the completion event; percentiles over the measured requests",
+            "admission": "arrival order; a request that fits may pass a waiting one at most 16 times"}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(t, useful, reps):
+    """The oracle on the host cores (the only place the benchmark runs it)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    import oracle
+    import workloads as W
+
+    def o2_step():
+        cur = None
+        for (an, bn), (ax, bx) in zip(STEPS, t["axes"]):
+            cur = oracle.tensordot_blockpair(t[an] if an else cur, t[bn], ax, bx)
+        oracle.norms(cur)
+
+    def med(fn, n):
+        ts = []
+        for _ in range(n):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    with threadpool_limits(1):
+        s1 = med(o2_step, reps)
+    with threadpool_limits(ncpu):
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        sall = med(o2_step, reps)
+        (p1,) = W.u1_d18()
+        f1 = 2199168.0
+        d1 = med(lambda: oracle.tensordot_dense(p1.a, p1.b, p1.axes_a, p1.axes_b), reps)
+
+        def o1_step():
+            cur = None
+            for (an, bn), (ax, bx) in zip(STEPS, t["axes"]):
+                cur = oracle.tensordot_dense(t[an] if an else cur, t[bn], ax, bx)
+        d2 = med(o1_step, 1)
+    return {"value": round(useful / sall / 1e12, 6), "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"median of {reps} full enlarged-corner steps (4 block-pair tensordots + norm, chi = 128, "
+                      f"D = 8) at {threads} BLAS threads: {sall * 1e3:.0f} ms per step",
+            "cpu_model": _cpu_model(), "host_cpus": ncpu,
+            "o2_one_thread": {"value": round(useful / s1 / 1e12, 6), "ms_per_step": round(s1 * 1e3, 1)},
+            "o1_dense_u1_d18": {"GFLOPs_useful": round(f1 / d1 / 1e9, 3), "ms": round(d1 * 1e3, 2)},
+            "o1_dense_corner_step": {"GFLOPs_useful": round(useful / d2 / 1e9, 3), "ms": round(d2 * 1e3, 1),
+                                     "note": "dense-embed form, one run"}}
 
 
 # --------------------------------------------------------------------- main
@@ -593,7 +713,8 @@ def main():
                     help="norm of the last output as its own two-pass kernel instead of fused into the contraction")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the precision sweep, the batched configs and the serving loop")
-    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--batch-only", default="", choices=["", "u1_d18_x64", "u1_d18_x512", "u1_uneven_x64"],
                     help="run only this grouped launch (autotuned, then --steps launches) and print its time; "
                          "for profiling")
@@ -669,6 +790,7 @@ def main():
         cur = pl.output(0)
     torch.cuda.synchronize()
     plan_ms = (time.perf_counter() - tp0) * 1e3
+    plan_rec = plan_costs(torch, Y, W, descs, plans, plan_ms, sp, args.tile_rows)
     stats = [pl.stats(0) for pl in plans]
     useful = sum(s["useful_flops"] for s in stats)
     alg_bytes = [s["alg_bytes"] for s in stats]
@@ -821,24 +943,12 @@ def main():
                  "graph_error": pg_err, "steps": KP, "max_rel_diff_vs_library": maxdiff,
                  "form": "gather into fused sector matrices, one torch.matmul (FP64) per sector, scatter"}
 
-    # ---- CPU oracle baseline (block-pair form), bounded sample
+    # ---- CPU oracle baseline, bounded sample: the block-pair form (O2) of the
+    # step at one BLAS thread and at all host cores (median of cpu_reps each),
+    # and the dense-embed form (O1) of the D = 18 contraction and of the step
     cpu = None
     if not args.no_cpu_baseline:
-        from threadpoolctl import threadpool_limits
-
-        import oracle
-        with threadpool_limits(1):
-            tc = time.perf_counter()
-            for _ in range(args.cpu_reps):
-                cur = None
-                for (an, bn), (ax, bx) in zip(STEPS, t["axes"]):
-                    cur = oracle.tensordot_blockpair(t[an] if an else cur, t[bn], ax, bx)
-                oracle.norms(cur)
-            csec = time.perf_counter() - tc
-        cpu = {"value": round(useful * args.cpu_reps / csec / 1e12, 6), "unit": "TFLOP/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"{args.cpu_reps} full enlarged-corner steps (4 block-pair tensordots + norm), "
-                         f"{csec:.1f} s, BLAS limited to 1 thread; host has {os.cpu_count()} CPUs"}
+        cpu = cpu_baseline(t, useful, args.cpu_reps)
 
     # ---- the other workloads (not the headline value)
     extras = None
@@ -849,7 +959,7 @@ def main():
                   "batched": batch_section(torch, Y, W, ev, sp),
                   "gradient": grad_section(torch, Y, W, ev, sp),
                   "svd": svd_section(torch, Y, outs[-1], plans[-1].output(0), sp),
-                  "serving": serving_section(torch, Y, W, sp, nreq=args.serve_requests)}
+                  "serving": serving_section(torch, Y, W, sp, nreq=args.serve_requests, warm=args.serve_warmup)}
 
     rec = {
         "metric": "useful TFLOP/s per block-sparse tensordot vs plain per-sector FP64; p50/p99 latency",
@@ -860,7 +970,7 @@ def main():
                    "useful_flop_per_step": int(useful), "plus": "fp64 norm of the step-4 output" + (" (separate kernel)" if args.separate_norm else " (fused into its contraction)"),
                    "parallelism": "single GPU"},
         "p50_ms": round(float(np.percentile(lat, 50)), 5), "p99_ms": round(float(np.percentile(lat, 99)), 5),
-        "plan_ms": round(plan_ms, 2),
+        "plan_ms": round(plan_ms, 2), "plan": plan_rec,
         "timing": {"graph": "step captured in one HIP graph, one replay per step",
                    "eager": "one host launch per kernel"}[mode],
         "ms_per_step_by_mode": {m: round(v[0], 5) for m, v in modes.items()}, "graph_error": graph_err,

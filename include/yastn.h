@@ -105,6 +105,10 @@ typedef struct {
  * (used when every sector has K, N <= 64; BF16 precisions always use MFMA). */
 #define YASTN_FLAG_MFMA 1
 #define YASTN_FLAG_ROWS 2
+/* Plans are kept in a structure cache by default (see yastn_plan);
+ * FLAG_NOCACHE (may be or-ed with the flags above) plans afresh and keeps
+ * nothing. */
+#define YASTN_FLAG_NOCACHE 4
 
 typedef struct {
   int64_t blocks_a, blocks_b;  /* stored blocks of A and B                                      */
@@ -133,6 +137,21 @@ typedef struct yastn_plan_s *yastn_plan_t;
  * Synchronises hip_stream once.  opts may be NULL (F64, F64 in/out, auto). */
 yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_options *opts,
                         void *hip_stream, yastn_plan_t *out);
+
+/* Structure cache: CTM runs contract tensors of one block structure in
+ * every iteration (Sec. III), so yastn_plan keeps each plan it builds under
+ * the exact description of the request (device, options, every descriptor
+ * array, compared in full) and answers a later identical request with a new
+ * handle to the same plan (up to 64 structures, least recently used
+ * dropped).  Handles of one structure share the plan, including its tuned
+ * kernel variant; its device tables are released when the last handle is
+ * freed and the cache has dropped it (yastn_plan_cache_clear drops every
+ * entry).  yastn_plan_profile: the wall time of the plan's construction in
+ * ms, ms[0] validation, ms[1] the charge-hash join (device), ms[2] the host
+ * tables, ms[3] the upload ([host] array of 4, may be NULL); *cached = 1 if
+ * this handle came from the cache. */
+yastn_status yastn_plan_profile(yastn_plan_t plan, double *ms, int32_t *cached);
+void yastn_plan_cache_clear(void);
 
 /* Structure of problem prob's output.  The returned arrays are owned by the
  * plan and live until yastn_free.  c->charges / shapes / offsets are [host]. */
@@ -217,8 +236,12 @@ yastn_status yastn_contract_timed(yastn_plan_t plan, const void *const *a, const
  * variant v or -1 if it does not fit.  Synchronises hip_stream.  Results of
  * different variants agree within rounding, and one plan always uses one
  * variant, so repeated contractions stay bitwise reproducible.
- * yastn_plan_set_variant restores a previously tuned choice (e.g. from a
- * cache keyed by structure); YASTN_ERR_STATE if the variant does not fit. */
+ * The choice is kept with the plan's structure: a later yastn_plan_autotune
+ * on any handle of a tuned structure (see the structure cache) returns the
+ * stored choice and times at once, without timing again.
+ * yastn_plan_set_variant sets the variant of this handle only;
+ * YASTN_ERR_STATE if the variant does not fit.  A new handle starts at the
+ * structure's tuned variant (0, the heuristic, before any tuning). */
 #define YASTN_NUM_VARIANTS 23
 yastn_status yastn_plan_autotune(yastn_plan_t plan, const void *const *a, const void *const *b,
                                  void *const *c, void *workspace, void *hip_stream, int32_t reps,
@@ -246,7 +269,9 @@ yastn_status yastn_contract_jobs(const yastn_job *jobs, int32_t njobs, void *hip
  * taking step i-1's output as its A operand.  The server admits queued
  * requests in arrival order while its device memory pool (one allocation made
  * by yastn_server_create; serving never calls hipMalloc) can hold their
- * intermediate outputs and workspaces; each yastn_server_step merges the next
+ * intermediate outputs and workspaces (a request that fits may pass a waiting
+ * one that does not, at most 16 times per waiting request, after which the
+ * waiting request is admitted next); each yastn_server_step merges the next
  * step of every admitted request into one grouped launch (yastn_contract_jobs)
  * on the server's stream, so requests that arrive while others run join the
  * next launch; a request completes when the event after the launch holding
@@ -270,6 +295,8 @@ typedef struct {
   int64_t ticks, launched_steps, max_batch; /* grouped launches, steps launched, most per launch */
   int64_t queued, running;                  /* requests waiting for memory / admitted, now       */
   size_t pool_bytes, pool_used, pool_peak;  /* device pool                                       */
+  int64_t bypasses;                         /* admissions past a waiting, larger request         */
+  int64_t queued_peak;                      /* most requests waiting at once                     */
 } yastn_server_stats;
 
 typedef struct yastn_server_s *yastn_server_t;
@@ -304,8 +331,9 @@ size_t yastn_norm_workspace(void);
 yastn_status yastn_norm(const void *x, int64_t n, yastn_dtype dtype, double *out, void *workspace,
                         void *hip_stream);
 
-/* Release a plan (host and device tables).  NULL is ignored.  The caller must
- * make sure no launch that uses the plan is still running. */
+/* Release a plan handle (the tables go with the last handle that shares
+ * them and the cache entry).  NULL is ignored.  The caller must make sure no
+ * launch that uses the plan is still running. */
 void yastn_free(yastn_plan_t plan);
 
 /* ---- leg permutation (transpose) of a block tensor ----------------------

@@ -26,13 +26,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libyastn.so")
 
 F64, F32, BF16X3, BF16X6 = 0, 1, 2, 3
-FLAG_MFMA, FLAG_ROWS = 1, 2
+FLAG_MFMA, FLAG_ROWS, FLAG_NOCACHE = 1, 2, 4
 DTYPE_F64, DTYPE_F32 = 0, 1
 PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3, "bf16x6": BF16X6}
 STATUS = ["OK", "ERR_ARG", "ERR_SYM", "ERR_CHARGE", "ERR_SIGNATURE", "ERR_SHAPE",
           "ERR_DUPLICATE", "ERR_NOMEM", "ERR_HIP", "ERR_STATE"]
 
-EXPORTS = ["yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats", "yastn_plan_info",
+EXPORTS = ["yastn_plan", "yastn_plan_profile", "yastn_plan_cache_clear", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats", "yastn_plan_info",
            "yastn_contract", "yastn_contract_noalloc", "yastn_contract_norm", "yastn_contract_timed",
            "yastn_contract_jobs", "yastn_norm_workspace", "yastn_norm",
            "yastn_free", "yastn_last_error", "yastn_status_string", "yastn_abi_version",
@@ -91,7 +91,8 @@ class Request(C.Structure):
 class ServerStats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("submitted", "admitted", "completed", "ticks", "launched_steps",
                                          "max_batch", "queued", "running")] + \
-               [(n, C.c_size_t) for n in ("pool_bytes", "pool_used", "pool_peak")]
+               [(n, C.c_size_t) for n in ("pool_bytes", "pool_used", "pool_peak")] + \
+               [(n, C.c_int64) for n in ("bypasses", "queued_peak")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -115,6 +116,10 @@ def lib():
         L = C.CDLL(LIB_PATH)
         L.yastn_plan.argtypes = [C.POINTER(Problem), C.c_int32, C.POINTER(Options), C.c_void_p,
                                  C.POINTER(C.c_void_p)]
+        L.yastn_plan_profile.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+        L.yastn_plan_profile.restype = C.c_int32
+        L.yastn_plan_cache_clear.argtypes = []
+        L.yastn_plan_cache_clear.restype = None
         L.yastn_plan_output.argtypes = [C.c_void_p, C.c_int32, C.POINTER(TensorDesc), C.POINTER(C.c_int64)]
         L.yastn_plan_workspace.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
         L.yastn_plan_stats.argtypes = [C.c_void_p, C.c_int32, C.POINTER(Stats)]
@@ -326,6 +331,13 @@ class Plan:
         _check(lib().yastn_plan_output(self._h, p, C.byref(d), C.byref(n)))
         return _structure(d, n)
 
+    def profile(self):
+        """(ms of validation, join, host tables, upload; from the cache?)."""
+        ms = (C.c_double * 4)()
+        cached = C.c_int32()
+        _check(lib().yastn_plan_profile(self._h, ms, C.byref(cached)))
+        return [float(v) for v in ms], bool(cached.value)
+
     def stats(self, p: int = 0) -> dict:
         st = Stats()
         _check(lib().yastn_plan_stats(self._h, p, C.byref(st)))
@@ -403,6 +415,11 @@ class Plan:
 
 def plan(problems, **kw) -> Plan:
     return Plan(problems, **kw)
+
+
+def plan_cache_clear():
+    """Drop every entry of the library's plan structure cache."""
+    lib().yastn_plan_cache_clear()
 
 
 class Perm:

@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <memory>
 #include <cstdio>
 #include <type_traits>
 #include <cstring>
@@ -266,14 +268,19 @@ yastn_status gpu_join(const HostProblem &hp, hipStream_t st, std::vector<std::pa
   contracted_keys(hp.b, hp.axes_b, hp.nc, kb);
   uint64_t tsize = 64;
   while (tsize < 2 * (uint64_t)nb) tsize <<= 1;
+  // one allocation for the keys, the hash table and the counts
   DevBufs bufs;
-  int32_t *d_ka, *d_kb, *owner, *head, *next;
-  int64_t *cnt, *off;
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t o_ka = 0, o_kb = o_ka + al(ka.size() * 4), o_ow = o_kb + al(kb.size() * 4),
+               o_hd = o_ow + al(tsize * 4), o_nx = o_hd + al(tsize * 4), o_cn = o_nx + al(size_t(nb) * 4),
+               o_of = o_cn + al(size_t(na) * 8), total_b = o_of + al(size_t(na + 1) * 8);
+  char *jb;
   yastn_status s;
-  if ((s = bufs.alloc(&d_ka, ka.size())) || (s = bufs.alloc(&d_kb, kb.size())) || (s = bufs.alloc(&owner, tsize)) ||
-      (s = bufs.alloc(&head, tsize)) || (s = bufs.alloc(&next, nb)) || (s = bufs.alloc(&cnt, na)) ||
-      (s = bufs.alloc(&off, na + 1)))
-    return s;
+  if ((s = bufs.alloc(&jb, total_b))) return s;
+  int32_t *d_ka = reinterpret_cast<int32_t *>(jb + o_ka), *d_kb = reinterpret_cast<int32_t *>(jb + o_kb),
+          *owner = reinterpret_cast<int32_t *>(jb + o_ow), *head = reinterpret_cast<int32_t *>(jb + o_hd),
+          *next = reinterpret_cast<int32_t *>(jb + o_nx);
+  int64_t *cnt = reinterpret_cast<int64_t *>(jb + o_cn), *off = reinterpret_cast<int64_t *>(jb + o_of);
   if (!ka.empty()) YASTN_HIP(hipMemcpyAsync(d_ka, ka.data(), ka.size() * 4, hipMemcpyHostToDevice, st));
   if (!kb.empty()) YASTN_HIP(hipMemcpyAsync(d_kb, kb.data(), kb.size() * 4, hipMemcpyHostToDevice, st));
   k_fill_i32<<<grid_for(tsize, 256), 256, 0, st>>>(owner, tsize, -1);
@@ -286,8 +293,9 @@ yastn_status gpu_join(const HostProblem &hp, hipStream_t st, std::vector<std::pa
   YASTN_HIP(hipMemcpyAsync(&total, off + na, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   YASTN_HIP(hipStreamSynchronize(st));
   if (total == 0) return YASTN_OK;
-  int32_t *pa, *pb;
-  if ((s = bufs.alloc(&pa, total)) || (s = bufs.alloc(&pb, total))) return s;
+  int32_t *pa;
+  if ((s = bufs.alloc(&pa, 2 * size_t(total)))) return s;
+  int32_t *pb = pa + total;
   k_join_emit<<<grid_for(na, 256), 256, 0, st>>>(d_ka, na, d_kb, klen, owner, head, next, tsize - 1, off, pa, pb);
   YASTN_HIP(hipGetLastError());
   std::vector<int32_t> ha(total), hb(total);
@@ -554,6 +562,7 @@ struct JobRef {
   const void *const *b;
   void *const *c;
   void *ws;
+  int variant;  // the kernel variant of the plan handle (0: heuristic)
 };
 
 // jobs: njobs entries (a pointer and a count, so a caller may pass an array
@@ -568,10 +577,10 @@ yastn_status launch(const JobRef *jobs, size_t njobs, hipStream_t st, void *cons
   }
   const yastn_options &o = jobs[0].plan->opts;
   Fit fit;
-  int variant = jobs[0].plan->variant;
+  int variant = jobs[0].variant;
   for (size_t k = 0; k < njobs; ++k) {
     fit_add(fit, *jobs[k].plan);
-    if (jobs[k].plan->variant != variant) variant = 0;
+    if (jobs[k].variant != variant) variant = 0;
   }
   const bool norm_one = norm_out && njobs == 1 && !fit.split;
   const Choice ch = choose(fit, o, variant, norm_one);
@@ -730,9 +739,111 @@ yastn_status scratch_ptr(int dev, void **out) {
 // ===========================================================================
 using namespace yastn;
 
+namespace {
+// A plan's tables live on the device until the last handle that shares it
+// (a caller's, or the structure cache's) lets go.
+std::shared_ptr<Plan> new_plan() {
+  return std::shared_ptr<Plan>(new Plan(), [](Plan *p) {
+    if (p->dev_mem) (void)hipFree(p->dev_mem);
+    delete p;
+  });
+}
+}  // namespace
+
+// A handle: the (possibly shared) plan and this handle's kernel variant,
+// which starts at the plan's tuned variant (0 until yastn_plan_autotune has
+// tuned the plan under any of its handles).
 struct yastn_plan_s {
-  Plan p;
+  std::shared_ptr<Plan> sp;
+  Plan &p;
+  bool cached = false;  // this handle came from the structure cache
+  int variant = 0;
+  yastn_plan_s() : sp(new_plan()), p(*sp) {}
+  explicit yastn_plan_s(std::shared_ptr<Plan> s) : sp(std::move(s)), p(*sp), cached(true), variant(p.variant) {}
 };
+
+// ---------------------------------------------------------------------------
+// structure cache: a CTM run contracts tensors of the same block structure in
+// every iteration, so plans are kept per exact problem description (device,
+// options, every descriptor array) and handed out again; a hit compares the
+// whole description, not only its hash
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kPlanCacheMax = 64;
+struct CacheEntry {
+  uint64_t hash;
+  std::vector<int64_t> key;
+  std::shared_ptr<Plan> plan;
+  uint64_t used;
+};
+std::mutex g_cache_mu;
+std::vector<CacheEntry> g_cache;
+uint64_t g_cache_tick = 0;
+
+bool put_desc(std::vector<int64_t> &k, const yastn_tensor_desc &d) {
+  if (d.rank < 0 || d.rank > YASTN_MAX_RANK || d.nsym < 1 || d.nsym > YASTN_MAX_NSYM) return false;
+  if (d.nblocks < 0 || d.nblocks > (int64_t(1) << 30) || !d.sym_mod || !d.n || (d.rank > 0 && !d.sig)) return false;
+  if (d.nblocks > 0 && (!d.offsets || (d.rank > 0 && (!d.charges || !d.shapes)))) return false;
+  k.push_back(d.rank);
+  k.push_back(d.nsym);
+  k.insert(k.end(), d.sym_mod, d.sym_mod + d.nsym);
+  k.insert(k.end(), d.n, d.n + d.nsym);
+  for (int i = 0; i < d.rank; ++i) k.push_back(d.sig[i]);
+  k.push_back(d.nblocks);
+  const size_t nq = size_t(d.nblocks) * d.rank * d.nsym, nsh = size_t(d.nblocks) * d.rank;
+  if (nq) k.insert(k.end(), d.charges, d.charges + nq);
+  if (nsh) k.insert(k.end(), d.shapes, d.shapes + nsh);
+  if (d.nblocks) k.insert(k.end(), d.offsets, d.offsets + d.nblocks);
+  return true;
+}
+
+// The full description of a plan request, or false when it is malformed
+// (then the request is planned, and rejected, without the cache).
+bool cache_key(const yastn_problem *probs, int32_t nprob, const yastn_options &o, int dev, std::vector<int64_t> &k,
+               uint64_t &h) {
+  k.clear();
+  k.insert(k.end(), {dev, o.precision, o.in_dtype, o.out_dtype, o.tile_rows, o.flags, nprob});
+  for (int p = 0; p < nprob; ++p) {
+    const yastn_problem &q = probs[p];
+    if (q.ncontract < 0 || q.ncontract > YASTN_MAX_RANK || (q.ncontract > 0 && (!q.axes_a || !q.axes_b))) return false;
+    k.push_back(q.ncontract);
+    k.insert(k.end(), q.axes_a, q.axes_a + q.ncontract);
+    k.insert(k.end(), q.axes_b, q.axes_b + q.ncontract);
+    if (!put_desc(k, q.a) || !put_desc(k, q.b)) return false;
+  }
+  h = 0xcbf29ce484222325ull;
+  for (int64_t v : k) {
+    h ^= (uint64_t)v;
+    h *= 0x100000001b3ull;
+    h ^= h >> 31;
+  }
+  return true;
+}
+
+std::shared_ptr<Plan> cache_find(uint64_t h, const std::vector<int64_t> &k) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  for (CacheEntry &e : g_cache)
+    if (e.hash == h && e.key == k) {
+      e.used = ++g_cache_tick;
+      return e.plan;
+    }
+  return nullptr;
+}
+
+void cache_put(uint64_t h, std::vector<int64_t> &&k, const std::shared_ptr<Plan> &p) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  if (g_cache.size() >= kPlanCacheMax) {
+    auto lru = std::min_element(g_cache.begin(), g_cache.end(),
+                                [](const CacheEntry &a, const CacheEntry &b) { return a.used < b.used; });
+    g_cache.erase(lru);
+  }
+  g_cache.push_back(CacheEntry{h, std::move(k), p, ++g_cache_tick});
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+}  // namespace
 
 extern "C" {
 
@@ -764,10 +875,36 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
   yastn_options o;
   yastn_status s = check_options(opts, &o);
   if (s) return s;
+  const bool use_cache = (o.flags & YASTN_FLAG_NOCACHE) == 0;
+  o.flags &= ~YASTN_FLAG_NOCACHE;
+  std::vector<int64_t> ckey;
+  uint64_t chash = 0;
+  bool keyed = false;
+  int dev = -1;
+  if (use_cache && hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    dev = -1;  // no device: plan without the cache (validation reports first)
+  }
+  if (use_cache && dev >= 0) {
+    try {
+      keyed = cache_key(probs, nprob, o, dev, ckey, chash);
+      if (keyed) {
+        std::shared_ptr<Plan> hit = cache_find(chash, ckey);
+        if (hit) {
+          yastn_plan_s *hh = new yastn_plan_s(hit);
+          *out = hh;
+          return YASTN_OK;
+        }
+      }
+    } catch (const std::bad_alloc &) {
+      return set_error(YASTN_ERR_NOMEM, "host allocation");
+    }
+  }
   yastn_plan_s *h = new (std::nothrow) yastn_plan_s();
   if (!h) return set_error(YASTN_ERR_NOMEM, "host allocation");
   Plan &pl = h->p;
   pl.opts = o;
+  auto tph = std::chrono::steady_clock::now();
   try {
     pl.probs.resize(nprob);
     for (int p = 0; p < nprob; ++p)
@@ -775,6 +912,8 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
         delete h;
         return s;
       }
+    pl.prof_ms[0] = ms_since(tph);
+    tph = std::chrono::steady_clock::now();
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     if (hipGetDevice(&pl.device) != hipSuccess) {
       (void)hipGetLastError();
@@ -788,6 +927,8 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
         delete h;
         return s;
       }
+    pl.prof_ms[1] = ms_since(tph);
+    tph = std::chrono::steady_clock::now();
     // Pass 0 builds 64 x 64 tiles to learn the sector shapes; then the plan
     // picks the kernel family and, for MFMA, the tile width, and rebuilds if
     // the tiling changed.
@@ -884,16 +1025,33 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
       return set_error(YASTN_ERR_ARG, "too many blocks in one plan");
     }
     finish_tiles(pl);
+    pl.prof_ms[2] = ms_since(tph);
+    tph = std::chrono::steady_clock::now();
     if ((s = upload(pl)) != YASTN_OK) {
       yastn_free(h);
       return s;
     }
+    pl.prof_ms[3] = ms_since(tph);
+    if (keyed) cache_put(chash, std::move(ckey), h->sp);
   } catch (const std::bad_alloc &) {
     delete h;
     return set_error(YASTN_ERR_NOMEM, "host allocation");
   }
   *out = h;
   return YASTN_OK;
+}
+
+yastn_status yastn_plan_profile(yastn_plan_t plan, double *ms, int32_t *cached) {
+  if (!plan) return set_error(YASTN_ERR_ARG, "null plan");
+  if (ms)
+    for (int i = 0; i < 4; ++i) ms[i] = plan->p.prof_ms[i];
+  if (cached) *cached = plan->cached ? 1 : 0;
+  return YASTN_OK;
+}
+
+void yastn_plan_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_cache.clear();
 }
 
 yastn_status yastn_plan_output(yastn_plan_t plan, int32_t prob, yastn_tensor_desc *c, int64_t *c_numel) {
@@ -939,7 +1097,7 @@ yastn_status yastn_contract(yastn_plan_t plan, const void *const *a, const void 
   yastn_status s = check_job_ptrs(&plan->p, a, b, c, workspace);
   if (s) return s;
   std::vector<JobRef> jobs;
-  for (const Group &g : plan->p.groups) jobs.push_back(JobRef{&plan->p, &g, a, b, c, workspace});
+  for (const Group &g : plan->p.groups) jobs.push_back(JobRef{&plan->p, &g, a, b, c, workspace, plan->variant});
   return launch(jobs, reinterpret_cast<hipStream_t>(hip_stream));
 }
 
@@ -961,7 +1119,7 @@ yastn_status yastn_contract_noalloc(yastn_plan_t plan, const void *const *a, con
   if ((s = check_job_ptrs(&plan->p, a, b, c, ws))) return s;
   // one launch per problem group, from an array on the stack
   for (const Group &g : plan->p.groups) {
-    const JobRef j{&plan->p, &g, a, b, c, ws};
+    const JobRef j{&plan->p, &g, a, b, c, ws, plan->variant};
     if ((s = launch(&j, 1, reinterpret_cast<hipStream_t>(hip_stream)))) return s;
   }
   return YASTN_OK;
@@ -974,7 +1132,7 @@ yastn_status yastn_contract_norm(yastn_plan_t plan, const void *const *a, const 
   yastn_status s = check_job_ptrs(&plan->p, a, b, c, workspace);
   if (s) return s;
   std::vector<JobRef> jobs;
-  for (const Group &g : plan->p.groups) jobs.push_back(JobRef{&plan->p, &g, a, b, c, workspace});
+  for (const Group &g : plan->p.groups) jobs.push_back(JobRef{&plan->p, &g, a, b, c, workspace, plan->variant});
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   bool fused = false;
   if ((s = launch(jobs, st, nullptr, norm_out, &fused))) return s;
@@ -1010,7 +1168,7 @@ yastn_status yastn_contract_timed(yastn_plan_t plan, const void *const *a, const
   yastn_status s = check_job_ptrs(&plan->p, a, b, c, workspace);
   if (s) return s;
   std::vector<JobRef> jobs;
-  for (const Group &g : plan->p.groups) jobs.push_back(JobRef{&plan->p, &g, a, b, c, workspace});
+  for (const Group &g : plan->p.groups) jobs.push_back(JobRef{&plan->p, &g, a, b, c, workspace, plan->variant});
   return launch(jobs, reinterpret_cast<hipStream_t>(hip_stream), events);
 }
 
@@ -1020,7 +1178,7 @@ yastn_status yastn_plan_set_variant(yastn_plan_t plan, int32_t variant) {
   Fit f;
   fit_add(f, plan->p);
   if (!variant_fits(f, plan->p.opts, variant)) return set_error(YASTN_ERR_STATE, "kernel variant does not fit this plan");
-  plan->p.variant = variant;
+  plan->variant = variant;
   return YASTN_OK;
 }
 
@@ -1031,19 +1189,29 @@ yastn_status yastn_plan_autotune(yastn_plan_t plan, const void *const *a, const 
   if (s) return s;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   std::vector<JobRef> jobs;
-  for (const Group &g : plan->p.groups) jobs.push_back(JobRef{&plan->p, &g, a, b, c, workspace});
+  for (const Group &g : plan->p.groups) jobs.push_back(JobRef{&plan->p, &g, a, b, c, workspace, plan->variant});
+  // tuning cache: a plan tuned before (under this or another handle of the
+  // same structure) hands out its choice and times without timing again
+  if (plan->p.variant != 0) {
+    plan->variant = plan->p.variant;
+    if (chosen) *chosen = plan->p.variant;
+    if (times_ms)
+      for (int v = 0; v < kVariants; ++v) times_ms[v] = plan->p.tuned_ms[v];
+    return YASTN_OK;
+  }
   hipEvent_t e0, e1;
   YASTN_HIP(hipEventCreate(&e0));
   YASTN_HIP(hipEventCreate(&e1));
-  const int keep = plan->p.variant;
   Fit fit;
   fit_add(fit, plan->p);
   int best = 1;
   float best_ms = 1e30f;
+  float tms[kVariants];
+  for (int v = 0; v < kVariants; ++v) tms[v] = -1.f;
   for (int v = 1; v < kVariants; ++v) {
     float ms = -1.f;
     if (variant_fits(fit, plan->p.opts, v)) {
-      plan->p.variant = v;
+      for (JobRef &j : jobs) j.variant = v;
       s = launch(jobs, st);  // warm-up
       if (!s) s = (hipEventRecord(e0, st) == hipSuccess) ? YASTN_OK : YASTN_ERR_HIP;
       for (int r = 0; r < reps && !s; ++r) s = launch(jobs, st);
@@ -1057,17 +1225,18 @@ yastn_status yastn_plan_autotune(yastn_plan_t plan, const void *const *a, const 
       }
       if (s) break;
     }
-    if (times_ms) times_ms[v] = ms;
+    tms[v] = ms;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (s) {
-    plan->p.variant = keep;
-    return s;
-  }
+  if (s) return s;
+  tms[0] = best_ms;
+  for (int v = 0; v < kVariants; ++v) plan->p.tuned_ms[v] = tms[v];
   plan->p.variant = best;
+  plan->variant = best;
   if (chosen) *chosen = best;
-  if (times_ms) times_ms[0] = best_ms;
+  if (times_ms)
+    for (int v = 0; v < kVariants; ++v) times_ms[v] = tms[v];
   return YASTN_OK;
 }
 
@@ -1082,7 +1251,7 @@ yastn_status yastn_contract_jobs(const yastn_job *jobs, int32_t njobs, void *hip
       return set_error(YASTN_ERR_STATE, "jobs of one launch must share precision and dtypes");
     yastn_status s = check_job_ptrs(&p, jobs[i].a, jobs[i].b, jobs[i].c, jobs[i].workspace);
     if (s) return s;
-    for (const Group &g : p.groups) refs.push_back(JobRef{&p, &g, jobs[i].a, jobs[i].b, jobs[i].c, jobs[i].workspace});
+    for (const Group &g : p.groups) refs.push_back(JobRef{&p, &g, jobs[i].a, jobs[i].b, jobs[i].c, jobs[i].workspace, jobs[i].plan->variant});
   }
   return launch(refs, reinterpret_cast<hipStream_t>(hip_stream));
 }
@@ -1106,8 +1275,7 @@ yastn_status yastn_norm(const void *x, int64_t n, yastn_dtype dtype, double *out
 
 void yastn_free(yastn_plan_t plan) {
   if (!plan) return;
-  if (plan->p.dev_mem) (void)hipFree(plan->p.dev_mem);
-  delete plan;
+  delete plan;  // the device tables go with the last handle that shares them
 }
 
 }  // extern "C"

@@ -68,8 +68,7 @@ struct TupleLess {
   }
 };
 
-yastn_status check_tensor(const HostTensor &t, const char *name,
-                          std::vector<std::map<std::vector<int32_t>, int64_t>> &legdims) {
+yastn_status check_tensor(HostTensor &t, const char *name) {
   std::string nm(name);
   for (int i = 0; i < t.rank; ++i)
     if (t.sig[i] != 1 && t.sig[i] != -1) return set_error(YASTN_ERR_ARG, nm + ": signature must be +1 or -1");
@@ -85,13 +84,81 @@ yastn_status check_tensor(const HostTensor &t, const char *name,
       if (sz > (int64_t(1) << 31) - 1) return set_error(YASTN_ERR_ARG, nm + ": block larger than 2^31 elements");
     }
   }
-  // duplicates (a charge tuple names one block)
-  std::vector<int64_t> idx(t.nblocks);
-  std::iota(idx.begin(), idx.end(), 0);
-  std::sort(idx.begin(), idx.end(), TupleLess{&t});
-  for (int64_t k = 1; k < t.nblocks; ++k)
-    if (!TupleLess{&t}(idx[k - 1], idx[k]) && !TupleLess{&t}(idx[k], idx[k - 1]))
-      return set_error(YASTN_ERR_DUPLICATE, nm + ": a charge tuple occurs twice");
+  // the distinct charges of each leg, ascending, and each block's index
+  // among them (charges packed into order-preserving 128-bit keys); a charge
+  // with two dims is reported after the duplicate and conservation checks
+  const int ns = t.nsym;
+  t.qid.assign(size_t(t.nblocks) * t.rank, 0);
+  t.legq.clear();
+  t.legdim.clear();
+  bool twodims = false;
+  {
+    // per leg: an open-addressing table from charge key to first-seen slot,
+    // then the (few) distinct keys sorted and the slots renumbered ascending
+    typedef unsigned __int128 u128k;
+    size_t cap = 16;
+    while (cap < 2 * size_t(t.nblocks)) cap <<= 1;
+    std::vector<u128k> hkey(cap);
+    std::vector<int32_t> hslot(cap), first(size_t(t.nblocks)), tmp(size_t(t.nblocks));
+    std::vector<u128k> dkeys;
+    for (int i = 0; i < t.rank; ++i) {
+      t.legq0[i] = (int64_t)t.legdim.size();
+      std::fill(hslot.begin(), hslot.end(), -1);
+      dkeys.clear();
+      for (int64_t b = 0; b < t.nblocks; ++b) {
+        u128k k = 0;
+        for (int c = 0; c < ns; ++c) k = (k << 32) | (uint32_t)(t.q(b, i)[c] ^ INT32_MIN);
+        uint64_t h = (uint64_t)k * 0x9E3779B97F4A7C15ull ^ (uint64_t)(k >> 64) * 0xC2B2AE3D27D4EB4Full;
+        size_t p = (size_t)(h ^ (h >> 29)) & (cap - 1);
+        while (hslot[p] >= 0 && hkey[p] != k) p = (p + 1) & (cap - 1);
+        if (hslot[p] < 0) {
+          hkey[p] = k;
+          hslot[p] = (int32_t)dkeys.size();
+          first[dkeys.size()] = (int32_t)b;
+          dkeys.push_back(k);
+        } else if (t.dim(first[hslot[p]], i) != t.dim(b, i)) {
+          twodims = true;
+        }
+        tmp[b] = hslot[p];
+      }
+      std::vector<int32_t> ord(dkeys.size()), rank(dkeys.size());
+      std::iota(ord.begin(), ord.end(), 0);
+      std::sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return dkeys[x] < dkeys[y]; });
+      for (size_t r = 0; r < ord.size(); ++r) {
+        rank[ord[r]] = (int32_t)r;
+        const int64_t b = first[ord[r]];
+        t.legq.insert(t.legq.end(), t.q(b, i), t.q(b, i) + ns);
+        t.legdim.push_back(t.dim(b, i));
+      }
+      for (int64_t b = 0; b < t.nblocks; ++b) t.qid[b * t.rank + i] = rank[tmp[b]];
+      t.nq[i] = (int32_t)dkeys.size();
+    }
+  }
+  t.legq0[t.rank] = (int64_t)t.legdim.size();
+  // duplicates (a charge tuple names one block): the tuple of leg indices
+  // as one key when it fits 128 bits, else a comparison of charge tuples
+  {
+    long double span = 1.0L;
+    for (int i = 0; i < t.rank; ++i) span *= (long double)std::max(1, t.nq[i]);
+    bool dup = false;
+    if (span < 1.0e38L) {
+      std::vector<unsigned __int128> full(size_t(t.nblocks));
+      for (int64_t b = 0; b < t.nblocks; ++b) {
+        unsigned __int128 k = 0;
+        for (int i = 0; i < t.rank; ++i) k = k * (uint32_t)t.nq[i] + (uint32_t)t.qid[b * t.rank + i];
+        full[b] = k;
+      }
+      std::sort(full.begin(), full.end());
+      dup = std::adjacent_find(full.begin(), full.end()) != full.end();
+    } else {
+      std::vector<int64_t> idx(t.nblocks);
+      std::iota(idx.begin(), idx.end(), 0);
+      std::sort(idx.begin(), idx.end(), TupleLess{&t});
+      for (int64_t k = 1; k < t.nblocks && !dup; ++k)
+        dup = !TupleLess{&t}(idx[k - 1], idx[k]) && !TupleLess{&t}(idx[k], idx[k - 1]);
+    }
+    if (dup) return set_error(YASTN_ERR_DUPLICATE, nm + ": a charge tuple occurs twice");
+  }
   // block form of charge conservation
   for (int64_t b = 0; b < t.nblocks; ++b)
     for (int c = 0; c < t.nsym; ++c) {
@@ -100,14 +167,7 @@ yastn_status check_tensor(const HostTensor &t, const char *name,
       if (norm_charge(s, t.sym_mod[c]) != t.n[c])
         return set_error(YASTN_ERR_CHARGE, nm + ": a block violates sum_i s_i rho_i = n");
     }
-  // one dim per charge and leg
-  legdims.assign(t.rank, {});
-  for (int64_t b = 0; b < t.nblocks; ++b)
-    for (int i = 0; i < t.rank; ++i) {
-      std::vector<int32_t> key(t.q(b, i), t.q(b, i) + t.nsym);
-      auto it = legdims[i].emplace(key, t.dim(b, i)).first;
-      if (it->second != t.dim(b, i)) return set_error(YASTN_ERR_SHAPE, nm + ": one charge has two dims on a leg");
-    }
+  if (twodims) return set_error(YASTN_ERR_SHAPE, nm + ": one charge has two dims on a leg");
   // offsets: non-negative, blocks disjoint
   std::vector<std::pair<int64_t, int64_t>> spans(t.nblocks);
   for (int64_t b = 0; b < t.nblocks; ++b) {
@@ -152,8 +212,9 @@ yastn_status check_options(const yastn_options *o, yastn_options *out) {
   if (d.tile_rows != 0 && d.tile_rows != 16 && d.tile_rows != 32 && d.tile_rows != 64 && d.tile_rows != 128 &&
       d.tile_rows != 256 && d.tile_rows != 512)
     return set_error(YASTN_ERR_ARG, "tile_rows must be 0, 16, 32, 64, 128, 256 or 512");
-  if (d.flags != 0 && d.flags != YASTN_FLAG_MFMA && d.flags != YASTN_FLAG_ROWS)
-    return set_error(YASTN_ERR_ARG, "flags must be 0, YASTN_FLAG_MFMA or YASTN_FLAG_ROWS");
+  const int32_t fam = d.flags & ~YASTN_FLAG_NOCACHE;
+  if (fam != 0 && fam != YASTN_FLAG_MFMA && fam != YASTN_FLAG_ROWS)
+    return set_error(YASTN_ERR_ARG, "flags must be 0, YASTN_FLAG_MFMA or YASTN_FLAG_ROWS, optionally with YASTN_FLAG_NOCACHE");
   *out = d;
   return YASTN_OK;
 }
@@ -165,8 +226,7 @@ yastn_status validate_tensor(const yastn_tensor_desc &d, const char *name, HostT
     if (d.sym_mod[c] < 0 || d.sym_mod[c] == 1) return set_error(YASTN_ERR_SYM, "sym_mod must be 0 (U(1)) or >= 2 (Z_m)");
   yastn_status st = copy_tensor(d, t, name);
   if (st != YASTN_OK) return st;
-  std::vector<std::map<std::vector<int32_t>, int64_t>> dims;
-  return check_tensor(t, name, dims);
+  return check_tensor(t, name);
 }
 
 yastn_status validate_problem(const yastn_problem &p, HostProblem &hp) {
@@ -193,18 +253,32 @@ yastn_status validate_problem(const yastn_problem &p, HostProblem &hp) {
   yastn_status st;
   if ((st = copy_tensor(A, hp.a, "A")) != YASTN_OK) return st;
   if ((st = copy_tensor(B, hp.b, "B")) != YASTN_OK) return st;
-  std::vector<std::map<std::vector<int32_t>, int64_t>> da, db;
-  if ((st = check_tensor(hp.a, "A", da)) != YASTN_OK) return st;
-  if ((st = check_tensor(hp.b, "B", db)) != YASTN_OK) return st;
+  if ((st = check_tensor(hp.a, "A")) != YASTN_OK) return st;
+  if ((st = check_tensor(hp.b, "B")) != YASTN_OK) return st;
   for (int c = 0; c < p.ncontract; ++c)
     if (hp.a.sig[p.axes_a[c]] == hp.b.sig[p.axes_b[c]])
       return set_error(YASTN_ERR_SIGNATURE, "a contracted leg pair has equal signatures");
-  for (int c = 0; c < p.ncontract; ++c)
-    for (auto &kv : da[p.axes_a[c]]) {
-      auto it = db[p.axes_b[c]].find(kv.first);
-      if (it != db[p.axes_b[c]].end() && it->second != kv.second)
-        return set_error(YASTN_ERR_SHAPE, "a contracted charge has different dims in A and B");
+  // a charge on both legs of a contracted pair has one dim (merge of the two
+  // ascending lists of distinct charges)
+  const int ns = hp.a.nsym;
+  for (int c = 0; c < p.ncontract; ++c) {
+    const int la = p.axes_a[c], lb = p.axes_b[c];
+    int64_t x = hp.a.legq0[la], y = hp.b.legq0[lb];
+    const int64_t xe = hp.a.legq0[la + 1], ye = hp.b.legq0[lb + 1];
+    while (x < xe && y < ye) {
+      const int32_t *qa = &hp.a.legq[size_t(x) * ns], *qb = &hp.b.legq[size_t(y) * ns];
+      if (std::lexicographical_compare(qa, qa + ns, qb, qb + ns)) {
+        ++x;
+      } else if (std::lexicographical_compare(qb, qb + ns, qa, qa + ns)) {
+        ++y;
+      } else {
+        if (hp.a.legdim[x] != hp.b.legdim[y])
+          return set_error(YASTN_ERR_SHAPE, "a contracted charge has different dims in A and B");
+        ++x;
+        ++y;
+      }
     }
+  }
   hp.nc = p.ncontract;
   for (int c = 0; c < p.ncontract; ++c) {
     hp.axes_a[c] = p.axes_a[c];
@@ -228,19 +302,44 @@ void contracted_keys(const HostTensor &t, const int *axes, int nc, std::vector<i
 }
 
 namespace {
-using Key = std::vector<int32_t>;
+// Order-preserving integer keys of charge tuples: the mixed-radix number of
+// the legs' charge indices (validation numbers each leg's distinct charges in
+// ascending order), first leg most significant, so comparing keys compares
+// the tuples lexicographically.  No heap allocation per key.
+typedef unsigned __int128 u128;
 
-Key legs_key(const HostTensor &t, int64_t b, const int *legs, int nl) {
-  Key k;
-  k.reserve(size_t(nl) * t.nsym);
-  for (int i = 0; i < nl; ++i) k.insert(k.end(), t.q(b, legs[i]), t.q(b, legs[i]) + t.nsym);
+bool key_fits(const HostTensor &t, const int *legs, int nl) {
+  long double p = 1.0L;
+  for (int i = 0; i < nl; ++i) p *= (long double)std::max(1, t.nq[legs[i]]);
+  return p < 1.0e38L;
+}
+
+u128 pack_key(const HostTensor &t, int64_t b, const int *legs, int nl) {
+  u128 k = 0;
+  for (int i = 0; i < nl; ++i) k = k * (u128)(uint32_t)t.nq[legs[i]] + (u128)(uint32_t)t.qid[b * t.rank + legs[i]];
   return k;
 }
 
-struct SectorBuild {
-  std::map<Key, int> rows, ctrs, cols;             // tuple -> local id (assigned after collection)
-  std::vector<std::pair<int64_t, int64_t>> pairs;  // (A block, B block)
-};
+// The fused contracted charge X of an A block (nsym components, each
+// normalised), as an order-preserving key.
+u128 sector_key(const HostTensor &A, int64_t b, const int *axes, int nc) {
+  u128 k = 0;
+  for (int s = 0; s < A.nsym; ++s) {
+    int64_t v = 0;
+    for (int c = 0; c < nc; ++c) v += int64_t(A.sig[axes[c]]) * A.q(b, axes[c])[s];
+    k = (k << 32) | (u128)(uint32_t)(int32_t)((int32_t)norm_charge(v, A.sym_mod[s]) ^ INT32_MIN);
+  }
+  return k;
+}
+
+template <typename T> int32_t rank_of(const std::vector<T> &sorted, const T &v) {
+  return (int32_t)(std::lower_bound(sorted.begin(), sorted.end(), v) - sorted.begin());
+}
+
+template <typename T> void sort_unique(std::vector<T> &v) {
+  std::sort(v.begin(), v.end());
+  v.erase(std::unique(v.begin(), v.end()), v.end());
+}
 }  // namespace
 
 yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::pair<int32_t, int32_t>> &pairs,
@@ -248,21 +347,32 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
                              bool gather) {
   const HostTensor &A = hp.a, &B = hp.b;
   const int nsym = A.nsym, nc = hp.nc;
-  // ---- group matches by sector X = sum over A's contracted legs of s_i rho_i
-  std::map<Key, SectorBuild> sect;
-  for (auto &pr : pairs) {
-    int64_t ia = pr.first, jb = pr.second;
-    Key X(nsym, 0);
-    for (int s = 0; s < nsym; ++s) {
-      int64_t v = 0;
-      for (int c = 0; c < nc; ++c) v += int64_t(A.sig[hp.axes_a[c]]) * A.q(ia, hp.axes_a[c])[s];
-      X[s] = (int32_t)norm_charge(v, A.sym_mod[s]);
-    }
-    SectorBuild &sb = sect[X];
-    sb.rows.emplace(legs_key(A, ia, hp.fa, hp.nfa), 0);
-    sb.ctrs.emplace(legs_key(A, ia, hp.axes_a, nc), 0);
-    sb.cols.emplace(legs_key(B, jb, hp.fb, hp.nfb), 0);
-    sb.pairs.emplace_back(ia, jb);
+  if (!key_fits(A, hp.fa, hp.nfa) || !key_fits(A, hp.axes_a, nc) || !key_fits(B, hp.fb, hp.nfb))
+    return set_error(YASTN_ERR_ARG, "too many distinct charges on the legs of one tensor (planner keys are 128-bit)");
+  // ---- per block: sector, row tuple, contracted tuple (A) and column tuple (B) keys
+  std::vector<u128> ax(size_t(A.nblocks)), ar(size_t(A.nblocks)), ac(size_t(A.nblocks)), bj(size_t(B.nblocks));
+  for (int64_t b = 0; b < A.nblocks; ++b) {
+    ax[b] = sector_key(A, b, hp.axes_a, nc);
+    ar[b] = pack_key(A, b, hp.fa, hp.nfa);
+    ac[b] = pack_key(A, b, hp.axes_a, nc);
+  }
+  for (int64_t b = 0; b < B.nblocks; ++b) bj[b] = pack_key(B, b, hp.fb, hp.nfb);
+  // ---- sectors in ascending X; the pairs of each sector in join order
+  std::vector<u128> xs;
+  xs.reserve(pairs.size());
+  for (auto &pr : pairs) xs.push_back(ax[pr.first]);
+  sort_unique(xs);
+  const int nS = (int)xs.size();
+  std::vector<int32_t> psec(pairs.size()), scount(size_t(nS) + 1, 0);
+  for (size_t k = 0; k < pairs.size(); ++k) {
+    psec[k] = rank_of(xs, ax[pairs[k].first]);
+    ++scount[size_t(psec[k]) + 1];
+  }
+  for (int x = 0; x < nS; ++x) scount[x + 1] += scount[x];
+  std::vector<int32_t> sorder(pairs.size());
+  {
+    std::vector<int32_t> fill(scount.begin(), scount.end() - 1);
+    for (size_t k = 0; k < pairs.size(); ++k) sorder[size_t(fill[psec[k]]++)] = (int32_t)k;
   }
   // ---- A storage structure: classes of free legs, contracted positions
   bool isctr[YASTN_MAX_RANK] = {false};
@@ -294,20 +404,17 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
   const size_t prob_slot = t.probs.size();
   t.probs.push_back(dp);
   // ---- output blocks: (A free tuple, B free tuple) reached by >= 1 pair, ascending order
-  std::map<Key, std::vector<int64_t>> cblocks;  // key -> shape
-  for (auto &kv : sect)
-    for (auto &pr : kv.second.pairs) {
-      Key k = legs_key(A, pr.first, hp.fa, hp.nfa);
-      Key kb = legs_key(B, pr.second, hp.fb, hp.nfb);
-      k.insert(k.end(), kb.begin(), kb.end());
-      auto it = cblocks.find(k);
-      if (it == cblocks.end()) {
-        std::vector<int64_t> shp;
-        for (int q = 0; q < hp.nfa; ++q) shp.push_back(A.dim(pr.first, hp.fa[q]));
-        for (int q = 0; q < hp.nfb; ++q) shp.push_back(B.dim(pr.second, hp.fb[q]));
-        cblocks.emplace(std::move(k), std::move(shp));
-      }
-    }
+  struct CKey {
+    u128 r, j;      // A free tuple, B free tuple
+    int32_t ia, jb; // a pair that reaches the block (its dims and charges)
+    bool operator<(const CKey &o) const { return r < o.r || (r == o.r && j < o.j); }
+    bool operator==(const CKey &o) const { return r == o.r && j == o.j; }
+  };
+  std::vector<CKey> ck;
+  ck.reserve(pairs.size());
+  for (auto &pr : pairs) ck.push_back(CKey{ar[pr.first], bj[pr.second], pr.first, pr.second});
+  std::sort(ck.begin(), ck.end());
+  ck.erase(std::unique(ck.begin(), ck.end()), ck.end());
   hp.c_rank = hp.nfa + hp.nfb;
   for (int q = 0; q < hp.nfa; ++q) hp.c_sig[q] = A.sig[hp.fa[q]];
   for (int q = 0; q < hp.nfb; ++q) hp.c_sig[hp.nfa + q] = B.sig[hp.fb[q]];
@@ -315,15 +422,23 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
   hp.c_charges.clear();
   hp.c_shapes.clear();
   hp.c_offsets.clear();
-  std::map<Key, int64_t> coff;
+  hp.c_charges.reserve(ck.size() * size_t(hp.nfa + hp.nfb) * nsym);
+  hp.c_shapes.reserve(ck.size() * size_t(hp.nfa + hp.nfb));
+  hp.c_offsets.reserve(ck.size());
   int64_t pos = 0;
-  for (auto &kv : cblocks) {
-    hp.c_charges.insert(hp.c_charges.end(), kv.first.begin(), kv.first.end());
-    hp.c_shapes.insert(hp.c_shapes.end(), kv.second.begin(), kv.second.end());
-    hp.c_offsets.push_back(pos);
-    coff.emplace(kv.first, pos);
+  for (const CKey &k : ck) {
     int64_t sz = 1;
-    for (int64_t d : kv.second) sz *= d;
+    for (int q = 0; q < hp.nfa; ++q) {
+      hp.c_charges.insert(hp.c_charges.end(), A.q(k.ia, hp.fa[q]), A.q(k.ia, hp.fa[q]) + nsym);
+      hp.c_shapes.push_back(A.dim(k.ia, hp.fa[q]));
+      sz *= A.dim(k.ia, hp.fa[q]);
+    }
+    for (int q = 0; q < hp.nfb; ++q) {
+      hp.c_charges.insert(hp.c_charges.end(), B.q(k.jb, hp.fb[q]), B.q(k.jb, hp.fb[q]) + nsym);
+      hp.c_shapes.push_back(B.dim(k.jb, hp.fb[q]));
+      sz *= B.dim(k.jb, hp.fb[q]);
+    }
+    hp.c_offsets.push_back(pos);
     pos += sz;
   }
   hp.c_numel = pos;
@@ -349,21 +464,28 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
   S.blocks_a = A.nblocks;
   S.blocks_b = B.nblocks;
   S.pairs = (int64_t)pairs.size();
-  S.sectors = (int64_t)sect.size();
-  S.c_blocks = (int64_t)cblocks.size();
+  S.sectors = (int64_t)nS;
+  S.c_blocks = (int64_t)ck.size();
   S.c_numel = hp.c_numel;
   S.numel_a = A.numel;
   S.numel_b = B.numel;
   const int TN = 16 * cb, TM = 16 * rb * nch;
-  for (auto &kv : sect) {
-    SectorBuild &sb = kv.second;
-    int id = 0;
-    for (auto &r : sb.rows) r.second = id++;
-    id = 0;
-    for (auto &r : sb.ctrs) r.second = id++;
-    id = 0;
-    for (auto &r : sb.cols) r.second = id++;
-    const int R = (int)sb.rows.size(), Sn = (int)sb.ctrs.size(), Q = (int)sb.cols.size();
+  std::vector<u128> rk, sk, jk;  // the sector's distinct row / contracted / column tuple keys, ascending
+  for (int x = 0; x < nS; ++x) {
+    const int32_t p0 = scount[x], p1 = scount[x + 1];
+    rk.clear();
+    sk.clear();
+    jk.clear();
+    for (int32_t u = p0; u < p1; ++u) {
+      const auto &pr = pairs[size_t(sorder[u])];
+      rk.push_back(ar[pr.first]);
+      sk.push_back(ac[pr.first]);
+      jk.push_back(bj[pr.second]);
+    }
+    sort_unique(rk);
+    sort_unique(sk);
+    sort_unique(jk);
+    const int R = (int)rk.size(), Sn = (int)sk.size(), Q = (int)jk.size();
     DevSector ds{};
     ds.prob = prob;
     ds.S = Sn;
@@ -374,10 +496,9 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
     // representative blocks for the dims of each tuple
     std::vector<int64_t> row_rep(R, -1), ctr_rep(Sn, -1), col_rep(Q, -1);
     std::vector<int32_t> agrid(size_t(R) * Sn, -1), bgrid(size_t(Sn) * Q, -1);
-    for (auto &pr : sb.pairs) {
-      int i = sb.rows.at(legs_key(A, pr.first, hp.fa, hp.nfa));
-      int s = sb.ctrs.at(legs_key(A, pr.first, hp.axes_a, nc));
-      int j = sb.cols.at(legs_key(B, pr.second, hp.fb, hp.nfb));
+    for (int32_t u = p0; u < p1; ++u) {
+      const auto &pr = pairs[size_t(sorder[u])];
+      const int i = rank_of(rk, ar[pr.first]), s = rank_of(sk, ac[pr.first]), j = rank_of(jk, bj[pr.second]);
       row_rep[i] = pr.first;
       ctr_rep[s] = pr.first;
       col_rep[j] = pr.second;
@@ -411,6 +532,19 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
       t.ctrs.push_back(ct);
     }
     ds.K = K;
+    // digits of each contracted index k of the sector within its tuple (C
+    // order over the contracted legs in axes order)
+    std::vector<int32_t> kdig(size_t(K) * std::max(1, nc));
+    for (int s = 0; s < Sn; ++s) {
+      const DevCtrTuple &ct = t.ctrs[ds.ctr0 + s];
+      for (int32_t kd = 0; kd < ct.k; ++kd) {
+        int32_t r = kd;
+        for (int c = nc - 1; c >= 0; --c) {
+          kdig[size_t(ct.ko + kd) * nc + c] = r % ct.dims[c];
+          r /= ct.dims[c];
+        }
+      }
+    }
     int32_t N = 0;
     for (int j = 0; j < Q; ++j) {
       DevColTuple ctp{};
@@ -473,9 +607,6 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
             t.items.push_back(DevPackItem{sec_id, s, j, bgrid[size_t(s) * Q + j], (int32_t)e0, 0});
         }
     }
-    std::vector<Key> rowkeys(R), colkeys(Q);
-    for (auto &r : sb.rows) rowkeys[r.second] = r.first;
-    for (auto &c : sb.cols) colkeys[c.second] = c.first;
     // split-K only for sectors with few output tiles (small M_X x N_X, e.g.
     // the gradient with respect to a site tensor): the partial slots cost
     // nslots x the tile's accumulators of workspace and a reduction pass
@@ -511,29 +642,32 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
       rt.agrid = (int64_t)t.agrid.size();
       t.agrid.insert(t.agrid.end(), agrid.begin() + size_t(i) * Sn, agrid.begin() + size_t(i + 1) * Sn);
       // offset of A(row 0, k) for every contracted index k of the sector (-1: block absent)
+      // (the digits of each contracted index are the sector's kdig table)
       rt.kofs = (int64_t)t.kofs.size();
+      t.kofs.resize(t.kofs.size() + size_t(K));
+      int64_t *ko = t.kofs.data() + rt.kofs;
       for (int s = 0; s < Sn; ++s) {
         const DevCtrTuple &ct = t.ctrs[ds.ctr0 + s];
         const int32_t blk = agrid[size_t(i) * Sn + s];
-        for (int64_t kd = 0; kd < ct.k; ++kd) {
-          if (blk < 0) {
-            t.kofs.push_back(-1);
-            continue;
-          }
-          int64_t r = kd, koff = 0;
-          for (int c = nc - 1; c >= 0; --c) {
-            koff += (r % ct.dims[c]) * (int64_t)rt.fac[c] * ct.cac[c];
-            r /= ct.dims[c];
-          }
-          t.kofs.push_back(t.aoff[blk] + koff);
+        if (blk < 0) {
+          std::fill(ko + ct.ko, ko + ct.ko + ct.k, int64_t(-1));
+          continue;
+        }
+        int64_t w[YASTN_MAX_RANK];
+        for (int c = 0; c < nc; ++c) w[c] = (int64_t)rt.fac[c] * ct.cac[c];
+        const int64_t base = t.aoff[blk];
+        for (int32_t kd = 0; kd < ct.k; ++kd) {
+          const int32_t *dg = &kdig[size_t(ct.ko + kd) * nc];
+          int64_t koff = base;
+          for (int c = 0; c < nc; ++c) koff += dg[c] * w[c];
+          ko[ct.ko + kd] = koff;
         }
       }
       rt.cgrid = (int64_t)t.cgrid.size();
       for (int j = 0; j < Q; ++j) {
-        Key k = rowkeys[i];
-        k.insert(k.end(), colkeys[j].begin(), colkeys[j].end());
-        auto it = coff.find(k);
-        t.cgrid.push_back(it == coff.end() ? -1 : it->second);
+        const CKey key{rk[i], jk[j], 0, 0};
+        auto it = std::lower_bound(ck.begin(), ck.end(), key);
+        t.cgrid.push_back(it != ck.end() && *it == key ? hp.c_offsets[size_t(it - ck.begin())] : -1);
       }
       const int32_t row_id = (int32_t)t.rows.size();
       t.rows.push_back(rt);
@@ -574,7 +708,8 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
     S.max_m = std::max<int64_t>(S.max_m, M);
     S.max_k = std::max<int64_t>(S.max_k, K);
     S.max_n = std::max<int64_t>(S.max_n, N);
-    for (auto &pr : sb.pairs) {
+    for (int32_t u = p0; u < p1; ++u) {
+      const auto &pr = pairs[size_t(sorder[u])];
       double m = 1, k = 1, n = 1;
       for (int q = 0; q < hp.nfa; ++q) m *= double(A.dim(pr.first, hp.fa[q]));
       for (int c = 0; c < nc; ++c) k *= double(A.dim(pr.first, hp.axes_a[c]));

@@ -20,6 +20,15 @@ struct HostTensor {
   std::vector<int64_t> shapes;   // [nblocks][rank]
   std::vector<int64_t> offsets;  // [nblocks]
   int64_t numel = 0;             // stored elements (sum of block sizes)
+  // distinct charges of each leg in ascending (lexicographic) order, set by
+  // validation: qid[b * rank + l] = index of block b's charge on leg l
+  // among the nq[l] distinct charges of leg l; legq / legdim hold those
+  // charges (nsym ints each) and their dims, leg l from entry legq0[l]
+  std::vector<int32_t> qid;
+  int32_t nq[YASTN_MAX_RANK] = {0};
+  std::vector<int32_t> legq;
+  std::vector<int64_t> legdim;
+  int64_t legq0[YASTN_MAX_RANK + 1] = {0};
   const int32_t *q(int64_t b, int leg) const { return &charges[(b * rank + leg) * nsym]; }
   int64_t dim(int64_t b, int leg) const { return shapes[b * rank + leg]; }
   int64_t size(int64_t b) const;
@@ -96,7 +105,8 @@ struct Plan {
   bool rows_fit = false;    // every sector has K, N <= 64: the row-per-lane kernel can run
   bool res_fit = false;     // every sector has K <= 80 and B offsets fit int32: k_gemm_res can run
   int nact = 1;             // largest number of A free-leg classes over the plan's problems
-  int variant = 0;          // kernel variant (0 = heuristic; set by yastn_plan_autotune)
+  int variant = 0;          // tuned kernel variant (0 = not tuned; set by yastn_plan_autotune)
+  float tuned_ms[YASTN_NUM_VARIANTS] = {0};  // the tuning run's times (ms per launch, -1 = does not fit)
   int kmax = 0;             // largest K_X of the plan
   void *dev_mem = nullptr;  // one device allocation holding every table
   DevPlan *dplan = nullptr; // device copy of the table of pointers
@@ -107,6 +117,7 @@ struct Plan {
   size_t norm_off = 0;      // workspace offset of the fused norm's per-tile parts
   size_t ptab_off = 0;      // workspace offset of the problem pointer table (groups of > kMaxProbs problems)
   int device = 0;
+  double prof_ms[4] = {0, 0, 0, 0};  // planning time: validation, join, host tables, upload
 };
 
 // error reporting (thread-local message)

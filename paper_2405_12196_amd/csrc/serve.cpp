@@ -4,8 +4,10 @@
 // cached plans, one plan per contraction of its enlarged-corner chain) submit
 // requests; a request is one chain of contractions whose step i > 0 takes the
 // output of step i - 1 as its A operand.  The server
-//   * admits queued requests (FIFO) while its device memory pool can hold
-//     their intermediates and workspaces (admission by HBM budget);
+//   * admits queued requests in arrival order while its device memory pool
+//     can hold their intermediates and workspaces (admission by HBM budget),
+//     letting a request that fits pass one that does not, at most 16 times
+//     per waiting request (bounded bypass, no starvation);
 //   * every tick, merges the next step of every admitted request into ONE
 //     grouped launch (yastn_contract_jobs) on its stream, so requests that
 //     arrive while others run join the very next launch and their work
@@ -106,6 +108,7 @@ struct Request {
   void *inter[YASTN_MAX_CHAIN] = {};
   void *ws[YASTN_MAX_CHAIN] = {};
   double t_submit = 0, t_admit = 0, t_done = 0;
+  int bypassed = 0;  // later requests admitted while this one waited
   // pointer arrays handed to yastn_contract_jobs for the step being launched
   const void *pa[1] = {}, *pb[1] = {};
   void *pc[1] = {};
@@ -168,11 +171,15 @@ yastn_status retire(yastn_server_s *s, bool wait) {
   return YASTN_OK;
 }
 
-void admit(yastn_server_s *s) {
-  while (!s->queue.empty()) {
-    Request &r = s->reqs[s->queue.front()];
-    size_t off = 0;
-    if (r.footprint && !s->pool->alloc(r.footprint, &off)) return;  // FIFO: later requests wait too
+// Admission in arrival order with bounded bypass: a queued request whose
+// footprint does not fit now is skipped and later requests that fit are
+// admitted past it, but each waiting request can be passed at most
+// kMaxBypass times; once a request has been passed that often nothing is
+// admitted past it any more (it is admitted next, as soon as memory frees
+// up), so no request starves behind a stream of smaller ones.
+constexpr int kMaxBypass = 16;
+
+void admit_one(yastn_server_s *s, Request &r, size_t off) {
     r.pool_off = off;
     char *p = s->base + off;
     for (int i = 0; i < r.nsteps; ++i) {
@@ -190,8 +197,27 @@ void admit(yastn_server_s *s) {
     r.state = YASTN_REQ_RUNNING;
     r.t_admit = now_ms();
     s->running.push_back(r.id);
-    s->queue.pop_front();
     s->st.admitted += 1;
+}
+
+void admit(yastn_server_s *s) {
+  size_t k = 0;
+  while (k < s->queue.size()) {
+    Request &r = s->reqs[s->queue[k]];
+    size_t off = 0;
+    if (!r.footprint || s->pool->alloc(r.footprint, &off)) {
+      admit_one(s, r, off);
+      // every request still waiting ahead of it has been passed once more;
+      // one that reached the bound stops admission past it
+      bool bound = false;
+      for (size_t i = 0; i < k; ++i) bound |= ++s->reqs[s->queue[i]].bypassed >= kMaxBypass;
+      if (k > 0) s->st.bypasses += 1;
+      s->queue.erase(s->queue.begin() + (std::ptrdiff_t)k);
+      if (bound) return;
+      continue;
+    }
+    if (r.bypassed >= kMaxBypass) return;  // the bound: nothing passes this request
+    ++k;
   }
 }
 
@@ -262,6 +288,7 @@ yastn_status yastn_server_submit(yastn_server_t s, const yastn_request *rq, int6
   s->queue.push_back(r.id);
   s->reqs.emplace(r.id, r);
   s->st.submitted += 1;
+  s->st.queued_peak = std::max<int64_t>(s->st.queued_peak, (int64_t)s->queue.size());
   *id = r.id;
   return YASTN_OK;
 }

@@ -654,3 +654,51 @@ def test_long_k_wide_sector_not_split():
     # packed B (K x N FP64) and the norm parts only: no partial slots
     assert pl.workspace_bytes < st["max_k"] * st["max_n"] * 8 + (1 << 20)
     check_f64(s, v, ref)
+
+
+# ------------------------------------------------------------ structure cache
+def test_structure_cache_handles_and_tuning():
+    """An identical request returns a handle to the cached plan (same
+    structure, same bits); FLAG_NOCACHE plans afresh; a handle's variant is
+    its own; a tuned structure hands its choice to later handles at once."""
+    import paper_2405_12196_amd as Y
+    Y.plan_cache_clear()
+    (p,) = W.u1_d18()
+    prob = [(p.a, p.b, p.axes_a, p.axes_b)]
+    pl1 = Y.plan(prob)
+    ms1, c1 = pl1.profile()
+    assert not c1 and len(ms1) == 4 and all(v >= 0 for v in ms1)
+    pl2 = Y.plan(prob)
+    assert pl2.profile()[1], "an identical request should hit the cache"
+    pl3 = Y.plan(prob, flags=Y.FLAG_NOCACHE)
+    assert not pl3.profile()[1]
+    A, B = G.upload(p.a), G.upload(p.b)
+    outs = []
+    for pl in (pl1, pl2, pl3):
+        c, s = G.alloc_out(pl, 0)
+        pl.contract([A], [B], [c], G.workspace(pl))
+        outs.append(c)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+    # per-handle variants: setting one handle's leaves the other on the heuristic
+    pl1.set_variant(1)
+    c1_, _ = G.alloc_out(pl1, 0)
+    c2_, _ = G.alloc_out(pl2, 0)
+    pl1.contract([A], [B], [c1_], G.workspace(pl1))
+    pl2.contract([A], [B], [c2_], G.workspace(pl2))
+    torch.cuda.synchronize()
+    ref = oracle.tensordot_blockpair(p.a, p.b, p.axes_a, p.axes_b)
+    for c in (c1_, c2_):
+        assert oracle.rel_frobenius(c.cpu().numpy()[:ref.data.size], ref.data) <= TOL_F64
+    # tuning: the first autotune times, a later handle gets the choice at once
+    c, _ = G.alloc_out(pl2, 0)
+    v, times = pl2.autotune([A], [B], [c], G.workspace(pl2), reps=2)
+    pl4 = Y.plan(prob)
+    v4, times4 = pl4.autotune([A], [B], [c], G.workspace(pl4), reps=2)
+    assert v4 == v and times4 == times
+    # a different structure misses
+    (q,) = W.u1_d18(1)
+    pl5 = Y.plan([(q.a, q.b, (2, 3), (0, 1))], precision="f32")
+    assert not pl5.profile()[1]
+    Y.plan_cache_clear()
+    assert not Y.plan(prob).profile()[1]

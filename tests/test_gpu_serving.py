@@ -121,3 +121,46 @@ def test_oversized_request_rejected(runs):
         r.submit(srv, out)
     assert e.value.status == "ERR_NOMEM"
     srv.close()
+
+
+def _footprint(plans):
+    al = lambda b: (b + 255) // 256 * 256
+    f = 0
+    for i, pl in enumerate(plans):
+        if i + 1 < len(plans):
+            f += al(pl.output(0).numel * 8)
+        f += al(pl.workspace_bytes)
+    return f
+
+
+def test_bounded_bypass_admission():
+    """A request that does not fit is passed by later ones that do, at most
+    16 times; then admission waits for it (no starvation), and every request
+    still completes with its alone-result."""
+    small, med, big = Run(16), Run(5), Run(21)  # U(1) D=4 chi=64; Z2 D=6 chi=128; U(1) D=6 chi=128
+    fs, fm, fb = _footprint(small.plans), _footprint(med.plans), _footprint(big.plans)
+    # memory alone would admit a 17th small request next to M; after M, B fits
+    # next to 16 small ones
+    assert fb - 256 >= 17 * fs and fm - 256 >= 16 * fs, (fs, fm, fb)
+    srv = Y.Server(pool_bytes=fm + fb - 256, max_ahead=2)
+    o_m = torch.empty(max(1, med.n_out), dtype=torch.float64, device=G.DEV)
+    o_b = torch.empty(max(1, big.n_out), dtype=torch.float64, device=G.DEV)
+    o_s = [torch.empty(max(1, small.n_out), dtype=torch.float64, device=G.DEV) for _ in range(30)]
+    rm = med.submit(srv, o_m)
+    rb = big.submit(srv, o_b)
+    rs = [small.submit(srv, o) for o in o_s]
+    srv.step()  # admission: M fits, B waits, S1..S16 pass B, S17.. wait behind B
+    assert srv.query(rm)[0] != Y.REQ_QUEUED
+    assert srv.query(rb)[0] == Y.REQ_QUEUED
+    states = [srv.query(r)[0] for r in rs]
+    assert all(s != Y.REQ_QUEUED for s in states[:16]), states
+    assert all(s == Y.REQ_QUEUED for s in states[16:]), states
+    srv.drain()
+    st = srv.stats()
+    assert st["completed"] == 32 and st["bypasses"] == 16 and st["queued_peak"] >= 31
+    assert torch.equal(o_m[:med.n_out], med.alone())
+    assert torch.equal(o_b[:big.n_out], big.alone())
+    ref = small.alone()
+    for o in o_s:
+        assert torch.equal(o[:small.n_out], ref)
+    srv.close()
