@@ -45,7 +45,7 @@ EXPORTS = ["yastn_plan", "yastn_plan_profile", "yastn_plan_cache_clear", "yastn_
            "yastn_svd_factors", "yastn_svd_free"]
 REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 MAX_CHAIN = 8
-NUM_VARIANTS = 23
+NUM_VARIANTS = 24
 SCRATCH_BYTES = 64 << 20
 
 

@@ -468,7 +468,7 @@ KernelFn res_kernel(const yastn_options &o, bool buf, int shape, int cb, int kq,
 // Which variants can run a set of plans in one launch.
 struct Fit {
   int cb = 1, kmax = 0, nact = 1;
-  bool buf = true, rows = true, res = true, bf16 = false;
+  bool buf = true, rows = true, res = true, bf16 = false, pair = true;
   bool split = false;     // some plan has split-K tiles (only the pipelined kernel writes partials)
   bool rows_pick = true;  // every plan asked for the row kernel (YASTN_FLAG_ROWS)
   bool mfma_pick = true;  // every plan asked for MFMA tiles (YASTN_FLAG_MFMA)
@@ -481,6 +481,7 @@ void fit_add(Fit &f, const Plan &p) {
   f.buf = f.buf && p.buf_ok;
   f.rows = f.rows && p.rows_fit;
   f.res = f.res && p.res_fit;
+  f.pair = f.pair && p.pair_ok;
   f.bf16 = is_bf16(p.opts);
   f.split = f.split || !p.t.red.empty();
   f.rows_pick = f.rows_pick && p.opts.flags == YASTN_FLAG_ROWS;
@@ -502,6 +503,7 @@ bool variant_fits(const Fit &f, const yastn_options &o, int v) {
   }
   if (v >= kVariantLds0 && v < kVariants) {  // K <= 80; FP32: one shape compiled (kLdsShapes[2])
     if (!f.res || !f.buf || f.kmax > kResMaxKWide) return false;
+    if (v == kVariantLds0 + kLdsPairShape) return o.precision == YASTN_F64 && f.pair && f.kmax <= kPairMaxK;
     return o.precision == YASTN_F64 || v == kVariantLds0 + 2;
   }
   if (v >= kVariantPf0 && v < kVariantLds0) {
@@ -929,31 +931,19 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
       }
     pl.prof_ms[1] = ms_since(tph);
     tph = std::chrono::steady_clock::now();
-    // Pass 0 builds 64 x 64 tiles to learn the sector shapes; then the plan
-    // picks the kernel family and, for MFMA, the tile width, and rebuilds if
-    // the tiling changed.
+    // The tables of every problem first; then the plan picks the tile shape
+    // from the sector shapes and builds the tiles.
     int64_t a_base = 0, b_base = 0;
-    auto build_all = [&](int rb, int cb, int nch, bool ksplit) -> yastn_status {
-      pl.t = PlanTables{};
-      pl.prob_t0.clear();
-      pl.prob_i0.clear();
-      a_base = b_base = 0;
-      pl.rb = rb;
-      pl.cb = cb;
-      pl.nch = nch;
-      for (int p = 0; p < nprob; ++p) {
-        pl.prob_t0.push_back((int32_t)pl.t.tiles.size());
-        pl.prob_i0.push_back((int32_t)pl.t.items.size());
-        yastn_status st2 = build_structure(pl.probs[p], p, allpairs[p], a_base, b_base, pl.t, rb, cb, nch, ksplit);
-        if (st2 != YASTN_OK) return st2;
-        a_base += pl.probs[p].a.nblocks;
-        b_base += pl.probs[p].b.nblocks;
+    pl.t = PlanTables{};
+    pl.prob_i0.clear();
+    for (int p = 0; p < nprob; ++p) {
+      pl.prob_i0.push_back((int32_t)pl.t.items.size());
+      if ((s = build_structure(pl.probs[p], p, allpairs[p], a_base, b_base, pl.t)) != YASTN_OK) {
+        delete h;
+        return s;
       }
-      return YASTN_OK;
-    };
-    if ((s = build_all(4, 4, 1, false)) != YASTN_OK) {
-      delete h;
-      return s;
+      a_base += pl.probs[p].a.nblocks;
+      b_base += pl.probs[p].b.nblocks;
     }
     // buffer addressing needs every A and B span and C size below 2 GiB
     const int64_t in_b = o.in_dtype == YASTN_DTYPE_F64 ? 8 : 4, out_b = o.out_dtype == YASTN_DTYPE_F64 ? 8 : 4;
@@ -977,6 +967,16 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
     }
     pl.kmax = (int)maxk;
     pl.rows_fit = !bf16 && maxk <= 64 && maxn <= 64;
+    // paired-row loads: in every row tuple the innermost free-leg class runs
+    // with unit stride (no contracted extent after it) over an even length
+    pl.pair_ok = !pl.t.rows.empty();
+    for (const DevRowTuple &rt : pl.t.rows) {
+      const int na = pl.t.sectors[rt.sector].nact;
+      if (na < 1 || (rt.lsuf[na - 1] & 1)) pl.pair_ok = false;
+    }
+    for (const DevSector &sec : pl.t.sectors)
+      for (int sx = 0; sx < sec.S && pl.pair_ok; ++sx)
+        if (sec.nact < 1 || pl.t.ctrs[sec.ctr0 + sx].p[sec.nact - 1] != 1) pl.pair_ok = false;
     pl.res_fit = maxk <= kResMaxKWide && !pl.t.bofs_overflow;
     pl.nact = 1;
     for (const DevProb &dp : pl.t.probs) pl.nact = std::max(pl.nact, (int)dp.nact);
@@ -1014,10 +1014,7 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
     }
     // tile height = 16 * rb * nch rows
     const int rb_t = tm >= 64 ? 4 : tm / 16, nch = tm >= 64 ? tm / 64 : 1;
-    if ((cb != 4 || tm != 64 || (ksplit && maxk > kSplitMinK)) && (s = build_all(rb_t, cb, nch, ksplit)) != YASTN_OK) {
-      delete h;
-      return s;
-    }
+    build_tiles(pl, rb_t, cb, nch, ksplit);
     (void)rows;
     (void)rows64;
     if (a_base > INT32_MAX || b_base > INT32_MAX) {

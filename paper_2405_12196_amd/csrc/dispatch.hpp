@@ -40,11 +40,14 @@ struct PfShape {
 constexpr PfShape kPfShapes[] = {{2, 2, 2}, {2, 2, 3}, {4, 1, 3}};
 constexpr int kNumPf = sizeof(kPfShapes) / sizeof(PfShape);
 // k_gemm_lds: rows per chunk = 16 * rb, A loads pd chunks ahead, occupancy
-// hint occ; K <= 80
+// hint occ; K <= 80.  The fourth shape loads rows in adjacent pairs (FP64,
+// K <= 40, plans whose row tuples allow it: Plan::pair_ok).
 struct LdsShape {
   int rb, pd, occ;
 };
-constexpr LdsShape kLdsShapes[] = {{1, 1, 2}, {1, 0, 3}, {2, 0, 2}};
+constexpr LdsShape kLdsShapes[] = {{1, 1, 2}, {1, 0, 3}, {2, 0, 2}, {2, 0, 2}};
+constexpr int kLdsPairShape = 3;
+constexpr int kPairMaxK = 40;
 constexpr int kNumLds = sizeof(kLdsShapes) / sizeof(LdsShape);
 constexpr int kResMaxK = 64;      // K limit of the shapes with occ > 1
 constexpr int kResMaxKWide = 80;  // K limit of the occupancy-1 shape

@@ -343,8 +343,7 @@ template <typename T> void sort_unique(std::vector<T> &v) {
 }  // namespace
 
 yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::pair<int32_t, int32_t>> &pairs,
-                             int64_t a_base, int64_t b_base, PlanTables &t, int rb, int cb, int nch, bool ksplit,
-                             bool gather) {
+                             int64_t a_base, int64_t b_base, PlanTables &t, bool gather) {
   const HostTensor &A = hp.a, &B = hp.b;
   const int nsym = A.nsym, nc = hp.nc;
   if (!key_fits(A, hp.fa, hp.nfa) || !key_fits(A, hp.axes_a, nc) || !key_fits(B, hp.fb, hp.nfb))
@@ -469,7 +468,6 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
   S.c_numel = hp.c_numel;
   S.numel_a = A.numel;
   S.numel_b = B.numel;
-  const int TN = 16 * cb, TM = 16 * rb * nch;
   std::vector<u128> rk, sk, jk;  // the sector's distinct row / contracted / column tuple keys, ascending
   for (int x = 0; x < nS; ++x) {
     const int32_t p0 = scount[x], p1 = scount[x + 1];
@@ -593,6 +591,7 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
       }
     const int32_t sec_id = (int32_t)t.sectors.size();
     t.sectors.push_back(ds);
+    t.sec_row0.push_back((int32_t)t.rows.size());
     if (!sec_over) {
       // gathers through the offset table: long coalesced runs, one table read each
       const int64_t total = int64_t(K) * N;
@@ -607,16 +606,6 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
             t.items.push_back(DevPackItem{sec_id, s, j, bgrid[size_t(s) * Q + j], (int32_t)e0, 0});
         }
     }
-    // split-K only for sectors with few output tiles (small M_X x N_X, e.g.
-    // the gradient with respect to a site tensor): the partial slots cost
-    // nslots x the tile's accumulators of workspace and a reduction pass
-    int64_t Msec = 0;
-    for (int i = 0; i < R; ++i) {
-      int64_t m = 1;
-      for (int q = 0; q < hp.nfa; ++q) m *= A.dim(row_rep[i], hp.fa[q]);
-      Msec += m;
-    }
-    const bool split_sec = ksplit && K > kSplitMinK && Msec * int64_t(N) <= kSplitMaxMN;
     int64_t M = 0;
     for (int i = 0; i < R; ++i) {
       DevRowTuple rt{};
@@ -669,41 +658,7 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
         auto it = std::lower_bound(ck.begin(), ck.end(), key);
         t.cgrid.push_back(it != ck.end() && *it == key ? hp.c_offsets[size_t(it - ck.begin())] : -1);
       }
-      const int32_t row_id = (int32_t)t.rows.size();
       t.rows.push_back(rt);
-      // split-K: a sector with a long K (few, long tiles: small M and N) is
-      // computed in nslots k ranges by separate tiles (same output tile), each
-      // into its own partial slot, summed afterwards in slot order
-      int32_t nslots = 1, chunk = (int32_t)K;
-      if (split_sec) {
-        nslots = (int32_t)std::min<int64_t>(kSplitMaxSlots, (K + kSplitChunk - 1) / kSplitChunk);
-        chunk = (int32_t)(((K + nslots - 1) / nslots + 7) / 8 * 8);
-        nslots = (int32_t)((K + chunk - 1) / chunk);
-      }
-      for (int32_t m0 = 0; m0 < rt.m; m0 += TM)
-        for (int32_t n0 = 0; n0 < N; n0 += TN) {
-          DevTile tl{};
-          tl.rowtuple = row_id;
-          tl.sector = sec_id;
-          tl.m0 = m0;
-          tl.n0 = n0;
-          tl.nrows = std::min<int32_t>(TM, rt.m - m0);
-          tl.ncols = std::min<int32_t>(TN, N - n0);
-          tl.red = -1;
-          if (nslots > 1) {
-            tl.red = (int32_t)t.red.size();
-            t.red.push_back(RedGroup{prob, row_id, sec_id, m0, n0, tl.nrows, tl.ncols, nslots});
-          }
-          for (int32_t sl = 0; sl < nslots; ++sl) {
-            tl.k0 = sl * chunk;
-            tl.kn = (int32_t)std::min<int64_t>(chunk, K - tl.k0);
-            tl.part = sl;
-            t.tiles.push_back(tl);
-            S.tiles += 1;
-            S.mfma_flops += 2.0 * (16.0 * ((tl.nrows + 15) / 16)) * (4.0 * ((tl.kn + 3) / 4)) *
-                            (16.0 * ((tl.ncols + 15) / 16));
-          }
-        }
     }
     S.max_m = std::max<int64_t>(S.max_m, M);
     S.max_k = std::max<int64_t>(S.max_k, K);
@@ -718,6 +673,75 @@ yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::p
     }
   }
   return YASTN_OK;
+}
+
+void build_tiles(Plan &plan, int rb, int cb, int nch, bool ksplit) {
+  PlanTables &t = plan.t;
+  const int TN = 16 * cb, TM = 16 * rb * nch;
+  plan.rb = rb;
+  plan.cb = cb;
+  plan.nch = nch;
+  t.tiles.clear();
+  t.red.clear();
+  plan.prob_t0.assign(plan.probs.size(), 0);
+  for (auto &hp : plan.probs) {
+    hp.stats.tiles = 0;
+    hp.stats.mfma_flops = 0.0;
+  }
+  const int nsec = (int)t.sectors.size();
+  int prev = -1;
+  for (int x = 0; x < nsec; ++x) {
+    const DevSector &ds = t.sectors[x];
+    const int prob = ds.prob;
+    for (int p = prev + 1; p <= prob; ++p) plan.prob_t0[p] = (int32_t)t.tiles.size();
+    prev = prob;
+    yastn_stats &S = plan.probs[prob].stats;
+    const int32_t r0 = t.sec_row0[x], r1 = x + 1 < nsec ? t.sec_row0[x + 1] : (int32_t)t.rows.size();
+    const int32_t K = ds.K, N = ds.N;
+    // split-K only for sectors with few output tiles (small M_X x N_X, e.g.
+    // the gradient with respect to a site tensor): the partial slots cost
+    // nslots x the tile's accumulators of workspace and a reduction pass
+    int64_t Msec = 0;
+    for (int32_t i = r0; i < r1; ++i) Msec += t.rows[i].m;
+    const bool split_sec = ksplit && K > kSplitMinK && Msec * int64_t(N) <= kSplitMaxMN;
+    // split-K: a sector with a long K (few, long tiles: small M and N) is
+    // computed in nslots k ranges by separate tiles (same output tile), each
+    // into its own partial slot, summed afterwards in slot order
+    int32_t nslots = 1, chunk = K;
+    if (split_sec) {
+      nslots = (int32_t)std::min<int64_t>(kSplitMaxSlots, (K + kSplitChunk - 1) / kSplitChunk);
+      chunk = (int32_t)(((K + nslots - 1) / nslots + 7) / 8 * 8);
+      nslots = (int32_t)((K + chunk - 1) / chunk);
+    }
+    for (int32_t row_id = r0; row_id < r1; ++row_id) {
+      const int32_t m = t.rows[row_id].m;
+      for (int32_t m0 = 0; m0 < m; m0 += TM)
+        for (int32_t n0 = 0; n0 < N; n0 += TN) {
+          DevTile tl{};
+          tl.rowtuple = row_id;
+          tl.sector = x;
+          tl.m0 = m0;
+          tl.n0 = n0;
+          tl.nrows = std::min<int32_t>(TM, m - m0);
+          tl.ncols = std::min<int32_t>(TN, N - n0);
+          tl.red = -1;
+          if (nslots > 1) {
+            tl.red = (int32_t)t.red.size();
+            t.red.push_back(RedGroup{prob, row_id, x, m0, n0, tl.nrows, tl.ncols, nslots});
+          }
+          for (int32_t sl = 0; sl < nslots; ++sl) {
+            tl.k0 = sl * chunk;
+            tl.kn = (int32_t)std::min<int64_t>(chunk, K - tl.k0);
+            tl.part = sl;
+            t.tiles.push_back(tl);
+            S.tiles += 1;
+            S.mfma_flops += 2.0 * (16.0 * ((tl.nrows + 15) / 16)) * (4.0 * ((tl.kn + 3) / 4)) *
+                            (16.0 * ((tl.ncols + 15) / 16));
+          }
+        }
+    }
+  }
+  for (int p = prev + 1; p < (int)plan.probs.size(); ++p) plan.prob_t0[p] = (int32_t)t.tiles.size();
 }
 
 void finish_tiles(Plan &plan) {

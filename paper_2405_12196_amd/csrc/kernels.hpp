@@ -242,6 +242,19 @@ template <typename T, int CP> struct Src<T, true, CP> {
   __device__ T ld_z(bool v, int32_t i) const {
     return BufIo<T>::template ld<CP>(r, v ? i * (int32_t)sizeof(T) : (int32_t)(0x80000000u - sizeof(T)));
   }
+  // elements i and i + 1 in one load if v, else two zeros
+  __device__ void ld2_z(bool v, int32_t i, T &x0, T &x1) const {
+    const int32_t byte = v ? i * (int32_t)sizeof(T) : (int32_t)(0x80000000u - 2 * sizeof(T));
+    if constexpr (sizeof(T) == 8) {
+      const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, byte, 0, CP);
+      x0 = __builtin_bit_cast(T, u2v{w[0], w[1]});
+      x1 = __builtin_bit_cast(T, u2v{w[2], w[3]});
+    } else {
+      const u2v w = __builtin_amdgcn_raw_buffer_load_b64(r, byte, 0, CP);
+      x0 = __builtin_bit_cast(T, w[0]);
+      x1 = __builtin_bit_cast(T, w[1]);
+    }
+  }
 };
 template <typename T, int CP> struct Src<T, false, CP> {
   const T *__restrict__ p;
@@ -974,11 +987,41 @@ __device__ __forceinline__ void lds_load_chunk(const Src<In, true, kStream> &A, 
     }
 }
 
+// lds_load_chunk for paired rows (RB = 2): lane i of a 16-lane group loads
+// rows 2i and 2i + 1 of the chunk in one 2-element load, into av[q][0] and
+// av[q][1].  Valid when the innermost free-leg class of every row tuple has
+// an even run length with unit stride (rows 2i, 2i + 1 adjacent in memory)
+// and every chunk starts at an even row; then a tile's row count is even, so
+// both rows of a pair are valid or both are padding.
+template <typename In, int KQ, int NA>
+__device__ __forceinline__ void lds_load_chunk_pair(const Src<In, true, kStream> &A, const DevRowTuple &rt, int nact,
+                                                    int K, int32_t row0, int rows, int lane,
+                                                    const int32_t (*kw)[1 + NA], In (&av)[KQ][2]) {
+  int32_t rg[NA];
+  const int lr = 2 * (lane & 15);
+  const bool rv = lr < rows;
+  a_rowparts_fast<NA>(rt, nact, row0 + (rv ? lr : 0), rg);
+  const int kl = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < KQ; ++q)
+    if (4 * q < K) {
+      const int32_t *m = kw[4 * q + kl];
+      const int32_t ko = m[0];
+      int32_t o = ko;
+#pragma unroll
+      for (int a = 0; a < NA; ++a) o += m[1 + a] * rg[a];
+      A.ld2_z(ko >= 0 && rv, o, av[q][0], av[q][1]);
+    }
+}
+
 // NORM: the instance that files the fused output norm (the others carry none
-// of its code).
-template <typename In, typename Cmp, typename Out, int RB, int CB, int KQ, int NA, int PD, int OCC, bool NORM>
+// of its code).  PAIR (RB = 2): rows loaded in adjacent pairs, row block 0 of
+// the MFMA holds the chunk's even rows and block 1 its odd rows.
+template <typename In, typename Cmp, typename Out, int RB, int CB, int KQ, int NA, int PD, int OCC, bool NORM,
+          bool PAIR = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) k_gemm_lds(LaunchArgs args) {
   static_assert(NA <= kRecAct + 1, "tile records carry kRecAct class boundaries");
+  static_assert(!PAIR || RB == 2, "paired rows fill two row blocks");
   constexpr bool BUF = true;
   typedef int32_t Off;
   typedef Mfma4<Cmp> M;
@@ -1028,13 +1071,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
     const int nch = (nrows + 16 * RB - 1) / (16 * RB);
     In ab[PD + 1][KQ][RB];
     auto load_chunk = [&](int c, In (&dst)[KQ][RB]) {
-      lds_load_chunk<In, RB, KQ, NA>(x.A, x.rt, nact, K, x.m0 + c * 16 * RB, min(16 * RB, nrows - c * 16 * RB),
-                                     lane, kls[w], dst);
+      if constexpr (PAIR)
+        lds_load_chunk_pair<In, KQ, NA>(x.A, x.rt, nact, K, x.m0 + c * 16 * RB, min(16 * RB, nrows - c * 16 * RB),
+                                        lane, kls[w], dst);
+      else
+        lds_load_chunk<In, RB, KQ, NA>(x.A, x.rt, nact, K, x.m0 + c * 16 * RB, min(16 * RB, nrows - c * 16 * RB),
+                                       lane, kls[w], dst);
     };
     auto compute_chunk = [&](int c, const In (&av)[KQ][RB]) {
       const int mc = c * 16 * RB;
       const int rows = min(16 * RB, nrows - mc);
-      const int rbn = (rows + 15) >> 4;
+      // paired rows: both row blocks hold rows of any chunk (even, odd rows)
+      const int rbn = PAIR ? RB : (rows + 15) >> 4;
       acc_t acc[RB][CB];
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
@@ -1065,7 +1113,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
           if (rb >= rbn) continue;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int lr = 16 * rb + M::row(lane, v);
+            const int lr = PAIR ? 2 * M::row(lane, v) + rb : 16 * rb + M::row(lane, v);
             const bool ok = cv && lr < rows;
             const Out val = Out(acc[rb][cb][v]);
             x.C.put_if(ok, T.cbase[cb] + (Off)(x.m0 + mc + lr) * (Off)T.cnj[cb] + (Off)T.ccl[cb], val);

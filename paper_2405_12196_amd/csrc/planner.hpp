@@ -78,6 +78,7 @@ struct PlanTables {
   bool bofs_overflow = false;  // some B offset does not fit in int32 (no direct B reads then)
   std::vector<RedGroup> red;   // split-K groups, in problem order
   std::vector<DevLdsJob> ljobs;  // shared-B workgroup jobs, per group
+  std::vector<int32_t> sec_row0;  // first row tuple of each sector (a sector's row tuples are contiguous)
 };
 
 // Problems are launched in groups: all of a plan's problems in one group (up
@@ -104,6 +105,7 @@ struct Plan {
   bool buf_ok = true;       // every buffer small enough for 32-bit buffer addressing
   bool rows_fit = false;    // every sector has K, N <= 64: the row-per-lane kernel can run
   bool res_fit = false;     // every sector has K <= 80 and B offsets fit int32: k_gemm_res can run
+  bool pair_ok = false;     // A's rows run contiguously in even-length runs: paired-row loads can run
   int nact = 1;             // largest number of A free-leg classes over the plan's problems
   int variant = 0;          // tuned kernel variant (0 = not tuned; set by yastn_plan_autotune)
   float tuned_ms[YASTN_NUM_VARIANTS] = {0};  // the tuning run's times (ms per launch, -1 = does not fit)
@@ -134,9 +136,13 @@ void contracted_keys(const HostTensor &t, const int *axes, int nc, std::vector<i
 // pipelined kernel (the one that writes partial slots) can run the plan.
 // gather: pack B through the offset table where it fits (else sub-block items)
 constexpr int64_t kSplitMinK = 4096, kSplitChunk = 2048, kSplitMaxSlots = 128, kSplitMaxMN = 64 * 64 * 16;
+// Tables of one problem (structure, sectors, tuples, offsets, pack items);
+// no tiles yet.
 yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::pair<int32_t, int32_t>> &pairs,
-                             int64_t a_base, int64_t b_base, PlanTables &t, int rb, int cb, int nch,
-                             bool ksplit = false, bool gather = true);
+                             int64_t a_base, int64_t b_base, PlanTables &t, bool gather = true);
+// Wave tiles of every problem (16 * rb * nch rows x 16 * cb columns), the
+// split-K groups, prob_t0 and the tile statistics.
+void build_tiles(Plan &plan, int rb, int cb, int nch, bool ksplit);
 void finish_tiles(Plan &plan);
 // Tile records with absolute addresses: `at` gives the address of each table
 // (device addresses for the GPU, host vector data for the CPU replay).

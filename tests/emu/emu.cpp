@@ -62,14 +62,10 @@ void *emu_plan(const yastn_problem *probs, int nprob, int rb_override, int cb_ov
         for (int32_t j : it->second) pairs[p].push_back({(int32_t)i, j});
     }
   }
-  pl.cb = cb_override;
-  pl.rb = rb_override;
-  pl.nch = 1 + (rb_override == 2);  // exercise multi-chunk tiles too
   int64_t ab = 0, bb = 0;
   for (int p = 0; p < nprob; ++p) {
-    pl.prob_t0.push_back((int32_t)pl.t.tiles.size());
     pl.prob_i0.push_back((int32_t)pl.t.items.size());
-    if (build_structure(pl.probs[p], p, pairs[p], ab, bb, pl.t, pl.rb, pl.cb, pl.nch, false, g_gather) != YASTN_OK) {
+    if (build_structure(pl.probs[p], p, pairs[p], ab, bb, pl.t, g_gather) != YASTN_OK) {
       g_msg = "build_structure failed";
       delete e;
       return nullptr;
@@ -77,6 +73,8 @@ void *emu_plan(const yastn_problem *probs, int nprob, int rb_override, int cb_ov
     ab += pl.probs[p].a.nblocks;
     bb += pl.probs[p].b.nblocks;
   }
+  // exercise multi-chunk tiles too
+  build_tiles(pl, rb_override, cb_override, 1 + (rb_override == 2), false);
   finish_tiles(pl);
   // shared-B jobs (k_gemm_lds): per group, every tile exactly once, the tiles
   // of a job on one (sector, k range, column range), its first slot filled
