@@ -21,7 +21,11 @@ Implementations (each cites the passage of the paper it follows):
   * ``structure_stats``    matched pairs, sectors, useful flops, bytes;
   * ``svd.*``              the block-sparse truncated SVD of a block tensor
                            (sector matrices, per-sector SVD, the global
-                           truncation rule, the kept factors as block tensors).
+                           truncation rule, the kept factors as block tensors);
+  * ``ctm.left_move``      one CTM move on a 1x1 unit cell: four enlarged
+                           corners, the halves and their product, its
+                           truncated SVD, the projectors, the renormalised
+                           left column.
 
 Every function is pinned by tests that do not re-use its own formula (closed
 forms, the paper's worked example, brute force, special cases that reduce to
@@ -36,3 +40,4 @@ from .blocksparse import (  # noqa: F401
     rel_frobenius, same_structure,
 )
 from . import svd  # noqa: F401
+from . import ctm  # noqa: F401

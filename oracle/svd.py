@@ -12,7 +12,12 @@ its legs into row legs and column legs:
     sector in ascending order (as ``fuse_legs``), each block's row index in C
     order over its row legs and its column index in C order over its column
     legs;
-  * M_X = U_X diag(S_X) V_X^T by numpy.linalg.svd, S_X descending;
+  * M_X = U_X diag(S_X) V_X^T by numpy.linalg.svd, S_X descending, with the
+    sign of every singular pair fixed (the reading taken, the paper fixes
+    none): (u_k, v_k) and (-u_k, -v_k) are equally valid, and the pair kept
+    is the one whose u_k has its entry of largest magnitude (the first such
+    in row order) positive, so the factors, and what is built from them, are
+    unique when the values are distinct;
   * one global truncation over all sectors (``truncation``): the rule below;
   * the kept factors as block tensors: U with legs (row legs..., v), the new
     leg v of charge X and signature -1, so U has total charge 0; V^T with
@@ -79,12 +84,23 @@ def sector_matrices(t: BlockTensor, row_legs):
     return {X: tuple(v) for X, v in out.items()}
 
 
+def sign_gauge(U, Vt):
+    """Flip (u_k, v_k) to (-u_k, -v_k) where u_k's entry of largest magnitude
+    (the first such) is negative."""
+    if U.size == 0:
+        return U, Vt
+    i = np.argmax(np.abs(U), axis=0)
+    f = np.where(U[i, np.arange(U.shape[1])] < 0.0, -1.0, 1.0)
+    return U * f, Vt * f[:, None]
+
+
 def svd_sectors(t: BlockTensor, row_legs):
     """{X: (U_X, S_X, Vt_X)}: the SVD of every sector matrix (full_matrices
-    off, S_X descending)."""
+    off, S_X descending, signs by ``sign_gauge``)."""
     res = {}
     for X, (M, _, _) in sector_matrices(t, row_legs).items():
         U, S, Vt = np.linalg.svd(M, full_matrices=False)
+        U, Vt = sign_gauge(U, Vt)
         res[X] = (U, S, Vt)
     return res
 
@@ -129,7 +145,11 @@ def svd_truncated(t: BlockTensor, row_legs, chi: int, tol: float = 0.0, deg_tol:
     row_legs = tuple(row_legs)
     col_legs = tuple(x for x in range(t.rank) if x not in row_legs)
     mats = sector_matrices(t, row_legs)
-    dec = {X: np.linalg.svd(M, full_matrices=False) for X, (M, _, _) in mats.items()}
+    dec = {}
+    for X, (M, _, _) in mats.items():
+        U, s, Vt = np.linalg.svd(M, full_matrices=False)
+        U, Vt = sign_gauge(U, Vt)
+        dec[X] = (U, s, Vt)
     kept = truncation({X: d[1] for X, d in dec.items()}, chi, tol, deg_tol)
     u_items, v_items, S = [], [], {}
     for X, (M, rl, cl) in mats.items():

@@ -144,3 +144,16 @@ def test_truncation_rule_hand_made_spectra():
     assert OS.truncation(s2, 2, deg_tol=0.0) == {"a": 2, "b": 0}
     # exact zeros never survive the floor
     assert OS.truncation({"a": np.array([1.0, 0.0])}, 5) == {"a": 1}
+
+
+@pytest.mark.parametrize("seed,sym,rank,rows,n", CASES)
+def test_sign_gauge_largest_entry_positive(seed, sym, rank, rows, n):
+    """The sign of each singular pair: u_k's entry of largest magnitude is
+    positive (the factors are then unique for distinct values), and the
+    flip is applied to both factors (reconstruction above still holds)."""
+    t = _random_tensor(seed, sym, rank, n)
+    for X, (U, s, Vt) in OS.svd_sectors(t, rows).items():
+        for k in range(U.shape[1]):
+            col = np.abs(U[:, k])
+            i = int(np.flatnonzero(col == col.max())[0])
+            assert U[i, k] > 0.0

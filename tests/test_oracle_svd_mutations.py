@@ -14,6 +14,7 @@ def _run_pins():
     for case in P.CASES:
         P.test_sector_values_are_the_dense_matrix_values(*case)
         P.test_full_rank_reconstruction_and_orthonormality(*case)
+        P.test_sign_gauge_largest_entry_positive(*case)
     P.test_block_diagonal_closed_form()
     P.test_truncation_rule_hand_made_spectra()
 
@@ -98,7 +99,18 @@ def _mut_values_ascending(monkeypatch):
     monkeypatch.setattr(OS, "svd_sectors", bad)
 
 
-MUTATIONS = [_mut_sector_unsigned, _mut_block_transposed, _mut_truncation_keeps_one_more,
+def _mut_no_sign_gauge(monkeypatch):
+    """The raw LAPACK signs kept."""
+    monkeypatch.setattr(OS, "sign_gauge", lambda U, Vt: (U, Vt))
+
+
+def _mut_gauge_flips_u_only(monkeypatch):
+    """The sign fixed on u_k but not carried to v_k."""
+    orig = OS.sign_gauge
+    monkeypatch.setattr(OS, "sign_gauge", lambda U, Vt: (orig(U, Vt)[0], Vt))
+
+
+MUTATIONS = [_mut_no_sign_gauge, _mut_gauge_flips_u_only, _mut_sector_unsigned, _mut_block_transposed, _mut_truncation_keeps_one_more,
              _mut_truncation_splits_multiplets, _mut_u_without_last_column, _mut_values_ascending]
 
 

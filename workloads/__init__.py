@@ -344,3 +344,69 @@ def spin_half_pair_hamiltonian():
         key = tuple(int(q) for q in t.charges[b, :, 0])
         t.data[t.offsets[b]] = val[key]
     return t
+
+
+# ---- a 1x1 unit cell of the CTM environment: the left move ------------------
+def ctm_env(E, V, P, sym_mod, seeds, mk=_leg2):
+    """Corners C1 (top-left), C2 (top-right), C3 (bottom-right), C4 (bottom-left),
+    edges T1 (top), T2 (right), T3 (bottom), T4 (left), the site tensor A and
+    its conjugate, all of total charge 0, on legs E (environment), V (virtual)
+    and P (physical).  Leg order and signatures (every bond joins a +1 leg to a
+    -1 leg of the same space):
+        C1 (d -, r +)  C2 (l -, d -)  C3 (u +, l -)  C4 (u +, r +)
+        T1 (l -, k -, b +, r +)   T2 (t +, k +, b -, bot -)
+        T3 (l -, k +, b -, r +)   T4 (t +, k -, b +, bot -)
+        A  (t +, l +, b -, r -, p +),  A* = A with every signature flipped
+    where k / b are an edge's legs to the ket / bra layer of the site.
+    ``seeds``: nine seeds, for C1, T1, T4, A, C2, C3, C4, T2, T3 in that order
+    (so C1, T1, T4, A coincide with ``ctm_tensors`` for the same first four)."""
+    z = (0,) * len(sym_mod)
+    s = dict(zip(("C1", "T1", "T4", "A", "C2", "C3", "C4", "T2", "T3"), seeds))
+    env = {
+        "C1": rand([mk(-1, E), mk(1, E)], z, sym_mod, s["C1"]),
+        "C2": rand([mk(-1, E), mk(-1, E)], z, sym_mod, s["C2"]),
+        "C3": rand([mk(1, E), mk(-1, E)], z, sym_mod, s["C3"]),
+        "C4": rand([mk(1, E), mk(1, E)], z, sym_mod, s["C4"]),
+        "T1": rand([mk(-1, E), mk(-1, V), mk(1, V), mk(1, E)], z, sym_mod, s["T1"]),
+        "T2": rand([mk(1, E), mk(1, V), mk(-1, V), mk(-1, E)], z, sym_mod, s["T2"]),
+        "T3": rand([mk(-1, E), mk(1, V), mk(-1, V), mk(1, E)], z, sym_mod, s["T3"]),
+        "T4": rand([mk(1, E), mk(-1, V), mk(1, V), mk(-1, E)], z, sym_mod, s["T4"]),
+        "A": rand([mk(1, V), mk(1, V), mk(-1, V), mk(-1, V), mk(1, P)], z, sym_mod, s["A"]),
+    }
+    env["Ac"] = conj(env["A"])
+    return env
+
+
+ENV_NAMES = ("C1", "C2", "C3", "C4", "T1", "T2", "T3", "T4", "A")
+
+
+def ctm_move_u1xu1(chi: int = 128):
+    """The left move at chi = 128, D = 8, d = 4 (U(1)xU(1), the legs of the
+    enlarged-corner workload; C1, T1, T4, A are its tensors), new chi = chi."""
+    E, V, P = _ctm_legs_u1u1(chi)
+    base = (201, 202, 203, 204) if chi == 128 else (401, 402, 403, 404)
+    env = ctm_env(E, V, P, (U1, U1), base + tuple(base[0] + 4 + i for i in range(5)))
+    env["chi"] = chi
+    env["name"] = f"ctm_move_u1xu1_chi{chi}"
+    return env
+
+
+CTM_SMALL = {
+    # name: (E, V, P, sym_mod); charges as tuples of one or two components
+    "u1": ([((-1,), 2), ((0,), 3), ((1,), 2)], [((-1,), 1), ((0,), 1), ((1,), 1)],
+           [((-1,), 1), ((1,), 1)], (U1,)),
+    "z2": ([((0,), 4), ((1,), 3)], [((0,), 2), ((1,), 1)], [((0,), 1), ((1,), 1)], (2,)),
+    "u1xu1": ([((0, 0), 3), ((1, 0), 1), ((-1, 0), 1), ((0, 1), 1), ((0, -1), 1)],
+              [((0, 0), 1), ((1, 0), 1), ((0, -1), 1)], [((0, 0), 1), ((1, 1), 1)], (U1, U1)),
+    "u1_mid": ([((-2,), 3), ((-1,), 6), ((0,), 8), ((1,), 6), ((2,), 3)],
+               [((-1,), 1), ((0,), 2), ((1,), 1)], [((-1,), 1), ((1,), 1)], (U1,)),
+}
+
+
+def ctm_move_small(name: str, seed: int = 700):
+    """Small left-move cases for exact checks (dense arrays of a few MB at most)."""
+    E, V, P, sm = CTM_SMALL[name]
+    env = ctm_env(E, V, P, sm, tuple(seed + i for i in range(9)))
+    env["chi"] = sum(d for _, d in E)
+    env["name"] = f"ctm_move_{name}"
+    return env
