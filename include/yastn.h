@@ -424,7 +424,14 @@ void yastn_grad_free(yastn_grad_t g);
  * block (X, column tuple) of dims (kept_X, column dims...).  Blocks ascending,
  * contiguous; sectors with nothing kept have none.  Arrays owned by the plan.
  * yastn_svd_factors writes them (async on hip_stream) into u and vt [device]
- * from the workspace of the last yastn_svd. */
+ * from the workspace of the last yastn_svd.  Signs: a singular pair
+ * (u_t, v_t) is only defined up to a common sign; the one written is the one
+ * whose u_t (as a column of the sector matrix) has its entry of largest
+ * magnitude, the first such in row order, positive.  yastn_svd_factors_scaled
+ * also multiplies U's kept column t by S_t^pu and V^T's row t by S_t^pv
+ * (pu = pv = -0.5 gives the factors U S^-1/2 and S^-1/2 V^T of the CTM
+ * projectors; 0 and 0 is yastn_svd_factors); YASTN_ERR_ARG for a power
+ * that is not finite. */
 typedef struct yastn_svd_s *yastn_svd_t;
 yastn_status yastn_svd_plan(const yastn_tensor_desc *t, int32_t nrow, const int32_t *row_legs, void *hip_stream,
                             yastn_svd_t *out);
@@ -435,7 +442,77 @@ yastn_status yastn_svd(yastn_svd_t s, const void *t, int32_t chi, double tol, do
 yastn_status yastn_svd_output(yastn_svd_t s, yastn_tensor_desc *u, int64_t *u_numel, yastn_tensor_desc *vt,
                               int64_t *vt_numel);
 yastn_status yastn_svd_factors(yastn_svd_t s, void *u, void *vt, const void *workspace, void *hip_stream);
+yastn_status yastn_svd_factors_scaled(yastn_svd_t s, void *u, void *vt, double pu, double pv, const void *workspace,
+                                      void *hip_stream);
 void yastn_svd_free(yastn_svd_t s);
+
+/* ---- one CTM move (Sec. III, Fig. 3) ------------------------------------
+ * The left move of the corner-transfer-matrix method for a 1x1 unit cell,
+ * all in FP64 on the device.  Inputs: env[9] = C1, C2, C3, C4, T1, T2, T3,
+ * T4, A (corners top-left, top-right, bottom-right, bottom-left; edges top,
+ * right, bottom, left; the site tensor), with these legs and signatures
+ * (every bond joins a +1 leg to a -1 leg of the same space; A* is A with
+ * every signature and the total charge flipped and the same values):
+ *     C1 (d -, r +)   C2 (l -, d -)   C3 (u +, l -)   C4 (u +, r +)
+ *     T1 (l -, k -, b +, r +)    T2 (t +, k +, b -, bot -)
+ *     T3 (l -, k +, b -, r +)    T4 (t +, k -, b +, bot -)
+ *     A  (t +, l +, b -, r -, p +)
+ * (an edge's k / b legs join the ket / bra layer of the site).  The move:
+ *  1. enlarged corners (Fig. 3 (b)-(c)), each four contractions:
+ *     Q1 = C1.T1.T4.A.A*  legs (T1.r, T4.bot, A.b, A.r, A*.b, A*.r)
+ *     Q2 = C2.T2.T1.A.A*  legs (T2.bot, T1.l, A.l, A.b, A*.l, A*.b)
+ *     Q3 = C3.T3.T2.A.A*  legs (T3.l, T2.t, A.t, A.l, A*.t, A*.l)
+ *     Q4 = C4.T4.T3.A.A*  legs (T4.t, T3.r, A.t, A.r, A*.t, A*.r)
+ *  2. halves R_up = Q2.Q1 over (T1, A, A* horizontal legs), legs (Q2's
+ *     bottom cut, Q1's bottom cut); R_dn = Q3.Q4, legs (Q3's top cut, Q4's
+ *     top cut);
+ *  3. the four-corner product M = R_up.R_dn over (Q1's bottom cut, Q4's top
+ *     cut) (Fig. 3 (d));
+ *  4. its truncated SVD (yastn_svd's rule and sign convention, rows = R_up's
+ *     remaining legs) to at most chi values;
+ *  5. projectors P_up = R_dn.(S^-1/2 V^T)*, P_dn = R_up.(U S^-1/2)* (F* the
+ *     dual of a factor), legs (cut..., k);
+ *  6. the new left column C1' = P_up.(C1.T1), C4' = P_dn.(C4.T3) and
+ *     T4' = P_dn^T (T4.A.A*) P_up, contracted as Z1 = P_dn.T4, Z2 = Z1.A,
+ *     Z3 = Z2.A*, T4' = Z3.P_up, with the legs and signatures of C1, T4, C4;
+ *  7. each divided by its largest |entry| (FP64 reduction on the device).
+ * Independent contractions share a grouped launch (the four corners' steps,
+ * C4.T3, the projectors, C1', C4' and Z1: eleven launches of contractions).
+ *
+ * yastn_ctm_plan validates the nine descriptors (yastn_plan's error classes;
+ * YASTN_ERR_SIGNATURE / _SHAPE when they do not form the network above),
+ * plans every contraction before the SVD and allocates the device memory of
+ * all intermediates (owned by the handle).  Synchronises hip_stream.
+ * yastn_ctm_move runs one move on env [device, 9 buffers, FP64]; it
+ * synchronises hip_stream after the SVD (the kept counts decide the
+ * projectors' structure, whose plans come from the plan cache when the
+ * structure repeats) and returns when the move is done.  flags:
+ * YASTN_CTM_AUTOTUNE times the kernel variants of every contraction plan not
+ * tuned yet and keeps the fastest.  The results stay in the handle's memory
+ * until the next move or yastn_ctm_free; yastn_ctm_tensor gives any tensor
+ * of the move (YASTN_CTM_* below): its structure (arrays owned by the handle)
+ * and its device buffer.  yastn_ctm_info: kept values (sum over sectors),
+ * Jacobi sweeps, and the time of each phase of the last move in ms
+ * (ms[0] corners, ms[1] halves and product, ms[2] SVD, ms[3] projectors and
+ * the new column, ms[4] normalisation), from HIP events on hip_stream. */
+typedef struct yastn_ctm_s *yastn_ctm_t;
+enum {
+  YASTN_CTM_Q1 = 0, YASTN_CTM_Q2, YASTN_CTM_Q3, YASTN_CTM_Q4, YASTN_CTM_RUP, YASTN_CTM_RDN, YASTN_CTM_M,
+  YASTN_CTM_US, YASTN_CTM_VTS, YASTN_CTM_PUP, YASTN_CTM_PDN, YASTN_CTM_C1T1, YASTN_CTM_C4T3, YASTN_CTM_Z1,
+  YASTN_CTM_Z2, YASTN_CTM_Z3, YASTN_CTM_C1N, YASTN_CTM_T4N, YASTN_CTM_C4N, YASTN_CTM_C1, YASTN_CTM_T4, YASTN_CTM_C4,
+  YASTN_CTM_NTENSORS
+};
+/* YASTN_CTM_US / _VTS: U S^-1/2 and S^-1/2 V^T; _C1N/_T4N/_C4N: the new
+ * column before step 7; _C1/_T4/_C4: after it (the move's result). */
+#define YASTN_CTM_AUTOTUNE 1
+yastn_status yastn_ctm_plan(const yastn_tensor_desc *env, void *hip_stream, yastn_ctm_t *out);
+yastn_status yastn_ctm_move(yastn_ctm_t h, const void *const *env, int32_t chi, double tol, double deg_tol,
+                            int32_t flags, void *hip_stream);
+yastn_status yastn_ctm_tensor(yastn_ctm_t h, int32_t which, yastn_tensor_desc *desc, int64_t *numel,
+                              const void **data);
+yastn_status yastn_ctm_copy(yastn_ctm_t h, int32_t which, void *dst, void *hip_stream);
+yastn_status yastn_ctm_info(yastn_ctm_t h, int32_t *kept, int32_t *sweeps, double *ms);
+void yastn_ctm_free(yastn_ctm_t h);
 
 const char *yastn_last_error(void);
 const char *yastn_status_string(yastn_status s);

@@ -45,9 +45,11 @@ C1..C4 corners, T1..T4 edges, A the site tensor, A* its conjugate.
    tests/test_oracle_ctm.py).
 6. The left column absorbs the next one, a projector on each vertical bond
    (P_up below the upper tensor, P_dn above the lower one):
-     C1' = P_up . (C1 . T1)             legs (k, T1.r)       = C1's form
-     T4' = (P_dn . (T4 . A . A*)) . P_up legs (k, A.r, A*.r, k) = T4's form
-     C4' = P_dn . (C4 . T3)             legs (k, T3.r)       = C4's form
+     C1' = P_up . (C1 . T1)               legs (k, T1.r)         = C1's form
+     T4' = P_dn^T (T4 . A . A*) P_up      legs (k, A.r, A*.r, k) = T4's form
+     C4' = P_dn . (C4 . T3)               legs (k, T3.r)         = C4's form
+   T4' is contracted as (((P_dn . T4) . A) . A*) . P_up, the order of an
+   enlarged corner's chain (T4 . A . A* alone would hold D^8 chi^2 numbers).
 7. Renormalisation: each new tensor divided by its largest |entry|.
 """
 
@@ -78,9 +80,12 @@ PRODUCT = ("Rup", "Rdn", (3, 4, 5), (3, 4, 5))
 M_ROWS = (0, 1, 2)
 # the column's own pieces before projection
 C1T1 = ("C1", "T1", (1,), (0,))          # legs (C1.d, T1.k, T1.b, T1.r)
-T4A = ("T4", "A", (1,), (1,))            # legs (T4.t, T4.b, T4.bot, A.t, A.b, A.r, A.p)
-T4AA = ("T4A", "Ac", (1, 6), (1, 4))     # legs (T4.t, T4.bot, A.t, A.b, A.r, A*.t, A*.b, A*.r)
 C4T3 = ("C4", "T3", (1,), (0,))          # legs (C4.u, T3.k, T3.b, T3.r)
+# T4' as a chain from P_dn (legs (T4.bot-, A.b-, A*.b-type, k)):
+T4_CHAIN = [("Pdn", "T4", (0,), (0,)),           # Z1 (A.b', A*.b', k, T4.k, T4.b, T4.bot)
+            ("Z1", "A", (0, 3), (0, 1)),          # Z2 (A*.b', k, T4.b, T4.bot, A.b, A.r, A.p)
+            ("Z2", "Ac", (0, 2, 6), (0, 1, 4)),   # Z3 (k, T4.bot, A.b, A.r, A*.b, A*.r)
+            ("Z3", "Pup", (1, 2, 4), (0, 1, 2))]  # T4' (k, A.r, A*.r, k)
 
 
 def _td(x, y, ax, bx):
@@ -132,17 +137,13 @@ def left_move(env: dict, chi: int, tol: float = 0.0, deg_tol: float = 1e-10) -> 
     r["Vts"] = scale_new_leg(vt, svals, -0.5, 0)
     r["Pup"] = _td(r["Rdn"], dual(r["Vts"]), (0, 1, 2), (1, 2, 3))
     r["Pdn"] = _td(r["Rup"], dual(r["Us"]), (0, 1, 2), (0, 1, 2))
-    both = dict(env)
-    both["C1T1"] = _td(env[C1T1[0]], env[C1T1[1]], C1T1[2], C1T1[3])
-    both["T4A"] = _td(env[T4A[0]], env[T4A[1]], T4A[2], T4A[3])
-    both["T4AA"] = _td(both[T4AA[0]], env[T4AA[1]], T4AA[2], T4AA[3])
-    both["C4T3"] = _td(env[C4T3[0]], env[C4T3[1]], C4T3[2], C4T3[3])
-    for k in ("C1T1", "T4A", "T4AA", "C4T3"):
-        r[k] = both[k]
-    r["C1n"] = _td(r["Pup"], both["C1T1"], (0, 1, 2), (0, 1, 2))
-    r["Y"] = _td(r["Pdn"], both["T4AA"], (0, 1, 2), (0, 2, 5))
-    r["T4n"] = _td(r["Y"], r["Pup"], (1, 2, 4), (0, 1, 2))
-    r["C4n"] = _td(r["Pdn"], both["C4T3"], (0, 1, 2), (0, 1, 2))
+    r["C1T1"] = _td(env[C1T1[0]], env[C1T1[1]], C1T1[2], C1T1[3])
+    r["C4T3"] = _td(env[C4T3[0]], env[C4T3[1]], C4T3[2], C4T3[3])
+    r["C1n"] = _td(r["Pup"], r["C1T1"], (0, 1, 2), (0, 1, 2))
+    r["C4n"] = _td(r["Pdn"], r["C4T3"], (0, 1, 2), (0, 1, 2))
+    both = dict(env, **r)
+    for out, (left, right, ax, bx) in zip(("Z1", "Z2", "Z3", "T4n"), T4_CHAIN):
+        both[out] = r[out] = _td(both[left], both[right], ax, bx)
     for k in ("C1n", "T4n", "C4n"):
         r[k + "_norm"] = normalise_max(r[k])
     return r

@@ -42,7 +42,13 @@ EXPORTS = ["yastn_plan", "yastn_plan_profile", "yastn_plan_cache_clear", "yastn_
            "yastn_perm_plan", "yastn_perm_output", "yastn_permute", "yastn_perm_free",
            "yastn_grad_plan", "yastn_grad_output", "yastn_grad_workspace", "yastn_grad", "yastn_grad_free",
            "yastn_svd_plan", "yastn_svd_info", "yastn_svd_sector", "yastn_svd", "yastn_svd_output",
-           "yastn_svd_factors", "yastn_svd_free"]
+           "yastn_svd_factors", "yastn_svd_factors_scaled", "yastn_svd_free",
+           "yastn_ctm_plan", "yastn_ctm_move", "yastn_ctm_tensor", "yastn_ctm_copy", "yastn_ctm_info",
+           "yastn_ctm_free"]
+CTM_NAMES = ("Q1", "Q2", "Q3", "Q4", "Rup", "Rdn", "M", "Us", "Vts", "Pup", "Pdn", "C1T1", "C4T3", "Z1", "Z2",
+             "Z3", "C1n", "T4n", "C4n", "C1", "T4", "C4")
+CTM_INPUTS = ("C1", "C2", "C3", "C4", "T1", "T2", "T3", "T4", "A")
+CTM_AUTOTUNE = 1
 REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 MAX_CHAIN = 8
 NUM_VARIANTS = 24
@@ -175,11 +181,23 @@ def lib():
         L.yastn_svd_output.argtypes = [C.c_void_p, C.POINTER(TensorDesc), C.POINTER(C.c_int64),
                                        C.POINTER(TensorDesc), C.POINTER(C.c_int64)]
         L.yastn_svd_factors.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.yastn_svd_factors_scaled.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
+                                               C.c_void_p, C.c_void_p]
         L.yastn_svd_free.argtypes = [C.c_void_p]
         L.yastn_svd_free.restype = None
+        L.yastn_ctm_plan.argtypes = [C.POINTER(TensorDesc), C.c_void_p, C.POINTER(C.c_void_p)]
+        L.yastn_ctm_move.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.c_int32, C.c_double, C.c_double,
+                                     C.c_int32, C.c_void_p]
+        L.yastn_ctm_tensor.argtypes = [C.c_void_p, C.c_int32, C.POINTER(TensorDesc), C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_void_p)]
+        L.yastn_ctm_copy.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+        L.yastn_ctm_info.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+        L.yastn_ctm_free.argtypes = [C.c_void_p]
+        L.yastn_ctm_free.restype = None
         for f in ("yastn_perm_plan", "yastn_perm_output", "yastn_permute", "yastn_grad_plan", "yastn_grad_output",
                   "yastn_grad_workspace", "yastn_grad", "yastn_svd_plan", "yastn_svd_info", "yastn_svd_sector",
-                  "yastn_svd", "yastn_svd_output", "yastn_svd_factors"):
+                  "yastn_svd", "yastn_svd_output", "yastn_svd_factors", "yastn_svd_factors_scaled",
+                  "yastn_ctm_plan", "yastn_ctm_move", "yastn_ctm_tensor", "yastn_ctm_copy", "yastn_ctm_info"):
             getattr(L, f).restype = C.c_int32
         for f in ("yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats",
                   "yastn_contract", "yastn_contract_noalloc", "yastn_contract_norm", "yastn_contract_timed",
@@ -542,13 +560,64 @@ class Svd:
         _check(lib().yastn_svd_output(self._h, C.byref(du), C.byref(nu), C.byref(dv), C.byref(nv)))
         return _structure(du, nu), _structure(dv, nv)
 
-    def factors(self, u, vt, workspace, stream=None):
-        _check(lib().yastn_svd_factors(self._h, C.c_void_p(_ptr(u)), C.c_void_p(_ptr(vt)),
-                                       C.c_void_p(_ptr(workspace)), C.c_void_p(_stream(stream))))
+    def factors(self, u, vt, workspace, stream=None, pu=0.0, pv=0.0):
+        """Kept factors into u and vt (device); U's column t times S_t^pu,
+        V^T's row t times S_t^pv."""
+        _check(lib().yastn_svd_factors_scaled(self._h, C.c_void_p(_ptr(u)), C.c_void_p(_ptr(vt)), float(pu),
+                                              float(pv), C.c_void_p(_ptr(workspace)),
+                                              C.c_void_p(_stream(stream))))
 
     def free(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().yastn_svd_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Ctm:
+    """One CTM left move on the device (yastn_ctm_*).  ``env``: the nine
+    input structures C1, C2, C3, C4, T1, T2, T3, T4, A (CTM_INPUTS order)."""
+
+    def __init__(self, env, stream=None):
+        keep = _Keep()
+        arr = (TensorDesc * 9)(*[_desc(t, keep) for t in env])
+        h = C.c_void_p()
+        _check(lib().yastn_ctm_plan(arr, C.c_void_p(_stream(stream)), C.byref(h)))
+        self._h = h
+
+    def move(self, env, chi, tol=0.0, deg_tol=1e-10, autotune=False, stream=None):
+        """Run one move on the nine device buffers ``env``; returns when done."""
+        ptrs = (C.c_void_p * 9)(*[_ptr(x) for x in env])
+        _check(lib().yastn_ctm_move(self._h, ptrs, int(chi), float(tol), float(deg_tol),
+                                    CTM_AUTOTUNE if autotune else 0, C.c_void_p(_stream(stream))))
+
+    def tensor(self, name):
+        """(structure, numel) of a tensor of the move (CTM_NAMES)."""
+        d, n, p = TensorDesc(), C.c_int64(), C.c_void_p()
+        _check(lib().yastn_ctm_tensor(self._h, CTM_NAMES.index(name), C.byref(d), C.byref(n), C.byref(p)))
+        return _structure(d, n)
+
+    def copy(self, name, dst, stream=None):
+        """Copy a tensor's values into dst (device, >= numel FP64)."""
+        _check(lib().yastn_ctm_copy(self._h, CTM_NAMES.index(name), C.c_void_p(_ptr(dst)),
+                                    C.c_void_p(_stream(stream))))
+
+    def info(self):
+        """(kept values, Jacobi sweeps, [ms corners, halves+product, SVD,
+        projectors+column, normalisation]) of the last move."""
+        k, sw = C.c_int32(), C.c_int32()
+        ms = (C.c_double * 5)()
+        _check(lib().yastn_ctm_info(self._h, C.byref(k), C.byref(sw), ms))
+        return int(k.value), int(sw.value), [float(x) for x in ms]
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().yastn_ctm_free(self._h)
             self._h = C.c_void_p()
 
     def __del__(self):

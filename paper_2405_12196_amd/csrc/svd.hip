@@ -28,7 +28,13 @@
 //  k_svd_*       the global truncation: values at or below tol x max are
 //                dropped; if more than chi remain and c is the (chi+1)-th
 //                largest, a value is kept iff it exceeds c (1 + deg_tol).
-//  k_svd_write   the kept columns of U and rows of V^T as block tensors.
+//  k_svd_gauge   the sign of each kept pair (u_t, v_t): the one whose u_t
+//                has its entry of largest magnitude (the first such in row
+//                order) positive, so the factors are unique for distinct
+//                values.
+//  k_svd_write   the kept columns of U and rows of V^T as block tensors, with
+//                that sign and, on request, column / row t scaled by S_t^p
+//                (p = -1/2 gives the CTM projector factors).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -453,20 +459,78 @@ __global__ void __launch_bounds__(256) k_svd_kept(const DevSvdSector *sec, int n
   }
 }
 
-// U block (kind 0): element (r, t) = src[r * ld + perm[t]], out row-major
-// a x b (b = t kept); V^T block (kind 1): element (t, c) = src[c * ld +
-// perm[t]], out row-major a x b (a = kept)
+// sign of kept pair t of a sector: u_t = column perm[t] of U (W, or V for a
+// sector stored transposed), rows 0 .. mU-1; the entry of largest |u| (the
+// first in row order on ties) decides.  One wave per kept pair, lanes stride
+// the rows, then a butterfly over (|u|, row) that keeps the larger magnitude
+// and, at equal magnitude, the smaller row.
+__global__ void __launch_bounds__(256) k_svd_gauge(const DevSvdSector *sec, int nsec, const double *ws,
+                                                   const int32_t *perm, const int32_t *kept, double *sign) {
+  const int lane = threadIdx.x & 63;
+  for (int k = blockIdx.y; k < nsec; k += gridDim.y) {
+    const DevSvdSector S = sec[k];
+    const double *U = ws + (S.trans ? S.v_off : S.w_off);
+    const int mU = S.trans ? S.cols : S.rows;
+    const int nk = kept[k];
+    for (int t = blockIdx.x * 4 + (threadIdx.x >> 6); t < nk; t += gridDim.x * 4) {
+      const int j = perm[S.sv0 + t];
+      double best = -1.0, val = 0.0;
+      int row = 0x7fffffff;
+      for (int r = lane; r < mU; r += 64) {
+        const double x = U[(int64_t)r * S.ld + j];
+        if (fabs(x) > best) {  // rows ascend per lane: the first maximum stays
+          best = fabs(x);
+          val = x;
+          row = r;
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64), ov = __shfl_xor(val, o, 64);
+        const int orow = __shfl_xor(row, o, 64);
+        if (ob > best || (ob == best && orow < row)) {
+          best = ob;
+          val = ov;
+          row = orow;
+        }
+      }
+      if (lane == 0) sign[S.sv0 + t] = val < 0.0 ? -1.0 : 1.0;
+    }
+  }
+}
+
+__device__ __forceinline__ double sv_power(double s, double p) {
+  if (p == 0.0) return 1.0;
+  if (p == -0.5) return 1.0 / sqrt(s);
+  if (p == 0.5) return sqrt(s);
+  return pow(s, p);
+}
+
+// U block (kind 0): element (r, t) = sign_t S_t^pu src[r * ld + perm[t]], out
+// row-major a x b (b = t kept); V^T block (kind 1): element (t, c) = sign_t
+// S_t^pv src[c * ld + perm[t]], out row-major a x b (a = kept).  S_t is the
+// sector's t-th largest value, sv_raw[sv0 + perm[sv0 + t]].
 __global__ void __launch_bounds__(256) k_svd_write(const DevSvdOut *__restrict__ items, int nitems,
                                                    const double *__restrict__ ws, const int32_t *__restrict__ perm,
+                                                   const double *__restrict__ sv_raw,
+                                                   const double *__restrict__ sign, double pu, double pv,
                                                    double *__restrict__ u, double *__restrict__ vt) {
+  __shared__ double fac[512];
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const DevSvdOut o = items[it];
     const int64_t n = (int64_t)o.a * o.b;
     double *out = o.kind == 0 ? u : vt;
+    const int nt = o.kind == 0 ? o.b : o.a;
+    const double p = o.kind == 0 ? pu : pv;
+    __syncthreads();
+    for (int t = threadIdx.x; t < nt && t < 512; t += 256)
+      fac[t] = sign[o.sv0 + t] * sv_power(sv_raw[o.sv0 + perm[o.sv0 + t]], p);
+    __syncthreads();
     for (int64_t e = threadIdx.x; e < n; e += 256) {
       const int32_t x = (int32_t)(e / o.b), y = (int32_t)(e - (int64_t)x * o.b);
       const int32_t r = o.kind == 0 ? x : y, t = o.kind == 0 ? y : x;
-      out[o.out_off + e] = ws[o.src_off + (int64_t)r * o.ld + perm[o.sv0 + t]];
+      const double f = t < 512 ? fac[t] : sign[o.sv0 + t] * sv_power(sv_raw[o.sv0 + perm[o.sv0 + t]], p);
+      out[o.out_off + e] = f * ws[o.src_off + (int64_t)r * o.ld + perm[o.sv0 + t]];
     }
   }
 }
@@ -495,7 +559,7 @@ struct SvdPlanImpl {
   int64_t nsv = 0;
   int max_rounds = 1, total_pairs = 0;
   size_t ws_bytes = 0;
-  size_t off_sv_raw = 0, off_perm = 0, off_conv = 0, off_done = 0, off_stat = 0, off_flag = 0;
+  size_t off_sv_raw = 0, off_perm = 0, off_conv = 0, off_done = 0, off_stat = 0, off_flag = 0, off_sign = 0;
   void *dev_mem = nullptr;  // sectors, gather blocks and tiles
   DevSvdSector *d_sec = nullptr;
   DevSvdGather *d_gather = nullptr;
@@ -653,6 +717,8 @@ yastn_status yastn_svd_plan(const yastn_tensor_desc *t, int32_t nrow, const int3
     off += al(4 * 8);
     P.off_flag = off;
     off += al(8);
+    P.off_sign = off;
+    off += al(size_t(std::max<int64_t>(1, P.nsv)) * 8);
     P.ws_bytes = off;
     // ---- gather items: one per block of T, W strides per leg
     std::vector<DevSvdGather> gat;
@@ -807,6 +873,8 @@ yastn_status yastn_svd(yastn_svd_t h, const void *t, int32_t chi, double tol, do
   hipLaunchKernelGGL(k_svd_cut, dim3(grid1(P.nsv, 256)), dim3(256), 0, st, sv, (int)P.nsv, chi, deg_tol, stat);
   int32_t *dkept = reinterpret_cast<int32_t *>(ws + P.off_done);  // done[] is free again
   hipLaunchKernelGGL(k_svd_kept, dim3(grid1(nsec, 256)), dim3(256), 0, st, P.d_sec, nsec, sv, stat, dkept);
+  hipLaunchKernelGGL(k_svd_gauge, dim3(8, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, W, perm, dkept,
+                     reinterpret_cast<double *>(ws + P.off_sign));
   SVD_HIP(hipGetLastError());
   SVD_HIP(hipMemcpyAsync(P.kept.data(), dkept, size_t(nsec) * 4, hipMemcpyDeviceToHost, st));
   SVD_HIP(hipStreamSynchronize(st));
@@ -924,21 +992,29 @@ yastn_status yastn_svd_output(yastn_svd_t h, yastn_tensor_desc *u, int64_t *u_nu
   return YASTN_OK;
 }
 
-yastn_status yastn_svd_factors(yastn_svd_t h, void *u, void *vt, const void *workspace, void *hip_stream) {
+yastn_status yastn_svd_factors_scaled(yastn_svd_t h, void *u, void *vt, double pu, double pv, const void *workspace,
+                                      void *hip_stream) {
   if (!h) return set_error(YASTN_ERR_ARG, "null plan");
   SvdPlanImpl &P = h->p;
   if (!P.have_kept) return set_error(YASTN_ERR_STATE, "no yastn_svd result yet");
   if ((P.u_numel > 0 && !u) || (P.v_numel > 0 && !vt) || (!P.outs.empty() && !workspace))
     return set_error(YASTN_ERR_ARG, "null buffer");
+  if (!std::isfinite(pu) || !std::isfinite(pv)) return set_error(YASTN_ERR_ARG, "powers must be finite");
   if (P.outs.empty()) return YASTN_OK;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   const char *ws = reinterpret_cast<const char *>(workspace);
   hipLaunchKernelGGL(k_svd_write, dim3(std::min<int>((int)P.outs.size(), 65535)), dim3(256), 0, st,
                      reinterpret_cast<const DevSvdOut *>(P.out_mem), (int)P.outs.size(),
                      reinterpret_cast<const double *>(ws), reinterpret_cast<const int32_t *>(ws + P.off_perm),
-                     reinterpret_cast<double *>(u), reinterpret_cast<double *>(vt));
+                     reinterpret_cast<const double *>(ws + P.off_sv_raw),
+                     reinterpret_cast<const double *>(ws + P.off_sign), pu, pv, reinterpret_cast<double *>(u),
+                     reinterpret_cast<double *>(vt));
   SVD_HIP(hipGetLastError());
   return YASTN_OK;
+}
+
+yastn_status yastn_svd_factors(yastn_svd_t h, void *u, void *vt, const void *workspace, void *hip_stream) {
+  return yastn_svd_factors_scaled(h, u, vt, 0.0, 0.0, workspace, hip_stream);
 }
 
 void yastn_svd_free(yastn_svd_t h) {

@@ -1,0 +1,184 @@
+"""Parity of the CTM left move on the device (yastn_ctm_*) with the oracle
+(oracle/ctm.py).
+
+Small cases (U(1), Z2, U(1)xU(1), and a U(1) case whose corners span several
+tiles with ragged edges): every tensor of the move, intermediates included,
+against the oracle's move element by element -- structures bit for bit,
+values within 1e-12 of the tensor's largest entry before the SVD and 1e-10
+after it (the factors of a value sigma_k carry the SVD's error, of order
+eps sigma_max / (gap to the nearest other value), and the projectors divide by
+sqrt(sigma_k)).  The SVD's signs are fixed by the same rule on both sides
+(u_k's largest entry positive); each case checks that the oracle's largest
+and second-largest |u| entries are far enough apart for that rule to decide
+the same way in both.
+
+Full size (chi = 128, D = 8, U(1)xU(1), the benchmark's workload, plans
+autotuned as there): every contraction's structure in full and sampled
+output blocks against the oracle on the GPU's own inputs of that step, the
+SVD's scaled factors against the oracle's SVD of the GPU's four-corner
+product, and the normalisation exactly.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import ctm as OC
+from oracle import svd as OS
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU hosts deselect -m gpu
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2405_12196_amd as Y  # noqa: E402
+from tests import gpu_util as G  # noqa: E402
+
+PRE = ("Q1", "Q2", "Q3", "Q4", "Rup", "Rdn", "M", "C1T1", "C4T3")
+POST = ("Us", "Vts", "Pup", "Pdn", "Z1", "Z2", "Z3", "C1n", "T4n", "C4n", "C1", "T4", "C4")
+ORACLE_NAME = {"C1": "C1n_norm", "T4": "T4n_norm", "C4": "C4n_norm"}
+
+
+def gpu_move(env, chi, tol=0.0, deg_tol=1e-10, autotune=False, names=PRE + POST):
+    ctm = Y.Ctm([env[k] for k in Y.CTM_INPUTS])
+    dev = [G.upload(env[k]) for k in Y.CTM_INPUTS]
+    ctm.move(dev, chi, tol, deg_tol, autotune=autotune)
+    out = {}
+    for k in names:
+        s = ctm.tensor(k)
+        buf = torch.full((max(1, s.numel),), float("nan"), dtype=torch.float64, device=G.DEV)
+        ctm.copy(k, buf)
+        torch.cuda.synchronize()
+        out[k] = (s, buf.cpu().numpy()[:s.numel])
+    return ctm, out
+
+
+def _gauge_margin(r):
+    """Smallest relative gap between the largest and second-largest |u|
+    entries over the oracle's kept columns (the sign rule's margin)."""
+    worst = np.inf
+    for X, (Ux, _, _) in OS.sector_matrices(r["U"], (0, 1, 2)).items():
+        for k in range(Ux.shape[1]):
+            col = np.sort(np.abs(Ux[:, k]))[::-1]
+            if col.size > 1:
+                worst = min(worst, (col[0] - col[1]) / col[0])
+    return worst
+
+
+def compare(name, got, ref, tol):
+    s, vals = got
+    assert G.structure_equal(s, ref), f"{name}: structure differs from the oracle"
+    if ref.data.size == 0:
+        return 0.0
+    scale = float(np.max(np.abs(ref.data)))
+    err = float(np.max(np.abs(vals - ref.data))) / max(scale, 1e-300)
+    assert np.all(np.isfinite(vals)), f"{name}: unwritten elements"
+    assert err <= tol, f"{name}: max error {err:.3e} of the largest entry"
+    return err
+
+
+CASES = [("u1", None), ("u1", -2), ("z2", None), ("u1xu1", None), ("u1xu1", 1), ("u1_mid", None), ("u1_mid", 4)]
+
+
+@pytest.mark.parametrize("name,dchi", CASES)
+def test_ctm_move_every_tensor_small(name, dchi):
+    env = W.ctm_move_small(name)
+    chi = env["chi"] if dchi is None else (dchi if dchi > 0 else env["chi"] + dchi)
+    ref = OC.left_move(env, chi)
+    assert _gauge_margin(ref) > 1e-6
+    ctm, got = gpu_move(env, chi)
+    for k in PRE:
+        compare(k, got[k], ref[k], 1e-12)
+    for k in POST:
+        compare(k, got[k], ref[ORACLE_NAME.get(k, k)], 1e-10)
+    kept, sweeps, ms = ctm.info()
+    assert kept == sum(ref["kept"].values())
+    assert sweeps >= 1 and len(ms) == 5 and all(x >= 0 for x in ms)
+
+
+def test_ctm_move_chi_zero_gives_empty_column():
+    env = W.ctm_move_small("u1")
+    ctm, got = gpu_move(env, 0, names=("Us", "Pup", "C1n", "T4n", "C1", "T4", "C4"))
+    ref = OC.left_move(env, 0)
+    for k in ("C1", "T4", "C4"):
+        assert got[k][0].nblocks == 0 and got[k][0].numel == 0
+        assert G.structure_equal(got[k][0], ref[ORACLE_NAME[k]])
+    assert ctm.info()[0] == 0
+
+
+def test_ctm_move_repeat_is_bitwise_and_tol_floor():
+    env = W.ctm_move_small("u1_mid")
+    _, a = gpu_move(env, 12)
+    ctm, b = gpu_move(env, 12)
+    for k in ("C1", "T4", "C4", "M"):
+        assert np.array_equal(a[k][1], b[k][1])
+    # a floor that drops values before chi does
+    ref = OC.left_move(env, 1000, tol=1e-3)
+    _, c = gpu_move(env, 1000, tol=1e-3, names=("Us", "C1", "T4", "C4"))
+    for k in ("Us", "C1", "T4", "C4"):
+        compare(k, c[k], ref[ORACLE_NAME.get(k, k)], 1e-10)
+
+
+def test_ctm_plan_rejects_a_broken_network():
+    env = W.ctm_move_small("u1")
+    bad = [env[k] for k in Y.CTM_INPUTS]
+    bad[4], bad[5] = bad[5], bad[4]  # T1 and T2 exchanged: signatures no longer dual
+    with pytest.raises(Y.YastnError) as e:
+        Y.Ctm(bad)
+    assert e.value.status in ("ERR_SIGNATURE", "ERR_SHAPE")
+
+
+# ------------------------------------------------------------ full size
+def _bt(got):
+    return G.as_block_tensor(*got)
+
+
+STEPS = {  # out: (left, right, axes_left, axes_right), the move's contractions
+    "Q1": None, "C1T1": ("C1", "T1", (1,), (0,)), "C4T3": ("C4", "T3", (1,), (0,)),
+    "Rup": ("Q2", "Q1", (1, 2, 4), (0, 3, 5)), "Rdn": ("Q3", "Q4", (0, 3, 5), (1, 3, 5)),
+    "M": ("Rup", "Rdn", (3, 4, 5), (3, 4, 5)),
+    "C1n": ("Pup", "C1T1", (0, 1, 2), (0, 1, 2)), "C4n": ("Pdn", "C4T3", (0, 1, 2), (0, 1, 2)),
+    "Z1": ("Pdn", "T4", (0,), (0,)), "Z2": ("Z1", "A", (0, 3), (0, 1)), "Z3": ("Z2", "Ac", (0, 2, 6), (0, 1, 4)),
+    "T4n": ("Z3", "Pup", (1, 2, 4), (0, 1, 2)),
+}
+
+
+def test_ctm_move_chi128_full_size_sampled():
+    from tests.test_gpu_fullsize import check_sampled
+    env = W.ctm_move_u1xu1(128)
+    names = PRE + POST
+    ctm, got = gpu_move(env, 128, autotune=True, names=names)
+    T = {k: _bt(v) for k, v in got.items()}
+    T.update({k: env[k] for k in Y.CTM_INPUTS})
+    T["Ac"] = env["Ac"]
+    # the corners: Q1 in full against the oracle's chain; the others sampled per step
+    ref_q1 = OC.enlarged_corner(env, "Q1")
+    compare("Q1", got["Q1"], ref_q1, 1e-12)
+    for q in ("Q2", "Q3", "Q4"):
+        cur = None
+        for i, (left, right, ax, bx) in enumerate(OC.CORNER_CHAINS[q]):
+            a = T[left] if left else cur
+            if i < 3:
+                cur = OC._td(a, T[right], ax, bx)
+            else:
+                check_sampled(a, T[right], ax, bx, got[q][0], got[q][1], 6, 11)
+    for k, (left, right, ax, bx) in ((k, v) for k, v in STEPS.items() if v):
+        if k in ("Pup", "Pdn"):
+            continue
+        check_sampled(T[left], T[right], ax, bx, got[k][0], got[k][1], 6, 17)
+    # the SVD of the GPU's four-corner product: scaled factors in full
+    u, svals, vt, kept = OS.svd_truncated(T["M"], (0, 1, 2), 128)
+    assert sum(kept.values()) == 128 == ctm.info()[0]
+    compare("Us", got["Us"], OC.scale_new_leg(u, svals, -0.5, u.rank - 1), 1e-10)
+    compare("Vts", got["Vts"], OC.scale_new_leg(vt, svals, -0.5, 0), 1e-10)
+    check_sampled(T["Rdn"], oracle.dual(T["Vts"]), (0, 1, 2), (1, 2, 3), got["Pup"][0], got["Pup"][1], 8, 5,
+                  tol=1e-11)
+    check_sampled(T["Rup"], oracle.dual(T["Us"]), (0, 1, 2), (0, 1, 2), got["Pdn"][0], got["Pdn"][1], 8, 5,
+                  tol=1e-11)
+    # the normalisation: division by the largest |entry|, exactly
+    for k, src in (("C1", "C1n"), ("T4", "T4n"), ("C4", "C4n")):
+        x = got[src][1]
+        assert np.array_equal(got[k][1], x / np.max(np.abs(x)))
+    print("chi128 move ms:", [round(v, 3) for v in ctm.info()[2]], flush=True)

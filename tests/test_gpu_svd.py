@@ -25,7 +25,7 @@ import paper_2405_12196_amd as Y  # noqa: E402
 from tests import gpu_util as G  # noqa: E402
 
 
-def gpu_svd(t, rows, chi, tol=0.0, deg_tol=1e-10):
+def gpu_svd(t, rows, chi, tol=0.0, deg_tol=1e-10, pu=0.0, pv=0.0):
     sv = Y.Svd(t, rows)
     tdev = G.upload(t)
     ws = torch.empty(max(256, sv.workspace_bytes), dtype=torch.uint8, device=G.DEV)
@@ -34,7 +34,7 @@ def gpu_svd(t, rows, chi, tol=0.0, deg_tol=1e-10):
     us, vs = sv.output()
     u = torch.full((max(1, us.numel),), float("nan"), dtype=torch.float64, device=G.DEV)
     vt = torch.full((max(1, vs.numel),), float("nan"), dtype=torch.float64, device=G.DEV)
-    sv.factors(u, vt, ws)
+    sv.factors(u, vt, ws, pu=pu, pv=pv)
     torch.cuda.synchronize()
     return sv, svals.cpu().numpy()[:sv.nsv], kept, sweeps, (us, u.cpu().numpy()[:us.numel]), \
         (vs, vt.cpu().numpy()[:vs.numel])
@@ -86,7 +86,37 @@ def check_svd(t, rows, chi, tol=0.0, deg_tol=1e-10, tol_sv=1e-12, tol_rec=1e-11)
         assert float(np.linalg.norm(got - ref)) / den <= tol_rec, f"sector {X}: truncated product"
         assert np.allclose(Uk.T @ Uk, np.eye(kx), atol=tol_rec)
         assert np.allclose(Vk @ Vk.T, np.eye(kx), atol=tol_rec)
+    # with the sign rule on both sides the factors themselves agree, where the
+    # rule's margin (largest vs second-largest |u|) and the kept values' gaps
+    # leave no room for rounding to decide differently
+    if _margins_ok(dec, kept, list(mats)):
+        compare_blocks(us, u, u_ref, 1e-9)
+        compare_blocks(vs, vt, vt_ref, 1e-9)
     return sv, kept, sweeps
+
+
+def _margins_ok(dec, kept, order):
+    for k, X in enumerate(order):
+        U, s, _ = dec[X]
+        kx = kept[k]
+        if kx == 0:
+            continue
+        if kx < s.size and (s[kx - 1] - s[kx]) <= 1e-6 * s[0]:
+            return False
+        if np.any(np.diff(s[:kx]) >= -1e-6 * s[0]):
+            return False
+        for j in range(kx):
+            col = np.sort(np.abs(U[:, j]))[::-1]
+            if col.size > 1 and col[0] - col[1] <= 1e-6 * col[0]:
+                return False
+    return True
+
+
+def compare_blocks(s, vals, ref, tol):
+    assert G.structure_equal(s, ref)
+    if ref.data.size:
+        err = float(np.max(np.abs(vals - ref.data)))
+        assert err <= tol * max(1.0, float(np.max(np.abs(ref.data)))), f"factor values off by {err:.3e}"
 
 
 @pytest.mark.parametrize("seed,sym,rank,rows,n", CASES)
@@ -125,6 +155,21 @@ def test_svd_ctm_corner_chi128():
     sv, kept, sweeps = check_svd(cur, (0, 3, 5), chi=128)
     assert sum(kept) == 128
     print(f"corner SVD: {sv.nsectors} sectors, {sv.nsv} values, {sweeps} sweeps", flush=True)
+
+
+def test_svd_scaled_factors():
+    """U's kept column t times S_t^pu and V^T's row t times S_t^pv (the CTM
+    projectors take -1/2 and -1/2)."""
+    from oracle import ctm as OC
+    t = _random_tensor(4, "U1xU1", 4, None)
+    rows = (0, 3)
+    u_ref, S_ref, vt_ref, _ = OS.svd_truncated(t, rows, 12)
+    dec = OS.svd_sectors(t, rows)
+    for pu, pv in ((-0.5, -0.5), (1.0, 0.25)):
+        sv, svals, kept, sweeps, (us, u), (vs, vt) = gpu_svd(t, rows, 12, pu=pu, pv=pv)
+        assert _margins_ok(dec, kept, [X for X, *_ in sv.sectors])
+        compare_blocks(us, u, OC.scale_new_leg(u_ref, S_ref, pu, u_ref.rank - 1), 1e-9)
+        compare_blocks(vs, vt, OC.scale_new_leg(vt_ref, S_ref, pv, 0), 1e-9)
 
 
 def test_svd_repeat_bitwise():
