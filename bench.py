@@ -556,6 +556,48 @@ def svd_section(torch, Y, last, last_struct, sp, chi=128, reps=5):
     return res
 
 
+def ctm_section(torch, Y, W, sp, chi=128, reps=5):
+    """One CTM left move (yastn_ctm_move) at chi = 128, D = 8, U(1)xU(1): four
+    enlarged corners, halves, four-corner product, truncated SVD to chi,
+    projectors, the new left column, FP64 normalisation, all on the device
+    from resident inputs.  The first move plans what follows the SVD and
+    autotunes every contraction plan; the timed moves repeat it with the
+    plans cached (the steady state of CTM, whose structure repeats).
+    Median wall time of ``reps`` moves, each returning when done (the move
+    waits for the SVD's kept counts), and the median per-phase event times."""
+    env = W.ctm_move_u1xu1(chi)
+    ctm = Y.Ctm([env[k] for k in Y.CTM_INPUTS], stream=sp)
+    dev = [torch.from_numpy(env[k].data).to("cuda:0") for k in Y.CTM_INPUTS]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctm.move(dev, chi, autotune=True, stream=sp)
+    first = (time.perf_counter() - t0) * 1e3
+    walls, phases = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctm.move(dev, chi, stream=sp)
+        walls.append((time.perf_counter() - t0) * 1e3)
+        kept, sweeps, ms, flops = ctm.info()
+        phases.append(ms)
+    med = np.median(np.array(phases), axis=0)
+    names = ("corners", "halves_and_product", "svd", "plans_after_svd_and_factors", "projectors_and_column",
+             "normalisation")
+    contr_ms = float(med[0] + med[1] + med[4])
+    res = {"ms": round(float(np.median(walls)), 3), "first_move_ms_with_autotune": round(first, 1),
+           "phases_ms": {n: round(float(v), 3) for n, v in zip(names, med)},
+           "chi": chi, "kept": kept, "sweeps": sweeps,
+           "useful_GFLOP": {"before_svd": round(flops[0] / 1e9, 3), "after_svd": round(flops[1] / 1e9, 3)},
+           "contractions_TFs": round((flops[0] + flops[1]) / (contr_ms * 1e-3) / 1e12, 3),
+           "svd_to_contractions": round(float(med[2]) / contr_ms, 2),
+           "contraction_launches": 11,
+           "timing": f"median of {reps} moves after one autotuned move; wall time per move, phases from HIP events"}
+    ctm.free()
+    del dev
+    torch.cuda.empty_cache()
+    return res
+
+
 def serving_section(torch, Y, W, sp, nreq=2000, warm=200, budget_gib=32, seed=5):
     """32 concurrent CTM runs (16 Z2, 16 U(1); D in {4,6,8,10} x chi in
     {64,128,192,256}) submit enlarged-corner requests with Poisson arrivals to
@@ -720,6 +762,8 @@ def main():
                          "for profiling")
     ap.add_argument("--svd-only", action="store_true",
                     help="run only the truncated SVD of the chi = 128 corner and print its record; for profiling")
+    ap.add_argument("--ctm-only", action="store_true",
+                    help="run only the CTM left move at chi = 128 and print its record; for profiling")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -772,6 +816,10 @@ def main():
         ch.step(sp)
         torch.cuda.synchronize()
         print(json.dumps({"svd": svd_section(torch, Y, ch.outs[-1], ch.plans[-1].output(0), sp)}))
+        return
+    if args.ctm_only:
+        sp = int(torch.cuda.current_stream().cuda_stream)
+        print(json.dumps({"ctm_move": ctm_section(torch, Y, W, sp, reps=max(1, args.steps))}))
         return
     dev = "cuda:0"
     torch.cuda.set_device(0)
@@ -959,6 +1007,7 @@ def main():
                   "batched": batch_section(torch, Y, W, ev, sp),
                   "gradient": grad_section(torch, Y, W, ev, sp),
                   "svd": svd_section(torch, Y, outs[-1], plans[-1].output(0), sp),
+                  "ctm_move": ctm_section(torch, Y, W, sp),
                   "serving": serving_section(torch, Y, W, sp, nreq=args.serve_requests, warm=args.serve_warmup)}
 
     rec = {

@@ -491,10 +491,14 @@ void yastn_svd_free(yastn_svd_t s);
  * tuned yet and keeps the fastest.  The results stay in the handle's memory
  * until the next move or yastn_ctm_free; yastn_ctm_tensor gives any tensor
  * of the move (YASTN_CTM_* below): its structure (arrays owned by the handle)
- * and its device buffer.  yastn_ctm_info: kept values (sum over sectors),
- * Jacobi sweeps, and the time of each phase of the last move in ms
- * (ms[0] corners, ms[1] halves and product, ms[2] SVD, ms[3] projectors and
- * the new column, ms[4] normalisation), from HIP events on hip_stream. */
+ * and its device buffer; yastn_ctm_copy copies a tensor's values (numel FP64)
+ * into dst [device] on hip_stream (async).  yastn_ctm_info [host outputs, each
+ * may be NULL]: kept values (sum over sectors), Jacobi sweeps, the time of
+ * each phase of the last move in ms from HIP events on hip_stream (ms[0]
+ * corners, ms[1] halves and product, ms[2] SVD, ms[3] the plans after the
+ * SVD and the scaled factors, ms[4] projectors and the new column, ms[5]
+ * normalisation), and the useful flops of its contractions (flops[0] before
+ * the SVD, flops[1] after; sums of 2 m k n over matched block pairs). */
 typedef struct yastn_ctm_s *yastn_ctm_t;
 enum {
   YASTN_CTM_Q1 = 0, YASTN_CTM_Q2, YASTN_CTM_Q3, YASTN_CTM_Q4, YASTN_CTM_RUP, YASTN_CTM_RDN, YASTN_CTM_M,
@@ -511,7 +515,7 @@ yastn_status yastn_ctm_move(yastn_ctm_t h, const void *const *env, int32_t chi, 
 yastn_status yastn_ctm_tensor(yastn_ctm_t h, int32_t which, yastn_tensor_desc *desc, int64_t *numel,
                               const void **data);
 yastn_status yastn_ctm_copy(yastn_ctm_t h, int32_t which, void *dst, void *hip_stream);
-yastn_status yastn_ctm_info(yastn_ctm_t h, int32_t *kept, int32_t *sweeps, double *ms);
+yastn_status yastn_ctm_info(yastn_ctm_t h, int32_t *kept, int32_t *sweeps, double *ms, double *flops);
 void yastn_ctm_free(yastn_ctm_t h);
 
 const char *yastn_last_error(void);

@@ -191,7 +191,8 @@ def lib():
         L.yastn_ctm_tensor.argtypes = [C.c_void_p, C.c_int32, C.POINTER(TensorDesc), C.POINTER(C.c_int64),
                                        C.POINTER(C.c_void_p)]
         L.yastn_ctm_copy.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
-        L.yastn_ctm_info.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+        L.yastn_ctm_info.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double)]
         L.yastn_ctm_free.argtypes = [C.c_void_p]
         L.yastn_ctm_free.restype = None
         for f in ("yastn_perm_plan", "yastn_perm_output", "yastn_permute", "yastn_grad_plan", "yastn_grad_output",
@@ -608,12 +609,14 @@ class Ctm:
                                     C.c_void_p(_stream(stream))))
 
     def info(self):
-        """(kept values, Jacobi sweeps, [ms corners, halves+product, SVD,
-        projectors+column, normalisation]) of the last move."""
+        """(kept values, Jacobi sweeps, [ms: corners, halves + product, SVD,
+        plans after the SVD + scaled factors, projectors + column,
+        normalisation], [useful flops before the SVD, after]) of the last move."""
         k, sw = C.c_int32(), C.c_int32()
-        ms = (C.c_double * 5)()
-        _check(lib().yastn_ctm_info(self._h, C.byref(k), C.byref(sw), ms))
-        return int(k.value), int(sw.value), [float(x) for x in ms]
+        ms = (C.c_double * 6)()
+        fl = (C.c_double * 2)()
+        _check(lib().yastn_ctm_info(self._h, C.byref(k), C.byref(sw), ms, fl))
+        return int(k.value), int(sw.value), [float(x) for x in ms], [float(x) for x in fl]
 
     def free(self):
         if getattr(self, "_h", None) is not None and self._h.value:

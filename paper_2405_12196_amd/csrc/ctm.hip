@@ -179,8 +179,9 @@ struct yastn_ctm_s {
   int64_t nsv = 0;
   std::vector<int32_t> kept;
   int32_t kept_total = 0, sweeps = 0;
-  double ms[5] = {0, 0, 0, 0, 0};
-  std::array<hipEvent_t, 6> ev{};
+  double ms[6] = {0, 0, 0, 0, 0, 0};
+  double flops[2] = {0, 0};
+  std::array<hipEvent_t, 7> ev{};
   bool have_result = false;
   int device = 0;
 };
@@ -375,6 +376,7 @@ yastn_status yastn_ctm_move(yastn_ctm_t h, const void *const *env, int32_t chi, 
   // ---- truncated SVD (waits for the kept counts), scaled factors
   CTM_TRY(yastn_svd(h->svd, h->s[kM].buf, chi, tol, deg_tol, h->sv, h->kept.data(), &h->sweeps, h->svd_ws,
                     hip_stream));
+  CTM_HIP(hipEventRecord(h->ev[3], st));
   h->kept_total = 0;
   for (int32_t k : h->kept) h->kept_total += k;
   yastn_tensor_desc u{}, vt{};
@@ -408,10 +410,10 @@ yastn_status yastn_ctm_move(yastn_ctm_t h, const void *const *env, int32_t chi, 
   h->s[kVtsD].buf = h->s[kVts].buf;
   CTM_TRY(grow_workspace(*h, h->post));
   CTM_TRY(yastn_svd_factors_scaled(h->svd, h->s[kUs].buf, h->s[kVts].buf, -0.5, -0.5, h->svd_ws, hip_stream));
-  CTM_HIP(hipEventRecord(h->ev[3], st));
+  CTM_HIP(hipEventRecord(h->ev[4], st));
   // ---- projectors and the new left column
   for (size_t l = 0; l < post.size(); ++l) CTM_TRY(run_level(*h, h->post[l], post[l], tune, st));
-  CTM_HIP(hipEventRecord(h->ev[4], st));
+  CTM_HIP(hipEventRecord(h->ev[5], st));
   // ---- each new tensor divided by its largest |entry|
   const int src[3] = {kC1n, kT4n, kC4n}, dst[3] = {kC1o, kT4o, kC4o};
   for (int i = 0; i < 3; ++i) {
@@ -423,12 +425,25 @@ yastn_status yastn_ctm_move(yastn_ctm_t h, const void *const *env, int32_t chi, 
                        h->norms + 2 * i);
     CTM_HIP(hipGetLastError());
   }
-  CTM_HIP(hipEventRecord(h->ev[5], st));
-  CTM_HIP(hipEventSynchronize(h->ev[5]));
-  for (int i = 0; i < 5; ++i) {
+  CTM_HIP(hipEventRecord(h->ev[6], st));
+  CTM_HIP(hipEventSynchronize(h->ev[6]));
+  for (int i = 0; i < 6; ++i) {
     float t = 0.f;
     CTM_HIP(hipEventElapsedTime(&t, h->ev[i], h->ev[i + 1]));
     h->ms[i] = t;
+  }
+  // useful flops of the contractions before and after the SVD
+  for (int half = 0; half < 2; ++half) {
+    h->flops[half] = 0.0;
+    for (auto p : half ? h->post : h->pre) {
+      int32_t np = 0;
+      CTM_TRY(yastn_plan_info(p, nullptr, &np));
+      for (int32_t i = 0; i < np; ++i) {
+        yastn_stats stt{};
+        CTM_TRY(yastn_plan_stats(p, i, &stt));
+        h->flops[half] += stt.useful_flops;
+      }
+    }
   }
   h->have_result = true;
   return YASTN_OK;
@@ -461,12 +476,13 @@ yastn_status yastn_ctm_copy(yastn_ctm_t h, int32_t which, void *dst, void *hip_s
   return YASTN_OK;
 }
 
-yastn_status yastn_ctm_info(yastn_ctm_t h, int32_t *kept, int32_t *sweeps, double *ms) {
+yastn_status yastn_ctm_info(yastn_ctm_t h, int32_t *kept, int32_t *sweeps, double *ms, double *flops) {
   if (!h) return set_error(YASTN_ERR_ARG, "null handle");
   if (!h->have_result) return set_error(YASTN_ERR_STATE, "no CTM move result yet");
   if (kept) *kept = h->kept_total;
   if (sweeps) *sweeps = h->sweeps;
   if (ms) std::memcpy(ms, h->ms, sizeof(h->ms));
+  if (flops) std::memcpy(flops, h->flops, sizeof(h->flops));
   return YASTN_OK;
 }
 

@@ -93,9 +93,36 @@ def test_ctm_move_every_tensor_small(name, dchi):
         compare(k, got[k], ref[k], 1e-12)
     for k in POST:
         compare(k, got[k], ref[ORACLE_NAME.get(k, k)], 1e-10)
-    kept, sweeps, ms = ctm.info()
+    kept, sweeps, ms, flops = ctm.info()
     assert kept == sum(ref["kept"].values())
-    assert sweeps >= 1 and len(ms) == 5 and all(x >= 0 for x in ms)
+    assert sweeps >= 1 and len(ms) == 6 and all(x >= 0 for x in ms)
+    pre = sum(oracle.structure_stats(*_operands(ref, env, k))["flops"] for k in PRE_STEPS)
+    post = sum(oracle.structure_stats(*_operands(ref, env, k))["flops"] for k in POST_STEPS)
+    assert flops == [pre, post]
+
+
+PRE_STEPS = ("Q1a", "Q1b", "Q1c", "Q1", "Q2a", "Q2b", "Q2c", "Q2", "Q3a", "Q3b", "Q3c", "Q3",
+             "Q4a", "Q4b", "Q4c", "Q4", "C4T3", "Rup", "Rdn", "M")
+POST_STEPS = ("Pup", "Pdn", "C1n", "C4n", "Z1", "Z2", "Z3", "T4n")
+
+
+def _operands(ref, env, k):
+    """(A, B, axes_a, axes_b) of the move's contraction that makes k, from
+    the oracle's tensors."""
+    both = dict(env, **ref)
+    if k[:2] in ("Q1", "Q2", "Q3", "Q4"):
+        chain = OC.CORNER_CHAINS[k[:2]]
+        i = "abc".index(k[2]) if len(k) == 3 else 3
+        cur = None
+        for left, right, ax, bx in chain[:i]:
+            cur = OC._td(both[left] if left else cur, both[right], ax, bx)
+        left, right, ax, bx = chain[i]
+        return (both[left] if left else cur, both[right], ax, bx)
+    if k in ("Pup", "Pdn"):
+        return ((both["Rdn"], oracle.dual(both["Vts"]), (0, 1, 2), (1, 2, 3)) if k == "Pup"
+                else (both["Rup"], oracle.dual(both["Us"]), (0, 1, 2), (0, 1, 2)))
+    left, right, ax, bx = STEPS[k]
+    return (both[left], both[right], ax, bx)
 
 
 def test_ctm_move_chi_zero_gives_empty_column():
@@ -136,7 +163,7 @@ def _bt(got):
 
 
 STEPS = {  # out: (left, right, axes_left, axes_right), the move's contractions
-    "Q1": None, "C1T1": ("C1", "T1", (1,), (0,)), "C4T3": ("C4", "T3", (1,), (0,)),
+    "Q1": None, "C4T3": ("C4", "T3", (1,), (0,)),
     "Rup": ("Q2", "Q1", (1, 2, 4), (0, 3, 5)), "Rdn": ("Q3", "Q4", (0, 3, 5), (1, 3, 5)),
     "M": ("Rup", "Rdn", (3, 4, 5), (3, 4, 5)),
     "C1n": ("Pup", "C1T1", (0, 1, 2), (0, 1, 2)), "C4n": ("Pdn", "C4T3", (0, 1, 2), (0, 1, 2)),
