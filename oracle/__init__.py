@@ -25,7 +25,9 @@ Implementations (each cites the passage of the paper it follows):
   * ``ctm.left_move``      one CTM move on a 1x1 unit cell: four enlarged
                            corners, the halves and their product, its
                            truncated SVD, the projectors, the renormalised
-                           left column.
+                           left column;
+  * ``fermionic.*``        complex conjugation, fermionic parity, swap gates,
+                           and the complex tensordot (O2 in complex128).
 
 Every function is pinned by tests that do not re-use its own formula (closed
 forms, the paper's worked example, brute force, special cases that reduce to
@@ -41,3 +43,4 @@ from .blocksparse import (  # noqa: F401
 )
 from . import svd  # noqa: F401
 from . import ctm  # noqa: F401
+from . import fermionic  # noqa: F401

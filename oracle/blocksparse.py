@@ -170,7 +170,12 @@ def output_structure(a: BlockTensor, b: BlockTensor, axes_a, axes_b, with_data=T
     sig = np.array([a.sig[x] for x in fa] + [b.sig[y] for y in fb], dtype=np.int8)
     n = np.array(_nq([int(p) + int(q) for p, q in zip(a.n, b.n)], a.sym_mod), dtype=np.int32)
     return BlockTensor(tuple(a.sym_mod), sig, n, charges, shapes, offsets,
-                       np.zeros(int(sizes.sum()) if with_data else 0, dtype=np.float64))
+                       np.zeros(int(sizes.sum()) if with_data else 0, dtype=_value_type(a, b)))
+
+
+def _value_type(a, b):
+    """float64, or complex128 when either operand holds complex values."""
+    return np.result_type(np.asarray(a.data).dtype, np.asarray(b.data).dtype, np.float64)
 
 
 # ---------------------------------------------------------------------------
@@ -199,7 +204,7 @@ def leg_index_maps(t: BlockTensor, extra=None):
 
 
 def to_dense(t: BlockTensor, maps):
-    full = np.zeros(tuple(m["D"] for m in maps), dtype=np.float64)
+    full = np.zeros(tuple(m["D"] for m in maps), dtype=np.result_type(np.asarray(t.data).dtype, np.float64))
     for b in range(t.nblocks):
         key = _block_key(t, b)
         sl = tuple(slice(maps[i]["start"][key[i]], maps[i]["start"][key[i]] + int(t.shapes[b, i]))
@@ -220,7 +225,8 @@ def _contracted_extra(a, b, axes_a, axes_b):
 
 def tensordot_dense(a: BlockTensor, b: BlockTensor, axes_a, axes_b, *, return_dense=False):
     """O1.  Embed A and B densely (contracted legs share the union of both
-    partners' charges), contract with numpy.tensordot in float64, read C's
+    partners' charges), contract with numpy.tensordot in float64 (complex128
+    for complex values), read C's
     blocks back at rule-R positions, and check that every dense entry outside
     those blocks is exactly zero (Sec. II.A element-wise conservation)."""
     validate_pair(a, b, axes_a, axes_b)
@@ -265,7 +271,7 @@ def tensordot_blockpair(a: BlockTensor, b: BlockTensor, axes_a, axes_b):
         groups.setdefault(k, []).append((_flat(_block_key(a, i, axes_a)), i, j))
     for k, lst in groups.items():
         lst.sort()
-        acc = np.zeros(tuple(int(x) for x in c.shapes[k]), dtype=np.float64)
+        acc = np.zeros(tuple(int(x) for x in c.shapes[k]), dtype=c.data.dtype)
         for _, i, j in lst:
             acc += np.tensordot(a.block(i), b.block(j), axes=(tuple(axes_a), tuple(axes_b)))
         c.data[c.offsets[k]:c.offsets[k] + acc.size] = acc.ravel()
@@ -292,7 +298,7 @@ def tensordot_blocks(a: BlockTensor, b: BlockTensor, axes_a, axes_b, block_ids):
             groups.setdefault(k, []).append((_flat(_block_key(a, i, axes_a)), i, j))
     out = {}
     for k in sorted(want):
-        acc = np.zeros(tuple(int(x) for x in c.shapes[k]), dtype=np.float64)
+        acc = np.zeros(tuple(int(x) for x in c.shapes[k]), dtype=_value_type(a, b))
         for _, i, j in sorted(groups.get(k, [])):
             acc += np.tensordot(a.block(i), b.block(j), axes=(tuple(axes_a), tuple(axes_b)))
         out[k] = acc

@@ -410,3 +410,42 @@ def ctm_move_small(name: str, seed: int = 700):
     env["chi"] = sum(d for _, d in E)
     env["name"] = f"ctm_move_{name}"
     return env
+
+
+# ---- complex values and fermionic charges ------------------------------------
+def rand_complex(legs, n, sym_mod, seed, **kw):
+    """As ``rand`` with complex128 values: one N(0,1) stream from ``seed``
+    gives each element's real and imaginary parts in turn (blocks in ascending
+    charge order, each in C order)."""
+    t = rand(legs, n, sym_mod, seed, **kw)
+    nb = t.nblocks
+    sizes = np.prod(t.shapes, axis=1).astype(np.int64) if nb else np.zeros(0, np.int64)
+    vals = np.random.default_rng(seed).standard_normal(2 * int(sizes.sum()))
+    data = np.zeros(t.data.size, dtype=np.complex128)
+    v = 0
+    for b in range(nb):
+        sz = int(sizes[b])
+        data[t.offsets[b]:t.offsets[b] + sz] = vals[v:v + 2 * sz:2] + 1j * vals[v + 1:v + 2 * sz:2]
+        v += 2 * sz
+    t.data = data
+    return t
+
+
+def complex_ctm(chi: int = 128):
+    """The enlarged-corner workload (``ctm``) with complex128 values on every
+    tensor (seeds 201-204 as there; A* = conj(A): flipped signatures and
+    conjugated values)."""
+    E, V, P = _ctm_legs_u1u1(chi)
+    z = (0, 0)
+    sm = (U1, U1)
+    t = {"C": rand_complex([_leg2(-1, E), _leg2(1, E)], z, sm, 201),
+         "T1": rand_complex([_leg2(-1, E), _leg2(-1, V), _leg2(1, V), _leg2(1, E)], z, sm, 202),
+         "T4": rand_complex([_leg2(1, E), _leg2(-1, V), _leg2(1, V), _leg2(-1, E)], z, sm, 203),
+         "A": rand_complex([_leg2(1, V), _leg2(1, V), _leg2(-1, V), _leg2(-1, V), _leg2(1, P)], z, sm, 204)}
+    t["axes"] = CTM_AXES
+    t["name"] = f"ctm_u1xu1_chi{chi}_c128"
+    return t
+
+
+# fermionic charge components per symmetry: parity = sum of those mod 2
+FERMIONIC = {(2,): (1,), (U1,): (1,), (U1, U1): (1, 1)}
