@@ -467,6 +467,49 @@ def grad_section(torch, Y, W, ev, sp):
     return res
 
 
+def complex_section(torch, Y, W, ev, sp, reps=5):
+    """The chi = 128 enlarged-corner chain with complex128 tensors
+    (yastn_zplan: C.T1, .T4, .A, .A* with A* = A under CONJ_B), each plan
+    autotuned, the four contractions timed as one graph per step as the real
+    chain is; useful flops = 8 m k n per matched block pair.  Then the
+    fermionic swap gate between the last output's legs (A.b, A*.b) and
+    (A.r, A*.r) in place (bytes = read + write of the negated blocks)."""
+    t = W.complex_ctm()
+    up = lambda x: torch.from_numpy(np.ascontiguousarray(x.data)).to("cuda:0")
+    plans, args, cur_s, cur_dev = [], [], None, None
+    for i, ((an, bn), (ax, bx)) in enumerate(zip([("C", "T1"), (None, "T4"), (None, "A"), (None, "A")],
+                                                 t["axes"])):
+        a_s = t[an] if an else cur_s
+        zp = Y.ZPlan([(a_s, t[bn], ax, bx)], conj=Y.CONJ_B if i == 3 else 0, stream=sp)
+        o = zp.output(0)
+        c = torch.empty(max(1, o.numel), dtype=torch.complex128, device="cuda:0")
+        ws = torch.empty(max(256, zp.workspace_bytes), dtype=torch.uint8, device="cuda:0")
+        a_dev = up(t[an]) if an else cur_dev
+        b_dev = up(t[bn])
+        zp.autotune([a_dev], [b_dev], [c], ws, reps=3, stream=sp)
+        plans.append(zp)
+        args.append(([a_dev], [b_dev], [c], ws))
+        cur_s, cur_dev = o, c
+    flop = sum(zp.stats(0)["useful_flops"] for zp in plans)
+
+    def step(s_):
+        for zp, (a, b, c, ws) in zip(plans, args):
+            zp.contract(a, b, c, ws, stream=s_)
+    ms = graph_time(torch, ev, sp, step)
+    sg = Y.SwapGate(cur_s, (2, 4), (3, 5), W.FERMIONIC[tuple(cur_s.sym_mod)])
+    sw_ms = graph_time(torch, ev, sp, lambda s_: sg.apply(cur_dev, Y.DTYPE_C128, stream=s_))
+    res = {"step_ms": round(ms, 4), "useful_GFLOP": round(flop / 1e9, 3),
+           "useful_TFs": round(flop / (ms * 1e-3) / 1e12, 3),
+           "swap_gate": {"us": round(sw_ms * 1e3, 2), "blocks_negated": sg.blocks,
+                         "bytes": 2 * 16 * sg.elements,
+                         "GBs": round(2 * 16 * sg.elements / (sw_ms * 1e-3) / 1e9, 1),
+                         "output_numel": int(cur_s.numel)},
+           "timing": "graph of the four contractions replayed; swap gate as a graph of one launch"}
+    del plans, args
+    torch.cuda.empty_cache()
+    return res
+
+
 SPLIT = ("validate", "join", "host_tables", "upload")
 
 
@@ -762,6 +805,8 @@ def main():
                          "for profiling")
     ap.add_argument("--svd-only", action="store_true",
                     help="run only the truncated SVD of the chi = 128 corner and print its record; for profiling")
+    ap.add_argument("--complex-only", action="store_true",
+                    help="run only the complex128 corner chain and the swap gate and print their record")
     ap.add_argument("--ctm-only", action="store_true",
                     help="run only the CTM left move at chi = 128 and print its record; for profiling")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -820,6 +865,10 @@ def main():
     if args.ctm_only:
         sp = int(torch.cuda.current_stream().cuda_stream)
         print(json.dumps({"ctm_move": ctm_section(torch, Y, W, sp, reps=max(1, args.steps))}))
+        return
+    if args.complex_only:
+        sp = int(torch.cuda.current_stream().cuda_stream)
+        print(json.dumps({"complex128": complex_section(torch, Y, W, HipEvents(), sp)}))
         return
     dev = "cuda:0"
     torch.cuda.set_device(0)
@@ -1008,6 +1057,7 @@ def main():
                   "gradient": grad_section(torch, Y, W, ev, sp),
                   "svd": svd_section(torch, Y, outs[-1], plans[-1].output(0), sp),
                   "ctm_move": ctm_section(torch, Y, W, sp),
+                  "complex128": complex_section(torch, Y, W, ev, sp),
                   "serving": serving_section(torch, Y, W, sp, nreq=args.serve_requests, warm=args.serve_warmup)}
 
     rec = {

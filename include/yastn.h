@@ -63,8 +63,9 @@ typedef enum {
  * all reduced precisions accumulate in FP32. */
 typedef enum { YASTN_F64 = 0, YASTN_F32 = 1, YASTN_BF16X3 = 2, YASTN_BF16X6 = 3 } yastn_precision;
 
-/* Element type of a stored tensor buffer. */
-typedef enum { YASTN_DTYPE_F64 = 0, YASTN_DTYPE_F32 = 1 } yastn_dtype;
+/* Element type of a stored tensor buffer.  C128: complex, (re, im) FP64
+ * pairs, interleaved (yastn_zplan_*, yastn_swap_gate only). */
+typedef enum { YASTN_DTYPE_F64 = 0, YASTN_DTYPE_F32 = 1, YASTN_DTYPE_C128 = 2 } yastn_dtype;
 
 /* One block-sparse tensor (Sec. II.A).  All arrays [host]. */
 typedef struct {
@@ -517,6 +518,62 @@ yastn_status yastn_ctm_tensor(yastn_ctm_t h, int32_t which, yastn_tensor_desc *d
 yastn_status yastn_ctm_copy(yastn_ctm_t h, int32_t which, void *dst, void *hip_stream);
 yastn_status yastn_ctm_info(yastn_ctm_t h, int32_t *kept, int32_t *sweeps, double *ms, double *flops);
 void yastn_ctm_free(yastn_ctm_t h);
+
+/* ---- complex128 tensordot ------------------------------------------------
+ * C = tensordot(A', B', axes) for complex tensors stored as interleaved
+ * (re, im) FP64 pairs (YASTN_DTYPE_C128; offsets and shapes count complex
+ * elements), where A' = conj(A) if conj has YASTN_CONJ_A and A otherwise,
+ * B' likewise with YASTN_CONJ_B.  Conjugation maps every leg to its dual:
+ * the signatures and the total charge flip and the values are conjugated
+ * (Sec. II.A); the descriptors passed are those of A and B themselves.
+ * The product runs on the FP64 MFMA kernels as one real contraction (A read
+ * in place with its (re, im) pairs as one more contracted leg of dim 2; B
+ * expanded in the workspace into 2 x 2 real blocks, one streaming kernel;
+ * C written in place with (re, im) as its last leg), so every property of
+ * yastn_plan / yastn_contract holds: one grouped launch for all problems,
+ * deterministic results, the structure cache.  Operand ranks: A <= 7,
+ * B <= 6 (the real form adds one and two legs).  yastn_zplan_output gives
+ * C's complex structure; yastn_zplan_workspace the workspace bytes (the real
+ * plan's plus 32 bytes per complex element spanned by each B);
+ * yastn_zplan_real the underlying real plan (owned by the zplan) for
+ * yastn_plan_stats (useful_flops = 8 m k n per matched block pair) and
+ * yastn_plan_set_variant; yastn_zplan_autotune is yastn_plan_autotune of the
+ * real plan on these complex buffers (it expands B first).  yastn_zcontract
+ * is asynchronous on hip_stream; complex buffers must be 16-byte aligned. */
+#define YASTN_CONJ_A 1
+#define YASTN_CONJ_B 2
+typedef struct yastn_zplan_s *yastn_zplan_t;
+yastn_status yastn_zplan(const yastn_problem *probs, int32_t nprob, int32_t conj, void *hip_stream,
+                         yastn_zplan_t *out);
+yastn_status yastn_zplan_output(yastn_zplan_t z, int32_t prob, yastn_tensor_desc *c, int64_t *c_numel);
+yastn_status yastn_zplan_workspace(yastn_zplan_t z, size_t *bytes);
+yastn_status yastn_zplan_real(yastn_zplan_t z, yastn_plan_t *real);
+yastn_status yastn_zcontract(yastn_zplan_t z, const void *const *a, const void *const *b, void *const *c,
+                             void *workspace, void *hip_stream);
+yastn_status yastn_zplan_autotune(yastn_zplan_t z, const void *const *a, const void *const *b, void *const *c,
+                                  void *workspace, void *hip_stream, int32_t reps, int32_t *chosen,
+                                  float *times_ms);
+void yastn_zplan_free(yastn_zplan_t z);
+
+/* ---- fermionic swap gate -------------------------------------------------
+ * The swap gate between leg groups legs1 and legs2 of one tensor (Sec. III,
+ * fermionic Hubbard example: swap gates on line crossings impose the
+ * fermionic order, changing the sign of blocks with odd-parity charges on
+ * both swapped legs).  The parity of a charge is the sum of its fermionic
+ * components (fermionic[c] = 1; [host], nsym entries of 0 or 1) mod 2; a
+ * group's parity is the sum over its legs mod 2; a block is negated iff both
+ * groups are odd -- the product of the swap gates of every pair (i in legs1,
+ * j in legs2).  yastn_swap_plan validates T (yastn_plan's classes; legs out
+ * of range or a bad mask: YASTN_ERR_ARG) and lists the negated blocks;
+ * yastn_swap_info gives their number and elements; yastn_swap_gate negates
+ * them in place in data [device] of the given dtype (F64, F32 or C128),
+ * asynchronously on hip_stream, touching no other element. */
+typedef struct yastn_swap_s *yastn_swap_t;
+yastn_status yastn_swap_plan(const yastn_tensor_desc *t, int32_t n1, const int32_t *legs1, int32_t n2,
+                             const int32_t *legs2, const int32_t *fermionic, yastn_swap_t *out);
+yastn_status yastn_swap_info(yastn_swap_t s, int64_t *blocks, int64_t *elements);
+yastn_status yastn_swap_gate(yastn_swap_t s, void *data, yastn_dtype dtype, void *hip_stream);
+void yastn_swap_free(yastn_swap_t s);
 
 const char *yastn_last_error(void);
 const char *yastn_status_string(yastn_status s);

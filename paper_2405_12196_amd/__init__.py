@@ -27,7 +27,8 @@ LIB_PATH = os.path.join(HERE, "libyastn.so")
 
 F64, F32, BF16X3, BF16X6 = 0, 1, 2, 3
 FLAG_MFMA, FLAG_ROWS, FLAG_NOCACHE = 1, 2, 4
-DTYPE_F64, DTYPE_F32 = 0, 1
+DTYPE_F64, DTYPE_F32, DTYPE_C128 = 0, 1, 2
+CONJ_A, CONJ_B = 1, 2
 PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3, "bf16x6": BF16X6}
 STATUS = ["OK", "ERR_ARG", "ERR_SYM", "ERR_CHARGE", "ERR_SIGNATURE", "ERR_SHAPE",
           "ERR_DUPLICATE", "ERR_NOMEM", "ERR_HIP", "ERR_STATE"]
@@ -44,7 +45,9 @@ EXPORTS = ["yastn_plan", "yastn_plan_profile", "yastn_plan_cache_clear", "yastn_
            "yastn_svd_plan", "yastn_svd_info", "yastn_svd_sector", "yastn_svd", "yastn_svd_output",
            "yastn_svd_factors", "yastn_svd_factors_scaled", "yastn_svd_free",
            "yastn_ctm_plan", "yastn_ctm_move", "yastn_ctm_tensor", "yastn_ctm_copy", "yastn_ctm_info",
-           "yastn_ctm_free"]
+           "yastn_ctm_free", "yastn_zplan", "yastn_zplan_output", "yastn_zplan_workspace", "yastn_zplan_real",
+           "yastn_zcontract", "yastn_zplan_autotune", "yastn_zplan_free", "yastn_swap_plan", "yastn_swap_info",
+           "yastn_swap_gate", "yastn_swap_free"]
 CTM_NAMES = ("Q1", "Q2", "Q3", "Q4", "Rup", "Rdn", "M", "Us", "Vts", "Pup", "Pdn", "C1T1", "C4T3", "Z1", "Z2",
              "Z3", "C1n", "T4n", "C4n", "C1", "T4", "C4")
 CTM_INPUTS = ("C1", "C2", "C3", "C4", "T1", "T2", "T3", "T4", "A")
@@ -195,10 +198,29 @@ def lib():
                                      C.POINTER(C.c_double)]
         L.yastn_ctm_free.argtypes = [C.c_void_p]
         L.yastn_ctm_free.restype = None
+        L.yastn_zplan.argtypes = [C.POINTER(Problem), C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
+        L.yastn_zplan_output.argtypes = [C.c_void_p, C.c_int32, C.POINTER(TensorDesc), C.POINTER(C.c_int64)]
+        L.yastn_zplan_workspace.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
+        L.yastn_zplan_real.argtypes = [C.c_void_p, C.POINTER(C.c_void_p)]
+        L.yastn_zcontract.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                      C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]
+        L.yastn_zplan_autotune.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                           C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p, C.c_int32,
+                                           C.POINTER(C.c_int32), C.POINTER(C.c_float)]
+        L.yastn_zplan_free.argtypes = [C.c_void_p]
+        L.yastn_zplan_free.restype = None
+        L.yastn_swap_plan.argtypes = [C.POINTER(TensorDesc), C.c_int32, C.POINTER(C.c_int32), C.c_int32,
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_void_p)]
+        L.yastn_swap_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.yastn_swap_gate.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
+        L.yastn_swap_free.argtypes = [C.c_void_p]
+        L.yastn_swap_free.restype = None
         for f in ("yastn_perm_plan", "yastn_perm_output", "yastn_permute", "yastn_grad_plan", "yastn_grad_output",
                   "yastn_grad_workspace", "yastn_grad", "yastn_svd_plan", "yastn_svd_info", "yastn_svd_sector",
                   "yastn_svd", "yastn_svd_output", "yastn_svd_factors", "yastn_svd_factors_scaled",
-                  "yastn_ctm_plan", "yastn_ctm_move", "yastn_ctm_tensor", "yastn_ctm_copy", "yastn_ctm_info"):
+                  "yastn_ctm_plan", "yastn_ctm_move", "yastn_ctm_tensor", "yastn_ctm_copy", "yastn_ctm_info",
+                  "yastn_zplan", "yastn_zplan_output", "yastn_zplan_workspace", "yastn_zplan_real", "yastn_zcontract",
+                  "yastn_zplan_autotune", "yastn_swap_plan", "yastn_swap_info", "yastn_swap_gate"):
             getattr(L, f).restype = C.c_int32
         for f in ("yastn_plan", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats",
                   "yastn_contract", "yastn_contract_noalloc", "yastn_contract_norm", "yastn_contract_timed",
@@ -571,6 +593,113 @@ class Svd:
     def free(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().yastn_svd_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _problems(problems, keep):
+    arr = (Problem * max(1, len(problems)))()
+    for i, (a, b, axes_a, axes_b) in enumerate(problems):
+        arr[i].a = _desc(a, keep)
+        arr[i].b = _desc(b, keep)
+        xa, xb = _arr(list(axes_a), np.int32), _arr(list(axes_b), np.int32)
+        arr[i].ncontract = int(len(axes_a)) if len(axes_a) == len(axes_b) else -1
+        arr[i].axes_a = keep.ptr(xa, C.c_int32)
+        arr[i].axes_b = keep.ptr(xb, C.c_int32)
+    return arr
+
+
+def _ptrs(xs, n):
+    return (C.c_void_p * max(1, n))(*[_ptr(x) for x in xs])
+
+
+class ZPlan:
+    """Complex128 tensordot (yastn_zplan_*): problems as for Plan, values
+    complex (interleaved); ``conj`` = CONJ_A | CONJ_B conjugates the operands."""
+
+    def __init__(self, problems, conj=0, stream=None):
+        keep = _Keep()
+        arr = _problems(problems, keep)
+        h = C.c_void_p()
+        _check(lib().yastn_zplan(arr, len(problems), int(conj), C.c_void_p(_stream(stream)), C.byref(h)))
+        self._h = h
+        self.nprob = len(problems)
+        ws = C.c_size_t()
+        _check(lib().yastn_zplan_workspace(h, C.byref(ws)))
+        self.workspace_bytes = int(ws.value)
+        r = C.c_void_p()
+        _check(lib().yastn_zplan_real(h, C.byref(r)))
+        self._real = r
+
+    def output(self, p: int = 0) -> Structure:
+        d, n = TensorDesc(), C.c_int64()
+        _check(lib().yastn_zplan_output(self._h, p, C.byref(d), C.byref(n)))
+        return _structure(d, n)
+
+    def stats(self, p: int = 0) -> dict:
+        """Stats of the real form (useful_flops = 8 m k n per matched pair)."""
+        st = Stats()
+        _check(lib().yastn_plan_stats(self._real, p, C.byref(st)))
+        return st.as_dict()
+
+    def contract(self, a, b, c, workspace, stream=None):
+        n = self.nprob
+        _check(lib().yastn_zcontract(self._h, _ptrs(a, n), _ptrs(b, n), _ptrs(c, n), C.c_void_p(_ptr(workspace)),
+                                     C.c_void_p(_stream(stream))))
+
+    def autotune(self, a, b, c, workspace, reps=5, stream=None):
+        n = self.nprob
+        ch = C.c_int32()
+        times = (C.c_float * NUM_VARIANTS)()
+        _check(lib().yastn_zplan_autotune(self._h, _ptrs(a, n), _ptrs(b, n), _ptrs(c, n),
+                                          C.c_void_p(_ptr(workspace)), C.c_void_p(_stream(stream)), int(reps),
+                                          C.byref(ch), times))
+        return int(ch.value), [float(t) for t in times]
+
+    def set_variant(self, v: int):
+        _check(lib().yastn_plan_set_variant(self._real, int(v)))
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().yastn_zplan_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class SwapGate:
+    """Fermionic swap gate between leg groups legs1, legs2 of a tensor
+    structure (yastn_swap_*); ``fermionic``: 0/1 per charge component."""
+
+    def __init__(self, t, legs1, legs2, fermionic):
+        keep = _Keep()
+        d = _desc(t, keep)
+        l1, l2 = _arr(list(legs1) or [0], np.int32), _arr(list(legs2) or [0], np.int32)
+        fm = _arr(list(fermionic), np.int32)
+        h = C.c_void_p()
+        _check(lib().yastn_swap_plan(C.byref(d), len(legs1), keep.ptr(l1, C.c_int32), len(legs2),
+                                     keep.ptr(l2, C.c_int32), keep.ptr(fm, C.c_int32), C.byref(h)))
+        self._h = h
+        nb, ne = C.c_int64(), C.c_int64()
+        _check(lib().yastn_swap_info(h, C.byref(nb), C.byref(ne)))
+        self.blocks, self.elements = int(nb.value), int(ne.value)
+
+    def apply(self, data, dtype=DTYPE_F64, stream=None):
+        """Negate the odd-odd blocks of ``data`` in place (asynchronous)."""
+        _check(lib().yastn_swap_gate(self._h, C.c_void_p(_ptr(data)), int(dtype), C.c_void_p(_stream(stream))))
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().yastn_swap_free(self._h)
             self._h = C.c_void_p()
 
     def __del__(self):

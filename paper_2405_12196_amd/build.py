@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libyastn.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["device.hip", "host.cpp", "serve.cpp", "ops.hip", "svd.hip", "ctm.hip", "inst_f64.hip", "inst_f32d.hip", "inst_f32f.hip",
+SOURCES = ["device.hip", "host.cpp", "serve.cpp", "ops.hip", "svd.hip", "ctm.hip", "fermion.hip", "inst_f64.hip", "inst_f32d.hip", "inst_f32f.hip",
            "inst_bf16.hip", "inst_lds.hip", "inst_lds_norm.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -138,3 +138,26 @@ def test_variant_count_matches_header():
     with open(os.path.join(root, "include", "yastn.h")) as f:
         n = int(re.search(r"#define YASTN_NUM_VARIANTS (\d+)", f.read()).group(1))
     assert Y.NUM_VARIANTS == n
+
+
+def test_complex_and_swap_gate_host_errors():
+    """Errors the host finds before any device work: complex operands whose
+    real form would exceed the rank limit, unknown conj flags, swap-gate legs
+    out of range, a fermionic mask entry other than 0 / 1, C128 for yastn_norm."""
+    from workloads import Leg
+    v = Leg(1, ((0,), (1,)), (1, 2))
+    big = W.rand_complex([v] * 4 + [v.conj()] * 4, (0,), (2,), 1)   # rank 8: no room for (re, im)
+    small = W.rand_complex([v, v.conj()], (0,), (2,), 2)
+    with pytest.raises(Y.YastnError) as e:
+        Y.ZPlan([(big, small, (0,), (1,))], stream=0)
+    assert e.value.status == "ERR_ARG"
+    with pytest.raises(Y.YastnError) as e:
+        Y.ZPlan([(small, small, (1,), (0,))], conj=4, stream=0)
+    assert e.value.status == "ERR_ARG"
+    with pytest.raises(Y.YastnError) as e:
+        Y.SwapGate(small, (0,), (2,), (1,))
+    assert e.value.status == "ERR_ARG"
+    with pytest.raises(Y.YastnError) as e:
+        Y.SwapGate(small, (0,), (1,), (2,))
+    assert e.value.status == "ERR_ARG"
+    assert Y.lib().yastn_norm(None, 10, Y.DTYPE_C128, None, None, None) == 1
