@@ -64,9 +64,13 @@ constexpr int kSvdW = 8;           // columns per block (a block pair is 16 colu
 constexpr int kSvdMaxSweeps = 40;  // outer sweeps before giving up
 constexpr int kSvdInnerSweeps = 1; // cyclic Jacobi sweeps on a pair's 16 x 16 Gram matrix per round
 
+// W (rows x ld) and V (ld x ld) are stored in panels of 8 columns: panel p
+// holds columns 8p .. 8p + 7 of every row, row after row, so a column block
+// of the Jacobi sweep is one contiguous array and every load and store of a
+// round touches whole runs of 64-byte rows
 struct DevSvdSector {
-  int64_t w_off;   // W: rows x ld, row-major, elements from the workspace base
-  int64_t v_off;   // V: ld x ld, row-major
+  int64_t w_off;   // W: rows x ld in 8-column panels, elements from the workspace base
+  int64_t v_off;   // V: ld x ld in 8-column panels
   int32_t rows;    // W's rows (>= cols)
   int32_t cols;    // W's columns
   int32_t ld;      // kSvdW * nb
@@ -79,12 +83,15 @@ struct DevSvdSector {
 
 struct DevSvdGather {  // one block of T: element e (C order over T's legs) -> W
   int64_t t_off;       // first element in T's buffer
-  int64_t w_base;      // W offset of the block's element 0
+  int64_t w_off;       // the sector's W
+  int64_t wr0, wc0;    // W row and column of the block's element 0
   int32_t numel, rank;
+  int32_t wrows;       // W's rows
+  uint32_t colmask;    // bit l: leg l's index moves along W's columns (else rows)
   int32_t dim[YASTN_MAX_RANK];
   uint32_t mag[YASTN_MAX_RANK];
   int32_t sh[YASTN_MAX_RANK];
-  int64_t wstr[YASTN_MAX_RANK];  // W stride of each leg's index
+  int64_t wstr[YASTN_MAX_RANK];  // W row or column step of each leg's index
 };
 struct DevSvdTile {
   int32_t blk, start;
@@ -93,11 +100,16 @@ constexpr int kSvdTile = 1024;
 
 struct DevSvdOut {     // one output block: U (kind 0) or V^T (kind 1)
   int64_t out_off;     // first element in the output buffer
-  int64_t src_off;     // workspace offset of the source row of the block's first row / column
+  int64_t base;        // workspace offset of the source matrix (W or V)
   int32_t a, b;        // U: m_i x t; V^T: t x n_j
-  int32_t ld, sv0;     // source row stride; the sector's first sorted index (perm)
-  int32_t kind, pad;
+  int32_t r0, rows;    // the source row of the block's first row (U) / column (V^T); the source's rows
+  int32_t sv0, kind;   // the sector's first sorted index (perm); 0 = U, 1 = V^T
 };
+
+// element (r, c) of a matrix of R rows in 8-column panels
+__device__ __forceinline__ int64_t pix(int64_t r, int c, int64_t R) {
+  return (int64_t)(c >> 3) * (R << 3) + (r << 3) + (c & 7);
+}
 
 // ------------------------------------------------------------------ kernels
 __global__ void __launch_bounds__(256) k_svd_init(const DevSvdSector *sec, int nsec, double *ws) {
@@ -108,8 +120,9 @@ __global__ void __launch_bounds__(256) k_svd_init(const DevSvdSector *sec, int n
       if (i < nw) {
         ws[s.w_off + i] = 0.0;
       } else {
-        const int64_t j = i - nw;
-        ws[s.v_off + j] = (j / s.ld == j % s.ld) ? 1.0 : 0.0;
+        const int64_t j = i - nw;  // panel p = j / (8 ld), row (j mod 8 ld) / 8, column 8 p + j mod 8
+        const int64_t pnl = j / (8 * (int64_t)s.ld), in = j - pnl * 8 * s.ld;
+        ws[s.v_off + j] = ((in >> 3) == 8 * pnl + (in & 7)) ? 1.0 : 0.0;
       }
     }
   }
@@ -124,13 +137,15 @@ __global__ void __launch_bounds__(256) k_svd_gather(const DevSvdGather *__restri
     const int end = min(tl.start + kSvdTile, b.numel);
     for (int e = tl.start + (int)threadIdx.x; e < end; e += 256) {
       uint32_t r = (uint32_t)e;
-      int64_t dst = b.w_base;
+      int64_t wr = b.wr0, wc = b.wc0;
       for (int d = b.rank - 1; d >= 0; --d) {
         const uint32_t q = (uint32_t)(((uint64_t)r * b.mag[d]) >> b.sh[d]);
-        dst += (int64_t)(r - q * (uint32_t)b.dim[d]) * b.wstr[d];
+        const int64_t step = (int64_t)(r - q * (uint32_t)b.dim[d]) * b.wstr[d];
+        if ((b.colmask >> d) & 1u) wc += step;
+        else wr += step;
         r = q;
       }
-      ws[dst] = t[b.t_off + e];
+      ws[b.w_off + pix(wr, (int)wc, b.wrows)] = t[b.t_off + e];
     }
   }
 }
@@ -190,7 +205,7 @@ __global__ void __launch_bounds__(256) k_svd_round(SvdRoundArgs a) {
     for (int r0 = 4 * wid; r0 < S.rows; r0 += 16 * 8) {
       double x[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) x[u] = W[(int64_t)min(r0 + 16 * u + kq, S.rows - 1) * S.ld + col];
+      for (int u = 0; u < 8; ++u) x[u] = W[pix(min(r0 + 16 * u + kq, S.rows - 1), col, S.rows)];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const double xv = r0 + 16 * u + kq < S.rows ? x[u] : 0.0;
@@ -301,14 +316,14 @@ __global__ void __launch_bounds__(256) k_svd_round(SvdRoundArgs a) {
   int cin[4];
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) cin[kk] = colof(4 * kk + kq);
-  auto rowptr = [&](int r) { return r < nw ? W + (int64_t)r * S.ld : V + (int64_t)(r - nw) * S.ld; };
+  auto at = [&](int r, int c) { return r < nw ? W + pix(r, c, nw) : V + pix(r - nw, c, S.ld); };
   for (int rb = 16 * wid; rb < nt; rb += 64 * 4) {
     double x[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const double *src = rowptr(min(rb + 64 * u + c16, nt - 1));
+      const int r = min(rb + 64 * u + c16, nt - 1);
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) x[u][kk] = src[cin[kk]];
+      for (int kk = 0; kk < 4; ++kk) x[u][kk] = *at(r, cin[kk]);
     }
     d4v acc[4];
 #pragma unroll
@@ -324,7 +339,7 @@ __global__ void __launch_bounds__(256) k_svd_round(SvdRoundArgs a) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = rb + 64 * u + kq + 4 * v;
-        if (r < nt) rowptr(r)[cout] = acc[u][v];
+        if (r < nt) *at(r, cout) = acc[u][v];
       }
   }
 }
@@ -365,14 +380,14 @@ __global__ void __launch_bounds__(256) k_svd_norms(const DevSvdSector *sec, int 
     for (int j = blockIdx.x * 4 + (threadIdx.x >> 6); j < S.cols; j += gridDim.x * 4) {
       double ss = 0.0;
       for (int r = lane; r < S.rows; r += 64) {
-        const double x = W[(int64_t)r * S.ld + j];
+        const double x = W[pix(r, j, S.rows)];
         ss = fma(x, x, ss);
       }
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
       const double sig = sqrt(ss);
       const double inv = sig > 0.0 ? 1.0 / sig : 0.0;
-      for (int r = lane; r < S.rows; r += 64) W[(int64_t)r * S.ld + j] *= inv;
+      for (int r = lane; r < S.rows; r += 64) W[pix(r, j, S.rows)] *= inv;
       if (lane == 0) sv_raw[S.sv0 + j] = sig;
     }
   }
@@ -470,14 +485,15 @@ __global__ void __launch_bounds__(256) k_svd_gauge(const DevSvdSector *sec, int 
   for (int k = blockIdx.y; k < nsec; k += gridDim.y) {
     const DevSvdSector S = sec[k];
     const double *U = ws + (S.trans ? S.v_off : S.w_off);
-    const int mU = S.trans ? S.cols : S.rows;
+    const int mU = S.trans ? S.cols : S.rows;     // U's rows: m
+    const int64_t RU = S.trans ? S.ld : S.rows;   // rows of the matrix that holds U
     const int nk = kept[k];
     for (int t = blockIdx.x * 4 + (threadIdx.x >> 6); t < nk; t += gridDim.x * 4) {
       const int j = perm[S.sv0 + t];
       double best = -1.0, val = 0.0;
       int row = 0x7fffffff;
       for (int r = lane; r < mU; r += 64) {
-        const double x = U[(int64_t)r * S.ld + j];
+        const double x = U[pix(r, j, RU)];
         if (fabs(x) > best) {  // rows ascend per lane: the first maximum stays
           best = fabs(x);
           val = x;
@@ -506,9 +522,9 @@ __device__ __forceinline__ double sv_power(double s, double p) {
   return pow(s, p);
 }
 
-// U block (kind 0): element (r, t) = sign_t S_t^pu src[r * ld + perm[t]], out
+// U block (kind 0): element (r, t) = sign_t S_t^pu src(r0 + r, perm[t]), out
 // row-major a x b (b = t kept); V^T block (kind 1): element (t, c) = sign_t
-// S_t^pv src[c * ld + perm[t]], out row-major a x b (a = kept).  S_t is the
+// S_t^pv src(r0 + c, perm[t]), out row-major a x b (a = kept).  S_t is the
 // sector's t-th largest value, sv_raw[sv0 + perm[sv0 + t]].
 __global__ void __launch_bounds__(256) k_svd_write(const DevSvdOut *__restrict__ items, int nitems,
                                                    const double *__restrict__ ws, const int32_t *__restrict__ perm,
@@ -530,7 +546,7 @@ __global__ void __launch_bounds__(256) k_svd_write(const DevSvdOut *__restrict__
       const int32_t x = (int32_t)(e / o.b), y = (int32_t)(e - (int64_t)x * o.b);
       const int32_t r = o.kind == 0 ? x : y, t = o.kind == 0 ? y : x;
       const double f = t < 512 ? fac[t] : sign[o.sv0 + t] * sv_power(sv_raw[o.sv0 + perm[o.sv0 + t]], p);
-      out[o.out_off + e] = f * ws[o.src_off + (int64_t)r * o.ld + perm[o.sv0 + t]];
+      out[o.out_off + e] = f * ws[o.base + pix(o.r0 + r, perm[o.sv0 + t], o.rows)];
     }
   }
 }
@@ -748,15 +764,18 @@ yastn_status yastn_svd_plan(const yastn_tensor_desc *t, int32_t nrow, const int3
         wcol[P.col_legs[i]] = acc;
         acc *= T.dim(b, P.col_legs[i]);
       }
-      // M[ro + rowidx][co + colidx]; W = M (row-major, ld) or W = M^T
-      const int64_t ld = d.ld;
-      g.w_base = d.w_off + (d.trans ? co * ld + ro : ro * ld + co);
+      // M[ro + rowidx][co + colidx]; W = M or W = M^T (rows and columns swapped)
+      g.w_off = d.w_off;
+      g.wrows = d.rows;
+      g.wr0 = d.trans ? co : ro;
+      g.wc0 = d.trans ? ro : co;
+      g.colmask = 0;
       for (int l = 0; l < r; ++l) {
         g.dim[l] = (int32_t)T.dim(b, l);
         div_magic((uint32_t)g.dim[l], &g.mag[l], &g.sh[l]);
-        const bool rl = wrow[l] != 0;
-        const int64_t w = rl ? wrow[l] : wcol[l];
-        g.wstr[l] = (rl != (d.trans != 0)) ? w * ld : w;
+        const bool rl = wrow[l] != 0;  // leg l indexes M's rows
+        g.wstr[l] = rl ? wrow[l] : wcol[l];
+        if (rl == (d.trans != 0)) g.colmask |= 1u << l;  // a W column: M's column, or M's row when transposed
       }
       for (int32_t s0 = 0; s0 < g.numel; s0 += kSvdTile) tiles.push_back(DevSvdTile{(int32_t)gat.size(), s0});
       gat.push_back(g);
@@ -910,7 +929,7 @@ yastn_status yastn_svd(yastn_svd_t h, const void *t, int32_t chi, double tol, do
       b.key.insert(b.key.end(), s.x.begin(), s.x.end());
       b.shape = tp.dims;
       b.shape.push_back(tk);
-      b.o = DevSvdOut{0, usrc + tp.off * d.ld, (int32_t)tp.size, tk, d.ld, d.sv0, 0, 0};
+      b.o = DevSvdOut{0, usrc, (int32_t)tp.size, tk, (int32_t)tp.off, d.trans ? d.ld : d.rows, d.sv0, 0};
       ub.push_back(std::move(b));
     }
     for (auto &tp : s.cols) {
@@ -919,7 +938,7 @@ yastn_status yastn_svd(yastn_svd_t h, const void *t, int32_t chi, double tol, do
       b.key.insert(b.key.end(), tp.key.begin(), tp.key.end());
       b.shape.push_back(tk);
       b.shape.insert(b.shape.end(), tp.dims.begin(), tp.dims.end());
-      b.o = DevSvdOut{0, vsrc + tp.off * d.ld, tk, (int32_t)tp.size, d.ld, d.sv0, 1, 0};
+      b.o = DevSvdOut{0, vsrc, tk, (int32_t)tp.size, (int32_t)tp.off, d.trans ? d.rows : d.ld, d.sv0, 1};
       vb.push_back(std::move(b));
     }
   }
