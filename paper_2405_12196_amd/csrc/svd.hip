@@ -63,6 +63,7 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 constexpr int kSvdW = 8;           // columns per block (a block pair is 16 columns: one MFMA tile)
 constexpr int kSvdMaxSweeps = 40;  // outer sweeps before giving up
 constexpr int kSvdInnerSweeps = 1; // cyclic Jacobi sweeps on a pair's 16 x 16 Gram matrix per round
+constexpr int kSvdWaves = 8;       // waves of a round's workgroup (one workgroup per block pair)
 
 // W (rows x ld) and V (ld x ld) are stored in panels of 8 columns: panel p
 // holds columns 8p .. 8p + 7 of every row, row after row, so a column block
@@ -172,8 +173,8 @@ __device__ __forceinline__ void rr_pair(int nb, int rr, int p, int &P, int &Q) {
   }
 }
 
-__global__ void __launch_bounds__(256) k_svd_round(SvdRoundArgs a) {
-  __shared__ double gpart[4][16][16];
+__global__ void __launch_bounds__(64 * kSvdWaves) k_svd_round(SvdRoundArgs a) {
+  __shared__ double gpart[kSvdWaves][16][16];
   __shared__ double g[16][17];
   __shared__ double q[16][17];
   __shared__ int rotated;
@@ -196,19 +197,20 @@ __global__ void __launch_bounds__(256) k_svd_round(SvdRoundArgs a) {
   const int c16 = lane & 15, kq = lane >> 4;
   auto colof = [&](int c) { return c < kSvdW ? kSvdW * P + c : kSvdW * Q + c - kSvdW; };
   // ---- Gram matrix of the 16 columns: wave w takes the 4-row groups w,
-  // w + 4, ...; eight groups' loads are issued before their MFMAs (row
-  // indices clamped, values past the last row zeroed after the load, so no
-  // load sits under a branch)
+  // w + kSvdWaves, ...; eight groups' loads are issued before their MFMAs
+  // (row indices clamped, values past the last row zeroed after the load, so
+  // no load sits under a branch)
   {
     const int col = colof(c16);
+    constexpr int kStride = 4 * kSvdWaves;
     d4v acc = {0, 0, 0, 0};
-    for (int r0 = 4 * wid; r0 < S.rows; r0 += 16 * 8) {
+    for (int r0 = 4 * wid; r0 < S.rows; r0 += kStride * 8) {
       double x[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) x[u] = W[pix(min(r0 + 16 * u + kq, S.rows - 1), col, S.rows)];
+      for (int u = 0; u < 8; ++u) x[u] = W[pix(min(r0 + kStride * u + kq, S.rows - 1), col, S.rows)];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const double xv = r0 + 16 * u + kq < S.rows ? x[u] : 0.0;
+        const double xv = r0 + kStride * u + kq < S.rows ? x[u] : 0.0;
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, xv, acc, 0, 0, 0);
       }
     }
@@ -217,10 +219,13 @@ __global__ void __launch_bounds__(256) k_svd_round(SvdRoundArgs a) {
   }
   __syncthreads();
   if (wid == 0) {
-    // sum the four waves' parts in a fixed order, Q = I
+    // sum the waves' parts in a fixed order, Q = I
     for (int e = lane; e < 256; e += 64) {
       const int i = e >> 4, j = e & 15;
-      g[i][j] = ((gpart[0][i][j] + gpart[1][i][j]) + gpart[2][i][j]) + gpart[3][i][j];
+      double sum = gpart[0][i][j];
+#pragma unroll
+      for (int w = 1; w < kSvdWaves; ++w) sum += gpart[w][i][j];
+      g[i][j] = sum;
       q[i][j] = i == j ? 1.0 : 0.0;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -303,8 +308,8 @@ __global__ void __launch_bounds__(256) k_svd_round(SvdRoundArgs a) {
   __syncthreads();
   if (!rotated) return;
   // ---- [W_P W_Q] <- [W_P W_Q] q and [V_P V_Q] <- [V_P V_Q] q: wave w takes
-  // 16-row chunks w, w + 4, ...; A operand = 16 rows x 4 of the 16 columns,
-  // B operand = 4 rows of q
+  // 16-row chunks w, w + kSvdWaves, ...; A operand = 16 rows x 4 of the 16
+  // columns, B operand = 4 rows of q
   double qb[4];
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) qb[kk] = q[4 * kk + kq][c16];
@@ -317,11 +322,12 @@ __global__ void __launch_bounds__(256) k_svd_round(SvdRoundArgs a) {
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) cin[kk] = colof(4 * kk + kq);
   auto at = [&](int r, int c) { return r < nw ? W + pix(r, c, nw) : V + pix(r - nw, c, S.ld); };
-  for (int rb = 16 * wid; rb < nt; rb += 64 * 4) {
+  constexpr int kChunk = 16 * kSvdWaves;
+  for (int rb = 16 * wid; rb < nt; rb += kChunk * 4) {
     double x[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int r = min(rb + 64 * u + c16, nt - 1);
+      const int r = min(rb + kChunk * u + c16, nt - 1);
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) x[u][kk] = *at(r, cin[kk]);
     }
@@ -338,7 +344,7 @@ __global__ void __launch_bounds__(256) k_svd_round(SvdRoundArgs a) {
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = rb + 64 * u + kq + 4 * v;
+        const int r = rb + kChunk * u + kq + 4 * v;
         if (r < nt) *at(r, cout) = acc[u][v];
       }
   }
@@ -875,7 +881,7 @@ yastn_status yastn_svd(yastn_svd_t h, const void *t, int32_t chi, double tol, do
     hipLaunchKernelGGL(k_svd_sweep_begin, dim3(grid1(nsec, 256)), dim3(256), 0, st, conv, (int32_t *)nullptr, nsec);
     for (int rr = 0; rr < P.max_rounds; ++rr) {
       ra.round = rr;
-      hipLaunchKernelGGL(k_svd_round, dim3(P.total_pairs), dim3(256), 0, st, ra);
+      hipLaunchKernelGGL(k_svd_round, dim3(P.total_pairs), dim3(64 * kSvdWaves), 0, st, ra);
     }
     hipLaunchKernelGGL(k_svd_sweep_end, dim3(1), dim3(256), 0, st, conv, done, nsec, P.d_sec, eps_scale, flag);
     SVD_HIP(hipGetLastError());
