@@ -805,6 +805,9 @@ def main():
                          "for profiling")
     ap.add_argument("--svd-only", action="store_true",
                     help="run only the truncated SVD of the chi = 128 corner and print its record; for profiling")
+    ap.add_argument("--tune-file", default="",
+                    help="tuning store (JSON): loaded before planning if it exists (known requests start at "
+                         "their tuned variant), saved after autotuning")
     ap.add_argument("--complex-only", action="store_true",
                     help="run only the complex128 corner chain and the swap gate and print their record")
     ap.add_argument("--ctm-only", action="store_true",
@@ -877,6 +880,9 @@ def main():
     t = W.ctm()
     # ---- plans (once; structure is fixed across CTM iterations)
     tp0 = time.perf_counter()
+    tune_loaded = None
+    if args.tune_file and os.path.exists(args.tune_file):
+        tune_loaded = Y.tune_load(args.tune_file)  # plans of known requests start at their tuned variant
     plans, descs = [], []
     cur = None
     for (an, bn), (ax, bx) in zip(STEPS, t["axes"]):
@@ -914,6 +920,8 @@ def main():
             v, times = pl.autotune([a], [b], [c], w, reps=5, stream=sp)
             tuned.append({"step": i + 1, "variant": v, "ms": [round(x, 4) for x in times]})
         torch.cuda.synchronize()
+        if args.tune_file:
+            Y.tune_save(args.tune_file)
 
     ev = HipEvents()
 
@@ -1069,7 +1077,7 @@ def main():
                    "useful_flop_per_step": int(useful), "plus": "fp64 norm of the step-4 output" + (" (separate kernel)" if args.separate_norm else " (fused into its contraction)"),
                    "parallelism": "single GPU"},
         "p50_ms": round(float(np.percentile(lat, 50)), 5), "p99_ms": round(float(np.percentile(lat, 99)), 5),
-        "plan_ms": round(plan_ms, 2), "plan": plan_rec,
+        "plan_ms": round(plan_ms, 2), "plan": plan_rec, "tuning_entries_loaded": tune_loaded,
         "timing": {"graph": "step captured in one HIP graph, one replay per step",
                    "eager": "one host launch per kernel"}[mode],
         "ms_per_step_by_mode": {m: round(v[0], 5) for m, v in modes.items()}, "graph_error": graph_err,

@@ -154,6 +154,23 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
 yastn_status yastn_plan_profile(yastn_plan_t plan, double *ms, int32_t *cached);
 void yastn_plan_cache_clear(void);
 
+/* Tuning store: every choice yastn_plan_autotune makes is kept for the
+ * process under a 128-bit fingerprint of the plan request (options, axes and
+ * every descriptor array; not the device ordinal) and the device's
+ * architecture name (hipDeviceProp_t::gcnArchName).  A new plan whose request
+ * and architecture are in the store starts at that variant when it fits the
+ * plan, with the stored times (yastn_plan_autotune then returns at once).
+ * yastn_tune_save writes the store to a JSON file (path [host]); a later
+ * process reads it with yastn_tune_load (*loaded = entries read, may be
+ * NULL), so the structures a CTM run repeats are tuned once across runs.
+ * The file names the variant count; a file made for another count is
+ * rejected with YASTN_ERR_ARG, as is a malformed or unreadable one (the store
+ * is then unchanged).  yastn_tune_clear empties the store.  Loading adds to
+ * the store, replacing entries with the same key and architecture. */
+yastn_status yastn_tune_save(const char *path);
+yastn_status yastn_tune_load(const char *path, int32_t *loaded);
+void yastn_tune_clear(void);
+
 /* Structure of problem prob's output.  The returned arrays are owned by the
  * plan and live until yastn_free.  c->charges / shapes / offsets are [host]. */
 yastn_status yastn_plan_output(yastn_plan_t plan, int32_t prob, yastn_tensor_desc *c,

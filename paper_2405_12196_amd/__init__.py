@@ -33,7 +33,8 @@ PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3, "bf16x6": BF16X6}
 STATUS = ["OK", "ERR_ARG", "ERR_SYM", "ERR_CHARGE", "ERR_SIGNATURE", "ERR_SHAPE",
           "ERR_DUPLICATE", "ERR_NOMEM", "ERR_HIP", "ERR_STATE"]
 
-EXPORTS = ["yastn_plan", "yastn_plan_profile", "yastn_plan_cache_clear", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats", "yastn_plan_info",
+EXPORTS = ["yastn_plan", "yastn_plan_profile", "yastn_plan_cache_clear", "yastn_tune_save", "yastn_tune_load",
+           "yastn_tune_clear", "yastn_plan_output", "yastn_plan_workspace", "yastn_plan_stats", "yastn_plan_info",
            "yastn_contract", "yastn_contract_noalloc", "yastn_contract_norm", "yastn_contract_timed",
            "yastn_contract_jobs", "yastn_norm_workspace", "yastn_norm",
            "yastn_free", "yastn_last_error", "yastn_status_string", "yastn_abi_version",
@@ -129,6 +130,12 @@ def lib():
         L.yastn_plan_profile.restype = C.c_int32
         L.yastn_plan_cache_clear.argtypes = []
         L.yastn_plan_cache_clear.restype = None
+        L.yastn_tune_save.argtypes = [C.c_char_p]
+        L.yastn_tune_save.restype = C.c_int32
+        L.yastn_tune_load.argtypes = [C.c_char_p, C.POINTER(C.c_int32)]
+        L.yastn_tune_load.restype = C.c_int32
+        L.yastn_tune_clear.argtypes = []
+        L.yastn_tune_clear.restype = None
         L.yastn_plan_output.argtypes = [C.c_void_p, C.c_int32, C.POINTER(TensorDesc), C.POINTER(C.c_int64)]
         L.yastn_plan_workspace.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
         L.yastn_plan_stats.argtypes = [C.c_void_p, C.c_int32, C.POINTER(Stats)]
@@ -616,6 +623,22 @@ def _problems(problems, keep):
 
 def _ptrs(xs, n):
     return (C.c_void_p * max(1, n))(*[_ptr(x) for x in xs])
+
+
+def tune_save(path):
+    """Write the process's tuning store (every autotuned choice) to a JSON file."""
+    _check(lib().yastn_tune_save(os.fsencode(path)))
+
+
+def tune_load(path) -> int:
+    """Add a saved tuning store; returns the number of entries read."""
+    n = C.c_int32()
+    _check(lib().yastn_tune_load(os.fsencode(path), C.byref(n)))
+    return int(n.value)
+
+
+def tune_clear():
+    lib().yastn_tune_clear()
 
 
 class ZPlan:

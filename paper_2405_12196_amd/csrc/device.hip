@@ -13,7 +13,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cctype>
 #include <chrono>
+#include <cstdlib>
 #include <memory>
 #include <cstdio>
 #include <type_traits>
@@ -842,6 +844,63 @@ void cache_put(uint64_t h, std::vector<int64_t> &&k, const std::shared_ptr<Plan>
   g_cache.push_back(CacheEntry{h, std::move(k), p, ++g_cache_tick});
 }
 
+// ---------------------------------------------------------------------------
+// Tuning store: the variant the autotuner chose for a plan request, keyed by
+// a 128-bit fingerprint of the request (every descriptor array, the axes and
+// the options; not the device ordinal) and the device's architecture name,
+// kept for the process and saved to / loaded from a JSON file, so a later
+// process starts every known structure at its tuned variant.
+// ---------------------------------------------------------------------------
+struct TuneEntry {
+  uint64_t k0, k1;
+  std::string arch;
+  int variant;
+  float ms[kVariants];
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+void tune_fingerprint(const std::vector<int64_t> &k, uint64_t out[2]) {
+  uint64_t a = 0xcbf29ce484222325ull, b = 0x9e3779b97f4a7c15ull;
+  for (int64_t v : k) {
+    a = (a ^ (uint64_t)v) * 0x100000001b3ull;
+    a ^= a >> 29;
+    b += (uint64_t)v + 0x632be59bd9b4e019ull;
+    b = (b ^ (b >> 30)) * 0xbf58476d1ce4e5b9ull;
+    b = (b ^ (b >> 27)) * 0x94d049bb133111ebull;
+    b ^= b >> 31;
+  }
+  out[0] = a;
+  out[1] = b;
+}
+
+std::string device_arch(int dev) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return std::string();
+  }
+  return std::string(prop.gcnArchName);
+}
+
+const TuneEntry *tune_find(const uint64_t k[2], const std::string &arch) {
+  for (const TuneEntry &e : g_tune)
+    if (e.k0 == k[0] && e.k1 == k[1] && e.arch == arch) return &e;
+  return nullptr;
+}
+
+void tune_put(const uint64_t k[2], const std::string &arch, int variant, const float *ms) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  TuneEntry e{k[0], k[1], arch, variant, {}};
+  for (int v = 0; v < kVariants; ++v) e.ms[v] = ms[v];
+  for (TuneEntry &x : g_tune)
+    if (x.k0 == e.k0 && x.k1 == e.k1 && x.arch == arch) {
+      x = e;
+      return;
+    }
+  g_tune.push_back(e);
+}
+
 double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -1029,6 +1088,28 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
       return s;
     }
     pl.prof_ms[3] = ms_since(tph);
+    // the tuning store: a request tuned before (in this process or a loaded
+    // file) starts at its variant when that variant fits this plan
+    {
+      std::vector<int64_t> tk;
+      uint64_t th = 0;
+      if (cache_key(probs, nprob, o, 0, tk, th)) {
+        tune_fingerprint(tk, pl.tkey);
+        pl.have_tkey = true;
+        const std::string arch = device_arch(pl.device);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        const TuneEntry *e = tune_find(pl.tkey, arch);
+        if (e) {
+          Fit fit;
+          fit_add(fit, pl);
+          if (variant_fits(fit, pl.opts, e->variant)) {
+            pl.variant = e->variant;
+            h->variant = e->variant;
+            for (int v = 0; v < kVariants; ++v) pl.tuned_ms[v] = e->ms[v];
+          }
+        }
+      }
+    }
     if (keyed) cache_put(chash, std::move(ckey), h->sp);
   } catch (const std::bad_alloc &) {
     delete h;
@@ -1049,6 +1130,90 @@ yastn_status yastn_plan_profile(yastn_plan_t plan, double *ms, int32_t *cached) 
 void yastn_plan_cache_clear(void) {
   std::lock_guard<std::mutex> lk(g_cache_mu);
   g_cache.clear();
+}
+
+yastn_status yastn_tune_save(const char *path) {
+  if (!path) return set_error(YASTN_ERR_ARG, "null path");
+  std::vector<TuneEntry> es;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    es = g_tune;
+  }
+  FILE *f = std::fopen(path, "w");
+  if (!f) return set_error(YASTN_ERR_ARG, std::string("cannot write ") + path);
+  std::fprintf(f, "{\"format\": \"yastn-tuning\", \"version\": 1, \"variants\": %d,\n \"entries\": [", kVariants);
+  for (size_t i = 0; i < es.size(); ++i) {
+    const TuneEntry &e = es[i];
+    std::fprintf(f, "%s\n  {\"key\": \"%016llx%016llx\", \"arch\": \"%s\", \"variant\": %d, \"ms\": [", i ? "," : "",
+                 (unsigned long long)e.k0, (unsigned long long)e.k1, e.arch.c_str(), e.variant);
+    for (int v = 0; v < kVariants; ++v) std::fprintf(f, "%s%.6g", v ? ", " : "", (double)e.ms[v]);
+    std::fprintf(f, "]}");
+  }
+  std::fprintf(f, "\n ]}\n");
+  const bool ok = std::ferror(f) == 0;
+  if (std::fclose(f) != 0 || !ok) return set_error(YASTN_ERR_ARG, std::string("error writing ") + path);
+  return YASTN_OK;
+}
+
+yastn_status yastn_tune_load(const char *path, int32_t *loaded) {
+  if (!path) return set_error(YASTN_ERR_ARG, "null path");
+  if (loaded) *loaded = 0;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return set_error(YASTN_ERR_ARG, std::string("cannot read ") + path);
+  std::string txt;
+  char buf[65536];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, n);
+  std::fclose(f);
+  auto bad = [&](const char *why) { return set_error(YASTN_ERR_ARG, std::string("tuning file ") + path + ": " + why); };
+  if (txt.find("\"format\": \"yastn-tuning\"") == std::string::npos) return bad("not a yastn tuning file");
+  const size_t pv = txt.find("\"variants\": ");
+  if (pv == std::string::npos || std::atoi(txt.c_str() + pv + 12) != kVariants)
+    return bad("made for another set of kernel variants");
+  std::vector<TuneEntry> es;
+  size_t pos = 0;
+  const std::string kk = "{\"key\": \"";
+  while ((pos = txt.find(kk, pos)) != std::string::npos) {
+    pos += kk.size();
+    if (pos + 32 > txt.size()) return bad("truncated key");
+    TuneEntry e{};
+    const std::string hx = txt.substr(pos, 32);
+    for (char c : hx)
+      if (!std::isxdigit((unsigned char)c)) return bad("bad key");
+    e.k0 = std::strtoull(hx.substr(0, 16).c_str(), nullptr, 16);
+    e.k1 = std::strtoull(hx.substr(16).c_str(), nullptr, 16);
+    const size_t pa = txt.find("\"arch\": \"", pos), pvv = txt.find("\"variant\": ", pos),
+                 pm = txt.find("\"ms\": [", pos), pe = txt.find("]}", pos);
+    if (pa == std::string::npos || pvv == std::string::npos || pm == std::string::npos || pe == std::string::npos ||
+        pa > pe || pvv > pe || pm > pe)
+      return bad("malformed entry");
+    const size_t a0 = pa + 9, a1 = txt.find('"', a0);
+    if (a1 == std::string::npos || a1 > pe) return bad("malformed arch");
+    e.arch = txt.substr(a0, a1 - a0);
+    e.variant = std::atoi(txt.c_str() + pvv + 11);
+    if (e.variant < 1 || e.variant >= kVariants) return bad("variant out of range");
+    const char *c = txt.c_str() + pm + 7;
+    for (int v = 0; v < kVariants; ++v) {
+      char *end = nullptr;
+      e.ms[v] = std::strtof(c, &end);
+      if (end == c) return bad("malformed times");
+      c = end;
+      while (*c == ',' || *c == ' ') ++c;
+    }
+    es.push_back(e);
+    pos = pe;
+  }
+  for (const TuneEntry &e : es) {
+    const uint64_t k[2] = {e.k0, e.k1};
+    tune_put(k, e.arch, e.variant, e.ms);
+  }
+  if (loaded) *loaded = (int32_t)es.size();
+  return YASTN_OK;
+}
+
+void yastn_tune_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
 }
 
 yastn_status yastn_plan_output(yastn_plan_t plan, int32_t prob, yastn_tensor_desc *c, int64_t *c_numel) {
@@ -1231,6 +1396,7 @@ yastn_status yastn_plan_autotune(yastn_plan_t plan, const void *const *a, const 
   for (int v = 0; v < kVariants; ++v) plan->p.tuned_ms[v] = tms[v];
   plan->p.variant = best;
   plan->variant = best;
+  if (plan->p.have_tkey) tune_put(plan->p.tkey, device_arch(plan->p.device), best, tms);
   if (chosen) *chosen = best;
   if (times_ms)
     for (int v = 0; v < kVariants; ++v) times_ms[v] = tms[v];

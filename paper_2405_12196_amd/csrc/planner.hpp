@@ -108,6 +108,8 @@ struct Plan {
   bool pair_ok = false;     // A's rows run contiguously in even-length runs: paired-row loads can run
   int nact = 1;             // largest number of A free-leg classes over the plan's problems
   int variant = 0;          // tuned kernel variant (0 = not tuned; set by yastn_plan_autotune)
+  uint64_t tkey[2] = {0, 0};  // the request's fingerprint in the tuning store (valid if have_tkey)
+  bool have_tkey = false;
   float tuned_ms[YASTN_NUM_VARIANTS] = {0};  // the tuning run's times (ms per launch, -1 = does not fit)
   int kmax = 0;             // largest K_X of the plan
   void *dev_mem = nullptr;  // one device allocation holding every table

@@ -161,3 +161,36 @@ def test_complex_and_swap_gate_host_errors():
         Y.SwapGate(small, (0,), (1,), (2,))
     assert e.value.status == "ERR_ARG"
     assert Y.lib().yastn_norm(None, 10, Y.DTYPE_C128, None, None, None) == 1
+
+
+def test_tuning_store_file_format(tmp_path):
+    """The tuning store's file round-trips on the host; files that are not
+    tuning files, were made for another variant count, or hold an entry with
+    a variant out of range are rejected and leave the store as it was."""
+    Y.tune_clear()
+    p = tmp_path / "tune.json"
+    Y.tune_save(str(p))
+    txt = p.read_text()
+    assert '"format": "yastn-tuning"' in txt and f'"variants": {Y.NUM_VARIANTS}' in txt
+    assert Y.tune_load(str(p)) == 0
+    ms = ", ".join(["0.5"] * Y.NUM_VARIANTS)
+    good = ('{"format": "yastn-tuning", "version": 1, "variants": %d,\n "entries": [\n'
+            '  {"key": "%s", "arch": "gfx950", "variant": 21, "ms": [%s]}\n ]}\n'
+            % (Y.NUM_VARIANTS, "0123456789abcdef" * 2, ms))
+    q = tmp_path / "one.json"
+    q.write_text(good)
+    assert Y.tune_load(str(q)) == 1
+    r = tmp_path / "again.json"
+    Y.tune_save(str(r))
+    assert "0123456789abcdef0123456789abcdef" in r.read_text() and '"variant": 21' in r.read_text()
+    for bad in ('{"something": 1}',
+                good.replace('"variants": %d' % Y.NUM_VARIANTS, '"variants": 7'),
+                good.replace('"variant": 21', '"variant": 99'),
+                good.replace("0123456789abcdef" * 2, "xyz")):
+        q.write_text(bad)
+        with pytest.raises(Y.YastnError) as e:
+            Y.tune_load(str(q))
+        assert e.value.status == "ERR_ARG"
+    with pytest.raises(Y.YastnError):
+        Y.tune_load(str(tmp_path / "missing.json"))
+    Y.tune_clear()
