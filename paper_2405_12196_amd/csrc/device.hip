@@ -311,6 +311,10 @@ yastn_status gpu_join(const HostProblem &hp, hipStream_t st, std::vector<std::pa
 
 template <typename T> size_t bytes_of(const std::vector<T> &v) { return v.size() * sizeof(T); }
 
+// Largest resolved column table a plan keeps (beyond it the shared-B kernel
+// reads the column map and the output block offsets instead).
+constexpr int64_t kColResMaxBytes = int64_t(64) << 20;
+
 yastn_status upload(Plan &pl) {
   PlanTables &t = pl.t;
   size_t off = 0;
@@ -325,7 +329,27 @@ yastn_status upload(Plan &pl) {
          o_tiles = take(bytes_of(t.tiles)), o_items = take(bytes_of(t.items)), o_kofs = take(bytes_of(t.kofs)),
          o_kp = take(bytes_of(t.kp)), o_cm = take(bytes_of(t.colmap)), o_bofs = take(bytes_of(t.bofs)),
          o_recs = take(t.tiles.size() * sizeof(DevTileRec)), o_red = take(t.red.size() * sizeof(DevRedItem)),
-         o_lj = take(bytes_of(t.ljobs)), o_plan = take(sizeof(DevPlan));
+         o_lj = take(bytes_of(t.ljobs)), o_ljr = take(t.ljobs.size() * kLdsJobTiles * sizeof(DevTileRec)),
+         o_plan = take(sizeof(DevPlan));
+  // the output columns of every row tuple with its output blocks resolved,
+  // read by the shared-B kernel in one load per column block (plans whose
+  // buffers fit 32-bit offsets, and while the table stays modest: it holds
+  // rows x N_X entries, where the column map and block offsets hold N_X and
+  // rows x Q_X)
+  std::vector<int64_t> cr0;
+  int64_t ncr = 0;
+  if (pl.buf_ok) {
+    cr0.resize(t.rows.size());
+    for (size_t i = 0; i < t.rows.size(); ++i) {
+      cr0[i] = ncr;
+      ncr += t.sectors[t.rows[i].sector].N;
+    }
+    if (ncr * int64_t(sizeof(DevColRes)) > kColResMaxBytes) {
+      cr0.clear();
+      ncr = 0;
+    }
+  }
+  const size_t o_cr = take(size_t(ncr) * sizeof(DevColRes));
   char *base;
   yastn_status s = dmalloc(&base, off);
   if (s) return s;
@@ -369,6 +393,21 @@ yastn_status upload(Plan &pl) {
   dp.recs = reinterpret_cast<const DevTileRec *>(base + o_recs);
   std::vector<DevTileRec> recs;
   build_tile_records(pl, dp, recs);
+  if (!cr0.empty()) {
+    std::vector<DevColRes> cr(static_cast<size_t>(ncr));
+    for (size_t i = 0; i < t.rows.size(); ++i) {
+      const DevRowTuple &rt = t.rows[i];
+      const DevSector &sec = t.sectors[rt.sector];
+      for (int32_t c = 0; c < sec.N; ++c) {
+        const DevColMap &cm = t.colmap[size_t(sec.cm0 + c)];
+        cr[size_t(cr0[i] + c)] = DevColRes{(int32_t)t.cgrid[size_t(rt.cgrid + cm.j)], cm.nj, cm.cl, 0};
+      }
+    }
+    put(o_cr, cr.data(), cr.size() * sizeof(DevColRes));
+    const DevColRes *dcr = reinterpret_cast<const DevColRes *>(base + o_cr);
+    for (size_t i = 0; i < recs.size(); ++i) recs[i].colres = dcr + cr0[size_t(t.tiles[i].rowtuple)] + t.tiles[i].n0;
+  }
+  put(o_recs, recs.data(), recs.size() * sizeof(DevTileRec));
   put(o_recs, recs.data(), recs.size() * sizeof(DevTileRec));
   // shared-B jobs with their B tile's fields
   for (DevLdsJob &lj : t.ljobs) {
@@ -381,6 +420,18 @@ yastn_status upload(Plan &pl) {
     lj.prob = r.prob;
   }
   put(o_lj, t.ljobs.data(), bytes_of(t.ljobs));
+  // the jobs' tile records in job order (an empty slot copies slot 0 with no
+  // rows, so a wave may read its tables and simply skip the rows)
+  std::vector<DevTileRec> ljrecs(t.ljobs.size() * kLdsJobTiles);
+  for (size_t l = 0; l < t.ljobs.size(); ++l)
+    for (int u = 0; u < kLdsJobTiles; ++u) {
+      const int32_t ti = t.ljobs[l].t[u];
+      DevTileRec r = recs[size_t(ti >= 0 ? ti : t.ljobs[l].t[0])];
+      if (ti < 0) r.nrows = 0;
+      ljrecs[l * kLdsJobTiles + size_t(u)] = r;
+    }
+  put(o_ljr, ljrecs.data(), ljrecs.size() * sizeof(DevTileRec));
+  pl.dljrecs = reinterpret_cast<const DevTileRec *>(base + o_ljr);
   // split-K groups with absolute table addresses
   std::vector<DevRedItem> red(t.red.size());
   for (size_t i = 0; i < t.red.size(); ++i) {
@@ -629,6 +680,7 @@ yastn_status launch(const JobRef *jobs, size_t njobs, hipStream_t st, void *cons
       ja.plan = j.plan->dplan;
       ja.recs = j.plan->drecs;
       ja.ljobs = j.plan->dljobs;
+      ja.ljrecs = j.plan->dljrecs;
       ja.ws = reinterpret_cast<char *>(j.ws);
       ja.tile0 = la.ntiles;
       ja.item0 = la.nitems;
@@ -1036,7 +1088,13 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
     for (const DevSector &sec : pl.t.sectors)
       for (int sx = 0; sx < sec.S && pl.pair_ok; ++sx)
         if (sec.nact < 1 || pl.t.ctrs[sec.ctr0 + sx].p[sec.nact - 1] != 1) pl.pair_ok = false;
-    pl.res_fit = maxk <= kResMaxKWide && !pl.t.bofs_overflow;
+    // the register-resident and shared-B kernels address A and C with 24-bit
+    // multiplies of row indices and output block widths
+    int64_t max_m = 0, max_nj = 0;
+    for (const DevRowTuple &rt : pl.t.rows) max_m = std::max<int64_t>(max_m, rt.m);
+    for (const DevColMap &cm : pl.t.colmap) max_nj = std::max<int64_t>(max_nj, cm.nj);
+    pl.res_fit = maxk <= kResMaxKWide && !pl.t.bofs_overflow && max_m < (int64_t(1) << 24) &&
+                 max_nj < (int64_t(1) << 24);
     pl.nact = 1;
     for (const DevProb &dp : pl.t.probs) pl.nact = std::max(pl.nact, (int)dp.nact);
     pl.variant = 0;

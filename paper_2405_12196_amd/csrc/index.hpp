@@ -25,7 +25,9 @@ YASTN_HD void a_rowparts(const DevRowTuple &rt, int nact, int32_t ra, int32_t *r
 // The same RG_a with one multiply-high division per class boundary instead of
 // two modulo operations per class: RG_a = (r mod Lsuf_a) - (r mod Lsuf_{a+1}),
 // r mod Lsuf_0 = r (rows of a tuple are below Lsuf_0 = m_i), Lsuf_nact = 1.
-template <int NA>
+// U24: the row count of the tuple is below 2^24 (so are the quotient and
+// Lsuf), and the device multiplies them at full rate in 24 bits.
+template <int NA, bool U24 = false>
 YASTN_HD void a_rowparts_fast(const DevRowTuple &rt, int nact, int32_t ra, int32_t *rg) {
   int32_t prev = ra;
 #pragma unroll
@@ -33,7 +35,14 @@ YASTN_HD void a_rowparts_fast(const DevRowTuple &rt, int nact, int32_t ra, int32
     int32_t next = 0;
     if (a + 1 < nact) {
       const uint32_t q = (uint32_t)(((uint64_t)(uint32_t)ra * rt.lmag[a + 1]) >> rt.lsh[a + 1]);
+#if defined(__HIP_DEVICE_COMPILE__)
+      if constexpr (U24)
+        next = ra - (int32_t)__umul24(q, (uint32_t)rt.lsuf[a + 1]);
+      else
+        next = ra - (int32_t)q * rt.lsuf[a + 1];
+#else
       next = ra - (int32_t)q * rt.lsuf[a + 1];
+#endif
     }
     rg[a] = a < nact ? prev - next : 0;
     prev = next;

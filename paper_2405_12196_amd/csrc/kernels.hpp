@@ -242,9 +242,17 @@ template <typename T, int CP> struct Src<T, true, CP> {
   __device__ T ld_z(bool v, int32_t i) const {
     return BufIo<T>::template ld<CP>(r, v ? i * (int32_t)sizeof(T) : (int32_t)(0x80000000u - sizeof(T)));
   }
+  // the element at byte offset `byte` if v, else 0
+  __device__ T ldb_z(bool v, int32_t byte) const {
+    return BufIo<T>::template ld<CP>(r, v ? byte : (int32_t)(0x80000000u - sizeof(T)));
+  }
   // elements i and i + 1 in one load if v, else two zeros
   __device__ void ld2_z(bool v, int32_t i, T &x0, T &x1) const {
-    const int32_t byte = v ? i * (int32_t)sizeof(T) : (int32_t)(0x80000000u - 2 * sizeof(T));
+    ld2b_z(v, i * (int32_t)sizeof(T), x0, x1);
+  }
+  // the two elements at byte offset `byte` if v, else two zeros
+  __device__ void ld2b_z(bool v, int32_t byte_in, T &x0, T &x1) const {
+    const int32_t byte = v ? byte_in : (int32_t)(0x80000000u - 2 * sizeof(T));
     if constexpr (sizeof(T) == 8) {
       const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, byte, 0, CP);
       x0 = __builtin_bit_cast(T, u2v{w[0], w[1]});
@@ -646,6 +654,17 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(LaunchArgs args) {
 }
 
 
+// x * y for a row index (or row part) and a per-row factor (class factor,
+// output block width): with 32-bit offsets both are below 2^24 (plans check
+// the row counts and widths for the kernels that use this), so the product is
+// a full-rate 24-bit multiply; 64-bit offsets multiply in 64 bits.
+template <typename Off> __device__ __forceinline__ Off mul_rows(int32_t x, int32_t y) {
+  if constexpr (sizeof(Off) == 4)
+    return (Off)__umul24((uint32_t)x, (uint32_t)y);
+  else
+    return (Off)x * (Off)y;
+}
+
 // ---------------------------------------------------------------------------
 // grouped gather GEMM with the tile's B columns resident in registers
 // ---------------------------------------------------------------------------
@@ -670,7 +689,7 @@ __device__ __forceinline__ void res_load_chunk(const Src<In, BUF, kStream> &A, c
   for (int rb = 0; rb < RB; ++rb) {
     const int lr = 16 * rb + (lane & 15);
     rv[rb] = lr < rows;
-    a_rowparts_fast<NA>(rt, nact, row0 + (rv[rb] ? lr : 0), rg[rb]);
+    a_rowparts_fast<NA, true>(rt, nact, row0 + (rv[rb] ? lr : 0), rg[rb]);
   }
 #pragma unroll
   for (int q = 0; q < KQ; ++q)
@@ -679,7 +698,7 @@ __device__ __forceinline__ void res_load_chunk(const Src<In, BUF, kStream> &A, c
       for (int rb = 0; rb < RB; ++rb) {
         Off o = ko[q];
 #pragma unroll
-        for (int a = 0; a < NA; ++a) o += (Off)pk[q][a] * (Off)rg[rb][a];
+        for (int a = 0; a < NA; ++a) o += mul_rows<Off>(pk[q][a], rg[rb][a]);
         av[q][rb] = A.ld_z(ko[q] >= 0 && rv[rb], o);
       }
     }
@@ -717,6 +736,7 @@ template <typename In, typename Out, bool BUF> struct RecCtx {
   const int32_t *bofs;
   const DevColMap *cmap;
   const int64_t *cgrid;
+  const DevColRes *colres;  // resolved output columns (null: use cmap and cgrid)
   int32_t m0, nrows, n0, ncols, K, N, nact;
   int32_t split;   // 1: split-K tile, accumulators go to the partial slot at `part`
   int64_t part;    // workspace byte offset of the partial slot
@@ -748,6 +768,7 @@ __device__ __forceinline__ void rec_setup(const LaunchArgs &args, const JobArg &
   x.bofs = cst(&r->bofs);
   x.cmap = cst(&r->cmap);
   x.cgrid = cst(&r->cgrid);
+  x.colres = cst(&r->colres);
   const int64_t a_span = cst(&r->a_span), b_span = cst(&r->b_span), c_numel = cst(&r->c_numel);
   x.m0 = cst(&r->m0);
   x.nrows = cst(&r->nrows);
@@ -924,7 +945,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
             const int lr = 16 * rb + M::row(lane, v);
             const bool ok = cv && lr < rows;
             const Out val = Out(acc[rb][cb][v]);
-            x.C.put_if(ok, cbase[cb] + (Off)(x.m0 + mc + lr) * (Off)cnj[cb] + (Off)ccl[cb], val);
+            x.C.put_if(ok, cbase[cb] + mul_rows<Off>(x.m0 + mc + lr, cnj[cb]) + (Off)ccl[cb], val);
             if (do_norm) nacc.add(ok ? (double)val : 0.0);
           }
         }
@@ -958,7 +979,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
 // load is paid once per job instead of once per tile, and the registers it
 // held in k_gemm_res are free for more resident waves.
 // res_load_chunk with the k metadata read from the wave's LDS slice
-// (kw[k] = {A offset of (row 0, k) or -1, class factors}).
+// (kw[k] = {A byte offset of (row 0, k) or -1, class factors in bytes}).
+// Row parts are below 2^24 (plans check the row counts) and the class
+// factors are at most K_X * 8, so every product is a full-rate 24-bit
+// multiply-add (a 32-bit integer multiply issues at a quarter of the rate).
 template <typename In, int RB, int KQ, int NA>
 __device__ __forceinline__ void lds_load_chunk(const Src<In, true, kStream> &A, const DevRowTuple &rt, int nact,
                                                int K, int32_t row0, int rows, int lane, const int32_t (*kw)[1 + NA],
@@ -969,7 +993,7 @@ __device__ __forceinline__ void lds_load_chunk(const Src<In, true, kStream> &A, 
   for (int rb = 0; rb < RB; ++rb) {
     const int lr = 16 * rb + (lane & 15);
     rv[rb] = lr < rows;
-    a_rowparts_fast<NA>(rt, nact, row0 + (rv[rb] ? lr : 0), rg[rb]);
+    a_rowparts_fast<NA, true>(rt, nact, row0 + (rv[rb] ? lr : 0), rg[rb]);
   }
   const int kl = lane >> 4;
 #pragma unroll
@@ -981,8 +1005,8 @@ __device__ __forceinline__ void lds_load_chunk(const Src<In, true, kStream> &A, 
       for (int rb = 0; rb < RB; ++rb) {
         int32_t o = ko;
 #pragma unroll
-        for (int a = 0; a < NA; ++a) o += m[1 + a] * rg[rb][a];
-        av[q][rb] = A.ld_z(ko >= 0 && rv[rb], o);
+        for (int a = 0; a < NA; ++a) o += (int32_t)__umul24((uint32_t)m[1 + a], (uint32_t)rg[rb][a]);
+        av[q][rb] = A.ldb_z(ko >= 0 && rv[rb], o);
       }
     }
 }
@@ -1000,7 +1024,7 @@ __device__ __forceinline__ void lds_load_chunk_pair(const Src<In, true, kStream>
   int32_t rg[NA];
   const int lr = 2 * (lane & 15);
   const bool rv = lr < rows;
-  a_rowparts_fast<NA>(rt, nact, row0 + (rv ? lr : 0), rg);
+  a_rowparts_fast<NA, true>(rt, nact, row0 + (rv ? lr : 0), rg);
   const int kl = lane >> 4;
 #pragma unroll
   for (int q = 0; q < KQ; ++q)
@@ -1009,19 +1033,50 @@ __device__ __forceinline__ void lds_load_chunk_pair(const Src<In, true, kStream>
       const int32_t ko = m[0];
       int32_t o = ko;
 #pragma unroll
-      for (int a = 0; a < NA; ++a) o += m[1 + a] * rg[a];
-      A.ld2_z(ko >= 0 && rv, o, av[q][0], av[q][1]);
+      for (int a = 0; a < NA; ++a) o += (int32_t)__umul24((uint32_t)m[1 + a], (uint32_t)rg[a]);
+      A.ld2b_z(ko >= 0 && rv, o, av[q][0], av[q][1]);
     }
+}
+
+// The tile's output columns from its resolved column table (one 16-byte
+// load per column block instead of the column map and then the output block
+// offsets).
+template <typename Off, int CB>
+__device__ __forceinline__ void tile_columns_res(const DevColRes *cr, int ncols, int lane, Off (&cbase)[CB],
+                                                 int32_t (&cnj)[CB], int32_t (&ccl)[CB]) {
+  DevColRes e[CB];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) {
+    const int lc = 16 * cb + (lane & 15);
+    e[cb] = cr[lc < ncols ? lc : 0];
+  }
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) {
+    const bool v = 16 * cb + (lane & 15) < ncols;
+    cbase[cb] = v ? (Off)e[cb].cbase : (Off)-1;
+    cnj[cb] = e[cb].nj;
+    ccl[cb] = e[cb].cl;
+  }
 }
 
 // NORM: the instance that files the fused output norm (the others carry none
 // of its code).  PAIR (RB = 2): rows loaded in adjacent pairs, row block 0 of
 // the MFMA holds the chunk's even rows and block 1 its odd rows.
+//
+// A workgroup job is one B tile (a sector's k range x column range) and one
+// tile of rows per wave.  Its start is arranged as few dependent round trips
+// as the data allows: the job's fields and the wave's tile record (stored in
+// job order, so its address needs no load) are read together; then the B
+// tile's offsets, the tile's output columns and its k metadata; then the B
+// values and, once the k metadata is in the wave's LDS slice, the A loads of
+// the tile's first row chunk, which are in flight while the B tile is
+// written to LDS and the workgroup waits for it.
 template <typename In, typename Cmp, typename Out, int RB, int CB, int KQ, int NA, int PD, int OCC, bool NORM,
           bool PAIR = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) k_gemm_lds(LaunchArgs args) {
   static_assert(NA <= kRecAct + 1, "tile records carry kRecAct class boundaries");
   static_assert(!PAIR || RB == 2, "paired rows fill two row blocks");
+  static_assert(kLdsJobTiles == 4, "one tile per wave of a job");
   constexpr bool BUF = true;
   typedef int32_t Off;
   typedef Mfma4<Cmp> M;
@@ -1035,49 +1090,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
   const int kl = lane >> 4;
   const int w = uni(threadIdx.x >> 6);
   NormAcc nacc;
-  // one wave tile: its record, output columns and k metadata (into the
-  // wave's LDS slice, where it stays through the row chunks)
   struct Tile {
     RecCtx<In, Out, BUF> x;
     Off cbase[CB];
     int32_t cnj[CB], ccl[CB];
   };
-  auto setup = [&](const JobArg &job, int32_t tl, Tile &T) {
-    rec_setup<In, Out, BUF>(args, job, cst(&job.recs) + tl, T.x);
-    tile_columns<Off, CB>(T.x.cmap, T.x.cgrid, T.x.ncols, lane, T.cbase, T.cnj, T.ccl);
-    const int K = T.x.K;
-    wave_lds_sync();
-#pragma unroll
-    for (int k0 = 0; k0 < 4 * KQ; k0 += 64) {
-      const int k = k0 + lane;
-      const int kk = k < K ? k : 0;
-      const int64_t o = T.x.kofs[kk];
-      int32_t pa[NA];
-#pragma unroll
-      for (int a = 0; a < NA; ++a) pa[a] = T.x.kp[kk].p[a];
-      if (k < 4 * KQ) {
-        kls[w][k][0] = k < K ? (int32_t)o : -1;
-#pragma unroll
-        for (int a = 0; a < NA; ++a) kls[w][k][1 + a] = pa[a];
-      }
-    }
-    wave_lds_sync();
-  };
-  // the tile's rows in chunks of 16 * RB, A loads PD chunks ahead
-  auto run = [&](int32_t tl, const Tile &T) {
+  auto load_chunk = [&](const Tile &T, int c, In (&dst)[KQ][RB]) {
     const RecCtx<In, Out, BUF> &x = T.x;
-    const int K = x.K, nact = x.nact, nrows = x.nrows;
+    if constexpr (PAIR)
+      lds_load_chunk_pair<In, KQ, NA>(x.A, x.rt, x.nact, x.K, x.m0 + c * 16 * RB, min(16 * RB, x.nrows - c * 16 * RB),
+                                      lane, kls[w], dst);
+    else
+      lds_load_chunk<In, RB, KQ, NA>(x.A, x.rt, x.nact, x.K, x.m0 + c * 16 * RB, min(16 * RB, x.nrows - c * 16 * RB),
+                                     lane, kls[w], dst);
+  };
+  // the tile's rows in chunks of 16 * RB, A loads PD chunks ahead; chunk 0
+  // is already in ab[0]
+  auto run = [&](int32_t tl, const Tile &T, In (&ab)[PD + 1][KQ][RB]) {
+    const RecCtx<In, Out, BUF> &x = T.x;
+    const int K = x.K, nrows = x.nrows;
     const int cbn = (x.ncols + 15) >> 4;
     const int nch = (nrows + 16 * RB - 1) / (16 * RB);
-    In ab[PD + 1][KQ][RB];
-    auto load_chunk = [&](int c, In (&dst)[KQ][RB]) {
-      if constexpr (PAIR)
-        lds_load_chunk_pair<In, KQ, NA>(x.A, x.rt, nact, K, x.m0 + c * 16 * RB, min(16 * RB, nrows - c * 16 * RB),
-                                        lane, kls[w], dst);
-      else
-        lds_load_chunk<In, RB, KQ, NA>(x.A, x.rt, nact, K, x.m0 + c * 16 * RB, min(16 * RB, nrows - c * 16 * RB),
-                                       lane, kls[w], dst);
-    };
     auto compute_chunk = [&](int c, const In (&av)[KQ][RB]) {
       const int mc = c * 16 * RB;
       const int rows = min(16 * RB, nrows - mc);
@@ -1116,21 +1149,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
             const int lr = PAIR ? 2 * M::row(lane, v) + rb : 16 * rb + M::row(lane, v);
             const bool ok = cv && lr < rows;
             const Out val = Out(acc[rb][cb][v]);
-            x.C.put_if(ok, T.cbase[cb] + (Off)(x.m0 + mc + lr) * (Off)T.cnj[cb] + (Off)T.ccl[cb], val);
+            x.C.put_if(ok, T.cbase[cb] + (Off)__umul24((uint32_t)(x.m0 + mc + lr), (uint32_t)T.cnj[cb]) + (Off)T.ccl[cb],
+                       val);
             if constexpr (NORM) nacc.add(ok ? (double)val : 0.0);
           }
         }
       }
     };
 #pragma unroll
-    for (int u = 0; u < PD; ++u)
-      if (u < nch) load_chunk(u, ab[u]);
+    for (int u = 1; u < PD; ++u)
+      if (u < nch) load_chunk(T, u, ab[u]);
     for (int c0 = 0; c0 < nch; c0 += PD + 1) {
 #pragma unroll
       for (int u = 0; u <= PD; ++u) {
         const int c = c0 + u;
         if (c < nch) {
-          if (c + PD < nch) load_chunk(c + PD, ab[(u + PD) % (PD + 1)]);
+          if (c + PD < nch && c + PD > 0) load_chunk(T, c + PD, ab[(u + PD) % (PD + 1)]);
           compute_chunk(c, ab[u]);
         }
       }
@@ -1142,42 +1176,65 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
     int jb = 0;
     while (jb + 1 < args.njobs && j >= args.jobs[jb + 1].tile0) ++jb;
     const JobArg &job = args.jobs[jb];
-    const DevLdsJob *lj = cst(&job.ljobs) + (j - job.tile0 + job.ptile0);
-    {
-      // the B tile: every offset-table read, then every B read, then the
-      // LDS stores
-      const int32_t *bofs = cst(&lj->bofs);
-      const int32_t K = cst(&lj->K), N = cst(&lj->N), n0 = cst(&lj->n0);
-      Src<In, BUF> B;
-      B.init(prob_ptrs(args, job.prob0 + cst(&lj->prob) - job.plo).b, cst(&lj->b_span));
-      int32_t bo[BR];
-      bool bv[BR];
+    const int32_t jl = j - job.tile0 + job.ptile0;
+    const DevLdsJob *lj = cst(&job.ljobs) + jl;
+    Tile T;
+    rec_setup<In, Out, BUF>(args, job, cst(&job.ljrecs) + (int64_t)jl * kLdsJobTiles + w, T.x);
+    const int32_t tl = uni(cst(&lj->t[w]));
+    const int32_t *bofs = cst(&lj->bofs);
+    const int32_t K = cst(&lj->K), N = cst(&lj->N), n0 = cst(&lj->n0);
+    Src<In, BUF> B;
+    B.init(prob_ptrs(args, job.prob0 + cst(&lj->prob) - job.plo).b, cst(&lj->b_span));
+    // B tile offsets, the tile's output columns and its k metadata
+    int32_t bo[BR];
+    bool bv[BR];
 #pragma unroll
-      for (int i = 0; i < BR; ++i) {
-        const int e = min((int)threadIdx.x + 256 * i, BE - 1);
-        const int k = e / BW, c = n0 + e % BW;
-        bv[i] = k < K && c < N;
-        bo[i] = bofs[bv[i] ? k * N + c : 0];
+    for (int i = 0; i < BR; ++i) {
+      const int e = min((int)threadIdx.x + 256 * i, BE - 1);
+      const int k = e / BW, c = n0 + e % BW;
+      bv[i] = k < K && c < N;
+      bo[i] = bofs[bv[i] ? k * N + c : 0];
+    }
+    if (T.x.colres)
+      tile_columns_res<Off, CB>(T.x.colres, T.x.ncols, lane, T.cbase, T.cnj, T.ccl);
+    else
+      tile_columns<Off, CB>(T.x.cmap, T.x.cgrid, T.x.ncols, lane, T.cbase, T.cnj, T.ccl);
+    int32_t ko[(4 * KQ + 63) / 64], pk[(4 * KQ + 63) / 64][NA];
+#pragma unroll
+    for (int k0 = 0; k0 < 4 * KQ; k0 += 64) {
+      const int k = k0 + lane;
+      const int kk = k < T.x.K ? k : 0;
+      ko[k0 / 64] = k < T.x.K ? (int32_t)T.x.kofs[kk] : -1;
+#pragma unroll
+      for (int a = 0; a < NA; ++a) pk[k0 / 64][a] = T.x.kp[kk].p[a];
+    }
+    // B values
+    In v[BR];
+#pragma unroll
+    for (int i = 0; i < BR; ++i) v[i] = B.ld_z(bv[i] && bo[i] >= 0, bo[i]);
+    // k metadata into the wave's LDS slice, then the first chunk's A loads
+#pragma unroll
+    for (int k0 = 0; k0 < 4 * KQ; k0 += 64) {
+      const int k = k0 + lane;
+      if (k < 4 * KQ) {
+        kls[w][k][0] = ko[k0 / 64] >= 0 ? ko[k0 / 64] * (int32_t)sizeof(In) : -1;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) kls[w][k][1 + a] = pk[k0 / 64][a] * (int32_t)sizeof(In);
       }
-      In v[BR];
+    }
+    wave_lds_sync();
+    In ab[PD + 1][KQ][RB];
+    const bool live = T.x.nrows > 0;  // empty job slot: a copy of slot 0 with no rows
+    if (live) load_chunk(T, 0, ab[0]);
+    // the B tile into LDS
 #pragma unroll
-      for (int i = 0; i < BR; ++i) v[i] = B.ld_z(bv[i] && bo[i] >= 0, bo[i]);
-#pragma unroll
-      for (int i = 0; i < BR; ++i) {
-        const int e = (int)threadIdx.x + 256 * i;
-        if (e < BE) bl[e / BW][e % BW] = Cmp(v[i]);
-      }
+    for (int i = 0; i < BR; ++i) {
+      const int e = (int)threadIdx.x + 256 * i;
+      if (e < BE) bl[e / BW][e % BW] = Cmp(v[i]);
     }
     __syncthreads();
-#pragma unroll 1
-    for (int h = 0; h < kLdsJobTiles / 4; ++h) {
-      const int32_t tl = uni(cst(&lj->t[w + 4 * h]));
-      if (tl < 0) continue;
-      Tile T;
-      setup(job, tl, T);
-      run(tl, T);
-    }
-    __syncthreads();  // the next job overwrites the B tile
+    if (live) run(tl, T, ab);
+    __syncthreads();  // the next job overwrites the B tile and the k metadata
   }
 }
 

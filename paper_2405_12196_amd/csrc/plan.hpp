@@ -80,6 +80,17 @@ struct DevColMap {             // one column of a sector's C_X / B_X
   int32_t pad;
 };
 
+// One column of a sector's C_X with the output block of one row tuple
+// resolved (the column map and the row tuple's output block offsets in one
+// 16-byte entry, so a tile's columns take one load instead of two dependent
+// ones).
+struct alignas(16) DevColRes {
+  int32_t cbase;               // C element offset of output block (i, j), -1 if absent
+  int32_t nj;                  // n_j
+  int32_t cl;                  // column within tuple j
+  int32_t pad;
+};
+
 struct DevKP {                 // P_a of one contracted index
   int32_t p[kMaxAct];
 };
@@ -143,7 +154,8 @@ struct DevTileRec {
   int32_t split;               // 1: a split-K tile, accumulators go to its partial slot; 0: to C
   int64_t bpack;               // the sector's packed B_X from k0 on, in the workspace (elements)
   int64_t part;                // split-K tiles: workspace byte offset of the partial slot
-  int64_t pad2;
+  const struct DevColRes *colres;  // the tile's columns from n0, output blocks resolved for its
+                                   // row tuple (plans whose buffers fit 32-bit offsets; else null)
 };
 static_assert(sizeof(DevTileRec) == 160, "tile record layout");
 
@@ -204,6 +216,8 @@ struct JobArg {                // a range of one plan's problems inside a launch
   const DevPlan *plan;
   const DevTileRec *recs;      // the plan's tile records (device)
   const DevLdsJob *ljobs;      // the plan's shared-B jobs (device)
+  const DevTileRec *ljrecs;    // the records of those jobs' tiles, kLdsJobTiles per job in
+                               // slot order (an empty slot: a copy of slot 0 with no rows)
   char *ws;                    // job workspace (packed B)
   int32_t tile0, item0;        // first launch-global tile (shared-B job) / pack item of this job
   int32_t ptile0, pitem0;      // first plan-local tile (shared-B job) / pack item of this job

@@ -117,6 +117,7 @@ struct Plan {
   const DevTileRec *drecs = nullptr;  // device tile records
   const DevRedItem *dred = nullptr;   // device split-K groups (null when none)
   const DevLdsJob *dljobs = nullptr;  // device shared-B jobs
+  const DevTileRec *dljrecs = nullptr;  // device records of the shared-B jobs' tiles, in job order
   size_t ws_bytes = 0;
   size_t norm_off = 0;      // workspace offset of the fused norm's per-tile parts
   size_t ptab_off = 0;      // workspace offset of the problem pointer table (groups of > kMaxProbs problems)
