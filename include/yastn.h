@@ -247,7 +247,11 @@ yastn_status yastn_contract_timed(yastn_plan_t plan, const void *const *a, const
  * to four row tiles of one sector column range into shared memory once
  * (three chunk / occupancy shapes; FP32 arithmetic: variant 22 only);
  * 23: as 22 with A's rows loaded in adjacent pairs (FP64, K <= 40, plans
- * whose A rows run contiguously in even-length runs).
+ * whose A rows run contiguously in even-length runs);
+ * 24: as 20-22 for any K, the B tile staged in shared memory in chunks of 32
+ * k straight from B's blocks (no packed copy of B), the next chunk's loads in
+ * flight during the current chunk's products (FP64, plans whose tiles hold at
+ * most 32 rows).
  * yastn_plan_autotune runs every variant that fits the plan `reps` times on
  * the caller's buffers (same arguments as yastn_contract; C is overwritten),
  * times them with HIP events, keeps the fastest in the plan and returns its
@@ -262,7 +266,7 @@ yastn_status yastn_contract_timed(yastn_plan_t plan, const void *const *a, const
  * yastn_plan_set_variant sets the variant of this handle only;
  * YASTN_ERR_STATE if the variant does not fit.  A new handle starts at the
  * structure's tuned variant (0, the heuristic, before any tuning). */
-#define YASTN_NUM_VARIANTS 24
+#define YASTN_NUM_VARIANTS 25
 yastn_status yastn_plan_autotune(yastn_plan_t plan, const void *const *a, const void *const *b,
                                  void *const *c, void *workspace, void *hip_stream, int32_t reps,
                                  int32_t *chosen, float *times_ms);

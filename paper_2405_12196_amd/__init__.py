@@ -55,7 +55,7 @@ CTM_INPUTS = ("C1", "C2", "C3", "C4", "T1", "T2", "T3", "T4", "A")
 CTM_AUTOTUNE = 1
 REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 MAX_CHAIN = 8
-NUM_VARIANTS = 24
+NUM_VARIANTS = 25
 SCRATCH_BYTES = 64 << 20
 
 

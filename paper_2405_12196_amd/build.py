@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libyastn.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["device.hip", "host.cpp", "serve.cpp", "ops.hip", "svd.hip", "ctm.hip", "fermion.hip", "inst_f64.hip", "inst_f32d.hip", "inst_f32f.hip",
-           "inst_bf16.hip", "inst_lds.hip", "inst_lds_norm.hip"]
+           "inst_bf16.hip", "inst_lds.hip", "inst_lds_norm.hip", "inst_ldsk.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -466,6 +466,7 @@ yastn_status upload(Plan &pl) {
 //   kVariantRes0 .. + kNumRes - 1      k_gemm_res with shape kResShapes[v - kVariantRes0]
 //   kVariantPf0 .. + kNumPf - 1        k_gemm_pf with shape kPfShapes[v - kVariantPf0]
 //   kVariantLds0 .. + kNumLds - 1      k_gemm_lds with shape kLdsShapes[v - kVariantLds0]
+//   kVariantLdsK                       k_gemm_ldsk (K in chunks through LDS)
 // yastn_plan_autotune times the candidates that fit the plan.  Tile widths
 // (CB) must cover the plan's tile width; the rest only tunes speed.
 // Wave tiles a launch should have at least, when the plan picks the tile
@@ -475,7 +476,8 @@ constexpr int kVariantRows = kNumMfma + 1;
 constexpr int kVariantRes0 = kVariantRows + 1;
 constexpr int kVariantPf0 = kVariantRes0 + kNumRes;
 constexpr int kVariantLds0 = kVariantPf0 + kNumPf;
-constexpr int kVariants = kVariantLds0 + kNumLds;
+constexpr int kVariantLdsK = kVariantLds0 + kNumLds;
+constexpr int kVariants = kVariantLdsK + 1;
 static_assert(kVariants == YASTN_NUM_VARIANTS, "variant count must match the header");
 
 enum Family { FAM_MFMA, FAM_ROWS, FAM_RES, FAM_PF, FAM_BF16, FAM_LDS };
@@ -521,7 +523,9 @@ KernelFn res_kernel(const yastn_options &o, bool buf, int shape, int cb, int kq,
 // Which variants can run a set of plans in one launch.
 struct Fit {
   int cb = 1, kmax = 0, nact = 1;
+  int tmax = 0;           // tallest wave tile (rows) of the plans
   bool buf = true, rows = true, res = true, bf16 = false, pair = true;
+  bool ldsk = true;       // every plan allows direct B reads and 24-bit row addressing
   bool split = false;     // some plan has split-K tiles (only the pipelined kernel writes partials)
   bool rows_pick = true;  // every plan asked for the row kernel (YASTN_FLAG_ROWS)
   bool mfma_pick = true;  // every plan asked for MFMA tiles (YASTN_FLAG_MFMA)
@@ -535,6 +539,8 @@ void fit_add(Fit &f, const Plan &p) {
   f.rows = f.rows && p.rows_fit;
   f.res = f.res && p.res_fit;
   f.pair = f.pair && p.pair_ok;
+  f.ldsk = f.ldsk && p.ldsk_fit;
+  f.tmax = std::max(f.tmax, 16 * p.rb * p.nch);
   f.bf16 = is_bf16(p.opts);
   f.split = f.split || !p.t.red.empty();
   f.rows_pick = f.rows_pick && p.opts.flags == YASTN_FLAG_ROWS;
@@ -554,7 +560,9 @@ bool variant_fits(const Fit &f, const yastn_options &o, int v) {
     if (!f.res || !f.buf || f.kmax > res_max_k(v - kVariantRes0)) return false;
     return o.precision == YASTN_F64 || v == kVariantRes0 + 1;  // FP32: one shape compiled (kResShapes[1])
   }
-  if (v >= kVariantLds0 && v < kVariants) {  // K <= 80; FP32: one shape compiled (kLdsShapes[2])
+  if (v == kVariantLdsK)  // FP64, tiles of at most 16 * kLdskRb rows, B read through the offset table
+    return o.precision == YASTN_F64 && f.buf && !f.split && f.ldsk && f.tmax <= 16 * kLdskRb && f.cb <= 4;
+  if (v >= kVariantLds0 && v < kVariantLdsK) {  // K <= 80; FP32: one shape compiled (kLdsShapes[2])
     if (!f.res || !f.buf || f.kmax > kResMaxKWide) return false;
     if (v == kVariantLds0 + kLdsPairShape) return o.precision == YASTN_F64 && f.pair && f.kmax <= kPairMaxK;
     return o.precision == YASTN_F64 || v == kVariantLds0 + 2;
@@ -585,6 +593,7 @@ Choice choose(const Fit &f, const yastn_options &o, int variant, bool norm = fal
   const int kq = (f.kmax + 3) / 4;
   const int na = f.nact <= 2 ? 2 : 4;
   if (variant == kVariantRows) return Choice{FAM_ROWS, rows_kernel(o, f.buf, f.kmax), pack_kernel(o)};
+  if (variant == kVariantLdsK) return Choice{FAM_LDS, ldsk_f64(f.cb, na, norm), nullptr};
   if (variant >= kVariantLds0) {
     KernelFn fn = o.precision == YASTN_F64          ? lds_f64(variant - kVariantLds0, f.cb, kq, na, norm)
                   : o.in_dtype == YASTN_DTYPE_F64 ? lds_f32d(o.out_dtype, f.cb, kq, norm)
@@ -1093,8 +1102,8 @@ yastn_status yastn_plan(const yastn_problem *probs, int32_t nprob, const yastn_o
     int64_t max_m = 0, max_nj = 0;
     for (const DevRowTuple &rt : pl.t.rows) max_m = std::max<int64_t>(max_m, rt.m);
     for (const DevColMap &cm : pl.t.colmap) max_nj = std::max<int64_t>(max_nj, cm.nj);
-    pl.res_fit = maxk <= kResMaxKWide && !pl.t.bofs_overflow && max_m < (int64_t(1) << 24) &&
-                 max_nj < (int64_t(1) << 24);
+    pl.ldsk_fit = !pl.t.bofs_overflow && max_m < (int64_t(1) << 24) && max_nj < (int64_t(1) << 24);
+    pl.res_fit = maxk <= kResMaxKWide && pl.ldsk_fit;
     pl.nact = 1;
     for (const DevProb &dp : pl.t.probs) pl.nact = std::max(pl.nact, (int)dp.nact);
     pl.variant = 0;

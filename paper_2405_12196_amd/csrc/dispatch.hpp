@@ -49,6 +49,10 @@ constexpr LdsShape kLdsShapes[] = {{1, 1, 2}, {1, 0, 3}, {2, 0, 2}, {2, 0, 2}};
 constexpr int kLdsPairShape = 3;
 constexpr int kPairMaxK = 40;
 constexpr int kNumLds = sizeof(kLdsShapes) / sizeof(LdsShape);
+// k_gemm_ldsk: the shared-B jobs with K in chunks of 4 * kLdskKq, tiles of
+// at most 16 * kLdskRb rows (any K; FP64)
+constexpr int kLdskRb = 2;
+constexpr int kLdskKq = 8;
 constexpr int kResMaxK = 64;      // K limit of the shapes with occ > 1
 constexpr int kResMaxKWide = 80;  // K limit of the occupancy-1 shape
 constexpr int res_max_k(int shape) { return kResShapes[shape].occ == 1 ? kResMaxKWide : kResMaxK; }
@@ -61,6 +65,7 @@ KernelFn pf_f64(bool buf, int shape, int cb, int na);
 KernelFn pack_f64();
 KernelFn lds_f64(int shape, int cb, int kq, int na, bool norm);  // kq <= 20; norm: files the fused norm
 KernelFn lds_f64_norm(int shape, int cb, int kq, int na);
+KernelFn ldsk_f64(int cb, int na, bool norm);  // cb <= 4; norm: files the fused norm
 // FP32 arithmetic with FP64 input buffers (out: F64 or F32)
 KernelFn gemm4_f32d(yastn_dtype out, bool buf, int shape, int cb);
 KernelFn res_f32d(yastn_dtype out, bool buf, int cb, int kq);

@@ -1239,6 +1239,189 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
 }
 
 // ---------------------------------------------------------------------------
+// shared-B grouped GEMM for sectors of any K, k in chunks through LDS
+// ---------------------------------------------------------------------------
+// The shared-B kernel's jobs (four tiles of 16 * RB rows of one sector column
+// range, one per wave) with K walked in chunks of 4 * KQ: the workgroup
+// stages each chunk of the B tile in LDS (two buffers, alternating, so the
+// workgroup meets once per chunk) straight from B's blocks through
+// the plan's offset table (no packed copy of B, so no pack pass), each wave
+// stages the chunk's k metadata in its LDS slice (two slices, alternating)
+// and keeps its accumulators across the chunks.  While the MFMAs of chunk c
+// run, the loads of chunk c + 1 (B values, A) and the offsets of chunk c + 2
+// (B offsets, k metadata) are in flight.  Tiles hold at most 16 * RB rows.
+template <typename In, typename Cmp, typename Out, int RB, int CB, int KQ, int NA, int OCC, bool NORM>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) k_gemm_ldsk(LaunchArgs args) {
+  static_assert(NA <= kRecAct + 1, "tile records carry kRecAct class boundaries");
+  static_assert(kLdsJobTiles == 4, "one tile per wave of a job");
+  static_assert(4 * KQ <= 64, "one k of a chunk per lane");
+  constexpr bool BUF = true;
+  typedef int32_t Off;
+  typedef Mfma4<Cmp> M;
+  typedef typename M::acc_t acc_t;
+  constexpr int BW = 16 * CB;       // tile columns
+  constexpr int KC = 4 * KQ;        // k of a chunk
+  constexpr int BE = KC * BW;       // B chunk elements
+  constexpr int BR = (BE + 255) / 256;
+  __shared__ Cmp bl[2][KC][BW];  // two chunks, alternating
+  __shared__ int32_t kls[4][2][KC][1 + NA];  // per wave, two chunks: A byte offset of (row 0, k) or -1, factors
+  const int lane = threadIdx.x & 63;
+  const int kl = lane >> 4;
+  const int w = uni(threadIdx.x >> 6);
+  NormAcc nacc;
+  for (int j = blockIdx.x; j < args.ntiles; j += gridDim.x) {
+    int jb = 0;
+    while (jb + 1 < args.njobs && j >= args.jobs[jb + 1].tile0) ++jb;
+    const JobArg &job = args.jobs[jb];
+    const int32_t jl = j - job.tile0 + job.ptile0;
+    const DevLdsJob *lj = cst(&job.ljobs) + jl;
+    RecCtx<In, Out, BUF> x;
+    rec_setup<In, Out, BUF>(args, job, cst(&job.ljrecs) + (int64_t)jl * kLdsJobTiles + w, x);
+    const int32_t tl = uni(cst(&lj->t[w]));
+    const int32_t *bofs = cst(&lj->bofs);
+    const int32_t K = cst(&lj->K), N = cst(&lj->N), n0 = cst(&lj->n0);
+    Src<In, BUF> B;
+    B.init(prob_ptrs(args, job.prob0 + cst(&lj->prob) - job.plo).b, cst(&lj->b_span));
+    Off cbase[CB];
+    int32_t cnj[CB], ccl[CB];
+    if (x.colres)
+      tile_columns_res<Off, CB>(x.colres, x.ncols, lane, cbase, cnj, ccl);
+    else
+      tile_columns<Off, CB>(x.cmap, x.cgrid, x.ncols, lane, cbase, cnj, ccl);
+    const bool live = x.nrows > 0;  // empty job slot: a copy of slot 0 with no rows
+    const int nk = (K + KC - 1) / KC;
+    // per-chunk loads: the B tile's offsets, the tile's k metadata (one k per
+    // lane), the B values, the A values
+    auto load_bofs = [&](int c, int32_t (&bo)[BR], bool (&bv)[BR]) {
+#pragma unroll
+      for (int i = 0; i < BR; ++i) {
+        const int e = min((int)threadIdx.x + 256 * i, BE - 1);
+        const int k = c * KC + e / BW, col = n0 + e % BW;
+        bv[i] = k < K && col < N;
+        bo[i] = bofs[bv[i] ? k * N + col : 0];
+      }
+    };
+    auto load_kmeta = [&](int c, int32_t &ko, int32_t (&pk)[NA]) {
+      const int k = c * KC + lane;
+      const bool v = lane < KC && k < x.K;
+      const int kk = v ? k : 0;
+      ko = v ? (int32_t)x.kofs[kk] : -1;
+#pragma unroll
+      for (int a = 0; a < NA; ++a) pk[a] = x.kp[kk].p[a];
+    };
+    auto load_b = [&](const int32_t (&bo)[BR], const bool (&bv)[BR], In (&v)[BR]) {
+#pragma unroll
+      for (int i = 0; i < BR; ++i) v[i] = B.ld_z(bv[i] && bo[i] >= 0, bo[i]);
+    };
+    auto put_kmeta = [&](int buf, int32_t ko, const int32_t (&pk)[NA]) {
+      if (lane < KC) {
+        kls[w][buf][lane][0] = ko >= 0 ? ko * (int32_t)sizeof(In) : -1;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) kls[w][buf][lane][1 + a] = pk[a] * (int32_t)sizeof(In);
+      }
+      wave_lds_sync();
+    };
+    auto load_a = [&](int c, int buf, In (&av)[KQ][RB]) {
+      lds_load_chunk<In, RB, KQ, NA>(x.A, x.rt, x.nact, min(KC, K - c * KC), x.m0, x.nrows, lane, kls[w][buf], av);
+    };
+    auto put_b = [&](int buf, const In (&v)[BR]) {
+#pragma unroll
+      for (int i = 0; i < BR; ++i) {
+        const int e = (int)threadIdx.x + 256 * i;
+        if (e < BE) bl[buf][e / BW][e % BW] = Cmp(v[i]);
+      }
+    };
+    const int cbn = (x.ncols + 15) >> 4;
+    const int rbn = (x.nrows + 15) >> 4;
+    acc_t acc[RB][CB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = acc_t{0, 0, 0, 0};
+    auto mfma_chunk = [&](int c, const In (&av)[KQ][RB]) {
+      const int Kc = min(KC, K - c * KC);
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) {
+        if (4 * q < Kc) {
+          Cmp b[CB];
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) b[cb] = bl[c & 1][4 * q + kl][16 * cb + (lane & 15)];
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            if (rb < rbn)
+#pragma unroll
+              for (int cb = 0; cb < CB; ++cb)
+                if (cb < cbn) acc[rb][cb] = M::run(Cmp(av[q][rb]), b[cb], acc[rb][cb]);
+        }
+      }
+    };
+    // prologue: chunk 0's metadata, B values and A loads; chunk 1's offsets
+    int32_t bo[BR];
+    bool bv[BR];
+    int32_t ko, pk[NA];
+    In v[BR];
+    In av0[KQ][RB], av1[KQ][RB];
+    load_bofs(0, bo, bv);
+    load_kmeta(0, ko, pk);
+    load_b(bo, bv, v);
+    put_kmeta(0, ko, pk);
+    if (live) load_a(0, 0, av0);
+    if (nk > 1) {
+      load_bofs(1, bo, bv);
+      load_kmeta(1, ko, pk);
+    }
+    put_b(0, v);
+    __syncthreads();
+    // chunk c: the loads of chunk c + 1 and the offsets of chunk c + 2 go out
+    // before chunk c's MFMAs; chunk c + 1's B values then go to the other LDS
+    // buffer (every wave finished chunk c - 1, which used it, before the
+    // previous barrier) and the workgroup meets once
+    auto step = [&](int c, const In (&acur)[KQ][RB], In (&anext)[KQ][RB]) {
+      const int nb = (c + 1) & 1;
+      if (c + 1 < nk) {
+        load_b(bo, bv, v);
+        put_kmeta(nb, ko, pk);
+        if (live) load_a(c + 1, nb, anext);
+        if (c + 2 < nk) {
+          load_bofs(c + 2, bo, bv);
+          load_kmeta(c + 2, ko, pk);
+        }
+      }
+      if (live) mfma_chunk(c, acur);
+      if (c + 1 < nk) put_b(nb, v);
+      __syncthreads();  // chunk c + 1's B tile is in LDS; every wave is done with chunk c
+    };
+    for (int c = 0; c < nk; c += 2) {
+      step(c, av0, av1);
+      if (c + 1 < nk) step(c + 1, av1, av0);
+    }
+    if (live) {
+      // stores without per-lane branches: padding rows and columns store
+      // past the end of C (dropped) and add 0 to the norm
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        if (cb >= cbn) continue;
+        const bool cv = cbase[cb] >= 0;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          if (rb >= rbn) continue;
+#pragma unroll
+          for (int vv = 0; vv < 4; ++vv) {
+            const int lr = 16 * rb + M::row(lane, vv);
+            const bool ok = cv && lr < x.nrows;
+            const Out val = Out(acc[rb][cb][vv]);
+            x.C.put_if(ok, cbase[cb] + (Off)__umul24((uint32_t)(x.m0 + lr), (uint32_t)cnj[cb]) + (Off)ccl[cb], val);
+            if constexpr (NORM) nacc.add(ok ? (double)val : 0.0);
+          }
+        }
+      }
+      if constexpr (NORM) norm_file_tile(args.norm, tl, lane, nacc);
+    }
+    __syncthreads();  // the next job overwrites the B chunk and the k metadata
+  }
+}
+
+// ---------------------------------------------------------------------------
 // grouped gather GEMM for sectors of any K, software-pipelined over k
 // ---------------------------------------------------------------------------
 // Tiles start from the flat tile record (as k_gemm_res); B comes from the

@@ -106,6 +106,7 @@ struct Plan {
   bool rows_fit = false;    // every sector has K, N <= 64: the row-per-lane kernel can run
   bool res_fit = false;     // every sector has K <= 80 and B offsets fit int32: k_gemm_res can run
   bool pair_ok = false;     // A's rows run contiguously in even-length runs: paired-row loads can run
+  bool ldsk_fit = false;    // B offsets fit int32, rows and block widths below 2^24: the K-chunked shared-B kernel can run
   int nact = 1;             // largest number of A free-leg classes over the plan's problems
   int variant = 0;          // tuned kernel variant (0 = not tuned; set by yastn_plan_autotune)
   uint64_t tkey[2] = {0, 0};  // the request's fingerprint in the tuning store (valid if have_tkey)

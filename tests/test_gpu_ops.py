@@ -56,6 +56,45 @@ def test_permute_ctm_intermediate():
     assert G.structure_equal(s, ref) and np.array_equal(v, ref.data)
 
 
+@pytest.mark.parametrize("perm", [[1, 3, 4, 5, 0, 2, 6], [4, 0, 5, 1, 2, 3, 6]])
+def test_permute_ctm_blocks_gradient_order(perm):
+    """The chi = 128 step-3 output with its contracted legs (b1, b4, p) moved
+    behind the free ones (the leg order the last contraction's gradient
+    produces), and back, in FP64 and FP32: large blocks whose output runs
+    are strided in the input."""
+    t = W.ctm()
+    cur = None
+    for (an, bn), (ax, bx) in zip([("C", "T1"), (None, "T4"), (None, "A")], t["axes"][:3]):
+        cur = oracle.tensordot_blockpair(t[an] if an else cur, t[bn], ax, bx)
+    ref = oracle.transpose(cur, perm)
+    for dt in (Y.DTYPE_F64, Y.DTYPE_F32):
+        s, v = run_perm(cur, perm, dt)
+        want = ref.data if dt == Y.DTYPE_F64 else ref.data.astype(np.float32).astype(np.float64)
+        assert G.structure_equal(s, ref) and np.array_equal(v, want)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_permute_large_blocks(seed):
+    """Large blocks (dims up to 70, dims of 1 anywhere) under random
+    permutations, in FP64 and FP32."""
+    from workloads import Leg
+    rng = np.random.default_rng(seed + 77)
+    while True:  # at most 4 M elements
+        legs = []
+        for _ in range(3 + seed % 3):
+            d = [int(v) for v in rng.choice([1, 2, 5, 33, 70], size=2)]
+            legs.append(Leg(int(rng.choice([1, -1])), ((0,), (1,)), tuple(d)))
+        a = W.rand(legs, (0,), (2,), seed + 5)
+        if a.data.size <= 4_000_000:
+            break
+    perm = [int(v) for v in rng.permutation(a.rank)]
+    ref = oracle.transpose(a, perm)
+    for dt in (Y.DTYPE_F64, Y.DTYPE_F32):
+        s, v = run_perm(a, perm, dt)
+        want = ref.data if dt == Y.DTYPE_F64 else ref.data.astype(np.float32).astype(np.float64)
+        assert G.structure_equal(s, ref) and np.array_equal(v, want)
+
+
 def test_permute_empty_and_bad_perm():
     a, _, _, _ = random_problem(9300, "U1", rank_a=3, rank_b=1)
     empty = a.copy()

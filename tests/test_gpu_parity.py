@@ -351,8 +351,9 @@ def test_norm_f64(n):
 
 
 # ------------------------------------------------------ kernel variants
-NUM_VARIANTS = 24  # yastn.h YASTN_NUM_VARIANTS
+NUM_VARIANTS = 25  # yastn.h YASTN_NUM_VARIANTS
 PAIR_VARIANT = 23  # paired-row loads: only plans whose A rows allow them
+CHUNK_VARIANT = 24  # K in chunks through LDS: any K, tiles of at most 32 rows
 
 
 @pytest.mark.parametrize("variant", range(1, NUM_VARIANTS))
@@ -370,6 +371,7 @@ def test_every_variant_matches_oracle(seed, variant):
         if variant == PAIR_VARIANT:  # needs K <= 40 and A rows in even contiguous runs
             assert e.status == "ERR_STATE"
             return
+        assert variant != CHUNK_VARIANT, "the K-chunked kernel fits every small plan"
         # the row kernel needs K, N <= 64, the register-resident B kernels
         # K <= 64 (variant 16 and the shared-B variants 20-22: K <= 80)
         assert e.status == "ERR_STATE" and variant >= 7 and not 17 <= variant <= 19
