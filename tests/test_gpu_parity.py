@@ -160,6 +160,48 @@ def test_u1_uneven_batched_one_launch():
     assert sum(pl.stats(i)["sectors"] for i in range(len(probs))) == 664
 
 
+def test_k_chunked_shared_b_fused_norm():
+    """The K-chunked shared-B kernel's fused-norm instance on the D = 18
+    contraction (K = 76: three chunks of 32, the last one partial): C and
+    both norms against the oracle, and bitwise on a second run."""
+    import paper_2405_12196_amd as Y
+    (p,) = W.u1_d18()
+    ref = oracle.tensordot_dense(p.a, p.b, p.axes_a, p.axes_b)
+    pl = Y.plan([(p.a, p.b, p.axes_a, p.axes_b)])
+    pl.set_variant(CHUNK_VARIANT)
+    A, B = G.upload(p.a), G.upload(p.b)
+    c, s = G.alloc_out(pl, 0)
+    ws = G.workspace(pl)
+    got = []
+    for _ in range(2):
+        nout = torch.full((2,), float("nan"), dtype=torch.float64, device=G.DEV)
+        pl.contract_norm([A], [B], [c], ws, nout)
+        torch.cuda.synchronize()
+        got.append(nout.cpu().numpy())
+    check_f64(s, c.cpu().numpy()[:s.numel], ref)
+    rf, rm = oracle.norms(ref)
+    assert abs(got[0][0] - rf) <= 1e-13 * rf and abs(got[0][1] - rm) <= 1e-13 * rm
+    assert np.array_equal(got[0], got[1])
+
+
+def test_u1_uneven_k_chunked_shared_b():
+    """The K-chunked shared-B kernel (variant 24) on the 64 uneven problems:
+    K up to 404 (13 chunks of 32, the last one partial), N up to 404 (seven
+    column ranges of a sector), every problem against the oracle."""
+    import paper_2405_12196_amd as Y
+    probs = [(p.a, p.b, p.axes_a, p.axes_b) for p in W.u1_uneven()]
+    pl = Y.plan(probs)
+    pl.set_variant(CHUNK_VARIANT)
+    assert max(pl.stats(i)["max_k"] for i in range(len(probs))) > 32 * 12
+    A = [G.upload(a) for a, _, _, _ in probs]
+    B = [G.upload(b) for _, b, _, _ in probs]
+    outs = [G.alloc_out(pl, i) for i in range(len(probs))]
+    pl.contract(A, B, [c for c, _ in outs], G.workspace(pl))
+    torch.cuda.synchronize()
+    for (a, b, xa, xb), (c, s) in zip(probs, outs):
+        check_f64(s, c.cpu().numpy()[:s.numel], oracle.tensordot_blockpair(a, b, xa, xb))
+
+
 # ------------------------------------------------------- reduced precision
 @pytest.mark.parametrize("prec", ["f32", "bf16x3", "bf16x6"])
 @pytest.mark.parametrize("in_f32", [True, False])
