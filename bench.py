@@ -70,7 +70,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ctm_corner_chi128_D8_f64_hbm_traf
 # the sources that define the contraction kernels, their instances, tables
 # and launches (the counters in profiles/ are valid while these are unchanged)
 CONTRACTION_SOURCES = ("device.hip", "dispatch.hpp", "host.cpp", "index.hpp", "inst_f64.hip", "inst_lds.hip",
-                       "inst_lds_norm.hip", "kernels.hpp", "lds_select.hpp", "plan.hpp", "planner.hpp")
+                       "inst_lds_norm.hip", "inst_ldsk.hip", "kernels.hpp", "lds_select.hpp", "plan.hpp",
+                       "planner.hpp")
 
 
 def kernel_source_hash():

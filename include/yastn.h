@@ -254,7 +254,9 @@ yastn_status yastn_contract_timed(yastn_plan_t plan, const void *const *a, const
  * most 32 rows).
  * yastn_plan_autotune runs every variant that fits the plan `reps` times on
  * the caller's buffers (same arguments as yastn_contract; C is overwritten),
- * times them with HIP events, keeps the fastest in the plan and returns its
+ * times them with HIP events (the variants within 15 % of the fastest a
+ * second time, in reverse order, keeping each one's better time), keeps the
+ * fastest in the plan and returns its
  * id in *chosen (may be NULL).  times_ms [host], if not NULL, receives
  * YASTN_NUM_VARIANTS floats: [0] = best time per contraction, [v] = time of
  * variant v or -1 if it does not fit.  Synchronises hip_stream.  Results of

@@ -1433,32 +1433,44 @@ yastn_status yastn_plan_autotune(yastn_plan_t plan, const void *const *a, const 
   YASTN_HIP(hipEventCreate(&e1));
   Fit fit;
   fit_add(fit, plan->p);
-  int best = 1;
-  float best_ms = 1e30f;
   float tms[kVariants];
   for (int v = 0; v < kVariants; ++v) tms[v] = -1.f;
-  for (int v = 1; v < kVariants; ++v) {
-    float ms = -1.f;
+  // one variant: a warm-up launch, then reps launches between two events
+  auto time_variant = [&](int v, float &ms) {
+    for (JobRef &j : jobs) j.variant = v;
+    s = launch(jobs, st);
+    if (!s) s = (hipEventRecord(e0, st) == hipSuccess) ? YASTN_OK : YASTN_ERR_HIP;
+    for (int r = 0; r < reps && !s; ++r) s = launch(jobs, st);
+    ms = -1.f;
+    if (!s && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+        hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+      ms /= reps;
+  };
+  // every variant that fits, then (in reverse order, so a drift of the
+  // clock or the caches does not favour one end) again those within 15 % of
+  // the fastest; each keeps its better time
+  float first_best = 1e30f;
+  for (int v = 1; v < kVariants && !s; ++v)
     if (variant_fits(fit, plan->p.opts, v)) {
-      for (JobRef &j : jobs) j.variant = v;
-      s = launch(jobs, st);  // warm-up
-      if (!s) s = (hipEventRecord(e0, st) == hipSuccess) ? YASTN_OK : YASTN_ERR_HIP;
-      for (int r = 0; r < reps && !s; ++r) s = launch(jobs, st);
-      if (!s && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
-          hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
-        ms /= reps;
-        if (ms < best_ms) {
-          best_ms = ms;
-          best = v;
-        }
-      }
-      if (s) break;
+      time_variant(v, tms[v]);
+      if (tms[v] >= 0.f) first_best = std::min(first_best, tms[v]);
     }
-    tms[v] = ms;
-  }
+  for (int v = kVariants - 1; v >= 1 && !s; --v)
+    if (tms[v] >= 0.f && tms[v] <= 1.15f * first_best) {
+      float ms;
+      time_variant(v, ms);
+      if (ms >= 0.f) tms[v] = std::min(tms[v], ms);
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (s) return s;
+  int best = 1;
+  float best_ms = 1e30f;
+  for (int v = 1; v < kVariants; ++v)
+    if (tms[v] >= 0.f && tms[v] < best_ms) {
+      best_ms = tms[v];
+      best = v;
+    }
   tms[0] = best_ms;
   for (int v = 0; v < kVariants; ++v) plan->p.tuned_ms[v] = tms[v];
   plan->p.variant = best;
