@@ -589,11 +589,32 @@ def svd_section(torch, Y, last, last_struct, sp, chi=128, reps=5):
         nb += nb & 1
         per_round = (nb // 2) * 2.0 * 16 * 16 * (2 * r + c)
         flop += per_round * (nb - 1) * sweeps
+    # the same with the kept right vectors recovered after the sweeps (the
+    # mode the CTM move uses): the sweeps rotate W only
+    sv.set_flags(Y.SVD_RECOVER_V)
+    rtimes = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rkept, rsweeps = sv.run(last, svals, ws, chi, stream=sp)
+        sv.factors(u, vt, ws, stream=sp)
+        torch.cuda.synchronize()
+        rtimes.append((time.perf_counter() - t0) * 1e3)
+    rms = float(np.median(rtimes))
+    rflop = 0.0
+    for X, m, n, s0 in sv.sectors:
+        r, c = max(m, n), min(m, n)
+        nb = max(2, -(-c // 8))
+        nb += nb & 1
+        rflop += (nb // 2) * 2.0 * 16 * 16 * (2 * r) * (nb - 1) * rsweeps
     dims = sorted(((max(m, n), min(m, n)) for _, m, n, _ in sv.sectors), reverse=True)
     res = {"ms": round(ms, 3), "sweeps": sweeps, "sectors": sv.nsectors, "singular_values": sv.nsv,
            "largest_sectors": dims[:4], "chi": chi, "kept": int(sum(kept)),
            "jacobi_mfma_GFLOP": round(flop / 1e9, 2), "jacobi_mfma_TFs": round(flop / (ms * 1e-3) / 1e12, 3),
            "frac_of_fp64_mfma_peak": round(flop / (ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFS, 4),
+           "recover_v": {"ms": round(rms, 3), "sweeps": rsweeps, "kept": int(sum(rkept)),
+                         "jacobi_mfma_GFLOP": round(rflop / 1e9, 2),
+                         "jacobi_mfma_TFs": round(rflop / (rms * 1e-3) / 1e12, 3)},
            "timing": f"median of {reps} synchronised runs (fuse, sweeps, sort, truncation, factors)"}
     del sv, ws, svals, u, vt
     torch.cuda.empty_cache()

@@ -29,6 +29,7 @@ F64, F32, BF16X3, BF16X6 = 0, 1, 2, 3
 FLAG_MFMA, FLAG_ROWS, FLAG_NOCACHE = 1, 2, 4
 DTYPE_F64, DTYPE_F32, DTYPE_C128 = 0, 1, 2
 CONJ_A, CONJ_B = 1, 2
+SVD_RECOVER_V = 1
 PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3, "bf16x6": BF16X6}
 STATUS = ["OK", "ERR_ARG", "ERR_SYM", "ERR_CHARGE", "ERR_SIGNATURE", "ERR_SHAPE",
           "ERR_DUPLICATE", "ERR_NOMEM", "ERR_HIP", "ERR_STATE"]
@@ -43,8 +44,8 @@ EXPORTS = ["yastn_plan", "yastn_plan_profile", "yastn_plan_cache_clear", "yastn_
            "yastn_server_forget", "yastn_server_drain", "yastn_server_get_stats", "yastn_server_destroy",
            "yastn_perm_plan", "yastn_perm_output", "yastn_permute", "yastn_perm_free",
            "yastn_grad_plan", "yastn_grad_output", "yastn_grad_workspace", "yastn_grad", "yastn_grad_free",
-           "yastn_svd_plan", "yastn_svd_info", "yastn_svd_sector", "yastn_svd", "yastn_svd_output",
-           "yastn_svd_factors", "yastn_svd_factors_scaled", "yastn_svd_free",
+           "yastn_svd_plan", "yastn_svd_info", "yastn_svd_set_flags", "yastn_svd_sector", "yastn_svd",
+           "yastn_svd_output", "yastn_svd_factors", "yastn_svd_factors_scaled", "yastn_svd_free",
            "yastn_ctm_plan", "yastn_ctm_move", "yastn_ctm_tensor", "yastn_ctm_copy", "yastn_ctm_info",
            "yastn_ctm_free", "yastn_zplan", "yastn_zplan_output", "yastn_zplan_workspace", "yastn_zplan_real",
            "yastn_zcontract", "yastn_zplan_autotune", "yastn_zplan_free", "yastn_swap_plan", "yastn_swap_info",
@@ -184,6 +185,7 @@ def lib():
         L.yastn_svd_plan.argtypes = [C.POINTER(TensorDesc), C.c_int32, C.POINTER(C.c_int32), C.c_void_p,
                                      C.POINTER(C.c_void_p)]
         L.yastn_svd_info.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]
+        L.yastn_svd_set_flags.argtypes = [C.c_void_p, C.c_int32]
         L.yastn_svd_sector.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                        C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.yastn_svd.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_void_p,
@@ -223,7 +225,8 @@ def lib():
         L.yastn_swap_free.argtypes = [C.c_void_p]
         L.yastn_swap_free.restype = None
         for f in ("yastn_perm_plan", "yastn_perm_output", "yastn_permute", "yastn_grad_plan", "yastn_grad_output",
-                  "yastn_grad_workspace", "yastn_grad", "yastn_svd_plan", "yastn_svd_info", "yastn_svd_sector",
+                  "yastn_grad_workspace", "yastn_grad", "yastn_svd_plan", "yastn_svd_info", "yastn_svd_set_flags",
+                  "yastn_svd_sector",
                   "yastn_svd", "yastn_svd_output", "yastn_svd_factors", "yastn_svd_factors_scaled",
                   "yastn_ctm_plan", "yastn_ctm_move", "yastn_ctm_tensor", "yastn_ctm_copy", "yastn_ctm_info",
                   "yastn_zplan", "yastn_zplan_output", "yastn_zplan_workspace", "yastn_zplan_real", "yastn_zcontract",
@@ -573,6 +576,10 @@ class Svd:
             m, n, s0 = C.c_int64(), C.c_int64(), C.c_int64()
             _check(lib().yastn_svd_sector(h, k, q, C.byref(m), C.byref(n), C.byref(s0)))
             self.sectors.append((tuple(int(v) for v in q), int(m.value), int(n.value), int(s0.value)))
+
+    def set_flags(self, flags: int):
+        """SVD_RECOVER_V: kept right vectors formed after the sweeps (0: accumulated)."""
+        _check(lib().yastn_svd_set_flags(self._h, int(flags)))
 
     def run(self, t, sv, workspace, chi, tol=0.0, deg_tol=1e-10, stream=None):
         """Singular values into ``sv`` (device, nsv FP64), each sector's

@@ -325,7 +325,12 @@ yastn_status yastn_ctm_plan(const yastn_tensor_desc *env, void *hip_stream, yast
   if (s != YASTN_OK) return fail(s);
   int32_t nsec = 0;
   size_t svd_ws = 0;
-  s = yastn_svd_info(h->svd, &nsec, &h->nsv, &svd_ws);
+  // the move keeps chi values of the four-corner product, far above eps
+  // times its largest: the kept right vectors are recovered after the sweeps
+  // (yastn_svd falls back to accumulated rotations when they would not be
+  // accurate)
+  if (s == YASTN_OK) s = yastn_svd_set_flags(h->svd, YASTN_SVD_RECOVER_V);
+  s = s == YASTN_OK ? yastn_svd_info(h->svd, &nsec, &h->nsv, &svd_ws) : s;
   if (s != YASTN_OK) return fail(s);
   h->kept.assign(size_t(std::max(0, nsec)), 0);
   const size_t extra = al256(size_t(std::max<int64_t>(1, h->nsv)) * 8) + 256 + al256(yastn_norm_workspace());

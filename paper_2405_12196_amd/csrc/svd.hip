@@ -72,6 +72,7 @@ constexpr int kSvdWaves = 8;       // waves of a round's workgroup (one workgrou
 struct DevSvdSector {
   int64_t w_off;   // W: rows x ld in 8-column panels, elements from the workspace base
   int64_t v_off;   // V: ld x ld in 8-column panels
+  int64_t m_off;   // a copy of the sector matrix (W's layout), for right vectors recovered at the end
   int32_t rows;    // W's rows (>= cols)
   int32_t cols;    // W's columns
   int32_t ld;      // kSvdW * nb
@@ -158,6 +159,7 @@ struct SvdRoundArgs {
   const int32_t *done;       // per sector: converged, skip
   int32_t nsec, round;
   double rot_tol;            // rotate a pair only above this scaled off-diagonal entry
+  int32_t with_v;            // 0: V is not accumulated (right vectors recovered after the sweeps)
 };
 
 // The round-robin pairing of nb blocks (nb even): round rr in [0, nb - 1),
@@ -316,7 +318,7 @@ __global__ void __launch_bounds__(64 * kSvdWaves) k_svd_round(SvdRoundArgs a) {
   // W's rows, then V's rows (the same row stride), in 16-row chunks: four
   // chunks of a wave in flight at once (clamped loads; stores past the last
   // row skipped), so V's loads overlap W's
-  const int nw = S.rows, nt = S.rows + S.cols;
+  const int nw = S.rows, nt = S.rows + (a.with_v ? S.cols : 0);
   const int cout = colof(c16);
   int cin[4];
 #pragma unroll
@@ -347,6 +349,54 @@ __global__ void __launch_bounds__(64 * kSvdWaves) k_svd_round(SvdRoundArgs a) {
         const int r = rb + kChunk * u + kq + 4 * v;
         if (r < nt) *at(r, cout) = acc[u][v];
       }
+  }
+}
+
+// M0 = W for every sector (the fused matrix, kept for the recovery of the
+// right vectors)
+__global__ void __launch_bounds__(256) k_svd_copy_m(const DevSvdSector *sec, int nsec, double *ws) {
+  for (int k = blockIdx.y; k < nsec; k += gridDim.y) {
+    const DevSvdSector s = sec[k];
+    const int64_t nw = (int64_t)s.rows * s.ld;
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < nw; i += (int64_t)gridDim.x * 256)
+      ws[s.m_off + i] = ws[s.w_off + i];
+  }
+}
+
+// The right vector of kept pair t of a sector without accumulated rotations:
+// with W = M0 V converged and u_j = w_j / s_j (column j = perm[t] of the
+// normalised W), M0^T u_j = s_j v_j, so v_j = M0^T u_j / s_j, written into
+// column j of V.  Its error is about (rows)^1/2 eps s_max / s_j relative, so
+// the mode suits truncations that keep the large values only.  One
+// workgroup per kept pair: u_j staged in LDS in chunks, one thread per
+// entry of v_j, a fixed summation order.
+constexpr int kSvdRecChunk = 2048;
+__global__ void __launch_bounds__(256) k_svd_recover(const DevSvdSector *sec, int nsec, double *ws,
+                                                     const int32_t *perm, const double *sv, const int32_t *kept) {
+  __shared__ double u[kSvdRecChunk];
+  for (int k = blockIdx.y; k < nsec; k += gridDim.y) {
+    const DevSvdSector S = sec[k];
+    const double *W = ws + S.w_off;
+    const double *M0 = ws + S.m_off;
+    double *V = ws + S.v_off;
+    const int nk = kept[k];
+    for (int t = blockIdx.x; t < nk; t += gridDim.x) {
+      const int j = perm[S.sv0 + t];
+      const double inv = 1.0 / sv[S.sv0 + t];
+      for (int c0 = 0; c0 < S.cols; c0 += 256) {
+        const int c = c0 + (int)threadIdx.x;
+        double acc = 0.0;
+        for (int r0 = 0; r0 < S.rows; r0 += kSvdRecChunk) {
+          const int nr = min(kSvdRecChunk, S.rows - r0);
+          __syncthreads();
+          for (int r = (int)threadIdx.x; r < nr; r += 256) u[r] = W[pix(r0 + r, j, S.rows)];
+          __syncthreads();
+          if (c < S.cols)
+            for (int r = 0; r < nr; ++r) acc = fma(M0[pix(r0 + r, c, S.rows)], u[r], acc);
+        }
+        if (c < S.cols) V[pix(c, j, S.ld)] = acc * inv;
+      }
+    }
   }
 }
 
@@ -580,6 +630,7 @@ struct SvdPlanImpl {
   std::vector<DevSvdSector> dsec;
   int64_t nsv = 0;
   int max_rounds = 1, total_pairs = 0;
+  int32_t flags = 0;  // YASTN_SVD_RECOVER_V
   size_t ws_bytes = 0;
   size_t off_sv_raw = 0, off_perm = 0, off_conv = 0, off_done = 0, off_stat = 0, off_flag = 0, off_sign = 0;
   void *dev_mem = nullptr;  // sectors, gather blocks and tiles
@@ -716,6 +767,8 @@ yastn_status yastn_svd_plan(const yastn_tensor_desc *t, int32_t nrow, const int3
       welems += int64_t(d.rows) * d.ld;
       d.v_off = welems;
       welems += int64_t(d.ld) * d.ld;
+      d.m_off = welems;
+      welems += int64_t(d.rows) * d.ld;
       d.wg0 = wg;
       wg += nb / 2;
       d.sv0 = (int32_t)P.nsv;
@@ -818,6 +871,13 @@ yastn_status yastn_svd_plan(const yastn_tensor_desc *t, int32_t nrow, const int3
   return YASTN_OK;
 }
 
+yastn_status yastn_svd_set_flags(yastn_svd_t h, int32_t flags) {
+  if (!h) return set_error(YASTN_ERR_ARG, "null plan");
+  if (flags & ~YASTN_SVD_RECOVER_V) return set_error(YASTN_ERR_ARG, "unknown SVD flag");
+  h->p.flags = flags;
+  return YASTN_OK;
+}
+
 yastn_status yastn_svd_info(yastn_svd_t h, int32_t *nsectors, int64_t *nsv, size_t *workspace_bytes) {
   if (!h) return set_error(YASTN_ERR_ARG, "null plan");
   if (nsectors) *nsectors = (int32_t)h->p.sectors.size();
@@ -858,51 +918,94 @@ yastn_status yastn_svd(yastn_svd_t h, const void *t, int32_t chi, double tol, do
   int32_t *done = reinterpret_cast<int32_t *>(ws + P.off_done);
   double *stat = reinterpret_cast<double *>(ws + P.off_stat);
   int32_t *flag = reinterpret_cast<int32_t *>(ws + P.off_flag);
-  // ---- W = fused sector matrices, V = I, no sector done
-  hipLaunchKernelGGL(k_svd_init, dim3(64, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, W);
-  hipLaunchKernelGGL(k_svd_sweep_begin, dim3(grid1(nsec, 256)), dim3(256), 0, st, conv, done, nsec);
-  if (P.ntiles > 0)
-    hipLaunchKernelGGL(k_svd_gather, dim3(std::min(P.ntiles, 65535)), dim3(256), 0, st, P.d_gather, P.d_tiles,
-                       P.ntiles, reinterpret_cast<const double *>(t), W);
-  SVD_HIP(hipGetLastError());
-  // ---- sweeps of rounds until every sector is converged
-  SvdRoundArgs ra{};
-  ra.sec = P.d_sec;
-  ra.ws = W;
-  ra.conv = conv;
-  ra.done = done;
-  ra.nsec = nsec;
-  const double eps = 2.220446049250313e-16;
-  const double eps_scale = 64.0 * eps;  // convergence: off <= max(1e-14, 64 eps sqrt(rows))
-  ra.rot_tol = 4.0 * eps;
-  int32_t all = 0;
-  int sw = 0;
-  for (; sw < kSvdMaxSweeps && !all; ++sw) {
-    hipLaunchKernelGGL(k_svd_sweep_begin, dim3(grid1(nsec, 256)), dim3(256), 0, st, conv, (int32_t *)nullptr, nsec);
-    for (int rr = 0; rr < P.max_rounds; ++rr) {
-      ra.round = rr;
-      hipLaunchKernelGGL(k_svd_round, dim3(P.total_pairs), dim3(64 * kSvdWaves), 0, st, ra);
-    }
-    hipLaunchKernelGGL(k_svd_sweep_end, dim3(1), dim3(256), 0, st, conv, done, nsec, P.d_sec, eps_scale, flag);
+  // one pass: fuse, sweeps, values, truncation, factors; with recover set, the
+  // right vectors are formed at the end if that is accurate enough
+  auto attempt = [&](bool recover, bool &accurate) -> yastn_status {
+    accurate = true;
+    // ---- W = fused sector matrices, V = I, no sector done
+    hipLaunchKernelGGL(k_svd_init, dim3(64, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, W);
+    hipLaunchKernelGGL(k_svd_sweep_begin, dim3(grid1(nsec, 256)), dim3(256), 0, st, conv, done, nsec);
+    if (P.ntiles > 0)
+      hipLaunchKernelGGL(k_svd_gather, dim3(std::min(P.ntiles, 65535)), dim3(256), 0, st, P.d_gather, P.d_tiles,
+                         P.ntiles, reinterpret_cast<const double *>(t), W);
+    if (recover)
+      hipLaunchKernelGGL(k_svd_copy_m, dim3(64, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, W);
     SVD_HIP(hipGetLastError());
-    SVD_HIP(hipMemcpyAsync(&all, flag, 4, hipMemcpyDeviceToHost, st));
+    // ---- sweeps of rounds until every sector is converged
+    SvdRoundArgs ra{};
+    ra.with_v = recover ? 0 : 1;
+    ra.sec = P.d_sec;
+    ra.ws = W;
+    ra.conv = conv;
+    ra.done = done;
+    ra.nsec = nsec;
+    const double eps = 2.220446049250313e-16;
+    const double eps_scale = 64.0 * eps;  // convergence: off <= max(1e-14, 64 eps sqrt(rows))
+    ra.rot_tol = 4.0 * eps;
+    int32_t all = 0;
+    int sw = 0;
+    for (; sw < kSvdMaxSweeps && !all; ++sw) {
+      hipLaunchKernelGGL(k_svd_sweep_begin, dim3(grid1(nsec, 256)), dim3(256), 0, st, conv, (int32_t *)nullptr, nsec);
+      for (int rr = 0; rr < P.max_rounds; ++rr) {
+        ra.round = rr;
+        hipLaunchKernelGGL(k_svd_round, dim3(P.total_pairs), dim3(64 * kSvdWaves), 0, st, ra);
+      }
+      hipLaunchKernelGGL(k_svd_sweep_end, dim3(1), dim3(256), 0, st, conv, done, nsec, P.d_sec, eps_scale, flag);
+      SVD_HIP(hipGetLastError());
+      SVD_HIP(hipMemcpyAsync(&all, flag, 4, hipMemcpyDeviceToHost, st));
+      SVD_HIP(hipStreamSynchronize(st));
+    }
+    P.sweeps += sw;
+    if (!all) return set_error(YASTN_ERR_STATE, "Jacobi sweeps did not converge");
+    // ---- singular values, sorted per sector; global truncation
+    hipLaunchKernelGGL(k_svd_norms, dim3(16, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, W, sv_raw);
+    hipLaunchKernelGGL(k_svd_sort, dim3(std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, sv_raw, sv, perm);
+    hipLaunchKernelGGL(k_svd_stats, dim3(1), dim3(1024), 0, st, sv, (int)P.nsv, tol, stat);
+    hipLaunchKernelGGL(k_svd_cut, dim3(grid1(P.nsv, 256)), dim3(256), 0, st, sv, (int)P.nsv, chi, deg_tol, stat);
+    int32_t *dkept = reinterpret_cast<int32_t *>(ws + P.off_done);  // done[] is free again
+    hipLaunchKernelGGL(k_svd_kept, dim3(grid1(nsec, 256)), dim3(256), 0, st, P.d_sec, nsec, sv, stat, dkept);
+    if (recover) {
+      // the recovered right vectors carry about sqrt(rows) eps s_max / s_t of
+      // relative error: only when the smallest kept value keeps that below
+      // 1e-11 is the mode used; else the caller runs the SVD again with the
+      // rotations accumulated
+      std::vector<double> hsv(size_t(P.nsv));
+      SVD_HIP(hipMemcpyAsync(P.kept.data(), dkept, size_t(nsec) * 4, hipMemcpyDeviceToHost, st));
+      SVD_HIP(hipMemcpyAsync(hsv.data(), sv, size_t(P.nsv) * 8, hipMemcpyDeviceToHost, st));
+      SVD_HIP(hipStreamSynchronize(st));
+      double smax = 0.0, smin = 0.0;
+      int rows_max = 1;
+      bool any = false;
+      for (int k = 0; k < nsec; ++k) {
+        const DevSvdSector &d = P.dsec[size_t(k)];
+        if (d.cols > 0) smax = std::max(smax, hsv[size_t(d.sv0)]);
+        if (P.kept[size_t(k)] > 0) {
+          const double v = hsv[size_t(d.sv0 + P.kept[size_t(k)] - 1)];
+          smin = any ? std::min(smin, v) : v;
+          any = true;
+          rows_max = std::max(rows_max, (int)d.rows);
+        }
+      }
+      if (any && !(smin > 0.0 && 4.0 * std::sqrt((double)rows_max) * eps * smax <= 1e-11 * smin)) {
+        accurate = false;
+        return YASTN_OK;
+      }
+      hipLaunchKernelGGL(k_svd_recover, dim3(std::max(1, std::min(chi, 1024)), std::min(nsec, 65535)), dim3(256), 0, st,
+                         P.d_sec, nsec, W, perm, sv, dkept);
+    }
+    hipLaunchKernelGGL(k_svd_gauge, dim3(8, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, W, perm, dkept,
+                       reinterpret_cast<double *>(ws + P.off_sign));
+    SVD_HIP(hipGetLastError());
+    SVD_HIP(hipMemcpyAsync(P.kept.data(), dkept, size_t(nsec) * 4, hipMemcpyDeviceToHost, st));
     SVD_HIP(hipStreamSynchronize(st));
-  }
-  P.sweeps = sw;
-  if (sweeps) *sweeps = sw;
-  if (!all) return set_error(YASTN_ERR_STATE, "Jacobi sweeps did not converge");
-  // ---- singular values, sorted per sector; global truncation
-  hipLaunchKernelGGL(k_svd_norms, dim3(16, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, W, sv_raw);
-  hipLaunchKernelGGL(k_svd_sort, dim3(std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, sv_raw, sv, perm);
-  hipLaunchKernelGGL(k_svd_stats, dim3(1), dim3(1024), 0, st, sv, (int)P.nsv, tol, stat);
-  hipLaunchKernelGGL(k_svd_cut, dim3(grid1(P.nsv, 256)), dim3(256), 0, st, sv, (int)P.nsv, chi, deg_tol, stat);
-  int32_t *dkept = reinterpret_cast<int32_t *>(ws + P.off_done);  // done[] is free again
-  hipLaunchKernelGGL(k_svd_kept, dim3(grid1(nsec, 256)), dim3(256), 0, st, P.d_sec, nsec, sv, stat, dkept);
-  hipLaunchKernelGGL(k_svd_gauge, dim3(8, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, W, perm, dkept,
-                     reinterpret_cast<double *>(ws + P.off_sign));
-  SVD_HIP(hipGetLastError());
-  SVD_HIP(hipMemcpyAsync(P.kept.data(), dkept, size_t(nsec) * 4, hipMemcpyDeviceToHost, st));
-  SVD_HIP(hipStreamSynchronize(st));
+    return YASTN_OK;
+  };
+  P.sweeps = 0;
+  bool accurate = true;
+  yastn_status ss = attempt((P.flags & YASTN_SVD_RECOVER_V) != 0, accurate);
+  if (ss == YASTN_OK && !accurate) ss = attempt(false, accurate);
+  if (sweeps) *sweeps = P.sweeps;
+  if (ss != YASTN_OK) return ss;
   std::memcpy(kept, P.kept.data(), size_t(nsec) * 4);
   P.have_kept = true;
   // ---- output structures for these kept counts

@@ -25,8 +25,10 @@ import paper_2405_12196_amd as Y  # noqa: E402
 from tests import gpu_util as G  # noqa: E402
 
 
-def gpu_svd(t, rows, chi, tol=0.0, deg_tol=1e-10, pu=0.0, pv=0.0):
+def gpu_svd(t, rows, chi, tol=0.0, deg_tol=1e-10, pu=0.0, pv=0.0, flags=0):
     sv = Y.Svd(t, rows)
+    if flags:
+        sv.set_flags(flags)
     tdev = G.upload(t)
     ws = torch.empty(max(256, sv.workspace_bytes), dtype=torch.uint8, device=G.DEV)
     svals = torch.full((max(1, sv.nsv),), float("nan"), dtype=torch.float64, device=G.DEV)
@@ -49,8 +51,8 @@ def _blocks(s, vals):
     return out
 
 
-def check_svd(t, rows, chi, tol=0.0, deg_tol=1e-10, tol_sv=1e-12, tol_rec=1e-11):
-    sv, svals, kept, sweeps, (us, u), (vs, vt) = gpu_svd(t, rows, chi, tol, deg_tol)
+def check_svd(t, rows, chi, tol=0.0, deg_tol=1e-10, tol_sv=1e-12, tol_rec=1e-11, flags=0):
+    sv, svals, kept, sweeps, (us, u), (vs, vt) = gpu_svd(t, rows, chi, tol, deg_tol, flags=flags)
     mats = OS.sector_matrices(t, rows)
     dec = OS.svd_sectors(t, rows)
     assert [X for X, *_ in sv.sectors] == list(mats), "sector order differs from the oracle"
@@ -140,15 +142,21 @@ def test_svd_wide_and_tall_sectors_and_tol():
         check_svd(t, rows, chi=1000, tol=1e-2)
 
 
-def test_svd_ctm_corner_chi128():
-    """The chi = 128, D = 8 enlarged corner (the oracle's chain output) split
-    as rows (r1, A_r, A*_r) x columns (bot4, A_b, A*_b): 51 sectors up to
-    924 x 924, truncated to chi = 128."""
+def _corner():
+    """The chi = 128, D = 8 enlarged corner (the oracle's chain output)."""
     from bench import STEPS
     t = W.ctm()
     cur = None
     for (an, bn), (ax, bx) in zip(STEPS, t["axes"]):
         cur = oracle.tensordot_blockpair(t[an] if an else cur, t[bn], ax, bx)
+    return cur
+
+
+def test_svd_ctm_corner_chi128():
+    """The chi = 128, D = 8 enlarged corner split as rows (r1, A_r, A*_r) x
+    columns (bot4, A_b, A*_b): 51 sectors up to 924 x 924, truncated to
+    chi = 128."""
+    cur = _corner()
     dec = OS.svd_sectors(cur, (0, 3, 5))
     allv = np.sort(np.concatenate([d[1] for d in dec.values()]))[::-1]
     assert (allv[127] - allv[128]) / allv[127] > 1e-6  # a clean cut: the kept set is unique
@@ -180,3 +188,55 @@ def test_svd_repeat_bitwise():
     b = gpu_svd(t, (4, 0), 10)
     assert np.array_equal(a[1], b[1]) and a[2] == b[2]
     assert np.array_equal(a[4][1], b[4][1]) and np.array_equal(a[5][1], b[5][1])
+
+
+def test_svd_recover_v_corner_chi128():
+    """Right vectors recovered after the sweeps on the chi = 128 corner: the
+    kept values lie far above eps s_max, so the mode is used (no second
+    pass: as many sweeps as the default), the values and U are bitwise those
+    of the default mode, and the factors pass the oracle checks."""
+    cur = _corner()
+    base = gpu_svd(cur, (0, 3, 5), 128)
+    sv, kept, sweeps = check_svd(cur, (0, 3, 5), chi=128, flags=Y.SVD_RECOVER_V)
+    rec = gpu_svd(cur, (0, 3, 5), 128, flags=Y.SVD_RECOVER_V)
+    assert sweeps == base[3] == rec[3], "the recover mode fell back to accumulated rotations"
+    assert np.array_equal(rec[1], base[1]) and rec[2] == base[2]
+    assert np.array_equal(rec[4][1], base[4][1]), "U differs from the default mode"
+    # V^T within the recovery's error of the accumulated one
+    err = float(np.max(np.abs(rec[5][1] - base[5][1])))
+    assert err <= 1e-10, f"recovered V^T off by {err:.3e}"
+
+
+def test_svd_recover_v_falls_back_on_small_kept_values():
+    """One sector scaled by 1e-10 and every value kept: recovered right
+    vectors there would carry ~1e-5 relative error, so the call runs again
+    with accumulated rotations (more sweeps in total) and returns bitwise the
+    default mode's result."""
+    from oracle.blocksparse import normalize
+    t = _random_tensor(4, "U1xU1", 4, None)
+    rows = (0, 3)
+    tn = normalize(t)
+    sec = [OS._sector_of(tn, b, rows) for b in range(t.nblocks)]
+    small = sorted(set(sec))[len(set(sec)) // 2]
+    for b in range(t.nblocks):
+        if sec[b] == small:
+            o = int(t.offsets[b])
+            t.data[o:o + int(np.prod(t.shapes[b]))] *= 1e-10
+    dec = OS.svd_sectors(t, rows)
+    allv = np.concatenate([d[1] for d in dec.values()])
+    assert allv.min() < 1e-9 * allv.max()
+    chi = int(allv.size)  # keep every value
+    base = gpu_svd(t, rows, chi, deg_tol=0.0)
+    assert sum(base[2]) == chi
+    rec = gpu_svd(t, rows, chi, deg_tol=0.0, flags=Y.SVD_RECOVER_V)
+    assert rec[3] > base[3], "no second pass"
+    assert np.array_equal(rec[1], base[1]) and rec[2] == base[2]
+    assert np.array_equal(rec[4][1], base[4][1]) and np.array_equal(rec[5][1], base[5][1])
+
+
+def test_svd_set_flags_rejects_unknown():
+    t = _random_tensor(2, "U1", 3, None)
+    sv = Y.Svd(t, (0,))
+    with pytest.raises(RuntimeError):
+        sv.set_flags(2)
+    sv.set_flags(0)
