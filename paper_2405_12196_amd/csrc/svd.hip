@@ -77,7 +77,7 @@ struct DevSvdSector {
   int32_t cols;    // W's columns
   int32_t ld;      // kSvdW * nb
   int32_t nb;      // column blocks, even, >= 2
-  int32_t wg0;     // first workgroup of this sector in a round
+  int32_t npairs;  // nb / 2: the sector's workgroups in a round
   int32_t sv0;     // first of the sector's cols singular values (global index)
   int32_t trans;   // 1: W = M^T
   int32_t pad;
@@ -111,6 +111,23 @@ struct DevSvdOut {     // one output block: U (kind 0) or V^T (kind 1)
 // element (r, c) of a matrix of R rows in 8-column panels
 __device__ __forceinline__ int64_t pix(int64_t r, int c, int64_t R) {
   return (int64_t)(c >> 3) * (R << 3) + (r << 3) + (c & 7);
+}
+
+// 1 / y and 1 / sqrt(x) from the hardware estimates refined by two Newton
+// steps each (the error of the estimate squared per step): the rotation
+// parameters need no correct rounding, only c^2 (1 + t^2) = 1 to working
+// precision, which the refined 1 / sqrt gives for any t
+__device__ __forceinline__ double rcp_nr(double y) {
+  double r = __builtin_amdgcn_rcp(y);
+  r = fma(r, fma(-y, r, 1.0), r);
+  r = fma(r, fma(-y, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = fma(0.5 * r, fma(-x * r, r, 1.0), r);
+  r = fma(0.5 * r, fma(-x * r, r, 1.0), r);
+  return r;
 }
 
 // ------------------------------------------------------------------ kernels
@@ -152,8 +169,15 @@ __global__ void __launch_bounds__(256) k_svd_gather(const DevSvdGather *__restri
   }
 }
 
+// workgroup -> (sector, block pair) of a round; the largest sectors' pairs
+// first, so the longest workgroups start first
+struct DevSvdWg {
+  int32_t sec, p;
+};
+
 struct SvdRoundArgs {
   const DevSvdSector *sec;
+  const DevSvdWg *wg;
   double *ws;
   unsigned long long *conv;  // per sector: largest scaled off-diagonal Gram entry this sweep (bits of a double >= 0)
   const int32_t *done;       // per sector: converged, skip
@@ -180,17 +204,10 @@ __global__ void __launch_bounds__(64 * kSvdWaves) k_svd_round(SvdRoundArgs a) {
   __shared__ double g[16][17];
   __shared__ double q[16][17];
   __shared__ int rotated;
-  const int bid = blockIdx.x;
-  int lo = 0, hi = a.nsec - 1;
-  while (lo < hi) {  // last sector whose first workgroup is <= bid
-    const int mid = (lo + hi + 1) >> 1;
-    if (a.sec[mid].wg0 <= bid) lo = mid;
-    else hi = mid - 1;
-  }
+  const DevSvdWg wgi = a.wg[blockIdx.x];
+  const int lo = wgi.sec, p = wgi.p;
   if (a.done[lo]) return;
   const DevSvdSector S = a.sec[lo];
-  const int p = bid - S.wg0;
-  if (p >= S.nb / 2) return;
   int P, Q;
   rr_pair(S.nb, a.round % (S.nb - 1), p, P, Q);
   double *W = a.ws + S.w_off;
@@ -220,6 +237,29 @@ __global__ void __launch_bounds__(64 * kSvdWaves) k_svd_round(SvdRoundArgs a) {
     for (int v = 0; v < 4; ++v) gpart[wid][kq + 4 * v][c16] = acc[v];
   }
   __syncthreads();
+  // W's rows, then V's rows (the same row stride), are rotated in 16-row
+  // chunks, four chunks of a wave in flight at once (clamped loads; stores
+  // past the last row skipped), so V's loads overlap W's.  The loads do not
+  // depend on the rotation: each wave issues its first four chunks now, and
+  // they arrive while wave 0 runs the Jacobi.
+  const int nw = S.rows, nt = S.rows + (a.with_v ? S.cols : 0);
+  const int cout = colof(c16);
+  int cin[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) cin[kk] = colof(4 * kk + kq);
+  auto at = [&](int r, int c) { return r < nw ? W + pix(r, c, nw) : V + pix(r - nw, c, S.ld); };
+  constexpr int kChunk = 16 * kSvdWaves;
+  const int rb0 = 16 * wid;
+  double x[4][4];
+  auto load_chunks = [&](int rb) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = min(rb + kChunk * u + c16, nt - 1);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) x[u][kk] = *at(r, cin[kk]);
+    }
+  };
+  if (rb0 < nt) load_chunks(rb0);
   if (wid == 0) {
     // sum the waves' parts in a fixed order, Q = I
     for (int e = lane; e < 256; e += 64) {
@@ -234,68 +274,91 @@ __global__ void __launch_bounds__(64 * kSvdWaves) k_svd_round(SvdRoundArgs a) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // convergence measure: largest |g_ij| / sqrt(g_ii g_jj) over i != j
-    double off = 0.0;
+    // (the largest square, one square root at the end)
+    double off2 = 0.0;
     for (int e = lane; e < 256; e += 64) {
       const int i = e >> 4, j = e & 15;
       const double d = g[i][i] * g[j][j];
-      if (i != j && d > 0.0) off = fmax(off, fabs(g[i][j]) / sqrt(d));
+      if (i != j && d > 0.0) off2 = fmax(off2, g[i][j] * g[i][j] * rcp_nr(d));
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o, 64));
+    for (int o = 32; o > 0; o >>= 1) off2 = fmax(off2, __shfl_xor(off2, o, 64));
+    const double off = off2 > 0.0 ? off2 * rsq_nr(off2) : 0.0;
     if (lane == 0) atomicMax(a.conv + lo, (unsigned long long)__double_as_longlong(off));
     int any = 0;
     if (off > a.rot_tol) {
-      // cyclic Jacobi on g (16 x 16): 15 rounds of 8 disjoint rotations; a
-      // rotation (i, j) uses lanes 8 rot .. 8 rot + 7, each lane two of the
-      // 16 rows (column phase) or columns (row phase)
-      const int rot = lane >> 3, e2 = 2 * (lane & 7);
+      // cyclic Jacobi on g (16 x 16): 15 rounds of 8 disjoint rotations.  Lane
+      // (rx, ry) owns the 2 x 2 block of g on the index pairs of rotations rx
+      // (rows) and ry (columns) and the same block of q: it reads the block
+      // and rotation ry's diagonal and off-diagonal entries together (one
+      // LDS round trip per round), forms rotation ry, takes rotation rx from
+      // lane rx, and writes g <- J^T g J and q <- q J on its block.  Lanes
+      // with the same ry compute the same (c, s).
+      const int rx = lane >> 3, ry = lane & 7;
+      const double tol2 = a.rot_tol * a.rot_tol;
+      // J = [[c, s], [-s, c]] on (i, j) zeroing g_ij of J^T g J: with
+      // a = g_jj - g_ii and b = 2 g_ij, t = tan = sign(a) b / (|a| + sqrt(a^2 + b^2))
+      // (the smaller root; |t| <= 1), c = 1 / sqrt(1 + t^2), s = t c; no rotation when
+      // g_ij is below rot_tol sqrt(g_ii g_jj) (compared squared)
+      auto rot_of = [&](double gii, double gjj, double gij, double &c, double &sn) {
+        const double d = gii * gjj;
+        const bool go = gij != 0.0 && d > 0.0 && gij * gij > tol2 * d;
+        // formed without a branch; a lane without rotation takes c = 1,
+        // s = 0 (what it formed, possibly not finite, is discarded by the
+        // select).  t needs no full precision (one Newton step on each
+        // estimate), c does (two).
+        const double aa = gjj - gii, bb = 2.0 * gij;
+        const double h = fma(aa, aa, bb * bb);
+        double r = __builtin_amdgcn_rsq(h);
+        r = fma(0.5 * r, fma(-h * r, r, 1.0), r);
+        const double den = fma(h, r, fabs(aa));
+        double rd = __builtin_amdgcn_rcp(den);
+        rd = fma(rd, fma(-den, rd, 1.0), rd);
+        const double t = (aa < 0.0 ? -bb : bb) * rd;
+        const double cc = rsq_nr(fma(t, t, 1.0));
+        c = go ? cc : 1.0;
+        sn = go ? t * cc : 0.0;
+        return go;
+      };
       for (int sw = 0; sw < kSvdInnerSweeps; ++sw) {
         int applied = 0;
         for (int rr = 0; rr < 15; ++rr) {
           // round-robin pair of 16 indices without a division
-          int i = 15, j = rr;
-          if (rot != 0) {
-            i = rr + rot;
-            i -= i >= 15 ? 15 : 0;
-            j = rr - rot;
-            j += j < 0 ? 15 : 0;
-          }
-          const double gii = g[i][i], gjj = g[j][j], gij = g[i][j];
-          double c = 1.0, s = 0.0;
-          const double d = gii * gjj;
-          const bool go = gij != 0.0 && d > 0.0 && fabs(gij) > a.rot_tol * sqrt(d);
-          if (go) {
-            // zero g_ij of J^T g J, J = [[c, s], [-s, c]] on (i, j)
-            const double zeta = (gjj - gii) / (2.0 * gij);
-            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-          }
-          applied |= go;
+          auto pair_of = [&](int r, int &i, int &j) {
+            i = 15;
+            j = rr;
+            if (r != 0) {
+              i = rr + r;
+              i -= i >= 15 ? 15 : 0;
+              j = rr - r;
+              j += j < 0 ? 15 : 0;
+            }
+          };
+          int ix, jx, iy, jy;
+          pair_of(rx, ix, jx);
+          pair_of(ry, iy, jy);
+          const double yii = g[iy][iy], yjj = g[jy][jy], yij = g[iy][jy];
+          const double b00 = g[ix][iy], b01 = g[ix][jy], b10 = g[jx][iy], b11 = g[jx][jy];
+          const double q00 = q[ix][iy], q01 = q[ix][jy], q10 = q[jx][iy], q11 = q[jx][jy];
+          double cy, sy;
+          applied |= rot_of(yii, yjj, yij, cy, sy);
+          // rotation rx as formed by lane rx (whose column rotation it is)
+          const double cx = __shfl(cy, rx, 64), sx = __shfl(sy, rx, 64);
+          // C = B J_y (columns), then J_x^T C (rows)
+          const double c00 = cy * b00 - sy * b01, c01 = sy * b00 + cy * b01;
+          const double c10 = cy * b10 - sy * b11, c11 = sy * b10 + cy * b11;
+          // every lane has read this round's entries before any lane writes
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-          // columns i, j of g and q: g <- g J, q <- q J
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            const int x = e2 + u;
-            const double gi = g[x][i], gj = g[x][j], qi = q[x][i], qj = q[x][j];
-            g[x][i] = c * gi - s * gj;
-            g[x][j] = s * gi + c * gj;
-            q[x][i] = c * qi - s * qj;
-            q[x][j] = s * qi + c * qj;
-          }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-          // rows i, j of g: g <- J^T g
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            const int x = e2 + u;
-            const double gi = g[i][x], gj = g[j][x];
-            g[i][x] = c * gi - s * gj;
-            g[j][x] = s * gi + c * gj;
-          }
+          g[ix][iy] = cx * c00 - sx * c10;
+          g[jx][iy] = sx * c00 + cx * c10;
+          g[ix][jy] = cx * c01 - sx * c11;
+          g[jx][jy] = sx * c01 + cx * c11;
+          q[ix][iy] = cy * q00 - sy * q01;
+          q[ix][jy] = sy * q00 + cy * q01;
+          q[jx][iy] = cy * q10 - sy * q11;
+          q[jx][jy] = sy * q10 + cy * q11;
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -315,24 +378,8 @@ __global__ void __launch_bounds__(64 * kSvdWaves) k_svd_round(SvdRoundArgs a) {
   double qb[4];
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) qb[kk] = q[4 * kk + kq][c16];
-  // W's rows, then V's rows (the same row stride), in 16-row chunks: four
-  // chunks of a wave in flight at once (clamped loads; stores past the last
-  // row skipped), so V's loads overlap W's
-  const int nw = S.rows, nt = S.rows + (a.with_v ? S.cols : 0);
-  const int cout = colof(c16);
-  int cin[4];
-#pragma unroll
-  for (int kk = 0; kk < 4; ++kk) cin[kk] = colof(4 * kk + kq);
-  auto at = [&](int r, int c) { return r < nw ? W + pix(r, c, nw) : V + pix(r - nw, c, S.ld); };
-  constexpr int kChunk = 16 * kSvdWaves;
-  for (int rb = 16 * wid; rb < nt; rb += kChunk * 4) {
-    double x[4][4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int r = min(rb + kChunk * u + c16, nt - 1);
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) x[u][kk] = *at(r, cin[kk]);
-    }
+  for (int rb = rb0; rb < nt; rb += kChunk * 4) {
+    if (rb != rb0) load_chunks(rb);
     d4v acc[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -637,6 +684,7 @@ struct SvdPlanImpl {
   DevSvdSector *d_sec = nullptr;
   DevSvdGather *d_gather = nullptr;
   DevSvdTile *d_tiles = nullptr;
+  DevSvdWg *d_wg = nullptr;
   int ngather = 0, ntiles = 0;
   int device = 0;
   // after yastn_svd: kept counts and the output structures
@@ -769,7 +817,7 @@ yastn_status yastn_svd_plan(const yastn_tensor_desc *t, int32_t nrow, const int3
       welems += int64_t(d.ld) * d.ld;
       d.m_off = welems;
       welems += int64_t(d.rows) * d.ld;
-      d.wg0 = wg;
+      d.npairs = nb / 2;
       wg += nb / 2;
       d.sv0 = (int32_t)P.nsv;
       P.nsv += d.cols;
@@ -778,6 +826,15 @@ yastn_status yastn_svd_plan(const yastn_tensor_desc *t, int32_t nrow, const int3
     }
     P.total_pairs = wg;
     const int nsec = (int)P.sectors.size();
+    // the round's workgroups: sectors by descending rows (then index), pairs in order
+    std::vector<DevSvdWg> wgs;
+    {
+      std::vector<int> ord(static_cast<size_t>(nsec), 0);
+      std::iota(ord.begin(), ord.end(), 0);
+      std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return P.dsec[size_t(x)].rows > P.dsec[size_t(y)].rows; });
+      for (int k : ord)
+        for (int q = 0; q < P.dsec[size_t(k)].npairs; ++q) wgs.push_back(DevSvdWg{k, q});
+    }
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     size_t off = al(size_t(welems) * 8);
     P.off_sv_raw = off;
@@ -842,11 +899,13 @@ yastn_status yastn_svd_plan(const yastn_tensor_desc *t, int32_t nrow, const int3
     P.ngather = (int)gat.size();
     P.ntiles = (int)tiles.size();
     const size_t o_sec = 0, o_gat = al(P.dsec.size() * sizeof(DevSvdSector)),
-                 o_til = o_gat + al(gat.size() * sizeof(DevSvdGather)), tot = o_til + al(tiles.size() * sizeof(DevSvdTile));
+                 o_til = o_gat + al(gat.size() * sizeof(DevSvdGather)), o_wg = o_til + al(tiles.size() * sizeof(DevSvdTile)),
+                 tot = o_wg + al(wgs.size() * sizeof(DevSvdWg));
     std::vector<char> host(std::max<size_t>(tot, 256), 0);
     if (!P.dsec.empty()) std::memcpy(host.data() + o_sec, P.dsec.data(), P.dsec.size() * sizeof(DevSvdSector));
     if (!gat.empty()) std::memcpy(host.data() + o_gat, gat.data(), gat.size() * sizeof(DevSvdGather));
     if (!tiles.empty()) std::memcpy(host.data() + o_til, tiles.data(), tiles.size() * sizeof(DevSvdTile));
+    if (!wgs.empty()) std::memcpy(host.data() + o_wg, wgs.data(), wgs.size() * sizeof(DevSvdWg));
     if (hipGetDevice(&P.device) != hipSuccess || hipMalloc(&P.dev_mem, host.size()) != hipSuccess) {
       (void)hipGetLastError();
       delete h;
@@ -856,6 +915,7 @@ yastn_status yastn_svd_plan(const yastn_tensor_desc *t, int32_t nrow, const int3
     P.d_sec = reinterpret_cast<DevSvdSector *>(base + o_sec);
     P.d_gather = reinterpret_cast<DevSvdGather *>(base + o_gat);
     P.d_tiles = reinterpret_cast<DevSvdTile *>(base + o_til);
+    P.d_wg = reinterpret_cast<DevSvdWg *>(base + o_wg);
     hipStream_t stm = reinterpret_cast<hipStream_t>(hip_stream);
     if (hipMemcpyAsync(P.dev_mem, host.data(), host.size(), hipMemcpyHostToDevice, stm) != hipSuccess ||
         hipStreamSynchronize(stm) != hipSuccess) {
@@ -935,6 +995,7 @@ yastn_status yastn_svd(yastn_svd_t h, const void *t, int32_t chi, double tol, do
     SvdRoundArgs ra{};
     ra.with_v = recover ? 0 : 1;
     ra.sec = P.d_sec;
+    ra.wg = P.d_wg;
     ra.ws = W;
     ra.conv = conv;
     ra.done = done;
