@@ -64,6 +64,9 @@ constexpr int kSvdW = 8;           // columns per block (a block pair is 16 colu
 constexpr int kSvdMaxSweeps = 40;  // outer sweeps before giving up
 constexpr int kSvdInnerSweeps = 1; // cyclic Jacobi sweeps on a pair's 16 x 16 Gram matrix per round
 constexpr int kSvdWaves = 8;       // waves of a round's workgroup (one workgroup per block pair)
+constexpr int kSvdGramGroups = 16; // 4-row groups of a wave's Gram loads in flight
+constexpr int kSvdRotChunks = 4;   // 16-row chunks of a wave's rotation loads in flight
+                                   // (8 needs 156 VGPRs: one workgroup per CU, slower)
 
 // W (rows x ld) and V (ld x ld) are stored in panels of 8 columns: panel p
 // holds columns 8p .. 8p + 7 of every row, row after row, so a column block
@@ -206,8 +209,8 @@ __global__ void __launch_bounds__(64 * kSvdWaves) k_svd_round(SvdRoundArgs a) {
   __shared__ int rotated;
   const DevSvdWg wgi = a.wg[blockIdx.x];
   const int lo = wgi.sec, p = wgi.p;
+  const DevSvdSector S = a.sec[lo];  // loaded together with the flag
   if (a.done[lo]) return;
-  const DevSvdSector S = a.sec[lo];
   int P, Q;
   rr_pair(S.nb, a.round % (S.nb - 1), p, P, Q);
   double *W = a.ws + S.w_off;
@@ -216,19 +219,19 @@ __global__ void __launch_bounds__(64 * kSvdWaves) k_svd_round(SvdRoundArgs a) {
   const int c16 = lane & 15, kq = lane >> 4;
   auto colof = [&](int c) { return c < kSvdW ? kSvdW * P + c : kSvdW * Q + c - kSvdW; };
   // ---- Gram matrix of the 16 columns: wave w takes the 4-row groups w,
-  // w + kSvdWaves, ...; eight groups' loads are issued before their MFMAs
-  // (row indices clamped, values past the last row zeroed after the load, so
-  // no load sits under a branch)
+  // w + kSvdWaves, ...; kSvdGramGroups groups' loads are issued before their
+  // MFMAs (row indices clamped, values past the last row zeroed after the
+  // load, so no load sits under a branch)
   {
     const int col = colof(c16);
     constexpr int kStride = 4 * kSvdWaves;
     d4v acc = {0, 0, 0, 0};
-    for (int r0 = 4 * wid; r0 < S.rows; r0 += kStride * 8) {
-      double x[8];
+    for (int r0 = 4 * wid; r0 < S.rows; r0 += kStride * kSvdGramGroups) {
+      double x[kSvdGramGroups];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) x[u] = W[pix(min(r0 + kStride * u + kq, S.rows - 1), col, S.rows)];
+      for (int u = 0; u < kSvdGramGroups; ++u) x[u] = W[pix(min(r0 + kStride * u + kq, S.rows - 1), col, S.rows)];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < kSvdGramGroups; ++u) {
         const double xv = r0 + kStride * u + kq < S.rows ? x[u] : 0.0;
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, xv, acc, 0, 0, 0);
       }
@@ -238,10 +241,10 @@ __global__ void __launch_bounds__(64 * kSvdWaves) k_svd_round(SvdRoundArgs a) {
   }
   __syncthreads();
   // W's rows, then V's rows (the same row stride), are rotated in 16-row
-  // chunks, four chunks of a wave in flight at once (clamped loads; stores
-  // past the last row skipped), so V's loads overlap W's.  The loads do not
-  // depend on the rotation: each wave issues its first four chunks now, and
-  // they arrive while wave 0 runs the Jacobi.
+  // chunks, kSvdRotChunks chunks of a wave in flight at once (clamped loads;
+  // stores past the last row skipped), so V's loads overlap W's.  The loads
+  // do not depend on the rotation: each wave issues its first chunks now,
+  // and they arrive while wave 0 runs the Jacobi.
   const int nw = S.rows, nt = S.rows + (a.with_v ? S.cols : 0);
   const int cout = colof(c16);
   int cin[4];
@@ -250,10 +253,10 @@ __global__ void __launch_bounds__(64 * kSvdWaves) k_svd_round(SvdRoundArgs a) {
   auto at = [&](int r, int c) { return r < nw ? W + pix(r, c, nw) : V + pix(r - nw, c, S.ld); };
   constexpr int kChunk = 16 * kSvdWaves;
   const int rb0 = 16 * wid;
-  double x[4][4];
+  double x[kSvdRotChunks][4];
   auto load_chunks = [&](int rb) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kSvdRotChunks; ++u) {
       const int r = min(rb + kChunk * u + c16, nt - 1);
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) x[u][kk] = *at(r, cin[kk]);
@@ -279,7 +282,8 @@ __global__ void __launch_bounds__(64 * kSvdWaves) k_svd_round(SvdRoundArgs a) {
     for (int e = lane; e < 256; e += 64) {
       const int i = e >> 4, j = e & 15;
       const double d = g[i][i] * g[j][j];
-      if (i != j && d > 0.0) off2 = fmax(off2, g[i][j] * g[i][j] * rcp_nr(d));
+      // (the estimate of 1 / d: the measure only decides convergence)
+      if (i != j && d > 0.0) off2 = fmax(off2, g[i][j] * g[i][j] * __builtin_amdgcn_rcp(d));
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) off2 = fmax(off2, __shfl_xor(off2, o, 64));
@@ -378,11 +382,11 @@ __global__ void __launch_bounds__(64 * kSvdWaves) k_svd_round(SvdRoundArgs a) {
   double qb[4];
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) qb[kk] = q[4 * kk + kq][c16];
-  for (int rb = rb0; rb < nt; rb += kChunk * 4) {
+  for (int rb = rb0; rb < nt; rb += kChunk * kSvdRotChunks) {
     if (rb != rb0) load_chunks(rb);
-    d4v acc[4];
+    d4v acc[kSvdRotChunks];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kSvdRotChunks; ++u) {
       acc[u] = d4v{0, 0, 0, 0};
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u][kk], qb[kk], acc[u], 0, 0, 0);
@@ -390,7 +394,7 @@ __global__ void __launch_bounds__(64 * kSvdWaves) k_svd_round(SvdRoundArgs a) {
     // every lane has read its rows before any lane of the wave writes them
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < kSvdRotChunks; ++u)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = rb + kChunk * u + kq + 4 * v;
