@@ -1598,9 +1598,18 @@ __global__ void __launch_bounds__(256) k_split_reduce(RedArgs args) {
       const DevColMap cm = it.cmap[c];
       const int64_t base = it.cgrid[cm.j];
       if (base < 0) continue;
+      // sixteen slots' loads in flight at a time, summed in slot order
       Acc sum = 0;
       const char *slot = args.ws + it.off0;
-      for (int s = 0; s < it.nslots; ++s, slot += it.slot_bytes) sum += reinterpret_cast<const Acc *>(slot)[e];
+      int s = 0;
+      for (; s + 16 <= it.nslots; s += 16, slot += 16 * (int64_t)it.slot_bytes) {
+        Acc v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = reinterpret_cast<const Acc *>(slot + (int64_t)u * it.slot_bytes)[e];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) sum += v[u];
+      }
+      for (; s < it.nslots; ++s, slot += it.slot_bytes) sum += reinterpret_cast<const Acc *>(slot)[e];
       C[base + (int64_t)(it.m0 + r) * cm.nj + cm.cl] = Out(sum);
     }
   }

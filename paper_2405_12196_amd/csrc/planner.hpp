@@ -139,7 +139,7 @@ void contracted_keys(const HostTensor &t, const int *axes, int nc, std::vector<i
 // computed in k ranges (split-K); the caller passes ksplit only when the
 // pipelined kernel (the one that writes partial slots) can run the plan.
 // gather: pack B through the offset table where it fits (else sub-block items)
-constexpr int64_t kSplitMinK = 4096, kSplitChunk = 2048, kSplitMaxSlots = 128, kSplitMaxMN = 64 * 64 * 16;
+constexpr int64_t kSplitMinK = 4096, kSplitChunk = 1024, kSplitMaxSlots = 256, kSplitMaxMN = 64 * 64 * 16;
 // Tables of one problem (structure, sectors, tuples, offsets, pack items);
 // no tiles yet.
 yastn_status build_structure(HostProblem &hp, int prob, const std::vector<std::pair<int32_t, int32_t>> &pairs,
