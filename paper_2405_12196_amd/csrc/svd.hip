@@ -76,6 +76,7 @@ struct DevSvdSector {
   int64_t w_off;   // W: rows x ld in 8-column panels, elements from the workspace base
   int64_t v_off;   // V: ld x ld in 8-column panels
   int64_t m_off;   // a copy of the sector matrix (W's layout), for right vectors recovered at the end
+  int64_t s_off;   // scratch for the column reordering: W's layout, then V's
   int32_t rows;    // W's rows (>= cols)
   int32_t cols;    // W's columns
   int32_t ld;      // kSvdW * nb
@@ -187,6 +188,7 @@ struct SvdRoundArgs {
   int32_t nsec, round;
   double rot_tol;            // rotate a pair only above this scaled off-diagonal entry
   int32_t with_v;            // 0: V is not accumulated (right vectors recovered after the sweeps)
+  double *nrm2;              // per column: its squared norm after the round that last rotated it
 };
 
 // The round-robin pairing of nb blocks (nb even): round rr in [0, nb - 1),
@@ -373,6 +375,12 @@ __global__ void __launch_bounds__(64 * kSvdWaves) k_svd_round(SvdRoundArgs a) {
       }
     }
     if (lane == 0) rotated = any;
+    // the squared column norms after this round (the diagonal of the rotated
+    // Gram matrix): the next sweep orders the columns by them
+    if (lane < 16) {
+      const int col = colof(lane);
+      if (col < S.cols) a.nrm2[S.sv0 + col] = g[lane][lane];
+    }
   }
   __syncthreads();
   if (!rotated) return;
@@ -446,6 +454,95 @@ __global__ void __launch_bounds__(256) k_svd_recover(const DevSvdSector *sec, in
             for (int r = 0; r < nr; ++r) acc = fma(M0[pix(r0 + r, c, S.rows)], u[r], acc);
         }
         if (c < S.cols) V[pix(c, j, S.ld)] = acc * inv;
+      }
+    }
+  }
+}
+
+// Squared column norms of W before the first sweep (one wave per 8-column
+// panel, lanes over 8 rows x 8 columns, fixed summation order); later sweeps
+// take them from the rounds.
+__global__ void __launch_bounds__(256) k_svd_colnorm2(const DevSvdSector *sec, int nsec, const double *ws,
+                                                      double *nrm2) {
+  const int lane = threadIdx.x & 63;
+  for (int k = blockIdx.y; k < nsec; k += gridDim.y) {
+    const DevSvdSector S = sec[k];
+    const int npan = S.ld >> 3;
+    for (int p = blockIdx.x * 4 + (threadIdx.x >> 6); p < npan; p += gridDim.x * 4) {
+      const double *pan = ws + S.w_off + (int64_t)p * S.rows * 8;
+      double ss = 0.0;
+      for (int r = lane >> 3; r < S.rows; r += 8) {
+        const double x = pan[(int64_t)r * 8 + (lane & 7)];
+        ss = fma(x, x, ss);
+      }
+      ss += __shfl_xor(ss, 8, 64);
+      ss += __shfl_xor(ss, 16, 64);
+      ss += __shfl_xor(ss, 32, 64);
+      const int col = 8 * p + (lane & 7);
+      if (lane < 8 && col < S.cols) nrm2[S.sv0 + col] = ss;
+    }
+  }
+}
+
+// Column order of each sector at the start of a sweep: descending norm
+// (ties by index), the order that sorting the columns of a one-sided Jacobi
+// before each sweep (de Rijk) uses; it cuts the sweeps of graded matrices.
+// One workgroup per sector: the squared norms into LDS, the rank of each
+// column by counting, perm[sv0 + rank] = column; chg[k] = 1 when the order is
+// not the identity.  Converged sectors and sectors wider than kSvdSortMax
+// keep their order.
+constexpr int kSvdSortMax = 4096;
+__global__ void __launch_bounds__(1024) k_svd_colsort(const DevSvdSector *sec, int nsec, const double *nrm2,
+                                                      const int32_t *done, int32_t *perm, int32_t *chg) {
+  __shared__ double nrm[kSvdSortMax];
+  __shared__ int moved;
+  for (int k = blockIdx.x; k < nsec; k += gridDim.x) {
+    const DevSvdSector S = sec[k];
+    if (done[k] || S.cols > kSvdSortMax) {  // uniform across the workgroup
+      if (threadIdx.x == 0) chg[k] = 0;
+      continue;
+    }
+    for (int j = threadIdx.x; j < S.cols; j += 1024) nrm[j] = nrm2[S.sv0 + j];
+    if (threadIdx.x == 0) moved = 0;
+    __syncthreads();
+    for (int j = threadIdx.x; j < S.cols; j += 1024) {
+      const double v = nrm[j];
+      int rank = 0;
+      for (int i = 0; i < S.cols; ++i) {
+        const double u = nrm[i];
+        rank += (u > v) || (u == v && i < j);
+      }
+      perm[S.sv0 + rank] = j;
+      if (rank != j) moved = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) chg[k] = moved;
+    __syncthreads();  // nrm and moved are reused by the next sector
+  }
+}
+
+// Reordered columns, for the sectors whose order changed: back = 0 gathers
+// W[:, perm[t]] (and V[:, perm[t]] when with_v) into the sector's scratch,
+// back = 1 copies the scratch over W (and V).  Padding columns keep their
+// (zero) values.
+__global__ void __launch_bounds__(256) k_svd_colperm(const DevSvdSector *sec, int nsec, double *ws, const int32_t *perm,
+                                                     const int32_t *chg, int with_v, int back) {
+  for (int k = blockIdx.y; k < nsec; k += gridDim.y) {
+    if (!chg[k]) continue;
+    const DevSvdSector S = sec[k];
+    const int64_t nw = (int64_t)S.rows * S.ld, nv = with_v ? (int64_t)S.ld * S.ld : 0;
+    double *scr = ws + S.s_off;
+    for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < nw + nv; e += (int64_t)gridDim.x * 256) {
+      const bool inw = e < nw;
+      const int64_t i = inw ? e : e - nw;           // element in W's or V's panel layout
+      const int64_t R = inw ? S.rows : S.ld;        // rows of that matrix
+      double *M = ws + (inw ? S.w_off : S.v_off);
+      if (back) {
+        M[i] = scr[e];
+      } else {
+        const int t = (int)((i / (R * 8)) * 8 + (i & 7));  // column of element i
+        const int64_t r = (i % (R * 8)) >> 3;
+        scr[e] = t < S.cols ? M[pix(r, perm[S.sv0 + t], R)] : M[i];
       }
     }
   }
@@ -683,7 +780,8 @@ struct SvdPlanImpl {
   int max_rounds = 1, total_pairs = 0;
   int32_t flags = 0;  // YASTN_SVD_RECOVER_V
   size_t ws_bytes = 0;
-  size_t off_sv_raw = 0, off_perm = 0, off_conv = 0, off_done = 0, off_stat = 0, off_flag = 0, off_sign = 0;
+  size_t off_sv_raw = 0, off_perm = 0, off_conv = 0, off_done = 0, off_stat = 0, off_flag = 0, off_sign = 0,
+         off_chg = 0;
   void *dev_mem = nullptr;  // sectors, gather blocks and tiles
   DevSvdSector *d_sec = nullptr;
   DevSvdGather *d_gather = nullptr;
@@ -821,6 +919,8 @@ yastn_status yastn_svd_plan(const yastn_tensor_desc *t, int32_t nrow, const int3
       welems += int64_t(d.ld) * d.ld;
       d.m_off = welems;
       welems += int64_t(d.rows) * d.ld;
+      d.s_off = welems;
+      welems += int64_t(d.rows) * d.ld + int64_t(d.ld) * d.ld;
       d.npairs = nb / 2;
       wg += nb / 2;
       d.sv0 = (int32_t)P.nsv;
@@ -855,6 +955,8 @@ yastn_status yastn_svd_plan(const yastn_tensor_desc *t, int32_t nrow, const int3
     off += al(8);
     P.off_sign = off;
     off += al(size_t(std::max<int64_t>(1, P.nsv)) * 8);
+    P.off_chg = off;
+    off += al(size_t(std::max(1, nsec)) * 4);
     P.ws_bytes = off;
     // ---- gather items: one per block of T, W strides per leg
     std::vector<DevSvdGather> gat;
@@ -982,6 +1084,7 @@ yastn_status yastn_svd(yastn_svd_t h, const void *t, int32_t chi, double tol, do
   int32_t *done = reinterpret_cast<int32_t *>(ws + P.off_done);
   double *stat = reinterpret_cast<double *>(ws + P.off_stat);
   int32_t *flag = reinterpret_cast<int32_t *>(ws + P.off_flag);
+  int32_t *chg = reinterpret_cast<int32_t *>(ws + P.off_chg);
   // one pass: fuse, sweeps, values, truncation, factors; with recover set, the
   // right vectors are formed at the end if that is accurate enough
   auto attempt = [&](bool recover, bool &accurate) -> yastn_status {
@@ -998,6 +1101,9 @@ yastn_status yastn_svd(yastn_svd_t h, const void *t, int32_t chi, double tol, do
     // ---- sweeps of rounds until every sector is converged
     SvdRoundArgs ra{};
     ra.with_v = recover ? 0 : 1;
+    ra.nrm2 = sv_raw;  // free until the values are formed after the sweeps
+    hipLaunchKernelGGL(k_svd_colnorm2, dim3(64, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec,
+                       (const double *)W, sv_raw);
     ra.sec = P.d_sec;
     ra.wg = P.d_wg;
     ra.ws = W;
@@ -1011,6 +1117,12 @@ yastn_status yastn_svd(yastn_svd_t h, const void *t, int32_t chi, double tol, do
     int sw = 0;
     for (; sw < kSvdMaxSweeps && !all; ++sw) {
       hipLaunchKernelGGL(k_svd_sweep_begin, dim3(grid1(nsec, 256)), dim3(256), 0, st, conv, (int32_t *)nullptr, nsec);
+      // columns by descending norm (the order is recomputed every sweep)
+      hipLaunchKernelGGL(k_svd_colsort, dim3(std::min(nsec, 65535)), dim3(1024), 0, st, P.d_sec, nsec,
+                         (const double *)sv_raw, (const int32_t *)done, perm, chg);
+      for (int back = 0; back < 2; ++back)
+        hipLaunchKernelGGL(k_svd_colperm, dim3(256, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, W,
+                           (const int32_t *)perm, (const int32_t *)chg, ra.with_v, back);
       for (int rr = 0; rr < P.max_rounds; ++rr) {
         ra.round = rr;
         hipLaunchKernelGGL(k_svd_round, dim3(P.total_pairs), dim3(64 * kSvdWaves), 0, st, ra);
