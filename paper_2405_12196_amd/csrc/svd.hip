@@ -523,8 +523,8 @@ __global__ void __launch_bounds__(1024) k_svd_colsort(const DevSvdSector *sec, i
 
 // Reordered columns, for the sectors whose order changed: back = 0 gathers
 // W[:, perm[t]] (and V[:, perm[t]] when with_v) into the sector's scratch,
-// back = 1 copies the scratch over W (and V).  Padding columns keep their
-// (zero) values.
+// back = 1 copies the scratch over W (and V); only the columns that move
+// (perm[t] != t) are touched, and padding columns keep their (zero) values.
 __global__ void __launch_bounds__(256) k_svd_colperm(const DevSvdSector *sec, int nsec, double *ws, const int32_t *perm,
                                                      const int32_t *chg, int with_v, int back) {
   for (int k = blockIdx.y; k < nsec; k += gridDim.y) {
@@ -537,12 +537,15 @@ __global__ void __launch_bounds__(256) k_svd_colperm(const DevSvdSector *sec, in
       const int64_t i = inw ? e : e - nw;           // element in W's or V's panel layout
       const int64_t R = inw ? S.rows : S.ld;        // rows of that matrix
       double *M = ws + (inw ? S.w_off : S.v_off);
+      const int t = (int)((i / (R * 8)) * 8 + (i & 7));  // column of element i
+      if (t >= S.cols) continue;
+      const int src = perm[S.sv0 + t];
+      if (src == t) continue;
       if (back) {
         M[i] = scr[e];
       } else {
-        const int t = (int)((i / (R * 8)) * 8 + (i & 7));  // column of element i
         const int64_t r = (i % (R * 8)) >> 3;
-        scr[e] = t < S.cols ? M[pix(r, perm[S.sv0 + t], R)] : M[i];
+        scr[e] = M[pix(r, src, R)];
       }
     }
   }
