@@ -507,8 +507,17 @@ __global__ void __launch_bounds__(1024) k_svd_colsort(const DevSvdSector *sec, i
     __syncthreads();
     for (int j = threadIdx.x; j < S.cols; j += 1024) {
       const double v = nrm[j];
-      int rank = 0;
-      for (int i = 0; i < S.cols; ++i) {
+      int rank = 0, i = 0;
+      // sixteen LDS reads in flight per batch (one read per step waits on
+      // the LDS latency every time)
+      for (; i + 16 <= S.cols; i += 16) {
+        double u[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) u[q] = nrm[i + q];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) rank += (u[q] > v) || (u[q] == v && i + q < j);
+      }
+      for (; i < S.cols; ++i) {
         const double u = nrm[i];
         rank += (u > v) || (u == v && i < j);
       }
