@@ -487,25 +487,22 @@ __global__ void __launch_bounds__(256) k_svd_colnorm2(const DevSvdSector *sec, i
 // Column order of each sector at the start of a sweep: descending norm
 // (ties by index), the order that sorting the columns of a one-sided Jacobi
 // before each sweep (de Rijk) uses; it cuts the sweeps of graded matrices.
-// One workgroup per sector: the squared norms into LDS, the rank of each
-// column by counting, perm[sv0 + rank] = column; chg[k] = 1 when the order is
-// not the identity.  Converged sectors and sectors wider than kSvdSortMax
-// keep their order.
-constexpr int kSvdSortMax = 4096;
-__global__ void __launch_bounds__(1024) k_svd_colsort(const DevSvdSector *sec, int nsec, const double *nrm2,
-                                                      const int32_t *done, int32_t *perm, int32_t *chg) {
+// Workgroup (x, y) ranks columns 256 y .. 256 y + 255 of sector x by
+// counting over the sector's squared norms (staged in LDS): perm[sv0 + rank]
+// = column; chg[k] (zeroed at the sweep's start) is set when a column moves.
+// Converged sectors and sectors wider than kSvdSortMax keep their order.
+constexpr int kSvdSortMax = 4096, kSvdSortSlice = 256;
+__global__ void __launch_bounds__(256) k_svd_colsort(const DevSvdSector *sec, int nsec, const double *nrm2,
+                                                     const int32_t *done, int32_t *perm, int32_t *chg) {
   __shared__ double nrm[kSvdSortMax];
-  __shared__ int moved;
   for (int k = blockIdx.x; k < nsec; k += gridDim.x) {
     const DevSvdSector S = sec[k];
-    if (done[k] || S.cols > kSvdSortMax) {  // uniform across the workgroup
-      if (threadIdx.x == 0) chg[k] = 0;
-      continue;
-    }
-    for (int j = threadIdx.x; j < S.cols; j += 1024) nrm[j] = nrm2[S.sv0 + j];
-    if (threadIdx.x == 0) moved = 0;
+    const int j0 = (int)blockIdx.y * kSvdSortSlice;
+    if (done[k] || S.cols > kSvdSortMax || j0 >= S.cols) continue;  // uniform across the workgroup
+    for (int j = threadIdx.x; j < S.cols; j += 256) nrm[j] = nrm2[S.sv0 + j];
     __syncthreads();
-    for (int j = threadIdx.x; j < S.cols; j += 1024) {
+    const int j = j0 + (int)threadIdx.x;
+    if (j < S.cols) {
       const double v = nrm[j];
       int rank = 0, i = 0;
       // sixteen LDS reads in flight per batch (one read per step waits on
@@ -522,11 +519,9 @@ __global__ void __launch_bounds__(1024) k_svd_colsort(const DevSvdSector *sec, i
         rank += (u > v) || (u == v && i < j);
       }
       perm[S.sv0 + rank] = j;
-      if (rank != j) moved = 1;
+      if (rank != j) atomicOr(chg + k, 1);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) chg[k] = moved;
-    __syncthreads();  // nrm and moved are reused by the next sector
+    __syncthreads();  // nrm is reused by the next sector
   }
 }
 
@@ -560,11 +555,13 @@ __global__ void __launch_bounds__(256) k_svd_colperm(const DevSvdSector *sec, in
   }
 }
 
-// conv[k] = 0 (every sweep); done[k] = 0 too when done is given (first sweep)
-__global__ void k_svd_sweep_begin(unsigned long long *conv, int32_t *done, int nsec) {
+// conv[k] = 0 (every sweep); done[k] = 0 too when done is given (first
+// sweep), chg[k] = 0 when chg is given
+__global__ void k_svd_sweep_begin(unsigned long long *conv, int32_t *done, int nsec, int32_t *chg) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nsec; k += gridDim.x * blockDim.x) {
     conv[k] = 0ull;
     if (done) done[k] = 0;
+    if (chg) chg[k] = 0;
   }
 }
 
@@ -789,7 +786,7 @@ struct SvdPlanImpl {
   std::vector<Sector> sectors;
   std::vector<DevSvdSector> dsec;
   int64_t nsv = 0;
-  int max_rounds = 1, total_pairs = 0;
+  int max_rounds = 1, total_pairs = 0, max_cols = 1;
   int32_t flags = 0;  // YASTN_SVD_RECOVER_V
   size_t ws_bytes = 0;
   size_t off_sv_raw = 0, off_perm = 0, off_conv = 0, off_done = 0, off_stat = 0, off_flag = 0, off_sign = 0,
@@ -938,6 +935,7 @@ yastn_status yastn_svd_plan(const yastn_tensor_desc *t, int32_t nrow, const int3
       d.sv0 = (int32_t)P.nsv;
       P.nsv += d.cols;
       P.max_rounds = std::max(P.max_rounds, nb - 1);
+      P.max_cols = std::max(P.max_cols, (int)d.cols);
       P.dsec.push_back(d);
     }
     P.total_pairs = wg;
@@ -1103,7 +1101,8 @@ yastn_status yastn_svd(yastn_svd_t h, const void *t, int32_t chi, double tol, do
     accurate = true;
     // ---- W = fused sector matrices, V = I, no sector done
     hipLaunchKernelGGL(k_svd_init, dim3(64, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, W);
-    hipLaunchKernelGGL(k_svd_sweep_begin, dim3(grid1(nsec, 256)), dim3(256), 0, st, conv, done, nsec);
+    hipLaunchKernelGGL(k_svd_sweep_begin, dim3(grid1(nsec, 256)), dim3(256), 0, st, conv, done, nsec,
+                       (int32_t *)nullptr);
     if (P.ntiles > 0)
       hipLaunchKernelGGL(k_svd_gather, dim3(std::min(P.ntiles, 65535)), dim3(256), 0, st, P.d_gather, P.d_tiles,
                          P.ntiles, reinterpret_cast<const double *>(t), W);
@@ -1128,10 +1127,12 @@ yastn_status yastn_svd(yastn_svd_t h, const void *t, int32_t chi, double tol, do
     int32_t all = 0;
     int sw = 0;
     for (; sw < kSvdMaxSweeps && !all; ++sw) {
-      hipLaunchKernelGGL(k_svd_sweep_begin, dim3(grid1(nsec, 256)), dim3(256), 0, st, conv, (int32_t *)nullptr, nsec);
+      hipLaunchKernelGGL(k_svd_sweep_begin, dim3(grid1(nsec, 256)), dim3(256), 0, st, conv, (int32_t *)nullptr, nsec,
+                         chg);
       // columns by descending norm (the order is recomputed every sweep)
-      hipLaunchKernelGGL(k_svd_colsort, dim3(std::min(nsec, 65535)), dim3(1024), 0, st, P.d_sec, nsec,
-                         (const double *)sv_raw, (const int32_t *)done, perm, chg);
+      hipLaunchKernelGGL(k_svd_colsort,
+                         dim3(std::min(nsec, 65535), std::min(P.max_cols + kSvdSortSlice - 1, kSvdSortMax) / kSvdSortSlice),
+                         dim3(256), 0, st, P.d_sec, nsec, (const double *)sv_raw, (const int32_t *)done, perm, chg);
       for (int back = 0; back < 2; ++back)
         hipLaunchKernelGGL(k_svd_colperm, dim3(256, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, W,
                            (const int32_t *)perm, (const int32_t *)chg, ra.with_v, back);
