@@ -428,8 +428,9 @@ void yastn_grad_free(yastn_grad_t g);
  *
  * yastn_svd computes every M_X = U_X diag(S_X) V_X^T on the device (FP64
  * block one-sided Jacobi: the columns of the tall orientation of M_X are
- * rotated in blocks of 8 until every pair is orthogonal to working
- * precision) and applies one global truncation: values at or below
+ * put in order of descending norm before each sweep and rotated in blocks of
+ * 8 until every pair is orthogonal to working precision) and applies one
+ * global truncation: values at or below
  * tol * (largest value) are dropped; if more than chi remain and c is the
  * (chi+1)-th largest of them, a value is kept iff it exceeds c (1 + deg_tol),
  * so at most chi are kept and a multiplet within deg_tol of the first dropped
@@ -437,7 +438,10 @@ void yastn_grad_free(yastn_grad_t g);
  * sector's descending; kept [host] (nsectors) the kept count of each sector
  * (a prefix of its values); sweeps [host, may be NULL] the Jacobi sweeps run.
  * t [device]: T's buffer; workspace [device]: yastn_svd_info bytes, 256-byte
- * aligned, which also holds the factors until the next yastn_svd.  Runs on
+ * aligned (per sector the working matrix, V, a copy of the matrix and a
+ * scratch copy of both for the column reordering: about 3 m n + 2 n^2
+ * doubles for an m x n tall sector, plus per-value arrays), which also holds
+ * the factors until the next yastn_svd.  Runs on
  * hip_stream and synchronises it once per sweep (it returns when done);
  * YASTN_ERR_STATE if the sweeps do not converge.
  *
