@@ -422,39 +422,51 @@ __global__ void __launch_bounds__(256) k_svd_copy_m(const DevSvdSector *sec, int
   }
 }
 
-// The right vector of kept pair t of a sector without accumulated rotations:
-// with W = M0 V converged and u_j = w_j / s_j (column j = perm[t] of the
-// normalised W), M0^T u_j = s_j v_j, so v_j = M0^T u_j / s_j, written into
-// column j of V.  Its error is about (rows)^1/2 eps s_max / s_j relative, so
-// the mode suits truncations that keep the large values only.  One
-// workgroup per kept pair: u_j staged in LDS in chunks, one thread per
-// entry of v_j, a fixed summation order.
-constexpr int kSvdRecChunk = 2048;
+// The right vectors of the kept pairs of a sector without accumulated
+// rotations: with W = M0 V converged and u_j = w_j / s_j (column j = perm[t]
+// of the normalised W), M0^T u_j = s_j v_j, so v_j = M0^T u_j / s_j, written
+// into column j of V.  Its error is about (rows)^1/2 eps s_max / s_j
+// relative, so the mode suits truncations that keep the large values only.
+// A workgroup takes kSvdRecT kept pairs and 256 columns: the pairs' u in
+// LDS in chunks of kSvdRecChunk rows, one thread per column, M0 read once
+// per kSvdRecT pairs, each sum in ascending row order.
+constexpr int kSvdRecChunk = 256, kSvdRecT = 8;
 __global__ void __launch_bounds__(256) k_svd_recover(const DevSvdSector *sec, int nsec, double *ws,
                                                      const int32_t *perm, const double *sv, const int32_t *kept) {
-  __shared__ double u[kSvdRecChunk];
+  __shared__ double u[kSvdRecT][kSvdRecChunk];
   for (int k = blockIdx.y; k < nsec; k += gridDim.y) {
     const DevSvdSector S = sec[k];
     const double *W = ws + S.w_off;
     const double *M0 = ws + S.m_off;
     double *V = ws + S.v_off;
     const int nk = kept[k];
-    for (int t = blockIdx.x; t < nk; t += gridDim.x) {
-      const int j = perm[S.sv0 + t];
-      const double inv = 1.0 / sv[S.sv0 + t];
-      for (int c0 = 0; c0 < S.cols; c0 += 256) {
-        const int c = c0 + (int)threadIdx.x;
-        double acc = 0.0;
-        for (int r0 = 0; r0 < S.rows; r0 += kSvdRecChunk) {
-          const int nr = min(kSvdRecChunk, S.rows - r0);
-          __syncthreads();
-          for (int r = (int)threadIdx.x; r < nr; r += 256) u[r] = W[pix(r0 + r, j, S.rows)];
-          __syncthreads();
-          if (c < S.cols)
-            for (int r = 0; r < nr; ++r) acc = fma(M0[pix(r0 + r, c, S.rows)], u[r], acc);
-        }
-        if (c < S.cols) V[pix(c, j, S.ld)] = acc * inv;
+    const int ntc = (nk + kSvdRecT - 1) / kSvdRecT, ncc = (S.cols + 255) / 256;
+    for (int item = blockIdx.x; item < ntc * ncc; item += gridDim.x) {
+      const int t0 = (item / ncc) * kSvdRecT, c = (item % ncc) * 256 + (int)threadIdx.x;
+      int jt[kSvdRecT];
+#pragma unroll
+      for (int q = 0; q < kSvdRecT; ++q) jt[q] = t0 + q < nk ? perm[S.sv0 + t0 + q] : -1;
+      double acc[kSvdRecT];
+#pragma unroll
+      for (int q = 0; q < kSvdRecT; ++q) acc[q] = 0.0;
+      for (int r0 = 0; r0 < S.rows; r0 += kSvdRecChunk) {
+        const int nr = min(kSvdRecChunk, S.rows - r0);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kSvdRecT; ++q)
+          if ((int)threadIdx.x < nr) u[q][threadIdx.x] = jt[q] >= 0 ? W[pix(r0 + (int)threadIdx.x, jt[q], S.rows)] : 0.0;
+        __syncthreads();
+        if (c < S.cols)
+          for (int r = 0; r < nr; ++r) {
+            const double m = M0[pix(r0 + r, c, S.rows)];
+#pragma unroll
+            for (int q = 0; q < kSvdRecT; ++q) acc[q] = fma(m, u[q][r], acc[q]);
+          }
       }
+      if (c < S.cols)
+#pragma unroll
+        for (int q = 0; q < kSvdRecT; ++q)
+          if (jt[q] >= 0) V[pix(c, jt[q], S.ld)] = acc[q] * (1.0 / sv[S.sv0 + t0 + q]);
     }
   }
 }
@@ -488,40 +500,46 @@ __global__ void __launch_bounds__(256) k_svd_colnorm2(const DevSvdSector *sec, i
 // (ties by index), the order that sorting the columns of a one-sided Jacobi
 // before each sweep (de Rijk) uses; it cuts the sweeps of graded matrices.
 // Workgroup (x, y) ranks columns 256 y .. 256 y + 255 of sector x by
-// counting over the sector's squared norms (staged in LDS): perm[sv0 + rank]
-// = column; chg[k] (zeroed at the sweep's start) is set when a column moves.
+// counting over the sector's squared norms, staged in LDS as FP32 (the order
+// is a heuristic: FP32 keys compare at the full VALU rate, and ties still
+// go by index, so the ranks are a permutation): perm[sv0 + rank] = column;
+// chg[k] (zeroed at the sweep's start) is set when a column moves.
 // Converged sectors and sectors wider than kSvdSortMax keep their order.
 constexpr int kSvdSortMax = 4096, kSvdSortSlice = 256;
 __global__ void __launch_bounds__(256) k_svd_colsort(const DevSvdSector *sec, int nsec, const double *nrm2,
                                                      const int32_t *done, int32_t *perm, int32_t *chg) {
-  __shared__ double nrm[kSvdSortMax];
+  __shared__ float nrm[kSvdSortMax];
   for (int k = blockIdx.x; k < nsec; k += gridDim.x) {
     const DevSvdSector S = sec[k];
     const int j0 = (int)blockIdx.y * kSvdSortSlice;
     if (done[k] || S.cols > kSvdSortMax || j0 >= S.cols) continue;  // uniform across the workgroup
-    for (int j = threadIdx.x; j < S.cols; j += 256) nrm[j] = nrm2[S.sv0 + j];
+    for (int j = threadIdx.x; j < S.cols; j += 256) nrm[j] = (float)nrm2[S.sv0 + j];
     __syncthreads();
     const int j = j0 + (int)threadIdx.x;
+    int moved = 0;
     if (j < S.cols) {
-      const double v = nrm[j];
+      const float v = nrm[j];
       int rank = 0, i = 0;
       // sixteen LDS reads in flight per batch (one read per step waits on
-      // the LDS latency every time)
+      // the LDS latency every time); bitwise, not short-circuit, logic, so
+      // the compares stay branch-free
       for (; i + 16 <= S.cols; i += 16) {
-        double u[16];
+        float u[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) u[q] = nrm[i + q];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) rank += (u[q] > v) || (u[q] == v && i + q < j);
+        for (int q = 0; q < 16; ++q) rank += (int)(u[q] > v) | ((int)(u[q] == v) & (int)(i + q < j));
       }
       for (; i < S.cols; ++i) {
-        const double u = nrm[i];
-        rank += (u > v) || (u == v && i < j);
+        const float u = nrm[i];
+        rank += (int)(u > v) | ((int)(u == v) & (int)(i < j));
       }
       perm[S.sv0 + rank] = j;
-      if (rank != j) atomicOr(chg + k, 1);
+      moved = rank != j;
     }
-    __syncthreads();  // nrm is reused by the next sector
+    // one atomic per workgroup (the barrier also keeps nrm until every
+    // thread has ranked: the next sector reuses it)
+    if (__syncthreads_or(moved) && threadIdx.x == 0) atomicOr(chg + k, 1);
   }
 }
 
@@ -583,42 +601,67 @@ __global__ void __launch_bounds__(256) k_svd_sweep_end(const unsigned long long 
 }
 
 // singular value j of a sector = norm of W's column j; the column scaled to
-// unit norm.  One wave per column, lanes stride the rows (fixed order).
+// unit norm.  One wave per 8-column panel: lanes over 8 rows x 8 columns
+// (64-byte row segments), a fixed summation order.
 __global__ void __launch_bounds__(256) k_svd_norms(const DevSvdSector *sec, int nsec, double *ws, double *sv_raw) {
   const int lane = threadIdx.x & 63;
-  int k = blockIdx.y;
-  for (; k < nsec; k += gridDim.y) {
+  for (int k = blockIdx.y; k < nsec; k += gridDim.y) {
     const DevSvdSector S = sec[k];
-    double *W = ws + S.w_off;
-    for (int j = blockIdx.x * 4 + (threadIdx.x >> 6); j < S.cols; j += gridDim.x * 4) {
+    const int npan = S.ld >> 3;
+    for (int p = blockIdx.x * 4 + (threadIdx.x >> 6); p < npan; p += gridDim.x * 4) {
+      double *pan = ws + S.w_off + (int64_t)p * S.rows * 8;
       double ss = 0.0;
-      for (int r = lane; r < S.rows; r += 64) {
-        const double x = W[pix(r, j, S.rows)];
+      for (int r = lane >> 3; r < S.rows; r += 8) {
+        const double x = pan[(int64_t)r * 8 + (lane & 7)];
         ss = fma(x, x, ss);
       }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
+      ss += __shfl_xor(ss, 8, 64);
+      ss += __shfl_xor(ss, 16, 64);
+      ss += __shfl_xor(ss, 32, 64);
+      const int col = 8 * p + (lane & 7);
       const double sig = sqrt(ss);
       const double inv = sig > 0.0 ? 1.0 / sig : 0.0;
-      for (int r = lane; r < S.rows; r += 64) W[pix(r, j, S.rows)] *= inv;
-      if (lane == 0) sv_raw[S.sv0 + j] = sig;
+      if (col < S.cols) {
+        for (int r = lane >> 3; r < S.rows; r += 8) pan[(int64_t)r * 8 + (lane & 7)] *= inv;
+        if (lane < 8) sv_raw[S.sv0 + col] = sig;
+      }
     }
   }
 }
 
 // descending order within each sector: rank of value j = values that are
-// larger, or equal with a smaller index; sv[sv0 + rank] and perm
+// larger, or equal with a smaller index; sv[sv0 + rank] and perm.
+// Workgroup (x, y) ranks values 256 y .. 256 y + 255 of sector x, from LDS
+// when the sector has at most kSvdSortMax values, else from memory.
 __global__ void __launch_bounds__(256) k_svd_sort(const DevSvdSector *sec, int nsec, const double *sv_raw, double *sv,
                                                   int32_t *perm) {
+  __shared__ double xs[kSvdSortMax];
   for (int k = blockIdx.x; k < nsec; k += gridDim.x) {
     const DevSvdSector S = sec[k];
     const double *x = sv_raw + S.sv0;
-    for (int j = threadIdx.x; j < S.cols; j += 256) {
-      const double v = x[j];
-      int rank = 0;
-      for (int i = 0; i < S.cols; ++i) rank += (x[i] > v) || (x[i] == v && i < j);
-      sv[S.sv0 + rank] = v;
-      perm[S.sv0 + rank] = j;
+    const bool lds = S.cols <= kSvdSortMax;
+    for (int j0 = (int)blockIdx.y * 256; j0 < S.cols; j0 += (int)gridDim.y * 256) {  // uniform
+      if (lds) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < S.cols; i += 256) xs[i] = x[i];
+        __syncthreads();
+      }
+      const double *src = lds ? xs : x;
+      const int j = j0 + (int)threadIdx.x;
+      if (j < S.cols) {
+        const double v = src[j];
+        int rank = 0, i = 0;
+        for (; i + 16 <= S.cols; i += 16) {
+          double w[16];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) w[q] = src[i + q];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) rank += (int)(w[q] > v) | ((int)(w[q] == v) & (int)(i + q < j));
+        }
+        for (; i < S.cols; ++i) rank += (int)(src[i] > v) | ((int)(src[i] == v) & (int)(i < j));
+        sv[S.sv0 + rank] = v;
+        perm[S.sv0 + rank] = j;
+      }
     }
   }
 }
@@ -1148,8 +1191,9 @@ yastn_status yastn_svd(yastn_svd_t h, const void *t, int32_t chi, double tol, do
     P.sweeps += sw;
     if (!all) return set_error(YASTN_ERR_STATE, "Jacobi sweeps did not converge");
     // ---- singular values, sorted per sector; global truncation
-    hipLaunchKernelGGL(k_svd_norms, dim3(16, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, W, sv_raw);
-    hipLaunchKernelGGL(k_svd_sort, dim3(std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, sv_raw, sv, perm);
+    hipLaunchKernelGGL(k_svd_norms, dim3(64, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, W, sv_raw);
+    hipLaunchKernelGGL(k_svd_sort, dim3(std::min(nsec, 65535), std::min((P.max_cols + 255) / 256, 64)), dim3(256), 0, st,
+                       P.d_sec, nsec, sv_raw, sv, perm);
     hipLaunchKernelGGL(k_svd_stats, dim3(1), dim3(1024), 0, st, sv, (int)P.nsv, tol, stat);
     hipLaunchKernelGGL(k_svd_cut, dim3(grid1(P.nsv, 256)), dim3(256), 0, st, sv, (int)P.nsv, chi, deg_tol, stat);
     int32_t *dkept = reinterpret_cast<int32_t *>(ws + P.off_done);  // done[] is free again
@@ -1180,7 +1224,7 @@ yastn_status yastn_svd(yastn_svd_t h, const void *t, int32_t chi, double tol, do
         accurate = false;
         return YASTN_OK;
       }
-      hipLaunchKernelGGL(k_svd_recover, dim3(std::max(1, std::min(chi, 1024)), std::min(nsec, 65535)), dim3(256), 0, st,
+      hipLaunchKernelGGL(k_svd_recover, dim3(256, std::min(nsec, 65535)), dim3(256), 0, st,
                          P.d_sec, nsec, W, perm, sv, dkept);
     }
     hipLaunchKernelGGL(k_svd_gauge, dim3(8, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, W, perm, dkept,
