@@ -710,23 +710,43 @@ __global__ void __launch_bounds__(256) k_svd_cut(const double *sv, int n, int ch
     tile[threadIdx.x] = j0 + (int)threadIdx.x < n ? sv[j0 + threadIdx.x] : -1.0;
     __syncthreads();
     const int m = min(256, n - j0);
-    for (int j = 0; j < m; ++j) {
+    // bitwise logic (no branch per compare), sixteen LDS reads in flight
+    int j = 0;
+    for (; j + 16 <= m; j += 16) {
+      double w[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) w[q] = tile[j + q];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int above = (int)(w[q] > floor_v);
+        gt += above & (int)(w[q] > v);
+        ge += above & (int)(w[q] >= v);
+      }
+    }
+    for (; j < m; ++j) {
       const double w = tile[j];
-      gt += w > floor_v && w > v;
-      ge += w > floor_v && w >= v;
+      const int above = (int)(w > floor_v);
+      gt += above & (int)(w > v);
+      ge += above & (int)(w >= v);
     }
   }
   if (i < n && v > floor_v && gt <= chi && chi < ge) stat[3] = v * (1.0 + deg_tol);
 }
 
+// kept[k] = how many of sector k's values exceed the cut: its values are
+// in descending order, so a binary search for the first one at or below it
 __global__ void __launch_bounds__(256) k_svd_kept(const DevSvdSector *sec, int nsec, const double *sv,
                                                   const double *stat, int32_t *kept) {
   for (int k = blockIdx.x * 256 + threadIdx.x; k < nsec; k += gridDim.x * 256) {
     const DevSvdSector S = sec[k];
     const double cut = stat[3];
-    int c = 0;
-    for (int j = 0; j < S.cols; ++j) c += sv[S.sv0 + j] > cut;
-    kept[k] = c;
+    int lo = 0, hi = S.cols;  // sv[sv0 + i] > cut for i < lo, <= cut for i >= hi
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (sv[S.sv0 + mid] > cut) lo = mid + 1;
+      else hi = mid;
+    }
+    kept[k] = lo;
   }
 }
 
