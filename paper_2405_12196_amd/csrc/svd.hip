@@ -65,8 +65,9 @@ constexpr int kSvdMaxSweeps = 40;  // outer sweeps before giving up
 constexpr int kSvdInnerSweeps = 1; // cyclic Jacobi sweeps on a pair's 16 x 16 Gram matrix per round
 constexpr int kSvdWaves = 8;       // waves of a round's workgroup (one workgroup per block pair)
 constexpr int kSvdGramGroups = 16; // 4-row groups of a wave's Gram loads in flight
-constexpr int kSvdRotChunks = 4;   // 16-row chunks of a wave's rotation loads in flight
-                                   // (8 needs 156 VGPRs: one workgroup per CU, slower)
+constexpr int kSvdRotChunks = 2;   // 16-row chunks of a wave's rotation loads in flight
+                                   // (78 VGPRs: three workgroups per CU; 4 chunks take 94
+                                   // and 8 take 156, fewer workgroups and slower rounds)
 
 // W (rows x ld) and V (ld x ld) are stored in panels of 8 columns: panel p
 // holds columns 8p .. 8p + 7 of every row, row after row, so a column block
