@@ -412,6 +412,225 @@ __global__ void __launch_bounds__(64 * kSvdWaves) k_svd_round(SvdRoundArgs a) {
   }
 }
 
+// ---- QR preconditioning of the sweeps (right vectors recovered) ----------
+// W = Q R by Householder reflections, then the sweeps run on X = R^T (n x n:
+// its columns are nearly orthogonal and graded, and one-sided Jacobi on it
+// needs about half the sweeps); the right vectors of W are X's converged
+// normalised columns and the left ones are recovered as W v / s.  Q itself
+// is never formed.
+constexpr int kSvdQrMaxRows = 1024;  // rows of a sector's panel held in LDS
+constexpr bool kSvdUseQr = true;     // precondition the sweeps when the right vectors are recovered
+constexpr int kSvdRecChunk = 256, kSvdRecT = 8;  // right-vector recovery: rows per LDS chunk, pairs per pass
+
+// sums of 8 per-thread values over a 256-thread workgroup, in a fixed order;
+// every thread returns the 8 sums
+__device__ __forceinline__ void qr_sum8(double (&v)[8], double (*red)[8], double *out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o, 64);
+  if (lane < 8) {
+    double x = v[0];
+#pragma unroll
+    for (int i = 1; i < 8; ++i) x = lane == i ? v[i] : x;
+    red[wid][lane] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < 8) out[threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = out[i];
+}
+
+// One panel step p (columns 8p .. 8p + 7) for every sector that has it.
+// Workgroup (x, y): sector y, panel q = p + x.  Every workgroup of a sector
+// factors panel p (rows 8p .. m - 1) in LDS with the same arithmetic, so all
+// hold the same reflectors (v with v_0 = 1, tau; beta on the diagonal).
+// x = 0 writes the panel's triangle of R, transposed, into X; x > 0 applies
+// the eight reflectors in order to panel q of W (rows 8p .. m - 1) in place,
+// each thread holding four rows of it.  Panel p itself is only read, so the
+// workgroups of a step do not race.
+__global__ void __launch_bounds__(256) k_svd_qr_step(const DevSvdSector *sec, const DevSvdSector *qsec, int nsec,
+                                                     double *ws, int p) {
+  __shared__ double P[kSvdQrMaxRows][8];
+  __shared__ double red[4][8];
+  __shared__ double sums[8];
+  __shared__ double tau[8];
+  const int tid = threadIdx.x;
+  for (int k = blockIdx.y; k < nsec; k += gridDim.y) {
+    const DevSvdSector S = sec[k];
+    const int npan = (S.cols + 7) >> 3;
+    const int q = p + (int)blockIdx.x;
+    if (p >= npan || q >= npan) continue;  // uniform across the workgroup
+    const int m = S.rows, r0 = 8 * p, mt = m - r0;
+    double *W = ws + S.w_off;
+    const double *Wp = W + (int64_t)p * m * 8 + (int64_t)r0 * 8;  // panel p, row r0
+    for (int e = tid; e < mt * 8; e += 256) P[e >> 3][e & 7] = Wp[e];
+    __syncthreads();
+    for (int c = 0; c < 8; ++c) {
+      // the reflector of column c from rows c .. mt - 1
+      double v8[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v8[i] = 0.0;
+      for (int r = c + 1 + tid; r < mt; r += 256) v8[0] = fma(P[r][c], P[r][c], v8[0]);
+      qr_sum8(v8, red, sums);
+      const double s = v8[0], alpha = P[c][c];
+      double t = 0.0, beta = alpha, scale = 0.0;
+      if (s > 0.0) {
+        beta = -copysign(sqrt(fma(alpha, alpha, s)), alpha);
+        t = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      __syncthreads();
+      for (int r = c + 1 + tid; r < mt; r += 256) P[r][c] *= scale;
+      if (tid == 0) {
+        P[c][c] = beta;
+        tau[c] = t;
+      }
+      __syncthreads();
+      // the panel's columns c + 1 .. 7: P[:, j] -= t v (v^T P[:, j]), the
+      // dot over rows c .. mt - 1 with v_c = 1 (every read before the
+      // reduction's barriers, every write after)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v8[i] = 0.0;
+      for (int r = c + tid; r < mt; r += 256) {
+        const double vr = r == c ? 1.0 : P[r][c];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v8[j] = fma(vr, P[r][j], v8[j]);
+      }
+      qr_sum8(v8, red, sums);
+      for (int r = c + tid; r < mt; r += 256) {
+        const double vr = r == c ? 1.0 : P[r][c];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (j > c) P[r][j] -= t * vr * v8[j];
+      }
+      __syncthreads();
+    }
+    if (blockIdx.x == 0) {
+      // R's diagonal block, transposed: X[8p + j][8p + c] = R[8p + c][8p + j], c <= j
+      const DevSvdSector Q = qsec[k];
+      double *X = ws + Q.w_off;
+      if (tid < 64) {
+        const int c = tid >> 3, j = tid & 7;
+        if (c <= j && r0 + j < S.cols) X[pix(r0 + j, r0 + c, Q.rows)] = P[c][j];
+      }
+      __syncthreads();  // P is reused by the next sector
+      continue;
+    }
+    // apply the reflectors to panel q, rows r0 .. m - 1 (four rows per thread)
+    double *Wq = W + (int64_t)q * m * 8 + (int64_t)r0 * 8;
+    double a[4][8];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = tid + 256 * u;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a[u][j] = r < mt ? Wq[r * 8 + j] : 0.0;
+    }
+    for (int c = 0; c < 8; ++c) {
+      double v8[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v8[j] = 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = tid + 256 * u;
+        const double vr = r < c || r >= mt ? 0.0 : (r == c ? 1.0 : P[r][c]);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v8[j] = fma(vr, a[u][j], v8[j]);
+      }
+      qr_sum8(v8, red, sums);
+      const double t = tau[c];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = tid + 256 * u;
+        const double vr = r < c || r >= mt ? 0.0 : (r == c ? 1.0 : P[r][c]);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[u][j] -= t * vr * v8[j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = tid + 256 * u;
+      if (r < mt)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) Wq[r * 8 + j] = a[u][j];
+    }
+    __syncthreads();  // P is reused by the next sector
+  }
+}
+
+// X = R^T below the diagonal blocks (R[b][a] from row b of W for panel(b) <
+// panel(a)) and zeros above the diagonal and in the padding columns; the
+// diagonal blocks were written by the panel steps
+__global__ void __launch_bounds__(256) k_svd_qr_finish(const DevSvdSector *sec, const DevSvdSector *qsec, int nsec,
+                                                       double *ws) {
+  for (int k = blockIdx.y; k < nsec; k += gridDim.y) {
+    const DevSvdSector S = sec[k], Q = qsec[k];
+    const double *W = ws + S.w_off;
+    double *X = ws + Q.w_off;
+    const int n = S.cols;
+    const int64_t ne = (int64_t)n * S.ld;
+    for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < ne; e += (int64_t)gridDim.x * 256) {
+      const int b = (int)((e / ((int64_t)n * 8)) * 8 + (e & 7));  // column of X
+      const int a = (int)((e % ((int64_t)n * 8)) >> 3);            // row of X
+      if (b < n && b <= a && (a >> 3) == (b >> 3)) continue;      // a diagonal block entry
+      X[e] = b < n && b <= a ? W[pix(b, a, S.rows)] : 0.0;
+    }
+  }
+}
+
+// Kept pair t of sector k after sweeps on X: v = X's normalised column j
+// (j = perm[t]) into column j of V, and the left vector w = M0 v / s_j into
+// column j of W.  A workgroup takes kSvdRecT pairs and 256 rows of W, v in
+// LDS in chunks, each sum in ascending column order.
+__global__ void __launch_bounds__(256) k_svd_recover_qr(const DevSvdSector *sec, const DevSvdSector *qsec, int nsec,
+                                                        double *ws, const int32_t *perm, const double *sv,
+                                                        const int32_t *kept) {
+  __shared__ double x[kSvdRecT][kSvdRecChunk];
+  for (int k = blockIdx.y; k < nsec; k += gridDim.y) {
+    const DevSvdSector S = sec[k], Q = qsec[k];
+    const double *X = ws + Q.w_off;
+    const double *M0 = ws + S.m_off;
+    double *W = ws + S.w_off;
+    double *V = ws + S.v_off;
+    const int nk = kept[k], n = S.cols;
+    const int ntc = (nk + kSvdRecT - 1) / kSvdRecT, nrc = (S.rows + 255) / 256;
+    for (int item = blockIdx.x; item < ntc * nrc; item += gridDim.x) {
+      const int t0 = (item / nrc) * kSvdRecT, r = (item % nrc) * 256 + (int)threadIdx.x;
+      int jt[kSvdRecT];
+#pragma unroll
+      for (int q = 0; q < kSvdRecT; ++q) jt[q] = t0 + q < nk ? perm[S.sv0 + t0 + q] : -1;
+      double acc[kSvdRecT];
+#pragma unroll
+      for (int q = 0; q < kSvdRecT; ++q) acc[q] = 0.0;
+      for (int c0 = 0; c0 < n; c0 += kSvdRecChunk) {
+        const int nc = min(kSvdRecChunk, n - c0);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kSvdRecT; ++q)
+          if ((int)threadIdx.x < nc) {
+            const double xv = jt[q] >= 0 ? X[pix(c0 + (int)threadIdx.x, jt[q], Q.rows)] : 0.0;
+            x[q][threadIdx.x] = xv;
+            // the right vector, once per pair (the row chunk 0 workgroup)
+            if (jt[q] >= 0 && item % nrc == 0) V[pix(c0 + (int)threadIdx.x, jt[q], S.ld)] = xv;
+          }
+        __syncthreads();
+        if (r < S.rows)
+          for (int c = 0; c < nc; ++c) {
+            const double mv = M0[pix(r, c0 + c, S.rows)];
+#pragma unroll
+            for (int q = 0; q < kSvdRecT; ++q) acc[q] = fma(mv, x[q][c], acc[q]);
+          }
+      }
+      if (r < S.rows)
+#pragma unroll
+        for (int q = 0; q < kSvdRecT; ++q)
+          if (jt[q] >= 0) W[pix(r, jt[q], S.rows)] = acc[q] * (1.0 / sv[S.sv0 + t0 + q]);
+    }
+  }
+}
+
 // M0 = W for every sector (the fused matrix, kept for the recovery of the
 // right vectors)
 __global__ void __launch_bounds__(256) k_svd_copy_m(const DevSvdSector *sec, int nsec, double *ws) {
@@ -431,7 +650,6 @@ __global__ void __launch_bounds__(256) k_svd_copy_m(const DevSvdSector *sec, int
 // A workgroup takes kSvdRecT kept pairs and 256 columns: the pairs' u in
 // LDS in chunks of kSvdRecChunk rows, one thread per column, M0 read once
 // per kSvdRecT pairs, each sum in ascending row order.
-constexpr int kSvdRecChunk = 256, kSvdRecT = 8;
 __global__ void __launch_bounds__(256) k_svd_recover(const DevSvdSector *sec, int nsec, double *ws,
                                                      const int32_t *perm, const double *sv, const int32_t *kept) {
   __shared__ double u[kSvdRecT][kSvdRecChunk];
@@ -851,6 +1069,8 @@ struct SvdPlanImpl {
   std::vector<DevSvdSector> dsec;
   int64_t nsv = 0;
   int max_rounds = 1, total_pairs = 0, max_cols = 1;
+  int max_panels = 0;   // 8-column panels of the widest sector (QR steps)
+  bool qr_ok = true;    // every sector's rows fit the QR panel step
   int32_t flags = 0;  // YASTN_SVD_RECOVER_V
   size_t ws_bytes = 0;
   size_t off_sv_raw = 0, off_perm = 0, off_conv = 0, off_done = 0, off_stat = 0, off_flag = 0, off_sign = 0,
@@ -860,6 +1080,7 @@ struct SvdPlanImpl {
   DevSvdGather *d_gather = nullptr;
   DevSvdTile *d_tiles = nullptr;
   DevSvdWg *d_wg = nullptr;
+  DevSvdSector *d_secqr = nullptr;  // the sectors as the sweeps on X = R^T see them
   int ngather = 0, ntiles = 0;
   int device = 0;
   // after yastn_svd: kept counts and the output structures
@@ -1000,6 +1221,8 @@ yastn_status yastn_svd_plan(const yastn_tensor_desc *t, int32_t nrow, const int3
       P.nsv += d.cols;
       P.max_rounds = std::max(P.max_rounds, nb - 1);
       P.max_cols = std::max(P.max_cols, (int)d.cols);
+      P.max_panels = std::max(P.max_panels, ((int)d.cols + 7) / 8);
+      P.qr_ok = P.qr_ok && d.rows <= kSvdQrMaxRows;
       P.dsec.push_back(d);
     }
     P.total_pairs = wg;
@@ -1078,14 +1301,23 @@ yastn_status yastn_svd_plan(const yastn_tensor_desc *t, int32_t nrow, const int3
     }
     P.ngather = (int)gat.size();
     P.ntiles = (int)tiles.size();
+    // the sectors for sweeps on X = R^T: n rows, X in the scratch region,
+    // the column reordering's scratch after it
+    std::vector<DevSvdSector> dsq(P.dsec);
+    for (auto &d : dsq) {
+      d.w_off = d.s_off;
+      d.s_off += int64_t(d.cols) * d.ld;
+      d.rows = d.cols;
+    }
     const size_t o_sec = 0, o_gat = al(P.dsec.size() * sizeof(DevSvdSector)),
                  o_til = o_gat + al(gat.size() * sizeof(DevSvdGather)), o_wg = o_til + al(tiles.size() * sizeof(DevSvdTile)),
-                 tot = o_wg + al(wgs.size() * sizeof(DevSvdWg));
+                 o_sq = o_wg + al(wgs.size() * sizeof(DevSvdWg)), tot = o_sq + al(dsq.size() * sizeof(DevSvdSector));
     std::vector<char> host(std::max<size_t>(tot, 256), 0);
     if (!P.dsec.empty()) std::memcpy(host.data() + o_sec, P.dsec.data(), P.dsec.size() * sizeof(DevSvdSector));
     if (!gat.empty()) std::memcpy(host.data() + o_gat, gat.data(), gat.size() * sizeof(DevSvdGather));
     if (!tiles.empty()) std::memcpy(host.data() + o_til, tiles.data(), tiles.size() * sizeof(DevSvdTile));
     if (!wgs.empty()) std::memcpy(host.data() + o_wg, wgs.data(), wgs.size() * sizeof(DevSvdWg));
+    if (!dsq.empty()) std::memcpy(host.data() + o_sq, dsq.data(), dsq.size() * sizeof(DevSvdSector));
     if (hipGetDevice(&P.device) != hipSuccess || hipMalloc(&P.dev_mem, host.size()) != hipSuccess) {
       (void)hipGetLastError();
       delete h;
@@ -1096,6 +1328,7 @@ yastn_status yastn_svd_plan(const yastn_tensor_desc *t, int32_t nrow, const int3
     P.d_gather = reinterpret_cast<DevSvdGather *>(base + o_gat);
     P.d_tiles = reinterpret_cast<DevSvdTile *>(base + o_til);
     P.d_wg = reinterpret_cast<DevSvdWg *>(base + o_wg);
+    P.d_secqr = reinterpret_cast<DevSvdSector *>(base + o_sq);
     hipStream_t stm = reinterpret_cast<hipStream_t>(hip_stream);
     if (hipMemcpyAsync(P.dev_mem, host.data(), host.size(), hipMemcpyHostToDevice, stm) != hipSuccess ||
         hipStreamSynchronize(stm) != hipSuccess) {
@@ -1172,14 +1405,24 @@ yastn_status yastn_svd(yastn_svd_t h, const void *t, int32_t chi, double tol, do
                          P.ntiles, reinterpret_cast<const double *>(t), W);
     if (recover)
       hipLaunchKernelGGL(k_svd_copy_m, dim3(64, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, W);
+    // with the right vectors recovered, the sweeps run on X = R^T of W = Q R
+    const bool qr = recover && kSvdUseQr && P.qr_ok;
+    const DevSvdSector *swsec = qr ? P.d_secqr : P.d_sec;
+    if (qr) {
+      for (int p = 0; p < P.max_panels; ++p)
+        hipLaunchKernelGGL(k_svd_qr_step, dim3(P.max_panels - p, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec,
+                           (const DevSvdSector *)P.d_secqr, nsec, W, p);
+      hipLaunchKernelGGL(k_svd_qr_finish, dim3(256, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec,
+                         (const DevSvdSector *)P.d_secqr, nsec, W);
+    }
     SVD_HIP(hipGetLastError());
     // ---- sweeps of rounds until every sector is converged
     SvdRoundArgs ra{};
     ra.with_v = recover ? 0 : 1;
     ra.nrm2 = sv_raw;  // free until the values are formed after the sweeps
-    hipLaunchKernelGGL(k_svd_colnorm2, dim3(64, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec,
+    hipLaunchKernelGGL(k_svd_colnorm2, dim3(64, std::min(nsec, 65535)), dim3(256), 0, st, swsec, nsec,
                        (const double *)W, sv_raw);
-    ra.sec = P.d_sec;
+    ra.sec = swsec;
     ra.wg = P.d_wg;
     ra.ws = W;
     ra.conv = conv;
@@ -1196,15 +1439,15 @@ yastn_status yastn_svd(yastn_svd_t h, const void *t, int32_t chi, double tol, do
       // columns by descending norm (the order is recomputed every sweep)
       hipLaunchKernelGGL(k_svd_colsort,
                          dim3(std::min(nsec, 65535), std::min(P.max_cols + kSvdSortSlice - 1, kSvdSortMax) / kSvdSortSlice),
-                         dim3(256), 0, st, P.d_sec, nsec, (const double *)sv_raw, (const int32_t *)done, perm, chg);
+                         dim3(256), 0, st, swsec, nsec, (const double *)sv_raw, (const int32_t *)done, perm, chg);
       for (int back = 0; back < 2; ++back)
-        hipLaunchKernelGGL(k_svd_colperm, dim3(256, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, W,
+        hipLaunchKernelGGL(k_svd_colperm, dim3(256, std::min(nsec, 65535)), dim3(256), 0, st, swsec, nsec, W,
                            (const int32_t *)perm, (const int32_t *)chg, ra.with_v, back);
       for (int rr = 0; rr < P.max_rounds; ++rr) {
         ra.round = rr;
         hipLaunchKernelGGL(k_svd_round, dim3(P.total_pairs), dim3(64 * kSvdWaves), 0, st, ra);
       }
-      hipLaunchKernelGGL(k_svd_sweep_end, dim3(1), dim3(256), 0, st, conv, done, nsec, P.d_sec, eps_scale, flag);
+      hipLaunchKernelGGL(k_svd_sweep_end, dim3(1), dim3(256), 0, st, conv, done, nsec, swsec, eps_scale, flag);
       SVD_HIP(hipGetLastError());
       SVD_HIP(hipMemcpyAsync(&all, flag, 4, hipMemcpyDeviceToHost, st));
       SVD_HIP(hipStreamSynchronize(st));
@@ -1212,7 +1455,7 @@ yastn_status yastn_svd(yastn_svd_t h, const void *t, int32_t chi, double tol, do
     P.sweeps += sw;
     if (!all) return set_error(YASTN_ERR_STATE, "Jacobi sweeps did not converge");
     // ---- singular values, sorted per sector; global truncation
-    hipLaunchKernelGGL(k_svd_norms, dim3(64, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, W, sv_raw);
+    hipLaunchKernelGGL(k_svd_norms, dim3(64, std::min(nsec, 65535)), dim3(256), 0, st, swsec, nsec, W, sv_raw);
     hipLaunchKernelGGL(k_svd_sort, dim3(std::min(nsec, 65535), std::min((P.max_cols + 255) / 256, 64)), dim3(256), 0, st,
                        P.d_sec, nsec, sv_raw, sv, perm);
     hipLaunchKernelGGL(k_svd_stats, dim3(1), dim3(1024), 0, st, sv, (int)P.nsv, tol, stat);
@@ -1245,8 +1488,12 @@ yastn_status yastn_svd(yastn_svd_t h, const void *t, int32_t chi, double tol, do
         accurate = false;
         return YASTN_OK;
       }
-      hipLaunchKernelGGL(k_svd_recover, dim3(256, std::min(nsec, 65535)), dim3(256), 0, st,
-                         P.d_sec, nsec, W, perm, sv, dkept);
+      if (qr)
+        hipLaunchKernelGGL(k_svd_recover_qr, dim3(256, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec,
+                           (const DevSvdSector *)P.d_secqr, nsec, W, perm, sv, dkept);
+      else
+        hipLaunchKernelGGL(k_svd_recover, dim3(256, std::min(nsec, 65535)), dim3(256), 0, st,
+                           P.d_sec, nsec, W, perm, sv, dkept);
     }
     hipLaunchKernelGGL(k_svd_gauge, dim3(8, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec, nsec, W, perm, dkept,
                        reinterpret_cast<double *>(ws + P.off_sign));

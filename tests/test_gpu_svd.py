@@ -192,19 +192,22 @@ def test_svd_repeat_bitwise():
 
 def test_svd_recover_v_corner_chi128():
     """Right vectors recovered after the sweeps on the chi = 128 corner: the
-    kept values lie far above eps s_max, so the mode is used (no second
-    pass: as many sweeps as the default), the values and U are bitwise those
-    of the default mode, and the factors pass the oracle checks."""
+    kept values lie far above eps s_max, so the mode is used (the sweeps run
+    on R^T of a QR factorisation of each sector, fewer of them than the
+    default mode's); the factors pass the oracle checks and the values and
+    factors agree with the default mode's within rounding."""
     cur = _corner()
     base = gpu_svd(cur, (0, 3, 5), 128)
     sv, kept, sweeps = check_svd(cur, (0, 3, 5), chi=128, flags=Y.SVD_RECOVER_V)
     rec = gpu_svd(cur, (0, 3, 5), 128, flags=Y.SVD_RECOVER_V)
-    assert sweeps == base[3] == rec[3], "the recover mode fell back to accumulated rotations"
-    assert np.array_equal(rec[1], base[1]) and rec[2] == base[2]
-    assert np.array_equal(rec[4][1], base[4][1]), "U differs from the default mode"
-    # V^T within the recovery's error of the accumulated one
-    err = float(np.max(np.abs(rec[5][1] - base[5][1])))
-    assert err <= 1e-10, f"recovered V^T off by {err:.3e}"
+    assert rec[3] < base[3], f"no fewer sweeps with the QR preconditioning ({rec[3]} vs {base[3]})"
+    smax = float(np.max(base[1]))
+    assert float(np.max(np.abs(rec[1] - base[1]))) <= 1e-12 * smax
+    assert rec[2] == base[2]
+    for i in (4, 5):
+        err = float(np.max(np.abs(rec[i][1] - base[i][1])))
+        assert err <= 1e-9, f"factor {i - 4} off the default mode's by {err:.3e}"
+    print(f"recovered mode: {rec[3]} sweeps (default {base[3]})", flush=True)
 
 
 def test_svd_recover_v_falls_back_on_small_kept_values():
