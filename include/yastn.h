@@ -462,14 +462,18 @@ void yastn_grad_free(yastn_grad_t g);
  * that is not finite.
  *
  * yastn_svd_set_flags: YASTN_SVD_RECOVER_V makes the following yastn_svd
- * calls on this plan rotate only the working matrix during the sweeps and
- * form the kept right vectors afterwards as v_t = M^T u_t / s_t (u_t, s_t of
- * the tall orientation of M_X): the sweeps move about 40 % fewer bytes and
- * the values and U are bitwise those of the default mode, while v_t carries
- * an error of about sqrt(rows) eps s_max / s_t relative, so the mode suits
- * truncations that keep only values well above eps s_max (the CTM move
- * uses it).  0 restores the default (rotations accumulated into V).
- * YASTN_ERR_ARG for an unknown flag. */
+ * calls on this plan form one set of singular vectors after the sweeps
+ * instead of accumulating rotations.  When every sector has at most 1024
+ * rows (tall orientation), each sector is first factored W = Q R by
+ * Householder reflections and the sweeps run on R^T (nearly orthogonal,
+ * graded columns: about half the sweeps on the CTM four-corner product);
+ * the right vectors of W are then the converged columns and the left ones
+ * are formed as w_t = W v_t / s_t.  Otherwise the sweeps run on W without
+ * rotating V and v_t = W^T u_t / s_t.  Either way the formed vectors carry
+ * an error of about sqrt(n) eps s_max / s_t relative, so the mode is used
+ * only when 4 sqrt(rows) eps s_max <= 1e-11 s_min over the kept values;
+ * otherwise the call runs again with accumulated rotations (the default,
+ * flags 0).  YASTN_ERR_ARG for an unknown flag. */
 #define YASTN_SVD_RECOVER_V 1
 typedef struct yastn_svd_s *yastn_svd_t;
 yastn_status yastn_svd_plan(const yastn_tensor_desc *t, int32_t nrow, const int32_t *row_legs, void *hip_stream,

@@ -326,9 +326,9 @@ yastn_status yastn_ctm_plan(const yastn_tensor_desc *env, void *hip_stream, yast
   int32_t nsec = 0;
   size_t svd_ws = 0;
   // the move keeps chi values of the four-corner product, far above eps
-  // times its largest: the kept right vectors are recovered after the sweeps
-  // (yastn_svd falls back to accumulated rotations when they would not be
-  // accurate)
+  // times its largest: the singular vectors are formed after QR-
+  // preconditioned sweeps (yastn_svd falls back to accumulated rotations
+  // when they would not be accurate)
   if (s == YASTN_OK) s = yastn_svd_set_flags(h->svd, YASTN_SVD_RECOVER_V);
   s = s == YASTN_OK ? yastn_svd_info(h->svd, &nsec, &h->nsv, &svd_ws) : s;
   if (s != YASTN_OK) return fail(s);

@@ -22,6 +22,12 @@
 //                accumulates the rotations, so W V stays M V with M the
 //                sector matrix).  The largest scaled off-diagonal Gram entry
 //                seen in a sweep decides convergence.
+//  k_svd_qr_*    with the singular vectors formed after the sweeps
+//                (YASTN_SVD_RECOVER_V): W = Q R by Householder panel steps,
+//                the sweeps then run on R^T (Q is never formed), and
+//                k_svd_recover_qr forms the left vectors as W v / s.
+//  k_svd_colsort before each sweep, the columns of each sector in order of
+//  k_svd_colperm descending norm (de Rijk's ordering).
 //  k_svd_norms   singular values = column norms of the converged W; W's
 //                columns scaled to unit norm (the left vectors).
 //  k_svd_sort    each sector's values in descending order (rank by count).
