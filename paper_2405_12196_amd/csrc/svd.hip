@@ -426,22 +426,36 @@ __global__ void __launch_bounds__(64 * kSvdWaves) k_svd_round(SvdRoundArgs a) {
 // is never formed.
 constexpr int kSvdQrMaxRows = 1024;  // rows of a sector's panel held in LDS
 constexpr bool kSvdUseQr = true;     // precondition the sweeps when the right vectors are recovered
+constexpr int kSvdQrGroup = 1;       // trailing panels per workgroup of a panel step (4: longer chains, slower)
 constexpr int kSvdRecChunk = 256, kSvdRecT = 8;  // right-vector recovery: rows per LDS chunk, pairs per pass
 
 // sums of 8 per-thread values over a 256-thread workgroup, in a fixed order;
-// every thread returns the 8 sums
+// every thread returns the 8 sums.  Within a wave a transposing butterfly:
+// the xor-32, -16 and -8 exchanges each halve the values a lane keeps (4, 2,
+// then 1: value ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3)
+// & 1)), the xor-4, -2 and -1 exchanges finish that value's sum: 10
+// exchanges instead of 48.
 __device__ __forceinline__ void qr_sum8(double (&v)[8], double (*red)[8], double *out) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+  double w[4], x[2];
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o, 64);
-  if (lane < 8) {
-    double x = v[0];
-#pragma unroll
-    for (int i = 1; i < 8; ++i) x = lane == i ? v[i] : x;
-    red[wid][lane] = x;
+  for (int i = 0; i < 4; ++i) {
+    const double send = b5 ? v[i] : v[i + 4];
+    const double keep = b5 ? v[i + 4] : v[i];
+    w[i] = keep + __shfl_xor(send, 32, 64);
   }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double send = b4 ? w[i] : w[i + 2];
+    const double keep = b4 ? w[i + 2] : w[i];
+    x[i] = keep + __shfl_xor(send, 16, 64);
+  }
+  double y = (b3 ? x[1] : x[0]) + __shfl_xor(b3 ? x[0] : x[1], 8, 64);
+  y += __shfl_xor(y, 4, 64);
+  y += __shfl_xor(y, 2, 64);
+  y += __shfl_xor(y, 1, 64);
+  if ((lane & 7) == 0) red[wid][(b5 ? 4 : 0) + (b4 ? 2 : 0) + (b3 ? 1 : 0)] = y;
   __syncthreads();
   if (threadIdx.x < 8) out[threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
   __syncthreads();
@@ -450,12 +464,13 @@ __device__ __forceinline__ void qr_sum8(double (&v)[8], double (*red)[8], double
 }
 
 // One panel step p (columns 8p .. 8p + 7) for every sector that has it.
-// Workgroup (x, y): sector y, panel q = p + x.  Every workgroup of a sector
+// Workgroup (x, y): sector y; x = 0 the panel itself, x >= 1 the trailing
+// panels p + 1 + (x - 1) G .. p + x G (G = kSvdQrGroup).  Every workgroup of a sector
 // factors panel p (rows 8p .. m - 1) in LDS with the same arithmetic, so all
 // hold the same reflectors (v with v_0 = 1, tau; beta on the diagonal).
 // x = 0 writes the panel's triangle of R, transposed, into X; x > 0 applies
-// the eight reflectors in order to panel q of W (rows 8p .. m - 1) in place,
-// each thread holding four rows of it.  Panel p itself is only read, so the
+// the eight reflectors in order to each of its panels of W (rows 8p .. m - 1)
+// in place, each thread holding four rows of it.  Panel p itself is only read, so the
 // workgroups of a step do not race.
 __global__ void __launch_bounds__(256) k_svd_qr_step(const DevSvdSector *sec, const DevSvdSector *qsec, int nsec,
                                                      double *ws, int p) {
@@ -467,50 +482,52 @@ __global__ void __launch_bounds__(256) k_svd_qr_step(const DevSvdSector *sec, co
   for (int k = blockIdx.y; k < nsec; k += gridDim.y) {
     const DevSvdSector S = sec[k];
     const int npan = (S.cols + 7) >> 3;
-    const int q = p + (int)blockIdx.x;
-    if (p >= npan || q >= npan) continue;  // uniform across the workgroup
+    // x = 0: the panel itself; x >= 1: trailing panels q0 .. q0 + kSvdQrGroup - 1
+    const int q0 = blockIdx.x == 0 ? p : p + 1 + ((int)blockIdx.x - 1) * kSvdQrGroup;
+    if (p >= npan || q0 >= npan) continue;  // uniform across the workgroup
     const int m = S.rows, r0 = 8 * p, mt = m - r0;
     double *W = ws + S.w_off;
     const double *Wp = W + (int64_t)p * m * 8 + (int64_t)r0 * 8;  // panel p, row r0
     for (int e = tid; e < mt * 8; e += 256) P[e >> 3][e & 7] = Wp[e];
     __syncthreads();
     for (int c = 0; c < 8; ++c) {
-      // the reflector of column c from rows c .. mt - 1
-      double v8[8];
+      // the reflector of column c from rows c .. mt - 1, and its effect on
+      // the panel's columns c + 1 .. 7, from one reduction: d_j = sum over
+      // rows r > c of x_r P[r][j] (d_c = |x_tail|^2), then with v_r =
+      // x_r / (alpha - beta) the dot v^T P[:, j] = P[c][j] + d_j / (alpha -
+      // beta).  Row c is read before the reduction's barriers, written after.
+      double v8[8], pc[8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) v8[i] = 0.0;
-      for (int r = c + 1 + tid; r < mt; r += 256) v8[0] = fma(P[r][c], P[r][c], v8[0]);
+      for (int i = 0; i < 8; ++i) {
+        v8[i] = 0.0;
+        pc[i] = P[c][i];
+      }
+      for (int r = c + 1 + tid; r < mt; r += 256) {
+        const double xr = P[r][c];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v8[j] = fma(xr, P[r][j], v8[j]);
+      }
       qr_sum8(v8, red, sums);
-      const double s = v8[0], alpha = P[c][c];
+      const double s = v8[c], alpha = pc[c];
       double t = 0.0, beta = alpha, scale = 0.0;
       if (s > 0.0) {
         beta = -copysign(sqrt(fma(alpha, alpha, s)), alpha);
         t = (beta - alpha) / beta;
         scale = 1.0 / (alpha - beta);
       }
-      __syncthreads();
-      for (int r = c + 1 + tid; r < mt; r += 256) P[r][c] *= scale;
+      double dot[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) dot[j] = fma(scale, v8[j], pc[j]);
+      for (int r = c + tid; r < mt; r += 256) {
+        const double vr = r == c ? 1.0 : P[r][c] * scale;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (j > c) P[r][j] -= t * vr * dot[j];
+        if (r > c) P[r][c] = vr;
+      }
       if (tid == 0) {
         P[c][c] = beta;
         tau[c] = t;
-      }
-      __syncthreads();
-      // the panel's columns c + 1 .. 7: P[:, j] -= t v (v^T P[:, j]), the
-      // dot over rows c .. mt - 1 with v_c = 1 (every read before the
-      // reduction's barriers, every write after)
-#pragma unroll
-      for (int i = 0; i < 8; ++i) v8[i] = 0.0;
-      for (int r = c + tid; r < mt; r += 256) {
-        const double vr = r == c ? 1.0 : P[r][c];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v8[j] = fma(vr, P[r][j], v8[j]);
-      }
-      qr_sum8(v8, red, sums);
-      for (int r = c + tid; r < mt; r += 256) {
-        const double vr = r == c ? 1.0 : P[r][c];
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-          if (j > c) P[r][j] -= t * vr * v8[j];
       }
       __syncthreads();
     }
@@ -525,42 +542,45 @@ __global__ void __launch_bounds__(256) k_svd_qr_step(const DevSvdSector *sec, co
       __syncthreads();  // P is reused by the next sector
       continue;
     }
-    // apply the reflectors to panel q, rows r0 .. m - 1 (four rows per thread)
-    double *Wq = W + (int64_t)q * m * 8 + (int64_t)r0 * 8;
-    double a[4][8];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int r = tid + 256 * u;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) a[u][j] = r < mt ? Wq[r * 8 + j] : 0.0;
-    }
-    for (int c = 0; c < 8; ++c) {
-      double v8[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) v8[j] = 0.0;
+    // apply the reflectors to panels q0 .. q0 + kSvdQrGroup - 1, rows
+    // r0 .. m - 1 (four rows per thread)
+    for (int q = q0; q < min(npan, q0 + kSvdQrGroup); ++q) {
+      double *Wq = W + (int64_t)q * m * 8 + (int64_t)r0 * 8;
+      double a[4][8];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int r = tid + 256 * u;
-        const double vr = r < c || r >= mt ? 0.0 : (r == c ? 1.0 : P[r][c]);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v8[j] = fma(vr, a[u][j], v8[j]);
+        for (int j = 0; j < 8; ++j) a[u][j] = r < mt ? Wq[r * 8 + j] : 0.0;
       }
-      qr_sum8(v8, red, sums);
-      const double t = tau[c];
+      for (int c = 0; c < 8; ++c) {
+        double v8[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v8[j] = 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = tid + 256 * u;
+          const double vr = r < c || r >= mt ? 0.0 : (r == c ? 1.0 : P[r][c]);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) v8[j] = fma(vr, a[u][j], v8[j]);
+        }
+        qr_sum8(v8, red, sums);
+        const double t = tau[c];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = tid + 256 * u;
+          const double vr = r < c || r >= mt ? 0.0 : (r == c ? 1.0 : P[r][c]);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) a[u][j] -= t * vr * v8[j];
+        }
+      }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int r = tid + 256 * u;
-        const double vr = r < c || r >= mt ? 0.0 : (r == c ? 1.0 : P[r][c]);
+        if (r < mt)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) a[u][j] -= t * vr * v8[j];
+          for (int j = 0; j < 8; ++j) Wq[r * 8 + j] = a[u][j];
       }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int r = tid + 256 * u;
-      if (r < mt)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) Wq[r * 8 + j] = a[u][j];
     }
     __syncthreads();  // P is reused by the next sector
   }
@@ -1416,7 +1436,8 @@ yastn_status yastn_svd(yastn_svd_t h, const void *t, int32_t chi, double tol, do
     const DevSvdSector *swsec = qr ? P.d_secqr : P.d_sec;
     if (qr) {
       for (int p = 0; p < P.max_panels; ++p)
-        hipLaunchKernelGGL(k_svd_qr_step, dim3(P.max_panels - p, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec,
+        hipLaunchKernelGGL(k_svd_qr_step, dim3(1 + (P.max_panels - p - 1 + kSvdQrGroup - 1) / kSvdQrGroup,
+                                               std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec,
                            (const DevSvdSector *)P.d_secqr, nsec, W, p);
       hipLaunchKernelGGL(k_svd_qr_finish, dim3(256, std::min(nsec, 65535)), dim3(256), 0, st, P.d_sec,
                          (const DevSvdSector *)P.d_secqr, nsec, W);
