@@ -210,6 +210,18 @@ def test_svd_recover_v_corner_chi128():
     print(f"recovered mode: {rec[3]} sweeps (default {base[3]})", flush=True)
 
 
+def test_svd_recover_v_tall_sector_without_qr():
+    """Formed vectors on a sector taller than the QR panel step holds (1100 x
+    40, plus a small one): the sweeps run on W itself and the right vectors
+    are formed as W^T u / s; factors against the oracle."""
+    from workloads import Leg, rand
+    rows = Leg(1, ((0,), (1,)), (1100, 6))
+    cols = Leg(-1, ((0,), (1,)), (40, 5))
+    t = rand([rows, cols], (0,), (0,), 77)
+    sv, kept, sweeps = check_svd(t, (0,), chi=30, flags=Y.SVD_RECOVER_V)
+    assert sum(kept) == 30 and sweeps >= 1
+
+
 def test_svd_recover_v_falls_back_on_small_kept_values():
     """One sector scaled by 1e-10 and every value kept: recovered right
     vectors there would carry ~1e-5 relative error, so the call runs again
