@@ -142,6 +142,20 @@ def test_svd_wide_and_tall_sectors_and_tol():
         check_svd(t, rows, chi=1000, tol=1e-2)
 
 
+def test_svd_recover_v_wide_and_tall_sectors():
+    """The formed-vector mode (QR of each sector, sweeps on R^T) on sectors
+    stored transposed next to tall ones: values, kept counts and factors
+    against the oracle, with and without a tol floor."""
+    from workloads import Leg, rand
+    l1 = Leg(1, ((-1,), (0,), (1,)), (3, 9, 2))
+    l2 = Leg(1, ((0,), (1,)), (5, 4))
+    l3 = Leg(-1, ((-1,), (0,), (1,), (2,)), (7, 11, 6, 3))
+    t = rand([l1, l2, l3], (0,), (0,), 909)
+    for rows in ((0, 1), (2,), (0,), (1, 2)):
+        check_svd(t, rows, chi=17, flags=Y.SVD_RECOVER_V)
+        check_svd(t, rows, chi=1000, tol=1e-2, flags=Y.SVD_RECOVER_V)
+
+
 def _corner():
     """The chi = 128, D = 8 enlarged corner (the oracle's chain output)."""
     from bench import STEPS
