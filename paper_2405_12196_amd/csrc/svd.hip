@@ -488,7 +488,20 @@ __global__ void __launch_bounds__(256) k_svd_qr_step(const DevSvdSector *sec, co
     const int m = S.rows, r0 = 8 * p, mt = m - r0;
     double *W = ws + S.w_off;
     const double *Wp = W + (int64_t)p * m * 8 + (int64_t)r0 * 8;  // panel p, row r0
-    for (int e = tid; e < mt * 8; e += 256) P[e >> 3][e & 7] = Wp[e];
+    // the panel into LDS, sixteen loads of a thread in flight at a time
+    for (int e0 = 0; e0 < mt * 8; e0 += 256 * 16) {
+      double buf[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int e = e0 + tid + 256 * i;
+        buf[i] = e < mt * 8 ? Wp[e] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int e = e0 + tid + 256 * i;
+        if (e < mt * 8) P[e >> 3][e & 7] = buf[i];
+      }
+    }
     __syncthreads();
     for (int c = 0; c < 8; ++c) {
       // the reflector of column c from rows c .. mt - 1, and its effect on
